@@ -1,0 +1,157 @@
+/*
+ * ffp.h -- exact symmetric products and LDL^T over a prime field on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Implements the method of Dumas, Pernet and Sedoglavic, "On Fast
+ * Multiplication of a Matrix by its Transpose" (ISSAC 2020,
+ * arXiv:2001.04109): the 2x2-block recursion of Algorithm 2 with three
+ * recursive symmetric products and two general products, through a
+ * skew-orthogonal Y with Y*Y^T = -I (Section 3.1), scheduled with the
+ * low-memory placements of Table 3 and Table 4 (Section 4.2), and its use
+ * for the Schur-complement updates of an LDL^T factorisation with diagonal
+ * scaling (Section 5, Algorithms 4 and 5).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major; a leading dimension counts elements of the
+ *     operand's storage type and is at least the number of columns.
+ *   - Matrix pointers are device pointers owned by the caller.  The library
+ *     never frees or retains them beyond the call's stream order.
+ *   - Residues are uint32 values in [0, p) unless the storage type says
+ *     otherwise.  p must be prime; which p each base path accepts is stated
+ *     at FFP_U32 below.
+ *   - Every call validates its arguments synchronously (negative status on
+ *     error, nothing enqueued), then enqueues its kernels on `stream` (a
+ *     hipStream_t; NULL is the null stream) and returns without waiting.
+ *     Device-detected conditions are reported through device memory (the
+ *     `info` argument of fldlt_modp).
+ *   - The library owns its device workspace (grown on demand, one per
+ *     device and stream) and is safe to call from several host threads on
+ *     different streams.
+ *
+ * Results are exact: every entry equals the plain definition reduced mod p.
+ */
+#ifndef FFP_H
+#define FFP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define FFP_OK            0
+#define FFP_EINVAL       (-1) /* negative size, leading dimension too small, NULL pointer */
+#define FFP_EPRIME       (-2) /* p not prime, or outside the range of the chosen path */
+#define FFP_EDTYPE       (-3) /* unknown operand storage, or storage not valid for p */
+#define FFP_ENOMEM       (-4) /* device workspace could not be allocated */
+#define FFP_EDEVICE      (-5) /* a HIP runtime call failed */
+#define FFP_EUNSUPPORTED (-6) /* a valid request this library does not implement */
+
+/* ---- operand storage of A ------------------------------------------- */
+/* uint32 residues in [0,p).  Any prime 2 < p < 2^25 is accepted.  The base
+ * path is chosen from p: p <= 251 packs to centered int8 (int8 matrix
+ * cores, int32 accumulation); p <= 65521 packs to two int8 limbs; larger p
+ * runs on FP64 matrix cores with delayed reduction, exact while every
+ * partial sum stays below 2^53. */
+#define FFP_U32          0
+/* int8 residues in [-(p-1)/2, (p-1)/2]; requires p <= 251. */
+#define FFP_I8_CENTERED  1
+/* Two int8 planes of the same shape and leading dimension: the value of an
+ * entry is 256*hi + lo, and must lie in [-32896, 32639] and be congruent to
+ * the residue.  `A` points to the hi plane; the lo plane starts at
+ * (const int8_t*)A + n*lda.  Requires p <= 65521. */
+#define FFP_I8_LIMB2     2
+
+/* ---- flags ----------------------------------------------------------- */
+/* Mirror the lower triangle into the upper one after the product, so C
+ * holds the full symmetric result.  Without it the strict upper triangle
+ * of C is scratch space on return (Algorithm 2 only defines the lower
+ * triangle, and Tables 3 and 4 use the upper triangle as temporary). */
+#define FFP_FILL_UPPER    0x1u
+/* Force d levels of Algorithm 2 (0 <= d <= 7) instead of the tuned depth. */
+#define FFP_DEPTH(d)      (((((unsigned)(d)) & 0x7u) + 1u) << 4)
+/* Run the base products on FP64 matrix cores even where an int8 path
+ * exists for p (only for FFP_U32 operands). */
+#define FFP_BASE_F64      0x100u
+
+/* lower(C) <- (alpha * A * A^T + beta * lower(C)) mod p.
+ * Algorithm 2 (Ensure: the lower triangle of A*A^T) in the accumulate form
+ * of Table 4.  alpha = 1, beta = 0 runs the Table 3 schedule; any other
+ * pair runs the Table 4 schedule.
+ *   n, k     A is n x k, C is n x n; n, k >= 0.
+ *   p        prime modulus (see FFP_U32 / FFP_I8_* for the accepted range).
+ *   A, lda   device pointer and leading dimension (elements of a_dtype).
+ *   a_dtype  FFP_U32, FFP_I8_CENTERED or FFP_I8_LIMB2.
+ *   alpha, beta  residues in [0,p).
+ *   C, ldc   device pointer, ldc >= n.  Entries of lower(C) must be in
+ *            [0,p) when beta != 0.
+ *   flags    FFP_FILL_UPPER, FFP_DEPTH(d), FFP_BASE_F64.
+ * Errors: FFP_EINVAL, FFP_EPRIME, FFP_EDTYPE, FFP_ENOMEM, FFP_EDEVICE. */
+int fsyrk_modp(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int a_dtype,
+               uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, unsigned flags,
+               void* stream);
+
+/* C <- (alpha * A * B^T + beta * C) mod p, the general products P3 and P4
+ * of Algorithm 2 as a stand-alone call.  A is m x k, B is n x k, C is
+ * m x n, all uint32 residues; 2 < p < 2^25.  FP64 matrix cores with
+ * delayed reduction.  Errors: FFP_EINVAL, FFP_EPRIME, FFP_EDEVICE. */
+int fgemm_modp(int64_t m, int64_t n, int64_t k, uint32_t p, const uint32_t* A, int64_t lda,
+               const uint32_t* B, int64_t ldb, uint32_t alpha, uint32_t beta, uint32_t* C,
+               int64_t ldc, void* stream);
+
+/* In-place LDL^T factorisation without pivoting, S = L * D * L^T mod p
+ * (the symmetric factorisation of Section 5, whose Schur-complement
+ * updates C <- C - A*D*A^T run as Algorithm 5 followed by fsyrk_modp with
+ * alpha = p-1, beta = 1).
+ *   n        order of S, n >= 0;  p an odd prime < 2^25.
+ *   S, lds   device pointer; on entry the lower triangle holds the
+ *            symmetric matrix (residues in [0,p)); on exit the strict lower
+ *            triangle holds the unit lower triangular L and the diagonal
+ *            holds D.  The strict upper triangle is scratch space.
+ *   info     device pointer to one int64: 0 on success, or j >= 1 when the
+ *            j-th pivot is zero (S has no generic rank profile); the
+ *            contents of S are then unspecified.
+ * Errors: FFP_EINVAL, FFP_EPRIME, FFP_ENOMEM, FFP_EDEVICE. */
+int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, void* stream);
+
+/* Device workspace fsyrk_modp needs for this shape (bytes), for admission
+ * control; flags as for fsyrk_modp (beta != 0 is signalled by
+ * FFP_WS_BETA). */
+#define FFP_WS_BETA 0x80000000u
+size_t ffp_workspace_bytes(int64_t n, int64_t k, uint32_t p, int a_dtype, unsigned flags);
+
+/* ---- batched form ----------------------------------------------------- */
+/* One independent fsyrk_modp job of a batch. */
+typedef struct ffp_job {
+    int64_t n, k;       /* A is n x k, C is n x n */
+    uint32_t p;         /* prime, 2 < p < 2^25 */
+    uint32_t alpha, beta;
+    int32_t a_dtype;    /* FFP_U32 only, in this version */
+    const void* A;      /* device pointer */
+    int64_t lda;
+    uint32_t* C;        /* device pointer */
+    int64_t ldc;
+} ffp_job;
+
+/* Runs njobs independent products lower(C_j) <- alpha_j A_j A_j^T +
+ * beta_j lower(C_j) mod p_j as grouped launches: jobs of the same base
+ * path share one launch of the product kernel, with work ordered longest
+ * first.  Each result is bit-identical to the job run alone by fsyrk_modp.
+ * jobs is a host array; flags as for fsyrk_modp (applied to every job).
+ * Errors: as fsyrk_modp, checked for every job before anything is
+ * enqueued. */
+int fsyrk_modp_batched(int njobs, const ffp_job* jobs, unsigned flags, void* stream);
+
+/* Human-readable name of a status code. */
+const char* ffp_strerror(int status);
+
+/* Library version string. */
+const char* ffp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFP_H */

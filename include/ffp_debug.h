@@ -1,0 +1,65 @@
+/*
+ * ffp_debug.h -- host-only introspection entry points of the ffp library.
+ * None of these touches a device; they exist so that the host logic (the
+ * field routines of Section 3.1 and the schedules of Tables 3 and 4) can be
+ * checked without a GPU.
+ */
+#ifndef FFP_DEBUG_H
+#define FFP_DEBUG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Skew-orthogonal Y = [[ya I, yb I], [-yb I, ya I]] chosen for p (Proposition
+ * 3.3 when p = 1 mod 4; a = 1, b = sqrt(-2) when p = 3 mod 8; Algorithm 3
+ * otherwise) and its cost y of Theorem 4.1.  FFP_EPRIME if p is not an odd
+ * prime. */
+int ffp_field_info(uint32_t p, uint32_t* ya, uint32_t* yb, int* ycost);
+
+/* Canonical square root min(r, p-r) of a mod p; FFP_EINVAL if a is not a
+ * square, FFP_EPRIME if p is not an odd prime. */
+int ffp_host_sqrt(uint32_t a, uint32_t p, uint32_t* r);
+
+/* Algorithm 3 (SoS): a^2 + b^2 = k mod p. */
+int ffp_host_sos(uint32_t p, uint32_t k, uint32_t* a, uint32_t* b);
+
+/* Algorithm 4 (nrsyf): Y (row-major 2x2) with Y Y^T = diag(alpha, beta) for
+ * two quadratic non-residues; FFP_EINVAL if either is a residue. */
+int ffp_host_nrsyf(uint32_t p, uint32_t alpha, uint32_t beta, uint32_t Y[4]);
+
+/* Text description of the schedule fsyrk_modp would run for these
+ * arguments (device pointers are taken as 16-byte aligned).  Writes at most
+ * len bytes (NUL-terminated) to buf and returns the full length, or a
+ * negative FFP_* status.  Format: a header line
+ *   "plan cls=<c> depth=<d> n_pad=<n> k_pad=<k> ws=<bytes> ya=<a> yb=<b>"
+ * then one line per operation:
+ *   "op kind cls src_cls mode m n k m_src k_src alpha beta level" followed
+ *   by six views "buf off ld plane" (buf 0 = A, 1 = C, 2 = workspace; off in
+ *   bytes, ld and plane in elements of the view's storage). */
+int ffp_plan_describe(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda, int64_t ldc,
+                      uint32_t alpha, uint32_t beta, unsigned flags, char* buf, size_t len);
+
+/* Test hook: cap the delayed-reduction block of the product kernels at kblk
+ * columns of k (rounded down to the kernel's k granularity; 0 restores the
+ * largest exact block).  Process-wide; affects launches made after the
+ * call.  Results stay exact for any cap: it only adds reductions. */
+void ffp_debug_set_kblk(int64_t kblk);
+
+/* Timing hook for benchmarks: while enabled, every product-kernel launch is
+ * bracketed by two HIP events on its stream.  ffp_debug_profile_read waits
+ * for the recorded launches of base-path class cls (0 = FP64, 1 = int8,
+ * 2 = int8 limbs, -1 = all), returns the sum of their durations (ms), of
+ * their algorithmic flops (2 m n k for a general product, n (n+1) k for a
+ * lower-triangle product) and their count, and forgets them. */
+void ffp_debug_profile(int enable);
+int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFP_DEBUG_H */

@@ -1,0 +1,350 @@
+// Block additions of Algorithm 2 and representation changes.
+//
+// These kernels are bound by HBM bandwidth: every thread handles a few
+// elements with coalesced row-major accesses; transposed accesses (the P4
+// versus P4^T reads of the post-additions, the Up/Low copies of Table 4 and
+// of the final mirror) go through 32 x 32 LDS tiles so that global traffic
+// stays coalesced.
+#include "prod_common.h"
+
+namespace ffp {
+
+namespace {
+
+// ---- modular scalar helpers (residues in [0,p), p < 2^25) --------------
+__device__ inline uint32_t add_m(uint32_t a, uint32_t b, uint32_t p)
+{
+    uint32_t s = a + b;
+    return s >= p ? s - p : s;
+}
+__device__ inline uint32_t sub_m(uint32_t a, uint32_t b, uint32_t p)
+{
+    return a >= b ? a - b : a + p - b;
+}
+__device__ inline uint32_t mul_m(uint32_t a, uint32_t b, uint32_t p, double pinv)
+{
+    const uint64_t prod = (uint64_t)a * b;   // < 2^50, exact in double
+    const double q = floor((double)prod * pinv);
+    int64_t r = (int64_t)prod - (int64_t)q * (int64_t)p;
+    if (r < 0) r += p;
+    if (r >= (int64_t)p) r -= p;
+    return (uint32_t)r;
+}
+
+// ---- class storage access ---------------------------------------------
+__device__ inline uint32_t ld_res(int cls, const Fp& f, const DView& v, int64_t i, int64_t j)
+{
+    if (cls == CLS_F64) return ((const uint32_t*)v.p)[i * v.ld + j];
+    if (cls == CLS_I8) {
+        int x = ((const int8_t*)v.p)[i * v.ld + j];
+        return x < 0 ? (uint32_t)(x + (int)f.p) : (uint32_t)x;
+    }
+    const int8_t* b = (const int8_t*)v.p;
+    int x = 256 * (int)b[i * v.ld + j] + (int)b[v.plane + i * v.ld + j];
+    x %= (int)f.p;
+    return x < 0 ? (uint32_t)(x + (int)f.p) : (uint32_t)x;
+}
+
+__device__ inline void st_res(int cls, const Fp& f, const DView& v, int64_t i, int64_t j, uint32_t r)
+{
+    if (cls == CLS_F64) { ((uint32_t*)v.p)[i * v.ld + j] = r; return; }
+    if (cls == CLS_I8) {
+        int x = r > f.half ? (int)r - (int)f.p : (int)r;
+        ((int8_t*)v.p)[i * v.ld + j] = (int8_t)x;
+        return;
+    }
+    // limb pair with value in [-32896, 32639]
+    int x = r <= 32639u ? (int)r : (int)r - (int)f.p;
+    int lo = ((x + 128) & 255) - 128;
+    int hi = (x - lo) >> 8;
+    int8_t* b = (int8_t*)v.p;
+    b[i * v.ld + j] = (int8_t)hi;
+    b[v.plane + i * v.ld + j] = (int8_t)lo;
+}
+
+template <int CLS>
+__global__ __launch_bounds__(256) void preadd_s1s2_kernel(Fp f, int64_t m, int64_t h, DView A11,
+                                                         DView A21, DView A22, DView S1, DView S2)
+{
+    const int64_t ncol = f.yb ? h / 2 : h;   // columns, or column pairs (c, c + h/2)
+    const int64_t h2 = h / 2;
+    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (c >= ncol) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < m; i += (int64_t)gridDim.y * 4) {
+        if (f.yb == 0) {
+            // Y = a I:  S1 = a (A21 - A11),  S2 = A22 - a A21
+            uint32_t a11 = ld_res(CLS, f, A11, i, c), a21 = ld_res(CLS, f, A21, i, c);
+            uint32_t a22 = ld_res(CLS, f, A22, i, c);
+            uint32_t s1 = mul_m(sub_m(a21, a11, f.p), f.ya, f.p, f.pinv);
+            uint32_t s2 = sub_m(a22, mul_m(a21, f.ya, f.p, f.pinv), f.p);
+            st_res(CLS, f, S1, i, c, s1);
+            st_res(CLS, f, S2, i, c, s2);
+        } else {
+            // X Y = [a X_L - b X_R, b X_L + a X_R] for Y = [[aI, bI], [-bI, aI]]
+            const int64_t cl = c, cr = c + h2;
+            uint32_t a11l = ld_res(CLS, f, A11, i, cl), a11r = ld_res(CLS, f, A11, i, cr);
+            uint32_t a21l = ld_res(CLS, f, A21, i, cl), a21r = ld_res(CLS, f, A21, i, cr);
+            uint32_t a22l = ld_res(CLS, f, A22, i, cl), a22r = ld_res(CLS, f, A22, i, cr);
+            uint32_t dl = sub_m(a21l, a11l, f.p), dr = sub_m(a21r, a11r, f.p);
+            uint32_t s1l = sub_m(mul_m(dl, f.ya, f.p, f.pinv), mul_m(dr, f.yb, f.p, f.pinv), f.p);
+            uint32_t s1r = add_m(mul_m(dl, f.yb, f.p, f.pinv), mul_m(dr, f.ya, f.p, f.pinv), f.p);
+            uint32_t tl = sub_m(mul_m(a21l, f.ya, f.p, f.pinv), mul_m(a21r, f.yb, f.p, f.pinv), f.p);
+            uint32_t tr = add_m(mul_m(a21l, f.yb, f.p, f.pinv), mul_m(a21r, f.ya, f.p, f.pinv), f.p);
+            st_res(CLS, f, S1, i, cl, s1l);
+            st_res(CLS, f, S1, i, cr, s1r);
+            st_res(CLS, f, S2, i, cl, sub_m(a22l, tl, f.p));
+            st_res(CLS, f, S2, i, cr, sub_m(a22r, tr, f.p));
+        }
+    }
+}
+
+template <int CLS>
+__global__ __launch_bounds__(256) void preadd_s34_kernel(Fp f, int mode, int64_t m, int64_t h,
+                                                        DView S1, DView A22, DView A12, DView S3,
+                                                        DView S4)
+{
+    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (c >= h) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < m; i += (int64_t)gridDim.y * 4) {
+        uint32_t s3;
+        if (mode & 1) {
+            s3 = sub_m(ld_res(CLS, f, S1, i, c), ld_res(CLS, f, A22, i, c), f.p);   // S3 = S1 - A22
+            st_res(CLS, f, S3, i, c, s3);
+        } else {
+            s3 = ld_res(CLS, f, S3, i, c);
+        }
+        if (mode & 2) {
+            uint32_t s4 = add_m(s3, ld_res(CLS, f, A12, i, c), f.p);               // S4 = S3 + A12
+            st_res(CLS, f, S4, i, c, s4);
+        }
+    }
+}
+
+constexpr int T = 32;
+
+__global__ __launch_bounds__(256) void postadd_kernel(Fp f, int m, const uint32_t* __restrict__ P1,
+                                                     int64_t ld1, const uint32_t* __restrict__ P5,
+                                                     int64_t ld5, uint32_t* C22, int64_t ld22,
+                                                     uint32_t* C21, int64_t ld21, uint32_t beta,
+                                                     const uint32_t* __restrict__ up, int64_t ldu,
+                                                     const uint32_t* __restrict__ dvec)
+{
+    __shared__ uint32_t sU1[T][T + 1];   // U1 on tile (bi,bj), lower elements
+    __shared__ uint32_t sT[T][T + 1];    // P4^T tile (bi,bj)
+    __shared__ uint32_t sTt[T][T + 1];   // P4^T tile (bj,bi)
+    __shared__ uint32_t sUp[T][T + 1];   // C11 tile (bj,bi): saved Low(C22)^T
+    int bi, bj;
+    tri_index(blockIdx.x, &bi, &bj);
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const uint32_t p = f.p;
+
+    for (int rr = ty; rr < T; rr += 8) {
+        const int I = bi * T + rr, J = bj * T + tx;        // element of tile (bi,bj)
+        const int Jr = bj * T + rr, Ic = bi * T + tx;      // element of tile (bj,bi)
+        if (I < m && J < m) {
+            sT[rr][tx] = C22[(int64_t)I * ld22 + J];
+            if (I >= J) sU1[rr][tx] = add_m(P1[(int64_t)I * ld1 + J], P5[(int64_t)I * ld5 + J], p);
+        }
+        if (Jr < m && Ic < m) {
+            sTt[rr][tx] = C22[(int64_t)Jr * ld22 + Ic];
+            if (beta) sUp[rr][tx] = up[(int64_t)Jr * ldu + Ic];
+        }
+    }
+    __syncthreads();
+
+    // lower tile (bi,bj): U4 -> C21, U5 -> C22
+    for (int rr = ty; rr < T; rr += 8) {
+        const int I = bi * T + rr, J = bj * T + tx;
+        if (I >= m || J >= m || I < J) continue;
+        const uint32_t u1 = sU1[rr][tx];
+        const uint32_t u2 = add_m(u1, sTt[tx][rr], p);                 // + P4[I][J] = P4^T[J][I]
+        uint32_t* c21 = C21 + (int64_t)I * ld21 + J;
+        *c21 = add_m(u2, *c21, p);                                      // U4 = U2 + P3
+        uint32_t u5 = add_m(u2, sT[rr][tx], p);                        // U5 = U2 + P4^T
+        if (beta) {
+            const uint32_t cin = (I == J) ? dvec[I] : sUp[tx][rr];     // C22_in[I][J]
+            u5 = add_m(u5, mul_m(beta, cin, p, f.pinv), p);
+        }
+        C22[(int64_t)I * ld22 + J] = u5;
+    }
+    // upper tile (bj,bi): element (J, I) with I > J, U4 only
+    for (int rr = ty; rr < T; rr += 8) {
+        const int Jr = bj * T + rr, Ic = bi * T + tx;                  // position (Jr, Ic), Ic > Jr
+        if (Jr >= m || Ic >= m || Ic <= Jr) continue;
+        const uint32_t u1 = sU1[tx][rr];                               // U1[Ic][Jr] (symmetric)
+        const uint32_t u2 = add_m(u1, sT[tx][rr], p);                  // + P4[Jr][Ic] = P4^T[Ic][Jr]
+        uint32_t* c21 = C21 + (int64_t)Jr * ld21 + Ic;
+        *c21 = add_m(u2, *c21, p);
+    }
+}
+
+__global__ __launch_bounds__(256) void add_lower_kernel(uint32_t p, int64_t m, const uint32_t* X,
+                                                       int64_t ldx, const uint32_t* Y, int64_t ldy,
+                                                       uint32_t* Z, int64_t ldz)
+{
+    const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < m; i += (int64_t)gridDim.y * 4) {
+        if (j > i) continue;
+        Z[i * ldz + j] = add_m(X[i * ldx + j], Y[i * ldy + j], p);
+    }
+}
+
+// dst[J][I] = src[I][J] for I > J (lower tile (bi,bj) -> upper tile (bj,bi));
+// dvec[I] = src[I][I] when dvec is not null.
+__global__ __launch_bounds__(256) void lower_to_upper_kernel(int m, const uint32_t* src, int64_t lds,
+                                                            uint32_t* dst, int64_t ldd,
+                                                            uint32_t* dvec)
+{
+    __shared__ uint32_t s[T][T + 1];
+    int bi, bj;
+    tri_index(blockIdx.x, &bi, &bj);
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int rr = ty; rr < T; rr += 8) {
+        const int I = bi * T + rr, J = bj * T + tx;
+        if (I < m && J < m && I >= J) {
+            const uint32_t v = src[(int64_t)I * lds + J];
+            s[rr][tx] = v;
+            if (I == J && dvec) dvec[I] = v;
+        }
+    }
+    __syncthreads();
+    for (int rr = ty; rr < T; rr += 8) {
+        const int Jr = bj * T + rr, Ic = bi * T + tx;   // destination (Jr, Ic), Ic > Jr
+        if (Jr < m && Ic < m && Ic > Jr) dst[(int64_t)Jr * ldd + Ic] = s[tx][rr];
+    }
+}
+
+template <int SRC, int DST>
+__global__ __launch_bounds__(256) void pack_kernel(Fp f, DView src, int64_t n, int64_t k, DView dst,
+                                                  int64_t n_pad, int64_t k_pad)
+{
+    const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (j >= k_pad) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < n_pad; i += (int64_t)gridDim.y * 4) {
+        uint32_t r = (i < n && j < k) ? ld_res(SRC, f, src, i, j) : 0u;
+        st_res(DST, f, dst, i, j, r);
+    }
+}
+
+__global__ __launch_bounds__(256) void copy_u32_kernel(int64_t rows, int64_t cols, const uint32_t* src,
+                                                      int64_t lds, uint32_t* dst, int64_t ldd,
+                                                      int lower_only)
+{
+    const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (j >= cols) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < rows; i += (int64_t)gridDim.y * 4) {
+        if (lower_only && j > i) continue;
+        dst[i * ldd + j] = src[i * lds + j];
+    }
+}
+
+inline dim3 grid2d(int64_t rows, int64_t cols)
+{
+    int64_t gx = (cols + 63) / 64;
+    int64_t gy = (rows + 3) / 4;
+    if (gy > 16384) gy = 16384;
+    if (gx < 1) gx = 1;
+    if (gy < 1) gy = 1;
+    return dim3((unsigned)gx, (unsigned)gy);
+}
+
+inline unsigned tri_blocks(int64_t m)
+{
+    const int64_t t = (m + T - 1) / T;
+    return (unsigned)(t * (t + 1) / 2);
+}
+
+}  // namespace
+
+hipError_t launch_preadd_s1s2(int cls, const Fp& f, int64_t m, int64_t h, DView A11, DView A21,
+                              DView A22, DView S1, DView S2, hipStream_t s)
+{
+    if (m <= 0 || h <= 0) return hipSuccess;
+    const int64_t ncol = f.yb ? h / 2 : h;
+    dim3 g = grid2d(m, ncol);
+    switch (cls) {
+    case CLS_F64: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_F64>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
+    case CLS_I8: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_I8>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
+    default: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_LIMB2>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_preadd_s34(int cls, const Fp& f, int mode, int64_t m, int64_t h, DView S1,
+                             DView A22, DView A12, DView S3, DView S4, hipStream_t s)
+{
+    if (m <= 0 || h <= 0) return hipSuccess;
+    dim3 g = grid2d(m, h);
+    switch (cls) {
+    case CLS_F64: hipLaunchKernelGGL(preadd_s34_kernel<CLS_F64>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
+    case CLS_I8: hipLaunchKernelGGL(preadd_s34_kernel<CLS_I8>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
+    default: hipLaunchKernelGGL(preadd_s34_kernel<CLS_LIMB2>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_postadd(const Fp& f, int64_t m, const uint32_t* P1, int64_t ld1,
+                          const uint32_t* P5, int64_t ld5, uint32_t* C22, int64_t ld22,
+                          uint32_t* C21, int64_t ld21, uint32_t beta, const uint32_t* up_c11,
+                          int64_t ldu, const uint32_t* dvec, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(postadd_kernel, dim3(tri_blocks(m)), dim3(256), 0, s, f, (int)m, P1, ld1, P5,
+                       ld5, C22, ld22, C21, ld21, beta, up_c11, ldu, dvec);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_lower(const Fp& f, int64_t m, const uint32_t* X, int64_t ldx,
+                            const uint32_t* Y, int64_t ldy, uint32_t* Z, int64_t ldz,
+                            hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(add_lower_kernel, grid2d(m, m), dim3(256), 0, s, f.p, m, X, ldx, Y, ldy, Z, ldz);
+    return hipGetLastError();
+}
+
+hipError_t launch_save_c22(int64_t m, const uint32_t* C22, int64_t ld22, uint32_t* C11,
+                           int64_t ld11, uint32_t* dvec, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lower_to_upper_kernel, dim3(tri_blocks(m)), dim3(256), 0, s, (int)m, C22, ld22,
+                       C11, ld11, dvec);
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror_lower(int64_t n, uint32_t* C, int64_t ldc, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lower_to_upper_kernel, dim3(tri_blocks(n)), dim3(256), 0, s, (int)n, C, ldc, C,
+                       ldc, (uint32_t*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const Fp& f, int src_cls, DView src, int64_t n, int64_t k, int dst_cls,
+                       DView dst, int64_t n_pad, int64_t k_pad, hipStream_t s)
+{
+    if (n_pad <= 0 || k_pad <= 0) return hipSuccess;
+    dim3 g = grid2d(n_pad, k_pad);
+#define FFP_PACK(SC, DC)                                                                       \
+    if (src_cls == SC && dst_cls == DC) {                                                      \
+        hipLaunchKernelGGL((pack_kernel<SC, DC>), g, dim3(256), 0, s, f, src, n, k, dst, n_pad, \
+                           k_pad);                                                             \
+        return hipGetLastError();                                                              \
+    }
+    FFP_PACK(CLS_F64, CLS_F64) FFP_PACK(CLS_F64, CLS_I8) FFP_PACK(CLS_F64, CLS_LIMB2)
+    FFP_PACK(CLS_I8, CLS_I8) FFP_PACK(CLS_I8, CLS_F64) FFP_PACK(CLS_LIMB2, CLS_LIMB2)
+    FFP_PACK(CLS_LIMB2, CLS_F64)
+#undef FFP_PACK
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy_u32(int64_t rows, int64_t cols, const uint32_t* src, int64_t lds,
+                           uint32_t* dst, int64_t ldd, int lower_only, hipStream_t s)
+{
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_u32_kernel, grid2d(rows, cols), dim3(256), 0, s, rows, cols, src, lds, dst,
+                       ldd, lower_only);
+    return hipGetLastError();
+}
+
+}  // namespace ffp

@@ -1,0 +1,226 @@
+// C-ABI entry points of the product library (declared in include/ffp.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "ffp.h"
+#include "ffp_debug.h"
+#include "field.h"
+#include "plan.h"
+#include "runtime.h"
+
+using namespace ffp;
+
+namespace {
+
+bool valid_dtype(int d) { return d == FFP_U32 || d == FFP_I8_CENTERED || d == FFP_I8_LIMB2; }
+
+int dtype_cls(int d)
+{
+    switch (d) {
+    case FFP_I8_CENTERED: return CLS_I8;
+    case FFP_I8_LIMB2: return CLS_LIMB2;
+    default: return CLS_F64;
+    }
+}
+
+bool aligned16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
+
+int make_request(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int a_dtype,
+                 uint32_t alpha, uint32_t beta, const uint32_t* C, int64_t ldc, unsigned flags,
+                 PlanRequest* rq)
+{
+    if (n < 0 || k < 0) return FFP_EINVAL;
+    if (!valid_dtype(a_dtype)) return FFP_EDTYPE;
+    if (p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return FFP_EPRIME;
+    if (a_dtype == FFP_I8_CENTERED && p > 251) return FFP_EDTYPE;
+    if (a_dtype == FFP_I8_LIMB2 && p > 65521) return FFP_EDTYPE;
+    if (alpha >= p || beta >= p) return FFP_EINVAL;
+    if (n > 0 && (C == nullptr || ldc < n)) return FFP_EINVAL;
+    if (n > 0 && k > 0 && (A == nullptr || lda < k)) return FFP_EINVAL;
+    if (n > (int64_t)1 << 30 || k > (int64_t)1 << 30) return FFP_EINVAL;
+    rq->n = n;
+    rq->k = k;
+    rq->p = p;
+    rq->a_cls = dtype_cls(a_dtype);
+    rq->lda = lda;
+    rq->ldc = ldc;
+    rq->a_plane = a_dtype == FFP_I8_LIMB2 ? n * lda : 0;
+    rq->alpha = alpha;
+    rq->beta = beta;
+    const unsigned dfield = (flags >> 4) & 0xFu;
+    rq->depth = dfield ? (int)dfield - 1 : -1;
+    rq->fill_upper = (flags & FFP_FILL_UPPER) != 0;
+    rq->force_f64 = (flags & FFP_BASE_F64) != 0;
+    rq->a_aligned16 = aligned16(A);
+    rq->c_aligned16 = aligned16(C);
+    return FFP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fsyrk_modp(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int a_dtype,
+               uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, unsigned flags, void* stream)
+{
+    PlanRequest rq;
+    int st = make_request(n, k, p, A, lda, a_dtype, alpha, beta, C, ldc, flags, &rq);
+    if (st != FFP_OK) return st;
+    if (n == 0) return FFP_OK;
+    Plan pl;
+    st = build_syrk_plan(rq, &pl);
+    if (st != FFP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace* ws = nullptr;
+    st = acquire_workspace(s, (size_t)pl.ws_bytes, 0, &ws);
+    if (st != FFP_OK) return st;
+    return execute_plan(pl, A, C, ws->ptr, s);
+}
+
+int fgemm_modp(int64_t m, int64_t n, int64_t k, uint32_t p, const uint32_t* A, int64_t lda,
+               const uint32_t* B, int64_t ldb, uint32_t alpha, uint32_t beta, uint32_t* C,
+               int64_t ldc, void* stream)
+{
+    if (m < 0 || n < 0 || k < 0) return FFP_EINVAL;
+    if (p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return FFP_EPRIME;
+    if (alpha >= p || beta >= p) return FFP_EINVAL;
+    if (m > 0 && n > 0 && (C == nullptr || ldc < n)) return FFP_EINVAL;
+    if (m > 0 && n > 0 && k > 0 && (A == nullptr || B == nullptr || lda < k || ldb < k))
+        return FFP_EINVAL;
+    if (m > (int64_t)1 << 30 || n > (int64_t)1 << 30 || k > (int64_t)1 << 30) return FFP_EINVAL;
+    if (m == 0 || n == 0) return FFP_OK;
+    FieldPlan f;
+    if (!make_field_plan(p, &f)) return FFP_EPRIME;
+    ProdTask t{};
+    init_task(&t, f);
+    t.A = DView{(void*)A, lda, 0};
+    t.B = DView{(void*)B, ldb, 0};
+    t.C = C;
+    t.ldc = ldc;
+    t.m = (int32_t)m;
+    t.n = (int32_t)n;
+    t.k = (int32_t)k;
+    t.syrk = 0;
+    t.alpha = alpha;
+    t.beta = beta;
+    hipError_t e = launch_products(CLS_F64, &t, 1, nullptr, (hipStream_t)stream);
+    return e == hipSuccess ? FFP_OK : FFP_EDEVICE;
+}
+
+size_t ffp_workspace_bytes(int64_t n, int64_t k, uint32_t p, int a_dtype, unsigned flags)
+{
+    PlanRequest rq;
+    const uint32_t beta = (flags & FFP_WS_BETA) ? 1u : 0u;
+    int64_t lda = a_dtype == FFP_U32 ? k : ((k + 15) / 16) * 16;
+    int64_t ldc = ((n + 3) / 4) * 4;
+    if (make_request(n, k, p, (const void*)16, lda, a_dtype, 1u % p, beta, (const uint32_t*)16, ldc,
+                     flags, &rq) != FFP_OK)
+        return 0;
+    Plan pl;
+    if (build_syrk_plan(rq, &pl) != FFP_OK) return 0;
+    return (size_t)pl.ws_bytes;
+}
+
+const char* ffp_strerror(int status)
+{
+    switch (status) {
+    case FFP_OK: return "ok";
+    case FFP_EINVAL: return "invalid argument";
+    case FFP_EPRIME: return "modulus not prime or out of range for the path";
+    case FFP_EDTYPE: return "operand storage not valid for this modulus";
+    case FFP_ENOMEM: return "device workspace allocation failed";
+    case FFP_EDEVICE: return "HIP runtime error";
+    case FFP_EUNSUPPORTED: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+const char* ffp_version(void) { return "ffp 0.1 (gfx950)"; }
+
+// ---- introspection (host only; no device work) ---------------------------
+
+int ffp_field_info(uint32_t p, uint32_t* ya, uint32_t* yb, int* ycost)
+{
+    FieldPlan f;
+    if (!make_field_plan(p, &f)) return FFP_EPRIME;
+    *ya = f.ya;
+    *yb = f.yb;
+    *ycost = f.ycost;
+    return FFP_OK;
+}
+
+int ffp_host_sqrt(uint32_t a, uint32_t p, uint32_t* r)
+{
+    if (p < 3 || !is_prime_u32(p)) return FFP_EPRIME;
+    uint64_t v = sqrt_mod(a, p);
+    if (v == UINT64_MAX) return FFP_EINVAL;
+    *r = (uint32_t)v;
+    return FFP_OK;
+}
+
+int ffp_host_sos(uint32_t p, uint32_t k, uint32_t* a, uint32_t* b)
+{
+    if (p < 3 || !is_prime_u32(p)) return FFP_EPRIME;
+    uint64_t x, y;
+    sum_of_squares(p, k, &x, &y);
+    *a = (uint32_t)x;
+    *b = (uint32_t)y;
+    return FFP_OK;
+}
+
+int ffp_host_nrsyf(uint32_t p, uint32_t alpha, uint32_t beta, uint32_t Y[4])
+{
+    if (p < 3 || !is_prime_u32(p)) return FFP_EPRIME;
+    uint64_t y[4];
+    if (!nrsyf(p, alpha, beta, y)) return FFP_EINVAL;
+    for (int i = 0; i < 4; ++i) Y[i] = (uint32_t)y[i];
+    return FFP_OK;
+}
+
+int ffp_plan_describe(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda, int64_t ldc,
+                      uint32_t alpha, uint32_t beta, unsigned flags, char* buf, size_t len)
+{
+    PlanRequest rq;
+    int st = make_request(n, k, p, (const void*)16, lda, a_dtype, alpha, beta, (const uint32_t*)16,
+                          ldc, flags, &rq);
+    if (st != FFP_OK) return st;
+    Plan pl;
+    st = build_syrk_plan(rq, &pl);
+    if (st != FFP_OK) return st;
+    std::string s = describe_plan(pl);
+    if (buf && len > 0) {
+        size_t c = s.size() < len - 1 ? s.size() : len - 1;
+        memcpy(buf, s.data(), c);
+        buf[c] = '\0';
+    }
+    return (int)s.size();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+void ffp_debug_set_kblk(int64_t kblk) { ffp::g_kblk_cap = kblk > 0 ? kblk : 0; }
+
+void ffp_debug_profile(int enable) { prof_enable(enable != 0); }
+
+int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches)
+{
+    return prof_read(cls, ms, flops, launches) == 0 ? FFP_OK : FFP_EDEVICE;
+}
+
+int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, void* stream)
+{
+    (void)n; (void)p; (void)S; (void)lds; (void)info; (void)stream;
+    return FFP_EUNSUPPORTED;
+}
+
+int fsyrk_modp_batched(int njobs, const ffp_job* jobs, unsigned flags, void* stream)
+{
+    (void)njobs; (void)jobs; (void)flags; (void)stream;
+    return FFP_EUNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Device kernels of the product library and their host launchers.
+//
+// Operand classes (storage of A and of the pre-added blocks S1..S4):
+//   CLS_F64   uint32 residues in [0,p); products run on FP64 matrix cores
+//             (v_mfma_f64_16x16x4f64) on centered values, delayed reduction.
+//   CLS_I8    int8 centered residues, p <= 251; int8 matrix cores with int32
+//             accumulation (v_mfma_i32_32x32x32_i8).
+//   CLS_LIMB2 two int8 planes, value 256*hi + lo in [-32896, 32639],
+//             p <= 65521; four limb products per tile, int32 accumulation.
+// Products and every block of C are uint32 residues in [0,p).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ffp {
+
+enum Cls : int32_t { CLS_F64 = 0, CLS_I8 = 1, CLS_LIMB2 = 2 };
+
+// Field constants passed to every kernel.
+struct Fp {
+    uint32_t p;
+    uint32_t half;   // (p-1)/2
+    double pinv;     // 1/p
+    uint32_t ya, yb; // skew-orthogonal Y = [[ya I, yb I], [-yb I, ya I]]
+};
+
+// A strided matrix view: element (i, j) is at base + i*ld + j; for CLS_LIMB2
+// the lo plane is at base + plane + i*ld + j.  Units are elements of the
+// view's storage type.
+struct DView {
+    void* p;
+    int64_t ld;
+    int64_t plane;
+};
+
+// ---- products --------------------------------------------------------
+// One product C <- alpha * A * B^T + beta * C (kind GEMM) or
+// lower(C) <- alpha * A * A^T + beta * lower(C) (kind SYRK), A m x k, B n x k.
+struct ProdTask {
+    DView A, B;
+    uint32_t* C;
+    int64_t ldc;
+    int32_t m, n, k;
+    int32_t syrk;
+    uint32_t p, alpha, beta, half;
+    double pinv;
+    int32_t kblk;     // delayed-reduction block length (FP64 class)
+    int32_t tm, tn;   // tile grid (rows, cols)
+    int32_t tile0;    // first global tile index
+};
+
+constexpr int kInlineTasks = 6;
+struct ProdArgs {
+    int32_t ntasks;
+    int32_t total_tiles;
+    const ProdTask* dev_tasks;       // used when ntasks > kInlineTasks
+    ProdTask inl[kInlineTasks];
+};
+
+// Tile shapes of the product kernels (output rows x cols per workgroup).
+constexpr int kF64TileM = 64, kF64TileN = 64;
+constexpr int kI8TileM = 256, kI8TileN = 256;
+constexpr int kL2TileM = 128, kL2TileN = 128;
+
+int64_t f64_kblk(uint32_t p);   // largest safe delayed-reduction block (multiple of 16)
+
+// Test cap on the delayed-reduction block (0: none).
+extern int64_t g_kblk_cap;
+inline int32_t cap_kblk(int64_t kb, int64_t unit)
+{
+    if (g_kblk_cap > 0 && g_kblk_cap < kb) kb = g_kblk_cap - g_kblk_cap % unit;
+    if (kb < unit) kb = unit;
+    return (int32_t)kb;
+}
+
+
+// ---- block additions (Algorithm 2, Tables 3 and 4) ---------------------
+// S1 = (A21 - A11) Y, S2 = A22 - A21 Y on m x h blocks.
+hipError_t launch_preadd_s1s2(int cls, const Fp& f, int64_t m, int64_t h, DView A11, DView A21,
+                              DView A22, DView S1, DView S2, hipStream_t s);
+// mode 1: S3 = S1 - A22 written to S3;  mode 2: S4 = S3 + A12 written to S4;
+// mode 3: both (S3 from S1, then S4 from that S3).  In-place aliasing of the
+// destination with the source block is allowed.
+hipError_t launch_preadd_s34(int cls, const Fp& f, int mode, int64_t m, int64_t h, DView S1,
+                             DView A22, DView A12, DView S3, DView S4, hipStream_t s);
+// Fused U1 = P1 + P5, U2 = U1 + P4, U4 = U2 + P3 -> C21 (all of it) and
+// U5 = U2 + P4^T (+ beta * C22_in) -> lower(C22).  P1, P5 lower triangles;
+// P4T = P4^T full (stored in C22, overwritten); P3 full (stored in C21,
+// overwritten).  When beta != 0, the strictly lower part of the input C22
+// is read transposed from the upper triangle of `up_c11` and its diagonal
+// from `dvec`.
+hipError_t launch_postadd(const Fp& f, int64_t m, const uint32_t* P1, int64_t ld1,
+                          const uint32_t* P5, int64_t ld5, uint32_t* C22, int64_t ld22,
+                          uint32_t* C21, int64_t ld21, uint32_t beta, const uint32_t* up_c11,
+                          int64_t ldu, const uint32_t* dvec, hipStream_t s);
+// lower(Z) = lower(X) + lower(Y) (Z may alias X or Y).
+hipError_t launch_add_lower(const Fp& f, int64_t m, const uint32_t* X, int64_t ldx,
+                            const uint32_t* Y, int64_t ldy, uint32_t* Z, int64_t ldz,
+                            hipStream_t s);
+// Up(C11) = Low(C22)^T strictly, dvec = diag(C22) (Table 4, with the
+// diagonal kept in its own vector).
+hipError_t launch_save_c22(int64_t m, const uint32_t* C22, int64_t ld22, uint32_t* C11,
+                           int64_t ld11, uint32_t* dvec, hipStream_t s);
+// Up(C) = Low(C)^T.
+hipError_t launch_mirror_lower(int64_t n, uint32_t* C, int64_t ldc, hipStream_t s);
+
+// ---- representation changes ----------------------------------------
+// Copy an n x k block of uint32 residues (or int8 / limb storage of class
+// src_cls) into the storage of class dst_cls, zero-padding to n_pad x
+// k_pad.  Source values must be valid residues of their storage.
+hipError_t launch_pack(const Fp& f, int src_cls, DView src, int64_t n, int64_t k, int dst_cls,
+                       DView dst, int64_t n_pad, int64_t k_pad, hipStream_t s);
+// Copy the lower triangle (or all, if full) of an n x n uint32 block.
+hipError_t launch_copy_u32(int64_t rows, int64_t cols, const uint32_t* src, int64_t lds,
+                           uint32_t* dst, int64_t ldd, int lower_only, hipStream_t s);
+
+}  // namespace ffp

@@ -1,0 +1,360 @@
+// Schedule builder for fsyrk_modp (host only, no device calls).
+#include "plan.h"
+
+#include <algorithm>
+#include <cstdio>
+
+#include "ffp.h"
+
+namespace ffp {
+
+namespace {
+
+int64_t elem_size(int cls) { return cls == CLS_F64 ? 4 : 1; }
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+PView sub(const PView& v, int64_t r, int64_t c, int64_t es)
+{
+    PView o = v;
+    o.off += (r * v.ld + c) * es;
+    return o;
+}
+
+struct Builder {
+    int cls;
+    Fp fp;
+    bool yb_nonzero;
+    int64_t ws_top = 0, ws_max = 0;
+    std::vector<Op>* ops;
+
+    int64_t es() const { return elem_size(cls); }
+
+    int64_t alloc(int64_t bytes)
+    {
+        const int64_t off = round_up(ws_top, 256);
+        ws_top = off + bytes;
+        ws_max = std::max(ws_max, ws_top);
+        return off;
+    }
+
+    // uint32 m x c matrix in the workspace
+    PView ws_u32(int64_t rows, int64_t cols)
+    {
+        PView v;
+        v.buf = BUF_WS;
+        v.ld = std::max<int64_t>(cols, 1);
+        v.off = alloc(rows * v.ld * 4);
+        return v;
+    }
+
+    // operand-class rows x cols matrix in the workspace
+    PView ws_opnd(int64_t rows, int64_t cols)
+    {
+        PView v;
+        v.buf = BUF_WS;
+        v.ld = round_up(std::max<int64_t>(cols, 1), 16);
+        const int64_t planes = cls == CLS_LIMB2 ? 2 : 1;
+        v.off = alloc(rows * v.ld * es() * planes);
+        v.plane = cls == CLS_LIMB2 ? rows * v.ld : 0;
+        return v;
+    }
+
+    // operand-class m x h matrix stored inside an m x m uint32 block (h <= m)
+    PView in_block(const PView& blk, int64_t h) const
+    {
+        PView v = blk;
+        v.ld = blk.ld * 4 / es();
+        v.plane = cls == CLS_LIMB2 ? h : 0;
+        return v;
+    }
+
+    void emit(const Op& o) { ops->push_back(o); }
+
+    Op op(OpKind kind, int level) const
+    {
+        Op o;
+        o.kind = kind;
+        o.cls = cls;
+        o.level = level;
+        return o;
+    }
+
+    void prod_syrk(int level, int64_t n, int64_t k, const PView& A, uint32_t alpha, uint32_t beta,
+                   const PView& C)
+    {
+        Op o = op(OP_SYRK, level);
+        o.m = o.n = n;
+        o.k = k;
+        o.alpha = alpha;
+        o.beta = beta;
+        o.v[0] = A;
+        o.v[1] = C;
+        emit(o);
+    }
+
+    void prod_gemm(int level, int64_t m, int64_t n, int64_t k, const PView& A, const PView& B,
+                   uint32_t alpha, uint32_t beta, const PView& C)
+    {
+        Op o = op(OP_GEMM, level);
+        o.m = m;
+        o.n = n;
+        o.k = k;
+        o.alpha = alpha;
+        o.beta = beta;
+        o.v[0] = A;
+        o.v[1] = B;
+        o.v[2] = C;
+        emit(o);
+    }
+
+    // Table 3: lower(C) <- alpha A A^T, with C's strict upper triangle as the
+    // only temporary when k <= n; two m x h workspace blocks otherwise.
+    void syrk3(int d, int level, int64_t n, int64_t k, const PView& A, uint32_t alpha, const PView& C)
+    {
+        if (d == 0) { prod_syrk(level, n, k, A, alpha, 0, C); return; }
+        const int64_t m = n / 2, h = k / 2, e = es();
+        const PView A11 = sub(A, 0, 0, e), A12 = sub(A, 0, h, e), A21 = sub(A, m, 0, e),
+                    A22 = sub(A, m, h, e);
+        const PView C11 = sub(C, 0, 0, 4), C12 = sub(C, 0, m, 4), C21 = sub(C, m, 0, 4),
+                    C22 = sub(C, m, m, 4);
+        const int64_t save = ws_top;
+        PView S1, S2, S4;
+        if (h <= m) {
+            S1 = in_block(C21, h);    // S1, then S3 in place
+            S2 = in_block(C12, h);
+            S4 = in_block(C11, h);
+        } else {
+            S1 = ws_opnd(m, h);
+            S2 = ws_opnd(m, h);
+            S4 = S2;                  // S2 is dead once P4^T is formed
+        }
+        Op a = op(OP_S1S2, level);
+        a.m = m; a.k = h;
+        a.v[0] = A11; a.v[1] = A21; a.v[2] = A22; a.v[3] = S1; a.v[4] = S2;
+        emit(a);
+        prod_gemm(level, m, m, h, S2, S1, alpha, 0, C22);                  // P4^T = S2 S1^T
+        Op b = op(OP_S34, level);
+        b.mode = 3; b.m = m; b.k = h;
+        b.v[0] = S1; b.v[1] = A22; b.v[2] = A12; b.v[3] = S1; b.v[4] = S4;
+        emit(b);                                                            // S3 = S1 - A22, S4 = S3 + A12
+        syrk3(d - 1, level + 1, m, h, S1, alpha, C12);                     // P5 = S3 S3^T
+        prod_gemm(level, m, m, h, A22, S4, alpha, 0, C21);                 // P3 = A22 S4^T
+        syrk3(d - 1, level + 1, m, h, A11, alpha, C11);                    // P1 = A11 A11^T
+        Op c = op(OP_POSTADD, level);
+        c.m = m;
+        c.v[0] = C11; c.v[1] = C12; c.v[2] = C22; c.v[3] = C21;
+        emit(c);                                                            // U1, U2, U4 -> C21, U5 -> C22
+        syrk3(d - 1, level + 1, m, h, A12, alpha, C12);                    // P2 = A12 A12^T
+        Op u = op(OP_ADDLOW, level);
+        u.m = m;
+        u.v[0] = C11; u.v[1] = C12; u.v[2] = C11;
+        emit(u);                                                            // U3 = P1 + P2
+        ws_top = save;
+    }
+
+    // Table 4: lower(C) <- alpha A A^T + beta lower(C), with C12 and one
+    // m x m block tmp as temporaries, plus an m-vector keeping diag(C22),
+    // which Up(C11) cannot hold.
+    void syrk4(int d, int level, int64_t n, int64_t k, const PView& A, uint32_t alpha,
+               uint32_t beta, const PView& C)
+    {
+        if (d == 0) { prod_syrk(level, n, k, A, alpha, beta, C); return; }
+        const int64_t m = n / 2, h = k / 2, e = es();
+        const PView A11 = sub(A, 0, 0, e), A12 = sub(A, 0, h, e), A21 = sub(A, m, 0, e),
+                    A22 = sub(A, m, h, e);
+        const PView C11 = sub(C, 0, 0, 4), C12 = sub(C, 0, m, 4), C21 = sub(C, m, 0, 4),
+                    C22 = sub(C, m, m, 4);
+        const int64_t save = ws_top;
+        const PView tmp = ws_u32(m, round_up(m, 4));
+        const PView dvec = ws_u32(1, m);
+        PView S1, S2;
+        if (h <= m) {
+            S1 = in_block(tmp, h);     // S1 -> S3 -> S4 in place
+            S2 = in_block(C12, h);
+        } else {
+            S1 = ws_opnd(m, h);
+            S2 = ws_opnd(m, h);
+        }
+        Op a = op(OP_S1S2, level);
+        a.m = m; a.k = h;
+        a.v[0] = A11; a.v[1] = A21; a.v[2] = A22; a.v[3] = S1; a.v[4] = S2;
+        emit(a);
+        Op sv = op(OP_SAVEC22, level);
+        sv.m = m;
+        sv.v[0] = C22; sv.v[1] = C11; sv.v[2] = dvec;
+        emit(sv);                                                            // Up(C11) = Low(C22)^T, diag
+        prod_gemm(level, m, m, h, S2, S1, alpha, 0, C22);                  // P4^T = alpha S2 S1^T
+        Op b3 = op(OP_S34, level);
+        b3.mode = 1; b3.m = m; b3.k = h;
+        b3.v[0] = S1; b3.v[1] = A22; b3.v[2] = A12; b3.v[3] = S1; b3.v[4] = S1;
+        emit(b3);                                                           // S3 = S1 - A22
+        syrk3(d - 1, level + 1, m, h, S1, alpha, C12);                     // P5 = alpha S3 S3^T
+        Op b4 = op(OP_S34, level);
+        b4.mode = 2; b4.m = m; b4.k = h;
+        b4.v[0] = S1; b4.v[1] = A22; b4.v[2] = A12; b4.v[3] = S1; b4.v[4] = S1;
+        emit(b4);                                                           // S4 = S3 + A12
+        prod_gemm(level, m, m, h, A22, S1, alpha, beta, C21);              // P3 = alpha A22 S4^T + beta C21
+        syrk3(d - 1, level + 1, m, h, A11, alpha, tmp);                    // P1 = alpha A11 A11^T
+        Op c = op(OP_POSTADD, level);
+        c.m = m;
+        c.beta = beta;
+        c.v[0] = tmp; c.v[1] = C12; c.v[2] = C22; c.v[3] = C21; c.v[4] = C11; c.v[5] = dvec;
+        emit(c);                                                            // U4, U5 (+ beta C22)
+        syrk4(d - 1, level + 1, m, h, A12, alpha, beta, C11);              // P2 = alpha A12 A12^T + beta C11
+        Op u = op(OP_ADDLOW, level);
+        u.m = m;
+        u.v[0] = tmp; u.v[1] = C11; u.v[2] = C11;
+        emit(u);                                                            // U3 = P1 + P2
+        ws_top = save;
+    }
+};
+
+}  // namespace
+
+int choose_class(uint32_t p, int a_cls, bool force_f64)
+{
+    if (a_cls == CLS_I8) return CLS_I8;
+    if (a_cls == CLS_LIMB2) return CLS_LIMB2;
+    if (force_f64) return CLS_F64;
+    if (p <= 251) return CLS_I8;
+    if (p <= 65521) return CLS_LIMB2;
+    return CLS_F64;
+}
+
+int default_depth(int cls, int64_t n, int64_t k)
+{
+    // Each level trades one eighth of the multiply-adds (5 products instead
+    // of 6 on half-size blocks, Table 1) for HBM-bound block additions.  On
+    // FP64 matrix cores that trade pays while the leaves stay large enough
+    // to fill the chip; on int8 matrix cores the additions cost more than
+    // the saved products at every size measured, so no recursion.
+    if (cls != CLS_F64) return 0;
+    int d = 0;
+    int64_t nn = std::min(n, 2 * k);
+    while (d < 4 && (nn >> (d + 1)) >= 1024) ++d;
+    return d;
+}
+
+int build_syrk_plan(const PlanRequest& rq, Plan* out)
+{
+    if (rq.n < 0 || rq.k < 0) return FFP_EINVAL;
+    Plan pl;
+    if (!make_field_plan(rq.p, &pl.field)) return FFP_EPRIME;
+    if (rq.p >= (1u << 25)) return FFP_EPRIME;
+    pl.cls = choose_class(rq.p, rq.a_cls, rq.force_f64);
+    if (pl.cls == CLS_I8 && rq.p > 251) return FFP_EDTYPE;
+    if (pl.cls == CLS_LIMB2 && rq.p > 65521) return FFP_EDTYPE;
+    const int64_t n = rq.n, k = rq.k;
+
+    int d = rq.depth >= 0 ? rq.depth : default_depth(pl.cls, n, k);
+    while (d > 0 && (n >> d) < 8) --d;
+    if (k == 0) d = 0;
+    pl.depth = d;
+
+    const int64_t es_op = elem_size(pl.cls);
+    const int64_t kunit = ((pl.cls == CLS_F64) ? 4 : 64) << (d + (pl.field.yb ? 1 : 0));
+    const int64_t nunit = d > 0 ? (int64_t)4 << d : 1;
+    const int64_t n_pad = n == 0 ? 0 : round_up(n, nunit);
+    const int64_t k_pad = k == 0 ? 0 : round_up(k, (pl.cls == CLS_F64 && d == 0) ? 1 : kunit);
+    pl.n_pad = n_pad;
+    pl.k_pad = k_pad;
+
+    Builder B;
+    B.cls = pl.cls;
+    B.fp = Fp{rq.p, (rq.p - 1) / 2, pl.field.pinv, pl.field.ya, pl.field.yb};
+    B.yb_nonzero = pl.field.yb != 0;
+    B.ops = &pl.ops;
+
+    // Operand: pack when the class, the shape or the alignment differ.
+    PView A;
+    A.buf = BUF_A;
+    A.off = 0;
+    A.ld = rq.lda;
+    A.plane = rq.a_plane;
+    bool a_ok = (pl.cls == rq.a_cls) && n_pad == n && k_pad == k;
+    if (pl.cls == CLS_F64) a_ok = a_ok && (d == 0 || ((rq.lda % 4) == 0 && rq.a_aligned16));
+    else a_ok = a_ok && (rq.lda % 16) == 0 && rq.a_aligned16 &&
+                (pl.cls != CLS_LIMB2 || (rq.a_plane % 16) == 0);
+    if (!a_ok && n_pad > 0 && k_pad > 0) {
+        PView Ap = B.ws_opnd(n_pad, k_pad);
+        Op o = B.op(OP_PACK, 0);
+        o.src_cls = rq.a_cls;
+        o.m = n_pad; o.k = k_pad; o.m_src = n; o.k_src = k;
+        o.v[0] = A; o.v[1] = Ap;
+        B.emit(o);
+        A = Ap;
+    }
+    (void)es_op;
+
+    // Output: a padded copy when n is padded or C's layout breaks alignment.
+    PView C;
+    C.buf = BUF_C;
+    C.ld = rq.ldc;
+    bool c_copy = n_pad != n || (d > 0 && ((rq.ldc % 4) != 0 || !rq.c_aligned16));
+    PView Cw = C;
+    if (c_copy && n_pad > 0) {
+        Cw = B.ws_u32(n_pad, round_up(n_pad, 4));
+        Op o = B.op(OP_PACK, 0);
+        o.cls = CLS_F64;
+        o.src_cls = CLS_F64;
+        o.m = n_pad; o.k = n_pad; o.m_src = rq.beta ? n : 0; o.k_src = rq.beta ? n : 0;
+        o.v[0] = C; o.v[1] = Cw;
+        B.emit(o);                 // zero-padded copy (copies C only when beta != 0)
+    }
+
+    if (n_pad > 0) {
+        if (k_pad == 0) {
+            // A A^T = 0: lower(C) <- beta lower(C), as a product with k = 0
+            B.prod_syrk(0, n_pad, 0, A, rq.alpha, rq.beta, Cw);
+        } else if (rq.beta == 0) {
+            B.syrk3(d, 0, n_pad, k_pad, A, rq.alpha, Cw);
+        } else {
+            B.syrk4(d, 0, n_pad, k_pad, A, rq.alpha, rq.beta, Cw);
+        }
+    }
+
+    if (c_copy && n > 0) {
+        Op o = B.op(OP_COPY, 0);
+        o.cls = CLS_F64;
+        o.mode = 1;
+        o.m = n; o.n = n;
+        o.v[0] = Cw; o.v[1] = C;
+        B.emit(o);
+    }
+    if (rq.fill_upper && n > 0) {
+        Op o = B.op(OP_MIRROR, 0);
+        o.cls = CLS_F64;
+        o.m = n;
+        o.v[0] = C;
+        B.emit(o);
+    }
+    pl.ws_bytes = B.ws_max;
+    *out = std::move(pl);
+    return FFP_OK;
+}
+
+std::string describe_plan(const Plan& pl)
+{
+    std::string s;
+    char buf[512];
+    snprintf(buf, sizeof buf, "plan cls=%d depth=%d n_pad=%lld k_pad=%lld ws=%lld ya=%u yb=%u\n",
+             pl.cls, pl.depth, (long long)pl.n_pad, (long long)pl.k_pad, (long long)pl.ws_bytes,
+             pl.field.ya, pl.field.yb);
+    s += buf;
+    for (const Op& o : pl.ops) {
+        snprintf(buf, sizeof buf, "op %d %d %d %d %lld %lld %lld %lld %lld %u %u %d", (int)o.kind, o.cls,
+                 o.src_cls, o.mode, (long long)o.m, (long long)o.n, (long long)o.k,
+                 (long long)o.m_src, (long long)o.k_src, o.alpha, o.beta, o.level);
+        s += buf;
+        for (int i = 0; i < 6; ++i) {
+            snprintf(buf, sizeof buf, " %d %lld %lld %lld", o.v[i].buf, (long long)o.v[i].off,
+                     (long long)o.v[i].ld, (long long)o.v[i].plane);
+            s += buf;
+        }
+        s += "\n";
+    }
+    return s;
+}
+
+}  // namespace ffp

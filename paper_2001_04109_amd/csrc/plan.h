@@ -1,0 +1,81 @@
+// Host-side schedule of one fsyrk_modp call: a list of block operations on
+// views of three buffers (the operand A, the output C and the library's
+// workspace), built without touching the device.  The schedule follows
+// Algorithm 2 with the placements of Table 3 (beta = 0) and Table 4
+// (beta != 0), recursing depth-first.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "field.h"
+#include "kernels.h"
+
+namespace ffp {
+
+enum BufId : int32_t { BUF_A = 0, BUF_C = 1, BUF_WS = 2, BUF_A_LO = 3 };
+
+// View of a matrix inside one buffer.  `off` is in bytes from the buffer
+// start; `ld` and `plane` are in elements of the view's storage type.
+struct PView {
+    int32_t buf = BUF_WS;
+    int64_t off = 0;
+    int64_t ld = 0;
+    int64_t plane = 0;
+};
+
+enum OpKind : int32_t {
+    OP_S1S2 = 0,     // v0=A11 v1=A21 v2=A22 -> v3=S1 v4=S2      (m x k blocks)
+    OP_S34 = 1,      // mode bit0: v3=S3 <- v0=S1 - v1=A22; bit1: v4=S4 <- S3 + v2=A12
+    OP_GEMM = 2,     // v2 <- alpha v0 v1^T + beta v2   (m x n, inner k)
+    OP_SYRK = 3,     // lower(v1) <- alpha v0 v0^T + beta lower(v1)   (n = m)
+    OP_POSTADD = 4,  // v0=P1 v1=P5 v2=C22(P4^T) v3=C21(P3) [beta: v4=Up(C11) v5=dvec]
+    OP_ADDLOW = 5,   // lower(v2) <- lower(v0) + lower(v1)
+    OP_SAVEC22 = 6,  // Up(v1) <- Low(v0)^T strictly, v2 <- diag(v0)
+    OP_MIRROR = 7,   // Up(v0) <- Low(v0)^T
+    OP_PACK = 8,     // v1 (class cls, m x k padded from n x k... see pack_*) <- v0 (class src_cls)
+    OP_COPY = 9,     // v1 <- v0 (m x n uint32), mode 1: lower triangle only
+};
+
+struct Op {
+    OpKind kind;
+    int32_t cls = CLS_F64;      // storage class of operand views (S, A)
+    int32_t src_cls = CLS_F64;  // OP_PACK source class
+    int32_t mode = 0;
+    int64_t m = 0, n = 0, k = 0;
+    int64_t m_src = 0, k_src = 0;  // OP_PACK: valid source extent
+    uint32_t alpha = 1, beta = 0;
+    int32_t level = 0;          // recursion level that emitted the op
+    PView v[6];
+};
+
+struct PlanRequest {
+    int64_t n = 0, k = 0;
+    uint32_t p = 0;
+    int32_t a_cls = CLS_F64;     // storage class of the caller's A
+    int64_t lda = 0, ldc = 0;
+    int64_t a_plane = 0;         // LIMB2: element offset of the lo plane
+    uint32_t alpha = 1, beta = 0;
+    int32_t depth = -1;          // -1: tuned default
+    bool fill_upper = false;
+    bool force_f64 = false;
+    bool a_aligned16 = true;     // caller's A pointer is 16-byte aligned
+    bool c_aligned16 = true;
+};
+
+struct Plan {
+    FieldPlan field;
+    int32_t cls = CLS_F64;       // base path class
+    int32_t depth = 0;
+    int64_t n_pad = 0, k_pad = 0;
+    int64_t ws_bytes = 0;
+    std::vector<Op> ops;
+};
+
+// Returns FFP_* status (0 on success).
+int build_syrk_plan(const PlanRequest& rq, Plan* out);
+int choose_class(uint32_t p, int a_cls, bool force_f64);
+int default_depth(int cls, int64_t n, int64_t k);
+std::string describe_plan(const Plan& pl);
+
+}  // namespace ffp

@@ -1,0 +1,60 @@
+// Device helpers shared by the product kernels: task lookup, triangular tile
+// enumeration and the XCD-aware block order.
+#pragma once
+#include "kernels.h"
+
+namespace ffp {
+
+// Copy the task that owns global tile g into registers.  Tasks are sorted by
+// tile0; the search is uniform across the workgroup.
+__device__ inline void select_task(const ProdArgs& a, int g, ProdTask* out)
+{
+    if (a.ntasks <= kInlineTasks) {
+        int idx = 0;
+#pragma unroll
+        for (int i = 1; i < kInlineTasks; ++i)
+            if (i < a.ntasks && g >= a.inl[i].tile0) idx = i;
+#pragma unroll
+        for (int i = 0; i < kInlineTasks; ++i)
+            if (i == idx) *out = a.inl[i];
+        return;
+    }
+    int lo = 0, hi = a.ntasks - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.dev_tasks[mid].tile0 <= g) lo = mid; else hi = mid - 1;
+    }
+    *out = a.dev_tasks[lo];
+}
+
+// r-th tile (row-major over the lower triangle) -> (ti, tj), tj <= ti.
+__device__ inline void tri_index(int r, int* ti, int* tj)
+{
+    int i = (int)((sqrtf(8.0f * (float)r + 1.0f) - 1.0f) * 0.5f);
+    while ((i + 1) * (i + 2) / 2 <= r) ++i;
+    while (i * (i + 1) / 2 > r) --i;
+    *ti = i;
+    *tj = r - i * (i + 1) / 2;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).
+// For a launch of one uniform task, give each XCD a contiguous range of
+// tiles so that neighbouring tiles, which share operand panels, meet in the
+// same L2.  `nblocks` is a multiple of 8.
+__device__ inline int xcd_remap(int b, int nblocks)
+{
+    const int per = nblocks >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+__device__ inline double mod_f64(double x, double p, double pinv)
+{
+    // x is an integer with |x| < 2^53; the quotient estimate is off by at most one
+    double q = floor(x * pinv);
+    double r = fma(-q, p, x);
+    if (r < 0.0) r += p;
+    if (r >= p) r -= p;
+    return r;
+}
+
+}  // namespace ffp

@@ -1,0 +1,235 @@
+// Workspace pool and plan executor of the product library.
+#include "runtime.h"
+
+#include <map>
+#include <vector>
+#include <mutex>
+#include <utility>
+
+#include "ffp.h"
+
+namespace ffp {
+
+namespace {
+
+std::mutex g_ws_mutex;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+void* at(const PView& v, const void* a, void* c, void* ws)
+{
+    char* base = nullptr;
+    switch (v.buf) {
+    case BUF_A: base = (char*)a; break;
+    case BUF_C: base = (char*)c; break;
+    default: base = (char*)ws; break;
+    }
+    return base + v.off;
+}
+
+DView dview(const PView& v, const void* a, void* c, void* ws)
+{
+    return DView{at(v, a, c, ws), v.ld, v.plane};
+}
+
+}  // namespace
+
+int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FFP_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    Workspace& w = g_ws[std::make_pair(dev, s)];
+    if (bytes > w.bytes || ntasks > w.task_cap) {
+        if (w.ptr || w.tasks) {
+            if (hipStreamSynchronize(s) != hipSuccess) return FFP_EDEVICE;
+        }
+        if (bytes > w.bytes) {
+            if (w.ptr) (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+            size_t want = bytes + bytes / 4 + 4096;
+            if (hipMalloc(&w.ptr, want) != hipSuccess) {
+                w.ptr = nullptr;
+                (void)hipGetLastError();
+                return FFP_ENOMEM;
+            }
+            w.bytes = want;
+        }
+        if (ntasks > w.task_cap) {
+            if (w.tasks) (void)hipFree(w.tasks);
+            w.tasks = nullptr;
+            w.task_cap = 0;
+            size_t cap = ntasks < 64 ? 64 : ntasks * 2;
+            if (hipMalloc((void**)&w.tasks, cap * sizeof(ProdTask)) != hipSuccess) {
+                w.tasks = nullptr;
+                (void)hipGetLastError();
+                return FFP_ENOMEM;
+            }
+            w.task_cap = cap;
+        }
+    }
+    *out = &w;
+    return FFP_OK;
+}
+
+int64_t g_kblk_cap = 0;
+
+// ---- optional per-launch timing (HIP events around each product launch) --
+namespace {
+struct ProfRec {
+    hipEvent_t e0, e1;
+    double work;   // algorithmic flops of the launch
+    int cls;
+};
+std::mutex g_prof_mutex;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+bool prof_enabled() { return g_prof_on; }
+
+void prof_begin(hipStream_t s, hipEvent_t* e0)
+{
+    if (hipEventCreate(e0) != hipSuccess) { *e0 = nullptr; return; }
+    (void)hipEventRecord(*e0, s);
+}
+
+void prof_end(hipStream_t s, hipEvent_t e0, double work, int cls)
+{
+    if (!e0) return;
+    hipEvent_t e1;
+    if (hipEventCreate(&e1) != hipSuccess) return;
+    (void)hipEventRecord(e1, s);
+    std::lock_guard<std::mutex> lk(g_prof_mutex);
+    g_prof.push_back(ProfRec{e0, e1, work, cls});
+}
+
+void prof_enable(bool on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mutex);
+    g_prof_on = on;
+}
+
+int prof_read(int cls, double* ms, double* work, int64_t* launches)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mutex);
+    double tms = 0.0, tw = 0.0;
+    int64_t nl = 0;
+    std::vector<ProfRec> keep;
+    for (ProfRec& r : g_prof) {
+        if (cls >= 0 && r.cls != cls) { keep.push_back(r); continue; }
+        float t = 0.f;
+        if (hipEventSynchronize(r.e1) != hipSuccess) return -1;
+        if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) return -1;
+        tms += t;
+        tw += r.work;
+        ++nl;
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    g_prof.swap(keep);
+    *ms = tms;
+    *work = tw;
+    *launches = nl;
+    return 0;
+}
+
+void init_task(ProdTask* t, const FieldPlan& f)
+{
+    t->p = f.p;
+    t->half = (f.p - 1) / 2;
+    t->pinv = f.pinv;
+    t->kblk = (int32_t)f64_kblk(f.p);
+}
+
+hipError_t launch_products(int cls, ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
+                           hipStream_t s)
+{
+    switch (cls) {
+    case CLS_F64: return launch_products_f64(tasks, ntasks, dev_task_buf, s);
+    case CLS_I8: return launch_products_i8(tasks, ntasks, dev_task_buf, s);
+    case CLS_LIMB2: return launch_products_limb2(tasks, ntasks, dev_task_buf, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s)
+{
+    const FieldPlan& fpl = pl.field;
+    const Fp f{fpl.p, (fpl.p - 1) / 2, fpl.pinv, fpl.ya, fpl.yb};
+    for (const Op& o : pl.ops) {
+        hipError_t e = hipSuccess;
+        switch (o.kind) {
+        case OP_S1S2:
+            e = launch_preadd_s1s2(o.cls, f, o.m, o.k, dview(o.v[0], a, c, ws), dview(o.v[1], a, c, ws),
+                                   dview(o.v[2], a, c, ws), dview(o.v[3], a, c, ws),
+                                   dview(o.v[4], a, c, ws), s);
+            break;
+        case OP_S34:
+            e = launch_preadd_s34(o.cls, f, o.mode, o.m, o.k, dview(o.v[0], a, c, ws),
+                                  dview(o.v[1], a, c, ws), dview(o.v[2], a, c, ws),
+                                  dview(o.v[3], a, c, ws), dview(o.v[4], a, c, ws), s);
+            break;
+        case OP_GEMM:
+        case OP_SYRK: {
+            ProdTask t{};
+            init_task(&t, fpl);
+            const bool syrk = o.kind == OP_SYRK;
+            t.A = dview(o.v[0], a, c, ws);
+            t.B = syrk ? t.A : dview(o.v[1], a, c, ws);
+            const PView& cv = syrk ? o.v[1] : o.v[2];
+            t.C = (uint32_t*)at(cv, a, c, ws);
+            t.ldc = cv.ld;
+            t.m = (int32_t)o.m;
+            t.n = (int32_t)(syrk ? o.m : o.n);
+            t.k = (int32_t)o.k;
+            t.syrk = syrk ? 1 : 0;
+            t.alpha = o.alpha;
+            t.beta = o.beta;
+            hipEvent_t e0 = nullptr;
+            const bool prof = prof_enabled();
+            if (prof) prof_begin(s, &e0);
+            e = launch_products(o.cls, &t, 1, nullptr, s);
+            if (prof) {
+                const double flops = syrk ? (double)t.m * (double)(t.m + 1) * (double)t.k
+                                          : 2.0 * (double)t.m * (double)t.n * (double)t.k;
+                prof_end(s, e0, flops, o.cls);
+            }
+            break;
+        }
+        case OP_POSTADD:
+            e = launch_postadd(f, o.m, (const uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld,
+                               (const uint32_t*)at(o.v[1], a, c, ws), o.v[1].ld,
+                               (uint32_t*)at(o.v[2], a, c, ws), o.v[2].ld,
+                               (uint32_t*)at(o.v[3], a, c, ws), o.v[3].ld, o.beta,
+                               o.beta ? (const uint32_t*)at(o.v[4], a, c, ws) : nullptr, o.v[4].ld,
+                               o.beta ? (const uint32_t*)at(o.v[5], a, c, ws) : nullptr, s);
+            break;
+        case OP_ADDLOW:
+            e = launch_add_lower(f, o.m, (const uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld,
+                                 (const uint32_t*)at(o.v[1], a, c, ws), o.v[1].ld,
+                                 (uint32_t*)at(o.v[2], a, c, ws), o.v[2].ld, s);
+            break;
+        case OP_SAVEC22:
+            e = launch_save_c22(o.m, (const uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld,
+                                (uint32_t*)at(o.v[1], a, c, ws), o.v[1].ld,
+                                (uint32_t*)at(o.v[2], a, c, ws), s);
+            break;
+        case OP_MIRROR:
+            e = launch_mirror_lower(o.m, (uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld, s);
+            break;
+        case OP_PACK:
+            e = launch_pack(f, o.src_cls, dview(o.v[0], a, c, ws), o.m_src, o.k_src, o.cls,
+                            dview(o.v[1], a, c, ws), o.m, o.k, s);
+            break;
+        case OP_COPY:
+            e = launch_copy_u32(o.m, o.n, (const uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld,
+                                (uint32_t*)at(o.v[1], a, c, ws), o.v[1].ld, o.mode & 1, s);
+            break;
+        }
+        if (e != hipSuccess) return FFP_EDEVICE;
+    }
+    return FFP_OK;
+}
+
+}  // namespace ffp

@@ -1,0 +1,48 @@
+// Device workspace pool and plan executor.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "plan.h"
+
+namespace ffp {
+
+// A grow-only device buffer owned by the library, one per (device, stream).
+// Growing waits for the stream so that no enqueued kernel still uses the
+// old buffer.
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    ProdTask* tasks = nullptr;   // device task table for grouped launches
+    size_t task_cap = 0;
+};
+
+// Returns FFP_OK or FFP_ENOMEM / FFP_EDEVICE.  The returned workspace stays
+// valid until the next call on the same stream that needs more memory.
+int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** out);
+
+// Enqueues every op of the plan on stream s.  a, c: caller buffers; ws:
+// workspace of at least pl.ws_bytes.
+int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s);
+
+hipError_t launch_products(int cls, ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
+                           hipStream_t s);
+hipError_t launch_products_f64(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s);
+hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s);
+hipError_t launch_products_limb2(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
+                                 hipStream_t s);
+
+// Optional timing of product launches with HIP events (for the benchmark's
+// roofline figures).  prof_read sums the elapsed times and algorithmic flops
+// of the recorded launches of class cls (-1: all) and forgets them.
+bool prof_enabled();
+void prof_enable(bool on);
+void prof_begin(hipStream_t s, hipEvent_t* e0);
+void prof_end(hipStream_t s, hipEvent_t e0, double work, int cls);
+int prof_read(int cls, double* ms, double* work, int64_t* launches);
+
+// Fills the product-kernel fields of a task from the field plan.
+void init_task(ProdTask* t, const FieldPlan& f);
+
+}  // namespace ffp

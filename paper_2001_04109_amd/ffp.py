@@ -1,0 +1,244 @@
+"""Python binding of libffp.so (include/ffp.h, include/ffp_debug.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device memory and streams come from PyTorch; matrices of residues
+are int32 tensors (values in [0, p) with p < 2^25), int8 tensors for the
+int8 storages.  The functions raise FfpError on a negative status and
+ImportError/OSError when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffp.so")
+
+FFP_OK = 0
+FFP_EINVAL = -1
+FFP_EPRIME = -2
+FFP_EDTYPE = -3
+FFP_ENOMEM = -4
+FFP_EDEVICE = -5
+FFP_EUNSUPPORTED = -6
+
+FFP_U32 = 0
+FFP_I8_CENTERED = 1
+FFP_I8_LIMB2 = 2
+
+FFP_FILL_UPPER = 0x1
+FFP_BASE_F64 = 0x100
+FFP_WS_BETA = 0x80000000
+
+
+def FFP_DEPTH(d: int) -> int:
+    return ((d & 0x7) + 1) << 4
+
+
+class FfpError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {strerror(status)} (status {status})")
+        self.status = status
+
+
+class ffp_job(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int64), ("p", ctypes.c_uint32),
+                ("alpha", ctypes.c_uint32), ("beta", ctypes.c_uint32), ("a_dtype", ctypes.c_int32),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("C", ctypes.c_void_p),
+                ("ldc", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libffp.so (built by paper_2001_04109_amd.build); raises if missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2001_04109_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, u32, P, c_int, c_uint = (ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p,
+                                      ctypes.c_int, ctypes.c_uint)
+        sigs = {
+            "fsyrk_modp": (c_int, [i64, i64, u32, P, i64, c_int, u32, u32, P, i64, c_uint, P]),
+            "fgemm_modp": (c_int, [i64, i64, i64, u32, P, i64, P, i64, u32, u32, P, i64, P]),
+            "fldlt_modp": (c_int, [i64, u32, P, i64, P, P]),
+            "ffp_workspace_bytes": (ctypes.c_size_t, [i64, i64, u32, c_int, c_uint]),
+            "fsyrk_modp_batched": (c_int, [c_int, P, c_uint, P]),
+            "ffp_strerror": (ctypes.c_char_p, [c_int]),
+            "ffp_version": (ctypes.c_char_p, []),
+            "ffp_field_info": (c_int, [u32, P, P, P]),
+            "ffp_host_sqrt": (c_int, [u32, u32, P]),
+            "ffp_host_sos": (c_int, [u32, u32, P, P]),
+            "ffp_host_nrsyf": (c_int, [u32, u32, u32, P]),
+            "ffp_plan_describe": (c_int, [i64, i64, u32, c_int, i64, i64, u32, u32, c_uint,
+                                          ctypes.c_char_p, ctypes.c_size_t]),
+        }
+        for name, (res, args) in sigs.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().ffp_strerror(status).decode()
+    except Exception:  # library missing: still give a readable message
+        return f"status {status}"
+
+
+def _check(st: int, what: str):
+    if st < 0:
+        raise FfpError(st, what)
+    return st
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---- C-ABI entry points (same names and argument order) ------------------
+
+def fsyrk_modp(n, k, p, A, lda, a_dtype, alpha, beta, C, ldc, flags=0, stream=None):
+    return _check(lib().fsyrk_modp(n, k, p, _ptr(A), lda, a_dtype, alpha, beta, _ptr(C), ldc,
+                                   flags, _stream(stream)), "fsyrk_modp")
+
+
+def fgemm_modp(m, n, k, p, A, lda, B, ldb, alpha, beta, C, ldc, stream=None):
+    return _check(lib().fgemm_modp(m, n, k, p, _ptr(A), lda, _ptr(B), ldb, alpha, beta, _ptr(C),
+                                   ldc, _stream(stream)), "fgemm_modp")
+
+
+def fldlt_modp(n, p, S, lds, info, stream=None):
+    return _check(lib().fldlt_modp(n, p, _ptr(S), lds, _ptr(info), _stream(stream)), "fldlt_modp")
+
+
+def ffp_workspace_bytes(n, k, p, a_dtype=FFP_U32, flags=0) -> int:
+    return int(lib().ffp_workspace_bytes(n, k, p, a_dtype, flags))
+
+
+def fsyrk_modp_batched(jobs, flags=0, stream=None):
+    arr = (ffp_job * len(jobs))(*jobs)
+    return _check(lib().fsyrk_modp_batched(len(jobs), ctypes.cast(arr, ctypes.c_void_p), flags,
+                                           _stream(stream)), "fsyrk_modp_batched")
+
+
+def make_job(A, C, p, alpha=1, beta=0, a_dtype=FFP_U32) -> ffp_job:
+    n, k = A.shape
+    return ffp_job(n=n, k=k, p=p, alpha=alpha, beta=beta, a_dtype=a_dtype, A=_ptr(A),
+                   lda=A.stride(0), C=_ptr(C), ldc=C.stride(0))
+
+
+def ffp_version() -> str:
+    return lib().ffp_version().decode()
+
+
+# ---- host-only introspection ---------------------------------------------
+
+def field_info(p: int):
+    a, b, y = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int()
+    _check(lib().ffp_field_info(p, ctypes.byref(a), ctypes.byref(b), ctypes.byref(y)), "field_info")
+    return a.value, b.value, y.value
+
+
+def host_sqrt(a: int, p: int):
+    r = ctypes.c_uint32()
+    st = lib().ffp_host_sqrt(a, p, ctypes.byref(r))
+    if st == FFP_EINVAL:
+        return None
+    _check(st, "host_sqrt")
+    return r.value
+
+
+def host_sos(p: int, k: int):
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().ffp_host_sos(p, k, ctypes.byref(a), ctypes.byref(b)), "host_sos")
+    return a.value, b.value
+
+
+def host_nrsyf(p: int, alpha: int, beta: int):
+    Y = (ctypes.c_uint32 * 4)()
+    _check(lib().ffp_host_nrsyf(p, alpha, beta, Y), "host_nrsyf")
+    return [[Y[0], Y[1]], [Y[2], Y[3]]]
+
+
+def plan_describe(n, k, p, a_dtype=FFP_U32, lda=None, ldc=None, alpha=1, beta=0, flags=0) -> str:
+    lda = k if lda is None else lda
+    ldc = n if ldc is None else ldc
+    size = _check(lib().ffp_plan_describe(n, k, p, a_dtype, lda, ldc, alpha, beta, flags, None, 0),
+                  "plan_describe")
+    buf = ctypes.create_string_buffer(size + 1)
+    _check(lib().ffp_plan_describe(n, k, p, a_dtype, lda, ldc, alpha, beta, flags, buf, size + 1),
+           "plan_describe")
+    return buf.value.decode()
+
+
+# ---- tensor conveniences (marshalling only) -------------------------------
+
+def syrk(A, p: int, alpha: int = 1, beta: int = 0, C=None, depth=None, fill_upper=False,
+         a_dtype=FFP_U32, force_f64=False, stream=None):
+    """lower(C) <- alpha A A^T + beta lower(C) mod p on device tensors.
+
+    A: (n, k) int32 residues (a_dtype FFP_U32), int8 centred residues
+    (FFP_I8_CENTERED), or int8 of shape (2, n, k) holding the hi and lo
+    limbs (FFP_I8_LIMB2).  Returns C ((n, n) int32)."""
+    import torch
+    if a_dtype == FFP_I8_LIMB2:
+        _, n, k = A.shape
+        lda = A.stride(1)
+        if A.stride(0) != n * lda:
+            raise ValueError("limb planes must be stacked with stride n*lda")
+    else:
+        n, k = A.shape
+        lda = A.stride(0)
+    if A.stride(-1) != 1:
+        raise ValueError("A must be row-major")
+    if C is None:
+        C = torch.zeros((n, n), dtype=torch.int32, device=A.device)
+    flags = FFP_FILL_UPPER if fill_upper else 0
+    if depth is not None:
+        flags |= FFP_DEPTH(depth)
+    if force_f64:
+        flags |= FFP_BASE_F64
+    fsyrk_modp(n, k, p, A, lda, a_dtype, alpha, beta, C, C.stride(0), flags, stream)
+    return C
+
+
+def gemm(A, B, p: int, alpha: int = 1, beta: int = 0, C=None, stream=None):
+    """C <- alpha A B^T + beta C mod p on device int32 tensors."""
+    import torch
+    m, k = A.shape
+    n = B.shape[0]
+    if C is None:
+        C = torch.zeros((m, n), dtype=torch.int32, device=A.device)
+    fgemm_modp(m, n, k, p, A, A.stride(0), B, B.stride(0), alpha, beta, C, C.stride(0), stream)
+    return C
+
+
+def ldlt(S, p: int, stream=None):
+    """In-place LDL^T of the lower triangle of S (n x n int32); returns the
+    device int64 info tensor (0, or 1-based index of the first zero pivot)."""
+    import torch
+    n = S.shape[0]
+    info = torch.zeros(1, dtype=torch.int64, device=S.device)
+    fldlt_modp(n, p, S, S.stride(0), info, stream)
+    return info

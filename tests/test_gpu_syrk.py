@@ -1,0 +1,220 @@
+"""GPU parity: fsyrk_modp / fgemm_modp through the C-ABI against the oracle.
+
+Bit-exact comparison (integer results).  Small cases compare every entry;
+the full-size workloads compare sampled entries, which the oracle computes
+one by one, plus symmetry and determinism properties.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_04109_amd import ffp, inputs
+from tests.gpu_util import (centred_i8, from_dev_u32, limbs, lower_mask, set_kblk, to_dev_u32)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    oracle.build(force=False)
+    ffp.lib()
+    yield
+    set_kblk(0)
+
+
+def gpu_syrk(A, p, depth=None, alpha=1, beta=0, C0=None, fill_upper=False, force_f64=False,
+             a_dtype=ffp.FFP_U32):
+    import torch
+    n = A.shape[-2]
+    if a_dtype == ffp.FFP_U32:
+        Ad = to_dev_u32(A)
+    elif a_dtype == ffp.FFP_I8_CENTERED:
+        Ad = torch.from_numpy(centred_i8(A, p)).cuda()
+    else:
+        Ad = torch.from_numpy(limbs(A, p)).cuda()
+    Cd = to_dev_u32(C0) if C0 is not None else torch.zeros((n, n), dtype=torch.int32, device="cuda")
+    ffp.syrk(Ad, p, alpha, beta, Cd, depth=depth, fill_upper=fill_upper, a_dtype=a_dtype,
+             force_f64=force_f64)
+    torch.cuda.synchronize()
+    return from_dev_u32(Cd)
+
+
+def check_lower(out, expect):
+    n = out.shape[0]
+    low = lower_mask(n)
+    bad = np.argwhere(low & (out != expect))
+    assert bad.size == 0, f"{len(bad)} mismatches, first at {bad[:3].tolist()}"
+
+
+# ------------------------------------------------------------- base kernels
+
+@pytest.mark.parametrize("p", [65537, 131071, 1000003, 33554393])
+@pytest.mark.parametrize("m,n,k", [(16, 16, 4), (64, 64, 64), (100, 37, 129), (257, 130, 300)])
+def test_gemm_f64_vs_oracle(p, m, n, k):
+    import torch
+    rng = np.random.default_rng(m * 7 + n + k)
+    A = rng.integers(0, p, size=(m, k), dtype=np.uint64).astype(np.uint32)
+    B = rng.integers(0, p, size=(n, k), dtype=np.uint64).astype(np.uint32)
+    C = rng.integers(0, p, size=(m, n), dtype=np.uint64).astype(np.uint32)
+    alpha, beta = int(rng.integers(0, p)), int(rng.integers(0, p))
+    Cd = to_dev_u32(C)
+    ffp.gemm(to_dev_u32(A), to_dev_u32(B), p, alpha, beta, Cd)
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev_u32(Cd), oracle.gemm(A, B, p, alpha, beta, C))
+
+
+@pytest.mark.parametrize("p", [65537, 131071])
+@pytest.mark.parametrize("n,k", [(1, 1), (15, 7), (64, 64), (200, 333), (513, 64)])
+def test_syrk_depth0_f64(p, n, k):
+    A = inputs.uniform(n + k, n, k, p)
+    check_lower(gpu_syrk(A, p, depth=0), oracle.syrk(A, p))
+
+
+def test_gemm_and_syrk_all_max_entries():
+    # all entries p-1: centred -1, every partial sum exact; with a forced
+    # k-block of 16 the delayed reduction runs many times.
+    p = 131071
+    for kb in (0, 16, 48):
+        set_kblk(kb)
+        A = np.full((70, 1000), p - 1, dtype=np.uint32)
+        check_lower(gpu_syrk(A, p, depth=0), oracle.syrk(A, p))
+    set_kblk(0)
+
+
+# -------------------------------------------------------- Algorithm 2 (F64)
+
+@pytest.mark.parametrize("p", [65537, 131071, 1000003])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("n,k", [(256, 256), (320, 96), (96, 320), (301, 199)])
+def test_syrk_recursive_f64(p, depth, n, k):
+    A = inputs.uniform(depth * 100 + n, n, k, p)
+    check_lower(gpu_syrk(A, p, depth=depth), oracle.syrk(A, p))
+
+
+@pytest.mark.parametrize("p", [65537, 131071])
+@pytest.mark.parametrize("depth", [0, 1, 2])
+def test_syrk_alpha_beta_f64(p, depth):
+    n, k = 192, 160
+    A = inputs.uniform(11, n, k, p)
+    C0 = inputs.uniform(12, n, n, p)
+    for alpha, beta in [(p - 1, 1), (5, 7), (1, 0), (3, 0)]:
+        out = gpu_syrk(A, p, depth=depth, alpha=alpha, beta=beta, C0=C0)
+        check_lower(out, oracle.syrk_ab(A, p, alpha, beta, C0))
+
+
+def test_config_small_512_p65537_depth1_full_symmetric():
+    # 512 x 512, p = 65537, one level of recursion, symmetric output.
+    p = 65537
+    A = inputs.uniform(0, 512, 512, p)
+    out = gpu_syrk(A, p, depth=1, fill_upper=True)
+    assert np.array_equal(out, oracle.syrk(A, p))
+
+
+def test_determinism():
+    p = 131071
+    A = inputs.uniform(5, 384, 384, p)
+    a = gpu_syrk(A, p, depth=2)
+    b = gpu_syrk(A, p, depth=2)
+    low = lower_mask(384)
+    assert np.array_equal(a[low], b[low])
+
+
+# ------------------------------------------------------------- int8 paths
+
+@pytest.mark.parametrize("p,a_dtype", [(251, ffp.FFP_U32), (251, ffp.FFP_I8_CENTERED),
+                                       (65521, ffp.FFP_U32), (65521, ffp.FFP_I8_LIMB2),
+                                       (257, ffp.FFP_U32)])
+@pytest.mark.parametrize("depth", [0, 1, 2])
+@pytest.mark.parametrize("n,k", [(256, 256), (200, 130), (130, 600)])
+def test_syrk_int8_paths(p, a_dtype, depth, n, k):
+    A = inputs.uniform(3 * n + k + depth, n, k, p)
+    check_lower(gpu_syrk(A, p, depth=depth, a_dtype=a_dtype), oracle.syrk(A, p))
+
+
+@pytest.mark.parametrize("p", [251, 65521])
+def test_int8_alpha_beta_and_forced_kblk(p):
+    n, k = 160, 1024
+    A = inputs.uniform(21, n, k, p)
+    C0 = inputs.uniform(22, n, n, p)
+    set_kblk(64)
+    out = gpu_syrk(A, p, depth=1, alpha=p - 1, beta=1, C0=C0)
+    set_kblk(0)
+    check_lower(out, oracle.syrk_ab(A, p, p - 1, 1, C0))
+
+
+def test_int8_max_entries():
+    for p in (251, 65521):
+        A = np.full((96, 4096), (p - 1) // 2 + 1, dtype=np.uint32)   # most negative centred value
+        check_lower(gpu_syrk(A, p, depth=0), oracle.syrk(A, p))
+
+
+def test_f64_forced_for_small_prime():
+    p = 251
+    A = inputs.uniform(31, 200, 300, p)
+    check_lower(gpu_syrk(A, p, depth=2, force_f64=True), oracle.syrk(A, p))
+
+
+# ----------------------------------------------------- argument validation
+
+def test_argument_errors():
+    import torch
+    A = torch.zeros((4, 4), dtype=torch.int32, device="cuda")
+    C = torch.zeros((4, 4), dtype=torch.int32, device="cuda")
+    with pytest.raises(ffp.FfpError) as e:
+        ffp.fsyrk_modp(4, 4, 65535, A, 4, ffp.FFP_U32, 1, 0, C, 4)   # not prime
+    assert e.value.status == ffp.FFP_EPRIME
+    with pytest.raises(ffp.FfpError) as e:
+        ffp.fsyrk_modp(4, 4, 65537, A, 3, ffp.FFP_U32, 1, 0, C, 4)   # lda < k
+    assert e.value.status == ffp.FFP_EINVAL
+    with pytest.raises(ffp.FfpError) as e:
+        ffp.fsyrk_modp(4, 4, 65537, A, 4, ffp.FFP_I8_CENTERED, 1, 0, C, 4)  # int8 needs p <= 251
+    assert e.value.status == ffp.FFP_EDTYPE
+    with pytest.raises(ffp.FfpError) as e:
+        ffp.fsyrk_modp(4, 4, 65537, A, 4, ffp.FFP_U32, 65537, 0, C, 4)   # alpha >= p
+    assert e.value.status == ffp.FFP_EINVAL
+    assert ffp.fsyrk_modp(0, 4, 65537, A, 4, ffp.FFP_U32, 1, 0, C, 4) == 0
+
+
+# ------------------------------------------------------ full-size workloads
+
+def _sampled(A, p, out, nsamp=4000, seed=0):
+    n = A.shape[0]
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, n, size=nsamp)
+    cols = rng.integers(0, n, size=nsamp)
+    lo, hi = np.maximum(rows, cols), np.minimum(rows, cols)
+    lo = np.concatenate([lo, [n - 1, n - 1, 0, n // 2]])
+    hi = np.concatenate([hi, [0, n - 1, 0, n // 2 - 1]])
+    expect = oracle.syrk_entries(A, p, lo, hi)
+    got = out[lo, hi]
+    assert np.array_equal(got, expect)
+
+
+@pytest.mark.parametrize("k", [8192, 32768])
+def test_full_size_8192_p131071_depth3(k):
+    import torch
+    p, n = 131071, 8192
+    A = inputs.uniform(1, n, k, p)
+    Ad = to_dev_u32(A)
+    Cd = torch.zeros((n, n), dtype=torch.int32, device="cuda")
+    ffp.syrk(Ad, p, C=Cd, depth=3)
+    torch.cuda.synchronize()
+    _sampled(A, p, from_dev_u32(Cd))
+
+
+@pytest.mark.parametrize("p,a_dtype", [(251, ffp.FFP_I8_CENTERED), (65521, ffp.FFP_I8_LIMB2)])
+def test_full_size_16384_int8(p, a_dtype):
+    import torch
+    n = 16384
+    A = inputs.uniform(2, n, n, p)
+    if a_dtype == ffp.FFP_I8_CENTERED:
+        Ad = torch.from_numpy(centred_i8(A, p)).cuda()
+    else:
+        Ad = torch.from_numpy(limbs(A, p)).cuda()
+    Cd = torch.zeros((n, n), dtype=torch.int32, device="cuda")
+    ffp.syrk(Ad, p, C=Cd, depth=0, a_dtype=a_dtype)
+    torch.cuda.synchronize()
+    _sampled(A, p, from_dev_u32(Cd), nsamp=2000)
