@@ -130,15 +130,16 @@ def run_workload(name, steps, warmup, check=True):
 
 
 def cpu_baseline(name):
-    """Oracle on a bounded row panel of the first shape: rows [n-r, n) of the
-    lower triangle, i.e. r*(2n-r+1)/2 dot products of length k."""
+    """Oracle on a bounded sample: rows [n-r, n) of the lower triangle of the
+    first shape, i.e. r*(2n-r+1)/2 dot products of length k (r = n for the
+    8192 x 8192 product: its whole lower triangle)."""
     import oracle
     from paper_2001_04109_amd import inputs
     w = WORKLOADS[name]
     n, k = w["shapes"][0]
     p = w["p"]
     A = inputs.uniform(w["seed"], n, k, p)
-    r = 96 if k >= 16384 else 256
+    r = n if n * n * k <= 8192 ** 3 else max(64, int(8192 ** 3 / (n * k)))
     t0 = time.perf_counter()
     oracle.syrk_rows(A, p, n - r, n)
     dt = time.perf_counter() - t0

@@ -116,6 +116,10 @@ int fgemm_modp(int64_t m, int64_t n, int64_t k, uint32_t p, const uint32_t* A, i
  * Errors: FFP_EINVAL, FFP_EPRIME, FFP_ENOMEM, FFP_EDEVICE. */
 int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, void* stream);
 
+/* Device workspace fldlt_modp needs for order n (bytes), for admission
+ * control; 0 if p is not an odd prime below 2^25. */
+size_t ffp_ldlt_workspace_bytes(int64_t n, uint32_t p);
+
 /* Device workspace fsyrk_modp needs for this shape (bytes), for admission
  * control; flags as for fsyrk_modp (beta != 0 is signalled by
  * FFP_WS_BETA). */

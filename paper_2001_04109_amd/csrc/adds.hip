@@ -5,31 +5,12 @@
 // versus P4^T reads of the post-additions, the Up/Low copies of Table 4 and
 // of the final mirror) go through 32 x 32 LDS tiles so that global traffic
 // stays coalesced.
+#include "modp.h"
 #include "prod_common.h"
 
 namespace ffp {
 
 namespace {
-
-// ---- modular scalar helpers (residues in [0,p), p < 2^25) --------------
-__device__ inline uint32_t add_m(uint32_t a, uint32_t b, uint32_t p)
-{
-    uint32_t s = a + b;
-    return s >= p ? s - p : s;
-}
-__device__ inline uint32_t sub_m(uint32_t a, uint32_t b, uint32_t p)
-{
-    return a >= b ? a - b : a + p - b;
-}
-__device__ inline uint32_t mul_m(uint32_t a, uint32_t b, uint32_t p, double pinv)
-{
-    const uint64_t prod = (uint64_t)a * b;   // < 2^50, exact in double
-    const double q = floor((double)prod * pinv);
-    int64_t r = (int64_t)prod - (int64_t)q * (int64_t)p;
-    if (r < 0) r += p;
-    if (r >= (int64_t)p) r -= p;
-    return (uint32_t)r;
-}
 
 // ---- class storage access ---------------------------------------------
 __device__ inline uint32_t ld_res(int cls, const Fp& f, const DView& v, int64_t i, int64_t j)

@@ -7,6 +7,7 @@
 #include "ffp.h"
 #include "ffp_debug.h"
 #include "field.h"
+#include "ldlt.h"
 #include "plan.h"
 #include "runtime.h"
 
@@ -213,8 +214,17 @@ int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches
 
 int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, void* stream)
 {
-    (void)n; (void)p; (void)S; (void)lds; (void)info; (void)stream;
-    return FFP_EUNSUPPORTED;
+    if (n < 0 || info == nullptr) return FFP_EINVAL;
+    if (p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return FFP_EPRIME;
+    if (n > 0 && (S == nullptr || lds < n)) return FFP_EINVAL;
+    if (n > (int64_t)1 << 30) return FFP_EINVAL;
+    return ldlt_run(n, p, S, lds, info, (hipStream_t)stream);
+}
+
+size_t ffp_ldlt_workspace_bytes(int64_t n, uint32_t p)
+{
+    if (n < 0 || p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return 0;
+    return ldlt_workspace_bytes(n, p, n);
 }
 
 int fsyrk_modp_batched(int njobs, const ffp_job* jobs, unsigned flags, void* stream)

@@ -88,7 +88,7 @@ uint64_t sqrt_mod(uint64_t a, uint64_t p)
     // Cipolla: find t with t^2 - a a non-residue, then
     // (t + w)^((p+1)/2) in F_p[w]/(w^2 - (t^2 - a)) is a root.
     uint64_t t = 0, w2 = 0;
-    for (t = 1; t < p; ++t) {
+    for (t = 0; t < p; ++t) {
         w2 = (mul_mod(t, t, p) + p - a) % p;
         if (legendre(w2, p) == -1) break;
     }

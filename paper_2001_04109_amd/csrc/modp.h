@@ -1,0 +1,80 @@
+// Device arithmetic on residues in [0,p) for primes p < 2^25.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ffp {
+
+__device__ inline uint32_t add_m(uint32_t a, uint32_t b, uint32_t p)
+{
+    uint32_t s = a + b;
+    return s >= p ? s - p : s;
+}
+
+__device__ inline uint32_t sub_m(uint32_t a, uint32_t b, uint32_t p)
+{
+    return a >= b ? a - b : a + p - b;
+}
+
+// a*b mod p: the product is below 2^50, exact in double; the quotient
+// estimate from 1/p is off by at most one.
+__device__ inline uint32_t mul_m(uint32_t a, uint32_t b, uint32_t p, double pinv)
+{
+    const uint64_t prod = (uint64_t)a * b;
+    const double q = floor((double)prod * pinv);
+    int64_t r = (int64_t)prod - (int64_t)q * (int64_t)p;
+    if (r < 0) r += p;
+    if (r >= (int64_t)p) r -= p;
+    return (uint32_t)r;
+}
+
+__device__ inline uint32_t pow_m(uint32_t a, uint32_t e, uint32_t p, double pinv)
+{
+    uint32_t r = 1, b = a;
+    while (e) {
+        if (e & 1u) r = mul_m(r, b, p, pinv);
+        b = mul_m(b, b, p, pinv);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Inverse by Fermat's little theorem (0 maps to 0).
+__device__ inline uint32_t inv_m(uint32_t a, uint32_t p, double pinv)
+{
+    return pow_m(a, p - 2, p, pinv);
+}
+
+// Euler's criterion: true if a is a non-zero quadratic non-residue.
+__device__ inline bool is_nonresidue(uint32_t a, uint32_t p, double pinv)
+{
+    return a != 0 && pow_m(a, (p - 1) / 2, p, pinv) == p - 1;
+}
+
+// Square root of a quadratic residue a (Tonelli-Shanks); z is any
+// quadratic non-residue mod p.  Returns the root r with r <= p - r.
+__device__ inline uint32_t sqrt_m(uint32_t a, uint32_t z, uint32_t p, double pinv)
+{
+    if (a == 0) return 0;
+    uint32_t q = p - 1, s = 0;
+    while ((q & 1u) == 0) { q >>= 1; ++s; }
+    uint32_t c = pow_m(z, q, p, pinv);
+    uint32_t x = pow_m(a, (q + 1) / 2, p, pinv);
+    uint32_t t = pow_m(a, q, p, pinv);
+    uint32_t m = s;
+    while (t != 1) {
+        uint32_t i = 0, u = t;
+        while (u != 1 && i < m) { u = mul_m(u, u, p, pinv); ++i; }
+        if (i >= m) break;   // not a square: never reached for residues
+        uint32_t b = c;
+        for (uint32_t j = 0; j + i + 1 < m; ++j) b = mul_m(b, b, p, pinv);
+        m = i;
+        c = mul_m(b, b, p, pinv);
+        t = mul_m(t, c, p, pinv);
+        x = mul_m(x, b, p, pinv);
+    }
+    return x <= p - x ? x : p - x;
+}
+
+}  // namespace ffp

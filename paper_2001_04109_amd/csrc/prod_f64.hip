@@ -119,8 +119,8 @@ __global__ __launch_bounds__(256) void prod_f64_kernel(ProdArgs args, int remap)
         }
     }
 
-    // Epilogue.  16x16 f64 MFMA result layout: lane l holds rows 4*(l/16)+e,
-    // column l%16, e = 0..3.
+    // Epilogue.  16x16 f64 MFMA result layout: element e of lane l is row
+    // 4*e + l/16, column l%16.
     const double alpha = (double)t.alpha, beta = (double)t.beta;
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void prod_f64_kernel(ProdArgs args, int remap)
             const int col = col0 + j * 16 + lr;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = row0 + i * 16 + 4 * lk + e;
+                const int row = row0 + i * 16 + 4 * e + lk;
                 if (row >= t.m || col >= t.n) continue;
                 if (t.syrk && col > row) continue;
                 uint32_t* dst = t.C + (int64_t)row * t.ldc + col;

@@ -1,0 +1,110 @@
+"""GPU parity of fldlt_modp against the oracle's Crout LDL^T (bit-exact:
+L and D are unique when every leading minor is nonzero)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_04109_amd import ffp, inputs
+from tests.gpu_util import from_dev_u32, to_dev_u32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    oracle.build(force=False)
+    ffp.lib()
+
+
+def gpu_ldlt(S, p):
+    import torch
+    Sd = to_dev_u32(S)
+    info = ffp.ldlt(Sd, p)
+    torch.cuda.synchronize()
+    return from_dev_u32(Sd), int(info.item())
+
+
+def constructed(n, p, seed, zero_at=None):
+    rng = np.random.default_rng(seed)
+    L = np.tril(rng.integers(0, p, size=(n, n), dtype=np.uint64), -1).astype(object)
+    L[np.arange(n), np.arange(n)] = 1
+    D = rng.integers(1, p, size=n).astype(object)
+    if zero_at is not None:
+        D[zero_at] = 0
+    S = np.array((L * D).dot(L.T) % p, dtype=np.uint32)
+    return L, D, S
+
+
+def packed(L, D):
+    n = len(D)
+    out = np.array(np.tril(L, -1), dtype=np.uint32)
+    out[np.arange(n), np.arange(n)] = np.array(D, dtype=np.uint32)
+    return out
+
+
+@pytest.mark.parametrize("p", [65537, 131071, 251, 65521, 1000003])
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 130, 300])
+def test_ldlt_recovers_constructed(p, n):
+    L, D, S = constructed(n, p, seed=n + p)
+    out, info = gpu_ldlt(S, p)
+    assert info == 0
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(out[low], packed(L, D)[low])
+
+
+@pytest.mark.parametrize("n", [200, 700, 1500])
+def test_ldlt_random_symmetric_vs_oracle(n):
+    p = 65537
+    S = inputs.symmetric(40 + n, n, p)
+    ref, rinfo = oracle.ldlt_packed(S, p)
+    out, info = gpu_ldlt(S, p)
+    assert info == rinfo
+    if info == 0:
+        low = np.tril(np.ones((n, n), dtype=bool))
+        assert np.array_equal(out[low], ref[low])
+
+
+@pytest.mark.parametrize("where", [0, 1, 63, 64, 100, 250])
+def test_ldlt_zero_pivot_reported(where):
+    p, n = 65537, 256
+    _, _, S = constructed(n, p, seed=where, zero_at=where)
+    _, rinfo = oracle.ldlt_packed(S, p)
+    assert rinfo == where + 1
+    _, info = gpu_ldlt(S, p)
+    assert info == where + 1
+
+
+def test_ldlt_many_nonresidues_odd_count():
+    # all pivots non-residues (3 is a non-residue mod 65537): Algorithm 4 on
+    # every pair and an extra zero column when the count is odd
+    p, n = 65537, 193
+    rng = np.random.default_rng(3)
+    L = np.tril(rng.integers(0, p, size=(n, n), dtype=np.uint64), -1).astype(object)
+    L[np.arange(n), np.arange(n)] = 1
+    D = np.array([3 * (i + 1) ** 2 % p for i in range(n)], dtype=object)
+    S = np.array((L * D).dot(L.T) % p, dtype=np.uint32)
+    out, info = gpu_ldlt(S, p)
+    assert info == 0
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(out[low], packed(L, D)[low])
+
+
+def test_ldlt_4096_sampled_reconstruction():
+    p, n = 65537, 4096
+    S = inputs.symmetric(77, n, p)
+    out, info = gpu_ldlt(S, p)
+    if info != 0:
+        pytest.skip(f"drawn matrix has a zero pivot at {info} (probability about n/p)")
+    L = np.tril(out.astype(np.int64), -1)
+    L[np.arange(n), np.arange(n)] = 1
+    D = out[np.arange(n), np.arange(n)].astype(np.int64)
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        i, j = sorted(rng.integers(0, n, size=2))[::-1]
+        m = min(i, j) + 1
+        # (L D L^T)_ij = sum_l L_il D_l L_jl, exact with Python ints
+        v = sum(int(L[i, l]) * int(D[l]) * int(L[j, l]) for l in range(m)) % p
+        assert v == int(S[i, j]), (i, j)
