@@ -49,6 +49,12 @@ int ffp_plan_describe(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda
  * call.  Results stay exact for any cap: it only adds reductions. */
 void ffp_debug_set_kblk(int64_t kblk);
 
+/* Tuning and test knobs (process-wide): "kblk" (as ffp_debug_set_kblk),
+ * "f64_tile" (64 or 128: force the FP64 product tile; 0 = automatic),
+ * "i8_tile" (128 or 256: force the int8 product tile; 0 = automatic).
+ * FFP_EINVAL for an unknown key. */
+int ffp_debug_set(const char* key, int64_t value);
+
 /* Timing hook for benchmarks: while enabled, every product-kernel launch is
  * bracketed by two HIP events on its stream.  ffp_debug_profile_read waits
  * for the recorded launches of base-path class cls (0 = FP64, 1 = int8,

@@ -205,6 +205,15 @@ extern "C" {
 
 void ffp_debug_set_kblk(int64_t kblk) { ffp::g_kblk_cap = kblk > 0 ? kblk : 0; }
 
+int ffp_debug_set(const char* key, int64_t value)
+{
+    if (!key) return FFP_EINVAL;
+    if (strcmp(key, "kblk") == 0) { ffp::g_kblk_cap = value > 0 ? value : 0; return FFP_OK; }
+    if (strcmp(key, "f64_tile") == 0) { ffp::g_f64_tile_override = (int)value; return FFP_OK; }
+    if (strcmp(key, "i8_tile") == 0) { ffp::g_i8_tile_override = (int)value; return FFP_OK; }
+    return FFP_EINVAL;
+}
+
 void ffp_debug_profile(int enable) { prof_enable(enable != 0); }
 
 int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches)

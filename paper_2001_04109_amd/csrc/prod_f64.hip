@@ -142,6 +142,166 @@ __global__ __launch_bounds__(256) void prod_f64_kernel(ProdArgs args, int remap)
     }
 }
 
+// ---- 128 x 128 tiles through LDS -------------------------------------------
+// Workgroup tile 128 x 128, waves 2 x 2 of 64 x 64 (4 x 4 MFMA blocks).  Per
+// stage of 32 columns of k the A and B panels (128 rows x 128 bytes each)
+// are copied global -> registers -> LDS (double-buffered; the loads for the
+// next stage are issued before the MFMAs of the current one).  Each lane
+// reads 16 bytes (4 consecutive k) per row block from LDS and feeds them to
+// four MFMA steps, as in the direct kernel.
+namespace {
+constexpr int BM2 = 128, BK2 = 32, PITCH2 = BK2 + 4;   // u32 units
+constexpr int WM2 = 4, WN2 = 4;
+
+struct Pf2 { uint4 v[4]; };   // 128 rows x 32 u32 / 256 threads = 4 x 16 bytes
+
+__device__ inline void gload2(Pf2& pf, const uint32_t* __restrict__ g, int64_t ld, int row0, int nrows,
+                              int k0, int K, bool vec_ok)
+{
+#pragma unroll
+    for (int ps = 0; ps < 4; ++ps) {
+        const int idx = ps * 256 + threadIdx.x;
+        const int r = idx >> 3, c = (idx & 7) * 4;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        const int row = row0 + r, kc = k0 + c;
+        if (row < nrows) {
+            const uint32_t* src = g + (int64_t)row * ld + kc;
+            if (vec_ok && kc + 4 <= K) {
+                v = *reinterpret_cast<const uint4*>(src);
+            } else {
+                v.x = kc < K ? src[0] : 0u;
+                v.y = kc + 1 < K ? src[1] : 0u;
+                v.z = kc + 2 < K ? src[2] : 0u;
+                v.w = kc + 3 < K ? src[3] : 0u;
+            }
+        }
+        pf.v[ps] = v;
+    }
+}
+
+__device__ inline void lstore2(uint32_t* __restrict__ lds, const Pf2& pf)
+{
+#pragma unroll
+    for (int ps = 0; ps < 4; ++ps) {
+        const int idx = ps * 256 + threadIdx.x;
+        const int r = idx >> 3, c = (idx & 7) * 4;
+        *reinterpret_cast<uint4*>(lds + r * PITCH2 + c) = pf.v[ps];
+    }
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void prod_f64_lds_kernel(ProdArgs args, int remap)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t sa[2][BM2 * PITCH2];
+    __shared__ __attribute__((aligned(16))) uint32_t sb[2][BM2 * PITCH2];
+    const int b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b >= args.total_tiles) return;
+    ProdTask t;
+    select_task(args, b, &t);
+    const int r = b - t.tile0;
+    int ti, tj;
+    if (t.syrk) tri_index(r, &ti, &tj);
+    else { ti = r / t.tn; tj = r - ti * t.tn; }
+    const int tile_r = ti * BM2, tile_c = tj * BM2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    const uint32_t* __restrict__ Ab = (const uint32_t*)t.A.p;
+    const uint32_t* __restrict__ Bb = (const uint32_t*)t.B.p;
+    const bool vec_ok = ((t.A.ld & 3) == 0) && ((t.B.ld & 3) == 0) &&
+                        ((((uintptr_t)Ab) & 15) == 0) && ((((uintptr_t)Bb) & 15) == 0);
+    const double pd = (double)t.p;
+    const int K = t.k;
+    const int nk = (K + BK2 - 1) / BK2;
+
+    v4d acc[WM2][WN2];
+#pragma unroll
+    for (int i = 0; i < WM2; ++i)
+#pragma unroll
+        for (int j = 0; j < WN2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    Pf2 pa, pb;
+    if (nk > 0) {
+        gload2(pa, Ab, t.A.ld, tile_r, t.m, 0, K, vec_ok);
+        gload2(pb, Bb, t.B.ld, tile_c, t.n, 0, K, vec_ok);
+        lstore2(sa[0], pa);
+        lstore2(sb[0], pb);
+    }
+    __syncthreads();
+    // k-blocks of kblk columns (a multiple of BK2); the accumulators are
+    // reduced mod p after every block, outside the stage loop.
+    const int nkb = t.kblk / BK2;
+    for (int kb0 = 0; kb0 < nk; kb0 += nkb) {
+        const int kend = min(kb0 + nkb, nk);
+        for (int kt = kb0; kt < kend; ++kt) {
+            const int cur = kt & 1;
+            const bool more = kt + 1 < nk;
+            if (more) {
+                gload2(pa, Ab, t.A.ld, tile_r, t.m, (kt + 1) * BK2, K, vec_ok);
+                gload2(pb, Bb, t.B.ld, tile_c, t.n, (kt + 1) * BK2, K, vec_ok);
+            }
+#pragma unroll
+            for (int kg = 0; kg < BK2 / 16; ++kg) {
+                uint4 ua[WM2], ub[WN2];
+#pragma unroll
+                for (int i = 0; i < WM2; ++i)
+                    ua[i] = *reinterpret_cast<const uint4*>(&sa[cur][(wr * 64 + i * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
+#pragma unroll
+                for (int j = 0; j < WN2; ++j)
+                    ub[j] = *reinterpret_cast<const uint4*>(&sb[cur][(wc * 64 + j * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    double av[WM2], bv[WN2];
+#pragma unroll
+                    for (int i = 0; i < WM2; ++i)
+                        av[i] = centred(s == 0 ? ua[i].x : s == 1 ? ua[i].y : s == 2 ? ua[i].z : ua[i].w, t.half, t.p);
+#pragma unroll
+                    for (int j = 0; j < WN2; ++j)
+                        bv[j] = centred(s == 0 ? ub[j].x : s == 1 ? ub[j].y : s == 2 ? ub[j].z : ub[j].w, t.half, t.p);
+#pragma unroll
+                    for (int i = 0; i < WM2; ++i)
+#pragma unroll
+                        for (int j = 0; j < WN2; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+                }
+            }
+            if (more) {
+                lstore2(sa[cur ^ 1], pa);
+                lstore2(sb[cur ^ 1], pb);
+            }
+            __syncthreads();
+        }
+        if (kend < nk) {
+#pragma unroll
+            for (int i = 0; i < WM2; ++i)
+#pragma unroll
+                for (int j = 0; j < WN2; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[i][j][e] = mod_f64(acc[i][j][e], pd, t.pinv);
+        }
+    }
+
+    const double alpha = (double)t.alpha, beta = (double)t.beta;
+#pragma unroll
+    for (int i = 0; i < WM2; ++i) {
+#pragma unroll
+        for (int j = 0; j < WN2; ++j) {
+            const int col = tile_c + wc * 64 + j * 16 + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = tile_r + wr * 64 + i * 16 + 4 * e + lk;
+                if (row >= t.m || col >= t.n) continue;
+                if (t.syrk && col > row) continue;
+                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                double v = mod_f64(acc[i][j][e], pd, t.pinv);
+                double x = alpha * v;
+                if (t.beta != 0u) x += beta * (double)(*dst);
+                *dst = (uint32_t)mod_f64(x, pd, t.pinv);
+            }
+        }
+    }
+}
+
 int64_t f64_kblk(uint32_t p)
 {
     const double half = (double)((p - 1) / 2);
@@ -153,15 +313,16 @@ int64_t f64_kblk(uint32_t p)
     return k;
 }
 
-hipError_t launch_products_f64(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
+template <int TILE>
+static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     ProdArgs args{};
     int total = 0;
     for (int i = 0; i < ntasks; ++i) {
         ProdTask& t = tasks[i];
-        t.kblk = cap_kblk(f64_kblk(t.p), 16);
-        t.tm = (t.m + BM - 1) / BM;
-        t.tn = (t.n + BN - 1) / BN;
+        t.kblk = cap_kblk(f64_kblk(t.p), TILE == 128 ? BK2 : 16);
+        t.tm = (t.m + TILE - 1) / TILE;
+        t.tn = (t.n + TILE - 1) / TILE;
         t.tile0 = total;
         total += t.syrk ? t.tm * (t.tm + 1) / 2 : t.tm * t.tn;
     }
@@ -178,8 +339,29 @@ hipError_t launch_products_f64(ProdTask* tasks, int ntasks, ProdTask* dev_task_b
     }
     const int remap = (ntasks == 1) ? 1 : 0;
     const int grid = remap ? (total + 7) / 8 * 8 : total;
-    hipLaunchKernelGGL(prod_f64_kernel, dim3(grid), dim3(256), 0, s, args, remap);
+    if (TILE == 128)
+        hipLaunchKernelGGL(prod_f64_lds_kernel, dim3(grid), dim3(256), 0, s, args, remap);
+    else
+        hipLaunchKernelGGL(prod_f64_kernel, dim3(grid), dim3(256), 0, s, args, remap);
     return hipGetLastError();
+}
+
+int g_f64_tile_override = 0;
+
+hipError_t launch_products_f64(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
+{
+    // 128 x 128 tiles (half the operand traffic per flop) once they alone
+    // give every CU at least two workgroups; 64 x 64 tiles otherwise.
+    int64_t tiles128 = 0;
+    for (int i = 0; i < ntasks; ++i) {
+        const int64_t tm = (tasks[i].m + 127) / 128, tn = (tasks[i].n + 127) / 128;
+        tiles128 += tasks[i].syrk ? tm * (tm + 1) / 2 : tm * tn;
+    }
+    bool big = tiles128 >= 512;
+    if (g_f64_tile_override == 64) big = false;
+    if (g_f64_tile_override == 128) big = true;
+    return big ? launch_f64_impl<128>(tasks, ntasks, dev_task_buf, s)
+               : launch_f64_impl<64>(tasks, ntasks, dev_task_buf, s);
 }
 
 }  // namespace ffp

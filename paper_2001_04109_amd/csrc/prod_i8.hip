@@ -2,21 +2,34 @@
 //
 // CLS_I8: centred int8 residues (|x| <= 125 for p <= 251); each product is
 // at most 125^2 in magnitude, so an int32 accumulator is exact for more than
-// 137 000 columns of k; the accumulators are reduced mod p every `kblk`
-// columns and in the epilogue.
+// 137 000 columns of k; longer products run as several launches over k
+// chunks, each reducing mod p into C.
 //
 // CLS_LIMB2: value = 256*hi + lo with int8 limbs; the tile accumulates
 // hh = Ahi Bhi^T, ll = Alo Blo^T and x = Ahi Blo^T + Alo Bhi^T in three
 // int32 accumulators and combines 2^16 hh + 2^8 x + ll mod p in the
 // epilogue.
 //
-// Both kernels stage A and B tiles through LDS (double-buffered): a 256-
-// thread workgroup computes a BM x BN tile, each of its 4 waves a
-// (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks.  Every lane feeds one MFMA
-// with 16 consecutive k-bytes of one row; A and B use the same lane-to-k
-// assignment, so the result is exact whatever the hardware's k order inside
-// the instruction.
+// A 256-thread workgroup computes a BM x BN tile; each of its 4 waves a
+// (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks.  Per stage of BK = 64
+// columns of k the workgroup copies the A and B row panels (BM and BN rows
+// of 64 bytes) into one of two LDS buffers: every thread issues its global
+// loads for stage t+1 into registers before the MFMAs of stage t and writes
+// them to the other buffer afterwards, so HBM/L2 latency overlaps matrix
+// work.  The LDS row pitch is padded by 16 bytes so that the 16-byte reads
+// of 8 consecutive rows fall in distinct banks.
+//
+// Every lane feeds one MFMA with 16 consecutive k-bytes of one row; A and B
+// use the same lane-to-k assignment, so the sum is exact whatever the
+// instruction's internal k order.
+//
+// Tile order: tiles are enumerated in bands of G tile rows (column by column
+// inside a band) so that the tiles in flight on one XCD share a few A and B
+// panels in its L2; for single-task launches each XCD gets a contiguous range
+// of that order (blocks are dispatched round-robin over the 8 XCDs).
 #include "prod_common.h"
+
+#include <vector>
 
 namespace ffp {
 
@@ -25,36 +38,89 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int BK = 64;          // k bytes per LDS stage
-constexpr int LDS_PITCH = BK + 16;   // padded row pitch (bytes), 16-byte aligned
-
-template <int BM, int BN, int PLANES>
-struct Smem {
-    int8_t a[2][PLANES][BM * LDS_PITCH];
-    int8_t b[2][PLANES][BN * LDS_PITCH];
-};
+constexpr int BK = 64;              // k bytes per stage
+constexpr int PITCH = BK + 16;      // padded LDS row pitch
+constexpr int GBAND = 4;            // tile rows per band
 
 __device__ inline int32_t mod_i32(int32_t x, double p, double pinv)
 {
     return (int32_t)mod_f64((double)x, p, pinv);
 }
 
-// Global -> LDS copy of a ROWS x BK byte tile, 16 bytes per thread per pass.
-template <int ROWS>
-__device__ inline void stage_tile(int8_t* __restrict__ lds, const int8_t* __restrict__ g, int64_t ld,
-                                  int row0, int nrows, int k0)
+// r-th tile of a tm x tn grid in banded order.
+__device__ inline void band_rect(int r, int tm, int tn, int* ti, int* tj)
 {
-    constexpr int CHUNKS = BK / 16;                 // 16-byte chunks per row
-    constexpr int PASSES = ROWS * CHUNKS / 256;
-    static_assert(ROWS * CHUNKS % 256 == 0, "tile must split evenly over 256 threads");
+    const int per_band = GBAND * tn;
+    const int b = r / per_band;
+    const int loc = r - b * per_band;
+    const int rows = min(GBAND, tm - b * GBAND);
+    *tj = loc / rows;
+    *ti = b * GBAND + loc % rows;
+}
+
+// r-th lower-triangle tile (tj <= ti) of a T x T grid in banded order:
+// band b holds tile rows [bG, bG + rows); its rectangular part (tj < bG) is
+// walked column by column, then its own rows x rows triangle, column by column.
+__device__ inline void band_tri(int r, int T, int* ti, int* tj)
+{
+    const int G = GBAND;
+    int b = 0, start = 0;
+    for (;;) {
+        const int rows = min(G, T - b * G);
+        if (rows <= 0) break;
+        const int cnt = b * G * rows + rows * (rows + 1) / 2;
+        if (r < start + cnt) break;
+        start += cnt;
+        ++b;
+    }
+    const int rows = min(G, T - b * G);
+    int loc = r - start;
+    const int rect = b * G * rows;
+    if (loc < rect) {
+        *tj = loc / rows;
+        *ti = b * G + loc % rows;
+        return;
+    }
+    loc -= rect;
+    int c = 0;
+    while (c < rows - 1 && loc >= rows - c) { loc -= rows - c; ++c; }
+    *tj = b * G + c;
+    *ti = b * G + c + loc;
+}
+
+template <int ROWS>
+struct Prefetch {
+    static constexpr int CHUNKS = BK / 16;
+    static constexpr int PASSES = ROWS * CHUNKS / 256;
+    static_assert(ROWS * CHUNKS % 256 == 0, "panel must split evenly over 256 threads");
+    v4i v[PASSES];
+};
+
+template <int ROWS>
+__device__ inline void gload(Prefetch<ROWS>& pf, const int8_t* __restrict__ g, int64_t ld, int row0,
+                             int nrows, int k0)
+{
+    constexpr int CHUNKS = Prefetch<ROWS>::CHUNKS;
 #pragma unroll
-    for (int ps = 0; ps < PASSES; ++ps) {
+    for (int ps = 0; ps < Prefetch<ROWS>::PASSES; ++ps) {
         const int idx = ps * 256 + threadIdx.x;
         const int r = idx / CHUNKS, c = idx % CHUNKS;
         v4i val = {0, 0, 0, 0};
         if (row0 + r < nrows)
             val = *reinterpret_cast<const v4i*>(g + (int64_t)(row0 + r) * ld + k0 + c * 16);
-        *reinterpret_cast<v4i*>(lds + r * LDS_PITCH + c * 16) = val;
+        pf.v[ps] = val;
+    }
+}
+
+template <int ROWS>
+__device__ inline void lstore(int8_t* __restrict__ lds, const Prefetch<ROWS>& pf)
+{
+    constexpr int CHUNKS = Prefetch<ROWS>::CHUNKS;
+#pragma unroll
+    for (int ps = 0; ps < Prefetch<ROWS>::PASSES; ++ps) {
+        const int idx = ps * 256 + threadIdx.x;
+        const int r = idx / CHUNKS, c = idx % CHUNKS;
+        *reinterpret_cast<v4i*>(lds + r * PITCH + c * 16) = pf.v[ps];
     }
 }
 
@@ -67,7 +133,10 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
     constexpr int WTM = BM / 2, WTN = BN / 2;         // wave tile
     constexpr int FM = WTM / 32, FN = WTN / 32;       // 32x32 blocks per wave
     constexpr int NACC = PLANES == 1 ? 1 : 3;
-    __shared__ Smem<BM, BN, PLANES> sm;
+    constexpr int SA = 2 * PLANES * BM * PITCH, SB = 2 * PLANES * BN * PITCH;
+    __shared__ __attribute__((aligned(16))) int8_t smem[SA + SB];
+    auto sa = reinterpret_cast<int8_t(*)[PLANES][BM * PITCH]>(smem);
+    auto sb = reinterpret_cast<int8_t(*)[PLANES][BN * PITCH]>(smem + SA);
 
     const int b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     if (b >= args.total_tiles) return;
@@ -75,8 +144,8 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
     select_task(args, b, &t);
     const int r = b - t.tile0;
     int ti, tj;
-    if (t.syrk) tri_index(r, &ti, &tj);
-    else { ti = r / t.tn; tj = r - ti * t.tn; }
+    if (t.syrk) band_tri(r, t.tm, &ti, &tj);
+    else band_rect(r, t.tm, t.tn, &ti, &tj);
     const int tile_r = ti * BM, tile_c = tj * BN;
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -97,30 +166,36 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[q][i][j][e] = 0;
 
-    // a wave whose sub-tile lies strictly above the diagonal skips the math
+    // a wave whose sub-tile lies strictly above the diagonal stores nothing
     const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
 
-    const int K = t.k;
-    const int nk = K / BK;
+    const int nk = t.k / BK;
+    Prefetch<BM> pa[PLANES];
+    Prefetch<BN> pb[PLANES];
     if (nk > 0) {
 #pragma unroll
         for (int pl = 0; pl < PLANES; ++pl) {
-            stage_tile<BM>(sm.a[0][pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, 0);
-            stage_tile<BN>(sm.b[0][pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, 0);
+            gload<BM>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, 0);
+            gload<BN>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, 0);
+        }
+#pragma unroll
+        for (int pl = 0; pl < PLANES; ++pl) {
+            lstore<BM>(sa[0][pl], pa[pl]);
+            lstore<BN>(sb[0][pl], pb[pl]);
         }
     }
     __syncthreads();
-    int since_red = 0;
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) {
+        const bool more = kt + 1 < nk;
+        if (more) {
 #pragma unroll
             for (int pl = 0; pl < PLANES; ++pl) {
-                stage_tile<BM>(sm.a[cur ^ 1][pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 1) * BK);
-                stage_tile<BN>(sm.b[cur ^ 1][pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
+                gload<BM>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 1) * BK);
+                gload<BN>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
             }
         }
-        if (wave_live) {
+        {   // every wave runs the MFMAs (a branch here costs accumulator copies)
 #pragma unroll
             for (int ks = 0; ks < BK / 32; ++ks) {
                 v4i fa[PLANES][FM], fb[PLANES][FN];
@@ -129,11 +204,11 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
 #pragma unroll
                     for (int i = 0; i < FM; ++i)
                         fa[pl][i] = *reinterpret_cast<const v4i*>(
-                            &sm.a[cur][pl][(wr * WTM + i * 32 + lrow) * LDS_PITCH + ks * 32 + lk * 16]);
+                            &sa[cur][pl][(wr * WTM + i * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
                         fb[pl][j] = *reinterpret_cast<const v4i*>(
-                            &sm.b[cur][pl][(wc * WTN + j * 32 + lrow) * LDS_PITCH + ks * 32 + lk * 16]);
+                            &sb[cur][pl][(wc * WTN + j * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
                 }
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
@@ -149,72 +224,81 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
                         }
                     }
             }
-            since_red += BK;
-            if (since_red >= t.kblk && kt + 1 < nk) {
-                since_red = 0;
+        }
+        if (more) {
 #pragma unroll
-                for (int q = 0; q < NACC; ++q)
-#pragma unroll
-                    for (int i = 0; i < FM; ++i)
-#pragma unroll
-                        for (int j = 0; j < FN; ++j)
-#pragma unroll
-                            for (int e = 0; e < 16; ++e) acc[q][i][j][e] = mod_i32(acc[q][i][j][e], pd, t.pinv);
+            for (int pl = 0; pl < PLANES; ++pl) {
+                lstore<BM>(sa[cur ^ 1][pl], pa[pl]);
+                lstore<BN>(sb[cur ^ 1][pl], pb[pl]);
             }
         }
         __syncthreads();
     }
-    if (!wave_live) return;
-
     // Epilogue.  32x32 i32 MFMA result layout: lane l, element e holds
     // row 8*(e/4) + 4*(l/32) + e%4, column l%32.
     const double alpha = (double)t.alpha, beta = (double)t.beta;
-    const double r16 = (double)((65536u) % t.p), r8 = (double)(256u % t.p);
+    if constexpr (PLANES == 1) {
+        // Through LDS, one 32-row slab of the wave tile at a time, so the
+        // reduction runs in a short loop with coalesced row-major stores.
+        static_assert(4 * 32 * WTN * 4 <= SA + SB, "epilogue slab must fit in LDS");
+        int32_t* ep = reinterpret_cast<int32_t*>(smem) + wave * (32 * WTN);
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i) {
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int col = tile_c + wc * WTN + j * 32 + lrow;
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int row = tile_r + wr * WTM + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
-                if (row >= t.m || col >= t.n) continue;
-                if (t.syrk && col > row) continue;
-                double v;
-                if constexpr (PLANES == 1) {
-                    v = mod_f64((double)acc[0][i][j][e], pd, t.pinv);
-                } else {
+                for (int e = 0; e < 16; ++e)
+                    ep[(8 * (e >> 2) + 4 * lk + (e & 3)) * WTN + j * 32 + lrow] = acc[0][i][j][e];
+            __syncthreads();
+            if (wave_live) {
+                for (int idx = lane; idx < 32 * WTN; idx += 64) {
+                    const int rr = idx / WTN, cc = idx - rr * WTN;
+                    const int row = tile_r + wr * WTM + i * 32 + rr;
+                    const int col = tile_c + wc * WTN + cc;
+                    if (row >= t.m || col >= t.n || (t.syrk && col > row)) continue;
+                    uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                    double x = alpha * mod_f64((double)ep[idx], pd, t.pinv);
+                    if (t.beta != 0u) x += beta * (double)(*dst);
+                    *dst = (uint32_t)mod_f64(x, pd, t.pinv);
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        if (!wave_live) return;
+        const double r16 = (double)((65536u) % t.p), r8 = (double)(256u % t.p);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = tile_c + wc * WTN + j * 32 + lrow;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int row = tile_r + wr * WTM + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
+                    if (row >= t.m || col >= t.n) continue;
+                    if (t.syrk && col > row) continue;
                     const double hh = mod_f64((double)acc[0][i][j][e], pd, t.pinv);
                     const double ll = mod_f64((double)acc[NACC - 2][i][j][e], pd, t.pinv);
                     const double xx = mod_f64((double)acc[NACC - 1][i][j][e], pd, t.pinv);
-                    v = mod_f64(hh * r16 + xx * r8 + ll, pd, t.pinv);
+                    const double v = mod_f64(hh * r16 + xx * r8 + ll, pd, t.pinv);
+                    uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                    double x = alpha * v;
+                    if (t.beta != 0u) x += beta * (double)(*dst);
+                    *dst = (uint32_t)mod_f64(x, pd, t.pinv);
                 }
-                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
-                double x = alpha * v;
-                if (t.beta != 0u) x += beta * (double)(*dst);
-                *dst = (uint32_t)mod_f64(x, pd, t.pinv);
             }
-        }
+    }
 }
 
 namespace {
 
 template <int BM, int BN, int PLANES>
-hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
+hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     ProdArgs args{};
     int total = 0;
     for (int i = 0; i < ntasks; ++i) {
         ProdTask& t = tasks[i];
-        if ((t.k % BK) != 0 || (t.A.ld % 16) != 0 || (t.B.ld % 16) != 0 ||
-            (((uintptr_t)t.A.p) & 15) != 0 || (((uintptr_t)t.B.p) & 15) != 0 ||
-            (PLANES == 2 && ((t.A.plane % 16) != 0 || (t.B.plane % 16) != 0)))
-            return hipErrorInvalidValue;
-        const int64_t half = (t.p - 1) / 2;
-        const int64_t per_k = PLANES == 1 ? half * half : 2 * 128 * 128;
-        int64_t kb = (2147483647LL - (int64_t)t.p) / (per_k > 0 ? per_k : 1);
-        kb -= kb % BK;
-        t.kblk = cap_kblk(kb > (1 << 30) ? (1 << 30) : kb, BK);
         t.tm = (t.m + BM - 1) / BM;
         t.tn = (t.n + BN - 1) / BN;
         t.tile0 = total;
@@ -237,10 +321,70 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
     return hipGetLastError();
 }
 
+// The kernel accumulates a whole task in int32; when k exceeds the exact
+// block length the task runs as consecutive launches over k-chunks, each
+// accumulating into C (beta = 1 after the first), which reduces mod p
+// between chunks.
+template <int BM, int BN, int PLANES>
+hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
+{
+    int32_t maxk = 0, kblk = 1 << 30;
+    for (int i = 0; i < ntasks; ++i) {
+        ProdTask& t = tasks[i];
+        if ((t.k % BK) != 0 || (t.A.ld % 16) != 0 || (t.B.ld % 16) != 0 ||
+            (((uintptr_t)t.A.p) & 15) != 0 || (((uintptr_t)t.B.p) & 15) != 0 ||
+            (PLANES == 2 && ((t.A.plane % 16) != 0 || (t.B.plane % 16) != 0)))
+            return hipErrorInvalidValue;
+        const int64_t half = (t.p - 1) / 2;
+        const int64_t per_k = PLANES == 1 ? half * half : 2 * 128 * 128;
+        int64_t kb = (2147483647LL - (int64_t)t.p) / (per_k > 0 ? per_k : 1);
+        kb -= kb % BK;
+        t.kblk = cap_kblk(kb > (1 << 30) ? (1 << 30) : kb, BK);
+        kblk = t.kblk < kblk ? t.kblk : kblk;
+        maxk = t.k > maxk ? t.k : maxk;
+    }
+    if (maxk <= kblk) return launch_i8_once<BM, BN, PLANES>(tasks, ntasks, dev_task_buf, s);
+    std::vector<ProdTask> part(tasks, tasks + ntasks);
+    for (int32_t k0 = 0; k0 < maxk; k0 += kblk) {
+        int np = 0;
+        for (int i = 0; i < ntasks; ++i) {
+            const ProdTask& t = tasks[i];
+            if (k0 >= t.k && !(k0 == 0 && t.k == 0)) continue;
+            ProdTask c = t;
+            c.k = t.k - k0 < kblk ? t.k - k0 : kblk;
+            c.A.p = (int8_t*)t.A.p + k0;
+            c.B.p = (int8_t*)t.B.p + k0;
+            c.beta = k0 == 0 ? t.beta : 1u;
+            part[np++] = c;
+        }
+        hipError_t e = launch_i8_once<BM, BN, PLANES>(part.data(), np, dev_task_buf, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int64_t tiles_of(const ProdTask* tasks, int ntasks, int bm)
+{
+    int64_t total = 0;
+    for (int i = 0; i < ntasks; ++i) {
+        const int64_t tm = (tasks[i].m + bm - 1) / bm, tn = (tasks[i].n + bm - 1) / bm;
+        total += tasks[i].syrk ? tm * (tm + 1) / 2 : tm * tn;
+    }
+    return total;
+}
+
 }  // namespace
+
+int g_i8_tile_override = 0;
 
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
+    // 256 x 256 tiles once they alone fill the 256 CUs twice over
+    bool big = tiles_of(tasks, ntasks, 256) >= 512;
+    if (g_i8_tile_override == 128) big = false;
+    if (g_i8_tile_override == 256) big = true;
+    if (big)
+        return launch_i8_impl<256, 256, 1>(tasks, ntasks, dev_task_buf, s);
     return launch_i8_impl<128, 128, 1>(tasks, ntasks, dev_task_buf, s);
 }
 

@@ -41,3 +41,10 @@ def set_kblk(k: int):
 
 def lower_mask(n):
     return np.tril(np.ones((n, n), dtype=bool))
+
+
+def set_knob(key: str, value: int):
+    f = ffp.lib().ffp_debug_set
+    f.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+    f.restype = ctypes.c_int
+    assert f(key.encode(), value) == 0

@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 from paper_2001_04109_amd import ffp, inputs
-from tests.gpu_util import (centred_i8, from_dev_u32, limbs, lower_mask, set_kblk, to_dev_u32)
+from tests.gpu_util import (centred_i8, from_dev_u32, limbs, lower_mask, set_kblk, set_knob,
+                            to_dev_u32)
 
 pytestmark = pytest.mark.gpu
 
@@ -122,7 +123,36 @@ def test_determinism():
     assert np.array_equal(a[low], b[low])
 
 
+@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("n,k,depth", [(300, 257, 0), (640, 640, 1), (130, 1000, 0)])
+def test_f64_tile_variants(tile, n, k, depth):
+    p = 131071
+    A = inputs.uniform(n + k + tile, n, k, p)
+    set_knob("f64_tile", tile)
+    try:
+        check_lower(gpu_syrk(A, p, depth=depth), oracle.syrk(A, p))
+        C0 = inputs.uniform(5, n, n, p)
+        check_lower(gpu_syrk(A, p, depth=depth, alpha=7, beta=p - 2, C0=C0),
+                    oracle.syrk_ab(A, p, 7, p - 2, C0))
+    finally:
+        set_knob("f64_tile", 0)
+
+
 # ------------------------------------------------------------- int8 paths
+
+@pytest.mark.parametrize("tile", [128, 256])
+@pytest.mark.parametrize("n,k", [(300, 256), (600, 192), (513, 64)])
+def test_i8_tile_variants(tile, n, k):
+    p = 251
+    A = inputs.uniform(n + tile, n, k, p)
+    set_knob("i8_tile", tile)
+    try:
+        check_lower(gpu_syrk(A, p, depth=0, a_dtype=ffp.FFP_I8_CENTERED), oracle.syrk(A, p))
+        C0 = inputs.uniform(6, n, n, p)
+        check_lower(gpu_syrk(A, p, depth=0, alpha=3, beta=5, C0=C0), oracle.syrk_ab(A, p, 3, 5, C0))
+    finally:
+        set_knob("i8_tile", 0)
+
 
 @pytest.mark.parametrize("p,a_dtype", [(251, ffp.FFP_U32), (251, ffp.FFP_I8_CENTERED),
                                        (65521, ffp.FFP_U32), (65521, ffp.FFP_I8_LIMB2),
