@@ -51,7 +51,8 @@ void ffp_debug_set_kblk(int64_t kblk);
 
 /* Tuning and test knobs (process-wide): "kblk" (as ffp_debug_set_kblk),
  * "f64_tile" (64 or 128: force the FP64 product tile; 0 = automatic),
- * "i8_tile" (128 or 256: force the int8 product tile; 0 = automatic).
+ * "i8_tile" (128 or 256: force the int8 product tile; 0 = automatic),
+ * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile).
  * FFP_EINVAL for an unknown key. */
 int ffp_debug_set(const char* key, int64_t value);
 

@@ -211,6 +211,7 @@ int ffp_debug_set(const char* key, int64_t value)
     if (strcmp(key, "kblk") == 0) { ffp::g_kblk_cap = value > 0 ? value : 0; return FFP_OK; }
     if (strcmp(key, "f64_tile") == 0) { ffp::g_f64_tile_override = (int)value; return FFP_OK; }
     if (strcmp(key, "i8_tile") == 0) { ffp::g_i8_tile_override = (int)value; return FFP_OK; }
+    if (strcmp(key, "i8_bk") == 0) { ffp::g_i8_bk_override = (int)value; return FFP_OK; }
     return FFP_EINVAL;
 }
 

@@ -70,6 +70,7 @@ extern int64_t g_kblk_cap;
 // Tile-variant overrides for tests and tuning (0: automatic).
 extern int g_f64_tile_override;
 extern int g_i8_tile_override;
+extern int g_i8_bk_override;
 inline int32_t cap_kblk(int64_t kb, int64_t unit)
 {
     if (g_kblk_cap > 0 && g_kblk_cap < kb) kb = g_kblk_cap - g_kblk_cap % unit;

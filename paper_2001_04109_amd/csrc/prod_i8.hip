@@ -11,9 +11,9 @@
 // epilogue.
 //
 // A 256-thread workgroup computes a BM x BN tile; each of its 4 waves a
-// (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks.  Per stage of BK = 64
-// columns of k the workgroup copies the A and B row panels (BM and BN rows
-// of 64 bytes) into one of two LDS buffers: every thread issues its global
+// (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks.  Per stage of BK (64 or
+// 128) columns of k the workgroup copies the A and B row panels (BM and BN
+// rows of BK bytes) into one of two LDS buffers: every thread issues its global
 // loads for stage t+1 into registers before the MFMAs of stage t and writes
 // them to the other buffer afterwards, so HBM/L2 latency overlaps matrix
 // work.  The LDS row pitch is padded by 16 bytes so that the 16-byte reads
@@ -38,8 +38,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int BK = 64;              // k bytes per stage
-constexpr int PITCH = BK + 16;      // padded LDS row pitch
+constexpr int KSTEP = 64;           // k granularity of every launch (bytes)
 constexpr int GBAND = 4;            // tile rows per band
 
 __device__ inline int32_t mod_i32(int32_t x, double p, double pinv)
@@ -88,21 +87,22 @@ __device__ inline void band_tri(int r, int T, int* ti, int* tj)
     *ti = b * G + c + loc;
 }
 
-template <int ROWS>
+template <int ROWS, int BK>
 struct Prefetch {
+    static constexpr int PITCH = BK + 16;   // padded LDS row pitch
     static constexpr int CHUNKS = BK / 16;
     static constexpr int PASSES = ROWS * CHUNKS / 256;
     static_assert(ROWS * CHUNKS % 256 == 0, "panel must split evenly over 256 threads");
     v4i v[PASSES];
 };
 
-template <int ROWS>
-__device__ inline void gload(Prefetch<ROWS>& pf, const int8_t* __restrict__ g, int64_t ld, int row0,
+template <int ROWS, int BK>
+__device__ inline void gload(Prefetch<ROWS, BK>& pf, const int8_t* __restrict__ g, int64_t ld, int row0,
                              int nrows, int k0)
 {
-    constexpr int CHUNKS = Prefetch<ROWS>::CHUNKS;
+    constexpr int CHUNKS = Prefetch<ROWS, BK>::CHUNKS;
 #pragma unroll
-    for (int ps = 0; ps < Prefetch<ROWS>::PASSES; ++ps) {
+    for (int ps = 0; ps < Prefetch<ROWS, BK>::PASSES; ++ps) {
         const int idx = ps * 256 + threadIdx.x;
         const int r = idx / CHUNKS, c = idx % CHUNKS;
         v4i val = {0, 0, 0, 0};
@@ -112,24 +112,25 @@ __device__ inline void gload(Prefetch<ROWS>& pf, const int8_t* __restrict__ g, i
     }
 }
 
-template <int ROWS>
-__device__ inline void lstore(int8_t* __restrict__ lds, const Prefetch<ROWS>& pf)
+template <int ROWS, int BK>
+__device__ inline void lstore(int8_t* __restrict__ lds, const Prefetch<ROWS, BK>& pf)
 {
-    constexpr int CHUNKS = Prefetch<ROWS>::CHUNKS;
+    constexpr int CHUNKS = Prefetch<ROWS, BK>::CHUNKS;
 #pragma unroll
-    for (int ps = 0; ps < Prefetch<ROWS>::PASSES; ++ps) {
+    for (int ps = 0; ps < Prefetch<ROWS, BK>::PASSES; ++ps) {
         const int idx = ps * 256 + threadIdx.x;
         const int r = idx / CHUNKS, c = idx % CHUNKS;
-        *reinterpret_cast<v4i*>(lds + r * PITCH + c * 16) = pf.v[ps];
+        *reinterpret_cast<v4i*>(lds + r * Prefetch<ROWS, BK>::PITCH + c * 16) = pf.v[ps];
     }
 }
 
 }  // namespace
 
-// PLANES = 1: CLS_I8;  PLANES = 2: CLS_LIMB2.
-template <int BM, int BN, int PLANES>
+// PLANES = 1: CLS_I8;  PLANES = 2: CLS_LIMB2.  BK: k bytes per stage.
+template <int BM, int BN, int BK, int PLANES>
 __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
 {
+    constexpr int PITCH = BK + 16;
     constexpr int WTM = BM / 2, WTN = BN / 2;         // wave tile
     constexpr int FM = WTM / 32, FN = WTN / 32;       // 32x32 blocks per wave
     constexpr int NACC = PLANES == 1 ? 1 : 3;
@@ -170,18 +171,18 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
     const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
 
     const int nk = t.k / BK;
-    Prefetch<BM> pa[PLANES];
-    Prefetch<BN> pb[PLANES];
+    Prefetch<BM, BK> pa[PLANES];
+    Prefetch<BN, BK> pb[PLANES];
     if (nk > 0) {
 #pragma unroll
         for (int pl = 0; pl < PLANES; ++pl) {
-            gload<BM>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, 0);
-            gload<BN>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, 0);
+            gload<BM, BK>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, 0);
+            gload<BN, BK>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, 0);
         }
 #pragma unroll
         for (int pl = 0; pl < PLANES; ++pl) {
-            lstore<BM>(sa[0][pl], pa[pl]);
-            lstore<BN>(sb[0][pl], pb[pl]);
+            lstore<BM, BK>(sa[0][pl], pa[pl]);
+            lstore<BN, BK>(sb[0][pl], pb[pl]);
         }
     }
     __syncthreads();
@@ -191,8 +192,8 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
         if (more) {
 #pragma unroll
             for (int pl = 0; pl < PLANES; ++pl) {
-                gload<BM>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 1) * BK);
-                gload<BN>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
+                gload<BM, BK>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 1) * BK);
+                gload<BN, BK>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
             }
         }
         {   // every wave runs the MFMAs (a branch here costs accumulator copies)
@@ -228,8 +229,8 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
         if (more) {
 #pragma unroll
             for (int pl = 0; pl < PLANES; ++pl) {
-                lstore<BM>(sa[cur ^ 1][pl], pa[pl]);
-                lstore<BN>(sb[cur ^ 1][pl], pb[pl]);
+                lstore<BM, BK>(sa[cur ^ 1][pl], pa[pl]);
+                lstore<BN, BK>(sb[cur ^ 1][pl], pb[pl]);
             }
         }
         __syncthreads();
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
 
 namespace {
 
-template <int BM, int BN, int PLANES>
+template <int BM, int BN, int BK, int PLANES>
 hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     ProdArgs args{};
@@ -317,7 +318,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
     }
     const int remap = (ntasks == 1) ? 1 : 0;
     const int grid = remap ? (total + 7) / 8 * 8 : total;
-    hipLaunchKernelGGL((prod_i8_kernel<BM, BN, PLANES>), dim3(grid), dim3(256), 0, s, args, remap);
+    hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, remap);
     return hipGetLastError();
 }
 
@@ -325,25 +326,25 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
 // block length the task runs as consecutive launches over k-chunks, each
 // accumulating into C (beta = 1 after the first), which reduces mod p
 // between chunks.
-template <int BM, int BN, int PLANES>
+template <int BM, int BN, int BK, int PLANES>
 hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     int32_t maxk = 0, kblk = 1 << 30;
     for (int i = 0; i < ntasks; ++i) {
         ProdTask& t = tasks[i];
-        if ((t.k % BK) != 0 || (t.A.ld % 16) != 0 || (t.B.ld % 16) != 0 ||
+        if ((t.k % KSTEP) != 0 || (t.A.ld % 16) != 0 || (t.B.ld % 16) != 0 ||
             (((uintptr_t)t.A.p) & 15) != 0 || (((uintptr_t)t.B.p) & 15) != 0 ||
             (PLANES == 2 && ((t.A.plane % 16) != 0 || (t.B.plane % 16) != 0)))
             return hipErrorInvalidValue;
         const int64_t half = (t.p - 1) / 2;
         const int64_t per_k = PLANES == 1 ? half * half : 2 * 128 * 128;
         int64_t kb = (2147483647LL - (int64_t)t.p) / (per_k > 0 ? per_k : 1);
-        kb -= kb % BK;
-        t.kblk = cap_kblk(kb > (1 << 30) ? (1 << 30) : kb, BK);
+        kb -= kb % KSTEP;
+        t.kblk = cap_kblk(kb > (1 << 30) ? (1 << 30) : kb, KSTEP);
         kblk = t.kblk < kblk ? t.kblk : kblk;
         maxk = t.k > maxk ? t.k : maxk;
     }
-    if (maxk <= kblk) return launch_i8_once<BM, BN, PLANES>(tasks, ntasks, dev_task_buf, s);
+    if (maxk <= kblk) return launch_i8_once<BM, BN, BK, PLANES>(tasks, ntasks, dev_task_buf, s);
     std::vector<ProdTask> part(tasks, tasks + ntasks);
     for (int32_t k0 = 0; k0 < maxk; k0 += kblk) {
         int np = 0;
@@ -357,7 +358,7 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
             c.beta = k0 == 0 ? t.beta : 1u;
             part[np++] = c;
         }
-        hipError_t e = launch_i8_once<BM, BN, PLANES>(part.data(), np, dev_task_buf, s);
+        hipError_t e = launch_i8_once<BM, BN, BK, PLANES>(part.data(), np, dev_task_buf, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -376,6 +377,7 @@ int64_t tiles_of(const ProdTask* tasks, int ntasks, int bm)
 }  // namespace
 
 int g_i8_tile_override = 0;
+int g_i8_bk_override = 0;
 
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
@@ -383,15 +385,19 @@ hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_bu
     bool big = tiles_of(tasks, ntasks, 256) >= 512;
     if (g_i8_tile_override == 128) big = false;
     if (g_i8_tile_override == 256) big = true;
-    if (big)
-        return launch_i8_impl<256, 256, 1>(tasks, ntasks, dev_task_buf, s);
-    return launch_i8_impl<128, 128, 1>(tasks, ntasks, dev_task_buf, s);
+    bool k128 = true;
+    for (int i = 0; i < ntasks; ++i) k128 = k128 && (tasks[i].k % 128) == 0;
+    if (big) {
+        if (g_i8_bk_override == 64 || !k128) return launch_i8_impl<256, 256, 64, 1>(tasks, ntasks, dev_task_buf, s);
+        return launch_i8_impl<256, 256, 128, 1>(tasks, ntasks, dev_task_buf, s);
+    }
+    return launch_i8_impl<128, 128, 64, 1>(tasks, ntasks, dev_task_buf, s);
 }
 
 hipError_t launch_products_limb2(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
                                  hipStream_t s)
 {
-    return launch_i8_impl<128, 128, 2>(tasks, ntasks, dev_task_buf, s);
+    return launch_i8_impl<128, 128, 64, 2>(tasks, ntasks, dev_task_buf, s);
 }
 
 }  // namespace ffp
