@@ -52,7 +52,9 @@ void ffp_debug_set_kblk(int64_t kblk);
 /* Tuning and test knobs (process-wide): "kblk" (as ffp_debug_set_kblk),
  * "f64_tile" (64 or 128: force the FP64 product tile; 0 = automatic),
  * "i8_tile" (128 or 256: force the int8 product tile; 0 = automatic),
- * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile).
+ * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile),
+ * "persistent" (1: grouped product launches run persistent workgroups that
+ * stride over the tiles; 0: one workgroup per tile).
  * FFP_EINVAL for an unknown key. */
 int ffp_debug_set(const char* key, int64_t value);
 

@@ -207,6 +207,32 @@ __global__ __launch_bounds__(256) void pack_kernel(Fp f, DView src, int64_t n, i
     }
 }
 
+// Grouped representation change: block b belongs to the descriptor whose
+// block range holds it; each block converts 4 rows x 64 columns.
+template <int SRC, int DST>
+__global__ __launch_bounds__(256) void pack_grouped_kernel(Fp f, const PackDesc* __restrict__ d,
+                                                          int nd)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const PackDesc q = d[lo];
+    Fp g = f;
+    g.p = q.p;
+    g.half = (q.p - 1) / 2;
+    g.pinv = q.pinv;
+    const int local = b - q.block0;
+    const int64_t bx = (q.k_pad + 63) / 64;
+    const int64_t j = (local % bx) * 64 + (threadIdx.x & 63);
+    const int64_t i = (local / bx) * 4 + (threadIdx.x >> 6);
+    if (j >= q.k_pad || i >= q.n_pad) return;
+    uint32_t r = (i < q.n && j < q.k) ? ld_res(SRC, g, q.src, i, j) : 0u;
+    st_res(DST, g, q.dst, i, j, r);
+}
+
 __global__ __launch_bounds__(256) void copy_u32_kernel(int64_t rows, int64_t cols, const uint32_t* src,
                                                       int64_t lds, uint32_t* dst, int64_t ldd,
                                                       int lower_only)
@@ -316,6 +342,30 @@ hipError_t launch_pack(const Fp& f, int src_cls, DView src, int64_t n, int64_t k
     FFP_PACK(CLS_I8, CLS_I8) FFP_PACK(CLS_I8, CLS_F64) FFP_PACK(CLS_LIMB2, CLS_LIMB2)
     FFP_PACK(CLS_LIMB2, CLS_F64)
 #undef FFP_PACK
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack_grouped(int src_cls, int dst_cls, PackDesc* descs, int nd,
+                               PackDesc* dev_descs, hipStream_t s)
+{
+    int total = 0;
+    for (int i = 0; i < nd; ++i) {
+        descs[i].block0 = total;
+        total += (int)(((descs[i].n_pad + 3) / 4) * ((descs[i].k_pad + 63) / 64));
+    }
+    if (total == 0) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(dev_descs, descs, sizeof(PackDesc) * nd, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    Fp f{};
+#define FFP_PACKG(SC, DC)                                                                        \
+    if (src_cls == SC && dst_cls == DC) {                                                        \
+        hipLaunchKernelGGL((pack_grouped_kernel<SC, DC>), dim3(total), dim3(256), 0, s, f,       \
+                           (const PackDesc*)dev_descs, nd);                                      \
+        return hipGetLastError();                                                                \
+    }
+    FFP_PACKG(CLS_F64, CLS_F64) FFP_PACKG(CLS_F64, CLS_I8) FFP_PACKG(CLS_F64, CLS_LIMB2)
+    FFP_PACKG(CLS_I8, CLS_I8) FFP_PACKG(CLS_LIMB2, CLS_LIMB2)
+#undef FFP_PACKG
     return hipErrorInvalidValue;
 }
 

@@ -9,55 +9,12 @@
 #include "field.h"
 #include "ldlt.h"
 #include "plan.h"
+#include "batch.h"
 #include "runtime.h"
 
 using namespace ffp;
 
 namespace {
-
-bool valid_dtype(int d) { return d == FFP_U32 || d == FFP_I8_CENTERED || d == FFP_I8_LIMB2; }
-
-int dtype_cls(int d)
-{
-    switch (d) {
-    case FFP_I8_CENTERED: return CLS_I8;
-    case FFP_I8_LIMB2: return CLS_LIMB2;
-    default: return CLS_F64;
-    }
-}
-
-bool aligned16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
-
-int make_request(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int a_dtype,
-                 uint32_t alpha, uint32_t beta, const uint32_t* C, int64_t ldc, unsigned flags,
-                 PlanRequest* rq)
-{
-    if (n < 0 || k < 0) return FFP_EINVAL;
-    if (!valid_dtype(a_dtype)) return FFP_EDTYPE;
-    if (p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return FFP_EPRIME;
-    if (a_dtype == FFP_I8_CENTERED && p > 251) return FFP_EDTYPE;
-    if (a_dtype == FFP_I8_LIMB2 && p > 65521) return FFP_EDTYPE;
-    if (alpha >= p || beta >= p) return FFP_EINVAL;
-    if (n > 0 && (C == nullptr || ldc < n)) return FFP_EINVAL;
-    if (n > 0 && k > 0 && (A == nullptr || lda < k)) return FFP_EINVAL;
-    if (n > (int64_t)1 << 30 || k > (int64_t)1 << 30) return FFP_EINVAL;
-    rq->n = n;
-    rq->k = k;
-    rq->p = p;
-    rq->a_cls = dtype_cls(a_dtype);
-    rq->lda = lda;
-    rq->ldc = ldc;
-    rq->a_plane = a_dtype == FFP_I8_LIMB2 ? n * lda : 0;
-    rq->alpha = alpha;
-    rq->beta = beta;
-    const unsigned dfield = (flags >> 4) & 0xFu;
-    rq->depth = dfield ? (int)dfield - 1 : -1;
-    rq->fill_upper = (flags & FFP_FILL_UPPER) != 0;
-    rq->force_f64 = (flags & FFP_BASE_F64) != 0;
-    rq->a_aligned16 = aligned16(A);
-    rq->c_aligned16 = aligned16(C);
-    return FFP_OK;
-}
 
 }  // namespace
 
@@ -67,7 +24,7 @@ int fsyrk_modp(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int
                uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, unsigned flags, void* stream)
 {
     PlanRequest rq;
-    int st = make_request(n, k, p, A, lda, a_dtype, alpha, beta, C, ldc, flags, &rq);
+    int st = make_syrk_request(n, k, p, A, lda, a_dtype, alpha, beta, C, ldc, flags, &rq);
     if (st != FFP_OK) return st;
     if (n == 0) return FFP_OK;
     Plan pl;
@@ -116,7 +73,7 @@ size_t ffp_workspace_bytes(int64_t n, int64_t k, uint32_t p, int a_dtype, unsign
     const uint32_t beta = (flags & FFP_WS_BETA) ? 1u : 0u;
     int64_t lda = a_dtype == FFP_U32 ? k : ((k + 15) / 16) * 16;
     int64_t ldc = ((n + 3) / 4) * 4;
-    if (make_request(n, k, p, (const void*)16, lda, a_dtype, 1u % p, beta, (const uint32_t*)16, ldc,
+    if (make_syrk_request(n, k, p, (const void*)16, lda, a_dtype, 1u % p, beta, (const uint32_t*)16, ldc,
                      flags, &rq) != FFP_OK)
         return 0;
     Plan pl;
@@ -184,7 +141,7 @@ int ffp_plan_describe(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda
                       uint32_t alpha, uint32_t beta, unsigned flags, char* buf, size_t len)
 {
     PlanRequest rq;
-    int st = make_request(n, k, p, (const void*)16, lda, a_dtype, alpha, beta, (const uint32_t*)16,
+    int st = make_syrk_request(n, k, p, (const void*)16, lda, a_dtype, alpha, beta, (const uint32_t*)16,
                           ldc, flags, &rq);
     if (st != FFP_OK) return st;
     Plan pl;
@@ -212,6 +169,7 @@ int ffp_debug_set(const char* key, int64_t value)
     if (strcmp(key, "f64_tile") == 0) { ffp::g_f64_tile_override = (int)value; return FFP_OK; }
     if (strcmp(key, "i8_tile") == 0) { ffp::g_i8_tile_override = (int)value; return FFP_OK; }
     if (strcmp(key, "i8_bk") == 0) { ffp::g_i8_bk_override = (int)value; return FFP_OK; }
+    if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value ? 1 : 0; return FFP_OK; }
     return FFP_EINVAL;
 }
 
@@ -239,8 +197,7 @@ size_t ffp_ldlt_workspace_bytes(int64_t n, uint32_t p)
 
 int fsyrk_modp_batched(int njobs, const ffp_job* jobs, unsigned flags, void* stream)
 {
-    (void)njobs; (void)jobs; (void)flags; (void)stream;
-    return FFP_EUNSUPPORTED;
+    return batched_run(njobs, jobs, flags, (hipStream_t)stream);
 }
 
 }  // extern "C"

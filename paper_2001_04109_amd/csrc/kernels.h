@@ -71,6 +71,11 @@ extern int64_t g_kblk_cap;
 extern int g_f64_tile_override;
 extern int g_i8_tile_override;
 extern int g_i8_bk_override;
+// Multi-task product launches run persistent workgroups (1, default) or one
+// workgroup per tile (0).
+extern int g_persistent;
+// Workgroups of `kernel` (256 threads) resident at once on the device.
+int resident_blocks(const void* kernel);
 inline int32_t cap_kblk(int64_t kb, int64_t unit)
 {
     if (g_kblk_cap > 0 && g_kblk_cap < kb) kb = g_kblk_cap - g_kblk_cap % unit;
@@ -115,6 +120,18 @@ hipError_t launch_mirror_lower(int64_t n, uint32_t* C, int64_t ldc, hipStream_t 
 // k_pad.  Source values must be valid residues of their storage.
 hipError_t launch_pack(const Fp& f, int src_cls, DView src, int64_t n, int64_t k, int dst_cls,
                        DView dst, int64_t n_pad, int64_t k_pad, hipStream_t s);
+// Grouped pack of many matrices in one launch (batched jobs).  Descriptors
+// are staged in host memory that stays valid until the copy to dev_descs
+// has executed; block0 is filled in by the launcher.
+struct PackDesc {
+    DView src, dst;
+    int64_t n, k, n_pad, k_pad;
+    uint32_t p;
+    double pinv;
+    int32_t block0;
+};
+hipError_t launch_pack_grouped(int src_cls, int dst_cls, PackDesc* descs, int nd,
+                               PackDesc* dev_descs, hipStream_t s);
 // Copy the lower triangle (or all, if full) of an n x n uint32 block.
 hipError_t launch_copy_u32(int64_t rows, int64_t cols, const uint32_t* src, int64_t lds,
                            uint32_t* dst, int64_t ldd, int lower_only, hipStream_t s);

@@ -212,6 +212,53 @@ struct Builder {
 
 }  // namespace
 
+namespace {
+bool valid_dtype_(int d) { return d == FFP_U32 || d == FFP_I8_CENTERED || d == FFP_I8_LIMB2; }
+
+int dtype_cls(int d)
+{
+    switch (d) {
+    case FFP_I8_CENTERED: return CLS_I8;
+    case FFP_I8_LIMB2: return CLS_LIMB2;
+    default: return CLS_F64;
+    }
+}
+
+bool aligned16(const void* p) { return (((uintptr_t)p) & 15) == 0; }
+
+}  // namespace
+
+int make_syrk_request(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int a_dtype,
+                 uint32_t alpha, uint32_t beta, const uint32_t* C, int64_t ldc, unsigned flags,
+                 PlanRequest* rq)
+{
+    if (n < 0 || k < 0) return FFP_EINVAL;
+    if (!valid_dtype_(a_dtype)) return FFP_EDTYPE;
+    if (p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return FFP_EPRIME;
+    if (a_dtype == FFP_I8_CENTERED && p > 251) return FFP_EDTYPE;
+    if (a_dtype == FFP_I8_LIMB2 && p > 65521) return FFP_EDTYPE;
+    if (alpha >= p || beta >= p) return FFP_EINVAL;
+    if (n > 0 && (C == nullptr || ldc < n)) return FFP_EINVAL;
+    if (n > 0 && k > 0 && (A == nullptr || lda < k)) return FFP_EINVAL;
+    if (n > (int64_t)1 << 30 || k > (int64_t)1 << 30) return FFP_EINVAL;
+    rq->n = n;
+    rq->k = k;
+    rq->p = p;
+    rq->a_cls = dtype_cls(a_dtype);
+    rq->lda = lda;
+    rq->ldc = ldc;
+    rq->a_plane = a_dtype == FFP_I8_LIMB2 ? n * lda : 0;
+    rq->alpha = alpha;
+    rq->beta = beta;
+    const unsigned dfield = (flags >> 4) & 0xFu;
+    rq->depth = dfield ? (int)dfield - 1 : -1;
+    rq->fill_upper = (flags & FFP_FILL_UPPER) != 0;
+    rq->force_f64 = (flags & FFP_BASE_F64) != 0;
+    rq->a_aligned16 = aligned16(A);
+    rq->c_aligned16 = aligned16(C);
+    return FFP_OK;
+}
+
 int choose_class(uint32_t p, int a_cls, bool force_f64)
 {
     if (a_cls == CLS_I8) return CLS_I8;

@@ -72,6 +72,11 @@ struct Plan {
     std::vector<Op> ops;
 };
 
+// Validates fsyrk_modp arguments and fills a request (FFP_* status).
+int make_syrk_request(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int a_dtype,
+                      uint32_t alpha, uint32_t beta, const uint32_t* C, int64_t ldc, unsigned flags,
+                      PlanRequest* rq);
+
 // Returns FFP_* status (0 on success).
 int build_syrk_plan(const PlanRequest& rq, Plan* out);
 int choose_class(uint32_t p, int a_cls, bool force_f64);

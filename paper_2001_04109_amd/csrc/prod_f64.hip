@@ -20,6 +20,8 @@
 namespace ffp {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+// 16-byte vector in the global address space (global_load rather than flat)
+typedef __attribute__((address_space(1))) const uint4 GU4;
 
 namespace {
 
@@ -35,7 +37,7 @@ __device__ inline void load4(const uint32_t* __restrict__ base, int64_t ld, int 
     if (row < nrows) {
         const uint32_t* src = base + (int64_t)row * ld + kcol;
         if (vec_ok && kcol + 4 <= K) {
-            uint4 q = *reinterpret_cast<const uint4*>(src);
+            uint4 q = *(const GU4*)src;
             out.v[0] = q.x; out.v[1] = q.y; out.v[2] = q.z; out.v[3] = q.w;
             return;
         }
@@ -55,10 +57,8 @@ __device__ inline double centred(uint32_t v, uint32_t half, uint32_t p)
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void prod_f64_kernel(ProdArgs args, int remap)
+__device__ __forceinline__ void f64_tile(const ProdArgs& args, int b)
 {
-    const int b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (b >= args.total_tiles) return;
     ProdTask t;
     select_task(args, b, &t);
     const int r = b - t.tile0;
@@ -167,7 +167,7 @@ __device__ inline void gload2(Pf2& pf, const uint32_t* __restrict__ g, int64_t l
         if (row < nrows) {
             const uint32_t* src = g + (int64_t)row * ld + kc;
             if (vec_ok && kc + 4 <= K) {
-                v = *reinterpret_cast<const uint4*>(src);
+                v = *(const GU4*)src;
             } else {
                 v.x = kc < K ? src[0] : 0u;
                 v.y = kc + 1 < K ? src[1] : 0u;
@@ -190,12 +190,10 @@ __device__ inline void lstore2(uint32_t* __restrict__ lds, const Pf2& pf)
 }
 }  // namespace
 
-__global__ __launch_bounds__(256) void prod_f64_lds_kernel(ProdArgs args, int remap)
+__device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
 {
     __shared__ __attribute__((aligned(16))) uint32_t sa[2][BM2 * PITCH2];
     __shared__ __attribute__((aligned(16))) uint32_t sb[2][BM2 * PITCH2];
-    const int b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (b >= args.total_tiles) return;
     ProdTask t;
     select_task(args, b, &t);
     const int r = b - t.tile0;
@@ -302,6 +300,28 @@ __global__ __launch_bounds__(256) void prod_f64_lds_kernel(ProdArgs args, int re
     }
 }
 
+// mode 0: one workgroup per tile; 1: same, XCD-aware order; 2: persistent
+// (workgroups stride over the tiles, which are ordered longest first).
+__global__ __launch_bounds__(256) void prod_f64_kernel(ProdArgs args, int mode)
+{
+    if (mode == 2) {
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) f64_tile(args, b);
+        return;
+    }
+    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b < args.total_tiles) f64_tile(args, b);
+}
+
+__global__ __launch_bounds__(256) void prod_f64_lds_kernel(ProdArgs args, int mode)
+{
+    if (mode == 2) {
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) f64_lds_tile(args, b);
+        return;
+    }
+    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b < args.total_tiles) f64_lds_tile(args, b);
+}
+
 int64_t f64_kblk(uint32_t p)
 {
     const double half = (double)((p - 1) / 2);
@@ -337,12 +357,17 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
         if (e != hipSuccess) return e;
         args.dev_tasks = dev_task_buf;
     }
-    const int remap = (ntasks == 1) ? 1 : 0;
-    const int grid = remap ? (total + 7) / 8 * 8 : total;
+    const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
+    int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
+    if (mode == 2) {
+        const int resident = resident_blocks(TILE == 128 ? (const void*)prod_f64_lds_kernel
+                                                         : (const void*)prod_f64_kernel);
+        grid = total < resident ? total : resident;
+    }
     if (TILE == 128)
-        hipLaunchKernelGGL(prod_f64_lds_kernel, dim3(grid), dim3(256), 0, s, args, remap);
+        hipLaunchKernelGGL(prod_f64_lds_kernel, dim3(grid), dim3(256), 0, s, args, mode);
     else
-        hipLaunchKernelGGL(prod_f64_kernel, dim3(grid), dim3(256), 0, s, args, remap);
+        hipLaunchKernelGGL(prod_f64_kernel, dim3(grid), dim3(256), 0, s, args, mode);
     return hipGetLastError();
 }
 

@@ -35,6 +35,8 @@ namespace ffp {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+// 16-byte vector in the global address space (global_load rather than flat)
+typedef __attribute__((address_space(1))) const v4i GV4;
 
 namespace {
 
@@ -105,10 +107,11 @@ __device__ inline void gload(Prefetch<ROWS, BK>& pf, const int8_t* __restrict__ 
     for (int ps = 0; ps < Prefetch<ROWS, BK>::PASSES; ++ps) {
         const int idx = ps * 256 + threadIdx.x;
         const int r = idx / CHUNKS, c = idx % CHUNKS;
-        v4i val = {0, 0, 0, 0};
-        if (row0 + r < nrows)
-            val = *reinterpret_cast<const v4i*>(g + (int64_t)(row0 + r) * ld + k0 + c * 16);
-        pf.v[ps] = val;
+        // Rows past the end re-read the last row: they only feed output rows
+        // (or columns) past the end, which the epilogue never stores.
+        const int row = row0 + r;
+        const int rs = row < nrows ? row : nrows - 1;
+        pf.v[ps] = *(const GV4*)(g + (int64_t)rs * ld + k0 + c * 16);
     }
 }
 
@@ -128,7 +131,7 @@ __device__ inline void lstore(int8_t* __restrict__ lds, const Prefetch<ROWS, BK>
 
 // PLANES = 1: CLS_I8;  PLANES = 2: CLS_LIMB2.  BK: k bytes per stage.
 template <int BM, int BN, int BK, int PLANES>
-__global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
+__device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
 {
     constexpr int PITCH = BK + 16;
     constexpr int WTM = BM / 2, WTN = BN / 2;         // wave tile
@@ -139,8 +142,6 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
     auto sa = reinterpret_cast<int8_t(*)[PLANES][BM * PITCH]>(smem);
     auto sb = reinterpret_cast<int8_t(*)[PLANES][BN * PITCH]>(smem + SA);
 
-    const int b = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (b >= args.total_tiles) return;
     ProdTask t;
     select_task(args, b, &t);
     const int r = b - t.tile0;
@@ -186,6 +187,42 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
         }
     }
     __syncthreads();
+    // Fragments of the current k-step are in fa/fb; those of the next one are
+    // read from LDS while the current MFMAs run (the scheduling hints keep the
+    // compiler from sinking the reads next to their uses).
+    constexpr int KS = BK / 32;
+    v4i fa[PLANES][FM], fb[PLANES][FN];
+    auto read_frags = [&](v4i (&xa)[PLANES][FM], v4i (&xb)[PLANES][FN], int buf, int ks) {
+#pragma unroll
+        for (int pl = 0; pl < PLANES; ++pl) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                xa[pl][i] = *reinterpret_cast<const v4i*>(
+                    &sa[buf][pl][(wr * WTM + i * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                xb[pl][j] = *reinterpret_cast<const v4i*>(
+                    &sb[buf][pl][(wc * WTN + j * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
+        }
+    };
+    auto mfmas = [&](const v4i (&xa)[PLANES][FM], const v4i (&xb)[PLANES][FN]) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                if constexpr (PLANES == 1) {
+                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][i], xb[0][j], acc[0][i][j], 0, 0, 0);
+                } else {
+                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][i], xb[0][j], acc[0][i][j], 0, 0, 0);
+                    acc[NACC - 2][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[PLANES - 1][i], xb[PLANES - 1][j], acc[NACC - 2][i][j], 0, 0, 0);
+                    acc[NACC - 1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][i], xb[PLANES - 1][j], acc[NACC - 1][i][j], 0, 0, 0);
+                    acc[NACC - 1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[PLANES - 1][i], xb[0][j], acc[NACC - 1][i][j], 0, 0, 0);
+                }
+            }
+    };
+    constexpr int NREAD = PLANES * (FM + FN);
+    constexpr int NMFMA = FM * FN * (PLANES == 1 ? 1 : 4);
+    if (nk > 0) read_frags(fa, fb, 0, 0);
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
@@ -196,34 +233,27 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
                 gload<BN, BK>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
             }
         }
-        {   // every wave runs the MFMAs (a branch here costs accumulator copies)
 #pragma unroll
-            for (int ks = 0; ks < BK / 32; ++ks) {
-                v4i fa[PLANES][FM], fb[PLANES][FN];
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks + 1 < KS) {
+                v4i na[PLANES][FM], nb[PLANES][FN];
+                read_frags(na, nb, cur, ks + 1);
+                mfmas(fa, fb);
+                // interleave: one LDS read, then a share of the MFMAs
+#pragma unroll
+                for (int q = 0; q < NREAD; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / NREAD > 0 ? NMFMA / NREAD : 1, 0);
+                }
 #pragma unroll
                 for (int pl = 0; pl < PLANES; ++pl) {
 #pragma unroll
-                    for (int i = 0; i < FM; ++i)
-                        fa[pl][i] = *reinterpret_cast<const v4i*>(
-                            &sa[cur][pl][(wr * WTM + i * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
+                    for (int i = 0; i < FM; ++i) fa[pl][i] = na[pl][i];
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        fb[pl][j] = *reinterpret_cast<const v4i*>(
-                            &sb[cur][pl][(wc * WTN + j * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
+                    for (int j = 0; j < FN; ++j) fb[pl][j] = nb[pl][j];
                 }
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        if constexpr (PLANES == 1) {
-                            acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[0][i], fb[0][j], acc[0][i][j], 0, 0, 0);
-                        } else {
-                            acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[0][i], fb[0][j], acc[0][i][j], 0, 0, 0);
-                            acc[NACC - 2][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[PLANES - 1][i], fb[PLANES - 1][j], acc[NACC - 2][i][j], 0, 0, 0);
-                            acc[NACC - 1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[0][i], fb[PLANES - 1][j], acc[NACC - 1][i][j], 0, 0, 0);
-                            acc[NACC - 1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[PLANES - 1][i], fb[0][j], acc[NACC - 1][i][j], 0, 0, 0);
-                        }
-                    }
+            } else {
+                mfmas(fa, fb);
             }
         }
         if (more) {
@@ -234,7 +264,9 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
             }
         }
         __syncthreads();
+        if (more) read_frags(fa, fb, cur ^ 1, 0);
     }
+
     // Epilogue.  32x32 i32 MFMA result layout: lane l, element e holds
     // row 8*(e/4) + 4*(l/32) + e%4, column l%32.
     const double alpha = (double)t.alpha, beta = (double)t.beta;
@@ -291,6 +323,19 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int remap)
     }
 }
 
+// mode 0: one workgroup per tile; 1: same, XCD-aware order; 2: persistent.
+template <int BM, int BN, int BK, int PLANES>
+__global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int mode)
+{
+    if (mode == 2) {
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x)
+            i8_tile<BM, BN, BK, PLANES>(args, b);
+        return;
+    }
+    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b < args.total_tiles) i8_tile<BM, BN, BK, PLANES>(args, b);
+}
+
 namespace {
 
 template <int BM, int BN, int BK, int PLANES>
@@ -316,9 +361,13 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         if (e != hipSuccess) return e;
         args.dev_tasks = dev_task_buf;
     }
-    const int remap = (ntasks == 1) ? 1 : 0;
-    const int grid = remap ? (total + 7) / 8 * 8 : total;
-    hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, remap);
+    const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
+    int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
+    if (mode == 2) {
+        const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES>);
+        grid = total < resident ? total : resident;
+    }
+    hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
     return hipGetLastError();
 }
 
@@ -358,8 +407,12 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
             c.beta = k0 == 0 ? t.beta : 1u;
             part[np++] = c;
         }
-        hipError_t e = launch_i8_once<BM, BN, BK, PLANES>(part.data(), np, dev_task_buf, s);
-        if (e != hipSuccess) return e;
+        // chunk launches carry their tasks inline (no staging copy outlives `part`)
+        for (int q0 = 0; q0 < np; q0 += kInlineTasks) {
+            const int nq = np - q0 < kInlineTasks ? np - q0 : kInlineTasks;
+            hipError_t e = launch_i8_once<BM, BN, BK, PLANES>(part.data() + q0, nq, nullptr, s);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }

@@ -72,7 +72,76 @@ int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** ou
     return FFP_OK;
 }
 
+namespace {
+struct Staging {
+    char* host = nullptr;
+    char* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+std::map<std::pair<int, hipStream_t>, Staging> g_stage;
+}  // namespace
+
+int acquire_staging(hipStream_t s, size_t bytes, char** host, char** dev)
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) return FFP_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    Staging& st = g_stage[std::make_pair(d, s)];
+    if (st.pending) {
+        if (hipEventSynchronize(st.done) != hipSuccess) return FFP_EDEVICE;
+        st.pending = false;
+    }
+    if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess)
+        return FFP_EDEVICE;
+    if (bytes > st.cap) {
+        if (st.host) (void)hipHostFree(st.host);
+        if (st.dev) (void)hipFree(st.dev);
+        st.host = nullptr;
+        st.dev = nullptr;
+        st.cap = 0;
+        const size_t want = bytes + bytes / 2 + 4096;
+        if (hipHostMalloc((void**)&st.host, want, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void**)&st.dev, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return FFP_ENOMEM;
+        }
+        st.cap = want;
+    }
+    *host = st.host;
+    *dev = st.dev;
+    return FFP_OK;
+}
+
+int release_staging(hipStream_t s)
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) return FFP_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    Staging& st = g_stage[std::make_pair(d, s)];
+    if (!st.done) return FFP_OK;
+    if (hipEventRecord(st.done, s) != hipSuccess) return FFP_EDEVICE;
+    st.pending = true;
+    return FFP_OK;
+}
+
 int64_t g_kblk_cap = 0;
+int g_persistent = 1;
+
+int resident_blocks(const void* kernel)
+{
+    static int cus = 0;
+    int dev = 0;
+    if (cus == 0) {
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per <= 0) per = 1;
+    return per * cus;
+}
 
 // ---- optional per-launch timing (HIP events around each product launch) --
 namespace {
@@ -155,9 +224,51 @@ hipError_t launch_products(int cls, ProdTask* tasks, int ntasks, ProdTask* dev_t
 
 int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s)
 {
+    for (const Op& o : pl.ops) {
+        int st = execute_op(pl, o, a, c, ws, s);
+        if (st != FFP_OK) return st;
+    }
+    return FFP_OK;
+}
+
+ProdTask make_task(const Plan& pl, const Op& o, const void* a, void* c, void* ws)
+{
+    ProdTask t{};
+    init_task(&t, pl.field);
+    const bool syrk = o.kind == OP_SYRK;
+    t.A = dview(o.v[0], a, c, ws);
+    t.B = syrk ? t.A : dview(o.v[1], a, c, ws);
+    const PView& cv = syrk ? o.v[1] : o.v[2];
+    t.C = (uint32_t*)at(cv, a, c, ws);
+    t.ldc = cv.ld;
+    t.m = (int32_t)o.m;
+    t.n = (int32_t)(syrk ? o.m : o.n);
+    t.k = (int32_t)o.k;
+    t.syrk = syrk ? 1 : 0;
+    t.alpha = o.alpha;
+    t.beta = o.beta;
+    return t;
+}
+
+PackDesc make_pack(const Plan& pl, const Op& o, const void* a, void* c, void* ws)
+{
+    PackDesc d{};
+    d.src = dview(o.v[0], a, c, ws);
+    d.dst = dview(o.v[1], a, c, ws);
+    d.n = o.m_src;
+    d.k = o.k_src;
+    d.n_pad = o.m;
+    d.k_pad = o.k;
+    d.p = pl.field.p;
+    d.pinv = pl.field.pinv;
+    return d;
+}
+
+int execute_op(const Plan& pl, const Op& o, const void* a, void* c, void* ws, hipStream_t s)
+{
     const FieldPlan& fpl = pl.field;
     const Fp f{fpl.p, (fpl.p - 1) / 2, fpl.pinv, fpl.ya, fpl.yb};
-    for (const Op& o : pl.ops) {
+    {
         hipError_t e = hipSuccess;
         switch (o.kind) {
         case OP_S1S2:
@@ -172,20 +283,8 @@ int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s
             break;
         case OP_GEMM:
         case OP_SYRK: {
-            ProdTask t{};
-            init_task(&t, fpl);
             const bool syrk = o.kind == OP_SYRK;
-            t.A = dview(o.v[0], a, c, ws);
-            t.B = syrk ? t.A : dview(o.v[1], a, c, ws);
-            const PView& cv = syrk ? o.v[1] : o.v[2];
-            t.C = (uint32_t*)at(cv, a, c, ws);
-            t.ldc = cv.ld;
-            t.m = (int32_t)o.m;
-            t.n = (int32_t)(syrk ? o.m : o.n);
-            t.k = (int32_t)o.k;
-            t.syrk = syrk ? 1 : 0;
-            t.alpha = o.alpha;
-            t.beta = o.beta;
+            ProdTask t = make_task(pl, o, a, c, ws);
             hipEvent_t e0 = nullptr;
             const bool prof = prof_enabled();
             if (prof) prof_begin(s, &e0);

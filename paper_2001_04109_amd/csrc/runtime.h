@@ -22,9 +22,21 @@ struct Workspace {
 // valid until the next call on the same stream that needs more memory.
 int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** out);
 
+// Pinned host staging plus a device buffer for kernel metadata (task and
+// descriptor tables) of one call on stream s.  acquire_staging waits until
+// the previous call's copies from the staging area have executed;
+// release_staging marks the area busy until the work enqueued so far on s
+// has run.
+int acquire_staging(hipStream_t s, size_t bytes, char** host, char** dev);
+int release_staging(hipStream_t s);
+
 // Enqueues every op of the plan on stream s.  a, c: caller buffers; ws:
 // workspace of at least pl.ws_bytes.
 int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s);
+
+int execute_op(const Plan& pl, const Op& o, const void* a, void* c, void* ws, hipStream_t s);
+ProdTask make_task(const Plan& pl, const Op& o, const void* a, void* c, void* ws);
+PackDesc make_pack(const Plan& pl, const Op& o, const void* a, void* c, void* ws);
 
 hipError_t launch_products(int cls, ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
                            hipStream_t s);
