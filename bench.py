@@ -66,11 +66,26 @@ def profile_hooks():
                                          ctypes.POINTER(ctypes.c_int64)]
     L.ffp_debug_profile_read.restype = ctypes.c_int
 
+    L.ffp_debug_profile_read_variant.argtypes = L.ffp_debug_profile_read.argtypes
+    L.ffp_debug_profile_read_variant.restype = ctypes.c_int
+    L.ffp_debug_variant_name.argtypes = [ctypes.c_int]
+    L.ffp_debug_variant_name.restype = ctypes.c_char_p
+
     def read(cls):
         ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
         L.ffp_debug_profile_read(cls, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n))
         return ms.value, fl.value, n.value
-    return L.ffp_debug_profile, read
+
+    def read_variants():
+        """{variant: (ms, flops, launches, name)} of the recorded launches."""
+        out = {}
+        for v in range(6):
+            ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+            L.ffp_debug_profile_read_variant(v, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n))
+            if n.value:
+                out[v] = (ms.value, fl.value, n.value, L.ffp_debug_variant_name(v).decode())
+        return out
+    return L.ffp_debug_profile, read, read_variants
 
 
 def run_workload(name, steps, warmup, check=True):
@@ -96,7 +111,7 @@ def run_workload(name, steps, warmup, check=True):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    prof_enable, prof_read = profile_hooks()
+    prof_enable, prof_read, prof_variants = profile_hooks()
     prof_read(-1)
     prof_enable(1)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -109,10 +124,16 @@ def run_workload(name, steps, warmup, check=True):
     torch.cuda.synchronize()
     prof_enable(0)
     ms = e0.elapsed_time(e1) / steps
-    kms, kflops, nl = prof_read(w["cls"])
+    variants = prof_variants()
+    # dominant product kernel: the variant with the most time in the step
+    dom = max(variants.items(), key=lambda kv: kv[1][0]) if variants else None
     eff = sum(n * n * k for (n, k) in w["shapes"])
-    res = dict(ms_per_step=ms, gops=eff / (ms * 1e-3) / 1e9,
-               kernel_ms=kms / steps, kernel_flops=kflops / steps, launches=nl // max(steps, 1))
+    res = dict(ms_per_step=ms, gops=eff / (ms * 1e-3) / 1e9)
+    if dom:
+        v, (kms, kflops, nl, kname) = dom
+        res.update(kernel=kname, kernel_ms=kms / steps, kernel_flops=kflops / steps,
+                   launches=nl // max(steps, 1), kernel_avg_ms=kms / nl,
+                   all_kernels={name: round(t / steps, 4) for (t, _, _, name) in variants.values()})
     if check:
         # sampled bit-exact check of the last step's results against the oracle
         for A, Cd in zip(mats, outs):
@@ -184,14 +205,17 @@ def main():
     res = run_workload(name, args.steps, args.warmup)
     log(f"bench: {name} {res['ms_per_step']:.3f} ms/step {res['gops']:.1f} Gop/s")
     if w["cls"] == 0:
-        peak, unit, kname = PEAK_F64, "TFLOP/s", "prod_f64_kernel"
+        peak, unit = PEAK_F64, "TFLOP/s"
     else:
-        peak, unit, kname = PEAK_I8, "TOP/s", "prod_i8_kernel"
-    achieved = res["kernel_flops"] / (res["kernel_ms"] * 1e-3) / 1e12 if res["kernel_ms"] else 0.0
+        peak, unit = PEAK_I8, "TOP/s"
+    kname = res.get("kernel", "")
+    achieved = res["kernel_flops"] / (res["kernel_ms"] * 1e-3) / 1e12 if res.get("kernel_ms") else 0.0
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "traffic": traffic_for(kname, name),
-            "kernel": kname, "kernel_ms_per_step": round(res["kernel_ms"], 4),
-            "launches_per_step": res["launches"]}
+            "kernel": kname, "kernel_avg_launch_ms": round(res.get("kernel_avg_ms", 0.0), 5),
+            "kernel_ms_per_step": round(res.get("kernel_ms", 0.0), 4),
+            "launches_per_step": res.get("launches", 0),
+            "product_kernels_ms_per_step": res.get("all_kernels", {})}
     extra = {}
     if not args.no_extra:
         for other in ("syrk_16384_p251_int8", "syrk_16384_p65521_limb2"):
@@ -199,7 +223,7 @@ def main():
                 continue
             log(f"bench: extra {other}")
             r2 = run_workload(other, max(3, args.steps // 3), 1)
-            a2 = r2["kernel_flops"] / (r2["kernel_ms"] * 1e-3) / 1e12 if r2["kernel_ms"] else 0.0
+            a2 = r2["kernel_flops"] / (r2["kernel_ms"] * 1e-3) / 1e12 if r2.get("kernel_ms") else 0.0
             extra[other] = {"gops": round(r2["gops"], 1), "ms_per_step": round(r2["ms_per_step"], 4),
                             "frac_int8_peak_effective": round(r2["gops"] / 1e3 / PEAK_I8, 4),
                             "kernel_achieved_TOPs": round(a2, 2)}

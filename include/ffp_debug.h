@@ -66,6 +66,12 @@ int ffp_debug_set(const char* key, int64_t value);
  * lower-triangle product) and their count, and forgets them. */
 void ffp_debug_profile(int enable);
 int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches);
+/* Same, restricted to one product-kernel variant (0 FP64 64x64 tiles, 1 FP64
+ * 128x128 LDS-staged tiles, 2 int8 128x128, 3 int8 256x256 with 64-byte k
+ * stages, 4 int8 256x256 with 128-byte k stages, 5 int8 limbs 128x128);
+ * ffp_debug_variant_name gives the kernel's demangled name. */
+int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches);
+const char* ffp_debug_variant_name(int variant);
 
 #ifdef __cplusplus
 }

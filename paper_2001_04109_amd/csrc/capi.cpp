@@ -180,6 +180,24 @@ int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches
     return prof_read(cls, ms, flops, launches) == 0 ? FFP_OK : FFP_EDEVICE;
 }
 
+int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches)
+{
+    return prof_read_variant(-1, variant, ms, flops, launches) == 0 ? FFP_OK : FFP_EDEVICE;
+}
+
+const char* ffp_debug_variant_name(int variant)
+{
+    switch (variant) {
+    case 0: return "ffp::prod_f64_kernel(ffp::ProdArgs, int)";
+    case 1: return "ffp::prod_f64_lds_kernel(ffp::ProdArgs, int)";
+    case 2: return "void ffp::prod_i8_kernel<128, 128, 64, 1>(ffp::ProdArgs, int)";
+    case 3: return "void ffp::prod_i8_kernel<256, 256, 64, 1>(ffp::ProdArgs, int)";
+    case 4: return "void ffp::prod_i8_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";
+    case 5: return "void ffp::prod_i8_kernel<128, 128, 64, 2>(ffp::ProdArgs, int)";
+    default: return "";
+    }
+}
+
 int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, void* stream)
 {
     if (n < 0 || info == nullptr) return FFP_EINVAL;

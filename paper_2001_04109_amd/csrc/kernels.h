@@ -74,6 +74,10 @@ extern int g_i8_bk_override;
 // Multi-task product launches run persistent workgroups (1, default) or one
 // workgroup per tile (0).
 extern int g_persistent;
+// Product-kernel variant chosen by the most recent launch on this thread
+// (for the timing hooks): 0 FP64 64x64, 1 FP64 128x128 LDS, 2 int8 128x128,
+// 3 int8 256x256 (k stage 64), 4 int8 256x256 (k stage 128), 5 int8 limbs.
+extern thread_local int g_last_variant;
 // Workgroups of `kernel` (256 threads) resident at once on the device.
 int resident_blocks(const void* kernel);
 inline int32_t cap_kblk(int64_t kb, int64_t unit)

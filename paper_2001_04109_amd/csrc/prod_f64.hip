@@ -21,7 +21,8 @@ namespace ffp {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 // 16-byte vector in the global address space (global_load rather than flat)
-typedef __attribute__((address_space(1))) const uint4 GU4;
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const v4u GU4;
 
 namespace {
 
@@ -37,7 +38,7 @@ __device__ inline void load4(const uint32_t* __restrict__ base, int64_t ld, int 
     if (row < nrows) {
         const uint32_t* src = base + (int64_t)row * ld + kcol;
         if (vec_ok && kcol + 4 <= K) {
-            uint4 q = *(const GU4*)src;
+            const v4u q = *(const GU4*)src;
             out.v[0] = q.x; out.v[1] = q.y; out.v[2] = q.z; out.v[3] = q.w;
             return;
         }
@@ -167,7 +168,8 @@ __device__ inline void gload2(Pf2& pf, const uint32_t* __restrict__ g, int64_t l
         if (row < nrows) {
             const uint32_t* src = g + (int64_t)row * ld + kc;
             if (vec_ok && kc + 4 <= K) {
-                v = *(const GU4*)src;
+                const v4u q = *(const GU4*)src;
+                v = make_uint4(q.x, q.y, q.z, q.w);
             } else {
                 v.x = kc < K ? src[0] : 0u;
                 v.y = kc + 1 < K ? src[1] : 0u;
@@ -364,6 +366,7 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
                                                          : (const void*)prod_f64_kernel);
         grid = total < resident ? total : resident;
     }
+    g_last_variant = TILE == 128 ? 1 : 0;
     if (TILE == 128)
         hipLaunchKernelGGL(prod_f64_lds_kernel, dim3(grid), dim3(256), 0, s, args, mode);
     else

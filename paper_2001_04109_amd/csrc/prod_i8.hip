@@ -367,6 +367,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES>);
         grid = total < resident ? total : resident;
     }
+    g_last_variant = PLANES == 2 ? 5 : (BM == 128 ? 2 : (BK == 64 ? 3 : 4));
     hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
     return hipGetLastError();
 }

@@ -128,6 +128,7 @@ int release_staging(hipStream_t s)
 
 int64_t g_kblk_cap = 0;
 int g_persistent = 1;
+thread_local int g_last_variant = -1;
 
 int resident_blocks(const void* kernel)
 {
@@ -149,6 +150,7 @@ struct ProfRec {
     hipEvent_t e0, e1;
     double work;   // algorithmic flops of the launch
     int cls;
+    int variant;
 };
 std::mutex g_prof_mutex;
 bool g_prof_on = false;
@@ -170,7 +172,7 @@ void prof_end(hipStream_t s, hipEvent_t e0, double work, int cls)
     if (hipEventCreate(&e1) != hipSuccess) return;
     (void)hipEventRecord(e1, s);
     std::lock_guard<std::mutex> lk(g_prof_mutex);
-    g_prof.push_back(ProfRec{e0, e1, work, cls});
+    g_prof.push_back(ProfRec{e0, e1, work, cls, g_last_variant});
 }
 
 void prof_enable(bool on)
@@ -181,12 +183,20 @@ void prof_enable(bool on)
 
 int prof_read(int cls, double* ms, double* work, int64_t* launches)
 {
+    return prof_read_variant(cls, -1, ms, work, launches);
+}
+
+int prof_read_variant(int cls, int variant, double* ms, double* work, int64_t* launches)
+{
     std::lock_guard<std::mutex> lk(g_prof_mutex);
     double tms = 0.0, tw = 0.0;
     int64_t nl = 0;
     std::vector<ProfRec> keep;
     for (ProfRec& r : g_prof) {
-        if (cls >= 0 && r.cls != cls) { keep.push_back(r); continue; }
+        if ((cls >= 0 && r.cls != cls) || (variant >= 0 && r.variant != variant)) {
+            keep.push_back(r);
+            continue;
+        }
         float t = 0.f;
         if (hipEventSynchronize(r.e1) != hipSuccess) return -1;
         if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) return -1;

@@ -53,6 +53,7 @@ void prof_enable(bool on);
 void prof_begin(hipStream_t s, hipEvent_t* e0);
 void prof_end(hipStream_t s, hipEvent_t e0, double work, int cls);
 int prof_read(int cls, double* ms, double* work, int64_t* launches);
+int prof_read_variant(int cls, int variant, double* ms, double* work, int64_t* launches);
 
 // Fills the product-kernel fields of a task from the field plan.
 void init_task(ProdTask* t, const FieldPlan& f);
