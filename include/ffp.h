@@ -148,6 +148,72 @@ typedef struct ffp_job {
  * enqueued. */
 int fsyrk_modp_batched(int njobs, const ffp_job* jobs, unsigned flags, void* stream);
 
+/* ---- request loop: continuous batching ---------------------------------- */
+/* A server owns a pool of HIP streams (default priority) and one device
+ * arena of hbm_budget bytes that holds every result and every running job's
+ * workspace.  A scheduler thread admits queued requests in arrival order
+ * while their footprint (result buffer plus workspace) fits in the arena and
+ * fewer than max_inflight requests are running; a job's workspace returns to
+ * the arena when the job is done, its result when the caller releases it.  Every scheduler iteration gathers the
+ * admitted A*A^T requests into one batched launch (fsyrk_modp_batched) on a
+ * free stream and gives each admitted LDL^T request a stream of its own, so
+ * requests that arrive while others run join at the next iteration and
+ * their work overlaps on the device.  Each result is bit-identical to the
+ * same job run alone.  Operands are caller-owned device memory that must
+ * stay valid and unchanged until the request is done. */
+#define FFP_REQ_SYRK 0      /* C = alpha * A * A^T mod p (lower triangle) */
+#define FFP_REQ_LDLT 1      /* L D L^T of the symmetric matrix whose lower triangle is A */
+#define FFP_STATE_QUEUED  0
+#define FFP_STATE_RUNNING 1
+#define FFP_STATE_DONE    2
+
+typedef struct ffp_request {
+    int32_t kind;          /* FFP_REQ_SYRK or FFP_REQ_LDLT */
+    int64_t n, k;          /* SYRK: A is n x k; LDLT: A is n x n and k is ignored */
+    uint32_t p;            /* prime, 2 < p < 2^25 (LDLT: odd) */
+    uint32_t alpha;        /* SYRK scale, residue in [0,p) */
+    const void* A;         /* device pointer, uint32 residues (FFP_U32 storage) */
+    int64_t lda;
+} ffp_request;
+
+typedef struct ffp_result {
+    int32_t state;         /* FFP_STATE_* or a negative FFP_* status */
+    uint32_t* C;           /* device result, valid from FFP_STATE_DONE until released:
+                              SYRK: lower triangle of C; LDLT: strict lower L, diagonal D */
+    int64_t ldc;
+    int64_t* info;         /* LDLT: device pointer to the first zero pivot (0: none) */
+    double t_submit, t_admit, t_done;   /* seconds on a steady clock */
+} ffp_result;
+
+typedef struct ffp_serve_stats {
+    int64_t submitted, completed, units, batched_jobs, max_batch;
+    int64_t peak_inflight, overlapped_units;   /* units launched while others ran */
+    size_t peak_bytes;
+} ffp_serve_stats;
+
+typedef struct ffp_server ffp_server;
+
+/* nstreams in [1, 16]; max_inflight >= 1.  FFP_ENOMEM if the arena cannot be
+ * allocated. */
+int ffp_server_create(size_t hbm_budget, int max_inflight, int nstreams, ffp_server** out);
+/* Queues a request (thread-safe, does not block on the device).  FFP_EINVAL
+ * or FFP_EPRIME for a malformed request, FFP_ENOMEM if its footprint alone
+ * exceeds the budget. */
+int ffp_server_submit(ffp_server* s, const ffp_request* r, uint64_t* ticket);
+int ffp_server_status(ffp_server* s, uint64_t ticket, ffp_result* out);
+/* Returns a done request's result memory to the budget. */
+int ffp_server_release(ffp_server* s, uint64_t ticket);
+/* Waits until every submitted request is done (FFP_EDEVICE on timeout). */
+int ffp_server_drain(ffp_server* s, double timeout_s);
+/* Enqueues on stream a copy of a done request's result into the caller's
+ * device buffer dst (n x n, row stride ldd >= n; only the lower triangle is
+ * meaningful) and, for LDLT when info_dst is not null, of its info word.
+ * FFP_EINVAL if the request is not done, failed or was released. */
+int ffp_server_fetch(ffp_server* s, uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst,
+                     void* stream);
+int ffp_server_stats(ffp_server* s, ffp_serve_stats* out);
+int ffp_server_destroy(ffp_server* s);
+
 /* Human-readable name of a status code. */
 const char* ffp_strerror(int status);
 

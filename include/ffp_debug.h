@@ -73,6 +73,13 @@ int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches
 int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches);
 const char* ffp_debug_variant_name(int variant);
 
+/* A server whose device is simulated on the host: units of work complete
+ * after launch_us + ns_per_op * (n^2 k, or n^3 / 3 for LDL^T) nanoseconds and
+ * compute nothing; it exercises the scheduler (admission, batching,
+ * overlap) without a GPU.  Results are not produced (C is NULL). */
+int ffp_server_create_simulated(size_t budget, int max_inflight, int nstreams, double ns_per_op,
+                                double launch_us, ffp_server** out);
+
 #ifdef __cplusplus
 }
 #endif

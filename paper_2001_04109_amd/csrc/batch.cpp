@@ -46,7 +46,18 @@ bool longer(const ProdTask& a, const ProdTask& b)
 
 }  // namespace
 
-int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s)
+int64_t job_workspace_bytes(const ffp_job& jb, unsigned flags)
+{
+    PlanRequest rq;
+    if (make_syrk_request(jb.n, jb.k, jb.p, jb.A, jb.lda, jb.a_dtype, jb.alpha, jb.beta, jb.C, jb.ldc,
+                          flags, &rq) != FFP_OK || jb.n == 0)
+        return 0;
+    Plan pl;
+    if (build_syrk_plan(rq, &pl) != FFP_OK) return 0;
+    return rup(pl.ws_bytes, 256);
+}
+
+int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s, char* const* job_ws)
 {
     if (njobs < 0 || (njobs > 0 && jobs == nullptr)) return FFP_EINVAL;
     std::vector<Plan> plans(njobs);
@@ -88,15 +99,21 @@ int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s)
             else if (o.kind == OP_PACK) meta += rup(g.size() * sizeof(PackDesc), 256);
         }
     }
-    Workspace* w = nullptr;
-    int st = acquire_workspace(s, (size_t)ws_total, 0, &w);
-    if (st != FFP_OK) return st;
+    std::vector<char*> jws(njobs, nullptr);
+    int st = FFP_OK;
+    if (job_ws) {
+        for (int j = 0; j < njobs; ++j) jws[j] = job_ws[j];
+    } else {
+        Workspace* w = nullptr;
+        st = acquire_workspace(s, (size_t)ws_total, 0, &w);
+        if (st != FFP_OK) return st;
+        for (int j = 0; j < njobs; ++j) jws[j] = (char*)w->ptr + wsoff[j];
+    }
     char* host_meta = nullptr;
     char* dev_meta = nullptr;
     st = acquire_staging(s, meta, &host_meta, &dev_meta);
     if (st != FFP_OK) return st;
     size_t moff = 0;
-    char* ws = (char*)w->ptr;
 
     for (const auto& g : groups) {
         const size_t nops = plans[g[0]].ops.size();
@@ -108,7 +125,7 @@ int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s)
                 moff += rup(g.size() * sizeof(ProdTask), 256);
                 int nt = 0;
                 for (int j : g)
-                    tasks[nt++] = make_task(plans[j], plans[j].ops[i], jobs[j].A, jobs[j].C, ws + wsoff[j]);
+                    tasks[nt++] = make_task(plans[j], plans[j].ops[i], jobs[j].A, jobs[j].C, jws[j]);
                 std::stable_sort(tasks, tasks + nt, longer);
                 if (launch_products(o0.cls, tasks, nt, dtasks, s) != hipSuccess) return FFP_EDEVICE;
             } else if (o0.kind == OP_PACK) {
@@ -117,11 +134,11 @@ int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s)
                 moff += rup(g.size() * sizeof(PackDesc), 256);
                 int nd = 0;
                 for (int j : g)
-                    d[nd++] = make_pack(plans[j], plans[j].ops[i], jobs[j].A, jobs[j].C, ws + wsoff[j]);
+                    d[nd++] = make_pack(plans[j], plans[j].ops[i], jobs[j].A, jobs[j].C, jws[j]);
                 if (launch_pack_grouped(o0.src_cls, o0.cls, d, nd, dd, s) != hipSuccess) return FFP_EDEVICE;
             } else {
                 for (int j : g) {
-                    st = execute_op(plans[j], plans[j].ops[i], jobs[j].A, jobs[j].C, ws + wsoff[j], s);
+                    st = execute_op(plans[j], plans[j].ops[i], jobs[j].A, jobs[j].C, jws[j], s);
                     if (st != FFP_OK) return st;
                 }
             }

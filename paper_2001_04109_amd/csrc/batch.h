@@ -6,6 +6,13 @@
 
 namespace ffp {
 
-int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s);
+// Workspace bytes that job j needs on its own inside batched_run.
+int64_t job_workspace_bytes(const ffp_job& j, unsigned flags);
+
+// job_ws: optional per-job device workspaces (job j gets job_ws[j], at least
+// job_workspace_bytes(jobs[j]) bytes, 256-byte aligned); when null the
+// library's per-stream workspace holds all jobs' slices.
+int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s,
+                char* const* job_ws = nullptr);
 
 }  // namespace ffp

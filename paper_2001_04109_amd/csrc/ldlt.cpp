@@ -146,7 +146,7 @@ size_t ws_need(int64_t n, uint32_t p, int64_t lds)
 
 size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds) { return ws_need(n, p, lds); }
 
-int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hipStream_t s)
+int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hipStream_t s, void* ws)
 {
     Ctx c;
     if (!make_field_plan(p, &c.fpl)) return FFP_EPRIME;
@@ -158,11 +158,15 @@ int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hip
     c.info = info;
     c.s = s;
     if (launch_zero_i64(info, s) != hipSuccess) return FFP_EDEVICE;
-    const size_t need = ldlt_workspace_bytes(n, p, lds);
-    Workspace* w = nullptr;
-    int st = acquire_workspace(s, need, 0, &w);
-    if (st != FFP_OK) return st;
-    c.ws = (char*)w->ptr;
+    if (ws) {
+        c.ws = (char*)ws;
+    } else {
+        const size_t need = ldlt_workspace_bytes(n, p, lds);
+        Workspace* w = nullptr;
+        int st = acquire_workspace(s, need, 0, &w);
+        if (st != FFP_OK) return st;
+        c.ws = (char*)w->ptr;
+    }
     return ldlt_rec(c, n, S, lds, 0);
 }
 

@@ -44,7 +44,10 @@ hipError_t launch_build_abar(const Fp& f, int64_t rows, int ncols, int kpad, con
 hipError_t launch_zero_i64(int64_t* p, hipStream_t s);
 
 // Host driver.  Returns an FFP_* status; enqueues everything on s.
-int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hipStream_t s);
+// ws: optional device workspace of ldlt_workspace_bytes(n, p, lds) bytes,
+// 256-byte aligned; when null the library's per-stream workspace is used.
+int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hipStream_t s,
+             void* ws = nullptr);
 size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds);
 
 }  // namespace ffp

@@ -1,0 +1,538 @@
+// Request loop with continuous batching (see serve.h and include/ffp.h).
+#include "serve.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+
+#include "batch.h"
+#include "field.h"
+#include "ldlt.h"
+
+namespace ffp {
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t rup(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+int64_t result_ld(const ffp_request& r) { return rup(r.n > 0 ? r.n : 1, 4); }
+
+size_t result_bytes(const ffp_request& r)
+{
+    size_t b = (size_t)r.n * (size_t)result_ld(r) * 4;
+    if (r.kind == FFP_REQ_LDLT) b = (size_t)rup((int64_t)b, 256) + 256;   // + info
+    return (size_t)rup((int64_t)b, 256);
+}
+
+constexpr int kMaxBatch = 128;
+
+// Workspace the request needs while it runs (the same figure the batched
+// launch and the LDL^T driver use for it).
+size_t workspace_bytes(const ffp_request& r)
+{
+    if (r.n == 0) return 0;
+    if (r.kind == FFP_REQ_LDLT) return (size_t)rup((int64_t)ldlt_workspace_bytes(r.n, r.p, result_ld(r)), 256);
+    ffp_job j{};
+    j.n = r.n;
+    j.k = r.k;
+    j.p = r.p;
+    j.alpha = r.alpha;
+    j.beta = 0;
+    j.a_dtype = FFP_U32;
+    j.A = r.A;
+    j.lda = r.lda;
+    j.C = (uint32_t*)(uintptr_t)256;   // results are 256-byte aligned in the arena
+    j.ldc = result_ld(r);
+    return (size_t)job_workspace_bytes(j, 0);
+}
+
+// ---- device backed by HIP --------------------------------------------------
+class HipDevice : public DeviceIface {
+public:
+    ~HipDevice() override
+    {
+        for (hipStream_t s : streams_) (void)hipStreamDestroy(s);
+        if (arena_) (void)hipFree(arena_);
+    }
+    int init(size_t arena_bytes, int nstreams) override
+    {
+        if (hipGetDevice(&device_) != hipSuccess) return FFP_EDEVICE;
+        if (hipMalloc((void**)&arena_, arena_bytes ? arena_bytes : 256) != hipSuccess) {
+            arena_ = nullptr;
+            (void)hipGetLastError();
+            return FFP_ENOMEM;
+        }
+        for (int i = 0; i < nstreams; ++i) {
+            hipStream_t s;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return FFP_EDEVICE;
+            streams_.push_back(s);
+        }
+        return FFP_OK;
+    }
+    void bind_thread() override { (void)hipSetDevice(device_); }
+    char* arena() override { return arena_; }
+    int launch_syrk(std::vector<ServeReq*>& batch, int s, Unit* u) override
+    {
+        std::vector<ffp_job> jobs;
+        std::vector<char*> ws;
+        jobs.reserve(batch.size());
+        for (ServeReq* r : batch) {
+            ffp_job j{};
+            j.n = r->rq.n;
+            j.k = r->rq.k;
+            j.p = r->rq.p;
+            j.alpha = r->rq.alpha;
+            j.beta = 0;
+            j.a_dtype = FFP_U32;
+            j.A = r->rq.A;
+            j.lda = r->rq.lda;
+            j.C = (uint32_t*)(arena_ + r->off);
+            j.ldc = result_ld(r->rq);
+            jobs.push_back(j);
+            ws.push_back(r->ws_bytes ? arena_ + r->ws_off : nullptr);
+        }
+        int st = batched_run((int)jobs.size(), jobs.data(), 0, streams_[s], ws.data());
+        if (st != FFP_OK) return st;
+        return record(s, u);
+    }
+    int launch_ldlt(ServeReq* r, int s, Unit* u) override
+    {
+        const int64_t n = r->rq.n, ld = result_ld(r->rq);
+        uint32_t* S = (uint32_t*)(arena_ + r->off);
+        int64_t* info = (int64_t*)(arena_ + r->off + rup(n * ld * 4, 256));
+        if (n > 0 && hipMemcpy2DAsync(S, ld * 4, r->rq.A, r->rq.lda * 4, n * 4, n,
+                                      hipMemcpyDeviceToDevice, streams_[s]) != hipSuccess)
+            return FFP_EDEVICE;
+        int st = ldlt_run(n, r->rq.p, S, ld, info, streams_[s], arena_ + r->ws_off);
+        if (st != FFP_OK) return st;
+        return record(s, u);
+    }
+    bool done(Unit* u) override
+    {
+        return hipEventQuery((hipEvent_t)u->event) == hipSuccess;
+    }
+    void sync_stream(int s) override { (void)hipStreamSynchronize(streams_[s]); }
+    void release(Unit* u) override
+    {
+        if (u->event) (void)hipEventDestroy((hipEvent_t)u->event);
+        u->event = nullptr;
+    }
+
+private:
+    int record(int s, Unit* u)
+    {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return FFP_EDEVICE;
+        if (hipEventRecord(e, streams_[s]) != hipSuccess) return FFP_EDEVICE;
+        u->event = e;
+        return FFP_OK;
+    }
+    char* arena_ = nullptr;
+    int device_ = 0;
+    std::vector<hipStream_t> streams_;
+};
+
+// ---- simulated device: no computation, completion after a modelled time ----
+class SimDevice : public DeviceIface {
+public:
+    SimDevice(double ns_per_op, double launch_us) : ns_(ns_per_op), launch_(launch_us) {}
+    int init(size_t, int nstreams) override
+    {
+        free_at_.assign(nstreams, 0.0);
+        return FFP_OK;
+    }
+    char* arena() override { return nullptr; }
+    int launch_syrk(std::vector<ServeReq*>& batch, int s, Unit* u) override
+    {
+        double ops = 0;
+        for (ServeReq* r : batch) ops += (double)r->rq.n * r->rq.n * r->rq.k;
+        return finish(s, u, ops);
+    }
+    int launch_ldlt(ServeReq* r, int s, Unit* u) override
+    {
+        return finish(s, u, (double)r->rq.n * r->rq.n * r->rq.n / 3.0);
+    }
+    bool done(Unit* u) override { return now_s() >= u->sim_done; }
+    void release(Unit*) override {}
+
+private:
+    int finish(int s, Unit* u, double ops)
+    {
+        const double start = std::max(now_s(), free_at_[s]);
+        u->sim_done = start + launch_ * 1e-6 + ops * ns_ * 1e-9;
+        free_at_[s] = u->sim_done;
+        return FFP_OK;
+    }
+    double ns_, launch_;
+    std::vector<double> free_at_;
+};
+
+}  // namespace
+
+DeviceIface* make_hip_device() { return new HipDevice(); }
+DeviceIface* make_sim_device(double ns_per_op, double launch_us)
+{
+    return new SimDevice(ns_per_op, launch_us);
+}
+
+Server::Server(DeviceIface* dev, size_t budget, int max_inflight, int nstreams)
+    : dev_(dev), budget_(budget), max_inflight_(max_inflight), nstreams_(nstreams)
+{
+    stream_busy_.assign(nstreams, 0);
+    free_.push_back({0, budget});
+}
+
+Server::~Server()
+{
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        stop_ = true;
+    }
+    cv_.notify_all();
+    if (th_.joinable()) th_.join();
+    delete dev_;
+}
+
+int Server::start()
+{
+    int st = dev_->init(budget_, nstreams_);
+    if (st != FFP_OK) return st;
+    th_ = std::thread([this] { loop(); });
+    return FFP_OK;
+}
+
+
+bool Server::arena_alloc(size_t bytes, size_t* off)
+{
+    for (size_t i = 0; i < free_.size(); ++i) {
+        if (free_[i].second >= bytes) {
+            *off = free_[i].first;
+            free_[i].first += bytes;
+            free_[i].second -= bytes;
+            if (free_[i].second == 0) free_.erase(free_.begin() + (long)i);
+            return true;
+        }
+    }
+    return false;
+}
+
+void Server::arena_free(size_t off, size_t bytes)
+{
+    auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (size_t)0));
+    it = free_.insert(it, {off, bytes});
+    // coalesce with neighbours
+    size_t i = (size_t)(it - free_.begin());
+    if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
+        free_[i].second += free_[i + 1].second;
+        free_.erase(free_.begin() + (long)i + 1);
+    }
+    if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
+        free_[i - 1].second += free_[i].second;
+        free_.erase(free_.begin() + (long)i);
+    }
+}
+
+int Server::submit(const ffp_request* r, uint64_t* ticket)
+{
+    if (!r || !ticket) return FFP_EINVAL;
+    if (r->kind != FFP_REQ_SYRK && r->kind != FFP_REQ_LDLT) return FFP_EINVAL;
+    if (r->n < 0 || r->n > ((int64_t)1 << 20)) return FFP_EINVAL;
+    if (r->p < 3 || r->p >= (1u << 25) || !is_prime_u32(r->p)) return FFP_EPRIME;
+    if (r->kind == FFP_REQ_SYRK) {
+        if (r->k < 0 || r->alpha >= r->p) return FFP_EINVAL;
+        if (r->n > 0 && r->k > 0 && (r->A == nullptr || r->lda < r->k)) return FFP_EINVAL;
+    } else {
+        if (r->n > 0 && (r->A == nullptr || r->lda < r->n)) return FFP_EINVAL;
+    }
+    ServeReq q;
+    q.rq = *r;
+    if (q.rq.kind == FFP_REQ_LDLT) q.rq.k = q.rq.n;
+    q.bytes = result_bytes(q.rq);
+    q.ws_bytes = workspace_bytes(q.rq);
+    if (q.bytes + q.ws_bytes > budget_) return FFP_ENOMEM;
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        q.ticket = reqs_.size() + 1;
+        q.t_submit = now_s();
+        reqs_.push_back(q);
+        queue_.push_back(q.ticket);
+        *ticket = q.ticket;
+    }
+    cv_.notify_all();
+    return FFP_OK;
+}
+
+int Server::status(uint64_t ticket, ffp_result* out)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (ticket == 0 || ticket > reqs_.size() || !out) return FFP_EINVAL;
+    const ServeReq& q = reqs_[ticket - 1];
+    memset(out, 0, sizeof *out);
+    out->state = q.status != FFP_OK ? q.status : q.state;
+    out->t_submit = q.t_submit;
+    out->t_admit = q.t_admit;
+    out->t_done = q.t_done;
+    char* base = dev_->arena();
+    if (q.state != FFP_STATE_QUEUED && !q.released && base) {
+        out->C = (uint32_t*)(base + q.off);
+        out->ldc = result_ld(q.rq);
+        if (q.rq.kind == FFP_REQ_LDLT)
+            out->info = (int64_t*)(base + q.off + rup(q.rq.n * result_ld(q.rq) * 4, 256));
+    }
+    return FFP_OK;
+}
+
+int Server::release(uint64_t ticket)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (ticket == 0 || ticket > reqs_.size()) return FFP_EINVAL;
+    ServeReq& q = reqs_[ticket - 1];
+    if (q.state != FFP_STATE_DONE) return FFP_EINVAL;
+    if (!q.released) {
+        q.released = true;
+        arena_free(q.off, q.bytes);
+        used_ -= q.bytes;
+    }
+    cv_.notify_all();
+    return FFP_OK;
+}
+
+int Server::drain(double timeout_s)
+{
+    std::unique_lock<std::mutex> lk(mu_);
+    const auto deadline = std::chrono::steady_clock::now() +
+                          std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                              std::chrono::duration<double>(timeout_s));
+    while (!(queue_.empty() && running_.empty())) {
+        if (cv_done_.wait_until(lk, deadline) == std::cv_status::timeout &&
+            !(queue_.empty() && running_.empty()))
+            return FFP_EDEVICE;
+    }
+    return FFP_OK;
+}
+
+int Server::fetch(uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst, void* stream)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (ticket == 0 || ticket > reqs_.size()) return FFP_EINVAL;
+    const ServeReq& q = reqs_[ticket - 1];
+    char* base = dev_->arena();
+    if (!base || q.state != FFP_STATE_DONE || q.status != FFP_OK || q.released) return FFP_EINVAL;
+    const int64_t n = q.rq.n, ld = result_ld(q.rq);
+    if (n == 0) return FFP_OK;
+    if (!dst || ldd < n) return FFP_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpy2DAsync(dst, ldd * 4, base + q.off, ld * 4, n * 4, n, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+        return FFP_EDEVICE;
+    if (q.rq.kind == FFP_REQ_LDLT && info_dst &&
+        hipMemcpyAsync(info_dst, base + q.off + rup(n * ld * 4, 256), sizeof(int64_t),
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return FFP_EDEVICE;
+    return FFP_OK;
+}
+
+int Server::stats(ffp_serve_stats* out)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (!out) return FFP_EINVAL;
+    memset(out, 0, sizeof *out);
+    out->submitted = (int64_t)reqs_.size();
+    for (const ServeReq& q : reqs_) out->completed += q.state == FFP_STATE_DONE;
+    out->units = units_;
+    out->batched_jobs = batched_jobs_;
+    out->max_batch = max_batch_;
+    out->peak_inflight = peak_inflight_;
+    out->overlapped_units = overlap_units_;
+    out->peak_bytes = peak_used_;
+    return FFP_OK;
+}
+
+void Server::loop()
+{
+    dev_->bind_thread();
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+        bool progress = false;
+        // completions
+        for (size_t i = 0; i < running_.size();) {
+            Unit& u = running_[i];
+            if (dev_->done(&u)) {
+                const double t = now_s();
+                for (uint64_t tk : u.tickets) {
+                    ServeReq& q = reqs_[tk - 1];
+                    q.state = FFP_STATE_DONE;
+                    q.t_done = t;
+                    --inflight_;
+                    if (q.ws_bytes) {
+                        arena_free(q.ws_off, q.ws_bytes);
+                        used_ -= q.ws_bytes;
+                    }
+                }
+                stream_busy_[u.stream] = 0;
+                dev_->release(&u);
+                running_.erase(running_.begin() + (long)i);
+                progress = true;
+            } else {
+                ++i;
+            }
+        }
+        if (progress) cv_done_.notify_all();
+        // admission and launch, one unit per free stream
+        for (int s = 0; s < nstreams_ && !queue_.empty(); ++s) {
+            if (stream_busy_[s]) continue;
+            std::vector<ServeReq*> batch;
+            ServeReq* ldlt = nullptr;
+            while (!queue_.empty() && (int)batch.size() < kMaxBatch && !ldlt) {
+                ServeReq& q = reqs_[queue_.front() - 1];
+                if (q.rq.kind == FFP_REQ_LDLT && !batch.empty()) break;   // arrival order
+                const size_t need = q.bytes + q.ws_bytes;
+                size_t off = 0, ws_off = 0;
+                if (inflight_ >= max_inflight_ || used_ + need > budget_ || !arena_alloc(q.bytes, &off))
+                    break;
+                if (q.ws_bytes && !arena_alloc(q.ws_bytes, &ws_off)) {
+                    arena_free(off, q.bytes);
+                    break;
+                }
+                q.off = off;
+                q.ws_off = ws_off;
+                used_ += need;
+                peak_used_ = std::max(peak_used_, used_);
+                q.state = FFP_STATE_RUNNING;
+                q.t_admit = now_s();
+                ++inflight_;
+                peak_inflight_ = std::max<int64_t>(peak_inflight_, inflight_);
+                queue_.pop_front();
+                if (q.rq.kind == FFP_REQ_LDLT) ldlt = &q;
+                else batch.push_back(&q);
+            }
+            if (batch.empty() && !ldlt) break;
+            Unit u;
+            u.stream = s;
+            u.t_launch = now_s();
+            int st;
+            if (ldlt) {
+                u.tickets.push_back(ldlt->ticket);
+                st = dev_->launch_ldlt(ldlt, s, &u);
+            } else {
+                for (ServeReq* q : batch) u.tickets.push_back(q->ticket);
+                st = dev_->launch_syrk(batch, s, &u);
+                batched_jobs_ += (int64_t)batch.size();
+                max_batch_ = std::max<int64_t>(max_batch_, (int64_t)batch.size());
+            }
+            if (!running_.empty()) ++overlap_units_;
+            ++units_;
+            if (st != FFP_OK) {
+                // nothing may still run on this stream for the failed unit
+                // before its workspace goes back to the arena
+                dev_->sync_stream(s);
+                for (uint64_t tk : u.tickets) {
+                    ServeReq& q = reqs_[tk - 1];
+                    q.status = st;
+                    q.state = FFP_STATE_DONE;
+                    q.t_done = now_s();
+                    --inflight_;
+                    if (q.ws_bytes) {
+                        arena_free(q.ws_off, q.ws_bytes);
+                        used_ -= q.ws_bytes;
+                    }
+                }
+                dev_->release(&u);
+                cv_done_.notify_all();
+                continue;
+            }
+            stream_busy_[s] = 1;
+            running_.push_back(u);
+            progress = true;
+        }
+        if (stop_ && running_.empty()) break;
+        if (!progress) cv_.wait_for(lk, std::chrono::microseconds(running_.empty() ? 2000 : 20));
+    }
+}
+
+}  // namespace ffp
+
+using ffp::Server;
+
+struct ffp_server {
+    Server* impl;
+};
+
+extern "C" {
+
+int ffp_server_create(size_t hbm_budget, int max_inflight, int nstreams, ffp_server** out)
+{
+    if (!out || max_inflight < 1 || nstreams < 1 || nstreams > 16 || hbm_budget == 0) return FFP_EINVAL;
+    Server* s = new Server(ffp::make_hip_device(), hbm_budget, max_inflight, nstreams);
+    int st = s->start();
+    if (st != FFP_OK) {
+        delete s;
+        return st;
+    }
+    *out = new ffp_server{s};
+    return FFP_OK;
+}
+
+int ffp_server_create_simulated(size_t budget, int max_inflight, int nstreams, double ns_per_op,
+                                double launch_us, ffp_server** out)
+{
+    if (!out || max_inflight < 1 || nstreams < 1 || nstreams > 16 || budget == 0) return FFP_EINVAL;
+    Server* s = new Server(ffp::make_sim_device(ns_per_op, launch_us), budget, max_inflight, nstreams);
+    int st = s->start();
+    if (st != FFP_OK) {
+        delete s;
+        return st;
+    }
+    *out = new ffp_server{s};
+    return FFP_OK;
+}
+
+int ffp_server_submit(ffp_server* s, const ffp_request* r, uint64_t* ticket)
+{
+    return s ? s->impl->submit(r, ticket) : FFP_EINVAL;
+}
+
+int ffp_server_status(ffp_server* s, uint64_t ticket, ffp_result* out)
+{
+    return s ? s->impl->status(ticket, out) : FFP_EINVAL;
+}
+
+int ffp_server_release(ffp_server* s, uint64_t ticket)
+{
+    return s ? s->impl->release(ticket) : FFP_EINVAL;
+}
+
+int ffp_server_drain(ffp_server* s, double timeout_s)
+{
+    return s ? s->impl->drain(timeout_s) : FFP_EINVAL;
+}
+
+int ffp_server_fetch(ffp_server* s, uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst,
+                     void* stream)
+{
+    return s ? s->impl->fetch(ticket, dst, ldd, info_dst, stream) : FFP_EINVAL;
+}
+
+int ffp_server_stats(ffp_server* s, ffp_serve_stats* out)
+{
+    return s ? s->impl->stats(out) : FFP_EINVAL;
+}
+
+int ffp_server_destroy(ffp_server* s)
+{
+    if (!s) return FFP_EINVAL;
+    delete s->impl;
+    delete s;
+    return FFP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Request loop with continuous (iteration-level) batching for A*A^T and
+// LDL^T jobs.  The scheduler is written against a small device interface so
+// that its admission and batching logic also runs against a simulated device
+// (no computation) in host-only tests.
+#pragma once
+#include <condition_variable>
+#include <cstddef>
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "ffp.h"
+
+namespace ffp {
+
+struct ServeReq {
+    ffp_request rq;
+    uint64_t ticket = 0;
+    int state = FFP_STATE_QUEUED;
+    size_t bytes = 0;        // arena bytes held for the result until release
+    size_t off = 0;          // offset of the result in the arena
+    size_t ws_bytes = 0;     // arena bytes of workspace, held while running
+    size_t ws_off = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int status = FFP_OK;
+    bool released = false;
+};
+
+// One launched unit of work: a batch of SYRK jobs or one LDL^T, on a stream.
+struct Unit {
+    int stream = -1;
+    std::vector<uint64_t> tickets;
+    double t_launch = 0;
+    double sim_done = 0;     // simulated device: completion time
+    void* event = nullptr;   // real device: hipEvent_t
+};
+
+class DeviceIface {
+public:
+    virtual ~DeviceIface() = default;
+    virtual int init(size_t arena_bytes, int nstreams) = 0;
+    virtual void bind_thread() {}   // called first on the scheduler thread
+    virtual char* arena() = 0;
+    // Enqueue a batch of SYRK requests (results at arena + off) on stream s.
+    virtual int launch_syrk(std::vector<ServeReq*>& batch, int s, Unit* u) = 0;
+    virtual int launch_ldlt(ServeReq* r, int s, Unit* u) = 0;
+    virtual bool done(Unit* u) = 0;
+    virtual void sync_stream(int) {}
+    virtual void release(Unit* u) = 0;
+};
+
+DeviceIface* make_hip_device();
+DeviceIface* make_sim_device(double ns_per_op, double launch_us);
+
+class Server {
+public:
+    Server(DeviceIface* dev, size_t budget, int max_inflight, int nstreams);
+    ~Server();
+    int start();
+    int submit(const ffp_request* rq, uint64_t* ticket);
+    int status(uint64_t ticket, ffp_result* out);
+    int release(uint64_t ticket);
+    int drain(double timeout_s);
+    int fetch(uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst, void* stream);
+    int stats(ffp_serve_stats* out);
+
+private:
+    void loop();
+    bool arena_alloc(size_t bytes, size_t* off);
+    void arena_free(size_t off, size_t bytes);
+
+    DeviceIface* dev_;
+    size_t budget_;
+    int max_inflight_, nstreams_;
+    std::mutex mu_;
+    std::condition_variable cv_, cv_done_;
+    std::thread th_;
+    bool stop_ = false;
+    std::deque<uint64_t> queue_;           // submitted, not admitted (FIFO)
+    std::vector<ServeReq> reqs_;           // by ticket - 1
+    std::vector<Unit> running_;
+    std::vector<char> stream_busy_;
+    std::vector<std::pair<size_t, size_t>> free_;   // (offset, size), sorted
+    size_t used_ = 0, peak_used_ = 0;
+    int inflight_ = 0, peak_inflight_ = 0;
+    int64_t units_ = 0, batched_jobs_ = 0, max_batch_ = 0, overlap_units_ = 0;
+};
+
+}  // namespace ffp

@@ -48,6 +48,31 @@ class ffp_job(ctypes.Structure):
                 ("ldc", ctypes.c_int64)]
 
 
+class ffp_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("p", ctypes.c_uint32), ("alpha", ctypes.c_uint32), ("A", ctypes.c_void_p),
+                ("lda", ctypes.c_int64)]
+
+
+class ffp_result(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("info", ctypes.c_void_p), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ffp_serve_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("units", ctypes.c_int64), ("batched_jobs", ctypes.c_int64),
+                ("max_batch", ctypes.c_int64), ("peak_inflight", ctypes.c_int64),
+                ("overlapped_units", ctypes.c_int64), ("peak_bytes", ctypes.c_size_t)]
+
+
+FFP_REQ_SYRK = 0
+FFP_REQ_LDLT = 1
+FFP_STATE_QUEUED = 0
+FFP_STATE_RUNNING = 1
+FFP_STATE_DONE = 2
+
 _lib = None
 
 
@@ -75,6 +100,17 @@ def lib():
             "ffp_host_nrsyf": (c_int, [u32, u32, u32, P]),
             "ffp_plan_describe": (c_int, [i64, i64, u32, c_int, i64, i64, u32, u32, c_uint,
                                           ctypes.c_char_p, ctypes.c_size_t]),
+            "ffp_ldlt_workspace_bytes": (ctypes.c_size_t, [i64, u32]),
+            "ffp_server_create": (c_int, [ctypes.c_size_t, c_int, c_int, P]),
+            "ffp_server_create_simulated": (c_int, [ctypes.c_size_t, c_int, c_int, ctypes.c_double,
+                                                    ctypes.c_double, P]),
+            "ffp_server_submit": (c_int, [P, P, P]),
+            "ffp_server_status": (c_int, [P, ctypes.c_uint64, P]),
+            "ffp_server_release": (c_int, [P, ctypes.c_uint64]),
+            "ffp_server_drain": (c_int, [P, ctypes.c_double]),
+            "ffp_server_stats": (c_int, [P, P]),
+            "ffp_server_fetch": (c_int, [P, ctypes.c_uint64, P, i64, P, P]),
+            "ffp_server_destroy": (c_int, [P]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name, None)
@@ -134,6 +170,10 @@ def fldlt_modp(n, p, S, lds, info, stream=None):
 
 def ffp_workspace_bytes(n, k, p, a_dtype=FFP_U32, flags=0) -> int:
     return int(lib().ffp_workspace_bytes(n, k, p, a_dtype, flags))
+
+
+def ffp_ldlt_workspace_bytes(n, p) -> int:
+    return int(lib().ffp_ldlt_workspace_bytes(n, p))
 
 
 def fsyrk_modp_batched(jobs, flags=0, stream=None):
@@ -242,3 +282,71 @@ def ldlt(S, p: int, stream=None):
     info = torch.zeros(1, dtype=torch.int64, device=S.device)
     fldlt_modp(n, p, S, S.stride(0), info, stream)
     return info
+
+
+# ---- request loop ----------------------------------------------------------
+
+class Server:
+    """Continuous-batching request loop (ffp_server_* of include/ffp.h)."""
+
+    def __init__(self, hbm_budget: int, max_inflight: int = 64, nstreams: int = 4,
+                 simulated: bool = False, ns_per_op: float = 0.02, launch_us: float = 10.0):
+        self._h = ctypes.c_void_p()
+        if simulated:
+            st = lib().ffp_server_create_simulated(hbm_budget, max_inflight, nstreams, ns_per_op,
+                                                   launch_us, ctypes.byref(self._h))
+        else:
+            st = lib().ffp_server_create(hbm_budget, max_inflight, nstreams, ctypes.byref(self._h))
+        _check(st, "ffp_server_create")
+
+    def submit_syrk(self, A, p, alpha=1, n=None, k=None, lda=None) -> int:
+        n = A.shape[0] if n is None else n
+        k = A.shape[1] if k is None else k
+        lda = A.stride(0) if lda is None else lda
+        r = ffp_request(kind=FFP_REQ_SYRK, n=n, k=k, p=p, alpha=alpha, A=_ptr(A), lda=lda)
+        return self._submit(r)
+
+    def submit_ldlt(self, S, p, n=None, lds=None) -> int:
+        n = S.shape[0] if n is None else n
+        lds = S.stride(0) if lds is None else lds
+        r = ffp_request(kind=FFP_REQ_LDLT, n=n, k=n, p=p, alpha=0, A=_ptr(S), lda=lds)
+        return self._submit(r)
+
+    def _submit(self, r) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().ffp_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "submit")
+        return t.value
+
+    def status(self, ticket: int) -> ffp_result:
+        out = ffp_result()
+        _check(lib().ffp_server_status(self._h, ticket, ctypes.byref(out)), "status")
+        return out
+
+    def release(self, ticket: int):
+        _check(lib().ffp_server_release(self._h, ticket), "release")
+
+    def drain(self, timeout_s: float = 600.0):
+        _check(lib().ffp_server_drain(self._h, timeout_s), "drain")
+
+    def fetch(self, ticket: int, out, info_out=None, stream=None):
+        """Copies a done request's result into the device tensor out (n x n
+        uint32/int32 view) and, for LDL^T, its info word into info_out."""
+        _check(lib().ffp_server_fetch(self._h, ticket, _ptr(out), out.stride(0),
+                                      _ptr(info_out) if info_out is not None else None,
+                                      _stream(stream)), "fetch")
+
+    def stats(self) -> ffp_serve_stats:
+        out = ffp_serve_stats()
+        _check(lib().ffp_server_stats(self._h, ctypes.byref(out)), "stats")
+        return out
+
+    def close(self):
+        if self._h:
+            lib().ffp_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
