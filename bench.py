@@ -79,7 +79,7 @@ def profile_hooks():
     def read_variants():
         """{variant: (ms, flops, launches, name)} of the recorded launches."""
         out = {}
-        for v in range(6):
+        for v in range(8):
             ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
             L.ffp_debug_profile_read_variant(v, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n))
             if n.value:
@@ -150,6 +150,241 @@ def run_workload(name, steps, warmup, check=True):
     return res
 
 
+def batched_vs_plain(steps=3, njobs=1024):
+    """1024 independent jobs (n ~ U[32,1024], k ~ U[n/2,2n], p ~ U{251, 65537,
+    131071}, seed 3): one fsyrk_modp_batched call against the same jobs as a
+    loop of per-call fsyrk_modp on one stream.  Results of both are compared
+    with each other bit for bit, and a sample with the oracle."""
+    import torch
+    import oracle
+    from paper_2001_04109_amd import ffp, inputs
+    shapes = inputs.batch_jobs(seed=3, njobs=njobs)
+    mats, devA, devC, devC2, jobs = [], [], [], [], []
+    for j, (n, k, p) in enumerate(shapes):
+        A = inputs.batch_matrix(3, j, n, k, p)
+        if j % 128 == 0:
+            mats.append((j, A))
+        Ad = torch.from_numpy(A.view(np.int32)).cuda()
+        devA.append(Ad)
+        devC.append(torch.zeros((n, n), dtype=torch.int32, device="cuda"))
+        devC2.append(torch.zeros((n, n), dtype=torch.int32, device="cuda"))
+        jobs.append(ffp.make_job(Ad, devC[-1], p, 1, 0))
+    torch.cuda.synchronize()
+    eff = float(sum(n * n * k for (n, k, _) in shapes))
+
+    def plain():
+        for (n, k, p), Ad, Cd in zip(shapes, devA, devC2):
+            ffp.syrk(Ad, p, C=Cd)
+
+    def batched():
+        ffp.fsyrk_modp_batched(jobs)
+
+    out = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[name] = {"ms": round(ms, 3), "gops": round(eff / (ms * 1e-3) / 1e9, 1)}
+    for (n, _, _), a, b in zip(shapes, devC, devC2):
+        low = torch.ones((n, n), dtype=torch.bool, device="cuda").tril()
+        if not torch.equal(a[low], b[low]):
+            raise SystemExit("bench: batched result differs from the per-call result")
+    for j, A in mats:
+        n, k, p = shapes[j]
+        rng = np.random.default_rng(j)
+        r = rng.integers(0, n, 32)
+        cc = rng.integers(0, n, 32)
+        lo, hi = np.maximum(r, cc), np.minimum(r, cc)
+        got = devC[j].cpu().numpy().view(np.uint32)[lo, hi]
+        if not np.array_equal(got, oracle.syrk_entries(A, p, lo, hi)):
+            raise SystemExit(f"bench: batched job {j} differs from the oracle")
+    out["speedup"] = round(out["plain"]["ms"] / out["batched"]["ms"], 3)
+    out["jobs"] = njobs
+    out["eff_ops"] = eff
+    del devA, devC, devC2, jobs
+    torch.cuda.empty_cache()
+    return out
+
+
+class OperandPool:
+    """Device-resident operands of the served stream: per prime p_i one
+    4096 x 8192 matrix of uniform residues (sub-seed (4, 1000 + i)), and one
+    symmetric 4096 x 4096 matrix mod 65537 whose leading principal minors
+    are all nonzero (sub-seed (4, 2000 + attempt), redrawn until the LDL^T of
+    the whole matrix reports no zero pivot).  Request r uses the leading
+    n x k (LDL^T: n x n) block; the LDL^T of a leading block is the leading
+    block of the whole factorisation, which checks served LDL^T results."""
+
+    def __init__(self, primes, ldlt_prime, seed=4, nmax=4096):
+        import torch
+        from paper_2001_04109_amd import ffp, inputs
+        self.A, self.A_host = {}, {}
+        for i, p in enumerate(primes):
+            self.A_host[p] = inputs.uniform((seed, 1000 + i), nmax, 2 * nmax, p)
+            self.A[p] = torch.from_numpy(self.A_host[p].view(np.int32)).cuda()
+        for attempt in range(8):
+            S = inputs.symmetric((seed, 2000 + attempt), nmax, ldlt_prime)
+            Sd = torch.from_numpy(S.view(np.int32)).cuda()
+            W = Sd.clone()
+            info = ffp.ldlt(W, ldlt_prime)
+            torch.cuda.synchronize()
+            if int(info.item()) == 0:
+                break
+        else:
+            raise SystemExit("bench: no generic-rank symmetric pool matrix in 8 draws")
+        self.S = Sd
+        self.LD = W      # packed L (strict lower) and D (diagonal) of the whole S
+
+    def operand(self, r):
+        if r["kind"] == "syrk":
+            return self.A[r["p"]][: r["n"], : r["k"]]
+        return self.S[: r["n"], : r["n"]]
+
+
+class ServedCheck:
+    """Checks every stride-th served result before it is released: LDL^T
+    results against the leading block of the pool's factorisation, A A^T
+    results on 32 sampled entries against the oracle.  Copies run on a side
+    stream of their own."""
+
+    def __init__(self, pool, stride=200):
+        import torch
+        self.pool, self.stride = pool, stride
+        self.side = torch.cuda.Stream()
+        self.samples = []      # (r, rows, cols, values)
+        self.ldlt_ok = 0
+        self.failures = []
+
+    def take(self, srv, t, r):
+        import torch
+        n = r["n"]
+        with torch.cuda.stream(self.side):
+            C = torch.empty((n, n), dtype=torch.int32, device="cuda")
+            info = torch.zeros(1, dtype=torch.int64, device="cuda")
+            srv.fetch(t, C, info if r["kind"] == "ldlt" else None, stream=self.side.cuda_stream)
+            if r["kind"] == "ldlt":
+                ref = self.pool.LD[:n, :n]
+                low = torch.ones((n, n), dtype=torch.bool, device="cuda").tril()
+                ok = bool(torch.equal(C[low], ref[low])) and int(info.item()) == 0
+                if ok:
+                    self.ldlt_ok += 1
+                else:
+                    self.failures.append(r["id"])
+            else:
+                rng = np.random.default_rng(r["id"])
+                a = rng.integers(0, n, 32)
+                b = rng.integers(0, n, 32)
+                lo, hi = np.maximum(a, b), np.minimum(a, b)
+                vals = C[torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()].cpu().numpy()
+                self.samples.append((r, lo, hi, vals.view(np.uint32)))
+        self.side.synchronize()
+
+    def finish(self):
+        import oracle
+        for r, lo, hi, vals in self.samples:
+            A = self.pool.A_host[r["p"]][: r["n"], : r["k"]]
+            if not np.array_equal(vals, oracle.syrk_entries(np.ascontiguousarray(A), r["p"], lo, hi)):
+                self.failures.append(r["id"])
+        if self.failures:
+            raise SystemExit(f"bench: served results differ from the reference: {self.failures[:5]}")
+        return {"checked_syrk": len(self.samples), "checked_ldlt": self.ldlt_ok}
+
+
+def eff_ops(r):
+    return float(r["n"]) ** 2 * r["k"] if r["kind"] == "syrk" else float(r["n"]) ** 3 / 3.0
+
+
+def served(nreq, rate=2000.0, budget=48 << 30, nstreams=4, max_inflight=256, saturate=False,
+           check=True, pool=None):
+    """Serves the Poisson stream (seed 4) through the request loop; arrival
+    times are followed unless saturate (all requests at t = 0).  Latency is
+    measured from the scheduled arrival time to completion, on the steady
+    clock the server stamps its events with (CLOCK_MONOTONIC)."""
+    import threading
+    import torch
+    from paper_2001_04109_amd import ffp, inputs
+    reqs = inputs.request_stream(seed=4, nreq=nreq, rate=rate)
+    if pool is None:
+        pool = OperandPool(inputs.BATCH_PRIMES, 65537)
+    ops = [pool.operand(r) for r in reqs]
+    torch.cuda.synchronize()
+    done_at = np.zeros(nreq)
+    bad = []
+    chk = ServedCheck(pool) if check else None
+    with ffp.Server(budget, max_inflight=max_inflight, nstreams=nstreams) as srv:
+        def reaper():
+            got = 0
+            while got < nreq:
+                for t in srv.poll(512, 0.05):
+                    st = srv.status(t)
+                    if st.state != ffp.FFP_STATE_DONE:
+                        bad.append((t - 1, st.state))
+                    elif chk and (t - 1) % chk.stride == 0:
+                        chk.take(srv, t, reqs[t - 1])
+                    done_at[t - 1] = st.t_done
+                    srv.release(t)
+                    got += 1
+
+        th = threading.Thread(target=reaper, daemon=True)
+        th.start()
+        t0 = time.monotonic()
+        for i, (r, d) in enumerate(zip(reqs, ops)):
+            if not saturate:
+                delay = t0 + r["t"] - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+            t = srv.submit_syrk(d, r["p"]) if r["kind"] == "syrk" else srv.submit_ldlt(d, r["p"])
+            assert t == i + 1
+        th.join(1800)
+        if th.is_alive():
+            raise SystemExit("bench: served stream did not finish")
+        stats = srv.stats()
+    if bad:
+        raise SystemExit(f"bench: {len(bad)} served requests failed, first {bad[0]}")
+    arrive = t0 + (np.zeros(nreq) if saturate else np.array([r["t"] for r in reqs]))
+    lat = done_at - arrive
+    span = done_at.max() - t0
+    syrk_ops = sum(eff_ops(r) for r in reqs if r["kind"] == "syrk")
+    ldlt_ops = sum(eff_ops(r) for r in reqs if r["kind"] == "ldlt")
+    return {"requests": nreq, "rate_per_s": rate, "saturated": saturate,
+            "span_s": round(span, 3),
+            "gops_syrk": round(syrk_ops / span / 1e9, 1),
+            "gops_ldlt_n3_over_3": round(ldlt_ops / span / 1e9, 1),
+            "gops_total": round((syrk_ops + ldlt_ops) / span / 1e9, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "units": stats.units, "max_batch": stats.max_batch,
+            "overlapped_units": stats.overlapped_units, "peak_inflight": stats.peak_inflight,
+            "peak_bytes": stats.peak_bytes,
+            "check": chk.finish() if chk else None}, reqs, pool
+
+
+def per_call_plain(reqs, pool):
+    """The same requests one after another through fsyrk_modp / fldlt_modp on
+    one stream (LDL^T works on a copy of the operand, as the server does)."""
+    import torch
+    from paper_2001_04109_amd import ffp
+    C = torch.empty((4096, 4096), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        n = r["n"]
+        if r["kind"] == "syrk":
+            ffp.syrk(pool.operand(r), r["p"], C=C[:n, :n])
+        else:
+            W = C[:n, :n]
+            W.copy_(pool.operand(r))
+            ffp.ldlt(W, r["p"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tot = sum(eff_ops(r) for r in reqs)
+    return {"s": round(dt, 3), "gops_total": round(tot / dt / 1e9, 1)}
+
+
 def cpu_baseline(name):
     """Oracle on a bounded sample: rows [n-r, n) of the lower triangle of the
     first shape, i.e. r*(2n-r+1)/2 dot products of length k (r = n for the
@@ -188,6 +423,10 @@ def main():
     ap.add_argument("--workload", default="syrk_8192_p131071_depth3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=20000,
+                    help="requests of the served stream (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus {args.gpus} "
@@ -227,6 +466,24 @@ def main():
             extra[other] = {"gops": round(r2["gops"], 1), "ms_per_step": round(r2["ms_per_step"], 4),
                             "frac_int8_peak_effective": round(r2["gops"] / 1e3 / PEAK_I8, 4),
                             "kernel_achieved_TOPs": round(a2, 2)}
+    if not args.no_extra and not args.no_batched:
+        log("bench: batched 1024 jobs vs per-call")
+        extra["batched_1024_jobs"] = batched_vs_plain()
+        log(f"bench: batched {extra['batched_1024_jobs']}")
+    if not args.no_extra and args.serve_requests > 0:
+        log(f"bench: served stream, {args.serve_requests} requests at {args.serve_rate}/s")
+        sv, reqs, pool = served(args.serve_requests, rate=args.serve_rate)
+        log(f"bench: served {sv}")
+        log("bench: same stream, all requests at t=0")
+        sat, _, _ = served(args.serve_requests, rate=args.serve_rate, saturate=True, pool=pool,
+                           check=False)
+        log(f"bench: saturated {sat}")
+        log("bench: same requests per call")
+        pc = per_call_plain(reqs, pool)
+        log(f"bench: per-call {pc}")
+        extra["served_stream"] = {"arrivals": sv, "saturated": sat, "per_call_plain": pc,
+                                  "saturated_vs_per_call": round(sat["gops_total"] / pc["gops_total"], 3)}
+        del pool
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")

@@ -205,6 +205,11 @@ int ffp_server_status(ffp_server* s, uint64_t ticket, ffp_result* out);
 int ffp_server_release(ffp_server* s, uint64_t ticket);
 /* Waits until every submitted request is done (FFP_EDEVICE on timeout). */
 int ffp_server_drain(ffp_server* s, double timeout_s);
+/* Completion queue: waits up to timeout_s seconds (0: no wait) until some
+ * request has finished, then returns in tickets up to max finished requests
+ * (failed ones included) not returned before, oldest first; *count is the
+ * number returned (0 on timeout). */
+int ffp_server_poll(ffp_server* s, uint64_t* tickets, int max, double timeout_s, int* count);
 /* Enqueues on stream a copy of a done request's result into the caller's
  * device buffer dst (n x n, row stride ldd >= n; only the lower triangle is
  * meaningful) and, for LDLT when info_dst is not null, of its info word.

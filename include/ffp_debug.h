@@ -53,6 +53,9 @@ void ffp_debug_set_kblk(int64_t kblk);
  * "f64_tile" (64 or 128: force the FP64 product tile; 0 = automatic),
  * "i8_tile" (128 or 256: force the int8 product tile; 0 = automatic),
  * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile),
+ * "i8_ring" (4 or 5: the 256 x 256 int8 tile loads its operands straight
+ * into a ring of that many LDS stages; 0 = register-staged loads; other
+ * values FFP_EINVAL),
  * "persistent" (1: grouped product launches run persistent workgroups that
  * stride over the tiles; 0: one workgroup per tile).
  * FFP_EINVAL for an unknown key. */
@@ -68,7 +71,8 @@ void ffp_debug_profile(int enable);
 int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches);
 /* Same, restricted to one product-kernel variant (0 FP64 64x64 tiles, 1 FP64
  * 128x128 LDS-staged tiles, 2 int8 128x128, 3 int8 256x256 with 64-byte k
- * stages, 4 int8 256x256 with 128-byte k stages, 5 int8 limbs 128x128);
+ * stages, 4 int8 256x256 with 128-byte k stages, 5 int8 limbs 128x128,
+ * 6 and 7 int8 256x256 with a ring of 4 or 5 direct-to-LDS stages);
  * ffp_debug_variant_name gives the kernel's demangled name. */
 int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches);
 const char* ffp_debug_variant_name(int variant);

@@ -169,6 +169,11 @@ int ffp_debug_set(const char* key, int64_t value)
     if (strcmp(key, "f64_tile") == 0) { ffp::g_f64_tile_override = (int)value; return FFP_OK; }
     if (strcmp(key, "i8_tile") == 0) { ffp::g_i8_tile_override = (int)value; return FFP_OK; }
     if (strcmp(key, "i8_bk") == 0) { ffp::g_i8_bk_override = (int)value; return FFP_OK; }
+    if (strcmp(key, "i8_ring") == 0) {
+        if (value != 0 && value != 4 && value != 5) return FFP_EINVAL;
+        ffp::g_i8_ring = (int)value;
+        return FFP_OK;
+    }
     if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value ? 1 : 0; return FFP_OK; }
     return FFP_EINVAL;
 }
@@ -194,6 +199,8 @@ const char* ffp_debug_variant_name(int variant)
     case 3: return "void ffp::prod_i8_kernel<256, 256, 64, 1>(ffp::ProdArgs, int)";
     case 4: return "void ffp::prod_i8_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";
     case 5: return "void ffp::prod_i8_kernel<128, 128, 64, 2>(ffp::ProdArgs, int)";
+    case 6: return "void ffp::prod_i8_ring_kernel<256, 256, 4>(ffp::ProdArgs, int)";
+    case 7: return "void ffp::prod_i8_ring_kernel<256, 256, 5>(ffp::ProdArgs, int)";
     default: return "";
     }
 }

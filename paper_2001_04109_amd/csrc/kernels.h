@@ -71,6 +71,7 @@ extern int64_t g_kblk_cap;
 extern int g_f64_tile_override;
 extern int g_i8_tile_override;
 extern int g_i8_bk_override;
+extern int g_i8_ring;          // CLS_I8 256x256: ring of 4 or 5 direct-to-LDS stages (0: off)
 // Multi-task product launches run persistent workgroups (1, default) or one
 // workgroup per tile (0).
 extern int g_persistent;

@@ -29,6 +29,7 @@
 // of that order (blocks are dispatched round-robin over the 8 XCDs).
 #include "prod_common.h"
 
+#include <type_traits>
 #include <vector>
 
 namespace ffp {
@@ -128,6 +129,49 @@ __device__ inline void lstore(int8_t* __restrict__ lds, const Prefetch<ROWS, BK>
 }
 
 }  // namespace
+
+// Epilogue of a CLS_I8 wave tile: through LDS, one 32-row slab of the wave
+// tile at a time, so that the reduction runs in a short loop with coalesced
+// row-major stores.  32x32 i32 MFMA result layout: lane l, element e holds
+// row 8*(e/4) + 4*(l/32) + e%4, column l%32.  Every wave of the workgroup
+// calls it (it contains workgroup barriers); `live` waves store.
+template <int WTM, int WTN, int FM, int FN>
+__device__ __forceinline__ void store_tile_i8(const v16i (&acc)[FM][FN], int32_t* smem32,
+                                              const ProdTask& t, int row0, int col0, bool live)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lrow = lane & 31, lk = lane >> 5;
+    const double pd = (double)t.p, alpha = (double)t.alpha, beta = (double)t.beta;
+    const bool plain = t.alpha == 1u && t.beta == 0u;
+    int32_t* ep = smem32 + wave * (32 * WTN);
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                ep[(8 * (e >> 2) + 4 * lk + (e & 3)) * WTN + j * 32 + lrow] = acc[i][j][e];
+        __syncthreads();
+        if (live) {
+            for (int idx = lane; idx < 32 * WTN; idx += 64) {
+                const int rr = idx / WTN, cc = idx - rr * WTN;
+                const int row = row0 + i * 32 + rr;
+                const int col = col0 + cc;
+                if (row >= t.m || col >= t.n || (t.syrk && col > row)) continue;
+                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                const double r = mod_f64((double)ep[idx], pd, t.pinv);
+                if (plain) {
+                    *dst = (uint32_t)r;
+                } else {
+                    double x = alpha * r;
+                    if (t.beta != 0u) x += beta * (double)(*dst);
+                    *dst = (uint32_t)mod_f64(x, pd, t.pinv);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
 
 // PLANES = 1: CLS_I8;  PLANES = 2: CLS_LIMB2.  BK: k bytes per stage.
 template <int BM, int BN, int BK, int PLANES>
@@ -271,32 +315,9 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
     // row 8*(e/4) + 4*(l/32) + e%4, column l%32.
     const double alpha = (double)t.alpha, beta = (double)t.beta;
     if constexpr (PLANES == 1) {
-        // Through LDS, one 32-row slab of the wave tile at a time, so the
-        // reduction runs in a short loop with coalesced row-major stores.
         static_assert(4 * 32 * WTN * 4 <= SA + SB, "epilogue slab must fit in LDS");
-        int32_t* ep = reinterpret_cast<int32_t*>(smem) + wave * (32 * WTN);
-#pragma unroll
-        for (int i = 0; i < FM; ++i) {
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int e = 0; e < 16; ++e)
-                    ep[(8 * (e >> 2) + 4 * lk + (e & 3)) * WTN + j * 32 + lrow] = acc[0][i][j][e];
-            __syncthreads();
-            if (wave_live) {
-                for (int idx = lane; idx < 32 * WTN; idx += 64) {
-                    const int rr = idx / WTN, cc = idx - rr * WTN;
-                    const int row = tile_r + wr * WTM + i * 32 + rr;
-                    const int col = tile_c + wc * WTN + cc;
-                    if (row >= t.m || col >= t.n || (t.syrk && col > row)) continue;
-                    uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
-                    double x = alpha * mod_f64((double)ep[idx], pd, t.pinv);
-                    if (t.beta != 0u) x += beta * (double)(*dst);
-                    *dst = (uint32_t)mod_f64(x, pd, t.pinv);
-                }
-            }
-            __syncthreads();
-        }
+        store_tile_i8<WTM, WTN, FM, FN>(acc[0], reinterpret_cast<int32_t*>(smem), t,
+                                        tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
     } else {
         if (!wave_live) return;
         const double r16 = (double)((65536u) % t.p), r8 = (double)(256u % t.p);
@@ -323,6 +344,191 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
     }
 }
 
+// ---- CLS_I8 with direct-to-LDS operand loads ---------------------------
+//
+// Same tile and wave decomposition as i8_tile with BK = 64, but the operand
+// panels go from global memory straight into LDS (global_load_lds_dwordx4:
+// each wave instruction fills 1 KB of LDS, lane L at byte 16 L) through a
+// ring of NS stages, so loads run NS - 2 stages ahead without staging
+// registers or LDS write instructions.  A stage holds the BM + BN rows of
+// 64 bytes of the A and B panels; the four 16-byte chunks of row r are
+// stored in the order c ^ s(r) with s(r) = ((r >> 1) ^ (r >> 3)) & 3, which
+// keeps the fragment reads (8 or 16 consecutive rows, one chunk) free of
+// bank conflicts.  The compiler does not order these loads against LDS
+// reads, so completion is waited for explicitly (vmcnt) before the
+// workgroup barrier that publishes a stage.
+
+__device__ __forceinline__ int swz64(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// Workgroup barrier without the compiler's fence (which would wait for every
+// direct-to-LDS load in flight); LDS reads of this wave are complete first.
+__device__ __forceinline__ void ring_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Waits until at most n of this wave's vector-memory loads are in flight.
+template <int L>
+__device__ __forceinline__ void wait_loads(int stages_after)
+{
+    static_assert(3 * L < 64, "vmcnt range");
+    if (stages_after >= 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * L) : "memory");
+    else if (stages_after == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * L) : "memory");
+    else if (stages_after == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(L) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+typedef __attribute__((address_space(1))) const void GVoid;
+typedef __attribute__((address_space(3))) void LVoid;
+
+template <int BM, int BN>
+__device__ __forceinline__ void ring_load(int8_t* stage, const int8_t* __restrict__ A, int64_t lda,
+                                          int a_row0, int a_rows, const int8_t* __restrict__ B,
+                                          int64_t ldb, int b_row0, int b_rows, int k0)
+{
+    constexpr int BLOCKS = (BM + BN) / 16;
+    constexpr int PER_WAVE = BLOCKS / 4;
+    static_assert(BLOCKS % 4 == 0 && (BM / 16) % PER_WAVE == 0, "a wave loads from one panel");
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const bool isA = wave * PER_WAVE < BM / 16;             // uniform per wave
+    const int8_t* __restrict__ g = isA ? A : B;
+    const int64_t ld = isA ? lda : ldb;
+    const int prow0 = isA ? a_row0 : b_row0, prows = isA ? a_rows : b_rows;
+    const int blk0 = isA ? wave * PER_WAVE : wave * PER_WAVE - BM / 16;
+#pragma unroll
+    for (int q = 0; q < PER_WAVE; ++q) {
+        const int r = (blk0 + q) * 16 + (lane >> 2);           // row within the panel
+        const int c = (lane & 3) ^ swz64(r);
+        // rows past the end re-read the last row (their outputs are not stored)
+        const int row = prow0 + r < prows ? prow0 + r : prows - 1;
+        const int8_t* src = g + (int64_t)row * ld + k0 + c * 16;
+        __builtin_amdgcn_global_load_lds((GVoid*)src, (LVoid*)(stage + (wave * PER_WAVE + q) * 1024),
+                                         16, 0, 0);
+    }
+}
+
+template <int BM, int BN, int NS>
+__device__ __forceinline__ void i8_ring_tile(const ProdArgs& args, int b)
+{
+    constexpr int BK = 64;
+    constexpr int STAGE = (BM + BN) * BK;
+    constexpr int WTM = BM / 2, WTN = BN / 2;
+    constexpr int FM = WTM / 32, FN = WTN / 32;
+    constexpr int LOADS = (BM + BN) / 16 / 4;              // per wave and stage
+    static_assert(4 * 32 * WTN * 4 <= NS * STAGE, "epilogue slab must fit in LDS");
+    __shared__ __attribute__((aligned(1024))) int8_t smem[NS * STAGE];
+
+    ProdTask t;
+    select_task(args, b, &t);
+    const int r = b - t.tile0;
+    int ti, tj;
+    if (t.syrk) band_tri(r, t.tm, &ti, &tj);
+    else band_rect(r, t.tm, t.tn, &ti, &tj);
+    const int tile_r = ti * BM, tile_c = tj * BN;
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lrow = lane & 31, lk = lane >> 5;
+    const int8_t* __restrict__ Ab = (const int8_t*)t.A.p;
+    const int8_t* __restrict__ Bb = (const int8_t*)t.B.p;
+
+    v16i acc[FM][FN];
+    // the task is the same for the whole workgroup: keep its loop bounds scalar
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0;
+    const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
+
+    // byte offsets of this lane's fragment rows inside a stage; the chunk of
+    // k-step ks is (2 ks + lk) ^ s(row), and s(row) only depends on lrow
+    const int sw = swz64(lrow);
+    const int ch0 = ((0 + lk) ^ sw) * 16, ch1 = ((2 + lk) ^ sw) * 16;
+    const int offA = (wr * WTM + lrow) * BK, offB = BM * BK + (wc * WTN + lrow) * BK;
+
+    const int nk = __builtin_amdgcn_readfirstlane(t.k / BK);
+    auto load_stage = [&](int s) {
+        ring_load<BM, BN>(smem + (s % NS) * STAGE, Ab, t.A.ld, tile_r, t.m, Bb, t.B.ld, tile_c, t.n,
+                          s * BK);
+    };
+    auto read_frags = [&](v4i (&xa)[FM], v4i (&xb)[FN], int s, int ch) {
+        const int8_t* st = smem + (s % NS) * STAGE;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            xa[i] = *reinterpret_cast<const v4i*>(st + offA + i * 32 * BK + ch);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            xb[j] = *reinterpret_cast<const v4i*>(st + offB + j * 32 * BK + ch);
+    };
+    auto mfmas = [&](const v4i (&xa)[FM], const v4i (&xb)[FN]) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[i], xb[j], acc[i][j], 0, 0, 0);
+    };
+    // one LDS read per MFMA over the first FM + FN MFMAs of a k-step, so the
+    // reads have the rest of the k-step to land; with mfma_first the k-step
+    // opens with an MFMA (its operands' wait then precedes the new reads)
+    auto interleave = [&](auto mfma_first) {
+        constexpr int lead = decltype(mfma_first)::value ? 1 : 0;
+        if constexpr (lead) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+#pragma unroll
+        for (int q = 0; q < FM + FN; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, FM * FN - (FM + FN) - lead, 0);
+    };
+
+    if (nk > 0) {
+        for (int s = 0; s < NS - 1 && s < nk; ++s) load_stage(s);
+        // stage 0 complete: the later prologue stages may stay in flight
+        wait_loads<LOADS>((nk < NS - 1 ? nk : NS - 1) - 1);
+        ring_barrier();
+        v4i fa[FM], fb[FN], na[FM], nb[FN];
+        read_frags(fa, fb, 0, ch0);
+        for (int kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) {
+                // publish stage kt + 1; this also ends every read of the
+                // buffer the next load overwrites (stage kt - 1)
+                const int issued = kt + NS - 1 < nk ? kt + NS - 1 : nk;
+                wait_loads<LOADS>(issued - (kt + 2));
+                ring_barrier();
+                if (kt + NS - 1 < nk) load_stage(kt + NS - 1);
+            }
+            // fa/fb (read during the previous k-step) have landed; stated to
+            // the compiler so that it adds no wait inside the MFMA stream
+            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+            read_frags(na, nb, kt, ch1);
+            mfmas(fa, fb);
+            interleave(std::false_type{});
+            // first k-step of the next stage; after the last stage this reads
+            // an idle ring buffer whose values are never used
+            read_frags(fa, fb, kt + 1, ch0);
+            mfmas(na, nb);
+            interleave(std::true_type{});
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    ring_barrier();
+    store_tile_i8<WTM, WTN, FM, FN>(acc, reinterpret_cast<int32_t*>(smem), t, tile_r + wr * WTM,
+                                    tile_c + wc * WTN, wave_live);
+}
+
+template <int BM, int BN, int NS>
+__global__ __launch_bounds__(256) void prod_i8_ring_kernel(ProdArgs args, int mode)
+{
+    if (mode == 2) {
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) i8_ring_tile<BM, BN, NS>(args, b);
+        return;
+    }
+    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b < args.total_tiles) i8_ring_tile<BM, BN, NS>(args, b);
+}
+
 // mode 0: one workgroup per tile; 1: same, XCD-aware order; 2: persistent.
 template <int BM, int BN, int BK, int PLANES>
 __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int mode)
@@ -338,7 +544,7 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int mode)
 
 namespace {
 
-template <int BM, int BN, int BK, int PLANES>
+template <int BM, int BN, int BK, int PLANES, int RING>
 hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     ProdArgs args{};
@@ -363,12 +569,22 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
     }
     const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
     int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
-    if (mode == 2) {
-        const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES>);
-        grid = total < resident ? total : resident;
+    if constexpr (RING > 0) {
+        static_assert(PLANES == 1 && BK == 64, "ring variant: CLS_I8, 64-byte stages");
+        if (mode == 2) {
+            const int resident = resident_blocks((const void*)prod_i8_ring_kernel<BM, BN, RING>);
+            grid = total < resident ? total : resident;
+        }
+        g_last_variant = 6 + (RING - 4);
+        hipLaunchKernelGGL((prod_i8_ring_kernel<BM, BN, RING>), dim3(grid), dim3(256), 0, s, args, mode);
+    } else {
+        if (mode == 2) {
+            const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES>);
+            grid = total < resident ? total : resident;
+        }
+        g_last_variant = PLANES == 2 ? 5 : (BM == 128 ? 2 : (BK == 64 ? 3 : 4));
+        hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
     }
-    g_last_variant = PLANES == 2 ? 5 : (BM == 128 ? 2 : (BK == 64 ? 3 : 4));
-    hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
     return hipGetLastError();
 }
 
@@ -376,7 +592,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
 // block length the task runs as consecutive launches over k-chunks, each
 // accumulating into C (beta = 1 after the first), which reduces mod p
 // between chunks.
-template <int BM, int BN, int BK, int PLANES>
+template <int BM, int BN, int BK, int PLANES, int RING = 0>
 hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     int32_t maxk = 0, kblk = 1 << 30;
@@ -394,7 +610,7 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         kblk = t.kblk < kblk ? t.kblk : kblk;
         maxk = t.k > maxk ? t.k : maxk;
     }
-    if (maxk <= kblk) return launch_i8_once<BM, BN, BK, PLANES>(tasks, ntasks, dev_task_buf, s);
+    if (maxk <= kblk) return launch_i8_once<BM, BN, BK, PLANES, RING>(tasks, ntasks, dev_task_buf, s);
     std::vector<ProdTask> part(tasks, tasks + ntasks);
     for (int32_t k0 = 0; k0 < maxk; k0 += kblk) {
         int np = 0;
@@ -411,7 +627,7 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         // chunk launches carry their tasks inline (no staging copy outlives `part`)
         for (int q0 = 0; q0 < np; q0 += kInlineTasks) {
             const int nq = np - q0 < kInlineTasks ? np - q0 : kInlineTasks;
-            hipError_t e = launch_i8_once<BM, BN, BK, PLANES>(part.data() + q0, nq, nullptr, s);
+            hipError_t e = launch_i8_once<BM, BN, BK, PLANES, RING>(part.data() + q0, nq, nullptr, s);
             if (e != hipSuccess) return e;
         }
     }
@@ -432,6 +648,7 @@ int64_t tiles_of(const ProdTask* tasks, int ntasks, int bm)
 
 int g_i8_tile_override = 0;
 int g_i8_bk_override = 0;
+int g_i8_ring = 0;
 
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
@@ -442,6 +659,8 @@ hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_bu
     bool k128 = true;
     for (int i = 0; i < ntasks; ++i) k128 = k128 && (tasks[i].k % 128) == 0;
     if (big) {
+        if (g_i8_ring == 4) return launch_i8_impl<256, 256, 64, 1, 4>(tasks, ntasks, dev_task_buf, s);
+        if (g_i8_ring == 5) return launch_i8_impl<256, 256, 64, 1, 5>(tasks, ntasks, dev_task_buf, s);
         if (g_i8_bk_override == 64 || !k128) return launch_i8_impl<256, 256, 64, 1>(tasks, ntasks, dev_task_buf, s);
         return launch_i8_impl<256, 256, 128, 1>(tasks, ntasks, dev_task_buf, s);
     }

@@ -312,11 +312,29 @@ int Server::drain(double timeout_s)
     const auto deadline = std::chrono::steady_clock::now() +
                           std::chrono::duration_cast<std::chrono::steady_clock::duration>(
                               std::chrono::duration<double>(timeout_s));
-    while (!(queue_.empty() && running_.empty())) {
-        if (cv_done_.wait_until(lk, deadline) == std::cv_status::timeout &&
-            !(queue_.empty() && running_.empty()))
-            return FFP_EDEVICE;
+    auto idle = [this] { return queue_.empty() && running_.empty() && !launching_; };
+    while (!idle()) {
+        if (cv_done_.wait_until(lk, deadline) == std::cv_status::timeout && !idle()) return FFP_EDEVICE;
     }
+    return FFP_OK;
+}
+
+int Server::poll(uint64_t* tickets, int max, double timeout_s, int* count)
+{
+    if (!tickets || !count || max < 1) return FFP_EINVAL;
+    std::unique_lock<std::mutex> lk(mu_);
+    const auto deadline = std::chrono::steady_clock::now() +
+                          std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                              std::chrono::duration<double>(timeout_s > 0 ? timeout_s : 0.0));
+    while (done_q_.empty() && timeout_s > 0) {
+        if (cv_done_.wait_until(lk, deadline) == std::cv_status::timeout) break;
+    }
+    int n = 0;
+    while (n < max && !done_q_.empty()) {
+        tickets[n++] = done_q_.front();
+        done_q_.pop_front();
+    }
+    *count = n;
     return FFP_OK;
 }
 
@@ -377,6 +395,7 @@ void Server::loop()
                         arena_free(q.ws_off, q.ws_bytes);
                         used_ -= q.ws_bytes;
                     }
+                    done_q_.push_back(tk);
                 }
                 stream_busy_[u.stream] = 0;
                 dev_->release(&u);
@@ -419,22 +438,26 @@ void Server::loop()
             Unit u;
             u.stream = s;
             u.t_launch = now_s();
-            int st;
             if (ldlt) {
                 u.tickets.push_back(ldlt->ticket);
-                st = dev_->launch_ldlt(ldlt, s, &u);
             } else {
                 for (ServeReq* q : batch) u.tickets.push_back(q->ticket);
-                st = dev_->launch_syrk(batch, s, &u);
                 batched_jobs_ += (int64_t)batch.size();
                 max_batch_ = std::max<int64_t>(max_batch_, (int64_t)batch.size());
             }
             if (!running_.empty()) ++overlap_units_;
             ++units_;
+            stream_busy_[s] = 1;
+            // Enqueue without the lock so that submitters are not held up by
+            // plan building; the admitted entries are not touched by other
+            // threads while RUNNING (reqs_ is a deque: addresses are stable).
+            launching_ = true;
+            lk.unlock();
+            const int st = ldlt ? dev_->launch_ldlt(ldlt, s, &u) : dev_->launch_syrk(batch, s, &u);
+            if (st != FFP_OK) dev_->sync_stream(s);   // nothing of the unit may still run
+            lk.lock();
+            launching_ = false;
             if (st != FFP_OK) {
-                // nothing may still run on this stream for the failed unit
-                // before its workspace goes back to the arena
-                dev_->sync_stream(s);
                 for (uint64_t tk : u.tickets) {
                     ServeReq& q = reqs_[tk - 1];
                     q.status = st;
@@ -445,12 +468,13 @@ void Server::loop()
                         arena_free(q.ws_off, q.ws_bytes);
                         used_ -= q.ws_bytes;
                     }
+                    done_q_.push_back(tk);
                 }
                 dev_->release(&u);
+                stream_busy_[s] = 0;
                 cv_done_.notify_all();
                 continue;
             }
-            stream_busy_[s] = 1;
             running_.push_back(u);
             progress = true;
         }
@@ -514,6 +538,11 @@ int ffp_server_release(ffp_server* s, uint64_t ticket)
 int ffp_server_drain(ffp_server* s, double timeout_s)
 {
     return s ? s->impl->drain(timeout_s) : FFP_EINVAL;
+}
+
+int ffp_server_poll(ffp_server* s, uint64_t* tickets, int max, double timeout_s, int* count)
+{
+    return s ? s->impl->poll(tickets, max, timeout_s, count) : FFP_EINVAL;
 }
 
 int ffp_server_fetch(ffp_server* s, uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst,

@@ -63,6 +63,7 @@ public:
     int status(uint64_t ticket, ffp_result* out);
     int release(uint64_t ticket);
     int drain(double timeout_s);
+    int poll(uint64_t* tickets, int max, double timeout_s, int* count);
     int fetch(uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst, void* stream);
     int stats(ffp_serve_stats* out);
 
@@ -78,8 +79,10 @@ private:
     std::condition_variable cv_, cv_done_;
     std::thread th_;
     bool stop_ = false;
+    bool launching_ = false;               // a unit is being enqueued (lock dropped)
     std::deque<uint64_t> queue_;           // submitted, not admitted (FIFO)
-    std::vector<ServeReq> reqs_;           // by ticket - 1
+    std::deque<ServeReq> reqs_;            // by ticket - 1 (stable addresses)
+    std::deque<uint64_t> done_q_;          // finished, not yet returned by poll
     std::vector<Unit> running_;
     std::vector<char> stream_busy_;
     std::vector<std::pair<size_t, size_t>> free_;   // (offset, size), sorted

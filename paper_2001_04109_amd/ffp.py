@@ -109,6 +109,7 @@ def lib():
             "ffp_server_release": (c_int, [P, ctypes.c_uint64]),
             "ffp_server_drain": (c_int, [P, ctypes.c_double]),
             "ffp_server_stats": (c_int, [P, P]),
+            "ffp_server_poll": (c_int, [P, P, c_int, ctypes.c_double, P]),
             "ffp_server_fetch": (c_int, [P, ctypes.c_uint64, P, i64, P, P]),
             "ffp_server_destroy": (c_int, [P]),
         }
@@ -327,6 +328,13 @@ class Server:
 
     def drain(self, timeout_s: float = 600.0):
         _check(lib().ffp_server_drain(self._h, timeout_s), "drain")
+
+    def poll(self, max_count: int = 256, timeout_s: float = 0.01) -> list:
+        """Tickets finished since the last poll (waits up to timeout_s)."""
+        buf = (ctypes.c_uint64 * max_count)()
+        cnt = ctypes.c_int()
+        _check(lib().ffp_server_poll(self._h, buf, max_count, timeout_s, ctypes.byref(cnt)), "poll")
+        return list(buf[:cnt.value])
 
     def fetch(self, ticket: int, out, info_out=None, stream=None):
         """Copies a done request's result into the device tensor out (n x n

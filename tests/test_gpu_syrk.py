@@ -154,6 +154,28 @@ def test_i8_tile_variants(tile, n, k):
         set_knob("i8_tile", 0)
 
 
+@pytest.mark.parametrize("ring", [4, 5])
+@pytest.mark.parametrize("n,k", [(300, 256), (513, 64), (1000, 320), (1100, 4096), (256, 128)])
+def test_i8_ring_variants(ring, n, k):
+    """256 x 256 int8 tiles fed by direct-to-LDS loads through a ring of 4
+    or 5 stages: fewer, as many and more k-stages than ring slots."""
+    p = 251
+    A = inputs.uniform(n + 7 * ring, n, k, p)
+    set_knob("i8_tile", 256)
+    set_knob("i8_ring", ring)
+    try:
+        check_lower(gpu_syrk(A, p, depth=0, a_dtype=ffp.FFP_I8_CENTERED), oracle.syrk(A, p))
+        C0 = inputs.uniform(8, n, n, p)
+        check_lower(gpu_syrk(A, p, depth=0, alpha=3, beta=5, C0=C0), oracle.syrk_ab(A, p, 3, 5, C0))
+        set_kblk(128)      # k in chunks of two stages, accumulated through C
+        check_lower(gpu_syrk(A, p, depth=1, alpha=p - 1, beta=1, C0=C0),
+                    oracle.syrk_ab(A, p, p - 1, 1, C0))
+    finally:
+        set_kblk(0)
+        set_knob("i8_ring", 0)
+        set_knob("i8_tile", 0)
+
+
 @pytest.mark.parametrize("p,a_dtype", [(251, ffp.FFP_U32), (251, ffp.FFP_I8_CENTERED),
                                        (65521, ffp.FFP_U32), (65521, ffp.FFP_I8_LIMB2),
                                        (257, ffp.FFP_U32)])
@@ -235,8 +257,9 @@ def test_full_size_8192_p131071_depth3(k):
     _sampled(A, p, from_dev_u32(Cd))
 
 
-@pytest.mark.parametrize("p,a_dtype", [(251, ffp.FFP_I8_CENTERED), (65521, ffp.FFP_I8_LIMB2)])
-def test_full_size_16384_int8(p, a_dtype):
+@pytest.mark.parametrize("p,a_dtype,ring", [(251, ffp.FFP_I8_CENTERED, 0), (251, ffp.FFP_I8_CENTERED, 4),
+                                            (251, ffp.FFP_I8_CENTERED, 5), (65521, ffp.FFP_I8_LIMB2, 0)])
+def test_full_size_16384_int8(p, a_dtype, ring):
     import torch
     n = 16384
     A = inputs.uniform(2, n, n, p)
@@ -245,6 +268,10 @@ def test_full_size_16384_int8(p, a_dtype):
     else:
         Ad = torch.from_numpy(limbs(A, p)).cuda()
     Cd = torch.zeros((n, n), dtype=torch.int32, device="cuda")
-    ffp.syrk(Ad, p, C=Cd, depth=0, a_dtype=a_dtype)
-    torch.cuda.synchronize()
+    set_knob("i8_ring", ring)
+    try:
+        ffp.syrk(Ad, p, C=Cd, depth=0, a_dtype=a_dtype)
+        torch.cuda.synchronize()
+    finally:
+        set_knob("i8_ring", 0)
     _sampled(A, p, from_dev_u32(Cd), nsamp=2000)

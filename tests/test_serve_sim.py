@@ -144,3 +144,25 @@ def test_request_validation():
         assert e.value.status == ffp.FFP_ENOMEM
     finally:
         srv.close()
+
+
+def test_completion_queue_returns_each_ticket_once():
+    reqs = inputs.request_stream(seed=5, nreq=200, rate=40000.0, nmin=32, nmax=256)
+    srv = ffp.Server(1 << 32, max_inflight=64, nstreams=3, simulated=True, ns_per_op=0.02,
+                     launch_us=10.0)
+    try:
+        seen = []
+        tickets = submit_stream(srv, reqs)
+        t_end = time.time() + 30
+        while len(seen) < len(tickets) and time.time() < t_end:
+            got = srv.poll(64, 0.05)
+            for t in got:
+                assert srv.status(t).state == ffp.FFP_STATE_DONE
+                srv.release(t)
+            seen.extend(got)
+        assert sorted(seen) == sorted(tickets)
+        assert srv.poll(8, 0.0) == []
+        st = srv.stats()
+        assert st.completed == len(reqs)
+    finally:
+        srv.close()
