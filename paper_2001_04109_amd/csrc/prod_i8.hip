@@ -130,47 +130,65 @@ __device__ inline void lstore(int8_t* __restrict__ lds, const Prefetch<ROWS, BK>
 
 }  // namespace
 
-// Epilogue of a CLS_I8 wave tile: through LDS, one 32-row slab of the wave
-// tile at a time, so that the reduction runs in a short loop with coalesced
-// row-major stores.  32x32 i32 MFMA result layout: lane l, element e holds
-// row 8*(e/4) + 4*(l/32) + e%4, column l%32.  Every wave of the workgroup
-// calls it (it contains workgroup barriers); `live` waves store.
-template <int WTM, int WTN, int FM, int FN>
-__device__ __forceinline__ void store_tile_i8(const v16i (&acc)[FM][FN], int32_t* smem32,
-                                              const ProdTask& t, int row0, int col0, bool live)
-{
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lrow = lane & 31, lk = lane >> 5;
-    const double pd = (double)t.p, alpha = (double)t.alpha, beta = (double)t.beta;
-    const bool plain = t.alpha == 1u && t.beta == 0u;
-    int32_t* ep = smem32 + wave * (32 * WTN);
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int e = 0; e < 16; ++e)
-                ep[(8 * (e >> 2) + 4 * lk + (e & 3)) * WTN + j * 32 + lrow] = acc[i][j][e];
-        __syncthreads();
-        if (live) {
-            for (int idx = lane; idx < 32 * WTN; idx += 64) {
-                const int rr = idx / WTN, cc = idx - rr * WTN;
-                const int row = row0 + i * 32 + rr;
-                const int col = col0 + cc;
-                if (row >= t.m || col >= t.n || (t.syrk && col > row)) continue;
-                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
-                const double r = mod_f64((double)ep[idx], pd, t.pinv);
-                if (plain) {
-                    *dst = (uint32_t)r;
-                } else {
-                    double x = alpha * r;
-                    if (t.beta != 0u) x += beta * (double)(*dst);
-                    *dst = (uint32_t)mod_f64(x, pd, t.pinv);
-                }
-            }
-        }
-        __syncthreads();
+// Exact reduction of an int32 accumulator mod a prime p <= 251 with integer
+// arithmetic (Barrett): u = x + B with B the smallest multiple of p that is
+// >= 2^31 makes u non-negative (|x| <= 2^31 - 1 - p by the block length),
+// q = floor(u m / 2^32) with m = floor(2^32 / p) is floor(u / p) or one
+// less, so u - q p lies in [0, 2p).
+struct SmallMod {
+    uint32_t p, m, bias;
+    __device__ explicit SmallMod(uint32_t p_) : p(p_), m(0xFFFFFFFFu / p_),
+        bias(((0x80000000u + p_ - 1u) / p_) * p_) {}
+    __device__ __forceinline__ uint32_t red_u(uint32_t u) const
+    {
+        const uint32_t q = __umulhi(u, m);
+        uint32_t r = u - q * p;
+        return r >= p ? r - p : r;
     }
+    __device__ __forceinline__ uint32_t red_i(int32_t x) const { return red_u((uint32_t)x + bias); }
+};
+
+// Register epilogue of a CLS_I8 wave tile: every accumulator is reduced
+// where it lies.  32x32 i32 MFMA result layout: lane l, element e holds row
+// 8*(e/4) + 4*(l/32) + e%4, column l%32, so for one element index the 64
+// lanes store two 128-byte row segments.  Tiles that lie wholly inside C
+// and below the diagonal skip the per-element bounds tests.
+template <int WTM, int WTN, int FM, int FN>
+__device__ __forceinline__ void store_tile_i8_reg(const v16i (&acc)[FM][FN], const ProdTask& t,
+                                                  int row0, int col0, bool live)
+{
+    if (!live) return;
+    const int lane = threadIdx.x & 63, lrow = lane & 31, lk = lane >> 5;
+    const SmallMod md(t.p);
+    const bool plain = t.alpha == 1u && t.beta == 0u;
+    const bool inside = row0 + WTM <= t.m && col0 + WTN <= t.n && (!t.syrk || col0 + WTN - 1 <= row0);
+    uint32_t* __restrict__ base = t.C + (int64_t)(row0 + 4 * lk) * t.ldc + col0 + lrow;
+    // one output row of the lane at a time: one address, FN stores with
+    // immediate offsets (the barrier keeps the compiler from hoisting every
+    // row's address at once)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int dr = i * 32 + 8 * (e >> 2) + (e & 3);        // row offset (before 4 lk)
+            uint32_t* __restrict__ rp = base + (int64_t)dr * t.ldc;
+            const int row = row0 + dr + 4 * lk;
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                if (!inside) {
+                    const int col = col0 + j * 32 + lrow;
+                    if (row >= t.m || col >= t.n || (t.syrk && col > row)) continue;
+                }
+                uint32_t r = md.red_i(acc[i][j][e]);
+                if (!plain) {
+                    uint32_t v = t.alpha * r;                        // < p^2
+                    if (t.beta != 0u) v += t.beta * rp[j * 32];       // < 2 p^2
+                    r = md.red_u(v);
+                }
+                rp[j * 32] = r;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
 }
 
 // PLANES = 1: CLS_I8;  PLANES = 2: CLS_LIMB2.  BK: k bytes per stage.
@@ -315,9 +333,7 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
     // row 8*(e/4) + 4*(l/32) + e%4, column l%32.
     const double alpha = (double)t.alpha, beta = (double)t.beta;
     if constexpr (PLANES == 1) {
-        static_assert(4 * 32 * WTN * 4 <= SA + SB, "epilogue slab must fit in LDS");
-        store_tile_i8<WTM, WTN, FM, FN>(acc[0], reinterpret_cast<int32_t*>(smem), t,
-                                        tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+        store_tile_i8_reg<WTM, WTN, FM, FN>(acc[0], t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
     } else {
         if (!wave_live) return;
         const double r16 = (double)((65536u) % t.p), r8 = (double)(256u % t.p);
@@ -352,13 +368,13 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
 // ring of NS stages, so loads run NS - 2 stages ahead without staging
 // registers or LDS write instructions.  A stage holds the BM + BN rows of
 // 64 bytes of the A and B panels; the four 16-byte chunks of row r are
-// stored in the order c ^ s(r) with s(r) = ((r >> 1) ^ (r >> 3)) & 3, which
-// keeps the fragment reads (8 or 16 consecutive rows, one chunk) free of
-// bank conflicts.  The compiler does not order these loads against LDS
+// stored in the order c ^ s(r) with s(r) = (r >> 2) & 3, which keeps the
+// fragment reads (consecutive rows, one chunk) free of LDS bank conflicts
+// (measured: the plain row-major order costs four times as much).  The compiler does not order these loads against LDS
 // reads, so completion is waited for explicitly (vmcnt) before the
 // workgroup barrier that publishes a stage.
 
-__device__ __forceinline__ int swz64(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ __forceinline__ int swz64(int r) { return (r >> 2) & 3; }
 
 // Workgroup barrier without the compiler's fence (which would wait for every
 // direct-to-LDS load in flight); LDS reads of this wave are complete first.
@@ -415,7 +431,6 @@ __device__ __forceinline__ void i8_ring_tile(const ProdArgs& args, int b)
     constexpr int WTM = BM / 2, WTN = BN / 2;
     constexpr int FM = WTM / 32, FN = WTN / 32;
     constexpr int LOADS = (BM + BN) / 16 / 4;              // per wave and stage
-    static_assert(4 * 32 * WTN * 4 <= NS * STAGE, "epilogue slab must fit in LDS");
     __shared__ __attribute__((aligned(1024))) int8_t smem[NS * STAGE];
 
     ProdTask t;
@@ -514,8 +529,7 @@ __device__ __forceinline__ void i8_ring_tile(const ProdArgs& args, int b)
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     ring_barrier();
-    store_tile_i8<WTM, WTN, FM, FN>(acc, reinterpret_cast<int32_t*>(smem), t, tile_r + wr * WTM,
-                                    tile_c + wc * WTN, wave_live);
+    store_tile_i8_reg<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
 }
 
 template <int BM, int BN, int NS>
