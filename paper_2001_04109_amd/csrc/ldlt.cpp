@@ -64,19 +64,25 @@ struct Ctx {
     FieldPlan fpl;
     Fp f;
     uint32_t s_lqnr, c_lqnr;
+    uint32_t* linv;     // inverses of the leaf blocks of L: column block c at linv + 64 c
     char* ws;
     int64_t* info;
     hipStream_t s;
 };
 
+// X <- X L^-T for the unit lower triangular m x m factor L whose first
+// column is column col0 of the whole factorisation.  The blocks split as
+// the factorisation did, so every leaf is a leaf block of ldlt_rec whose
+// inverse is in c.linv.
 int trsm_rec(Ctx& c, int64_t nrows, int64_t m, uint32_t* X, int64_t ldx, const uint32_t* L,
-             int64_t ldl)
+             int64_t ldl, int64_t col0)
 {
     if (m <= kLdltLeaf)
-        return launch_trsm_leaf(c.f, nrows, (int)m, X, ldx, L, ldl, c.s) == hipSuccess ? FFP_OK
-                                                                                     : FFP_EDEVICE;
+        return launch_trsm_leaf(c.f, nrows, (int)m, X, ldx, c.linv + col0 * kLdltLeaf, c.s) == hipSuccess
+                   ? FFP_OK
+                   : FFP_EDEVICE;
     const int64_t m1 = rup((m + 1) / 2, kLdltLeaf);
-    int st = trsm_rec(c, nrows, m1, X, ldx, L, ldl);
+    int st = trsm_rec(c, nrows, m1, X, ldx, L, ldl, col0);
     if (st != FFP_OK) return st;
     // X[:, m1:] <- X[:, m1:] - X[:, :m1] L[m1:, :m1]^T
     ProdTask t{};
@@ -92,15 +98,17 @@ int trsm_rec(Ctx& c, int64_t nrows, int64_t m, uint32_t* X, int64_t ldx, const u
     t.alpha = c.f.p - 1;
     t.beta = 1;
     if (launch_products(CLS_F64, &t, 1, nullptr, c.s) != hipSuccess) return FFP_EDEVICE;
-    return trsm_rec(c, nrows, m - m1, X + m1, ldx, L + m1 * ldl + m1, ldl);
+    return trsm_rec(c, nrows, m - m1, X + m1, ldx, L + m1 * ldl + m1, ldl, col0 + m1);
 }
 
 int ldlt_rec(Ctx& c, int64_t n, uint32_t* S, int64_t lds, int64_t offset)
 {
     if (n <= 0) return FFP_OK;
     if (n <= kLdltLeaf)
-        return launch_ldlt_leaf(c.f, (int)n, S, lds, c.info, offset, c.s) == hipSuccess ? FFP_OK
-                                                                                      : FFP_EDEVICE;
+        return launch_ldlt_leaf(c.f, (int)n, S, lds, c.info, offset, c.linv + offset * kLdltLeaf, c.s) ==
+                       hipSuccess
+                   ? FFP_OK
+                   : FFP_EDEVICE;
     const int64_t n1 = split_point(n), n2 = n - n1;
     uint32_t* S11 = S;
     uint32_t* S21 = S + n1 * lds;
@@ -108,7 +116,7 @@ int ldlt_rec(Ctx& c, int64_t n, uint32_t* S, int64_t lds, int64_t offset)
     int st = ldlt_rec(c, n1, S11, lds, offset);
     if (st != FFP_OK) return st;
     // W = S21 L11^-T, then L21 = W D1^-1
-    st = trsm_rec(c, n2, n1, S21, lds, S11, lds);
+    st = trsm_rec(c, n2, n1, S21, lds, S11, lds, offset);
     if (st != FFP_OK) return st;
     const NodeLayout L = layout(n1, n2);
     Alg5Scratch sc{(int32_t*)(c.ws + L.off_flag), (uint32_t*)(c.ws + L.off_root),
@@ -142,9 +150,11 @@ size_t ws_need(int64_t n, uint32_t p, int64_t lds)
     return std::max(here, std::max(ws_need(n1, p, lds), ws_need(n2, p, lds)));
 }
 
+size_t linv_bytes(int64_t n) { return (size_t)rup(n * kLdltLeaf * 4, 256); }
+
 }  // namespace
 
-size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds) { return ws_need(n, p, lds); }
+size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds) { return linv_bytes(n) + ws_need(n, p, lds); }
 
 int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hipStream_t s, void* ws)
 {
@@ -158,15 +168,15 @@ int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hip
     c.info = info;
     c.s = s;
     if (launch_zero_i64(info, s) != hipSuccess) return FFP_EDEVICE;
-    if (ws) {
-        c.ws = (char*)ws;
-    } else {
+    if (!ws) {
         const size_t need = ldlt_workspace_bytes(n, p, lds);
         Workspace* w = nullptr;
         int st = acquire_workspace(s, need, 0, &w);
         if (st != FFP_OK) return st;
-        c.ws = (char*)w->ptr;
+        ws = w->ptr;
     }
+    c.linv = (uint32_t*)ws;
+    c.ws = (char*)ws + linv_bytes(n);
     return ldlt_rec(c, n, S, lds, 0);
 }
 

@@ -30,10 +30,14 @@ struct Alg5Scratch {
     ColOp* desc;        // n1 + 1 column operations
 };
 
+// Leaf factorisation; also writes the inverse of the leaf's unit lower
+// factor to linv (nb rows of stride kLdltLeaf), used by launch_trsm_leaf.
 hipError_t launch_ldlt_leaf(const Fp& f, int nb, uint32_t* S, int64_t lds, int64_t* info,
-                            int64_t offset, hipStream_t s);
+                            int64_t offset, uint32_t* linv, hipStream_t s);
+// X <- X L^-T for an nrows x nb block X, given linv = L^-1 of the unit lower
+// nb x nb factor as written by launch_ldlt_leaf.
 hipError_t launch_trsm_leaf(const Fp& f, int64_t nrows, int nb, uint32_t* X, int64_t ldx,
-                            const uint32_t* L, int64_t ldl, hipStream_t s);
+                            const uint32_t* linv, hipStream_t s);
 hipError_t launch_alg5(const Fp& f, int n1, const uint32_t* S11, int64_t lds, uint32_t s_lqnr,
                        uint32_t c_lqnr, uint32_t z, Alg5Scratch sc, hipStream_t s);
 hipError_t launch_scale_cols(const Fp& f, int64_t rows, int n1, uint32_t* W, int64_t ldw,

@@ -11,88 +11,155 @@ namespace {
 
 constexpr int NB = kLdltLeaf;   // leaf order and triangular-solve block
 
-// In-place LDL^T of an nb x nb block held in LDS (nb <= NB), right-looking.
-__global__ __launch_bounds__(256) void ldlt_leaf_kernel(Fp f, int nb, uint32_t* S, int64_t lds,
-                                                       int64_t* info, int64_t offset)
+// In-place LDL^T of an nb x nb block (nb <= NB) in LDS, followed (when
+// every pivot is nonzero) by the inverse of its unit lower triangular
+// factor, written to linv (row i at linv + 64 i, columns <= i), which the
+// triangular solves against this block use.  kb: number of products of two
+// residues whose sum stays below 2^53.
+//
+// The elimination is division-free, so no modular inverse sits on the
+// sequential path: step k replaces M[i][j] by a_k M[i][j] - M[i][k] M[k][j]
+// (i, j > k) with a_k = M[k][k].  By induction M = g_k S_k on the trailing
+// block, where S_k is the true Schur complement and g_k = a_0 ... a_{k-1};
+// hence D[k] = a_k / g_k and L[i][k] = M[i][k] / a_k (M taken at step k),
+// and a_k = 0 exactly when the true pivot is 0.  The 2 nb inverses are then
+// formed in parallel.
+__global__ __launch_bounds__(256) void ldlt_leaf_kernel(Fp f, int kb, int nb, uint32_t* S, int64_t lds,
+                                                       int64_t* info, int64_t offset, uint32_t* linv)
 {
-    __shared__ uint32_t s[NB][NB + 1];
-    __shared__ uint32_t w[NB], l[NB];
-    __shared__ int stop;
+    __shared__ uint32_t sm[NB][NB + 1];
+    __shared__ uint32_t li[NB][NB + 1];
+    __shared__ uint32_t ainv[NB];
     const uint32_t p = f.p;
     const int tid = threadIdx.x;
     for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
-        if (j <= i) s[i][j] = S[(int64_t)i * lds + j];
+        if (j <= i) sm[i][j] = S[(int64_t)i * lds + j];
     }
-    if (tid == 0) stop = 0;
     __syncthreads();
-    int jend = nb;
-    for (int j = 0; j < nb; ++j) {
-        const uint32_t d = s[j][j];
-        if (d == 0) {
-            if (tid == 0) {
-                stop = 1;
-                if (*info == 0) *info = offset + j + 1;
-            }
-            jend = j;
+    bool stop = false;
+    for (int k = 0; k < nb; ++k) {
+        const uint32_t a = sm[k][k];
+        if (a == 0u) {
+            if (tid == 0 && *info == 0) *info = offset + k + 1;
+            stop = true;                            // every thread read the same a
             break;
         }
-        const uint32_t dinv = inv_m(d, p, f.pinv);
-        for (int i = j + 1 + tid; i < nb; i += blockDim.x) {
-            w[i] = s[i][j];
-            l[i] = mul_m(s[i][j], dinv, p, f.pinv);
+        // trailing update of the lower triangle: rows i > k, columns k < j <= i
+        const int r = nb - k - 1;
+        const int cnt = r * (r + 1) / 2;
+        for (int e = tid; e < cnt; e += blockDim.x) {
+            // e -> (ii, jj) with 0 <= jj <= ii < r, row-major over the triangle
+            int ii = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+            while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+            while (ii * (ii + 1) / 2 > e) --ii;
+            const int jj = e - ii * (ii + 1) / 2;
+            const int i = k + 1 + ii, j = k + 1 + jj;
+            const uint32_t v = mul_m(a, sm[i][j], p, f.pinv);
+            sm[i][j] = sub_m(v, mul_m(sm[i][k], sm[j][k], p, f.pinv), p);
         }
-        __syncthreads();
-        // trailing update s[i][c] -= l_i * d * l_c = l_i * w_c  for j < c <= i
-        const int r = nb - j - 1;
-        for (int e = tid; e < r * r; e += blockDim.x) {
-            const int i = j + 1 + e / r, c = j + 1 + e % r;
-            if (c <= i) s[i][c] = sub_m(s[i][c], mul_m(l[i], w[c], p, f.pinv), p);
-        }
-        for (int i = j + 1 + tid; i < nb; i += blockDim.x) s[i][j] = l[i];
         __syncthreads();
     }
-    (void)jend;
-    __syncthreads();
     if (stop) return;   // contents unspecified after a zero pivot
+    // D[k] = a_k / g_k, L[i][k] = M[i][k] / a_k
+    uint32_t dk = 0u;
+    if (tid < nb) {
+        const int k = tid;
+        uint32_t g = 1u;
+        for (int t = 0; t < k; ++t) g = mul_m(g, sm[t][t], p, f.pinv);
+        const uint32_t a = sm[k][k];
+        ainv[k] = inv_m(a, p, f.pinv);
+        dk = mul_m(a, inv_m(g, p, f.pinv), p, f.pinv);
+    }
+    __syncthreads();                 // every a_k read before D overwrites the diagonal
+    if (tid < nb) sm[tid][tid] = dk;
+    __syncthreads();
     for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
-        if (j <= i) S[(int64_t)i * lds + j] = s[i][j];
+        if (j < i) sm[i][j] = mul_m(sm[i][j], ainv[j], p, f.pinv);
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        if (j <= i) S[(int64_t)i * lds + j] = sm[i][j];
+    }
+    // inverse of the unit lower factor, one column per thread:
+    // X[i][j] = -sum_{j <= t < i} L[i][t] X[t][j], X[j][j] = 1
+    if (tid < nb) {
+        const int j = tid;
+        li[j][j] = 1u;
+        for (int i = j + 1; i < nb; ++i) {
+            double acc = 0.0;
+            int cnt = 0;
+            for (int t = j; t < i; ++t) {
+                acc = fma((double)sm[i][t], (double)li[t][j], acc);
+                if (++cnt == kb) {
+                    acc = (double)mod53(acc, p, f.pinv);
+                    cnt = 1;
+                }
+            }
+            const uint32_t v = mod53(acc, p, f.pinv);
+            li[i][j] = v == 0u ? 0u : p - v;
+        }
+        for (int i = j; i < nb; ++i) linv[i * NB + j] = li[i][j];
     }
 }
 
-// X <- X * L^-T for an nrows x nb block X and an nb x nb unit lower
-// triangular L (strict lower part stored; diagonal ignored), nb <= NB.
-// 128 rows per block; each thread solves one row in LDS.
-constexpr int TR = 128;
-__global__ __launch_bounds__(TR) void trsm_leaf_kernel(Fp f, int64_t nrows, int nb, uint32_t* X,
-                                                      int64_t ldx, const uint32_t* L, int64_t ldl)
+// X <- X L^-T for an nrows x nb block X, given Linv = L^-1 of the unit lower
+// triangular nb x nb factor (row i at linv + 64 i, columns <= i):
+// X'[r][c] = sum_{t <= c} X[r][t] Linv[c][t].  64 rows per workgroup; each
+// thread forms a 4 x 4 block of entries in FP64 with delayed reduction
+// (Linv is zero above the diagonal in LDS, so every sum runs over all t).
+constexpr int TR = 64;
+__global__ __launch_bounds__(256) void trsm_inv_kernel(Fp f, int kb, int64_t nrows, int nb, uint32_t* X,
+                                                      int64_t ldx, const uint32_t* linv)
 {
-    __shared__ uint32_t sl[NB][NB + 1];
-    __shared__ uint32_t sx[TR][NB + 1];
+    __shared__ double sl[NB][NB + 1];
+    __shared__ double sx[TR][NB + 1];
     const uint32_t p = f.p;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * TR;
-    for (int e = tid; e < nb * nb; e += TR) {
-        const int i = e / nb, j = e % nb;
-        sl[i][j] = j < i ? L[(int64_t)i * ldl + j] : 0u;
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int i = e / NB, j = e % NB;
+        sl[i][j] = (i < nb && j <= i) ? (double)linv[i * NB + j] : 0.0;
     }
-    for (int e = tid; e < TR * nb; e += TR) {
-        const int i = e / nb, j = e % nb;
-        if (r0 + i < nrows) sx[i][j] = X[(r0 + i) * ldx + j];
+    for (int e = tid; e < TR * NB; e += 256) {
+        const int i = e / NB, j = e % NB;
+        sx[i][j] = (r0 + i < nrows && j < nb) ? (double)X[(r0 + i) * ldx + j] : 0.0;
     }
     __syncthreads();
-    if (r0 + tid < nrows) {
-        for (int j = 1; j < nb; ++j) {
-            uint32_t acc = sx[tid][j];
-            for (int c = 0; c < j; ++c) acc = sub_m(acc, mul_m(sx[tid][c], sl[j][c], p, f.pinv), p);
-            sx[tid][j] = acc;
+    const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    int cnt = 0;
+    for (int t = 0; t < NB; ++t) {
+        double xv[4], lv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) xv[a] = sx[tr + a][t];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) lv[b] = sl[tc + b][t];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], lv[b], acc[a][b]);
+        if (++cnt == kb) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = (double)mod53(acc[a][b], p, f.pinv);
+            cnt = 1;
         }
     }
-    __syncthreads();
-    for (int e = tid; e < TR * nb; e += TR) {
-        const int i = e / nb, j = e % nb;
-        if (r0 + i < nrows) X[(r0 + i) * ldx + j] = sx[i][j];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t r = r0 + tr + a;
+        if (r >= nrows) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (tc + b < nb) X[r * ldx + tc + b] = mod53(acc[a][b], p, f.pinv);
     }
 }
 
@@ -217,19 +284,28 @@ hipError_t launch_zero_i64(int64_t* p, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ldlt_leaf(const Fp& f, int nb, uint32_t* S, int64_t lds, int64_t* info,
-                            int64_t offset, hipStream_t s)
+// Terms of a dot product of residues whose sum stays below 2^53.
+static int dot_block(uint32_t p)
 {
-    hipLaunchKernelGGL(ldlt_leaf_kernel, dim3(1), dim3(256), 0, s, f, nb, S, lds, info, offset);
+    const double pm = (double)(p - 1);
+    const double kb = floor(9007199254740992.0 / (pm * pm + 1.0)) - 1.0;
+    return kb > 64.0 ? 64 : (int)kb;
+}
+
+hipError_t launch_ldlt_leaf(const Fp& f, int nb, uint32_t* S, int64_t lds, int64_t* info,
+                            int64_t offset, uint32_t* linv, hipStream_t s)
+{
+    hipLaunchKernelGGL(ldlt_leaf_kernel, dim3(1), dim3(256), 0, s, f, dot_block(f.p), nb, S, lds, info,
+                       offset, linv);
     return hipGetLastError();
 }
 
 hipError_t launch_trsm_leaf(const Fp& f, int64_t nrows, int nb, uint32_t* X, int64_t ldx,
-                            const uint32_t* L, int64_t ldl, hipStream_t s)
+                            const uint32_t* linv, hipStream_t s)
 {
     if (nrows <= 0 || nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(trsm_leaf_kernel, dim3((unsigned)((nrows + TR - 1) / TR)), dim3(TR), 0, s, f,
-                       nrows, nb, X, ldx, L, ldl);
+    hipLaunchKernelGGL(trsm_inv_kernel, dim3((unsigned)((nrows + TR - 1) / TR)), dim3(256), 0, s, f,
+                       dot_block(f.p), nrows, nb, X, ldx, linv);
     return hipGetLastError();
 }
 

@@ -40,6 +40,42 @@ __device__ inline uint32_t pow_m(uint32_t a, uint32_t e, uint32_t p, double pinv
     return r;
 }
 
+// Reduction of a non-negative integer x < 2^53 held in a double.
+__device__ inline uint32_t mod53(double x, uint32_t p, double pinv)
+{
+    const double q = floor(x * pinv);
+    double r = fma(-q, (double)p, x);
+    if (r < 0.0) r += (double)p;
+    if (r >= (double)p) r -= (double)p;
+    return (uint32_t)r;
+}
+
+// Inverse of a in [1, p) for an odd prime p by the binary extended Euclidean
+// algorithm (invariants x1 a = u and x2 a = v mod p); 0 maps to 0.
+__device__ inline uint32_t inv_binary(uint32_t a, uint32_t p)
+{
+    if (a == 0u) return 0u;
+    uint32_t u = a, v = p, x1 = 1u, x2 = 0u;
+    while (u != 1u && v != 1u) {
+        while ((u & 1u) == 0u) {
+            u >>= 1;
+            x1 = (x1 & 1u) ? (uint32_t)(((uint64_t)x1 + p) >> 1) : x1 >> 1;
+        }
+        while ((v & 1u) == 0u) {
+            v >>= 1;
+            x2 = (x2 & 1u) ? (uint32_t)(((uint64_t)x2 + p) >> 1) : x2 >> 1;
+        }
+        if (u >= v) {
+            u -= v;
+            x1 = x1 >= x2 ? x1 - x2 : x1 + (p - x2);
+        } else {
+            v -= u;
+            x2 = x2 >= x1 ? x2 - x1 : x2 + (p - x1);
+        }
+    }
+    return u == 1u ? x1 : x2;
+}
+
 // Inverse by Fermat's little theorem (0 maps to 0).
 __device__ inline uint32_t inv_m(uint32_t a, uint32_t p, double pinv)
 {
