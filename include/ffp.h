@@ -75,6 +75,13 @@ extern "C" {
 /* Run the base products on FP64 matrix cores even where an int8 path
  * exists for p (only for FFP_U32 operands). */
 #define FFP_BASE_F64      0x100u
+/* Keep the placements of Table 3 (beta = 0): the strict upper triangle of C
+ * is the only temporary when k <= n, and sibling sub-products reuse one
+ * workspace region.  Without this flag the products P2, P5, P1 and P3 of
+ * every level get memory of their own (S1, S2 and P2 in workspace blocks),
+ * so that they run together; that needs more workspace (see
+ * ffp_workspace_bytes).  Results are identical. */
+#define FFP_LOW_MEMORY    0x200u
 
 /* lower(C) <- (alpha * A * A^T + beta * lower(C)) mod p.
  * Algorithm 2 (Ensure: the lower triangle of A*A^T) in the accumulate form

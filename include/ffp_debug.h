@@ -43,6 +43,14 @@ int ffp_host_nrsyf(uint32_t p, uint32_t alpha, uint32_t beta, uint32_t Y[4]);
 int ffp_plan_describe(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda, int64_t ldc,
                       uint32_t alpha, uint32_t beta, unsigned flags, char* buf, size_t len);
 
+/* Level of every operation of the same plan (as ffp_plan_describe lists
+ * them) under the library's level scheduler: an operation's level is one
+ * more than the highest level of the earlier operations it depends on.
+ * Writes min(count, cap) levels; returns the number of operations or a
+ * negative FFP_* status.  Host only. */
+int ffp_plan_levels(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda, int64_t ldc,
+                    uint32_t alpha, uint32_t beta, unsigned flags, int32_t* levels, size_t cap);
+
 /* Test hook: cap the delayed-reduction block of the product kernels at kblk
  * columns of k (rounded down to the kernel's k granularity; 0 restores the
  * largest exact block).  Process-wide; affects launches made after the
@@ -57,7 +65,12 @@ void ffp_debug_set_kblk(int64_t kblk);
  * into a ring of that many LDS stages; 0 = register-staged loads; other
  * values FFP_EINVAL),
  * "persistent" (1: grouped product launches run persistent workgroups that
- * stride over the tiles; 0: one workgroup per tile).
+ * stride over the tiles; 0: one workgroup per tile), "leveled" (1, the
+ * default: a call's block operations run level by level, independent
+ * products of a level as one grouped launch; 0: one by one in schedule
+ * order), "wide" (1, the default: Algorithm 2 keeps S1, S2 and P2 in
+ * workspace blocks of their own, so that P2, P5, P1 and P3 are independent
+ * and share levels; more workspace; 0: the placements of Table 3).
  * FFP_EINVAL for an unknown key. */
 int ffp_debug_set(const char* key, int64_t value);
 

@@ -156,6 +156,28 @@ int ffp_plan_describe(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda
     return (int)s.size();
 }
 
+int ffp_plan_levels(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda, int64_t ldc,
+                    uint32_t alpha, uint32_t beta, unsigned flags, int32_t* levels, size_t cap)
+{
+    PlanRequest rq;
+    int st = make_syrk_request(n, k, p, (const void*)16, lda, a_dtype, alpha % (p ? p : 1), beta,
+                               (const uint32_t*)16, ldc, flags, &rq);
+    if (st != FFP_OK) return st;
+    Plan pl;
+    st = build_syrk_plan(rq, &pl);
+    if (st != FFP_OK) return st;
+    // distinct, far-apart stand-in addresses for the three buffers
+    const void* a = (const void*)((uintptr_t)1 << 44);
+    void* c = (void*)((uintptr_t)2 << 44);
+    void* ws = (void*)((uintptr_t)3 << 44);
+    std::vector<SchedItem> items;
+    for (const Op& o : pl.ops) items.push_back(SchedItem{&pl, &o, a, c, ws, 0});
+    const std::vector<int> lv = schedule_levels(items);
+    if (levels)
+        for (size_t i = 0; i < lv.size() && i < cap; ++i) levels[i] = lv[i];
+    return (int)lv.size();
+}
+
 }  // extern "C"
 
 extern "C" {
@@ -169,6 +191,8 @@ int ffp_debug_set(const char* key, int64_t value)
     if (strcmp(key, "f64_tile") == 0) { ffp::g_f64_tile_override = (int)value; return FFP_OK; }
     if (strcmp(key, "i8_tile") == 0) { ffp::g_i8_tile_override = (int)value; return FFP_OK; }
     if (strcmp(key, "i8_bk") == 0) { ffp::g_i8_bk_override = (int)value; return FFP_OK; }
+    if (strcmp(key, "wide") == 0) { ffp::g_wide_schedule = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "leveled") == 0) { ffp::g_leveled = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "i8_ring") == 0) {
         if (value != 0 && value != 4 && value != 5) return FFP_EINVAL;
         ffp::g_i8_ring = (int)value;

@@ -8,6 +8,8 @@
 
 namespace ffp {
 
+int g_wide_schedule = 1;
+
 namespace {
 
 int64_t elem_size(int cls) { return cls == CLS_F64 ? 4 : 1; }
@@ -25,6 +27,7 @@ struct Builder {
     int cls;
     Fp fp;
     bool yb_nonzero;
+    bool wide = false;
     int64_t ws_top = 0, ws_max = 0;
     std::vector<Op>* ops;
 
@@ -120,7 +123,7 @@ struct Builder {
                     C22 = sub(C, m, m, 4);
         const int64_t save = ws_top;
         PView S1, S2, S4;
-        if (h <= m) {
+        if (h <= m && !wide) {
             S1 = in_block(C21, h);    // S1, then S3 in place
             S2 = in_block(C12, h);
             S4 = in_block(C11, h);
@@ -145,12 +148,14 @@ struct Builder {
         c.m = m;
         c.v[0] = C11; c.v[1] = C12; c.v[2] = C22; c.v[3] = C21;
         emit(c);                                                            // U1, U2, U4 -> C21, U5 -> C22
-        syrk3(d - 1, level + 1, m, h, A12, alpha, C12);                    // P2 = A12 A12^T
+        // P2 = A12 A12^T: in place of P5 (C12), or in a block of its own
+        const PView P2 = wide ? ws_u32(m, round_up(m, 4)) : C12;
+        syrk3(d - 1, level + 1, m, h, A12, alpha, P2);
         Op u = op(OP_ADDLOW, level);
         u.m = m;
-        u.v[0] = C11; u.v[1] = C12; u.v[2] = C11;
+        u.v[0] = C11; u.v[1] = P2; u.v[2] = C11;
         emit(u);                                                            // U3 = P1 + P2
-        ws_top = save;
+        if (!wide) ws_top = save;
     }
 
     // Table 4: lower(C) <- alpha A A^T + beta lower(C), with C12 and one
@@ -254,6 +259,7 @@ int make_syrk_request(int64_t n, int64_t k, uint32_t p, const void* A, int64_t l
     rq->depth = dfield ? (int)dfield - 1 : -1;
     rq->fill_upper = (flags & FFP_FILL_UPPER) != 0;
     rq->force_f64 = (flags & FFP_BASE_F64) != 0;
+    rq->wide = g_wide_schedule != 0 && (flags & FFP_LOW_MEMORY) == 0;
     rq->a_aligned16 = aligned16(A);
     rq->c_aligned16 = aligned16(C);
     return FFP_OK;
@@ -311,6 +317,7 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
     B.cls = pl.cls;
     B.fp = Fp{rq.p, (rq.p - 1) / 2, pl.field.pinv, pl.field.ya, pl.field.yb};
     B.yb_nonzero = pl.field.yb != 0;
+    B.wide = rq.wide;
     B.ops = &pl.ops;
 
     // Operand: pack when the class, the shape or the alignment differ.

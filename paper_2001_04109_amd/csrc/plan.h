@@ -61,6 +61,11 @@ struct PlanRequest {
     bool force_f64 = false;
     bool a_aligned16 = true;     // caller's A pointer is 16-byte aligned
     bool c_aligned16 = true;
+    // Table 3 with independent siblings: S1, S2 always in the workspace,
+    // P2 into a workspace block, no workspace reuse between siblings, so
+    // that P2 and the recursive calls P5, P1 with P3 have no memory in common
+    // and the level scheduler runs them together (more workspace).
+    bool wide = false;
 };
 
 struct Plan {
@@ -79,6 +84,9 @@ int make_syrk_request(int64_t n, int64_t k, uint32_t p, const void* A, int64_t l
 
 // Returns FFP_* status (0 on success).
 int build_syrk_plan(const PlanRequest& rq, Plan* out);
+// Process-wide default of PlanRequest::wide for fsyrk_modp (tuning knob;
+// 1 by default).
+extern int g_wide_schedule;
 int choose_class(uint32_t p, int a_cls, bool force_f64);
 int default_depth(int cls, int64_t n, int64_t k);
 std::string describe_plan(const Plan& pl);

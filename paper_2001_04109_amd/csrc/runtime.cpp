@@ -1,6 +1,7 @@
 // Workspace pool and plan executor of the product library.
 #include "runtime.h"
 
+#include <algorithm>
 #include <map>
 #include <vector>
 #include <mutex>
@@ -232,13 +233,270 @@ hipError_t launch_products(int cls, ProdTask* tasks, int ntasks, ProdTask* dev_t
     }
 }
 
+int g_leveled = 1;
+
 int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s)
 {
+    if (g_leveled) {
+        std::vector<SchedItem> items;
+        items.reserve(pl.ops.size());
+        for (const Op& o : pl.ops) items.push_back(SchedItem{&pl, &o, a, c, ws, 0});
+        return run_leveled(items, s);
+    }
     for (const Op& o : pl.ops) {
         int st = execute_op(pl, o, a, c, ws, s);
         if (st != FFP_OK) return st;
     }
     return FFP_OK;
+}
+
+namespace {
+
+// Bytes [base + r ld, base + r ld + cols) for r < rows.
+struct Region {
+    uintptr_t base;
+    int64_t ld, rows, cols;
+};
+
+bool overlap(const Region& x, const Region& y)
+{
+    if (x.rows <= 0 || x.cols <= 0 || y.rows <= 0 || y.cols <= 0) return false;
+    const uintptr_t xe = x.base + (uintptr_t)((x.rows - 1) * x.ld + x.cols);
+    const uintptr_t ye = y.base + (uintptr_t)((y.rows - 1) * y.ld + y.cols);
+    if (xe <= y.base || ye <= x.base) return false;
+    if (x.ld != y.ld || x.ld <= 0) return true;          // different pitch: spans overlap
+    const int64_t ld = x.ld;
+    const uintptr_t o = x.base < y.base ? x.base : y.base;
+    const int64_t xr = (int64_t)((x.base - o) / (uintptr_t)ld), xc = (int64_t)((x.base - o) % (uintptr_t)ld);
+    const int64_t yr = (int64_t)((y.base - o) / (uintptr_t)ld), yc = (int64_t)((y.base - o) % (uintptr_t)ld);
+    if (xc + x.cols > ld || yc + y.cols > ld) return true; // a row wraps past the pitch
+    return xr < yr + y.rows && yr < xr + x.rows && xc < yc + y.cols && yc < xc + x.cols;
+}
+
+struct OpRegions {
+    std::vector<Region> rd, wr;
+};
+
+void add_view(std::vector<Region>& out, const PView& v, int64_t rows, int64_t cols, int64_t es,
+              bool planes, const SchedItem& it)
+{
+    const uintptr_t b = (uintptr_t)at(v, it.a, it.c, it.ws);
+    const int64_t ld = (rows > 1 ? v.ld : cols) * es;
+    out.push_back(Region{b, ld, rows, cols * es});
+    if (planes) out.push_back(Region{b + (uintptr_t)(v.plane * es), ld, rows, cols * es});
+}
+
+int64_t class_es(int cls) { return cls == CLS_F64 ? 4 : 1; }
+
+OpRegions regions_of(const SchedItem& it)
+{
+    const Op& o = *it.op;
+    OpRegions r;
+    const int64_t es = class_es(o.cls);
+    const bool pl = o.cls == CLS_LIMB2;
+    switch (o.kind) {
+    case OP_S1S2:
+        for (int i = 0; i < 3; ++i) add_view(r.rd, o.v[i], o.m, o.k, es, pl, it);
+        add_view(r.wr, o.v[3], o.m, o.k, es, pl, it);
+        add_view(r.wr, o.v[4], o.m, o.k, es, pl, it);
+        break;
+    case OP_S34:
+        for (int i = 0; i < 3; ++i) add_view(r.rd, o.v[i], o.m, o.k, es, pl, it);
+        if (o.mode & 1) add_view(r.wr, o.v[3], o.m, o.k, es, pl, it);
+        if (o.mode & 2) add_view(r.wr, o.v[4], o.m, o.k, es, pl, it);
+        break;
+    case OP_GEMM:
+        add_view(r.rd, o.v[0], o.m, o.k, es, pl, it);
+        add_view(r.rd, o.v[1], o.n, o.k, es, pl, it);
+        add_view(r.wr, o.v[2], o.m, o.n, 4, false, it);
+        if (o.beta) add_view(r.rd, o.v[2], o.m, o.n, 4, false, it);
+        break;
+    case OP_SYRK:
+        add_view(r.rd, o.v[0], o.m, o.k, es, pl, it);
+        add_view(r.wr, o.v[1], o.m, o.m, 4, false, it);
+        if (o.beta) add_view(r.rd, o.v[1], o.m, o.m, 4, false, it);
+        break;
+    case OP_POSTADD:
+        for (int i = 0; i < (o.beta ? 5 : 4); ++i) {
+            add_view(r.rd, o.v[i], o.m, o.m, 4, false, it);
+            add_view(r.wr, o.v[i], o.m, o.m, 4, false, it);
+        }
+        if (o.beta) {
+            add_view(r.rd, o.v[5], 1, o.m, 4, false, it);
+            add_view(r.wr, o.v[5], 1, o.m, 4, false, it);
+        }
+        break;
+    case OP_ADDLOW:
+        add_view(r.rd, o.v[0], o.m, o.m, 4, false, it);
+        add_view(r.rd, o.v[1], o.m, o.m, 4, false, it);
+        add_view(r.wr, o.v[2], o.m, o.m, 4, false, it);
+        break;
+    case OP_SAVEC22:
+        add_view(r.rd, o.v[0], o.m, o.m, 4, false, it);
+        add_view(r.wr, o.v[1], o.m, o.m, 4, false, it);
+        add_view(r.wr, o.v[2], 1, o.m, 4, false, it);
+        break;
+    case OP_MIRROR:
+        add_view(r.rd, o.v[0], o.m, o.m, 4, false, it);
+        add_view(r.wr, o.v[0], o.m, o.m, 4, false, it);
+        break;
+    case OP_PACK:
+        add_view(r.rd, o.v[0], o.m_src, o.k_src, class_es(o.src_cls), o.src_cls == CLS_LIMB2, it);
+        add_view(r.wr, o.v[1], o.m, o.k, es, pl, it);
+        break;
+    case OP_COPY:
+        add_view(r.rd, o.v[0], o.m, o.n, 4, false, it);
+        add_view(r.wr, o.v[1], o.m, o.n, 4, false, it);
+        break;
+    }
+    return r;
+}
+
+bool any_overlap(const std::vector<Region>& x, const std::vector<Region>& y)
+{
+    for (const Region& a : x)
+        for (const Region& b : y)
+            if (overlap(a, b)) return true;
+    return false;
+}
+
+// j (later) depends on i (earlier)
+bool depends(const OpRegions& i, const OpRegions& j)
+{
+    return any_overlap(i.wr, j.rd) || any_overlap(i.wr, j.wr) || any_overlap(i.rd, j.wr);
+}
+
+bool longer_task(const ProdTask& a, const ProdTask& b)
+{
+    if (a.k != b.k) return a.k > b.k;
+    return (int64_t)a.m * a.n > (int64_t)b.m * b.n;
+}
+
+int64_t rup256(int64_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+std::vector<int> schedule_levels(const std::vector<SchedItem>& items)
+{
+    const size_t n = items.size();
+    std::vector<OpRegions> regs(n);
+    for (size_t i = 0; i < n; ++i) regs[i] = regions_of(items[i]);
+    std::vector<int> level(n, 0);
+    size_t start = 0;
+    for (size_t j = 0; j < n; ++j) {
+        if (j > 0 && items[j].job != items[j - 1].job) start = j;
+        int lv = 0;
+        for (size_t i = start; i < j; ++i)
+            if (level[i] + 1 > lv && depends(regs[i], regs[j])) lv = level[i] + 1;
+        level[j] = lv;
+    }
+    return level;
+}
+
+int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
+{
+    const size_t n = items.size();
+    if (n == 0) return FFP_OK;
+    const std::vector<int> level = schedule_levels(items);
+    int maxlev = 0;
+    for (int lv : level) maxlev = lv > maxlev ? lv : maxlev;
+    std::vector<std::vector<size_t>> by_level(maxlev + 1);
+    for (size_t j = 0; j < n; ++j) by_level[level[j]].push_back(j);
+
+    // staging for the task and descriptor tables of grouped launches
+    size_t meta = 0;
+    for (const auto& lv : by_level) {
+        size_t np[3] = {0, 0, 0}, nk[9] = {0};
+        for (size_t j : lv) {
+            const Op& o = *items[j].op;
+            if (o.kind == OP_SYRK || o.kind == OP_GEMM) ++np[o.cls];
+            else if (o.kind == OP_PACK) ++nk[o.src_cls * 3 + o.cls];
+        }
+        for (size_t q : np)
+            if (q > (size_t)kInlineTasks) meta += (size_t)rup256((int64_t)(q * sizeof(ProdTask)));
+        for (size_t q : nk) if (q > 1) meta += (size_t)rup256((int64_t)(q * sizeof(PackDesc)));
+    }
+    char* host_meta = nullptr;
+    char* dev_meta = nullptr;
+    if (meta > 0) {
+        int st = acquire_staging(s, meta, &host_meta, &dev_meta);
+        if (st != FFP_OK) return st;
+    }
+    size_t moff = 0;
+    int status = FFP_OK;
+    for (const auto& lv : by_level) {
+        std::vector<size_t> prods[3], packs[9];
+        for (size_t j : lv) {
+            const SchedItem& it = items[j];
+            const Op& o = *it.op;
+            if (o.kind == OP_SYRK || o.kind == OP_GEMM) {
+                prods[o.cls].push_back(j);
+            } else if (o.kind == OP_PACK) {
+                packs[o.src_cls * 3 + o.cls].push_back(j);
+            } else {
+                const int st = execute_op(*it.pl, o, it.a, it.c, it.ws, s);
+                if (st != FFP_OK) { status = st; break; }
+            }
+        }
+        if (status != FFP_OK) break;
+        for (int cls = 0; cls < 3 && status == FFP_OK; ++cls) {
+            const auto& g = prods[cls];
+            if (g.empty()) continue;
+            if (g.size() == 1) {
+                const SchedItem& it = items[g[0]];
+                status = execute_op(*it.pl, *it.op, it.a, it.c, it.ws, s);
+                continue;
+            }
+            // up to kInlineTasks tasks travel in the kernel arguments
+            ProdTask inl[kInlineTasks];
+            ProdTask* tasks = inl;
+            ProdTask* dtasks = nullptr;
+            if (g.size() > (size_t)kInlineTasks) {
+                tasks = (ProdTask*)(host_meta + moff);
+                dtasks = (ProdTask*)(dev_meta + moff);
+                moff += (size_t)rup256((int64_t)(g.size() * sizeof(ProdTask)));
+            }
+            int nt = 0;
+            double flops = 0.0;
+            for (size_t j : g) {
+                const SchedItem& it = items[j];
+                ProdTask t = make_task(*it.pl, *it.op, it.a, it.c, it.ws);
+                flops += t.syrk ? (double)t.m * (double)(t.m + 1) * (double)t.k
+                                : 2.0 * (double)t.m * (double)t.n * (double)t.k;
+                tasks[nt++] = t;
+            }
+            std::stable_sort(tasks, tasks + nt, longer_task);
+            hipEvent_t e0 = nullptr;
+            const bool prof = prof_enabled();
+            if (prof) prof_begin(s, &e0);
+            if (launch_products(cls, tasks, nt, dtasks, s) != hipSuccess) status = FFP_EDEVICE;
+            if (prof) prof_end(s, e0, flops, cls);
+        }
+        for (int q = 0; q < 9 && status == FFP_OK; ++q) {
+            const auto& g = packs[q];
+            if (g.empty()) continue;
+            if (g.size() == 1) {
+                const SchedItem& it = items[g[0]];
+                status = execute_op(*it.pl, *it.op, it.a, it.c, it.ws, s);
+                continue;
+            }
+            PackDesc* d = (PackDesc*)(host_meta + moff);
+            PackDesc* dd = (PackDesc*)(dev_meta + moff);
+            moff += (size_t)rup256((int64_t)(g.size() * sizeof(PackDesc)));
+            int nd = 0;
+            for (size_t j : g) {
+                const SchedItem& it = items[j];
+                d[nd++] = make_pack(*it.pl, *it.op, it.a, it.c, it.ws);
+            }
+            if (launch_pack_grouped(q / 3, q % 3, d, nd, dd, s) != hipSuccess) status = FFP_EDEVICE;
+        }
+        if (status != FFP_OK) break;
+    }
+    if (meta > 0) {
+        const int st = release_staging(s);
+        if (status == FFP_OK) status = st;
+    }
+    return status;
 }
 
 ProdTask make_task(const Plan& pl, const Op& o, const void* a, void* c, void* ws)

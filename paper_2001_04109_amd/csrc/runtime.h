@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <vector>
 
 #include "plan.h"
 
@@ -35,6 +36,29 @@ int release_staging(hipStream_t s);
 int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s);
 
 int execute_op(const Plan& pl, const Op& o, const void* a, void* c, void* ws, hipStream_t s);
+
+// Level scheduling of block operations.  Every op is placed on the
+// earliest level after all earlier ops of its job that it depends on (it
+// reads or writes memory that one of them writes, or writes memory that
+// one of them reads; views are compared as rectangles).  The ops of one
+// level are independent: the products of one class in a level run as one
+// grouped launch of the product kernel (tiles longest first), the packs of
+// one class pair as one grouped pack, other ops one by one.  Items of one
+// job are consecutive and in program order; different jobs must touch
+// disjoint memory.  Results are those of the program order.
+struct SchedItem {
+    const Plan* pl;
+    const Op* op;
+    const void* a;
+    void* c;
+    void* ws;
+    int job;
+};
+int run_leveled(const std::vector<SchedItem>& items, hipStream_t s);
+// The level of every item (host only; also used by tests through the C ABI).
+std::vector<int> schedule_levels(const std::vector<SchedItem>& items);
+// 1: execute_plan runs the level scheduler (default); 0: ops in program order.
+extern int g_leveled;
 ProdTask make_task(const Plan& pl, const Op& o, const void* a, void* c, void* ws);
 PackDesc make_pack(const Plan& pl, const Op& o, const void* a, void* c, void* ws);
 

@@ -28,6 +28,7 @@ FFP_I8_LIMB2 = 2
 
 FFP_FILL_UPPER = 0x1
 FFP_BASE_F64 = 0x100
+FFP_LOW_MEMORY = 0x200
 FFP_WS_BETA = 0x80000000
 
 
@@ -101,6 +102,8 @@ def lib():
             "ffp_plan_describe": (c_int, [i64, i64, u32, c_int, i64, i64, u32, u32, c_uint,
                                           ctypes.c_char_p, ctypes.c_size_t]),
             "ffp_ldlt_workspace_bytes": (ctypes.c_size_t, [i64, u32]),
+            "ffp_plan_levels": (c_int, [i64, i64, u32, c_int, i64, i64, u32, u32, c_uint, P,
+                                        ctypes.c_size_t]),
             "ffp_server_create": (c_int, [ctypes.c_size_t, c_int, c_int, P]),
             "ffp_server_create_simulated": (c_int, [ctypes.c_size_t, c_int, c_int, ctypes.c_double,
                                                     ctypes.c_double, P]),
@@ -231,6 +234,26 @@ def plan_describe(n, k, p, a_dtype=FFP_U32, lda=None, ldc=None, alpha=1, beta=0,
     _check(lib().ffp_plan_describe(n, k, p, a_dtype, lda, ldc, alpha, beta, flags, buf, size + 1),
            "plan_describe")
     return buf.value.decode()
+
+
+def plan_levels(n, k, p, a_dtype=FFP_U32, lda=None, ldc=None, alpha=1, beta=0, flags=0) -> list:
+    """Scheduler level of every operation of the plan plan_describe prints."""
+    lda = k if lda is None else lda
+    ldc = n if ldc is None else ldc
+    cnt = _check(lib().ffp_plan_levels(n, k, p, a_dtype, lda, ldc, alpha, beta, flags, None, 0),
+                 "plan_levels")
+    buf = (ctypes.c_int32 * max(cnt, 1))()
+    _check(lib().ffp_plan_levels(n, k, p, a_dtype, lda, ldc, alpha, beta, flags, buf, cnt),
+           "plan_levels")
+    return list(buf[:cnt])
+
+
+def set_knob(key: str, value: int):
+    """ffp_debug_set: process-wide tuning and test knobs."""
+    f = lib().ffp_debug_set
+    f.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+    f.restype = ctypes.c_int
+    _check(f(key.encode(), value), "ffp_debug_set")
 
 
 # ---- tensor conveniences (marshalling only) -------------------------------

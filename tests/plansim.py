@@ -126,8 +126,9 @@ class Sim:
         L, R = X[:, :h2], X[:, h2:]
         return np.concatenate([(a * L - b * R) % p, (b * L + a * R) % p], axis=1)
 
-    def run(self):
-        for op in self.plan.ops:
+    def run(self, order=None):
+        ops = self.plan.ops if order is None else [self.plan.ops[i] for i in order]
+        for op in ops:
             getattr(self, f"op{op.kind}")(op)
 
     def op0(self, o):   # S1 = (A21 - A11) Y, S2 = A22 - A21 Y
@@ -227,8 +228,9 @@ class Sim:
         self.put(o.v[1], CLS_F64, Y)
 
 
-def simulate(plan_text: str, p: int, A_bytes: bytes, C: np.ndarray) -> np.ndarray:
-    """Run the schedule on host copies; returns the resulting C (uint32)."""
+def simulate(plan_text: str, p: int, A_bytes: bytes, C: np.ndarray, order=None) -> np.ndarray:
+    """Run the schedule on host copies (in program order, or in the given
+    order of operation indices); returns the resulting C (uint32)."""
     plan = parse(plan_text)
     bufA = bytearray(A_bytes)
     bufC = bytearray(np.ascontiguousarray(C, dtype=np.uint32).tobytes())
@@ -237,5 +239,5 @@ def simulate(plan_text: str, p: int, A_bytes: bytes, C: np.ndarray) -> np.ndarra
     rng = np.random.default_rng(12345)
     bufW[:] = rng.integers(0, 256, size=len(bufW), dtype=np.uint8).tobytes()
     sim = Sim([bufA, bufC, bufW], p, plan)
-    sim.run()
+    sim.run(order)
     return np.frombuffer(bytes(bufC), dtype=np.uint32).reshape(C.shape).copy()

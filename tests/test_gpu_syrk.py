@@ -245,15 +245,48 @@ def _sampled(A, p, out, nsamp=4000, seed=0):
     assert np.array_equal(got, expect)
 
 
+@pytest.mark.parametrize("wide", [0, 1])
+@pytest.mark.parametrize("p,depth", [(131071, 1), (131071, 3), (65537, 2), (1000003, 2)])
+@pytest.mark.parametrize("n,k", [(256, 256), (300, 1000), (520, 130)])
+def test_syrk_level_scheduler(wide, p, depth, n, k):
+    """Independent products grouped per level (and the wide placements)."""
+    A = inputs.uniform(n + 3 * k + depth, n, k, p)
+    set_knob("wide", wide)
+    try:
+        check_lower(gpu_syrk(A, p, depth=depth), oracle.syrk(A, p))
+        C0 = inputs.uniform(9, n, n, p)
+        check_lower(gpu_syrk(A, p, depth=depth, alpha=3, beta=p - 2, C0=C0),
+                    oracle.syrk_ab(A, p, 3, p - 2, C0))
+    finally:
+        set_knob("wide", 1)
+
+
+def test_program_order_execution_matches():
+    p, n, k = 131071, 384, 512
+    A = inputs.uniform(44, n, k, p)
+    set_knob("leveled", 0)
+    try:
+        seq = gpu_syrk(A, p, depth=2)
+    finally:
+        set_knob("leveled", 1)
+    check_lower(seq, oracle.syrk(A, p))
+    check_lower(gpu_syrk(A, p, depth=2), seq)
+
+
+@pytest.mark.parametrize("wide", [0, 1])
 @pytest.mark.parametrize("k", [8192, 32768])
-def test_full_size_8192_p131071_depth3(k):
+def test_full_size_8192_p131071_depth3(k, wide):
     import torch
     p, n = 131071, 8192
     A = inputs.uniform(1, n, k, p)
     Ad = to_dev_u32(A)
     Cd = torch.zeros((n, n), dtype=torch.int32, device="cuda")
-    ffp.syrk(Ad, p, C=Cd, depth=3)
-    torch.cuda.synchronize()
+    set_knob("wide", wide)
+    try:
+        ffp.syrk(Ad, p, C=Cd, depth=3)
+        torch.cuda.synchronize()
+    finally:
+        set_knob("wide", 1)
     _sampled(A, p, from_dev_u32(Cd))
 
 

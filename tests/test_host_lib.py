@@ -94,10 +94,14 @@ def test_non_prime_rejected():
 
 
 def test_workspace_bytes_monotone():
-    w1 = ffp.ffp_workspace_bytes(1024, 1024, 131071, 0, ffp.FFP_DEPTH(2))
-    w2 = ffp.ffp_workspace_bytes(1024, 4096, 131071, 0, ffp.FFP_DEPTH(2))
-    w3 = ffp.ffp_workspace_bytes(1024, 1024, 131071, 0, ffp.FFP_DEPTH(2) | ffp.FFP_WS_BETA)
+    low = ffp.FFP_DEPTH(2) | ffp.FFP_LOW_MEMORY
+    w1 = ffp.ffp_workspace_bytes(1024, 1024, 131071, 0, low)
+    w2 = ffp.ffp_workspace_bytes(1024, 4096, 131071, 0, low)
+    w3 = ffp.ffp_workspace_bytes(1024, 1024, 131071, 0, low | ffp.FFP_WS_BETA)
     assert w1 == 0 and w2 > 0 and w3 > 0
+    # the default (wide) placements trade memory for independent products
+    w4 = ffp.ffp_workspace_bytes(1024, 1024, 131071, 0, ffp.FFP_DEPTH(2))
+    assert w4 > 0
     L = ffp.lib()
     L.ffp_ldlt_workspace_bytes.restype = ctypes.c_size_t
     L.ffp_ldlt_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_uint32]

@@ -56,11 +56,12 @@ def run_case(n, k, p, depth, alpha=1, beta=0, a_dtype=ffp.FFP_U32, flags=0, seed
     return plansim.parse(text)
 
 
+@pytest.mark.parametrize("placement", [0, ffp.FFP_LOW_MEMORY], ids=["wide", "table3"])
 @pytest.mark.parametrize("p", [65537, 131071, 1000003])
 @pytest.mark.parametrize("depth", [1, 2, 3])
 @pytest.mark.parametrize("n,k", [(32, 32), (48, 24), (40, 72), (37, 29)])
-def test_table3_f64(p, depth, n, k):
-    plan = run_case(n, k, p, depth)
+def test_table3_f64(placement, p, depth, n, k):
+    plan = run_case(n, k, p, depth, flags=placement)
     assert plan.cls == plansim.CLS_F64
 
 
@@ -89,6 +90,7 @@ def test_table4_keeps_diagonal_of_c22():
                                        (257, ffp.FFP_I8_LIMB2)])
 @pytest.mark.parametrize("depth", [0, 1, 2])
 def test_int8_classes(p, a_dtype, depth):
+    run_case(40, 72, p, depth, a_dtype=a_dtype, seed=5, flags=ffp.FFP_LOW_MEMORY)
     plan = run_case(40, 72, p, depth, a_dtype=a_dtype, seed=5)
     assert plan.cls == (plansim.CLS_I8 if p <= 251 else plansim.CLS_LIMB2)
     run_case(64, 64, p, depth, alpha=3, beta=p - 1, a_dtype=a_dtype, seed=6)
@@ -107,10 +109,10 @@ def test_fill_upper_and_padded_ldc(depth):
 
 def test_table3_uses_no_workspace_when_k_le_n():
     # Table 3: the block C12 is the only temporary when k <= n.
-    text = ffp.plan_describe(64, 64, 65537, flags=ffp.FFP_DEPTH(3))
+    text = ffp.plan_describe(64, 64, 65537, flags=ffp.FFP_DEPTH(3) | ffp.FFP_LOW_MEMORY)
     assert plansim.parse(text).ws == 0
     # k > n needs two m x h blocks per level.
-    text = ffp.plan_describe(64, 128, 65537, flags=ffp.FFP_DEPTH(1))
+    text = ffp.plan_describe(64, 128, 65537, flags=ffp.FFP_DEPTH(1) | ffp.FFP_LOW_MEMORY)
     assert plansim.parse(text).ws >= 2 * 32 * 64 * 4
 
 
