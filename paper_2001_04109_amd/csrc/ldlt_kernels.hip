@@ -11,6 +11,23 @@ namespace {
 
 constexpr int NB = kLdltLeaf;   // leaf order and triangular-solve block
 
+// a b mod p for residues (the product is below 2^50, exact in a double).
+__device__ __forceinline__ uint32_t mulmod_d(uint32_t a, uint32_t b, uint32_t p, double pinv)
+{
+    return mod53((double)a * (double)b, p, pinv);
+}
+
+__device__ uint32_t powmod_d(uint32_t a, uint32_t e, uint32_t p, double pinv)
+{
+    uint32_t r = 1u;
+    while (e) {
+        if (e & 1u) r = mulmod_d(r, a, p, pinv);
+        a = mulmod_d(a, a, p, pinv);
+        e >>= 1;
+    }
+    return r;
+}
+
 // In-place LDL^T of an nb x nb block (nb <= NB) in LDS, followed (when
 // every pivot is nonzero) by the inverse of its unit lower triangular
 // factor, written to linv (row i at linv + 64 i, columns <= i), which the
@@ -18,20 +35,24 @@ constexpr int NB = kLdltLeaf;   // leaf order and triangular-solve block
 // residues whose sum stays below 2^53.
 //
 // The elimination is division-free, so no modular inverse sits on the
-// sequential path: step k replaces M[i][j] by a_k M[i][j] - M[i][k] M[k][j]
-// (i, j > k) with a_k = M[k][k].  By induction M = g_k S_k on the trailing
-// block, where S_k is the true Schur complement and g_k = a_0 ... a_{k-1};
-// hence D[k] = a_k / g_k and L[i][k] = M[i][k] / a_k (M taken at step k),
-// and a_k = 0 exactly when the true pivot is 0.  The 2 nb inverses are then
-// formed in parallel.
+// sequential path: step k replaces M[i][j] by a_k M[i][j] - M[i][k] M[j][k]
+// (i >= j > k) with a_k = M[k][k].  By induction M = g_k S_k on the
+// trailing block, where S_k is the true Schur complement and
+// g_k = a_0 ... a_{k-1}; hence D[k] = a_k / g_k and L[i][k] = M[i][k] / a_k
+// (M taken at step k), and a_k = 0 exactly when the true pivot is 0.  The
+// inverses are then formed in parallel.  The inverse of L is built from its
+// 8 x 8 diagonal blocks up: [[A, 0], [B, C]]^-1 = [[A^-1, 0], [-C^-1 B A^-1,
+// C^-1]] on blocks of 8, 16 and 32.
 __global__ __launch_bounds__(256) void ldlt_leaf_kernel(Fp f, int kb, int nb, uint32_t* S, int64_t lds,
                                                        int64_t* info, int64_t offset, uint32_t* linv)
 {
     __shared__ uint32_t sm[NB][NB + 1];
     __shared__ uint32_t li[NB][NB + 1];
+    __shared__ uint32_t tq[NB][NB + 1];
     __shared__ uint32_t ainv[NB];
     const uint32_t p = f.p;
-    const int tid = threadIdx.x;
+    const double pd = (double)p, pinv = f.pinv;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
         if (j <= i) sm[i][j] = S[(int64_t)i * lds + j];
@@ -45,18 +66,18 @@ __global__ __launch_bounds__(256) void ldlt_leaf_kernel(Fp f, int kb, int nb, ui
             stop = true;                            // every thread read the same a
             break;
         }
-        // trailing update of the lower triangle: rows i > k, columns k < j <= i
+        // trailing lower triangle: lane -> column k + 1 + jj, waves stride the rows
         const int r = nb - k - 1;
-        const int cnt = r * (r + 1) / 2;
-        for (int e = tid; e < cnt; e += blockDim.x) {
-            // e -> (ii, jj) with 0 <= jj <= ii < r, row-major over the triangle
-            int ii = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-            while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-            while (ii * (ii + 1) / 2 > e) --ii;
-            const int jj = e - ii * (ii + 1) / 2;
-            const int i = k + 1 + ii, j = k + 1 + jj;
-            const uint32_t v = mul_m(a, sm[i][j], p, f.pinv);
-            sm[i][j] = sub_m(v, mul_m(sm[i][k], sm[j][k], p, f.pinv), p);
+        const int jj = lane;
+        if (jj < r) {
+            const int j = k + 1 + jj;
+            const double mjk = (double)sm[j][k];
+            int ii = jj + ((wv - jj) & 3);          // first row >= jj with ii = wv (mod 4)
+            for (; ii < r; ii += 4) {
+                const int i = k + 1 + ii;
+                const double x = fma((double)a, (double)sm[i][j], (pd - (double)sm[i][k]) * mjk);
+                sm[i][j] = mod53(x, p, pinv);       // x < 2 p^2 < 2^51
+            }
         }
         __syncthreads();
     }
@@ -66,42 +87,70 @@ __global__ __launch_bounds__(256) void ldlt_leaf_kernel(Fp f, int kb, int nb, ui
     if (tid < nb) {
         const int k = tid;
         uint32_t g = 1u;
-        for (int t = 0; t < k; ++t) g = mul_m(g, sm[t][t], p, f.pinv);
+        for (int t = 0; t < k; ++t) g = mulmod_d(g, sm[t][t], p, pinv);
         const uint32_t a = sm[k][k];
-        ainv[k] = inv_m(a, p, f.pinv);
-        dk = mul_m(a, inv_m(g, p, f.pinv), p, f.pinv);
+        ainv[k] = powmod_d(a, p - 2, p, pinv);
+        dk = mulmod_d(a, powmod_d(g, p - 2, p, pinv), p, pinv);
     }
     __syncthreads();                 // every a_k read before D overwrites the diagonal
     if (tid < nb) sm[tid][tid] = dk;
-    __syncthreads();
     for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
-        if (j < i) sm[i][j] = mul_m(sm[i][j], ainv[j], p, f.pinv);
+        if (j < i) sm[i][j] = mulmod_d(sm[i][j], ainv[j], p, pinv);
     }
     __syncthreads();
     for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
         if (j <= i) S[(int64_t)i * lds + j] = sm[i][j];
     }
-    // inverse of the unit lower factor, one column per thread:
-    // X[i][j] = -sum_{j <= t < i} L[i][t] X[t][j], X[j][j] = 1
-    if (tid < nb) {
-        const int j = tid;
-        li[j][j] = 1u;
-        for (int i = j + 1; i < nb; ++i) {
+    // inverse of the unit lower factor; rows and columns past nb act as an
+    // identity block.  Strict lower entries of L: lo(i, j).
+    auto lo = [&](int i, int j) -> uint32_t { return (i < nb && j < nb) ? sm[i][j] : 0u; };
+    // 8 x 8 diagonal blocks by forward substitution, one column per thread
+    if (tid < NB) {
+        const int q = tid >> 3, c = tid & 7, b0 = q * 8;
+        li[b0 + c][b0 + c] = 1u;
+        for (int i = c + 1; i < 8; ++i) {
+            double acc = 0.0;
+            for (int t = c; t < i; ++t) acc = fma((double)lo(b0 + i, b0 + t), (double)li[b0 + t][b0 + c], acc);
+            const uint32_t v = mod53(acc, p, pinv);   // at most 7 terms
+            li[b0 + i][b0 + c] = v == 0u ? 0u : p - v;
+        }
+    }
+    __syncthreads();
+    for (int b = 8; b < NB; b *= 2) {
+        const int pairs = NB / (2 * b);
+        // T = B A^-1 for each pair: B = L[C rows][A cols], A^-1 lower triangular
+        for (int e = tid; e < pairs * b * b; e += blockDim.x) {
+            const int q = e / (b * b), rem = e - q * b * b, i = rem / b, j = rem - i * b;
+            const int a0 = q * 2 * b, c0 = a0 + b;
             double acc = 0.0;
             int cnt = 0;
-            for (int t = j; t < i; ++t) {
-                acc = fma((double)sm[i][t], (double)li[t][j], acc);
-                if (++cnt == kb) {
-                    acc = (double)mod53(acc, p, f.pinv);
-                    cnt = 1;
-                }
+            for (int t = j; t < b; ++t) {
+                acc = fma((double)lo(c0 + i, a0 + t), (double)li[a0 + t][a0 + j], acc);
+                if (++cnt == kb) { acc = (double)mod53(acc, p, pinv); cnt = 1; }
             }
-            const uint32_t v = mod53(acc, p, f.pinv);
-            li[i][j] = v == 0u ? 0u : p - v;
+            tq[c0 + i][a0 + j] = mod53(acc, p, pinv);
         }
-        for (int i = j; i < nb; ++i) linv[i * NB + j] = li[i][j];
+        __syncthreads();
+        // X21 = -C^-1 T
+        for (int e = tid; e < pairs * b * b; e += blockDim.x) {
+            const int q = e / (b * b), rem = e - q * b * b, i = rem / b, j = rem - i * b;
+            const int a0 = q * 2 * b, c0 = a0 + b;
+            double acc = 0.0;
+            int cnt = 0;
+            for (int t = 0; t <= i; ++t) {
+                acc = fma((double)li[c0 + i][c0 + t], (double)tq[c0 + t][a0 + j], acc);
+                if (++cnt == kb) { acc = (double)mod53(acc, p, pinv); cnt = 1; }
+            }
+            const uint32_t v = mod53(acc, p, pinv);
+            li[c0 + i][a0 + j] = v == 0u ? 0u : p - v;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        if (j <= i) linv[i * NB + j] = li[i][j];
     }
 }
 
