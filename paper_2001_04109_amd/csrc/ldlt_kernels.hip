@@ -11,23 +11,6 @@ namespace {
 
 constexpr int NB = kLdltLeaf;   // leaf order and triangular-solve block
 
-// a b mod p for residues (the product is below 2^50, exact in a double).
-__device__ __forceinline__ uint32_t mulmod_d(uint32_t a, uint32_t b, uint32_t p, double pinv)
-{
-    return mod53((double)a * (double)b, p, pinv);
-}
-
-__device__ uint32_t powmod_d(uint32_t a, uint32_t e, uint32_t p, double pinv)
-{
-    uint32_t r = 1u;
-    while (e) {
-        if (e & 1u) r = mulmod_d(r, a, p, pinv);
-        a = mulmod_d(a, a, p, pinv);
-        e >>= 1;
-    }
-    return r;
-}
-
 // In-place LDL^T of an nb x nb block (nb <= NB) in LDS, followed (when
 // every pivot is nonzero) by the inverse of its unit lower triangular
 // factor, written to linv (row i at linv + 64 i, columns <= i), which the
@@ -87,16 +70,16 @@ __global__ __launch_bounds__(256) void ldlt_leaf_kernel(Fp f, int kb, int nb, ui
     if (tid < nb) {
         const int k = tid;
         uint32_t g = 1u;
-        for (int t = 0; t < k; ++t) g = mulmod_d(g, sm[t][t], p, pinv);
+        for (int t = 0; t < k; ++t) g = mul_m(g, sm[t][t], p, pinv);
         const uint32_t a = sm[k][k];
-        ainv[k] = powmod_d(a, p - 2, p, pinv);
-        dk = mulmod_d(a, powmod_d(g, p - 2, p, pinv), p, pinv);
+        ainv[k] = pow_m(a, p - 2, p, pinv);
+        dk = mul_m(a, pow_m(g, p - 2, p, pinv), p, pinv);
     }
     __syncthreads();                 // every a_k read before D overwrites the diagonal
     if (tid < nb) sm[tid][tid] = dk;
     for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
-        if (j < i) sm[i][j] = mulmod_d(sm[i][j], ainv[j], p, pinv);
+        if (j < i) sm[i][j] = mul_m(sm[i][j], ainv[j], p, pinv);
     }
     __syncthreads();
     for (int e = tid; e < nb * nb; e += blockDim.x) {

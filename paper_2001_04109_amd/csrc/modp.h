@@ -17,16 +17,21 @@ __device__ inline uint32_t sub_m(uint32_t a, uint32_t b, uint32_t p)
     return a >= b ? a - b : a + p - b;
 }
 
-// a*b mod p: the product is below 2^50, exact in double; the quotient
-// estimate from 1/p is off by at most one.
+// Reduction of a non-negative integer x < 2^53 held in a double: the
+// quotient estimate from 1/p is off by at most one, the remainder is exact.
+__device__ inline uint32_t mod53(double x, uint32_t p, double pinv)
+{
+    const double q = floor(x * pinv);
+    double r = fma(-q, (double)p, x);
+    if (r < 0.0) r += (double)p;
+    if (r >= (double)p) r -= (double)p;
+    return (uint32_t)r;
+}
+
+// a*b mod p: the product of two residues is below 2^50, exact in a double.
 __device__ inline uint32_t mul_m(uint32_t a, uint32_t b, uint32_t p, double pinv)
 {
-    const uint64_t prod = (uint64_t)a * b;
-    const double q = floor((double)prod * pinv);
-    int64_t r = (int64_t)prod - (int64_t)q * (int64_t)p;
-    if (r < 0) r += p;
-    if (r >= (int64_t)p) r -= p;
-    return (uint32_t)r;
+    return mod53((double)a * (double)b, p, pinv);
 }
 
 __device__ inline uint32_t pow_m(uint32_t a, uint32_t e, uint32_t p, double pinv)
@@ -38,16 +43,6 @@ __device__ inline uint32_t pow_m(uint32_t a, uint32_t e, uint32_t p, double pinv
         e >>= 1;
     }
     return r;
-}
-
-// Reduction of a non-negative integer x < 2^53 held in a double.
-__device__ inline uint32_t mod53(double x, uint32_t p, double pinv)
-{
-    const double q = floor(x * pinv);
-    double r = fma(-q, (double)p, x);
-    if (r < 0.0) r += (double)p;
-    if (r >= (double)p) r -= (double)p;
-    return (uint32_t)r;
 }
 
 // Inverse of a in [1, p) for an odd prime p by the binary extended Euclidean
