@@ -431,6 +431,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests of the served stream (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--underload-rate", type=float, default=300.0,
+                    help="offered rate of the latency run below the GPU's capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus {args.gpus} "
@@ -478,15 +480,20 @@ def main():
         log(f"bench: served stream, {args.serve_requests} requests at {args.serve_rate}/s")
         sv, reqs, pool = served(args.serve_requests, rate=args.serve_rate)
         log(f"bench: served {sv}")
-        log("bench: same stream, all requests at t=0")
-        sat, _, _ = served(args.serve_requests, rate=args.serve_rate, saturate=True, pool=pool,
-                           check=False)
+        ncmp = min(args.serve_requests, 4000)
+        log(f"bench: first {ncmp} requests at once")
+        sat, reqs_c, _ = served(ncmp, rate=args.serve_rate, saturate=True, pool=pool, check=False)
         log(f"bench: saturated {sat}")
-        log("bench: same requests per call")
-        pc = per_call_plain(reqs, pool)
+        log(f"bench: first {ncmp} requests per call")
+        pc = per_call_plain(reqs_c, pool)
         log(f"bench: per-call {pc}")
+        nlow = min(args.serve_requests, 2000)
+        log(f"bench: first {nlow} requests at {args.underload_rate}/s")
+        low, _, _ = served(nlow, rate=args.underload_rate, pool=pool, check=False)
+        log(f"bench: underload {low}")
         extra["served_stream"] = {"arrivals": sv, "saturated": sat, "per_call_plain": pc,
-                                  "saturated_vs_per_call": round(sat["gops_total"] / pc["gops_total"], 3)}
+                                  "saturated_vs_per_call": round(sat["gops_total"] / pc["gops_total"], 3),
+                                  "underload": low}
         del pool
     cpu = None
     if not args.no_cpu_baseline:
