@@ -127,6 +127,24 @@ int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, v
  * control; 0 if p is not an odd prime below 2^25. */
 size_t ffp_ldlt_workspace_bytes(int64_t n, uint32_t p);
 
+/* One factorisation of fldlt_modp_batched (host struct; device pointers). */
+typedef struct ffp_ldlt_job {
+    int64_t n;
+    uint32_t p;
+    uint32_t* S;
+    int64_t lds;
+    int64_t* info;
+} ffp_ldlt_job;
+
+/* Runs njobs independent fldlt_modp factorisations together: the steps of
+ * all recursions run level by level, each kind of step (leaf
+ * factorisations, triangular solves, Algorithm 5, products) of all jobs as
+ * one launch.  Each job must use its own S and info; results are
+ * bit-identical to the jobs run one by one.  jobs is a host array.
+ * Errors: as fldlt_modp, checked for every job before anything is
+ * enqueued. */
+int fldlt_modp_batched(int njobs, const ffp_ldlt_job* jobs, void* stream);
+
 /* Device workspace fsyrk_modp needs for this shape (bytes), for admission
  * control; flags as for fsyrk_modp (beta != 0 is signalled by
  * FFP_WS_BETA). */
@@ -161,13 +179,14 @@ int fsyrk_modp_batched(int njobs, const ffp_job* jobs, unsigned flags, void* str
  * workspace.  A scheduler thread admits queued requests in arrival order
  * while their footprint (result buffer plus workspace) fits in the arena and
  * fewer than max_inflight requests are running; a job's workspace returns to
- * the arena when the job is done, its result when the caller releases it.  Every scheduler iteration gathers the
- * admitted A*A^T requests into one batched launch (fsyrk_modp_batched) on a
- * free stream and gives each admitted LDL^T request a stream of its own, so
- * requests that arrive while others run join at the next iteration and
- * their work overlaps on the device.  Each result is bit-identical to the
- * same job run alone.  Operands are caller-owned device memory that must
- * stay valid and unchanged until the request is done. */
+ * the arena when the job is done, its result when the caller releases it.
+ * Every scheduler iteration turns the requests admitted for a free stream
+ * into one unit: its A*A^T requests as one fsyrk_modp_batched launch, then
+ * its LDL^T requests as one fldlt_modp_batched run; requests that arrive
+ * while units run join the next unit, so their work overlaps on the device.
+ * Each result is bit-identical to the same job run alone.  Operands are
+ * caller-owned device memory that must stay valid and unchanged until the
+ * request is done. */
 #define FFP_REQ_SYRK 0      /* C = alpha * A * A^T mod p (lower triangle) */
 #define FFP_REQ_LDLT 1      /* L D L^T of the symmetric matrix whose lower triangle is A */
 #define FFP_STATE_QUEUED  0

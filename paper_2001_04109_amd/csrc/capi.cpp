@@ -3,6 +3,7 @@
 
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "ffp.h"
 #include "ffp_debug.h"
@@ -236,6 +237,32 @@ int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, v
     if (n > 0 && (S == nullptr || lds < n)) return FFP_EINVAL;
     if (n > (int64_t)1 << 30) return FFP_EINVAL;
     return ldlt_run(n, p, S, lds, info, (hipStream_t)stream);
+}
+
+int fldlt_modp_batched(int njobs, const ffp_ldlt_job* jobs, void* stream)
+{
+    if (njobs < 0 || (njobs > 0 && jobs == nullptr)) return FFP_EINVAL;
+    size_t total = 0;
+    std::vector<size_t> off((size_t)njobs, 0);
+    for (int j = 0; j < njobs; ++j) {
+        const ffp_ldlt_job& b = jobs[j];
+        if (b.n < 0 || b.info == nullptr || b.n > ((int64_t)1 << 30)) return FFP_EINVAL;
+        if (b.p < 3 || b.p >= (1u << 25) || !is_prime_u32(b.p)) return FFP_EPRIME;
+        if (b.n > 0 && (b.S == nullptr || b.lds < b.n)) return FFP_EINVAL;
+        off[j] = total;
+        total += (ldlt_workspace_bytes(b.n, b.p, b.lds) + 255) / 256 * 256;
+    }
+    if (njobs == 0) return FFP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace* w = nullptr;
+    const int st = acquire_workspace(s, total, 0, &w);
+    if (st != FFP_OK) return st;
+    std::vector<LdltJobSpec> specs;
+    for (int j = 0; j < njobs; ++j) {
+        const ffp_ldlt_job& b = jobs[j];
+        specs.push_back(LdltJobSpec{b.n, b.p, b.S, b.lds, b.info, (char*)w->ptr + off[j]});
+    }
+    return ldlt_run_multi(specs, s);
 }
 
 size_t ffp_ldlt_workspace_bytes(int64_t n, uint32_t p)

@@ -5,6 +5,8 @@
 #include "ldlt.h"
 
 #include <algorithm>
+#include <cstring>
+#include <deque>
 
 #include "ffp.h"
 #include "field.h"
@@ -60,82 +62,278 @@ PlanRequest schur_request(int64_t n2, const NodeLayout& L, uint32_t p, int64_t l
     return rq;
 }
 
-struct Ctx {
+// One step of a factorisation, at its level in the job's sequence.
+enum StepKind { SK_DEV = 0, SK_PROD = 1, SK_OP = 2 };
+struct Step {
+    int level;
+    int sk;
+    int kind;          // SK_DEV: LK_*
+    int cls;           // SK_PROD: base class of the product
+    LdltDesc d;        // SK_DEV
+    ProdTask t;        // SK_PROD
+    const Plan* pl;    // SK_OP
+    const Op* op;
+    const void* a;
+    void* c;
+    void* ws;
+};
+
+// Flattens the recursion of one factorisation into steps.  Consecutive
+// steps depend on each other, except the block operations of one Schur
+// update, which take the levels of the level scheduler.
+struct Builder {
     FieldPlan fpl;
     Fp f;
+    int kb;
     uint32_t s_lqnr, c_lqnr;
     uint32_t* linv;     // inverses of the leaf blocks of L: column block c at linv + 64 c
     char* ws;
     int64_t* info;
-    hipStream_t s;
+    int64_t lds;
+    std::deque<Plan>* plans;
+    std::vector<Step>* out;
+    int level = 0;
+    int status = FFP_OK;
+
+    LdltDesc base() const
+    {
+        LdltDesc d{};
+        d.f = f;
+        d.kb = kb;
+        d.s_lqnr = s_lqnr;
+        d.c_lqnr = c_lqnr;
+        d.info = info;
+        return d;
+    }
+    void dev(int kind, const LdltDesc& d)
+    {
+        Step s{};
+        s.level = level++;
+        s.sk = SK_DEV;
+        s.kind = kind;
+        s.d = d;
+        out->push_back(s);
+    }
+    void prod(const ProdTask& t)
+    {
+        Step s{};
+        s.level = level++;
+        s.sk = SK_PROD;
+        s.cls = CLS_F64;
+        s.t = t;
+        out->push_back(s);
+    }
+    void plan_ops(const Plan& pl, const void* a, void* c, void* w)
+    {
+        std::vector<SchedItem> items;
+        items.reserve(pl.ops.size());
+        for (const Op& o : pl.ops) items.push_back(SchedItem{&pl, &o, a, c, w, 0});
+        const std::vector<int> lv = schedule_levels(items);
+        int mx = -1;
+        for (size_t i = 0; i < items.size(); ++i) {
+            const Op& o = pl.ops[i];
+            Step s{};
+            s.level = level + lv[i];
+            if (o.kind == OP_SYRK || o.kind == OP_GEMM) {
+                s.sk = SK_PROD;
+                s.cls = o.cls;
+                s.t = make_task(pl, o, a, c, w);
+            } else {
+                s.sk = SK_OP;
+                s.pl = &pl;
+                s.op = &o;
+                s.a = a;
+                s.c = c;
+                s.ws = w;
+            }
+            out->push_back(s);
+            mx = std::max(mx, lv[i]);
+        }
+        level += mx + 1;
+    }
+
+    // X <- X L^-T for the unit lower triangular m x m factor L whose first
+    // column is column col0 of the whole factorisation.  The blocks split as
+    // the factorisation does, so every leaf is a leaf block of rec() whose
+    // inverse is in linv.
+    void trsm(int64_t nrows, int64_t m, uint32_t* X, int64_t ldx, const uint32_t* L, int64_t ldl, int64_t col0)
+    {
+        if (nrows <= 0 || m <= 0) return;
+        if (m <= kLdltLeaf) {
+            LdltDesc d = base();
+            d.rows = nrows;
+            d.nb = (int32_t)m;
+            d.X = X;
+            d.ldx = ldx;
+            d.linv = linv + col0 * kLdltLeaf;
+            dev(LK_TRSM, d);
+            return;
+        }
+        const int64_t m1 = rup((m + 1) / 2, kLdltLeaf);
+        trsm(nrows, m1, X, ldx, L, ldl, col0);
+        // X[:, m1:] <- X[:, m1:] - X[:, :m1] L[m1:, :m1]^T
+        ProdTask t{};
+        init_task(&t, fpl);
+        t.A = DView{X, ldx, 0};
+        t.B = DView{(void*)(L + m1 * ldl), ldl, 0};
+        t.C = X + m1;
+        t.ldc = ldx;
+        t.m = (int32_t)nrows;
+        t.n = (int32_t)(m - m1);
+        t.k = (int32_t)m1;
+        t.syrk = 0;
+        t.alpha = f.p - 1;
+        t.beta = 1;
+        prod(t);
+        trsm(nrows, m - m1, X + m1, ldx, L + m1 * ldl + m1, ldl, col0 + m1);
+    }
+
+    void rec(int64_t n, uint32_t* S, int64_t offset)
+    {
+        if (n <= 0 || status != FFP_OK) return;
+        if (n <= kLdltLeaf) {
+            LdltDesc d = base();
+            d.nb = (int32_t)n;
+            d.X = S;
+            d.ldx = lds;
+            d.offset = offset;
+            d.linv = linv + offset * kLdltLeaf;
+            dev(LK_LEAF, d);
+            return;
+        }
+        const int64_t n1 = split_point(n), n2 = n - n1;
+        uint32_t* S11 = S;
+        uint32_t* S21 = S + n1 * lds;
+        uint32_t* S22 = S + n1 * lds + n1;
+        rec(n1, S11, offset);
+        // W = S21 L11^-T, then L21 = W D1^-1
+        trsm(n2, n1, S21, lds, S11, lds, offset);
+        const NodeLayout L = layout(n1, n2);
+        LdltDesc d = base();
+        d.sc = Alg5Scratch{(int32_t*)(ws + L.off_flag), (uint32_t*)(ws + L.off_root),
+                           (uint32_t*)(ws + L.off_dinv), (int32_t*)(ws + L.off_rank),
+                           (ColOp*)(ws + L.off_desc)};
+        d.nb = (int32_t)n1;
+        d.X = S11;
+        d.ldx = lds;
+        dev(LK_CLASSIFY, d);
+        dev(LK_PAIR, d);
+        LdltDesc sd = d;
+        sd.rows = n2;
+        sd.X = S21;
+        dev(LK_SCALE, sd);
+        uint32_t* Ab = (uint32_t*)(ws + L.off_abar);
+        LdltDesc ad = d;
+        ad.rows = n2;
+        ad.ncols = (int32_t)(n1 + 1);
+        ad.kpad = (int32_t)L.kpad;
+        ad.X = S21;
+        ad.Ab = Ab;
+        ad.ldab = L.abar_ld;
+        dev(LK_ABAR, ad);
+        // S22 <- S22 - Abar Abar^T  (alpha = p - 1, beta = 1: Table 4 schedule)
+        plans->emplace_back();
+        Plan& pl = plans->back();
+        const int st = build_syrk_plan(schur_request(n2, L, f.p, lds, (((uintptr_t)S22) & 15) == 0), &pl);
+        if (st != FFP_OK) {
+            status = st;
+            return;
+        }
+        plan_ops(pl, Ab, S22, ws + L.off_syrk);
+        rec(n2, S22, offset + n1);
+    }
 };
 
-// X <- X L^-T for the unit lower triangular m x m factor L whose first
-// column is column col0 of the whole factorisation.  The blocks split as
-// the factorisation did, so every leaf is a leaf block of ldlt_rec whose
-// inverse is in c.linv.
-int trsm_rec(Ctx& c, int64_t nrows, int64_t m, uint32_t* X, int64_t ldx, const uint32_t* L,
-             int64_t ldl, int64_t col0)
-{
-    if (m <= kLdltLeaf)
-        return launch_trsm_leaf(c.f, nrows, (int)m, X, ldx, c.linv + col0 * kLdltLeaf, c.s) == hipSuccess
-                   ? FFP_OK
-                   : FFP_EDEVICE;
-    const int64_t m1 = rup((m + 1) / 2, kLdltLeaf);
-    int st = trsm_rec(c, nrows, m1, X, ldx, L, ldl, col0);
-    if (st != FFP_OK) return st;
-    // X[:, m1:] <- X[:, m1:] - X[:, :m1] L[m1:, :m1]^T
-    ProdTask t{};
-    init_task(&t, c.fpl);
-    t.A = DView{X, ldx, 0};
-    t.B = DView{(void*)(L + m1 * ldl), ldl, 0};
-    t.C = X + m1;
-    t.ldc = ldx;
-    t.m = (int32_t)nrows;
-    t.n = (int32_t)(m - m1);
-    t.k = (int32_t)m1;
-    t.syrk = 0;
-    t.alpha = c.f.p - 1;
-    t.beta = 1;
-    if (launch_products(CLS_F64, &t, 1, nullptr, c.s) != hipSuccess) return FFP_EDEVICE;
-    return trsm_rec(c, nrows, m - m1, X + m1, ldx, L + m1 * ldl + m1, ldl, col0 + m1);
-}
+int64_t rup256(int64_t x) { return (x + 255) / 256 * 256; }
 
-int ldlt_rec(Ctx& c, int64_t n, uint32_t* S, int64_t lds, int64_t offset)
+// Runs the steps of independent jobs level by level: device steps of one
+// kind in a level as one launch over their descriptors, products of one
+// class as one grouped launch, block operations one by one.
+int execute_steps(const std::vector<Step>& steps, hipStream_t s)
 {
-    if (n <= 0) return FFP_OK;
-    if (n <= kLdltLeaf)
-        return launch_ldlt_leaf(c.f, (int)n, S, lds, c.info, offset, c.linv + offset * kLdltLeaf, c.s) ==
-                       hipSuccess
-                   ? FFP_OK
-                   : FFP_EDEVICE;
-    const int64_t n1 = split_point(n), n2 = n - n1;
-    uint32_t* S11 = S;
-    uint32_t* S21 = S + n1 * lds;
-    uint32_t* S22 = S + n1 * lds + n1;
-    int st = ldlt_rec(c, n1, S11, lds, offset);
-    if (st != FFP_OK) return st;
-    // W = S21 L11^-T, then L21 = W D1^-1
-    st = trsm_rec(c, n2, n1, S21, lds, S11, lds, offset);
-    if (st != FFP_OK) return st;
-    const NodeLayout L = layout(n1, n2);
-    Alg5Scratch sc{(int32_t*)(c.ws + L.off_flag), (uint32_t*)(c.ws + L.off_root),
-                   (uint32_t*)(c.ws + L.off_dinv), (int32_t*)(c.ws + L.off_rank),
-                   (ColOp*)(c.ws + L.off_desc)};
-    if (launch_alg5(c.f, (int)n1, S11, lds, c.s_lqnr, c.c_lqnr, c.s_lqnr, sc, c.s) != hipSuccess)
-        return FFP_EDEVICE;
-    if (launch_scale_cols(c.f, n2, (int)n1, S21, lds, sc.dinv, c.s) != hipSuccess) return FFP_EDEVICE;
-    uint32_t* Ab = (uint32_t*)(c.ws + L.off_abar);
-    if (launch_build_abar(c.f, n2, (int)(n1 + 1), (int)L.kpad, S21, lds, sc.desc, Ab, L.abar_ld, c.s) !=
-        hipSuccess)
-        return FFP_EDEVICE;
-    // S22 <- S22 - Abar Abar^T  (alpha = p - 1, beta = 1: Table 4 schedule)
-    Plan pl;
-    st = build_syrk_plan(schur_request(n2, L, c.f.p, lds, (((uintptr_t)S22) & 15) == 0), &pl);
-    if (st != FFP_OK) return st;
-    st = execute_plan(pl, Ab, S22, c.ws + L.off_syrk, c.s);
-    if (st != FFP_OK) return st;
-    return ldlt_rec(c, n2, S22, lds, offset + n1);
+    if (steps.empty()) return FFP_OK;
+    int maxlev = 0;
+    for (const Step& st : steps) maxlev = std::max(maxlev, st.level);
+    std::vector<std::vector<int>> by(maxlev + 1);
+    for (size_t i = 0; i < steps.size(); ++i) by[steps[i].level].push_back((int)i);
+
+    // descriptor table: one slice per (level, kind); product tables for groups
+    // beyond the inline capacity
+    struct Slice { int kind, first, count, blocks; };
+    std::vector<std::vector<Slice>> slices(maxlev + 1);
+    std::vector<LdltDesc> table;
+    size_t prod_bytes = 0;
+    for (int lv = 0; lv <= maxlev; ++lv) {
+        for (int kind = 0; kind < LK_KINDS; ++kind) {
+            Slice sl{kind, (int)table.size(), 0, 0};
+            for (int i : by[lv]) {
+                const Step& st = steps[i];
+                if (st.sk != SK_DEV || st.kind != kind) continue;
+                LdltDesc d = st.d;
+                const int nbk = ldlt_blocks(kind, &d);
+                if (nbk <= 0) continue;
+                d.block0 = sl.blocks;
+                sl.blocks += nbk;
+                table.push_back(d);
+                ++sl.count;
+            }
+            if (sl.count) slices[lv].push_back(sl);
+        }
+        int np[3] = {0, 0, 0};
+        for (int i : by[lv])
+            if (steps[i].sk == SK_PROD) ++np[steps[i].cls];
+        for (int q : np)
+            if (q > kInlineTasks) prod_bytes += (size_t)rup256((int64_t)q * (int64_t)sizeof(ProdTask));
+    }
+    const size_t desc_bytes = (size_t)rup256((int64_t)(table.size() * sizeof(LdltDesc)));
+    char* host = nullptr;
+    char* dev = nullptr;
+    if (desc_bytes + prod_bytes > 0) {
+        const int st = acquire_staging(s, desc_bytes + prod_bytes, &host, &dev);
+        if (st != FFP_OK) return st;
+    }
+    if (!table.empty()) {
+        memcpy(host, table.data(), table.size() * sizeof(LdltDesc));
+        if (hipMemcpyAsync(dev, host, table.size() * sizeof(LdltDesc), hipMemcpyHostToDevice, s) != hipSuccess)
+            return FFP_EDEVICE;
+    }
+    const LdltDesc* dtable = (const LdltDesc*)dev;
+    size_t poff = desc_bytes;
+    int status = FFP_OK;
+    for (int lv = 0; lv <= maxlev && status == FFP_OK; ++lv) {
+        for (const Slice& sl : slices[lv])
+            if (launch_ldlt_kind(sl.kind, dtable + sl.first, sl.count, sl.blocks, s) != hipSuccess)
+                status = FFP_EDEVICE;
+        for (int cls = 0; cls < 3 && status == FFP_OK; ++cls) {
+            std::vector<ProdTask> g;
+            for (int i : by[lv])
+                if (steps[i].sk == SK_PROD && steps[i].cls == cls) g.push_back(steps[i].t);
+            if (g.empty()) continue;
+            std::stable_sort(g.begin(), g.end(), [](const ProdTask& a, const ProdTask& b) {
+                if (a.k != b.k) return a.k > b.k;
+                return (int64_t)a.m * a.n > (int64_t)b.m * b.n;
+            });
+            ProdTask* tasks = g.data();
+            ProdTask* dtasks = nullptr;
+            if (g.size() > (size_t)kInlineTasks) {
+                tasks = (ProdTask*)(host + poff);
+                dtasks = (ProdTask*)(dev + poff);
+                poff += (size_t)rup256((int64_t)(g.size() * sizeof(ProdTask)));
+                memcpy(tasks, g.data(), g.size() * sizeof(ProdTask));
+            }
+            if (launch_products(cls, tasks, (int)g.size(), dtasks, s) != hipSuccess) status = FFP_EDEVICE;
+        }
+        for (int i : by[lv]) {
+            if (status != FFP_OK) break;
+            const Step& st = steps[i];
+            if (st.sk == SK_OP) status = execute_op(*st.pl, *st.op, st.a, st.c, st.ws, s);
+        }
+    }
+    if (desc_bytes + prod_bytes > 0) {
+        const int st = release_staging(s);
+        if (status == FFP_OK) status = st;
+    }
+    return status;
 }
 
 size_t ws_need(int64_t n, uint32_t p, int64_t lds)
@@ -156,18 +354,34 @@ size_t linv_bytes(int64_t n) { return (size_t)rup(n * kLdltLeaf * 4, 256); }
 
 size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds) { return linv_bytes(n) + ws_need(n, p, lds); }
 
+int ldlt_run_multi(const std::vector<LdltJobSpec>& jobs, hipStream_t s)
+{
+    std::deque<Plan> plans;
+    std::vector<Step> steps;
+    for (const LdltJobSpec& j : jobs) {
+        Builder b;
+        if (!make_field_plan(j.p, &b.fpl)) return FFP_EPRIME;
+        b.f = Fp{j.p, (j.p - 1) / 2, b.fpl.pinv, b.fpl.ya, b.fpl.yb};
+        b.kb = ldlt_dot_block(j.p);
+        uint32_t sq = 2;
+        while (legendre(sq, j.p) == 1) ++sq;
+        b.s_lqnr = sq;
+        b.c_lqnr = (uint32_t)sqrt_mod(sq - 1, j.p);
+        b.info = j.info;
+        b.lds = j.lds;
+        b.linv = (uint32_t*)j.ws;
+        b.ws = (char*)j.ws + linv_bytes(j.n);
+        b.plans = &plans;
+        b.out = &steps;
+        b.dev(LK_ZERO, b.base());
+        b.rec(j.n, j.S, 0);
+        if (b.status != FFP_OK) return b.status;
+    }
+    return execute_steps(steps, s);
+}
+
 int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hipStream_t s, void* ws)
 {
-    Ctx c;
-    if (!make_field_plan(p, &c.fpl)) return FFP_EPRIME;
-    c.f = Fp{p, (p - 1) / 2, c.fpl.pinv, c.fpl.ya, c.fpl.yb};
-    uint32_t sq = 2;
-    while (legendre(sq, p) == 1) ++sq;
-    c.s_lqnr = sq;
-    c.c_lqnr = (uint32_t)sqrt_mod(sq - 1, p);
-    c.info = info;
-    c.s = s;
-    if (launch_zero_i64(info, s) != hipSuccess) return FFP_EDEVICE;
     if (!ws) {
         const size_t need = ldlt_workspace_bytes(n, p, lds);
         Workspace* w = nullptr;
@@ -175,9 +389,7 @@ int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hip
         if (st != FFP_OK) return st;
         ws = w->ptr;
     }
-    c.linv = (uint32_t*)ws;
-    c.ws = (char*)ws + linv_bytes(n);
-    return ldlt_rec(c, n, S, lds, 0);
+    return ldlt_run_multi({LdltJobSpec{n, p, S, lds, info, ws}}, s);
 }
 
 }  // namespace ffp

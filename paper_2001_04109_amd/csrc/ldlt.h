@@ -2,11 +2,16 @@
 // split, unit-lower triangular solve, Algorithm 5 applied to the pivots and
 // the Schur-complement update S22 <- S22 - Abar Abar^T through the Table 4
 // schedule of fsyrk.
+//
+// The host flattens the recursion of every factorisation into a sequence of
+// steps; the steps of several factorisations run together, level by level,
+// each device step kind as one launch over an array of descriptors.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "kernels.h"
 
@@ -30,28 +35,62 @@ struct Alg5Scratch {
     ColOp* desc;        // n1 + 1 column operations
 };
 
-// Leaf factorisation; also writes the inverse of the leaf's unit lower
-// factor to linv (nb rows of stride kLdltLeaf), used by launch_trsm_leaf.
-hipError_t launch_ldlt_leaf(const Fp& f, int nb, uint32_t* S, int64_t lds, int64_t* info,
-                            int64_t offset, uint32_t* linv, hipStream_t s);
-// X <- X L^-T for an nrows x nb block X, given linv = L^-1 of the unit lower
-// nb x nb factor as written by launch_ldlt_leaf.
-hipError_t launch_trsm_leaf(const Fp& f, int64_t nrows, int nb, uint32_t* X, int64_t ldx,
-                            const uint32_t* linv, hipStream_t s);
-hipError_t launch_alg5(const Fp& f, int n1, const uint32_t* S11, int64_t lds, uint32_t s_lqnr,
-                       uint32_t c_lqnr, uint32_t z, Alg5Scratch sc, hipStream_t s);
-hipError_t launch_scale_cols(const Fp& f, int64_t rows, int n1, uint32_t* W, int64_t ldw,
-                             const uint32_t* dinv, hipStream_t s);
-hipError_t launch_build_abar(const Fp& f, int64_t rows, int ncols, int kpad, const uint32_t* L,
-                             int64_t ldl, const ColOp* desc, uint32_t* Ab, int64_t ldab,
-                             hipStream_t s);
-hipError_t launch_zero_i64(int64_t* p, hipStream_t s);
+// Device step kinds.
+enum LdltKind : int32_t {
+    LK_ZERO = 0,     // *info = 0
+    LK_LEAF,         // leaf factorisation of the nb x nb block at X, inverse of its unit factor to linv
+    LK_TRSM,         // X (rows x nb) <- X L^-T with L^-1 at linv
+    LK_CLASSIFY,     // Algorithm 5, per pivot of S11 = X (nb pivots): flag, root, inverse
+    LK_PAIR,         // Algorithm 5: rank the non-residues, Algorithm 4 per pair, column ops
+    LK_SCALE,        // L21 = W D1^-1 (X = W, rows x nb)
+    LK_ABAR,         // Abar (rows x kpad) from the column ops on L21 = X
+    LK_KINDS
+};
+
+// Descriptor of one device step (read by the kernels from device memory).
+struct LdltDesc {
+    Fp f;
+    int32_t kb;        // residue products per FP64 partial sum
+    int32_t nb;        // leaf / solve width; Algorithm 5: n1
+    int64_t rows;      // solve, scale, abar: rows
+    int32_t ncols, kpad;
+    int32_t block0;    // first workgroup of this descriptor in its launch
+    int32_t gx;        // scale, abar: workgroups across the columns
+    uint32_t* X;
+    int64_t ldx;
+    int64_t* info;
+    int64_t offset;    // leaf: its first column in the whole factorisation
+    uint32_t* linv;
+    Alg5Scratch sc;
+    uint32_t s_lqnr, c_lqnr;
+    uint32_t* Ab;
+    int64_t ldab;
+};
+
+// Workgroups a descriptor of the kind needs (sets d->gx where used).
+int ldlt_blocks(int kind, LdltDesc* d);
+// One launch of the kind over n descriptors in device memory (block0 set).
+hipError_t launch_ldlt_kind(int kind, const LdltDesc* dev, int n, int total_blocks, hipStream_t s);
+// Residue products whose sum stays below 2^53, at most 64.
+int ldlt_dot_block(uint32_t p);
+
+struct LdltJobSpec {
+    int64_t n;
+    uint32_t p;
+    uint32_t* S;
+    int64_t lds;
+    int64_t* info;
+    void* ws;          // ldlt_workspace_bytes(n, p, lds) bytes, 256-byte aligned
+};
 
 // Host driver.  Returns an FFP_* status; enqueues everything on s.
 // ws: optional device workspace of ldlt_workspace_bytes(n, p, lds) bytes,
 // 256-byte aligned; when null the library's per-stream workspace is used.
 int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hipStream_t s,
              void* ws = nullptr);
+// Several independent factorisations (disjoint S, info and workspaces)
+// enqueued together on s.
+int ldlt_run_multi(const std::vector<LdltJobSpec>& jobs, hipStream_t s);
 size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds);
 
 }  // namespace ffp

@@ -26,8 +26,8 @@ constexpr int NB = kLdltLeaf;   // leaf order and triangular-solve block
 // inverses are then formed in parallel.  The inverse of L is built from its
 // 8 x 8 diagonal blocks up: [[A, 0], [B, C]]^-1 = [[A^-1, 0], [-C^-1 B A^-1,
 // C^-1]] on blocks of 8, 16 and 32.
-__global__ __launch_bounds__(256) void ldlt_leaf_kernel(Fp f, int kb, int nb, uint32_t* S, int64_t lds,
-                                                       int64_t* info, int64_t offset, uint32_t* linv)
+__device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S, int64_t lds, int64_t* info,
+                                               int64_t offset, uint32_t* linv)
 {
     __shared__ uint32_t sm[NB][NB + 1];
     __shared__ uint32_t li[NB][NB + 1];
@@ -143,14 +143,14 @@ __global__ __launch_bounds__(256) void ldlt_leaf_kernel(Fp f, int kb, int nb, ui
 // thread forms a 4 x 4 block of entries in FP64 with delayed reduction
 // (Linv is zero above the diagonal in LDS, so every sum runs over all t).
 constexpr int TR = 64;
-__global__ __launch_bounds__(256) void trsm_inv_kernel(Fp f, int kb, int64_t nrows, int nb, uint32_t* X,
-                                                      int64_t ldx, const uint32_t* linv)
+__device__ __forceinline__ void trsm_inv_body(Fp f, int kb, int64_t nrows, int nb, uint32_t* X, int64_t ldx,
+                                              const uint32_t* linv, int lb)
 {
     __shared__ double sl[NB][NB + 1];
     __shared__ double sx[TR][NB + 1];
     const uint32_t p = f.p;
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * TR;
+    const int64_t r0 = (int64_t)lb * TR;
     for (int e = tid; e < NB * NB; e += 256) {
         const int i = e / NB, j = e % NB;
         sl[i][j] = (i < nb && j <= i) ? (double)linv[i * NB + j] : 0.0;
@@ -196,11 +196,10 @@ __global__ __launch_bounds__(256) void trsm_inv_kernel(Fp f, int kb, int64_t nro
 }
 
 // Per pivot j: non-residue flag, square root of residues, inverse.
-__global__ __launch_bounds__(256) void classify_kernel(Fp f, int n1, const uint32_t* S, int64_t lds,
-                                                      uint32_t z, int32_t* flag, uint32_t* root,
-                                                      uint32_t* dinv)
+__device__ __forceinline__ void classify_body(Fp f, int n1, const uint32_t* S, int64_t lds, uint32_t z,
+                                              int32_t* flag, uint32_t* root, uint32_t* dinv, int lb)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = lb * 256 + (int)threadIdx.x;
     if (j >= n1) return;
     const uint32_t d = S[(int64_t)j * lds + j];
     const bool nr = is_nonresidue(d, f.p, f.pinv);
@@ -215,10 +214,9 @@ __global__ __launch_bounds__(256) void classify_kernel(Fp f, int n1, const uint3
 // extra zero column, used when the number of non-residues is odd).
 //   desc[c] = (j1, s1, j2, s2):  Abar[:, c] = s1 L[:, j1] + s2 L[:, j2]
 // (an index of -1 contributes nothing).
-__global__ __launch_bounds__(1024) void pair_kernel(Fp f, int n1, const uint32_t* S, int64_t lds,
-                                                   const int32_t* flag, const uint32_t* root,
-                                                   int32_t* rank_idx, uint32_t s_lqnr,
-                                                   uint32_t c_lqnr, uint32_t z, ColOp* desc)
+__device__ __forceinline__ void pair_body(Fp f, int n1, const uint32_t* S, int64_t lds, const int32_t* flag,
+                                          const uint32_t* root, int32_t* rank_idx, uint32_t s_lqnr,
+                                          uint32_t c_lqnr, uint32_t z, ColOp* desc)
 {
     __shared__ int32_t part[1024];
     __shared__ int32_t base;
@@ -272,26 +270,25 @@ __global__ __launch_bounds__(1024) void pair_kernel(Fp f, int n1, const uint32_t
 }
 
 // L21 = W D^-1 in place (column j scaled by dinv[j]).
-__global__ __launch_bounds__(256) void scale_cols_kernel(Fp f, int64_t rows, int n1, uint32_t* W,
-                                                        int64_t ldw, const uint32_t* dinv)
+__device__ __forceinline__ void scale_cols_body(Fp f, int64_t rows, int n1, uint32_t* W, int64_t ldw,
+                                                const uint32_t* dinv, int bx, int by, int gy)
 {
-    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int64_t c = (int64_t)bx * 64 + (threadIdx.x & 63);
     if (c >= n1) return;
     const uint32_t s = dinv[c];
-    for (int64_t r = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gridDim.y * 4)
+    for (int64_t r = (int64_t)by * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gy * 4)
         W[r * ldw + c] = mul_m(W[r * ldw + c], s, f.p, f.pinv);
 }
 
 // Abar[:, c] from the column operations (zero beyond ncols, up to kpad).
-__global__ __launch_bounds__(256) void build_abar_kernel(Fp f, int64_t rows, int ncols, int kpad,
-                                                        const uint32_t* L, int64_t ldl,
-                                                        const ColOp* desc, uint32_t* Ab,
-                                                        int64_t ldab)
+__device__ __forceinline__ void build_abar_body(Fp f, int64_t rows, int ncols, int kpad, const uint32_t* L,
+                                                int64_t ldl, const ColOp* desc, uint32_t* Ab, int64_t ldab,
+                                                int bx, int by, int gy)
 {
-    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int64_t c = (int64_t)bx * 64 + (threadIdx.x & 63);
     if (c >= kpad) return;
     ColOp o = c < ncols ? desc[c] : ColOp{-1, 0u, -1, 0u};
-    for (int64_t r = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gridDim.y * 4) {
+    for (int64_t r = (int64_t)by * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gy * 4) {
         uint32_t v = 0;
         if (o.j1 >= 0) v = mul_m(L[r * ldl + o.j1], o.s1, f.p, f.pinv);
         if (o.j2 >= 0) v = add_m(v, mul_m(L[r * ldl + o.j2], o.s2, f.p, f.pinv), f.p);
@@ -299,75 +296,115 @@ __global__ __launch_bounds__(256) void build_abar_kernel(Fp f, int64_t rows, int
     }
 }
 
-__global__ void zero_i64_kernel(int64_t* p) { if (threadIdx.x == 0) *p = 0; }
+// ---- launches over descriptor arrays ---------------------------------------
 
-inline dim3 grid2(int64_t rows, int64_t cols)
+// Descriptor owning workgroup b (descriptors sorted by block0; uniform).
+__device__ inline int desc_of(const LdltDesc* D, int n, int b)
 {
-    int64_t gx = (cols + 63) / 64, gy = (rows + 3) / 4;
-    if (gy > 16384) gy = 16384;
-    return dim3((unsigned)(gx < 1 ? 1 : gx), (unsigned)(gy < 1 ? 1 : gy));
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (D[mid].block0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int kRowBands = 256;   // scale, abar: at most this many bands of 4 rows per descriptor
+
+__host__ __device__ inline int row_bands(int64_t rows)
+{
+    const int64_t g = (rows + 3) / 4;
+    return (int)(g < 1 ? 1 : (g > kRowBands ? kRowBands : g));
+}
+
+__global__ __launch_bounds__(256) void zero_multi(const LdltDesc* D, int n)
+{
+    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
+    if (threadIdx.x == 0) *d.info = 0;
+}
+
+__global__ __launch_bounds__(256) void leaf_multi(const LdltDesc* D, int n)
+{
+    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
+    ldlt_leaf_body(d.f, d.kb, d.nb, d.X, d.ldx, d.info, d.offset, d.linv);
+}
+
+__global__ __launch_bounds__(256) void trsm_multi(const LdltDesc* D, int n)
+{
+    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
+    trsm_inv_body(d.f, d.kb, d.rows, d.nb, d.X, d.ldx, d.linv, blockIdx.x - d.block0);
+}
+
+__global__ __launch_bounds__(256) void classify_multi(const LdltDesc* D, int n)
+{
+    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
+    classify_body(d.f, d.nb, d.X, d.ldx, d.s_lqnr, d.sc.flag, d.sc.root, d.sc.dinv, blockIdx.x - d.block0);
+}
+
+__global__ __launch_bounds__(1024) void pair_multi(const LdltDesc* D, int n)
+{
+    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
+    pair_body(d.f, d.nb, d.X, d.ldx, d.sc.flag, d.sc.root, d.sc.rank_idx, d.s_lqnr, d.c_lqnr, d.s_lqnr,
+              d.sc.desc);
+}
+
+__global__ __launch_bounds__(256) void scale_multi(const LdltDesc* D, int n)
+{
+    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
+    const int lb = blockIdx.x - d.block0;
+    scale_cols_body(d.f, d.rows, d.nb, d.X, d.ldx, d.sc.dinv, lb % d.gx, lb / d.gx, row_bands(d.rows));
+}
+
+__global__ __launch_bounds__(256) void abar_multi(const LdltDesc* D, int n)
+{
+    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
+    const int lb = blockIdx.x - d.block0;
+    build_abar_body(d.f, d.rows, d.ncols, d.kpad, d.X, d.ldx, d.sc.desc, d.Ab, d.ldab, lb % d.gx, lb / d.gx,
+                    row_bands(d.rows));
 }
 
 }  // namespace
 
-hipError_t launch_zero_i64(int64_t* p, hipStream_t s)
-{
-    hipLaunchKernelGGL(zero_i64_kernel, dim3(1), dim3(64), 0, s, p);
-    return hipGetLastError();
-}
-
-// Terms of a dot product of residues whose sum stays below 2^53.
-static int dot_block(uint32_t p)
+int ldlt_dot_block(uint32_t p)
 {
     const double pm = (double)(p - 1);
     const double kb = floor(9007199254740992.0 / (pm * pm + 1.0)) - 1.0;
     return kb > 64.0 ? 64 : (int)kb;
 }
 
-hipError_t launch_ldlt_leaf(const Fp& f, int nb, uint32_t* S, int64_t lds, int64_t* info,
-                            int64_t offset, uint32_t* linv, hipStream_t s)
+int ldlt_blocks(int kind, LdltDesc* d)
 {
-    hipLaunchKernelGGL(ldlt_leaf_kernel, dim3(1), dim3(256), 0, s, f, dot_block(f.p), nb, S, lds, info,
-                       offset, linv);
-    return hipGetLastError();
+    switch (kind) {
+    case LK_ZERO:
+    case LK_LEAF:
+    case LK_PAIR: return 1;
+    case LK_TRSM: return (int)((d->rows + TR - 1) / TR);
+    case LK_CLASSIFY: return (d->nb + 255) / 256;
+    case LK_SCALE:
+        d->gx = (d->nb + 63) / 64;
+        return d->rows > 0 ? d->gx * row_bands(d->rows) : 0;
+    case LK_ABAR:
+        d->gx = (d->kpad + 63) / 64;
+        return d->rows > 0 ? d->gx * row_bands(d->rows) : 0;
+    default: return 0;
+    }
 }
 
-hipError_t launch_trsm_leaf(const Fp& f, int64_t nrows, int nb, uint32_t* X, int64_t ldx,
-                            const uint32_t* linv, hipStream_t s)
+hipError_t launch_ldlt_kind(int kind, const LdltDesc* dev, int n, int total_blocks, hipStream_t s)
 {
-    if (nrows <= 0 || nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(trsm_inv_kernel, dim3((unsigned)((nrows + TR - 1) / TR)), dim3(256), 0, s, f,
-                       dot_block(f.p), nrows, nb, X, ldx, linv);
-    return hipGetLastError();
-}
-
-hipError_t launch_alg5(const Fp& f, int n1, const uint32_t* S11, int64_t lds, uint32_t s_lqnr,
-                       uint32_t c_lqnr, uint32_t z, Alg5Scratch sc, hipStream_t s)
-{
-    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, f, n1,
-                       S11, lds, z, sc.flag, sc.root, sc.dinv);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pair_kernel, dim3(1), dim3(1024), 0, s, f, n1, S11, lds, sc.flag, sc.root,
-                       sc.rank_idx, s_lqnr, c_lqnr, z, sc.desc);
-    return hipGetLastError();
-}
-
-hipError_t launch_scale_cols(const Fp& f, int64_t rows, int n1, uint32_t* W, int64_t ldw,
-                             const uint32_t* dinv, hipStream_t s)
-{
-    if (rows <= 0 || n1 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scale_cols_kernel, grid2(rows, n1), dim3(256), 0, s, f, rows, n1, W, ldw, dinv);
-    return hipGetLastError();
-}
-
-hipError_t launch_build_abar(const Fp& f, int64_t rows, int ncols, int kpad, const uint32_t* L,
-                             int64_t ldl, const ColOp* desc, uint32_t* Ab, int64_t ldab,
-                             hipStream_t s)
-{
-    if (rows <= 0 || kpad <= 0) return hipSuccess;
-    hipLaunchKernelGGL(build_abar_kernel, grid2(rows, kpad), dim3(256), 0, s, f, rows, ncols, kpad, L,
-                       ldl, desc, Ab, ldab);
+    if (n <= 0 || total_blocks <= 0) return hipSuccess;
+    const dim3 g((unsigned)total_blocks);
+    switch (kind) {
+    case LK_ZERO: hipLaunchKernelGGL(zero_multi, g, dim3(256), 0, s, dev, n); break;
+    case LK_LEAF: hipLaunchKernelGGL(leaf_multi, g, dim3(256), 0, s, dev, n); break;
+    case LK_TRSM: hipLaunchKernelGGL(trsm_multi, g, dim3(256), 0, s, dev, n); break;
+    case LK_CLASSIFY: hipLaunchKernelGGL(classify_multi, g, dim3(256), 0, s, dev, n); break;
+    case LK_PAIR: hipLaunchKernelGGL(pair_multi, g, dim3(1024), 0, s, dev, n); break;
+    case LK_SCALE: hipLaunchKernelGGL(scale_multi, g, dim3(256), 0, s, dev, n); break;
+    case LK_ABAR: hipLaunchKernelGGL(abar_multi, g, dim3(256), 0, s, dev, n); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

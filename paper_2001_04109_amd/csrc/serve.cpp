@@ -33,7 +33,8 @@ size_t result_bytes(const ffp_request& r)
     return (size_t)rup((int64_t)b, 256);
 }
 
-constexpr int kMaxBatch = 128;
+constexpr int kMaxBatch = 128;      // A*A^T requests per unit
+constexpr int kMaxLdltBatch = 32;   // LDL^T requests per unit
 
 // Workspace the request needs while it runs (the same figure the batched
 // launch and the LDL^T driver use for it).
@@ -80,7 +81,7 @@ public:
     }
     void bind_thread() override { (void)hipSetDevice(device_); }
     char* arena() override { return arena_; }
-    int launch_syrk(std::vector<ServeReq*>& batch, int s, Unit* u) override
+    int launch_syrk(std::vector<ServeReq*>& batch, int s, UnitPart* u) override
     {
         std::vector<ffp_job> jobs;
         std::vector<char*> ws;
@@ -104,31 +105,36 @@ public:
         if (st != FFP_OK) return st;
         return record(s, u);
     }
-    int launch_ldlt(ServeReq* r, int s, Unit* u) override
+    int launch_ldlt(std::vector<ServeReq*>& batch, int s, UnitPart* u) override
     {
-        const int64_t n = r->rq.n, ld = result_ld(r->rq);
-        uint32_t* S = (uint32_t*)(arena_ + r->off);
-        int64_t* info = (int64_t*)(arena_ + r->off + rup(n * ld * 4, 256));
-        if (n > 0 && hipMemcpy2DAsync(S, ld * 4, r->rq.A, r->rq.lda * 4, n * 4, n,
-                                      hipMemcpyDeviceToDevice, streams_[s]) != hipSuccess)
-            return FFP_EDEVICE;
-        int st = ldlt_run(n, r->rq.p, S, ld, info, streams_[s], arena_ + r->ws_off);
+        std::vector<LdltJobSpec> jobs;
+        jobs.reserve(batch.size());
+        for (ServeReq* r : batch) {
+            const int64_t n = r->rq.n, ld = result_ld(r->rq);
+            uint32_t* S = (uint32_t*)(arena_ + r->off);
+            int64_t* info = (int64_t*)(arena_ + r->off + rup(n * ld * 4, 256));
+            if (n > 0 && hipMemcpy2DAsync(S, ld * 4, r->rq.A, r->rq.lda * 4, n * 4, n,
+                                          hipMemcpyDeviceToDevice, streams_[s]) != hipSuccess)
+                return FFP_EDEVICE;
+            jobs.push_back(LdltJobSpec{n, r->rq.p, S, ld, info, arena_ + r->ws_off});
+        }
+        int st = ldlt_run_multi(jobs, streams_[s]);
         if (st != FFP_OK) return st;
         return record(s, u);
     }
-    bool done(Unit* u) override
+    bool done(UnitPart* u) override
     {
         return hipEventQuery((hipEvent_t)u->event) == hipSuccess;
     }
     void sync_stream(int s) override { (void)hipStreamSynchronize(streams_[s]); }
-    void release(Unit* u) override
+    void release(UnitPart* u) override
     {
         if (u->event) (void)hipEventDestroy((hipEvent_t)u->event);
         u->event = nullptr;
     }
 
 private:
-    int record(int s, Unit* u)
+    int record(int s, UnitPart* u)
     {
         hipEvent_t e;
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return FFP_EDEVICE;
@@ -151,21 +157,23 @@ public:
         return FFP_OK;
     }
     char* arena() override { return nullptr; }
-    int launch_syrk(std::vector<ServeReq*>& batch, int s, Unit* u) override
+    int launch_syrk(std::vector<ServeReq*>& batch, int s, UnitPart* u) override
     {
         double ops = 0;
         for (ServeReq* r : batch) ops += (double)r->rq.n * r->rq.n * r->rq.k;
         return finish(s, u, ops);
     }
-    int launch_ldlt(ServeReq* r, int s, Unit* u) override
+    int launch_ldlt(std::vector<ServeReq*>& batch, int s, UnitPart* u) override
     {
-        return finish(s, u, (double)r->rq.n * r->rq.n * r->rq.n / 3.0);
+        double ops = 0;
+        for (ServeReq* r : batch) ops += (double)r->rq.n * r->rq.n * r->rq.n / 3.0;
+        return finish(s, u, ops);
     }
-    bool done(Unit* u) override { return now_s() >= u->sim_done; }
-    void release(Unit*) override {}
+    bool done(UnitPart* u) override { return now_s() >= u->sim_done; }
+    void release(UnitPart*) override {}
 
 private:
-    int finish(int s, Unit* u, double ops)
+    int finish(int s, UnitPart* u, double ops)
     {
         const double start = std::max(now_s(), free_at_[s]);
         u->sim_done = start + launch_ * 1e-6 + ops * ns_ * 1e-9;
@@ -239,6 +247,28 @@ void Server::arena_free(size_t off, size_t bytes)
         free_[i - 1].second += free_[i].second;
         free_.erase(free_.begin() + (long)i);
     }
+}
+
+// Marks the requests of a part done (with a failure status unless FFP_OK)
+// and returns their workspace to the arena.  Called with the lock held.
+void Server::finish_part(UnitPart& part, int status)
+{
+    const double t = now_s();
+    for (uint64_t tk : part.tickets) {
+        ServeReq& q = reqs_[tk - 1];
+        if (status != FFP_OK) q.status = status;
+        q.state = FFP_STATE_DONE;
+        q.t_done = t;
+        --inflight_;
+        if (q.ws_bytes) {
+            arena_free(q.ws_off, q.ws_bytes);
+            used_ -= q.ws_bytes;
+        }
+        done_q_.push_back(tk);
+    }
+    part.finished = true;
+    dev_->release(&part);
+    cv_done_.notify_all();
 }
 
 int Server::submit(const ffp_request* r, uint64_t* ticket)
@@ -381,24 +411,21 @@ void Server::loop()
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
         bool progress = false;
-        // completions
+        // completions, part by part
         for (size_t i = 0; i < running_.size();) {
             Unit& u = running_[i];
-            if (dev_->done(&u)) {
-                const double t = now_s();
-                for (uint64_t tk : u.tickets) {
-                    ServeReq& q = reqs_[tk - 1];
-                    q.state = FFP_STATE_DONE;
-                    q.t_done = t;
-                    --inflight_;
-                    if (q.ws_bytes) {
-                        arena_free(q.ws_off, q.ws_bytes);
-                        used_ -= q.ws_bytes;
-                    }
-                    done_q_.push_back(tk);
+            bool all = true;
+            for (UnitPart& part : u.part) {
+                if (part.tickets.empty() || part.finished) continue;
+                if (dev_->done(&part)) {
+                    finish_part(part, FFP_OK);
+                    progress = true;
+                } else {
+                    all = false;
                 }
+            }
+            if (all) {
                 stream_busy_[u.stream] = 0;
-                dev_->release(&u);
                 running_.erase(running_.begin() + (long)i);
                 progress = true;
             } else {
@@ -409,11 +436,13 @@ void Server::loop()
         // admission and launch, one unit per free stream
         for (int s = 0; s < nstreams_ && !queue_.empty(); ++s) {
             if (stream_busy_[s]) continue;
-            std::vector<ServeReq*> batch;
-            ServeReq* ldlt = nullptr;
-            while (!queue_.empty() && (int)batch.size() < kMaxBatch && !ldlt) {
+            // a unit: the requests at the head of the queue, in arrival order,
+            // while they fit (A*A^T and LDL^T requests go to their own batch)
+            std::vector<ServeReq*> batch[2];
+            while (!queue_.empty()) {
                 ServeReq& q = reqs_[queue_.front() - 1];
-                if (q.rq.kind == FFP_REQ_LDLT && !batch.empty()) break;   // arrival order
+                const int kind = q.rq.kind == FFP_REQ_LDLT ? 1 : 0;
+                if ((int)batch[kind].size() >= (kind ? kMaxLdltBatch : kMaxBatch)) break;
                 const size_t need = q.bytes + q.ws_bytes;
                 size_t off = 0, ws_off = 0;
                 if (inflight_ >= max_inflight_ || used_ + need > budget_ || !arena_alloc(q.bytes, &off))
@@ -431,51 +460,35 @@ void Server::loop()
                 ++inflight_;
                 peak_inflight_ = std::max<int64_t>(peak_inflight_, inflight_);
                 queue_.pop_front();
-                if (q.rq.kind == FFP_REQ_LDLT) ldlt = &q;
-                else batch.push_back(&q);
+                batch[kind].push_back(&q);
             }
-            if (batch.empty() && !ldlt) break;
-            Unit u;
+            if (batch[0].empty() && batch[1].empty()) break;
+            running_.emplace_back();
+            Unit& u = running_.back();
             u.stream = s;
             u.t_launch = now_s();
-            if (ldlt) {
-                u.tickets.push_back(ldlt->ticket);
-            } else {
-                for (ServeReq* q : batch) u.tickets.push_back(q->ticket);
-                batched_jobs_ += (int64_t)batch.size();
-                max_batch_ = std::max<int64_t>(max_batch_, (int64_t)batch.size());
+            for (int k = 0; k < 2; ++k) {
+                for (ServeReq* q : batch[k]) u.part[k].tickets.push_back(q->ticket);
+                batched_jobs_ += (int64_t)batch[k].size();
+                max_batch_ = std::max<int64_t>(max_batch_, (int64_t)batch[k].size());
             }
-            if (!running_.empty()) ++overlap_units_;
+            if (running_.size() > 1) ++overlap_units_;
             ++units_;
             stream_busy_[s] = 1;
             // Enqueue without the lock so that submitters are not held up by
             // plan building; the admitted entries are not touched by other
-            // threads while RUNNING (reqs_ is a deque: addresses are stable).
+            // threads while RUNNING (reqs_ is a deque: addresses are stable),
+            // and running_ only changes on this thread.
             launching_ = true;
             lk.unlock();
-            const int st = ldlt ? dev_->launch_ldlt(ldlt, s, &u) : dev_->launch_syrk(batch, s, &u);
-            if (st != FFP_OK) dev_->sync_stream(s);   // nothing of the unit may still run
+            int st[2] = {FFP_OK, FFP_OK};
+            if (!batch[0].empty()) st[0] = dev_->launch_syrk(batch[0], s, &u.part[0]);
+            if (!batch[1].empty()) st[1] = dev_->launch_ldlt(batch[1], s, &u.part[1]);
+            if (st[0] != FFP_OK || st[1] != FFP_OK) dev_->sync_stream(s);   // nothing may still run
             lk.lock();
             launching_ = false;
-            if (st != FFP_OK) {
-                for (uint64_t tk : u.tickets) {
-                    ServeReq& q = reqs_[tk - 1];
-                    q.status = st;
-                    q.state = FFP_STATE_DONE;
-                    q.t_done = now_s();
-                    --inflight_;
-                    if (q.ws_bytes) {
-                        arena_free(q.ws_off, q.ws_bytes);
-                        used_ -= q.ws_bytes;
-                    }
-                    done_q_.push_back(tk);
-                }
-                dev_->release(&u);
-                stream_busy_[s] = 0;
-                cv_done_.notify_all();
-                continue;
-            }
-            running_.push_back(u);
+            for (int k = 0; k < 2; ++k)
+                if (!batch[k].empty() && st[k] != FFP_OK) finish_part(u.part[k], st[k]);
             progress = true;
         }
         if (stop_ && running_.empty()) break;

@@ -28,13 +28,21 @@ struct ServeReq {
     bool released = false;
 };
 
-// One launched unit of work: a batch of SYRK jobs or one LDL^T, on a stream.
-struct Unit {
-    int stream = -1;
+// One batch of a unit: its requests complete together.
+struct UnitPart {
     std::vector<uint64_t> tickets;
-    double t_launch = 0;
     double sim_done = 0;     // simulated device: completion time
     void* event = nullptr;   // real device: hipEvent_t
+    bool finished = false;
+};
+
+// One launched unit of work on a stream: the admitted A*A^T requests as one
+// batched launch (part 0), then the admitted LDL^T requests as one
+// multi-factorisation (part 1).
+struct Unit {
+    int stream = -1;
+    double t_launch = 0;
+    UnitPart part[2];
 };
 
 class DeviceIface {
@@ -43,12 +51,13 @@ public:
     virtual int init(size_t arena_bytes, int nstreams) = 0;
     virtual void bind_thread() {}   // called first on the scheduler thread
     virtual char* arena() = 0;
-    // Enqueue a batch of SYRK requests (results at arena + off) on stream s.
-    virtual int launch_syrk(std::vector<ServeReq*>& batch, int s, Unit* u) = 0;
-    virtual int launch_ldlt(ServeReq* r, int s, Unit* u) = 0;
-    virtual bool done(Unit* u) = 0;
+    // Enqueue a batch of SYRK (or of LDLT) requests, results at arena + off,
+    // on stream s.
+    virtual int launch_syrk(std::vector<ServeReq*>& batch, int s, UnitPart* u) = 0;
+    virtual int launch_ldlt(std::vector<ServeReq*>& batch, int s, UnitPart* u) = 0;
+    virtual bool done(UnitPart* u) = 0;
     virtual void sync_stream(int) {}
-    virtual void release(Unit* u) = 0;
+    virtual void release(UnitPart* u) = 0;
 };
 
 DeviceIface* make_hip_device();
@@ -63,6 +72,7 @@ public:
     int status(uint64_t ticket, ffp_result* out);
     int release(uint64_t ticket);
     int drain(double timeout_s);
+    void finish_part(UnitPart& part, int status);
     int poll(uint64_t* tickets, int max, double timeout_s, int* count);
     int fetch(uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst, void* stream);
     int stats(ffp_serve_stats* out);

@@ -49,6 +49,11 @@ class ffp_job(ctypes.Structure):
                 ("ldc", ctypes.c_int64)]
 
 
+class ffp_ldlt_job(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_uint32), ("S", ctypes.c_void_p),
+                ("lds", ctypes.c_int64), ("info", ctypes.c_void_p)]
+
+
 class ffp_request(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
                 ("p", ctypes.c_uint32), ("alpha", ctypes.c_uint32), ("A", ctypes.c_void_p),
@@ -104,6 +109,7 @@ def lib():
             "ffp_ldlt_workspace_bytes": (ctypes.c_size_t, [i64, u32]),
             "ffp_plan_levels": (c_int, [i64, i64, u32, c_int, i64, i64, u32, u32, c_uint, P,
                                         ctypes.c_size_t]),
+            "fldlt_modp_batched": (c_int, [c_int, P, P]),
             "ffp_server_create": (c_int, [ctypes.c_size_t, c_int, c_int, P]),
             "ffp_server_create_simulated": (c_int, [ctypes.c_size_t, c_int, c_int, ctypes.c_double,
                                                     ctypes.c_double, P]),
@@ -296,6 +302,20 @@ def gemm(A, B, p: int, alpha: int = 1, beta: int = 0, C=None, stream=None):
         C = torch.zeros((m, n), dtype=torch.int32, device=A.device)
     fgemm_modp(m, n, k, p, A, A.stride(0), B, B.stride(0), alpha, beta, C, C.stride(0), stream)
     return C
+
+
+def ldlt_batched(mats, p_list, stream=None):
+    """fldlt_modp_batched over device int32 tensors (in place); returns the
+    device int64 info tensor (one entry per job)."""
+    import torch
+    info = torch.zeros(len(mats), dtype=torch.int64, device=mats[0].device)
+    arr = (ffp_ldlt_job * len(mats))()
+    for j, (S, p) in enumerate(zip(mats, p_list)):
+        arr[j] = ffp_ldlt_job(n=S.shape[0], p=p, S=_ptr(S), lds=S.stride(0),
+                              info=info.data_ptr() + 8 * j)
+    _check(lib().fldlt_modp_batched(len(mats), ctypes.cast(arr, ctypes.c_void_p), _stream(stream)),
+           "fldlt_modp_batched")
+    return info
 
 
 def ldlt(S, p: int, stream=None):

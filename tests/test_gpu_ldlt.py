@@ -108,3 +108,33 @@ def test_ldlt_4096_sampled_reconstruction():
         # (L D L^T)_ij = sum_l L_il D_l L_jl, exact with Python ints
         v = sum(int(L[i, l]) * int(D[l]) * int(L[j, l]) for l in range(m)) % p
         assert v == int(S[i, j]), (i, j)
+
+
+def test_ldlt_batched_equals_alone_and_oracle():
+    """fldlt_modp_batched: jobs of different order and prime (int8, limb and
+    FP64 Schur updates), one with a zero pivot, each bit-identical to the
+    job alone and to the oracle."""
+    import torch
+    specs = [(1, 65537), (64, 65537), (65, 131071), (130, 251), (300, 65521), (700, 65537),
+             (256, 65537)]
+    mats = []
+    for i, (n, p) in enumerate(specs):
+        if i == len(specs) - 1:
+            _, _, S = constructed(n, p, seed=5, zero_at=100)
+        else:
+            S = inputs.symmetric(900 + i, n, p)
+        mats.append(S)
+    dev = [to_dev_u32(S) for S in mats]
+    info = ffp.ldlt_batched(dev, [p for _, p in specs])
+    torch.cuda.synchronize()
+    infos = info.cpu().numpy()
+    for (n, p), S, Sd, inf in zip(specs, mats, dev, infos):
+        alone, ainfo = gpu_ldlt(S, p)
+        ref, rinfo = oracle.ldlt_packed(S, p)
+        assert inf == ainfo == rinfo, (n, p)
+        if inf == 0:
+            low = np.tril(np.ones((n, n), dtype=bool))
+            out = from_dev_u32(Sd)
+            assert np.array_equal(out[low], alone[low])
+            assert np.array_equal(out[low], ref[low])
+    assert infos[-1] == 101
