@@ -156,9 +156,12 @@ def run_workload(name, steps, warmup, check=True):
 
 def batched_vs_plain(steps=3, njobs=1024):
     """1024 independent jobs (n ~ U[32,1024], k ~ U[n/2,2n], p ~ U{251, 65537,
-    131071}, seed 3): one fsyrk_modp_batched call against the same jobs as a
-    loop of per-call fsyrk_modp on one stream.  Results of both are compared
-    with each other bit for bit, and a sample with the oracle."""
+    131071}, seed 3): one fsyrk_modp_batched call, and the same batch recorded
+    once as a HIP graph and replayed, against the same jobs as a loop of
+    per-call fsyrk_modp on one stream.  The autotuner first tunes each shape
+    class of the mix (untimed); all three forms then follow its table.  The
+    graph replays write the batched outputs last, which are compared with the
+    per-call results bit for bit, and a sample with the oracle."""
     import torch
     import oracle
     from paper_2001_04109_amd import ffp, inputs
@@ -176,6 +179,22 @@ def batched_vs_plain(steps=3, njobs=1024):
     torch.cuda.synchronize()
     eff = float(sum(n * n * k for (n, k, _) in shapes))
 
+    # autotuner: one tuning run per shape class of the mix (base path,
+    # ceil(log2 n), ceil(log2 k)); plain and batched calls then follow it
+    ffp.ffp_tune_clear()
+    t0 = time.perf_counter()
+    seen = {}
+    for n, k, p in shapes:
+        key = (p <= 251, int(np.ceil(np.log2(n))), int(np.ceil(np.log2(k))))
+        if key not in seen:
+            try:
+                seen[key] = ffp.ffp_autotune(n, k, p)
+            except ffp.FfpError as e:
+                raise SystemExit(f"bench: autotune of n={n} k={k} p={p} failed: {e}")
+    tune_s = time.perf_counter() - t0
+    depths = sorted({r["depth"] for r in seen.values()})
+    tiles = sorted({r["tile"] for r in seen.values()})
+
     def plain():
         for (n, k, p), Ad, Cd in zip(shapes, devA, devC2):
             ffp.syrk(Ad, p, C=Cd)
@@ -183,8 +202,17 @@ def batched_vs_plain(steps=3, njobs=1024):
     def batched():
         ffp.fsyrk_modp_batched(jobs)
 
+    # the same batch recorded once as a HIP graph, replayed per step
+    rec = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    graph = ffp.Graph.syrk_batched(jobs, stream=rec, keep=(devA, devC))
+    record_ms = (time.perf_counter() - t0) * 1e3
+
+    def replay():
+        graph.launch()
+
     out = {}
-    for name, fn in (("plain", plain), ("batched", batched)):
+    for name, fn in (("plain", plain), ("batched", batched), ("graph", replay)):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -207,8 +235,15 @@ def batched_vs_plain(steps=3, njobs=1024):
         if not np.array_equal(got, oracle.syrk_entries(A, p, lo, hi)):
             raise SystemExit(f"bench: batched job {j} differs from the oracle")
     out["speedup"] = round(out["plain"]["ms"] / out["batched"]["ms"], 3)
+    out["graph_speedup"] = round(out["plain"]["ms"] / out["graph"]["ms"], 3)
+    out["graph_record_ms"] = round(record_ms, 1)
+    out["graph_nodes"] = graph.nodes
     out["jobs"] = njobs
     out["eff_ops"] = eff
+    out["autotune"] = {"shape_classes": len(seen), "seconds": round(tune_s, 2), "depths": depths,
+                       "tiles": tiles}
+    graph.close()
+    ffp.ffp_tune_clear()
     del devA, devC, devC2, jobs
     torch.cuda.empty_cache()
     return out

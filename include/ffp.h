@@ -173,6 +173,78 @@ typedef struct ffp_job {
  * enqueued. */
 int fsyrk_modp_batched(int njobs, const ffp_job* jobs, unsigned flags, void* stream);
 
+/* ---- autotuner ------------------------------------------------------------ */
+/* fsyrk_modp picks, for every call that does not force a depth, the
+ * recursion depth of Algorithm 2 (its cut-off to the base products), the
+ * placements (those of Tables 3 and 4, or the wide ones that give sibling
+ * products memory of their own) and the product tile edge from a
+ * process-wide tuning table, and falls back to a built-in rule for shapes
+ * the table does not hold.  Entries cover a shape class: the base path
+ * (FP64, int8, int8 limbs, from p and a_dtype), ceil(log2 n), ceil(log2 k),
+ * the form ((alpha, beta) = (1, 0) or not) and FFP_LOW_MEMORY.  Batched
+ * jobs consult the same table.  The LDL^T driver's Schur updates use the
+ * built-in rule. */
+typedef struct ffp_tune_result {
+    int32_t depth;       /* levels of Algorithm 2 */
+    int32_t tile;        /* product tile edge (0: the launch rule) */
+    int32_t wide;        /* 1: wide placements, 0: those of Tables 3 and 4 */
+    int32_t candidates;  /* configurations timed */
+    double ms;           /* time of one call with the choice (at tuning) */
+    double rule_ms;      /* time of one call with the built-in rule */
+} ffp_tune_result;
+
+/* Times fsyrk_modp on synthetic operands of shape n x k (storage a_dtype,
+ * form alpha/beta, flags without FFP_DEPTH) for each candidate depth, tile
+ * edge and placement, stores the fastest in the table for the shape class
+ * and returns it.  Allocates its operands, runs on `stream` and waits for
+ * it (a tuning call, not for the hot path).
+ * Errors: FFP_EINVAL (n or k <= 0, FFP_DEPTH given), as fsyrk_modp
+ * otherwise. */
+int ffp_autotune(int64_t n, int64_t k, uint32_t p, int a_dtype, uint32_t alpha, uint32_t beta, unsigned flags,
+                 void* stream, ffp_tune_result* out);
+/* The depth, tile and placement a call of this shape would use now (host
+ * only).  Returns 1 if they come from the table, 0 for the built-in rule,
+ * or a negative FFP_* status. */
+int ffp_tune_lookup(int64_t n, int64_t k, uint32_t p, int a_dtype, uint32_t alpha, uint32_t beta, unsigned flags,
+                    ffp_tune_result* out);
+/* Text form of the table (one shape class per line).  ffp_tune_load adds
+ * the entries of a file written by ffp_tune_save and returns their number;
+ * a malformed file changes nothing and gives FFP_EINVAL. */
+int ffp_tune_save(const char* path);
+int ffp_tune_load(const char* path);
+void ffp_tune_clear(void);
+int ffp_tune_entries(void);
+
+/* ---- batched calls as HIP graphs ----------------------------------------- */
+/* A batch recorded once and replayed: the host work of a batched call
+ * (schedules of Algorithm 2 or of the LDL^T recursion, level grouping, task
+ * tables) is done once, and each replay is one hipGraphLaunch of the
+ * recorded kernels and table copies.  The graph owns the workspace and the
+ * table buffers of the batch (ffp_graph_device_bytes), allocated before the
+ * capture begins; nothing is allocated during the capture or a replay.
+ *
+ * Recording enqueues nothing: `stream` (not the null stream) is captured
+ * and only serves to record.  A replay reads the jobs' operands at the
+ * recorded addresses and writes the recorded outputs, so the caller keeps
+ * those buffers alive and fills the inputs before each replay (an LDL^T
+ * replay factors S in place again).  Replays of one graph share its
+ * workspace and must not overlap: enqueue them on one stream, or order them
+ * with events.  Results of every replay are bit-identical to the eager
+ * batched call on the same inputs.
+ * Errors: as fsyrk_modp_batched / fldlt_modp_batched; FFP_EINVAL for a null
+ * stream or out pointer; FFP_EDEVICE if the capture or instantiation fails. */
+typedef struct ffp_graph_s* ffp_graph;
+int ffp_graph_syrk_batched(int njobs, const ffp_job* jobs, unsigned flags, void* stream, ffp_graph* out);
+int ffp_graph_ldlt_batched(int njobs, const ffp_ldlt_job* jobs, void* stream, ffp_graph* out);
+/* Enqueues one replay on stream (any stream of the recording device). */
+int ffp_graph_launch(ffp_graph g, void* stream);
+/* Device memory the graph owns (workspace and tables). */
+size_t ffp_graph_device_bytes(ffp_graph g);
+/* Nodes of the recorded graph (kernels and copies); 0 for an empty batch. */
+size_t ffp_graph_nodes(ffp_graph g);
+/* Frees the graph and its buffers; no replay may still be pending. */
+void ffp_graph_destroy(ffp_graph g);
+
 /* ---- request loop: continuous batching ---------------------------------- */
 /* A server owns a pool of HIP streams (default priority) and one device
  * arena of hbm_budget bytes that holds every result and every running job's
@@ -250,6 +322,10 @@ const char* ffp_strerror(int status);
 
 /* Library version string. */
 const char* ffp_version(void);
+
+/* The HIP call behind the calling thread's most recent FFP_ENOMEM or
+ * FFP_EDEVICE from the library, with its HIP error name ("" if none). */
+const char* ffp_last_error_detail(void);
 
 #ifdef __cplusplus
 }

@@ -245,6 +245,35 @@ __global__ __launch_bounds__(256) void copy_u32_kernel(int64_t rows, int64_t col
     }
 }
 
+// Pseudo-random residues (splitmix64 of the element index and a seed, mod
+// p) in the storage of the operand: uint32 in [0,p), centred int8, or two
+// int8 limb planes (256 hi + lo); for the autotuner's synthetic operands.
+__global__ __launch_bounds__(256) void fill_residues_kernel(int64_t rows, int64_t cols, void* dst, int64_t ld,
+                                                           int64_t plane, int dtype, uint32_t p, uint64_t seed)
+{
+    const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (j >= cols) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < rows; i += (int64_t)gridDim.y * 4) {
+        uint64_t z = seed + (uint64_t)(i * cols + j) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const uint32_t r = (uint32_t)(z % p);
+        if (dtype == 0) {
+            ((uint32_t*)dst)[i * ld + j] = r;
+            continue;
+        }
+        const int32_t x = r > (p - 1) / 2 ? (int32_t)r - (int32_t)p : (int32_t)r;
+        if (dtype == 1) {
+            ((int8_t*)dst)[i * ld + j] = (int8_t)x;
+        } else {
+            const int32_t lo = ((x + 128) & 255) - 128;
+            ((int8_t*)dst)[i * ld + j] = (int8_t)((x - lo) >> 8);
+            ((int8_t*)dst)[plane + i * ld + j] = (int8_t)lo;
+        }
+    }
+}
+
 inline dim3 grid2d(int64_t rows, int64_t cols)
 {
     int64_t gx = (cols + 63) / 64;
@@ -375,6 +404,15 @@ hipError_t launch_copy_u32(int64_t rows, int64_t cols, const uint32_t* src, int6
     if (rows <= 0 || cols <= 0) return hipSuccess;
     hipLaunchKernelGGL(copy_u32_kernel, grid2d(rows, cols), dim3(256), 0, s, rows, cols, src, lds, dst,
                        ldd, lower_only);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_residues(int64_t rows, int64_t cols, void* dst, int64_t ld, int64_t plane, int dtype,
+                                uint32_t p, uint64_t seed, hipStream_t s)
+{
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_residues_kernel, grid2d(rows, cols), dim3(256), 0, s, rows, cols, dst, ld, plane,
+                       dtype, p, seed);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Batched form of fsyrk_modp: many independent jobs of uneven n, k and p.
 //
-// Every job gets its own schedule (Algorithm 2 at the tuned depth).  All
+// Every job gets its own schedule (Algorithm 2 at the depth of the tuning
+// table, or of the built-in rule).  All
 // jobs' operations go through the level scheduler as one program: an
 // operation's level only depends on earlier operations of its own job, and
 // the products of one class (and the packs) of all jobs on one level run
@@ -32,7 +33,8 @@ int64_t job_workspace_bytes(const ffp_job& jb, unsigned flags)
     return rup(pl.ws_bytes, 256);
 }
 
-int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s, char* const* job_ws)
+int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s, char* const* job_ws,
+                const unsigned* job_flags)
 {
     if (njobs < 0 || (njobs > 0 && jobs == nullptr)) return FFP_EINVAL;
     std::vector<Plan> plans(njobs);
@@ -43,7 +45,7 @@ int batched_run(int njobs, const ffp_job* jobs, unsigned flags, hipStream_t s, c
         const ffp_job& jb = jobs[j];
         PlanRequest rq;
         int st = make_syrk_request(jb.n, jb.k, jb.p, jb.A, jb.lda, jb.a_dtype, jb.alpha, jb.beta, jb.C,
-                                   jb.ldc, flags, &rq);
+                                   jb.ldc, job_flags ? job_flags[j] : flags, &rq);
         if (st != FFP_OK) return st;
         if (jb.n == 0) continue;
         st = build_syrk_plan(rq, &plans[j]);

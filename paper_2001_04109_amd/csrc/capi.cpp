@@ -98,6 +98,8 @@ const char* ffp_strerror(int status)
 
 const char* ffp_version(void) { return "ffp 0.1 (gfx950)"; }
 
+const char* ffp_last_error_detail(void) { return last_error_detail(); }
+
 // ---- introspection (host only; no device work) ---------------------------
 
 int ffp_field_info(uint32_t p, uint32_t* ya, uint32_t* yb, int* ycost)

@@ -71,6 +71,10 @@ extern int64_t g_kblk_cap;
 extern int g_f64_tile_override;
 extern int g_i8_tile_override;
 extern int g_i8_bk_override;
+// Tile edge chosen for the product launches of the current call on this
+// thread (0: the launch rule or the override above); set from the tuned
+// choice of the call's plan.
+extern thread_local int g_tile_hint;
 extern int g_i8_ring;          // CLS_I8 256x256: ring of 4 or 5 direct-to-LDS stages (0: off)
 // Multi-task product launches run persistent workgroups (1, default) or one
 // workgroup per tile (0).
@@ -140,5 +144,10 @@ hipError_t launch_pack_grouped(int src_cls, int dst_cls, PackDesc* descs, int nd
 // Copy the lower triangle (or all, if full) of an n x n uint32 block.
 hipError_t launch_copy_u32(int64_t rows, int64_t cols, const uint32_t* src, int64_t lds,
                            uint32_t* dst, int64_t ldd, int lower_only, hipStream_t s);
+// rows x cols pseudo-random residues mod p in operand storage dtype
+// (FFP_U32, FFP_I8_CENTERED, FFP_I8_LIMB2 with the lo plane `plane` bytes
+// after the hi plane).
+hipError_t launch_fill_residues(int64_t rows, int64_t cols, void* dst, int64_t ld, int64_t plane, int dtype,
+                                uint32_t p, uint64_t seed, hipStream_t s);
 
 }  // namespace ffp

@@ -57,6 +57,7 @@ PlanRequest schur_request(int64_t n2, const NodeLayout& L, uint32_t p, int64_t l
     rq.alpha = p - 1;
     rq.beta = 1;
     rq.depth = -1;
+    rq.no_tune = true;      // the workspace figure must not depend on the tuning table
     rq.a_aligned16 = true;
     rq.c_aligned16 = c_aligned;
     return rq;
@@ -292,6 +293,7 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
         const int st = acquire_staging(s, desc_bytes + prod_bytes, &host, &dev);
         if (st != FFP_OK) return st;
     }
+    if (const int st = capture_point(s); st != FFP_OK) return st;
     if (!table.empty()) {
         memcpy(host, table.data(), table.size() * sizeof(LdltDesc));
         if (hipMemcpyAsync(dev, host, table.size() * sizeof(LdltDesc), hipMemcpyHostToDevice, s) != hipSuccess)

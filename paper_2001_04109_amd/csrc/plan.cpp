@@ -1,5 +1,6 @@
 // Schedule builder for fsyrk_modp (host only, no device calls).
 #include "plan.h"
+#include "tune.h"
 
 #include <algorithm>
 #include <cstdio>
@@ -300,10 +301,26 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
     if (pl.cls == CLS_LIMB2 && rq.p > 65521) return FFP_EDTYPE;
     const int64_t n = rq.n, k = rq.k;
 
-    int d = rq.depth >= 0 ? rq.depth : default_depth(pl.cls, n, k);
+    int d = rq.depth;
+    bool wide = rq.wide;
+    int tile = rq.tile;
+    if (!rq.no_tune) {
+        TuneChoice tc;
+        if (tune_lookup(pl.cls, n, k, rq.alpha != 1u || rq.beta != 0u, !rq.wide, &tc)) {
+            if (d < 0) {
+                d = tc.depth;
+                wide = rq.wide && tc.wide != 0;
+                pl.tuned = true;
+            }
+            if (d == tc.depth && tile == 0) tile = tc.tile;
+        }
+    }
+    if (d < 0) d = default_depth(pl.cls, n, k);
     while (d > 0 && (n >> d) < 8) --d;
     if (k == 0) d = 0;
     pl.depth = d;
+    pl.wide = wide;
+    pl.tile = tile;
 
     const int64_t es_op = elem_size(pl.cls);
     const int64_t kunit = ((pl.cls == CLS_F64) ? 4 : 64) << (d + (pl.field.yb ? 1 : 0));
@@ -317,7 +334,7 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
     B.cls = pl.cls;
     B.fp = Fp{rq.p, (rq.p - 1) / 2, pl.field.pinv, pl.field.ya, pl.field.yb};
     B.yb_nonzero = pl.field.yb != 0;
-    B.wide = rq.wide;
+    B.wide = wide;
     B.ops = &pl.ops;
 
     // Operand: pack when the class, the shape or the alignment differ.
@@ -392,9 +409,10 @@ std::string describe_plan(const Plan& pl)
 {
     std::string s;
     char buf[512];
-    snprintf(buf, sizeof buf, "plan cls=%d depth=%d n_pad=%lld k_pad=%lld ws=%lld ya=%u yb=%u\n",
+    snprintf(buf, sizeof buf,
+             "plan cls=%d depth=%d n_pad=%lld k_pad=%lld ws=%lld ya=%u yb=%u wide=%d tile=%d tuned=%d\n",
              pl.cls, pl.depth, (long long)pl.n_pad, (long long)pl.k_pad, (long long)pl.ws_bytes,
-             pl.field.ya, pl.field.yb);
+             pl.field.ya, pl.field.yb, pl.wide ? 1 : 0, pl.tile, pl.tuned ? 1 : 0);
     s += buf;
     for (const Op& o : pl.ops) {
         snprintf(buf, sizeof buf, "op %d %d %d %d %lld %lld %lld %lld %lld %u %u %d", (int)o.kind, o.cls,

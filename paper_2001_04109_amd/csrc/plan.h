@@ -66,12 +66,17 @@ struct PlanRequest {
     // that P2 and the recursive calls P5, P1 with P3 have no memory in common
     // and the level scheduler runs them together (more workspace).
     bool wide = false;
+    int32_t tile = 0;            // product tile edge (0: launch rule)
+    bool no_tune = false;        // ignore the tuning table
 };
 
 struct Plan {
     FieldPlan field;
     int32_t cls = CLS_F64;       // base path class
     int32_t depth = 0;
+    bool wide = false;           // placements used (see PlanRequest::wide)
+    int32_t tile = 0;            // product tile edge for its launches (0: rule)
+    bool tuned = false;          // depth and placements came from the tuning table
     int64_t n_pad = 0, k_pad = 0;
     int64_t ws_bytes = 0;
     std::vector<Op> ops;

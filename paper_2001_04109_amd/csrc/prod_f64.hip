@@ -386,8 +386,9 @@ hipError_t launch_products_f64(ProdTask* tasks, int ntasks, ProdTask* dev_task_b
         tiles128 += tasks[i].syrk ? tm * (tm + 1) / 2 : tm * tn;
     }
     bool big = tiles128 >= 512;
-    if (g_f64_tile_override == 64) big = false;
-    if (g_f64_tile_override == 128) big = true;
+    const int ov = g_tile_hint ? g_tile_hint : g_f64_tile_override;
+    if (ov == 64) big = false;
+    if (ov == 128) big = true;
     return big ? launch_f64_impl<128>(tasks, ntasks, dev_task_buf, s)
                : launch_f64_impl<64>(tasks, ntasks, dev_task_buf, s);
 }

@@ -668,8 +668,9 @@ hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_bu
 {
     // 256 x 256 tiles once they alone fill the 256 CUs twice over
     bool big = tiles_of(tasks, ntasks, 256) >= 512;
-    if (g_i8_tile_override == 128) big = false;
-    if (g_i8_tile_override == 256) big = true;
+    const int ov = g_tile_hint ? g_tile_hint : g_i8_tile_override;
+    if (ov == 128) big = false;
+    if (ov == 256) big = true;
     bool k128 = true;
     for (int i = 0; i < ntasks; ++i) k128 = k128 && (tasks[i].k % 128) == 0;
     if (big) {

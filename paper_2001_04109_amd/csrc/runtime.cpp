@@ -5,6 +5,7 @@
 #include <map>
 #include <vector>
 #include <mutex>
+#include <string>
 #include <utility>
 
 #include "ffp.h"
@@ -34,22 +35,98 @@ DView dview(const PView& v, const void* a, void* c, void* ws)
 
 }  // namespace
 
+namespace {
+thread_local std::string g_err_detail;
+}  // namespace
+
+hipError_t note_hip(const char* where, hipError_t e)
+{
+    if (e != hipSuccess) {
+        g_err_detail = std::string(where) + ": " + hipGetErrorName(e);
+        (void)hipGetLastError();
+    }
+    return e;
+}
+
+const char* last_error_detail() { return g_err_detail.c_str(); }
+
+namespace {
+thread_local CaptureCtx* g_cap = nullptr;
+
+int cap_dev_alloc(CaptureCtx* c, size_t bytes, void** out)
+{
+    *out = nullptr;
+    if (c->capturing) return FFP_EUNSUPPORTED;
+    if (bytes == 0) return FFP_OK;
+    if (note_hip("hipMalloc (graph buffer)", hipMalloc(out, bytes)) != hipSuccess) {
+        *out = nullptr;
+        (void)hipGetLastError();
+        return FFP_ENOMEM;
+    }
+    c->dev.push_back(*out);
+    c->dev_bytes += bytes;
+    return FFP_OK;
+}
+}  // namespace
+
+void CaptureCtx::free_all()
+{
+    for (void* p : dev) (void)hipFree(p);
+    for (void* p : host) (void)hipHostFree(p);
+    for (Workspace* w : ws) delete w;
+    dev.clear();
+    host.clear();
+    ws.clear();
+    dev_bytes = host_bytes = 0;
+}
+
+void set_capture_ctx(CaptureCtx* c) { g_cap = c; }
+CaptureCtx* capture_ctx() { return g_cap; }
+
+int capture_point(hipStream_t s)
+{
+    CaptureCtx* c = g_cap;
+    if (!c || c->capturing) return FFP_OK;
+    if (s == nullptr || s != c->stream) return FFP_EINVAL;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return FFP_EDEVICE;
+    }
+    c->capturing = true;
+    return FFP_OK;
+}
+
 int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** out)
 {
+    if (CaptureCtx* c = g_cap) {
+        Workspace* w = new Workspace();
+        c->ws.push_back(w);
+        int st = cap_dev_alloc(c, bytes, &w->ptr);
+        if (st != FFP_OK) return st;
+        w->bytes = bytes;
+        if (ntasks > 0) {
+            st = cap_dev_alloc(c, ntasks * sizeof(ProdTask), (void**)&w->tasks);
+            if (st != FFP_OK) return st;
+            w->task_cap = ntasks;
+        }
+        *out = w;
+        return FFP_OK;
+    }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return FFP_EDEVICE;
     std::lock_guard<std::mutex> lk(g_ws_mutex);
     Workspace& w = g_ws[std::make_pair(dev, s)];
     if (bytes > w.bytes || ntasks > w.task_cap) {
         if (w.ptr || w.tasks) {
-            if (hipStreamSynchronize(s) != hipSuccess) return FFP_EDEVICE;
+            if (note_hip("hipStreamSynchronize (workspace)", hipStreamSynchronize(s)) != hipSuccess)
+                return FFP_EDEVICE;
         }
         if (bytes > w.bytes) {
             if (w.ptr) (void)hipFree(w.ptr);
             w.ptr = nullptr;
             w.bytes = 0;
             size_t want = bytes + bytes / 4 + 4096;
-            if (hipMalloc(&w.ptr, want) != hipSuccess) {
+            if (note_hip("hipMalloc (workspace)", hipMalloc(&w.ptr, want)) != hipSuccess) {
                 w.ptr = nullptr;
                 (void)hipGetLastError();
                 return FFP_ENOMEM;
@@ -61,7 +138,8 @@ int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** ou
             w.tasks = nullptr;
             w.task_cap = 0;
             size_t cap = ntasks < 64 ? 64 : ntasks * 2;
-            if (hipMalloc((void**)&w.tasks, cap * sizeof(ProdTask)) != hipSuccess) {
+            if (note_hip("hipMalloc (task table)", hipMalloc((void**)&w.tasks, cap * sizeof(ProdTask))) !=
+                hipSuccess) {
                 w.tasks = nullptr;
                 (void)hipGetLastError();
                 return FFP_ENOMEM;
@@ -86,6 +164,20 @@ std::map<std::pair<int, hipStream_t>, Staging> g_stage;
 
 int acquire_staging(hipStream_t s, size_t bytes, char** host, char** dev)
 {
+    if (CaptureCtx* c = g_cap) {
+        *host = nullptr;
+        *dev = nullptr;
+        if (c->capturing) return FFP_EUNSUPPORTED;
+        if (note_hip("hipHostMalloc (graph tables)", hipHostMalloc((void**)host, bytes, hipHostMallocDefault)) !=
+            hipSuccess) {
+            *host = nullptr;
+            (void)hipGetLastError();
+            return FFP_ENOMEM;
+        }
+        c->host.push_back(*host);
+        c->host_bytes += bytes;
+        return cap_dev_alloc(c, bytes, (void**)dev);
+    }
     int d = 0;
     if (hipGetDevice(&d) != hipSuccess) return FFP_EDEVICE;
     std::lock_guard<std::mutex> lk(g_ws_mutex);
@@ -103,8 +195,9 @@ int acquire_staging(hipStream_t s, size_t bytes, char** host, char** dev)
         st.dev = nullptr;
         st.cap = 0;
         const size_t want = bytes + bytes / 2 + 4096;
-        if (hipHostMalloc((void**)&st.host, want, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void**)&st.dev, want) != hipSuccess) {
+        if (note_hip("hipHostMalloc (staging)", hipHostMalloc((void**)&st.host, want, hipHostMallocDefault)) !=
+                hipSuccess ||
+            note_hip("hipMalloc (staging)", hipMalloc((void**)&st.dev, want)) != hipSuccess) {
             (void)hipGetLastError();
             return FFP_ENOMEM;
         }
@@ -117,6 +210,7 @@ int acquire_staging(hipStream_t s, size_t bytes, char** host, char** dev)
 
 int release_staging(hipStream_t s)
 {
+    if (g_cap) return FFP_OK;   // the graph owns its staging area
     int d = 0;
     if (hipGetDevice(&d) != hipSuccess) return FFP_EDEVICE;
     std::lock_guard<std::mutex> lk(g_ws_mutex);
@@ -126,6 +220,17 @@ int release_staging(hipStream_t s)
     st.pending = true;
     return FFP_OK;
 }
+
+thread_local int g_tile_hint = 0;
+
+namespace {
+// Sets the tile hint for the launches made while it lives.
+struct TileHint {
+    int saved;
+    explicit TileHint(int tile) : saved(g_tile_hint) { g_tile_hint = tile; }
+    ~TileHint() { g_tile_hint = saved; }
+};
+}  // namespace
 
 int64_t g_kblk_cap = 0;
 int g_persistent = 1;
@@ -158,7 +263,7 @@ bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 }  // namespace
 
-bool prof_enabled() { return g_prof_on; }
+bool prof_enabled() { return g_prof_on && g_cap == nullptr; }
 
 void prof_begin(hipStream_t s, hipEvent_t* e0)
 {
@@ -422,6 +527,7 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
         int st = acquire_staging(s, meta, &host_meta, &dev_meta);
         if (st != FFP_OK) return st;
     }
+    if (const int st = capture_point(s); st != FFP_OK) return st;
     size_t moff = 0;
     int status = FFP_OK;
     for (const auto& lv : by_level) {
@@ -458,6 +564,9 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
             }
             int nt = 0;
             double flops = 0.0;
+            int tile = items[g[0]].pl->tile;
+            for (size_t j : g)
+                if (items[j].pl->tile != tile) tile = 0;
             for (size_t j : g) {
                 const SchedItem& it = items[j];
                 ProdTask t = make_task(*it.pl, *it.op, it.a, it.c, it.ws);
@@ -469,7 +578,10 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
             hipEvent_t e0 = nullptr;
             const bool prof = prof_enabled();
             if (prof) prof_begin(s, &e0);
-            if (launch_products(cls, tasks, nt, dtasks, s) != hipSuccess) status = FFP_EDEVICE;
+            {
+                TileHint hint(tile);
+                if (launch_products(cls, tasks, nt, dtasks, s) != hipSuccess) status = FFP_EDEVICE;
+            }
             if (prof) prof_end(s, e0, flops, cls);
         }
         for (int q = 0; q < 9 && status == FFP_OK; ++q) {
@@ -556,7 +668,10 @@ int execute_op(const Plan& pl, const Op& o, const void* a, void* c, void* ws, hi
             hipEvent_t e0 = nullptr;
             const bool prof = prof_enabled();
             if (prof) prof_begin(s, &e0);
-            e = launch_products(o.cls, &t, 1, nullptr, s);
+            {
+                TileHint hint(pl.tile);
+                e = launch_products(o.cls, &t, 1, nullptr, s);
+            }
             if (prof) {
                 const double flops = syrk ? (double)t.m * (double)(t.m + 1) * (double)t.k
                                           : 2.0 * (double)t.m * (double)t.n * (double)t.k;

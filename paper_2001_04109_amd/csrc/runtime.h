@@ -31,6 +31,34 @@ int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** ou
 int acquire_staging(hipStream_t s, size_t bytes, char** host, char** dev);
 int release_staging(hipStream_t s);
 
+// Records which HIP call failed (with its error name) for
+// ffp_last_error_detail; returns e.
+hipError_t note_hip(const char* where, hipError_t e);
+const char* last_error_detail();
+
+// Capture of a batched call into a HIP graph.  While a capture context is
+// installed on the calling thread, acquire_workspace and acquire_staging
+// allocate buffers that the context owns (they live as long as the graph)
+// instead of using the per-stream pool, and nothing waits on the host.  The
+// batched drivers acquire everything before their first launch and then
+// call capture_point, which begins the stream capture; an acquisition after
+// that point fails with FFP_EUNSUPPORTED (no allocation inside a capture).
+struct CaptureCtx {
+    hipStream_t stream = nullptr;
+    bool capturing = false;
+    std::vector<void*> dev;        // device buffers
+    std::vector<void*> host;       // pinned host buffers
+    std::vector<Workspace*> ws;
+    size_t dev_bytes = 0;
+    size_t host_bytes = 0;
+    void free_all();
+};
+void set_capture_ctx(CaptureCtx* c);
+CaptureCtx* capture_ctx();
+// Begins the capture of stream s if a context is installed and not yet
+// capturing; otherwise does nothing.
+int capture_point(hipStream_t s);
+
 // Enqueues every op of the plan on stream s.  a, c: caller buffers; ws:
 // workspace of at least pl.ws_bytes.
 int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s);

@@ -11,6 +11,7 @@
 #include "batch.h"
 #include "field.h"
 #include "ldlt.h"
+#include "tune.h"
 
 namespace ffp {
 
@@ -38,10 +39,8 @@ constexpr int kMaxLdltBatch = 32;   // LDL^T requests per unit
 
 // Workspace the request needs while it runs (the same figure the batched
 // launch and the LDL^T driver use for it).
-size_t workspace_bytes(const ffp_request& r)
+ffp_job syrk_job(const ffp_request& r)
 {
-    if (r.n == 0) return 0;
-    if (r.kind == FFP_REQ_LDLT) return (size_t)rup((int64_t)ldlt_workspace_bytes(r.n, r.p, result_ld(r)), 256);
     ffp_job j{};
     j.n = r.n;
     j.k = r.k;
@@ -53,7 +52,24 @@ size_t workspace_bytes(const ffp_request& r)
     j.lda = r.lda;
     j.C = (uint32_t*)(uintptr_t)256;   // results are 256-byte aligned in the arena
     j.ldc = result_ld(r);
-    return (size_t)job_workspace_bytes(j, 0);
+    return j;
+}
+
+// Flags that fix the request's depth and placements at submission (from
+// the tuning table or the built-in rule).
+unsigned pinned_flags(const ffp_request& r)
+{
+    if (r.kind != FFP_REQ_SYRK || r.n == 0) return 0;
+    return pin_flags(syrk_job(r), 0);
+}
+
+// Workspace the request needs while it runs (the same figure the batched
+// launch and the LDL^T driver use for it).
+size_t workspace_bytes(const ffp_request& r, unsigned flags)
+{
+    if (r.n == 0) return 0;
+    if (r.kind == FFP_REQ_LDLT) return (size_t)rup((int64_t)ldlt_workspace_bytes(r.n, r.p, result_ld(r)), 256);
+    return (size_t)job_workspace_bytes(syrk_job(r), flags);
 }
 
 // ---- device backed by HIP --------------------------------------------------
@@ -85,6 +101,7 @@ public:
     {
         std::vector<ffp_job> jobs;
         std::vector<char*> ws;
+        std::vector<unsigned> flags;
         jobs.reserve(batch.size());
         for (ServeReq* r : batch) {
             ffp_job j{};
@@ -100,8 +117,9 @@ public:
             j.ldc = result_ld(r->rq);
             jobs.push_back(j);
             ws.push_back(r->ws_bytes ? arena_ + r->ws_off : nullptr);
+            flags.push_back(r->flags);
         }
-        int st = batched_run((int)jobs.size(), jobs.data(), 0, streams_[s], ws.data());
+        int st = batched_run((int)jobs.size(), jobs.data(), 0, streams_[s], ws.data(), flags.data());
         if (st != FFP_OK) return st;
         return record(s, u);
     }
@@ -287,7 +305,8 @@ int Server::submit(const ffp_request* r, uint64_t* ticket)
     q.rq = *r;
     if (q.rq.kind == FFP_REQ_LDLT) q.rq.k = q.rq.n;
     q.bytes = result_bytes(q.rq);
-    q.ws_bytes = workspace_bytes(q.rq);
+    q.flags = pinned_flags(q.rq);
+    q.ws_bytes = workspace_bytes(q.rq, q.flags);
     if (q.bytes + q.ws_bytes > budget_) return FFP_ENOMEM;
     {
         std::lock_guard<std::mutex> lk(mu_);

@@ -23,6 +23,7 @@ struct ServeReq {
     size_t off = 0;          // offset of the result in the arena
     size_t ws_bytes = 0;     // arena bytes of workspace, held while running
     size_t ws_off = 0;
+    unsigned flags = 0;      // A*A^T: depth and placements fixed at submission
     double t_submit = 0, t_admit = 0, t_done = 0;
     int status = FFP_OK;
     bool released = false;

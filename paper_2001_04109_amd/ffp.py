@@ -38,7 +38,14 @@ def FFP_DEPTH(d: int) -> int:
 
 class FfpError(RuntimeError):
     def __init__(self, status: int, what: str):
-        super().__init__(f"{what}: {strerror(status)} (status {status})")
+        detail = ""
+        if status in (FFP_ENOMEM, FFP_EDEVICE):
+            try:
+                d = lib().ffp_last_error_detail().decode()
+                detail = f" [{d}]" if d else ""
+            except Exception:  # library missing: the status alone
+                pass
+        super().__init__(f"{what}: {strerror(status)} (status {status}){detail}")
         self.status = status
 
 
@@ -66,6 +73,14 @@ class ffp_result(ctypes.Structure):
                 ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
+class ffp_tune_result(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("tile", ctypes.c_int32), ("wide", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("ms", ctypes.c_double), ("rule_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class ffp_serve_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("units", ctypes.c_int64), ("batched_jobs", ctypes.c_int64),
@@ -86,6 +101,14 @@ def lib():
     """Load libffp.so (built by paper_2001_04109_amd.build); raises if missing."""
     global _lib
     if _lib is None:
+        # torch first: the library must bind to the HIP runtime torch loads
+        # (the one that owns the device memory and streams passed in);
+        # loading the system runtime before torch's gives a second runtime
+        # in the process that sees no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover - host-only use without torch
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2001_04109_amd.build`")
@@ -100,6 +123,7 @@ def lib():
             "fsyrk_modp_batched": (c_int, [c_int, P, c_uint, P]),
             "ffp_strerror": (ctypes.c_char_p, [c_int]),
             "ffp_version": (ctypes.c_char_p, []),
+            "ffp_last_error_detail": (ctypes.c_char_p, []),
             "ffp_field_info": (c_int, [u32, P, P, P]),
             "ffp_host_sqrt": (c_int, [u32, u32, P]),
             "ffp_host_sos": (c_int, [u32, u32, P, P]),
@@ -121,6 +145,18 @@ def lib():
             "ffp_server_poll": (c_int, [P, P, c_int, ctypes.c_double, P]),
             "ffp_server_fetch": (c_int, [P, ctypes.c_uint64, P, i64, P, P]),
             "ffp_server_destroy": (c_int, [P]),
+            "ffp_graph_syrk_batched": (c_int, [c_int, P, c_uint, P, P]),
+            "ffp_graph_ldlt_batched": (c_int, [c_int, P, P, P]),
+            "ffp_graph_launch": (c_int, [P, P]),
+            "ffp_graph_device_bytes": (ctypes.c_size_t, [P]),
+            "ffp_graph_nodes": (ctypes.c_size_t, [P]),
+            "ffp_graph_destroy": (None, [P]),
+            "ffp_autotune": (c_int, [i64, i64, u32, c_int, u32, u32, c_uint, P, P]),
+            "ffp_tune_lookup": (c_int, [i64, i64, u32, c_int, u32, u32, c_uint, P]),
+            "ffp_tune_save": (c_int, [ctypes.c_char_p]),
+            "ffp_tune_load": (c_int, [ctypes.c_char_p]),
+            "ffp_tune_clear": (None, []),
+            "ffp_tune_entries": (c_int, []),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name, None)
@@ -190,6 +226,112 @@ def fsyrk_modp_batched(jobs, flags=0, stream=None):
     arr = (ffp_job * len(jobs))(*jobs)
     return _check(lib().fsyrk_modp_batched(len(jobs), ctypes.cast(arr, ctypes.c_void_p), flags,
                                            _stream(stream)), "fsyrk_modp_batched")
+
+
+def ffp_graph_syrk_batched(jobs, flags=0, stream=None) -> int:
+    arr = (ffp_job * len(jobs))(*jobs)
+    g = ctypes.c_void_p()
+    _check(lib().ffp_graph_syrk_batched(len(jobs), ctypes.cast(arr, ctypes.c_void_p), flags,
+                                        _stream(stream), ctypes.byref(g)), "ffp_graph_syrk_batched")
+    return g.value or 0
+
+
+def ffp_graph_ldlt_batched(jobs, stream=None) -> int:
+    arr = (ffp_ldlt_job * len(jobs))(*jobs)
+    g = ctypes.c_void_p()
+    _check(lib().ffp_graph_ldlt_batched(len(jobs), ctypes.cast(arr, ctypes.c_void_p),
+                                        _stream(stream), ctypes.byref(g)), "ffp_graph_ldlt_batched")
+    return g.value or 0
+
+
+def ffp_graph_launch(g: int, stream=None):
+    return _check(lib().ffp_graph_launch(g, _stream(stream)), "ffp_graph_launch")
+
+
+def ffp_graph_device_bytes(g: int) -> int:
+    return int(lib().ffp_graph_device_bytes(g))
+
+
+def ffp_graph_nodes(g: int) -> int:
+    return int(lib().ffp_graph_nodes(g))
+
+
+def ffp_graph_destroy(g: int):
+    if g:
+        lib().ffp_graph_destroy(g)
+
+
+def ffp_autotune(n, k, p, a_dtype=FFP_U32, alpha=1, beta=0, flags=0, stream=None) -> dict:
+    r = ffp_tune_result()
+    _check(lib().ffp_autotune(n, k, p, a_dtype, alpha, beta, flags, _stream(stream), ctypes.byref(r)),
+           "ffp_autotune")
+    return r.as_dict()
+
+
+def ffp_tune_lookup(n, k, p, a_dtype=FFP_U32, alpha=1, beta=0, flags=0) -> dict:
+    """The depth, tile and placements a call of this shape uses now, and
+    whether they come from the tuning table (key "tuned")."""
+    r = ffp_tune_result()
+    st = _check(lib().ffp_tune_lookup(n, k, p, a_dtype, alpha, beta, flags, ctypes.byref(r)),
+                "ffp_tune_lookup")
+    d = r.as_dict()
+    d["tuned"] = bool(st)
+    return d
+
+
+def ffp_tune_save(path: str):
+    _check(lib().ffp_tune_save(os.fsencode(path)), "ffp_tune_save")
+
+
+def ffp_tune_load(path: str) -> int:
+    return _check(lib().ffp_tune_load(os.fsencode(path)), "ffp_tune_load")
+
+
+def ffp_tune_clear():
+    lib().ffp_tune_clear()
+
+
+def ffp_tune_entries() -> int:
+    return int(lib().ffp_tune_entries())
+
+
+class Graph:
+    """A recorded batched call (ffp_graph_* of include/ffp.h).  The recording
+    stream must not be the null stream; keep the jobs' tensors alive while the
+    graph exists."""
+
+    def __init__(self, handle: int, keep=()):
+        self.handle = handle
+        self._keep = keep
+
+    @classmethod
+    def syrk_batched(cls, jobs, flags=0, stream=None, keep=()):
+        return cls(ffp_graph_syrk_batched(jobs, flags, stream), keep)
+
+    @classmethod
+    def ldlt_batched(cls, jobs, stream=None, keep=()):
+        return cls(ffp_graph_ldlt_batched(jobs, stream), keep)
+
+    def launch(self, stream=None):
+        ffp_graph_launch(self.handle, stream)
+
+    @property
+    def device_bytes(self) -> int:
+        return ffp_graph_device_bytes(self.handle)
+
+    @property
+    def nodes(self) -> int:
+        return ffp_graph_nodes(self.handle)
+
+    def close(self):
+        ffp_graph_destroy(self.handle)
+        self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def make_job(A, C, p, alpha=1, beta=0, a_dtype=FFP_U32) -> ffp_job:
