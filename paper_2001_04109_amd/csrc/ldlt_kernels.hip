@@ -33,37 +33,77 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
     __shared__ uint32_t li[NB][NB + 1];
     __shared__ uint32_t tq[NB][NB + 1];
     __shared__ uint32_t ainv[NB];
+    __shared__ __attribute__((aligned(16))) uint32_t colk[2][NB];
     const uint32_t p = f.p;
     const double pd = (double)p, pinv = f.pinv;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int e = tid; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        if (j <= i) sm[i][j] = S[(int64_t)i * lds + j];
-    }
+    const int tid = threadIdx.x;
+    // The elimination keeps the whole (symmetric, both triangles) block in
+    // registers: thread t owns the 4 x 4 block of rows r0.. r0+3 and columns
+    // c0.. c0+3.  Step k only needs column k, which its 16 owners publish
+    // in LDS (double-buffered, one barrier per step); by symmetry M[j][k] is
+    // the column entry of row j.
+    const int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
+    uint32_t m[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = r0 + a, j = c0 + b;
+            uint32_t v = 0u;
+            if (i < nb && j < nb) v = j <= i ? S[(int64_t)i * lds + j] : S[(int64_t)j * lds + i];
+            m[a][b] = v;
+        }
+    if (c0 == 0)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) colk[0][r0 + a] = m[a][0];
     __syncthreads();
     bool stop = false;
-    for (int k = 0; k < nb; ++k) {
-        const uint32_t a = sm[k][k];
-        if (a == 0u) {
-            if (tid == 0 && *info == 0) *info = offset + k + 1;
-            stop = true;                            // every thread read the same a
-            break;
-        }
-        // trailing lower triangle: lane -> column k + 1 + jj, waves stride the rows
-        const int r = nb - k - 1;
-        const int jj = lane;
-        if (jj < r) {
-            const int j = k + 1 + jj;
-            const double mjk = (double)sm[j][k];
-            int ii = jj + ((wv - jj) & 3);          // first row >= jj with ii = wv (mod 4)
-            for (; ii < r; ii += 4) {
-                const int i = k + 1 + ii;
-                const double x = fma((double)a, (double)sm[i][j], (pd - (double)sm[i][k]) * mjk);
-                sm[i][j] = mod53(x, p, pinv);       // x < 2 p^2 < 2^51
+    for (int k0 = 0; k0 < nb && !stop; k0 += 4) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = k0 + kk;
+            if (k >= nb) break;
+            const uint32_t* col = colk[k & 1];
+            const uint32_t a = col[k];
+            if (a == 0u) {
+                if (tid == 0 && *info == 0) *info = offset + k + 1;
+                stop = true;                          // every thread read the same a
+                break;
             }
+            const uint4 ci = *reinterpret_cast<const uint4*>(&col[r0]);
+            const uint4 cj = *reinterpret_cast<const uint4*>(&col[c0]);
+            const double nci[4] = {pd - (double)ci.x, pd - (double)ci.y, pd - (double)ci.z, pd - (double)ci.w};
+            const double vcj[4] = {(double)cj.x, (double)cj.y, (double)cj.z, (double)cj.w};
+            const double ad = (double)a;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    if (r0 + x > k && c0 + y > k)     // a M[i][j] - M[i][k] M[j][k] < 2 p^2
+                        m[x][y] = mod53(fma(ad, (double)m[x][y], nci[x] * vcj[y]), p, pinv);
+            // owners of column k + 1 publish it for the next step
+            if (kk < 3) {
+                if (c0 == k0)
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) colk[(k + 1) & 1][r0 + x] = m[x][kk + 1];
+            } else {
+                if (c0 == k0 + 4)
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) colk[(k + 1) & 1][r0 + x] = m[x][0];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
+    if (!stop) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = r0 + a, j = c0 + b;
+                if (i < nb && j <= i) sm[i][j] = m[a][b];
+            }
+    }
+    __syncthreads();
     if (stop) return;   // contents unspecified after a zero pivot
     // D[k] = a_k / g_k, L[i][k] = M[i][k] / a_k
     uint32_t dk = 0u;

@@ -564,9 +564,12 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
             }
             int nt = 0;
             double flops = 0.0;
+            // a tuned tile applies to the products of one call; grouped
+            // launches over several jobs keep the launch rule, which sizes
+            // the tile from the whole group
             int tile = items[g[0]].pl->tile;
             for (size_t j : g)
-                if (items[j].pl->tile != tile) tile = 0;
+                if (items[j].pl->tile != tile || items[j].job != items[g[0]].job) tile = 0;
             for (size_t j : g) {
                 const SchedItem& it = items[j];
                 ProdTask t = make_task(*it.pl, *it.op, it.a, it.c, it.ws);
