@@ -247,9 +247,9 @@ struct Builder {
 
 int64_t rup256(int64_t x) { return (x + 255) / 256 * 256; }
 
-// Runs the steps of independent jobs level by level: device steps of one
-// kind in a level as one launch over their descriptors, products of one
-// class as one grouped launch, block operations one by one.
+// Runs the steps of independent jobs level by level: all device steps of a
+// level (whatever their kinds) as one launch over their descriptors,
+// products of one class as one grouped launch, block operations one by one.
 int execute_steps(const std::vector<Step>& steps, hipStream_t s)
 {
     if (steps.empty()) return FFP_OK;
@@ -258,19 +258,22 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
     std::vector<std::vector<int>> by(maxlev + 1);
     for (size_t i = 0; i < steps.size(); ++i) by[steps[i].level].push_back((int)i);
 
-    // descriptor table: one slice per (level, kind); product tables for groups
-    // beyond the inline capacity
-    struct Slice { int kind, first, count, blocks; };
-    std::vector<std::vector<Slice>> slices(maxlev + 1);
+    // descriptor table: one slice per level (kinds in a fixed order, the
+    // longest-running first); product tables for groups beyond the inline
+    // capacity
+    struct Slice { int first, count, blocks; };
+    static const int kOrder[LK_KINDS] = {LK_LEAF, LK_PAIR, LK_CLASSIFY, LK_TRSM, LK_ABAR, LK_SCALE, LK_ZERO};
+    std::vector<Slice> slices(maxlev + 1, Slice{0, 0, 0});
     std::vector<LdltDesc> table;
     size_t prod_bytes = 0;
     for (int lv = 0; lv <= maxlev; ++lv) {
-        for (int kind = 0; kind < LK_KINDS; ++kind) {
-            Slice sl{kind, (int)table.size(), 0, 0};
+        Slice sl{(int)table.size(), 0, 0};
+        for (int kind : kOrder) {
             for (int i : by[lv]) {
                 const Step& st = steps[i];
                 if (st.sk != SK_DEV || st.kind != kind) continue;
                 LdltDesc d = st.d;
+                d.kind = kind;
                 const int nbk = ldlt_blocks(kind, &d);
                 if (nbk <= 0) continue;
                 d.block0 = sl.blocks;
@@ -278,8 +281,8 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
                 table.push_back(d);
                 ++sl.count;
             }
-            if (sl.count) slices[lv].push_back(sl);
         }
+        slices[lv] = sl;
         int np[3] = {0, 0, 0};
         for (int i : by[lv])
             if (steps[i].sk == SK_PROD) ++np[steps[i].cls];
@@ -303,9 +306,9 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
     size_t poff = desc_bytes;
     int status = FFP_OK;
     for (int lv = 0; lv <= maxlev && status == FFP_OK; ++lv) {
-        for (const Slice& sl : slices[lv])
-            if (launch_ldlt_kind(sl.kind, dtable + sl.first, sl.count, sl.blocks, s) != hipSuccess)
-                status = FFP_EDEVICE;
+        const Slice& sl = slices[lv];
+        if (sl.count && launch_ldlt_steps(dtable + sl.first, sl.count, sl.blocks, s) != hipSuccess)
+            status = FFP_EDEVICE;
         for (int cls = 0; cls < 3 && status == FFP_OK; ++cls) {
             std::vector<ProdTask> g;
             for (int i : by[lv])

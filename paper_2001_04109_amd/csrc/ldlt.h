@@ -49,6 +49,7 @@ enum LdltKind : int32_t {
 
 // Descriptor of one device step (read by the kernels from device memory).
 struct LdltDesc {
+    int32_t kind;      // LK_*
     Fp f;
     int32_t kb;        // residue products per FP64 partial sum
     int32_t nb;        // leaf / solve width; Algorithm 5: n1
@@ -69,8 +70,9 @@ struct LdltDesc {
 
 // Workgroups a descriptor of the kind needs (sets d->gx where used).
 int ldlt_blocks(int kind, LdltDesc* d);
-// One launch of the kind over n descriptors in device memory (block0 set).
-hipError_t launch_ldlt_kind(int kind, const LdltDesc* dev, int n, int total_blocks, hipStream_t s);
+// One launch over n descriptors of any kinds in device memory (block0 set,
+// ascending): each workgroup runs the step of its descriptor's kind.
+hipError_t launch_ldlt_steps(const LdltDesc* dev, int n, int total_blocks, hipStream_t s);
 // Residue products whose sum stays below 2^53, at most 64.
 int ldlt_dot_block(uint32_t p);
 

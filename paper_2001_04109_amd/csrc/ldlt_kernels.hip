@@ -26,14 +26,28 @@ constexpr int NB = kLdltLeaf;   // leaf order and triangular-solve block
 // inverses are then formed in parallel.  The inverse of L is built from its
 // 8 x 8 diagonal blocks up: [[A, 0], [B, C]]^-1 = [[A^-1, 0], [-C^-1 B A^-1,
 // C^-1]] on blocks of 8, 16 and 32.
-__device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S, int64_t lds, int64_t* info,
-                                               int64_t offset, uint32_t* linv)
+struct LeafLds {
+    uint32_t sm[NB][NB + 1];
+    uint32_t li[NB][NB + 1];
+    uint32_t tq[NB][NB + 1];
+    uint32_t ainv[NB];
+    __attribute__((aligned(16))) double colk[2][NB];
+};
+
+// The residue in [0, p) of a double congruent to it in [-p, 2p).
+__device__ __forceinline__ double canon(double x, double pd)
 {
-    __shared__ uint32_t sm[NB][NB + 1];
-    __shared__ uint32_t li[NB][NB + 1];
-    __shared__ uint32_t tq[NB][NB + 1];
-    __shared__ uint32_t ainv[NB];
-    __shared__ __attribute__((aligned(16))) uint32_t colk[2][NB];
+    return x < 0.0 ? x + pd : (x >= pd ? x - pd : x);
+}
+
+__device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S, int64_t lds, int64_t* info,
+                                               int64_t offset, uint32_t* linv, LeafLds& L)
+{
+    auto& sm = L.sm;
+    auto& li = L.li;
+    auto& tq = L.tq;
+    auto& ainv = L.ainv;
+    auto& colk = L.colk;
     const uint32_t p = f.p;
     const double pd = (double)p, pinv = f.pinv;
     const int tid = threadIdx.x;
@@ -41,9 +55,13 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
     // registers: thread t owns the 4 x 4 block of rows r0.. r0+3 and columns
     // c0.. c0+3.  Step k only needs column k, which its 16 owners publish
     // in LDS (double-buffered, one barrier per step); by symmetry M[j][k] is
-    // the column entry of row j.
+    // the column entry of row j.  Entries are kept as doubles congruent to
+    // their residue in [-p, 2p) (one quotient estimate, no correction):
+    // a M[i][j] - M[i][k] M[j][k] then stays below 8 p^2 < 2^53, so every
+    // product is exact; entries are brought into [0, p) at the end, the
+    // pivot at every step for the zero test.
     const int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
-    uint32_t m[4][4];
+    double m[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -51,7 +69,7 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
             const int i = r0 + a, j = c0 + b;
             uint32_t v = 0u;
             if (i < nb && j < nb) v = j <= i ? S[(int64_t)i * lds + j] : S[(int64_t)j * lds + i];
-            m[a][b] = v;
+            m[a][b] = (double)v;
         }
     if (c0 == 0)
 #pragma unroll
@@ -63,24 +81,27 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
         for (int kk = 0; kk < 4; ++kk) {
             const int k = k0 + kk;
             if (k >= nb) break;
-            const uint32_t* col = colk[k & 1];
-            const uint32_t a = col[k];
-            if (a == 0u) {
+            const double* col = colk[k & 1];
+            const double a = col[k];
+            if (canon(a, pd) == 0.0) {
                 if (tid == 0 && *info == 0) *info = offset + k + 1;
                 stop = true;                          // every thread read the same a
                 break;
             }
-            const uint4 ci = *reinterpret_cast<const uint4*>(&col[r0]);
-            const uint4 cj = *reinterpret_cast<const uint4*>(&col[c0]);
-            const double nci[4] = {pd - (double)ci.x, pd - (double)ci.y, pd - (double)ci.z, pd - (double)ci.w};
-            const double vcj[4] = {(double)cj.x, (double)cj.y, (double)cj.z, (double)cj.w};
-            const double ad = (double)a;
+            double ci[4], cj[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                ci[x] = col[r0 + x];
+                cj[x] = col[c0 + x];
+            }
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
                 for (int y = 0; y < 4; ++y)
-                    if (r0 + x > k && c0 + y > k)     // a M[i][j] - M[i][k] M[j][k] < 2 p^2
-                        m[x][y] = mod53(fma(ad, (double)m[x][y], nci[x] * vcj[y]), p, pinv);
+                    if (r0 + x > k && c0 + y > k) {
+                        const double v = fma(a, m[x][y], -(ci[x] * cj[y]));   // |v| < 8 p^2
+                        m[x][y] = fma(-floor(v * pinv), pd, v);               // in [-p, 2p)
+                    }
             // owners of column k + 1 publish it for the next step
             if (kk < 3) {
                 if (c0 == k0)
@@ -100,7 +121,7 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = r0 + a, j = c0 + b;
-                if (i < nb && j <= i) sm[i][j] = m[a][b];
+                if (i < nb && j <= i) sm[i][j] = (uint32_t)canon(m[a][b], pd);
             }
     }
     __syncthreads();
@@ -183,11 +204,16 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
 // thread forms a 4 x 4 block of entries in FP64 with delayed reduction
 // (Linv is zero above the diagonal in LDS, so every sum runs over all t).
 constexpr int TR = 64;
+struct TrsmLds {
+    double sl[NB][NB + 1];
+    double sx[TR][NB + 1];
+};
+
 __device__ __forceinline__ void trsm_inv_body(Fp f, int kb, int64_t nrows, int nb, uint32_t* X, int64_t ldx,
-                                              const uint32_t* linv, int lb)
+                                              const uint32_t* linv, int lb, TrsmLds& L)
 {
-    __shared__ double sl[NB][NB + 1];
-    __shared__ double sx[TR][NB + 1];
+    auto& sl = L.sl;
+    auto& sx = L.sx;
     const uint32_t p = f.p;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)lb * TR;
@@ -248,46 +274,48 @@ __device__ __forceinline__ void classify_body(Fp f, int n1, const uint32_t* S, i
     dinv[j] = inv_m(d, f.p, f.pinv);
 }
 
-// One workgroup: rank the non-residues (prefix count), pair them in index
-// order, factor each pair with Algorithm 4 and emit the column operations
-// of Algorithm 5 for the n1 + 1 columns of Abar (the last column is the
-// extra zero column, used when the number of non-residues is odd).
+// One workgroup of 256 threads: rank the non-residues (prefix count by
+// wave ballots), pair them in index order, factor each pair with
+// Algorithm 4 and emit the column operations of Algorithm 5 for the n1 + 1
+// columns of Abar (the last column is the extra zero column, used when the
+// number of non-residues is odd).
 //   desc[c] = (j1, s1, j2, s2):  Abar[:, c] = s1 L[:, j1] + s2 L[:, j2]
 // (an index of -1 contributes nothing).
+struct PairLds {
+    int32_t wave_cnt[4];
+    int32_t base;
+};
+
 __device__ __forceinline__ void pair_body(Fp f, int n1, const uint32_t* S, int64_t lds, const int32_t* flag,
                                           const uint32_t* root, int32_t* rank_idx, uint32_t s_lqnr,
-                                          uint32_t c_lqnr, uint32_t z, ColOp* desc)
+                                          uint32_t c_lqnr, uint32_t z, ColOp* desc, PairLds& L)
 {
-    __shared__ int32_t part[1024];
-    __shared__ int32_t base;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t p = f.p;
-    if (tid == 0) base = 0;
+    if (tid == 0) L.base = 0;
     __syncthreads();
     // ordered list of non-residue indices: rank_idx[r] = j
-    for (int c0 = 0; c0 < n1; c0 += 1024) {
+    for (int c0 = 0; c0 < n1; c0 += 256) {
         const int j = c0 + tid;
-        const int v = (j < n1) ? flag[j] : 0;
-        part[tid] = v;
+        const bool v = j < n1 && flag[j] != 0;
+        const uint64_t mask = __ballot(v);
+        const int below = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) L.wave_cnt[wv] = __popcll(mask);
         __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            int t = (tid >= off) ? part[tid - off] : 0;
-            __syncthreads();
-            part[tid] += t;
-            __syncthreads();
-        }
-        if (v) rank_idx[base + part[tid] - 1] = j;
+        int off = L.base;
+        for (int w = 0; w < wv; ++w) off += L.wave_cnt[w];
+        if (v) rank_idx[off + below] = j;
         __syncthreads();
-        if (tid == 1023) base += part[1023];
+        if (tid == 0) L.base += L.wave_cnt[0] + L.wave_cnt[1] + L.wave_cnt[2] + L.wave_cnt[3];
         __syncthreads();
     }
-    const int total = base;
+    const int total = L.base;
     const uint32_t s_inv = inv_m(s_lqnr, p, f.pinv);
     // residues: scale by a square root
-    for (int j = tid; j < n1; j += 1024)
+    for (int j = tid; j < n1; j += 256)
         if (!flag[j]) desc[j] = ColOp{j, root[j], -1, 0u};
     // non-residue pairs (rank 2t, 2t+1); an odd one out pairs with the extra column
-    for (int t = tid; 2 * t < total; t += 1024) {
+    for (int t = tid; 2 * t < total; t += 256) {
         const int i = rank_idx[2 * t];
         const bool has_partner = 2 * t + 1 < total;
         const int j = has_partner ? rank_idx[2 * t + 1] : -1;
@@ -358,50 +386,47 @@ __host__ __device__ inline int row_bands(int64_t rows)
     return (int)(g < 1 ? 1 : (g > kRowBands ? kRowBands : g));
 }
 
-__global__ __launch_bounds__(256) void zero_multi(const LdltDesc* D, int n)
-{
-    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
-    if (threadIdx.x == 0) *d.info = 0;
-}
+// One launch runs the device steps of one level, whatever their kinds:
+// workgroup b takes the descriptor whose block range holds b and runs the
+// step of its kind (uniform per workgroup).  The steps share one LDS area.
+union StepLds {
+    LeafLds leaf;
+    TrsmLds trsm;
+    PairLds pair;
+};
 
-__global__ __launch_bounds__(256) void leaf_multi(const LdltDesc* D, int n)
+__global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n)
 {
-    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
-    ldlt_leaf_body(d.f, d.kb, d.nb, d.X, d.ldx, d.info, d.offset, d.linv);
-}
-
-__global__ __launch_bounds__(256) void trsm_multi(const LdltDesc* D, int n)
-{
-    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
-    trsm_inv_body(d.f, d.kb, d.rows, d.nb, d.X, d.ldx, d.linv, blockIdx.x - d.block0);
-}
-
-__global__ __launch_bounds__(256) void classify_multi(const LdltDesc* D, int n)
-{
-    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
-    classify_body(d.f, d.nb, d.X, d.ldx, d.s_lqnr, d.sc.flag, d.sc.root, d.sc.dinv, blockIdx.x - d.block0);
-}
-
-__global__ __launch_bounds__(1024) void pair_multi(const LdltDesc* D, int n)
-{
-    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
-    pair_body(d.f, d.nb, d.X, d.ldx, d.sc.flag, d.sc.root, d.sc.rank_idx, d.s_lqnr, d.c_lqnr, d.s_lqnr,
-              d.sc.desc);
-}
-
-__global__ __launch_bounds__(256) void scale_multi(const LdltDesc* D, int n)
-{
+    __shared__ __attribute__((aligned(16))) StepLds lds;
     const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
     const int lb = blockIdx.x - d.block0;
-    scale_cols_body(d.f, d.rows, d.nb, d.X, d.ldx, d.sc.dinv, lb % d.gx, lb / d.gx, row_bands(d.rows));
-}
-
-__global__ __launch_bounds__(256) void abar_multi(const LdltDesc* D, int n)
-{
-    const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
-    const int lb = blockIdx.x - d.block0;
-    build_abar_body(d.f, d.rows, d.ncols, d.kpad, d.X, d.ldx, d.sc.desc, d.Ab, d.ldab, lb % d.gx, lb / d.gx,
-                    row_bands(d.rows));
+    switch (d.kind) {
+    case LK_ZERO:
+        if (threadIdx.x == 0) *d.info = 0;
+        break;
+    case LK_LEAF:
+        ldlt_leaf_body(d.f, d.kb, d.nb, d.X, d.ldx, d.info, d.offset, d.linv, lds.leaf);
+        break;
+    case LK_TRSM:
+        trsm_inv_body(d.f, d.kb, d.rows, d.nb, d.X, d.ldx, d.linv, lb, lds.trsm);
+        break;
+    case LK_CLASSIFY:
+        classify_body(d.f, d.nb, d.X, d.ldx, d.s_lqnr, d.sc.flag, d.sc.root, d.sc.dinv, lb);
+        break;
+    case LK_PAIR:
+        pair_body(d.f, d.nb, d.X, d.ldx, d.sc.flag, d.sc.root, d.sc.rank_idx, d.s_lqnr, d.c_lqnr, d.s_lqnr,
+                  d.sc.desc, lds.pair);
+        break;
+    case LK_SCALE:
+        scale_cols_body(d.f, d.rows, d.nb, d.X, d.ldx, d.sc.dinv, lb % d.gx, lb / d.gx, row_bands(d.rows));
+        break;
+    case LK_ABAR:
+        build_abar_body(d.f, d.rows, d.ncols, d.kpad, d.X, d.ldx, d.sc.desc, d.Ab, d.ldab, lb % d.gx, lb / d.gx,
+                        row_bands(d.rows));
+        break;
+    default:
+        break;
+    }
 }
 
 }  // namespace
@@ -431,20 +456,10 @@ int ldlt_blocks(int kind, LdltDesc* d)
     }
 }
 
-hipError_t launch_ldlt_kind(int kind, const LdltDesc* dev, int n, int total_blocks, hipStream_t s)
+hipError_t launch_ldlt_steps(const LdltDesc* dev, int n, int total_blocks, hipStream_t s)
 {
     if (n <= 0 || total_blocks <= 0) return hipSuccess;
-    const dim3 g((unsigned)total_blocks);
-    switch (kind) {
-    case LK_ZERO: hipLaunchKernelGGL(zero_multi, g, dim3(256), 0, s, dev, n); break;
-    case LK_LEAF: hipLaunchKernelGGL(leaf_multi, g, dim3(256), 0, s, dev, n); break;
-    case LK_TRSM: hipLaunchKernelGGL(trsm_multi, g, dim3(256), 0, s, dev, n); break;
-    case LK_CLASSIFY: hipLaunchKernelGGL(classify_multi, g, dim3(256), 0, s, dev, n); break;
-    case LK_PAIR: hipLaunchKernelGGL(pair_multi, g, dim3(1024), 0, s, dev, n); break;
-    case LK_SCALE: hipLaunchKernelGGL(scale_multi, g, dim3(256), 0, s, dev, n); break;
-    case LK_ABAR: hipLaunchKernelGGL(abar_multi, g, dim3(256), 0, s, dev, n); break;
-    default: return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL(ldlt_step_kernel, dim3((unsigned)total_blocks), dim3(256), 0, s, dev, n);
     return hipGetLastError();
 }
 
