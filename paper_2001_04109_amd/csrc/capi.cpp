@@ -202,6 +202,16 @@ int ffp_debug_set(const char* key, int64_t value)
         return FFP_OK;
     }
     if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "i8_waves") == 0) {
+        if (value != 4 && value != 8) return FFP_EINVAL;
+        ffp::g_i8_waves = (int)value;
+        return FFP_OK;
+    }
+    if (strcmp(key, "f64_waves") == 0) {
+        if (value != 4 && value != 8) return FFP_EINVAL;
+        ffp::g_f64_waves = (int)value;
+        return FFP_OK;
+    }
     return FFP_EINVAL;
 }
 
@@ -221,13 +231,15 @@ const char* ffp_debug_variant_name(int variant)
 {
     switch (variant) {
     case 0: return "ffp::prod_f64_kernel(ffp::ProdArgs, int)";
-    case 1: return "ffp::prod_f64_lds_kernel(ffp::ProdArgs, int)";
+    case 1: return "void ffp::prod_f64_lds_kernel<4>(ffp::ProdArgs, int)";
     case 2: return "void ffp::prod_i8_kernel<128, 128, 64, 1>(ffp::ProdArgs, int)";
     case 3: return "void ffp::prod_i8_kernel<256, 256, 64, 1>(ffp::ProdArgs, int)";
     case 4: return "void ffp::prod_i8_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";
     case 5: return "void ffp::prod_i8_kernel<128, 128, 64, 2>(ffp::ProdArgs, int)";
     case 6: return "void ffp::prod_i8_ring_kernel<256, 256, 4>(ffp::ProdArgs, int)";
     case 7: return "void ffp::prod_i8_ring_kernel<256, 256, 5>(ffp::ProdArgs, int)";
+    case 8: return "void ffp::prod_f64_lds_kernel<8>(ffp::ProdArgs, int)";
+    case 9: return "void ffp::prod_i8_kernel<256, 256, 64, 1, 8>(ffp::ProdArgs, int)";
     default: return "";
     }
 }

@@ -249,7 +249,9 @@ int64_t rup256(int64_t x) { return (x + 255) / 256 * 256; }
 
 // Runs the steps of independent jobs level by level: all device steps of a
 // level (whatever their kinds) as one launch over their descriptors,
-// products of one class as one grouped launch, block operations one by one.
+// products of one class as one grouped launch (on a paired stream when the
+// level also has device steps, joined before the level ends), block
+// operations one by one.
 int execute_steps(const std::vector<Step>& steps, hipStream_t s)
 {
     if (steps.empty()) return FFP_OK;
@@ -296,6 +298,19 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
         const int st = acquire_staging(s, desc_bytes + prod_bytes, &host, &dev);
         if (st != FFP_OK) return st;
     }
+    // levels with both device steps and products (of other jobs) run the
+    // products on a paired stream, so that the two overlap
+    bool overlap = false;
+    for (int lv = 0; lv <= maxlev && !overlap; ++lv) {
+        if (!slices[lv].count) continue;
+        for (int i : by[lv])
+            if (steps[i].sk == SK_PROD) { overlap = true; break; }
+    }
+    SideStream* ss = nullptr;
+    if (overlap) {
+        const int st = side_stream(s, &ss);
+        if (st != FFP_OK) return st;
+    }
     if (const int st = capture_point(s); st != FFP_OK) return st;
     if (!table.empty()) {
         memcpy(host, table.data(), table.size() * sizeof(LdltDesc));
@@ -307,7 +322,15 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
     int status = FFP_OK;
     for (int lv = 0; lv <= maxlev && status == FFP_OK; ++lv) {
         const Slice& sl = slices[lv];
-        if (sl.count && launch_ldlt_steps(dtable + sl.first, sl.count, sl.blocks, s) != hipSuccess)
+        bool has_prod = false;
+        for (int i : by[lv]) has_prod = has_prod || steps[i].sk == SK_PROD;
+        hipStream_t ps = s;
+        if (ss && sl.count && has_prod) {
+            if (hipEventRecord(ss->fork, s) != hipSuccess || hipStreamWaitEvent(ss->side, ss->fork, 0) != hipSuccess)
+                status = FFP_EDEVICE;
+            ps = ss->side;
+        }
+        if (status == FFP_OK && sl.count && launch_ldlt_steps(dtable + sl.first, sl.count, sl.blocks, s) != hipSuccess)
             status = FFP_EDEVICE;
         for (int cls = 0; cls < 3 && status == FFP_OK; ++cls) {
             std::vector<ProdTask> g;
@@ -326,7 +349,12 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
                 poff += (size_t)rup256((int64_t)(g.size() * sizeof(ProdTask)));
                 memcpy(tasks, g.data(), g.size() * sizeof(ProdTask));
             }
-            if (launch_products(cls, tasks, (int)g.size(), dtasks, s) != hipSuccess) status = FFP_EDEVICE;
+            if (launch_products(cls, tasks, (int)g.size(), dtasks, ps) != hipSuccess) status = FFP_EDEVICE;
+        }
+        if (ps != s) {
+            // join even after a failure, so that no work is left unordered
+            if (hipEventRecord(ss->join, ps) != hipSuccess || hipStreamWaitEvent(s, ss->join, 0) != hipSuccess)
+                status = FFP_EDEVICE;
         }
         for (int i : by[lv]) {
             if (status != FFP_OK) break;

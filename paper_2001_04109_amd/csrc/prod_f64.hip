@@ -144,24 +144,35 @@ __device__ __forceinline__ void f64_tile(const ProdArgs& args, int b)
 }
 
 // ---- 128 x 128 tiles through LDS -------------------------------------------
-// Workgroup tile 128 x 128, waves 2 x 2 of 64 x 64 (4 x 4 MFMA blocks).  Per
-// stage of 32 columns of k the A and B panels (128 rows x 128 bytes each)
-// are copied global -> registers -> LDS (double-buffered; the loads for the
-// next stage are issued before the MFMAs of the current one).  Each lane
-// reads 16 bytes (4 consecutive k) per row block from LDS and feeds them to
-// four MFMA steps, as in the direct kernel.
+// Workgroup tile 128 x 128 of NW waves: 4 waves of 64 x 64 (4 x 4 MFMA
+// blocks) or 8 waves of 64 x 32 (4 x 2 blocks; half the accumulators per
+// wave, so that two waves share each SIMD and hide each other's LDS and
+// barrier waits).  Per stage of 32 columns of k the A and B panels (128
+// rows x 128 bytes each) are copied global -> registers -> LDS
+// (double-buffered; the loads for the next stage are issued before the
+// MFMAs of the current one).  Each lane reads 16 bytes (4 consecutive k)
+// per row block from LDS and feeds them to four MFMA steps, as in the
+// direct kernel.
 namespace {
 constexpr int BM2 = 128, BK2 = 32, PITCH2 = BK2 + 4;   // u32 units
-constexpr int WM2 = 4, WN2 = 4;
 
-struct Pf2 { uint4 v[4]; };   // 128 rows x 32 u32 / 256 threads = 4 x 16 bytes
+template <int NW>
+struct F64Lds {
+    static constexpr int NT = 64 * NW;
+    static constexpr int WCOLS = NW / 2;            // waves across the columns
+    static constexpr int WTN = BM2 / WCOLS;         // wave tile columns
+    static constexpr int WM = 4, WN = WTN / 16;     // 16 x 16 MFMA blocks per wave
+    static constexpr int PASSES = BM2 * (BK2 / 4) / NT;
+    struct Pf { uint4 v[PASSES]; };
+};
 
-__device__ inline void gload2(Pf2& pf, const uint32_t* __restrict__ g, int64_t ld, int row0, int nrows,
-                              int k0, int K, bool vec_ok)
+template <int NW>
+__device__ inline void gload2(typename F64Lds<NW>::Pf& pf, const uint32_t* __restrict__ g, int64_t ld, int row0,
+                              int nrows, int k0, int K, bool vec_ok)
 {
 #pragma unroll
-    for (int ps = 0; ps < 4; ++ps) {
-        const int idx = ps * 256 + threadIdx.x;
+    for (int ps = 0; ps < F64Lds<NW>::PASSES; ++ps) {
+        const int idx = ps * F64Lds<NW>::NT + threadIdx.x;
         const int r = idx >> 3, c = (idx & 7) * 4;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         const int row = row0 + r, kc = k0 + c;
@@ -181,19 +192,23 @@ __device__ inline void gload2(Pf2& pf, const uint32_t* __restrict__ g, int64_t l
     }
 }
 
-__device__ inline void lstore2(uint32_t* __restrict__ lds, const Pf2& pf)
+template <int NW>
+__device__ inline void lstore2(uint32_t* __restrict__ lds, const typename F64Lds<NW>::Pf& pf)
 {
 #pragma unroll
-    for (int ps = 0; ps < 4; ++ps) {
-        const int idx = ps * 256 + threadIdx.x;
+    for (int ps = 0; ps < F64Lds<NW>::PASSES; ++ps) {
+        const int idx = ps * F64Lds<NW>::NT + threadIdx.x;
         const int r = idx >> 3, c = (idx & 7) * 4;
         *reinterpret_cast<uint4*>(lds + r * PITCH2 + c) = pf.v[ps];
     }
 }
 }  // namespace
 
+template <int NW>
 __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
 {
+    using G = F64Lds<NW>;
+    constexpr int WM2 = G::WM, WN2 = G::WN;
     __shared__ __attribute__((aligned(16))) uint32_t sa[2][BM2 * PITCH2];
     __shared__ __attribute__((aligned(16))) uint32_t sb[2][BM2 * PITCH2];
     ProdTask t;
@@ -204,7 +219,7 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
     else { ti = r / t.tn; tj = r - ti * t.tn; }
     const int tile_r = ti * BM2, tile_c = tj * BM2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / G::WCOLS, wc = wave % G::WCOLS;
     const int lr = lane & 15, lk = lane >> 4;
     const uint32_t* __restrict__ Ab = (const uint32_t*)t.A.p;
     const uint32_t* __restrict__ Bb = (const uint32_t*)t.B.p;
@@ -220,12 +235,12 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
 #pragma unroll
         for (int j = 0; j < WN2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    Pf2 pa, pb;
+    typename G::Pf pa, pb;
     if (nk > 0) {
-        gload2(pa, Ab, t.A.ld, tile_r, t.m, 0, K, vec_ok);
-        gload2(pb, Bb, t.B.ld, tile_c, t.n, 0, K, vec_ok);
-        lstore2(sa[0], pa);
-        lstore2(sb[0], pb);
+        gload2<NW>(pa, Ab, t.A.ld, tile_r, t.m, 0, K, vec_ok);
+        gload2<NW>(pb, Bb, t.B.ld, tile_c, t.n, 0, K, vec_ok);
+        lstore2<NW>(sa[0], pa);
+        lstore2<NW>(sb[0], pb);
     }
     __syncthreads();
     // k-blocks of kblk columns (a multiple of BK2); the accumulators are
@@ -237,8 +252,8 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
             const int cur = kt & 1;
             const bool more = kt + 1 < nk;
             if (more) {
-                gload2(pa, Ab, t.A.ld, tile_r, t.m, (kt + 1) * BK2, K, vec_ok);
-                gload2(pb, Bb, t.B.ld, tile_c, t.n, (kt + 1) * BK2, K, vec_ok);
+                gload2<NW>(pa, Ab, t.A.ld, tile_r, t.m, (kt + 1) * BK2, K, vec_ok);
+                gload2<NW>(pb, Bb, t.B.ld, tile_c, t.n, (kt + 1) * BK2, K, vec_ok);
             }
 #pragma unroll
             for (int kg = 0; kg < BK2 / 16; ++kg) {
@@ -248,7 +263,8 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
                     ua[i] = *reinterpret_cast<const uint4*>(&sa[cur][(wr * 64 + i * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
 #pragma unroll
                 for (int j = 0; j < WN2; ++j)
-                    ub[j] = *reinterpret_cast<const uint4*>(&sb[cur][(wc * 64 + j * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
+                    ub[j] = *reinterpret_cast<const uint4*>(
+                        &sb[cur][(wc * G::WTN + j * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     double av[WM2], bv[WN2];
@@ -266,8 +282,8 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
                 }
             }
             if (more) {
-                lstore2(sa[cur ^ 1], pa);
-                lstore2(sb[cur ^ 1], pb);
+                lstore2<NW>(sa[cur ^ 1], pa);
+                lstore2<NW>(sb[cur ^ 1], pb);
             }
             __syncthreads();
         }
@@ -286,7 +302,7 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
     for (int i = 0; i < WM2; ++i) {
 #pragma unroll
         for (int j = 0; j < WN2; ++j) {
-            const int col = tile_c + wc * 64 + j * 16 + lr;
+            const int col = tile_c + wc * G::WTN + j * 16 + lr;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = tile_r + wr * 64 + i * 16 + 4 * e + lk;
@@ -314,14 +330,15 @@ __global__ __launch_bounds__(256) void prod_f64_kernel(ProdArgs args, int mode)
     if (b < args.total_tiles) f64_tile(args, b);
 }
 
-__global__ __launch_bounds__(256) void prod_f64_lds_kernel(ProdArgs args, int mode)
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void prod_f64_lds_kernel(ProdArgs args, int mode)
 {
     if (mode == 2) {
-        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) f64_lds_tile(args, b);
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) f64_lds_tile<NW>(args, b);
         return;
     }
     const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (b < args.total_tiles) f64_lds_tile(args, b);
+    if (b < args.total_tiles) f64_lds_tile<NW>(args, b);
 }
 
 int64_t f64_kblk(uint32_t p)
@@ -334,6 +351,8 @@ int64_t f64_kblk(uint32_t p)
     k -= k % 16;
     return k;
 }
+
+int g_f64_waves = 4;
 
 template <int TILE>
 static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
@@ -361,16 +380,21 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
     }
     const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
     int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
+    const bool w8 = TILE == 128 && g_f64_waves == 8;
+    const void* kern = TILE != 128 ? (const void*)prod_f64_kernel
+                                   : (w8 ? (const void*)prod_f64_lds_kernel<8> : (const void*)prod_f64_lds_kernel<4>);
+    const int threads = w8 ? 512 : 256;
     if (mode == 2) {
-        const int resident = resident_blocks(TILE == 128 ? (const void*)prod_f64_lds_kernel
-                                                         : (const void*)prod_f64_kernel);
+        const int resident = resident_blocks(kern, threads);
         grid = total < resident ? total : resident;
     }
-    g_last_variant = TILE == 128 ? 1 : 0;
-    if (TILE == 128)
-        hipLaunchKernelGGL(prod_f64_lds_kernel, dim3(grid), dim3(256), 0, s, args, mode);
-    else
+    g_last_variant = TILE == 128 ? (w8 ? 8 : 1) : 0;
+    if (TILE != 128)
         hipLaunchKernelGGL(prod_f64_kernel, dim3(grid), dim3(256), 0, s, args, mode);
+    else if (w8)
+        hipLaunchKernelGGL((prod_f64_lds_kernel<8>), dim3(grid), dim3(512), 0, s, args, mode);
+    else
+        hipLaunchKernelGGL((prod_f64_lds_kernel<4>), dim3(grid), dim3(256), 0, s, args, mode);
     return hipGetLastError();
 }
 

@@ -96,6 +96,34 @@ int capture_point(hipStream_t s)
     return FFP_OK;
 }
 
+namespace {
+std::map<std::pair<int, hipStream_t>, SideStream> g_side;
+}  // namespace
+
+int side_stream(hipStream_t s, SideStream** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FFP_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    SideStream& ss = g_side[std::make_pair(dev, s)];
+    if (!ss.side) {
+        if (g_cap && g_cap->capturing) return FFP_EUNSUPPORTED;
+        if (note_hip("hipStreamCreateWithFlags", hipStreamCreateWithFlags(&ss.side, hipStreamNonBlocking)) !=
+                hipSuccess ||
+            note_hip("hipEventCreateWithFlags", hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) !=
+                hipSuccess ||
+            note_hip("hipEventCreateWithFlags", hipEventCreateWithFlags(&ss.join, hipEventDisableTiming)) !=
+                hipSuccess) {
+            if (ss.side) (void)hipStreamDestroy(ss.side);
+            if (ss.fork) (void)hipEventDestroy(ss.fork);
+            ss = SideStream{};
+            return FFP_EDEVICE;
+        }
+    }
+    *out = &ss;
+    return FFP_OK;
+}
+
 int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** out)
 {
     if (CaptureCtx* c = g_cap) {
@@ -236,7 +264,7 @@ int64_t g_kblk_cap = 0;
 int g_persistent = 1;
 thread_local int g_last_variant = -1;
 
-int resident_blocks(const void* kernel)
+int resident_blocks(const void* kernel, int threads)
 {
     static int cus = 0;
     int dev = 0;
@@ -246,7 +274,7 @@ int resident_blocks(const void* kernel)
             cus = 256;
     }
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per <= 0) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per <= 0) per = 1;
     return per * cus;
 }
 

@@ -31,6 +31,17 @@ int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** ou
 int acquire_staging(hipStream_t s, size_t bytes, char** host, char** dev);
 int release_staging(hipStream_t s);
 
+// A second stream paired with s (created on first use: non-blocking,
+// default priority) and two events, for work that runs beside s inside one
+// call: record `fork` on s, make `side` wait for it, enqueue on side, record
+// `join` on side, make s wait for it.  Lives until the process ends.  Must
+// be obtained before a capture begins (capture_point).
+struct SideStream {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+int side_stream(hipStream_t s, SideStream** out);
+
 // Records which HIP call failed (with its error name) for
 // ffp_last_error_detail; returns e.
 hipError_t note_hip(const char* where, hipError_t e);
