@@ -59,9 +59,8 @@ void ffp_debug_set_kblk(int64_t kblk);
 
 /* Tuning and test knobs (process-wide): "kblk" (as ffp_debug_set_kblk),
  * "f64_tile" (64 or 128: force the FP64 product tile; 0 = automatic),
- * "f64_waves" (4, the default, or 8: waves per 128 x 128 FP64 workgroup;
- * other values FFP_EINVAL), "i8_waves" (4, the default, or 8: waves per
- * 256 x 256 int8 workgroup; 8 waves use 64-byte k stages),
+ * "f64_waves" (8, the default, or 4: waves per 128 x 128 FP64 workgroup;
+ * other values FFP_EINVAL),
  * "i8_tile" (128 or 256: force the int8 product tile; 0 = automatic),
  * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile),
  * "i8_ring" (4 or 5: the 256 x 256 int8 tile loads its operands straight

@@ -202,11 +202,6 @@ int ffp_debug_set(const char* key, int64_t value)
         return FFP_OK;
     }
     if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value ? 1 : 0; return FFP_OK; }
-    if (strcmp(key, "i8_waves") == 0) {
-        if (value != 4 && value != 8) return FFP_EINVAL;
-        ffp::g_i8_waves = (int)value;
-        return FFP_OK;
-    }
     if (strcmp(key, "f64_waves") == 0) {
         if (value != 4 && value != 8) return FFP_EINVAL;
         ffp::g_f64_waves = (int)value;
@@ -239,7 +234,6 @@ const char* ffp_debug_variant_name(int variant)
     case 6: return "void ffp::prod_i8_ring_kernel<256, 256, 4>(ffp::ProdArgs, int)";
     case 7: return "void ffp::prod_i8_ring_kernel<256, 256, 5>(ffp::ProdArgs, int)";
     case 8: return "void ffp::prod_f64_lds_kernel<8>(ffp::ProdArgs, int)";
-    case 9: return "void ffp::prod_i8_kernel<256, 256, 64, 1, 8>(ffp::ProdArgs, int)";
     default: return "";
     }
 }

@@ -71,8 +71,7 @@ extern int64_t g_kblk_cap;
 extern int g_f64_tile_override;
 extern int g_i8_tile_override;
 extern int g_i8_bk_override;
-extern int g_f64_waves;        // waves per 128 x 128 FP64 workgroup: 4 (default) or 8
-extern int g_i8_waves;         // waves per 256 x 256 int8 workgroup: 4 (default) or 8
+extern int g_f64_waves;        // waves per 128 x 128 FP64 workgroup: 8 (default) or 4
 // Tile edge chosen for the product launches of the current call on this
 // thread (0: the launch rule or the override above); set from the tuned
 // choice of the call's plan.
@@ -84,8 +83,7 @@ extern int g_persistent;
 // Product-kernel variant chosen by the most recent launch on this thread
 // (for the timing hooks): 0 FP64 64x64, 1 FP64 128x128 LDS (4 waves), 2 int8
 // 128x128, 3 int8 256x256 (k stage 64), 4 int8 256x256 (k stage 128), 5 int8
-// limbs, 6 and 7 int8 ring, 8 FP64 128x128 LDS (8 waves), 9 int8 256x256
-// (k stage 64, 8 waves).
+// limbs, 6 and 7 int8 ring, 8 FP64 128x128 LDS (8 waves).
 extern thread_local int g_last_variant;
 // Workgroups of `kernel` (256 threads) resident at once on the device.
 int resident_blocks(const void* kernel, int threads = 256);

@@ -192,25 +192,44 @@ __device__ inline void gload2(typename F64Lds<NW>::Pf& pf, const uint32_t* __res
     }
 }
 
+// Residues are stored centred (as int32 bit patterns), so a fragment value
+// only needs one conversion to double.
 template <int NW>
-__device__ inline void lstore2(uint32_t* __restrict__ lds, const typename F64Lds<NW>::Pf& pf)
+__device__ inline void lstore2(uint32_t* __restrict__ lds, const typename F64Lds<NW>::Pf& pf, uint32_t half,
+                               uint32_t p)
 {
 #pragma unroll
     for (int ps = 0; ps < F64Lds<NW>::PASSES; ++ps) {
         const int idx = ps * F64Lds<NW>::NT + threadIdx.x;
         const int r = idx >> 3, c = (idx & 7) * 4;
-        *reinterpret_cast<uint4*>(lds + r * PITCH2 + c) = pf.v[ps];
+        const uint4 v = pf.v[ps];
+        *reinterpret_cast<uint4*>(lds + r * PITCH2 + c) =
+            make_uint4(v.x > half ? v.x - p : v.x, v.y > half ? v.y - p : v.y, v.z > half ? v.z - p : v.z,
+                       v.w > half ? v.w - p : v.w);
     }
+}
+
+__device__ inline double sel4(const uint4& q, int s)
+{
+    return (double)(int32_t)(s == 0 ? q.x : s == 1 ? q.y : s == 2 ? q.z : q.w);
 }
 }  // namespace
 
+// Three LDS buffers: stage t is read from buffer t % 3 while the loads of
+// stage t + 2 are in flight and are written to buffer (t + 2) % 3 at its
+// end (that buffer was last read in stage t - 1, before the previous
+// barrier).  Stage t + 1 was published by the barrier that ended stage
+// t - 1, so the fragments of its first k-group are read during the last
+// MFMAs of stage t, and the k-groups inside a stage are likewise read one
+// ahead: no LDS latency sits between the matrix instructions.
 template <int NW>
 __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
 {
     using G = F64Lds<NW>;
     constexpr int WM2 = G::WM, WN2 = G::WN;
-    __shared__ __attribute__((aligned(16))) uint32_t sa[2][BM2 * PITCH2];
-    __shared__ __attribute__((aligned(16))) uint32_t sb[2][BM2 * PITCH2];
+    constexpr int NBUF = 3, KG = BK2 / 16;
+    __shared__ __attribute__((aligned(16))) uint32_t sa[NBUF][BM2 * PITCH2];
+    __shared__ __attribute__((aligned(16))) uint32_t sb[NBUF][BM2 * PITCH2];
     ProdTask t;
     select_task(args, b, &t);
     const int r = b - t.tile0;
@@ -236,44 +255,55 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
         for (int j = 0; j < WN2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
     typename G::Pf pa, pb;
-    if (nk > 0) {
-        gload2<NW>(pa, Ab, t.A.ld, tile_r, t.m, 0, K, vec_ok);
-        gload2<NW>(pb, Bb, t.B.ld, tile_c, t.n, 0, K, vec_ok);
-        lstore2<NW>(sa[0], pa);
-        lstore2<NW>(sb[0], pb);
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+        if (st < nk) {
+            gload2<NW>(pa, Ab, t.A.ld, tile_r, t.m, st * BK2, K, vec_ok);
+            gload2<NW>(pb, Bb, t.B.ld, tile_c, t.n, st * BK2, K, vec_ok);
+            lstore2<NW>(sa[st], pa, t.half, t.p);
+            lstore2<NW>(sb[st], pb, t.half, t.p);
+        }
     }
     __syncthreads();
+    auto read_frags = [&](uint4 (&xa)[WM2], uint4 (&xb)[WN2], int buf, int kg) {
+#pragma unroll
+        for (int i = 0; i < WM2; ++i)
+            xa[i] = *reinterpret_cast<const uint4*>(&sa[buf][(wr * 64 + i * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
+#pragma unroll
+        for (int j = 0; j < WN2; ++j)
+            xb[j] = *reinterpret_cast<const uint4*>(&sb[buf][(wc * G::WTN + j * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
+    };
+    // fragments double-buffered in registers: k-group g of a stage uses set
+    // g & 1 (KG is even, so the first k-group of every stage uses set 0)
+    static_assert(KG % 2 == 0, "fragment sets alternate per k-group");
+    uint4 fa[2][WM2], fb[2][WN2];
+    if (nk > 0) read_frags(fa[0], fb[0], 0, 0);
     // k-blocks of kblk columns (a multiple of BK2); the accumulators are
     // reduced mod p after every block, outside the stage loop.
     const int nkb = t.kblk / BK2;
     for (int kb0 = 0; kb0 < nk; kb0 += nkb) {
         const int kend = min(kb0 + nkb, nk);
         for (int kt = kb0; kt < kend; ++kt) {
-            const int cur = kt & 1;
-            const bool more = kt + 1 < nk;
-            if (more) {
-                gload2<NW>(pa, Ab, t.A.ld, tile_r, t.m, (kt + 1) * BK2, K, vec_ok);
-                gload2<NW>(pb, Bb, t.B.ld, tile_c, t.n, (kt + 1) * BK2, K, vec_ok);
+            const int cur = kt % NBUF;
+            const bool load2 = kt + 2 < nk;
+            if (load2) {
+                gload2<NW>(pa, Ab, t.A.ld, tile_r, t.m, (kt + 2) * BK2, K, vec_ok);
+                gload2<NW>(pb, Bb, t.B.ld, tile_c, t.n, (kt + 2) * BK2, K, vec_ok);
             }
 #pragma unroll
-            for (int kg = 0; kg < BK2 / 16; ++kg) {
-                uint4 ua[WM2], ub[WN2];
-#pragma unroll
-                for (int i = 0; i < WM2; ++i)
-                    ua[i] = *reinterpret_cast<const uint4*>(&sa[cur][(wr * 64 + i * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
-#pragma unroll
-                for (int j = 0; j < WN2; ++j)
-                    ub[j] = *reinterpret_cast<const uint4*>(
-                        &sb[cur][(wc * G::WTN + j * 16 + lr) * PITCH2 + kg * 16 + 4 * lk]);
+            for (int kg = 0; kg < KG; ++kg) {
+                // fragments of the next k-group (this stage or the next one)
+                // no branch here (one scheduling region per k-group): after
+                // the last stage this reads a stale buffer, which is never used
+                if (kg + 1 < KG) read_frags(fa[(kg + 1) & 1], fb[(kg + 1) & 1], cur, kg + 1);
+                else read_frags(fa[(kg + 1) & 1], fb[(kg + 1) & 1], (kt + 1) % NBUF, 0);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     double av[WM2], bv[WN2];
 #pragma unroll
-                    for (int i = 0; i < WM2; ++i)
-                        av[i] = centred(s == 0 ? ua[i].x : s == 1 ? ua[i].y : s == 2 ? ua[i].z : ua[i].w, t.half, t.p);
+                    for (int i = 0; i < WM2; ++i) av[i] = sel4(fa[kg & 1][i], s);
 #pragma unroll
-                    for (int j = 0; j < WN2; ++j)
-                        bv[j] = centred(s == 0 ? ub[j].x : s == 1 ? ub[j].y : s == 2 ? ub[j].z : ub[j].w, t.half, t.p);
+                    for (int j = 0; j < WN2; ++j) bv[j] = sel4(fb[kg & 1][j], s);
 #pragma unroll
                     for (int i = 0; i < WM2; ++i)
 #pragma unroll
@@ -281,9 +311,9 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
                             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
                 }
             }
-            if (more) {
-                lstore2<NW>(sa[cur ^ 1], pa);
-                lstore2<NW>(sb[cur ^ 1], pb);
+            if (load2) {
+                lstore2<NW>(sa[(kt + 2) % NBUF], pa, t.half, t.p);
+                lstore2<NW>(sb[(kt + 2) % NBUF], pb, t.half, t.p);
             }
             __syncthreads();
         }
@@ -352,7 +382,7 @@ int64_t f64_kblk(uint32_t p)
     return k;
 }
 
-int g_f64_waves = 4;
+int g_f64_waves = 8;
 
 template <int TILE>
 static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)

@@ -90,23 +90,23 @@ __device__ inline void band_tri(int r, int T, int* ti, int* tj)
     *ti = b * G + c + loc;
 }
 
-template <int ROWS, int BK, int NT = 256>
+template <int ROWS, int BK>
 struct Prefetch {
     static constexpr int PITCH = BK + 16;   // padded LDS row pitch
     static constexpr int CHUNKS = BK / 16;
-    static constexpr int PASSES = ROWS * CHUNKS / NT;
-    static_assert(ROWS * CHUNKS % NT == 0, "panel must split evenly over the threads");
+    static constexpr int PASSES = ROWS * CHUNKS / 256;
+    static_assert(ROWS * CHUNKS % 256 == 0, "panel must split evenly over 256 threads");
     v4i v[PASSES];
 };
 
-template <int ROWS, int BK, int NT>
-__device__ inline void gload(Prefetch<ROWS, BK, NT>& pf, const int8_t* __restrict__ g, int64_t ld, int row0,
+template <int ROWS, int BK>
+__device__ inline void gload(Prefetch<ROWS, BK>& pf, const int8_t* __restrict__ g, int64_t ld, int row0,
                              int nrows, int k0)
 {
-    constexpr int CHUNKS = Prefetch<ROWS, BK, NT>::CHUNKS;
+    constexpr int CHUNKS = Prefetch<ROWS, BK>::CHUNKS;
 #pragma unroll
-    for (int ps = 0; ps < Prefetch<ROWS, BK, NT>::PASSES; ++ps) {
-        const int idx = ps * NT + threadIdx.x;
+    for (int ps = 0; ps < Prefetch<ROWS, BK>::PASSES; ++ps) {
+        const int idx = ps * 256 + threadIdx.x;
         const int r = idx / CHUNKS, c = idx % CHUNKS;
         // Rows past the end re-read the last row: they only feed output rows
         // (or columns) past the end, which the epilogue never stores.
@@ -116,15 +116,15 @@ __device__ inline void gload(Prefetch<ROWS, BK, NT>& pf, const int8_t* __restric
     }
 }
 
-template <int ROWS, int BK, int NT>
-__device__ inline void lstore(int8_t* __restrict__ lds, const Prefetch<ROWS, BK, NT>& pf)
+template <int ROWS, int BK>
+__device__ inline void lstore(int8_t* __restrict__ lds, const Prefetch<ROWS, BK>& pf)
 {
-    constexpr int CHUNKS = Prefetch<ROWS, BK, NT>::CHUNKS;
+    constexpr int CHUNKS = Prefetch<ROWS, BK>::CHUNKS;
 #pragma unroll
-    for (int ps = 0; ps < Prefetch<ROWS, BK, NT>::PASSES; ++ps) {
-        const int idx = ps * NT + threadIdx.x;
+    for (int ps = 0; ps < Prefetch<ROWS, BK>::PASSES; ++ps) {
+        const int idx = ps * 256 + threadIdx.x;
         const int r = idx / CHUNKS, c = idx % CHUNKS;
-        *reinterpret_cast<v4i*>(lds + r * Prefetch<ROWS, BK, NT>::PITCH + c * 16) = pf.v[ps];
+        *reinterpret_cast<v4i*>(lds + r * Prefetch<ROWS, BK>::PITCH + c * 16) = pf.v[ps];
     }
 }
 
@@ -191,15 +191,12 @@ __device__ __forceinline__ void store_tile_i8_reg(const v16i (&acc)[FM][FN], con
         }
 }
 
-// PLANES = 1: CLS_I8;  PLANES = 2: CLS_LIMB2.  BK: k bytes per stage.  NW
-// waves in 2 rows of NW / 2 (8 waves: half the accumulators per wave, two
-// waves per SIMD).
-template <int BM, int BN, int BK, int PLANES, int NW = 4>
+// PLANES = 1: CLS_I8;  PLANES = 2: CLS_LIMB2.  BK: k bytes per stage.
+template <int BM, int BN, int BK, int PLANES>
 __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
 {
-    constexpr int NT = 64 * NW;
     constexpr int PITCH = BK + 16;
-    constexpr int WTM = BM / 2, WTN = BN / (NW / 2);  // wave tile
+    constexpr int WTM = BM / 2, WTN = BN / 2;         // wave tile
     constexpr int FM = WTM / 32, FN = WTN / 32;       // 32x32 blocks per wave
     constexpr int NACC = PLANES == 1 ? 1 : 3;
     constexpr int SA = 2 * PLANES * BM * PITCH, SB = 2 * PLANES * BN * PITCH;
@@ -216,7 +213,7 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
     const int tile_r = ti * BM, tile_c = tj * BN;
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wr = wave / (NW / 2), wc = wave % (NW / 2);
+    const int wr = wave >> 1, wc = wave & 1;
     const int lrow = lane & 31, lk = lane >> 5;      // lane -> (row in block, 16-byte k half)
 
     const int8_t* __restrict__ Ab = (const int8_t*)t.A.p;
@@ -237,18 +234,18 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
     const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
 
     const int nk = t.k / BK;
-    Prefetch<BM, BK, NT> pa[PLANES];
-    Prefetch<BN, BK, NT> pb[PLANES];
+    Prefetch<BM, BK> pa[PLANES];
+    Prefetch<BN, BK> pb[PLANES];
     if (nk > 0) {
 #pragma unroll
         for (int pl = 0; pl < PLANES; ++pl) {
-            gload<BM, BK, NT>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, 0);
-            gload<BN, BK, NT>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, 0);
+            gload<BM, BK>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, 0);
+            gload<BN, BK>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, 0);
         }
 #pragma unroll
         for (int pl = 0; pl < PLANES; ++pl) {
-            lstore<BM, BK, NT>(sa[0][pl], pa[pl]);
-            lstore<BN, BK, NT>(sb[0][pl], pb[pl]);
+            lstore<BM, BK>(sa[0][pl], pa[pl]);
+            lstore<BN, BK>(sb[0][pl], pb[pl]);
         }
     }
     __syncthreads();
@@ -294,8 +291,8 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
         if (more) {
 #pragma unroll
             for (int pl = 0; pl < PLANES; ++pl) {
-                gload<BM, BK, NT>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 1) * BK);
-                gload<BN, BK, NT>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
+                gload<BM, BK>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 1) * BK);
+                gload<BN, BK>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
             }
         }
 #pragma unroll
@@ -324,8 +321,8 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
         if (more) {
 #pragma unroll
             for (int pl = 0; pl < PLANES; ++pl) {
-                lstore<BM, BK, NT>(sa[cur ^ 1][pl], pa[pl]);
-                lstore<BN, BK, NT>(sb[cur ^ 1][pl], pb[pl]);
+                lstore<BM, BK>(sa[cur ^ 1][pl], pa[pl]);
+                lstore<BN, BK>(sb[cur ^ 1][pl], pb[pl]);
             }
         }
         __syncthreads();
@@ -547,21 +544,21 @@ __global__ __launch_bounds__(256) void prod_i8_ring_kernel(ProdArgs args, int mo
 }
 
 // mode 0: one workgroup per tile; 1: same, XCD-aware order; 2: persistent.
-template <int BM, int BN, int BK, int PLANES, int NW = 4>
-__global__ __launch_bounds__(64 * NW) void prod_i8_kernel(ProdArgs args, int mode)
+template <int BM, int BN, int BK, int PLANES>
+__global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int mode)
 {
     if (mode == 2) {
         for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x)
-            i8_tile<BM, BN, BK, PLANES, NW>(args, b);
+            i8_tile<BM, BN, BK, PLANES>(args, b);
         return;
     }
     const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (b < args.total_tiles) i8_tile<BM, BN, BK, PLANES, NW>(args, b);
+    if (b < args.total_tiles) i8_tile<BM, BN, BK, PLANES>(args, b);
 }
 
 namespace {
 
-template <int BM, int BN, int BK, int PLANES, int RING, int NW = 4>
+template <int BM, int BN, int BK, int PLANES, int RING>
 hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     ProdArgs args{};
@@ -596,11 +593,11 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         hipLaunchKernelGGL((prod_i8_ring_kernel<BM, BN, RING>), dim3(grid), dim3(256), 0, s, args, mode);
     } else {
         if (mode == 2) {
-            const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES, NW>, 64 * NW);
+            const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES>);
             grid = total < resident ? total : resident;
         }
-        g_last_variant = NW == 8 ? 9 : (PLANES == 2 ? 5 : (BM == 128 ? 2 : (BK == 64 ? 3 : 4)));
-        hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES, NW>), dim3(grid), dim3(64 * NW), 0, s, args, mode);
+        g_last_variant = PLANES == 2 ? 5 : (BM == 128 ? 2 : (BK == 64 ? 3 : 4));
+        hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
     }
     return hipGetLastError();
 }
@@ -609,7 +606,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
 // block length the task runs as consecutive launches over k-chunks, each
 // accumulating into C (beta = 1 after the first), which reduces mod p
 // between chunks.
-template <int BM, int BN, int BK, int PLANES, int RING = 0, int NW = 4>
+template <int BM, int BN, int BK, int PLANES, int RING = 0>
 hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     int32_t maxk = 0, kblk = 1 << 30;
@@ -627,7 +624,7 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         kblk = t.kblk < kblk ? t.kblk : kblk;
         maxk = t.k > maxk ? t.k : maxk;
     }
-    if (maxk <= kblk) return launch_i8_once<BM, BN, BK, PLANES, RING, NW>(tasks, ntasks, dev_task_buf, s);
+    if (maxk <= kblk) return launch_i8_once<BM, BN, BK, PLANES, RING>(tasks, ntasks, dev_task_buf, s);
     std::vector<ProdTask> part(tasks, tasks + ntasks);
     for (int32_t k0 = 0; k0 < maxk; k0 += kblk) {
         int np = 0;
@@ -644,7 +641,7 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         // chunk launches carry their tasks inline (no staging copy outlives `part`)
         for (int q0 = 0; q0 < np; q0 += kInlineTasks) {
             const int nq = np - q0 < kInlineTasks ? np - q0 : kInlineTasks;
-            hipError_t e = launch_i8_once<BM, BN, BK, PLANES, RING, NW>(part.data() + q0, nq, nullptr, s);
+            hipError_t e = launch_i8_once<BM, BN, BK, PLANES, RING>(part.data() + q0, nq, nullptr, s);
             if (e != hipSuccess) return e;
         }
     }
@@ -666,7 +663,6 @@ int64_t tiles_of(const ProdTask* tasks, int ntasks, int bm)
 int g_i8_tile_override = 0;
 int g_i8_bk_override = 0;
 int g_i8_ring = 0;
-int g_i8_waves = 4;
 
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
@@ -680,7 +676,6 @@ hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_bu
     if (big) {
         if (g_i8_ring == 4) return launch_i8_impl<256, 256, 64, 1, 4>(tasks, ntasks, dev_task_buf, s);
         if (g_i8_ring == 5) return launch_i8_impl<256, 256, 64, 1, 5>(tasks, ntasks, dev_task_buf, s);
-        if (g_i8_waves == 8) return launch_i8_impl<256, 256, 64, 1, 0, 8>(tasks, ntasks, dev_task_buf, s);
         if (g_i8_bk_override == 64 || !k128) return launch_i8_impl<256, 256, 64, 1>(tasks, ntasks, dev_task_buf, s);
         return launch_i8_impl<256, 256, 128, 1>(tasks, ntasks, dev_task_buf, s);
     }
