@@ -82,6 +82,12 @@ extern "C" {
  * so that they run together; that needs more workspace (see
  * ffp_workspace_bytes).  Results are identical. */
 #define FFP_LOW_MEMORY    0x200u
+/* Run the base products on three int8 limbs (value = l + 256 m + 65536 h of
+ * the centred residue, nine int8 matrix-core products per block, exact
+ * int32 sums) instead of FP64 matrix cores; FFP_U32 operands, p < 2^23,
+ * no recursion (depth 0).  The autotuner chooses it where it is faster.
+ * Not with FFP_BASE_F64 (FFP_EINVAL); other storage or p: FFP_EDTYPE. */
+#define FFP_BASE_LIMB3    0x400u
 
 /* lower(C) <- (alpha * A * A^T + beta * lower(C)) mod p.
  * Algorithm 2 (Ensure: the lower triangle of A*A^T) in the accumulate form
@@ -94,7 +100,8 @@ extern "C" {
  *   alpha, beta  residues in [0,p).
  *   C, ldc   device pointer, ldc >= n.  Entries of lower(C) must be in
  *            [0,p) when beta != 0.
- *   flags    FFP_FILL_UPPER, FFP_DEPTH(d), FFP_BASE_F64.
+ *   flags    FFP_FILL_UPPER, FFP_DEPTH(d), FFP_BASE_F64, FFP_BASE_LIMB3,
+ *            FFP_LOW_MEMORY.
  * Errors: FFP_EINVAL, FFP_EPRIME, FFP_EDTYPE, FFP_ENOMEM, FFP_EDEVICE. */
 int fsyrk_modp(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int a_dtype,
                uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, unsigned flags,
@@ -188,6 +195,7 @@ typedef struct ffp_tune_result {
     int32_t depth;       /* levels of Algorithm 2 */
     int32_t tile;        /* product tile edge (0: the launch rule) */
     int32_t wide;        /* 1: wide placements, 0: those of Tables 3 and 4 */
+    int32_t base;        /* 0: the base path of p; 3: three int8 limbs (FFP_BASE_LIMB3) */
     int32_t candidates;  /* configurations timed */
     double ms;           /* time of one call with the choice (at tuning) */
     double rule_ms;      /* time of one call with the built-in rule */
@@ -195,8 +203,9 @@ typedef struct ffp_tune_result {
 
 /* Times fsyrk_modp on synthetic operands of shape n x k (storage a_dtype,
  * form alpha/beta, flags without FFP_DEPTH) for each candidate depth, tile
- * edge and placement, stores the fastest in the table for the shape class
- * and returns it.  Allocates its operands, runs on `stream` and waits for
+ * edge and placement (and, for FP64-path shapes with p < 2^23, the
+ * three-limb base path), stores the fastest in the table for the shape
+ * class and returns it.  Allocates its operands, runs on `stream` and waits for
  * it (a tuning call, not for the hot path).
  * Errors: FFP_EINVAL (n or k <= 0, FFP_DEPTH given), as fsyrk_modp
  * otherwise. */

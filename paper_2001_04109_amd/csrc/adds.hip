@@ -21,7 +21,11 @@ __device__ inline uint32_t ld_res(int cls, const Fp& f, const DView& v, int64_t 
         return x < 0 ? (uint32_t)(x + (int)f.p) : (uint32_t)x;
     }
     const int8_t* b = (const int8_t*)v.p;
-    int x = 256 * (int)b[i * v.ld + j] + (int)b[v.plane + i * v.ld + j];
+    int x;
+    if (cls == CLS_LIMB3)
+        x = (int)b[i * v.ld + j] + 256 * (int)b[v.plane + i * v.ld + j] + 65536 * (int)b[2 * v.plane + i * v.ld + j];
+    else
+        x = 256 * (int)b[i * v.ld + j] + (int)b[v.plane + i * v.ld + j];
     x %= (int)f.p;
     return x < 0 ? (uint32_t)(x + (int)f.p) : (uint32_t)x;
 }
@@ -32,6 +36,18 @@ __device__ inline void st_res(int cls, const Fp& f, const DView& v, int64_t i, i
     if (cls == CLS_I8) {
         int x = r > f.half ? (int)r - (int)f.p : (int)r;
         ((int8_t*)v.p)[i * v.ld + j] = (int8_t)x;
+        return;
+    }
+    if (cls == CLS_LIMB3) {
+        // centred value (|x| < 2^22) = l + 256 m + 65536 h
+        const int x = r > f.half ? (int)r - (int)f.p : (int)r;
+        const int l = ((x + 128) & 255) - 128;
+        const int y = (x - l) >> 8;
+        const int mid = ((y + 128) & 255) - 128;
+        int8_t* b = (int8_t*)v.p;
+        b[i * v.ld + j] = (int8_t)l;
+        b[v.plane + i * v.ld + j] = (int8_t)mid;
+        b[2 * v.plane + i * v.ld + j] = (int8_t)((y - mid) >> 8);
         return;
     }
     // limb pair with value in [-32896, 32639]
@@ -369,7 +385,7 @@ hipError_t launch_pack(const Fp& f, int src_cls, DView src, int64_t n, int64_t k
     }
     FFP_PACK(CLS_F64, CLS_F64) FFP_PACK(CLS_F64, CLS_I8) FFP_PACK(CLS_F64, CLS_LIMB2)
     FFP_PACK(CLS_I8, CLS_I8) FFP_PACK(CLS_I8, CLS_F64) FFP_PACK(CLS_LIMB2, CLS_LIMB2)
-    FFP_PACK(CLS_LIMB2, CLS_F64)
+    FFP_PACK(CLS_LIMB2, CLS_F64) FFP_PACK(CLS_F64, CLS_LIMB3)
 #undef FFP_PACK
     return hipErrorInvalidValue;
 }
@@ -393,7 +409,7 @@ hipError_t launch_pack_grouped(int src_cls, int dst_cls, PackDesc* descs, int nd
         return hipGetLastError();                                                                \
     }
     FFP_PACKG(CLS_F64, CLS_F64) FFP_PACKG(CLS_F64, CLS_I8) FFP_PACKG(CLS_F64, CLS_LIMB2)
-    FFP_PACKG(CLS_I8, CLS_I8) FFP_PACKG(CLS_LIMB2, CLS_LIMB2)
+    FFP_PACKG(CLS_I8, CLS_I8) FFP_PACKG(CLS_LIMB2, CLS_LIMB2) FFP_PACKG(CLS_F64, CLS_LIMB3)
 #undef FFP_PACKG
     return hipErrorInvalidValue;
 }

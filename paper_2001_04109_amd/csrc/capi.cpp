@@ -234,6 +234,7 @@ const char* ffp_debug_variant_name(int variant)
     case 6: return "void ffp::prod_i8_ring_kernel<256, 256, 4>(ffp::ProdArgs, int)";
     case 7: return "void ffp::prod_i8_ring_kernel<256, 256, 5>(ffp::ProdArgs, int)";
     case 8: return "void ffp::prod_f64_lds_kernel<8>(ffp::ProdArgs, int)";
+    case 9: return "void ffp::prod_i8_kernel<64, 64, 64, 3>(ffp::ProdArgs, int)";
     default: return "";
     }
 }

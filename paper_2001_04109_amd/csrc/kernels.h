@@ -15,7 +15,13 @@
 
 namespace ffp {
 
-enum Cls : int32_t { CLS_F64 = 0, CLS_I8 = 1, CLS_LIMB2 = 2 };
+// Storage classes of product operands: FP64 path (uint32 residues,
+// converted in the kernel), centred int8, two int8 limbs (256 hi + lo),
+// three int8 limbs (lo + 256 mid + 65536 hi; p < 2^23, depth 0 only).
+enum Cls : int32_t { CLS_F64 = 0, CLS_I8 = 1, CLS_LIMB2 = 2, CLS_LIMB3 = 3 };
+constexpr int kNumCls = 4;
+// int8 planes of a class's storage
+constexpr int cls_planes(int cls) { return cls == CLS_LIMB2 ? 2 : (cls == CLS_LIMB3 ? 3 : 1); }
 
 // Field constants passed to every kernel.
 struct Fp {
@@ -25,9 +31,9 @@ struct Fp {
     uint32_t ya, yb; // skew-orthogonal Y = [[ya I, yb I], [-yb I, ya I]]
 };
 
-// A strided matrix view: element (i, j) is at base + i*ld + j; for CLS_LIMB2
-// the lo plane is at base + plane + i*ld + j.  Units are elements of the
-// view's storage type.
+// A strided matrix view: element (i, j) is at base + i*ld + j; for limb
+// classes plane q is at base + q*plane + i*ld + j (CLS_LIMB2: hi, lo;
+// CLS_LIMB3: lo, mid, hi).  Units are elements of the view's storage type.
 struct DView {
     void* p;
     int64_t ld;
@@ -83,7 +89,7 @@ extern int g_persistent;
 // Product-kernel variant chosen by the most recent launch on this thread
 // (for the timing hooks): 0 FP64 64x64, 1 FP64 128x128 LDS (4 waves), 2 int8
 // 128x128, 3 int8 256x256 (k stage 64), 4 int8 256x256 (k stage 128), 5 int8
-// limbs, 6 and 7 int8 ring, 8 FP64 128x128 LDS (8 waves).
+// limbs, 6 and 7 int8 ring, 8 FP64 128x128 LDS (8 waves), 9 int8 three limbs.
 extern thread_local int g_last_variant;
 // Workgroups of `kernel` (256 threads) resident at once on the device.
 int resident_blocks(const void* kernel, int threads = 256);

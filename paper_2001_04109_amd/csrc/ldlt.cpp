@@ -285,7 +285,7 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
             }
         }
         slices[lv] = sl;
-        int np[3] = {0, 0, 0};
+        int np[kNumCls] = {0};
         for (int i : by[lv])
             if (steps[i].sk == SK_PROD) ++np[steps[i].cls];
         for (int q : np)
@@ -332,7 +332,7 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
         }
         if (status == FFP_OK && sl.count && launch_ldlt_steps(dtable + sl.first, sl.count, sl.blocks, s) != hipSuccess)
             status = FFP_EDEVICE;
-        for (int cls = 0; cls < 3 && status == FFP_OK; ++cls) {
+        for (int cls = 0; cls < kNumCls && status == FFP_OK; ++cls) {
             std::vector<ProdTask> g;
             for (int i : by[lv])
                 if (steps[i].sk == SK_PROD && steps[i].cls == cls) g.push_back(steps[i].t);

@@ -58,9 +58,9 @@ struct Builder {
         PView v;
         v.buf = BUF_WS;
         v.ld = round_up(std::max<int64_t>(cols, 1), 16);
-        const int64_t planes = cls == CLS_LIMB2 ? 2 : 1;
+        const int64_t planes = cls_planes(cls);
         v.off = alloc(rows * v.ld * es() * planes);
-        v.plane = cls == CLS_LIMB2 ? rows * v.ld : 0;
+        v.plane = planes > 1 ? rows * v.ld : 0;
         return v;
     }
 
@@ -260,17 +260,21 @@ int make_syrk_request(int64_t n, int64_t k, uint32_t p, const void* A, int64_t l
     rq->depth = dfield ? (int)dfield - 1 : -1;
     rq->fill_upper = (flags & FFP_FILL_UPPER) != 0;
     rq->force_f64 = (flags & FFP_BASE_F64) != 0;
+    rq->force_limb3 = (flags & FFP_BASE_LIMB3) != 0;
+    if (rq->force_f64 && rq->force_limb3) return FFP_EINVAL;
+    if (rq->force_limb3 && (a_dtype != FFP_U32 || p >= (1u << 23))) return FFP_EDTYPE;
     rq->wide = g_wide_schedule != 0 && (flags & FFP_LOW_MEMORY) == 0;
     rq->a_aligned16 = aligned16(A);
     rq->c_aligned16 = aligned16(C);
     return FFP_OK;
 }
 
-int choose_class(uint32_t p, int a_cls, bool force_f64)
+int choose_class(uint32_t p, int a_cls, bool force_f64, bool force_limb3)
 {
     if (a_cls == CLS_I8) return CLS_I8;
     if (a_cls == CLS_LIMB2) return CLS_LIMB2;
     if (force_f64) return CLS_F64;
+    if (force_limb3) return CLS_LIMB3;
     if (p <= 251) return CLS_I8;
     if (p <= 65521) return CLS_LIMB2;
     return CLS_F64;
@@ -296,9 +300,10 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
     Plan pl;
     if (!make_field_plan(rq.p, &pl.field)) return FFP_EPRIME;
     if (rq.p >= (1u << 25)) return FFP_EPRIME;
-    pl.cls = choose_class(rq.p, rq.a_cls, rq.force_f64);
+    pl.cls = choose_class(rq.p, rq.a_cls, rq.force_f64, rq.force_limb3);
     if (pl.cls == CLS_I8 && rq.p > 251) return FFP_EDTYPE;
     if (pl.cls == CLS_LIMB2 && rq.p > 65521) return FFP_EDTYPE;
+    if (pl.cls == CLS_LIMB3 && rq.p >= (1u << 23)) return FFP_EDTYPE;
     const int64_t n = rq.n, k = rq.k;
 
     int d = rq.depth;
@@ -311,13 +316,18 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
                 d = tc.depth;
                 wide = rq.wide && tc.wide != 0;
                 pl.tuned = true;
+                // the table may move FP64-path shapes (uint32 operands, p < 2^23)
+                // to the three-limb int8 products
+                if (tc.base == CLS_LIMB3 && pl.cls == CLS_F64 && rq.a_cls == CLS_F64 && !rq.force_f64 &&
+                    rq.p < (1u << 23))
+                    pl.cls = CLS_LIMB3;
             }
             if (d == tc.depth && tile == 0) tile = tc.tile;
         }
     }
     if (d < 0) d = default_depth(pl.cls, n, k);
     while (d > 0 && (n >> d) < 8) --d;
-    if (k == 0) d = 0;
+    if (k == 0 || pl.cls == CLS_LIMB3) d = 0;   // three-limb storage: base products only
     pl.depth = d;
     pl.wide = wide;
     pl.tile = tile;
@@ -346,7 +356,7 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
     bool a_ok = (pl.cls == rq.a_cls) && n_pad == n && k_pad == k;
     if (pl.cls == CLS_F64) a_ok = a_ok && (d == 0 || ((rq.lda % 4) == 0 && rq.a_aligned16));
     else a_ok = a_ok && (rq.lda % 16) == 0 && rq.a_aligned16 &&
-                (pl.cls != CLS_LIMB2 || (rq.a_plane % 16) == 0);
+                (pl.cls == CLS_I8 || (rq.a_plane % 16) == 0);
     if (!a_ok && n_pad > 0 && k_pad > 0) {
         PView Ap = B.ws_opnd(n_pad, k_pad);
         Op o = B.op(OP_PACK, 0);

@@ -59,6 +59,7 @@ struct PlanRequest {
     int32_t depth = -1;          // -1: tuned default
     bool fill_upper = false;
     bool force_f64 = false;
+    bool force_limb3 = false;    // base products on three int8 limbs (p < 2^23, depth 0)
     bool a_aligned16 = true;     // caller's A pointer is 16-byte aligned
     bool c_aligned16 = true;
     // Table 3 with independent siblings: S1, S2 always in the workspace,
@@ -92,7 +93,7 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out);
 // Process-wide default of PlanRequest::wide for fsyrk_modp (tuning knob;
 // 1 by default).
 extern int g_wide_schedule;
-int choose_class(uint32_t p, int a_cls, bool force_f64);
+int choose_class(uint32_t p, int a_cls, bool force_f64, bool force_limb3 = false);
 int default_depth(int cls, int64_t n, int64_t k);
 std::string describe_plan(const Plan& pl);
 

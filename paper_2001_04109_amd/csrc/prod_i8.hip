@@ -10,6 +10,13 @@
 // int32 accumulators and combines 2^16 hh + 2^8 x + ll mod p in the
 // epilogue.
 //
+// CLS_LIMB3: value = l + 256 m + 65536 h with int8 limbs (centred residues
+// of p < 2^23: |h| <= 65); the nine limb products go to five int32
+// accumulators by weight 2^0 (ll), 2^8 (lm + ml), 2^16 (lh + mm + hl),
+// 2^24 (mh + hm), 2^32 (hh), each exact for 32768 columns of k (three
+// products of at most 128^2 per column), and the epilogue combines them
+// mod p.
+//
 // A 256-thread workgroup computes a BM x BN tile; each of its 4 waves a
 // (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks.  Per stage of BK (64 or
 // 128) columns of k the workgroup copies the A and B row panels (BM and BN
@@ -191,14 +198,14 @@ __device__ __forceinline__ void store_tile_i8_reg(const v16i (&acc)[FM][FN], con
         }
 }
 
-// PLANES = 1: CLS_I8;  PLANES = 2: CLS_LIMB2.  BK: k bytes per stage.
+// PLANES = 1: CLS_I8;  2: CLS_LIMB2;  3: CLS_LIMB3.  BK: k bytes per stage.
 template <int BM, int BN, int BK, int PLANES>
 __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
 {
     constexpr int PITCH = BK + 16;
     constexpr int WTM = BM / 2, WTN = BN / 2;         // wave tile
     constexpr int FM = WTM / 32, FN = WTN / 32;       // 32x32 blocks per wave
-    constexpr int NACC = PLANES == 1 ? 1 : 3;
+    constexpr int NACC = PLANES == 1 ? 1 : (PLANES == 2 ? 3 : 5);
     constexpr int SA = 2 * PLANES * BM * PITCH, SB = 2 * PLANES * BN * PITCH;
     __shared__ __attribute__((aligned(16))) int8_t smem[SA + SB];
     auto sa = reinterpret_cast<int8_t(*)[PLANES][BM * PITCH]>(smem);
@@ -274,6 +281,13 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
             for (int j = 0; j < FN; ++j) {
                 if constexpr (PLANES == 1) {
                     acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][i], xb[0][j], acc[0][i][j], 0, 0, 0);
+                } else if constexpr (PLANES == 3) {
+                    // planes: 0 = l, 1 = m, 2 = h; accumulator q has weight 2^(8 q)
+#pragma unroll
+                    for (int u = 0; u < 3; ++u)
+#pragma unroll
+                        for (int v = 0; v < 3; ++v)
+                            acc[u + v][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[u][i], xb[v][j], acc[u + v][i][j], 0, 0, 0);
                 } else {
                     acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][i], xb[0][j], acc[0][i][j], 0, 0, 0);
                     acc[NACC - 2][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[PLANES - 1][i], xb[PLANES - 1][j], acc[NACC - 2][i][j], 0, 0, 0);
@@ -283,7 +297,7 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
             }
     };
     constexpr int NREAD = PLANES * (FM + FN);
-    constexpr int NMFMA = FM * FN * (PLANES == 1 ? 1 : 4);
+    constexpr int NMFMA = FM * FN * PLANES * PLANES;
     if (nk > 0) read_frags(fa, fb, 0, 0);
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
@@ -334,6 +348,33 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
     const double alpha = (double)t.alpha, beta = (double)t.beta;
     if constexpr (PLANES == 1) {
         store_tile_i8_reg<WTM, WTN, FM, FN>(acc[0], t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+    } else if constexpr (PLANES == 3) {
+        if (!wave_live) return;
+        // 2^(8 q) mod p for the five weights
+        double cw[5];
+        cw[0] = 1.0;
+#pragma unroll
+        for (int q = 1; q < 5; ++q) cw[q] = mod_f64(cw[q - 1] * 256.0, pd, t.pinv);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = tile_c + wc * WTN + j * 32 + lrow;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int row = tile_r + wr * WTM + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
+                    if (row >= t.m || col >= t.n) continue;
+                    if (t.syrk && col > row) continue;
+                    double v = 0.0;                      // five terms below p^2 < 2^46: exact
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) v += mod_f64((double)acc[q][i][j][e], pd, t.pinv) * cw[q];
+                    v = mod_f64(v, pd, t.pinv);
+                    uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                    double x = alpha * v;
+                    if (t.beta != 0u) x += beta * (double)(*dst);
+                    *dst = (uint32_t)mod_f64(x, pd, t.pinv);
+                }
+            }
     } else {
         if (!wave_live) return;
         const double r16 = (double)((65536u) % t.p), r8 = (double)(256u % t.p);
@@ -596,7 +637,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
             const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES>);
             grid = total < resident ? total : resident;
         }
-        g_last_variant = PLANES == 2 ? 5 : (BM == 128 ? 2 : (BK == 64 ? 3 : 4));
+        g_last_variant = PLANES == 3 ? 9 : (PLANES == 2 ? 5 : (BM == 128 ? 2 : (BK == 64 ? 3 : 4)));
         hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
     }
     return hipGetLastError();
@@ -614,10 +655,10 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         ProdTask& t = tasks[i];
         if ((t.k % KSTEP) != 0 || (t.A.ld % 16) != 0 || (t.B.ld % 16) != 0 ||
             (((uintptr_t)t.A.p) & 15) != 0 || (((uintptr_t)t.B.p) & 15) != 0 ||
-            (PLANES == 2 && ((t.A.plane % 16) != 0 || (t.B.plane % 16) != 0)))
+            (PLANES > 1 && ((t.A.plane % 16) != 0 || (t.B.plane % 16) != 0)))
             return hipErrorInvalidValue;
         const int64_t half = (t.p - 1) / 2;
-        const int64_t per_k = PLANES == 1 ? half * half : 2 * 128 * 128;
+        const int64_t per_k = PLANES == 1 ? half * half : (PLANES == 2 ? 2 * 128 * 128 : 3 * 128 * 128);
         int64_t kb = (2147483647LL - (int64_t)t.p) / (per_k > 0 ? per_k : 1);
         kb -= kb % KSTEP;
         t.kblk = cap_kblk(kb > (1 << 30) ? (1 << 30) : kb, KSTEP);
@@ -686,6 +727,12 @@ hipError_t launch_products_limb2(ProdTask* tasks, int ntasks, ProdTask* dev_task
                                  hipStream_t s)
 {
     return launch_i8_impl<128, 128, 64, 2>(tasks, ntasks, dev_task_buf, s);
+}
+
+hipError_t launch_products_limb3(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
+                                 hipStream_t s)
+{
+    return launch_i8_impl<64, 64, 64, 3>(tasks, ntasks, dev_task_buf, s);
 }
 
 }  // namespace ffp

@@ -362,6 +362,7 @@ hipError_t launch_products(int cls, ProdTask* tasks, int ntasks, ProdTask* dev_t
     case CLS_F64: return launch_products_f64(tasks, ntasks, dev_task_buf, s);
     case CLS_I8: return launch_products_i8(tasks, ntasks, dev_task_buf, s);
     case CLS_LIMB2: return launch_products_limb2(tasks, ntasks, dev_task_buf, s);
+    case CLS_LIMB3: return launch_products_limb3(tasks, ntasks, dev_task_buf, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -411,12 +412,11 @@ struct OpRegions {
 };
 
 void add_view(std::vector<Region>& out, const PView& v, int64_t rows, int64_t cols, int64_t es,
-              bool planes, const SchedItem& it)
+              int planes, const SchedItem& it)
 {
     const uintptr_t b = (uintptr_t)at(v, it.a, it.c, it.ws);
     const int64_t ld = (rows > 1 ? v.ld : cols) * es;
-    out.push_back(Region{b, ld, rows, cols * es});
-    if (planes) out.push_back(Region{b + (uintptr_t)(v.plane * es), ld, rows, cols * es});
+    for (int q = 0; q < planes; ++q) out.push_back(Region{b + (uintptr_t)(q * v.plane * es), ld, rows, cols * es});
 }
 
 int64_t class_es(int cls) { return cls == CLS_F64 ? 4 : 1; }
@@ -426,7 +426,7 @@ OpRegions regions_of(const SchedItem& it)
     const Op& o = *it.op;
     OpRegions r;
     const int64_t es = class_es(o.cls);
-    const bool pl = o.cls == CLS_LIMB2;
+    const int pl = cls_planes(o.cls);
     switch (o.kind) {
     case OP_S1S2:
         for (int i = 0; i < 3; ++i) add_view(r.rd, o.v[i], o.m, o.k, es, pl, it);
@@ -441,45 +441,45 @@ OpRegions regions_of(const SchedItem& it)
     case OP_GEMM:
         add_view(r.rd, o.v[0], o.m, o.k, es, pl, it);
         add_view(r.rd, o.v[1], o.n, o.k, es, pl, it);
-        add_view(r.wr, o.v[2], o.m, o.n, 4, false, it);
-        if (o.beta) add_view(r.rd, o.v[2], o.m, o.n, 4, false, it);
+        add_view(r.wr, o.v[2], o.m, o.n, 4, 1, it);
+        if (o.beta) add_view(r.rd, o.v[2], o.m, o.n, 4, 1, it);
         break;
     case OP_SYRK:
         add_view(r.rd, o.v[0], o.m, o.k, es, pl, it);
-        add_view(r.wr, o.v[1], o.m, o.m, 4, false, it);
-        if (o.beta) add_view(r.rd, o.v[1], o.m, o.m, 4, false, it);
+        add_view(r.wr, o.v[1], o.m, o.m, 4, 1, it);
+        if (o.beta) add_view(r.rd, o.v[1], o.m, o.m, 4, 1, it);
         break;
     case OP_POSTADD:
         for (int i = 0; i < (o.beta ? 5 : 4); ++i) {
-            add_view(r.rd, o.v[i], o.m, o.m, 4, false, it);
-            add_view(r.wr, o.v[i], o.m, o.m, 4, false, it);
+            add_view(r.rd, o.v[i], o.m, o.m, 4, 1, it);
+            add_view(r.wr, o.v[i], o.m, o.m, 4, 1, it);
         }
         if (o.beta) {
-            add_view(r.rd, o.v[5], 1, o.m, 4, false, it);
-            add_view(r.wr, o.v[5], 1, o.m, 4, false, it);
+            add_view(r.rd, o.v[5], 1, o.m, 4, 1, it);
+            add_view(r.wr, o.v[5], 1, o.m, 4, 1, it);
         }
         break;
     case OP_ADDLOW:
-        add_view(r.rd, o.v[0], o.m, o.m, 4, false, it);
-        add_view(r.rd, o.v[1], o.m, o.m, 4, false, it);
-        add_view(r.wr, o.v[2], o.m, o.m, 4, false, it);
+        add_view(r.rd, o.v[0], o.m, o.m, 4, 1, it);
+        add_view(r.rd, o.v[1], o.m, o.m, 4, 1, it);
+        add_view(r.wr, o.v[2], o.m, o.m, 4, 1, it);
         break;
     case OP_SAVEC22:
-        add_view(r.rd, o.v[0], o.m, o.m, 4, false, it);
-        add_view(r.wr, o.v[1], o.m, o.m, 4, false, it);
-        add_view(r.wr, o.v[2], 1, o.m, 4, false, it);
+        add_view(r.rd, o.v[0], o.m, o.m, 4, 1, it);
+        add_view(r.wr, o.v[1], o.m, o.m, 4, 1, it);
+        add_view(r.wr, o.v[2], 1, o.m, 4, 1, it);
         break;
     case OP_MIRROR:
-        add_view(r.rd, o.v[0], o.m, o.m, 4, false, it);
-        add_view(r.wr, o.v[0], o.m, o.m, 4, false, it);
+        add_view(r.rd, o.v[0], o.m, o.m, 4, 1, it);
+        add_view(r.wr, o.v[0], o.m, o.m, 4, 1, it);
         break;
     case OP_PACK:
-        add_view(r.rd, o.v[0], o.m_src, o.k_src, class_es(o.src_cls), o.src_cls == CLS_LIMB2, it);
+        add_view(r.rd, o.v[0], o.m_src, o.k_src, class_es(o.src_cls), cls_planes(o.src_cls), it);
         add_view(r.wr, o.v[1], o.m, o.k, es, pl, it);
         break;
     case OP_COPY:
-        add_view(r.rd, o.v[0], o.m, o.n, 4, false, it);
-        add_view(r.wr, o.v[1], o.m, o.n, 4, false, it);
+        add_view(r.rd, o.v[0], o.m, o.n, 4, 1, it);
+        add_view(r.wr, o.v[1], o.m, o.n, 4, 1, it);
         break;
     }
     return r;
@@ -539,11 +539,11 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
     // staging for the task and descriptor tables of grouped launches
     size_t meta = 0;
     for (const auto& lv : by_level) {
-        size_t np[3] = {0, 0, 0}, nk[9] = {0};
+        size_t np[kNumCls] = {0}, nk[kNumCls * kNumCls] = {0};
         for (size_t j : lv) {
             const Op& o = *items[j].op;
             if (o.kind == OP_SYRK || o.kind == OP_GEMM) ++np[o.cls];
-            else if (o.kind == OP_PACK) ++nk[o.src_cls * 3 + o.cls];
+            else if (o.kind == OP_PACK) ++nk[o.src_cls * kNumCls + o.cls];
         }
         for (size_t q : np)
             if (q > (size_t)kInlineTasks) meta += (size_t)rup256((int64_t)(q * sizeof(ProdTask)));
@@ -559,21 +559,21 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
     size_t moff = 0;
     int status = FFP_OK;
     for (const auto& lv : by_level) {
-        std::vector<size_t> prods[3], packs[9];
+        std::vector<size_t> prods[kNumCls], packs[kNumCls * kNumCls];
         for (size_t j : lv) {
             const SchedItem& it = items[j];
             const Op& o = *it.op;
             if (o.kind == OP_SYRK || o.kind == OP_GEMM) {
                 prods[o.cls].push_back(j);
             } else if (o.kind == OP_PACK) {
-                packs[o.src_cls * 3 + o.cls].push_back(j);
+                packs[o.src_cls * kNumCls + o.cls].push_back(j);
             } else {
                 const int st = execute_op(*it.pl, o, it.a, it.c, it.ws, s);
                 if (st != FFP_OK) { status = st; break; }
             }
         }
         if (status != FFP_OK) break;
-        for (int cls = 0; cls < 3 && status == FFP_OK; ++cls) {
+        for (int cls = 0; cls < kNumCls && status == FFP_OK; ++cls) {
             const auto& g = prods[cls];
             if (g.empty()) continue;
             if (g.size() == 1) {
@@ -615,7 +615,7 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
             }
             if (prof) prof_end(s, e0, flops, cls);
         }
-        for (int q = 0; q < 9 && status == FFP_OK; ++q) {
+        for (int q = 0; q < kNumCls * kNumCls && status == FFP_OK; ++q) {
             const auto& g = packs[q];
             if (g.empty()) continue;
             if (g.size() == 1) {
@@ -631,7 +631,7 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
                 const SchedItem& it = items[j];
                 d[nd++] = make_pack(*it.pl, *it.op, it.a, it.c, it.ws);
             }
-            if (launch_pack_grouped(q / 3, q % 3, d, nd, dd, s) != hipSuccess) status = FFP_EDEVICE;
+            if (launch_pack_grouped(q / kNumCls, q % kNumCls, d, nd, dd, s) != hipSuccess) status = FFP_EDEVICE;
         }
         if (status != FFP_OK) break;
     }

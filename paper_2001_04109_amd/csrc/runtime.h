@@ -107,6 +107,8 @@ hipError_t launch_products_f64(ProdTask* tasks, int ntasks, ProdTask* dev_task_b
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s);
 hipError_t launch_products_limb2(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
                                  hipStream_t s);
+hipError_t launch_products_limb3(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
+                                 hipStream_t s);
 
 // Optional timing of product launches with HIP events (for the benchmark's
 // roofline figures).  prof_read sums the elapsed times and algorithmic flops

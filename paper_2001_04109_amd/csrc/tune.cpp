@@ -51,6 +51,7 @@ Key key_of(int cls, int64_t n, int64_t k, bool accumulate, bool lowmem)
 bool valid_choice(int cls, const TuneChoice& c)
 {
     if (c.depth < 0 || c.depth > 7 || (c.wide != 0 && c.wide != 1)) return false;
+    if (c.base != 0 && !(c.base == CLS_LIMB3 && cls == CLS_F64 && c.depth == 0 && c.tile == 0)) return false;
     if (c.tile == 0) return true;
     if (cls == CLS_F64) return c.tile == 64 || c.tile == 128;
     if (cls == CLS_I8) return c.tile == 128 || c.tile == 256;
@@ -87,6 +88,7 @@ unsigned pin_flags(const ffp_job& j, unsigned flags)
     if (build_syrk_plan(rq, &pl) != FFP_OK) return flags;
     unsigned f = flags | FFP_DEPTH(pl.depth);
     if (!pl.wide) f |= FFP_LOW_MEMORY;
+    if (pl.cls == CLS_LIMB3) f |= FFP_BASE_LIMB3;
     return f;
 }
 
@@ -147,7 +149,7 @@ int ffp_autotune(int64_t n, int64_t k, uint32_t p, int a_dtype, uint32_t alpha, 
     int st = make_syrk_request(n, k, p, (const void*)256, lda, a_dtype, alpha, beta, (const uint32_t*)256, ldc,
                                flags, &base);
     if (st != FFP_OK) return st;
-    const int cls = choose_class(p, base.a_cls, base.force_f64);
+    const int cls = choose_class(p, base.a_cls, base.force_f64, base.force_limb3);
     const bool accumulate = alpha != 1u || beta != 0u;
     const bool lowmem = !base.wide;
 
@@ -184,6 +186,25 @@ int ffp_autotune(int64_t n, int64_t k, uint32_t p, int a_dtype, uint32_t alpha, 
     TuneChoice best;
     double best_ms = INFINITY;
     int tried = 0;
+    // the three-limb int8 path (depth 0) as an alternative base for FP64
+    // shapes with uint32 operands and p < 2^23
+    if (cls == CLS_F64 && a_dtype == FFP_U32 && !base.force_f64 && p < (1u << 23)) {
+        PlanRequest rq = base;
+        rq.depth = 0;
+        rq.force_limb3 = true;
+        rq.no_tune = true;
+        double ms = 0.0;
+        if (st == FFP_OK) st = time_request(rq, A, C, s, e0, e1, &ms);
+        if (st == FFP_OK) {
+            ++tried;
+            best_ms = ms;
+            best.depth = 0;
+            best.tile = 0;
+            best.wide = lowmem ? 0 : 1;
+            best.base = CLS_LIMB3;
+            best.ms = ms;
+        }
+    }
     for (int tile : tiles) {
         if (st != FFP_OK) break;
         double tile_best = INFINITY;
@@ -206,6 +227,7 @@ int ffp_autotune(int64_t n, int64_t k, uint32_t p, int a_dtype, uint32_t alpha, 
                     best.depth = d;
                     best.tile = tile;
                     best.wide = wide;
+                    best.base = 0;
                     best.ms = ms;
                 }
             }
@@ -230,6 +252,7 @@ int ffp_autotune(int64_t n, int64_t k, uint32_t p, int a_dtype, uint32_t alpha, 
     out->depth = best.depth;
     out->tile = best.tile;
     out->wide = best.wide;
+    out->base = best.base;
     out->candidates = tried;
     out->ms = best.ms;
     out->rule_ms = rule_ms;
@@ -252,6 +275,7 @@ int ffp_tune_lookup(int64_t n, int64_t k, uint32_t p, int a_dtype, uint32_t alph
     out->depth = pl.depth;
     out->tile = pl.tile;
     out->wide = pl.wide ? 1 : 0;
+    out->base = pl.cls == CLS_LIMB3 ? CLS_LIMB3 : 0;
     TuneChoice tc;
     if (pl.tuned && tune_lookup(pl.cls, n, k, alpha != 1u || beta != 0u, !rq.wide, &tc)) out->ms = tc.ms;
     return pl.tuned ? 1 : 0;
@@ -262,12 +286,12 @@ int ffp_tune_save(const char* path)
     if (!path) return FFP_EINVAL;
     FILE* f = fopen(path, "w");
     if (!f) return FFP_EINVAL;
-    fprintf(f, "# ffp tuning table 1: cls log2n log2k accumulate lowmem depth tile wide ms\n");
+    fprintf(f, "# ffp tuning table 2: cls log2n log2k accumulate lowmem depth tile wide base ms\n");
     {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         for (const auto& [key, c] : g_table)
-            fprintf(f, "%d %d %d %d %d %d %d %d %.6g\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
-                    std::get<3>(key), std::get<4>(key), c.depth, c.tile, c.wide, c.ms);
+            fprintf(f, "%d %d %d %d %d %d %d %d %d %.6g\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
+                    std::get<3>(key), std::get<4>(key), c.depth, c.tile, c.wide, c.base, c.ms);
     }
     return fclose(f) == 0 ? FFP_OK : FFP_EINVAL;
 }
@@ -287,9 +311,9 @@ int ffp_tune_load(const char* path)
         int cls, ln, lk, acc, lm;
         TuneChoice c;
         double ms = 0.0;
-        if (sscanf(q, "%d %d %d %d %d %d %d %d %lf", &cls, &ln, &lk, &acc, &lm, &c.depth, &c.tile, &c.wide, &ms) !=
-                9 ||
-            cls < 0 || cls > 2 || ln < 0 || ln > 31 || lk < 0 || lk > 31 || (acc != 0 && acc != 1) ||
+        if (sscanf(q, "%d %d %d %d %d %d %d %d %d %lf", &cls, &ln, &lk, &acc, &lm, &c.depth, &c.tile, &c.wide, &c.base,
+                   &ms) != 10 ||
+            cls < 0 || cls >= kNumCls || ln < 0 || ln > 31 || lk < 0 || lk > 31 || (acc != 0 && acc != 1) ||
             (lm != 0 && lm != 1) || !valid_choice(cls, c)) {
             status = FFP_EINVAL;
             break;

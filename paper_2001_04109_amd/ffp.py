@@ -29,6 +29,7 @@ FFP_I8_LIMB2 = 2
 FFP_FILL_UPPER = 0x1
 FFP_BASE_F64 = 0x100
 FFP_LOW_MEMORY = 0x200
+FFP_BASE_LIMB3 = 0x400
 FFP_WS_BETA = 0x80000000
 
 
@@ -75,7 +76,8 @@ class ffp_result(ctypes.Structure):
 
 class ffp_tune_result(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("tile", ctypes.c_int32), ("wide", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("ms", ctypes.c_double), ("rule_ms", ctypes.c_double)]
+                ("base", ctypes.c_int32), ("candidates", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("rule_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -407,7 +409,7 @@ def set_knob(key: str, value: int):
 # ---- tensor conveniences (marshalling only) -------------------------------
 
 def syrk(A, p: int, alpha: int = 1, beta: int = 0, C=None, depth=None, fill_upper=False,
-         a_dtype=FFP_U32, force_f64=False, stream=None):
+         a_dtype=FFP_U32, force_f64=False, limb3=False, stream=None):
     """lower(C) <- alpha A A^T + beta lower(C) mod p on device tensors.
 
     A: (n, k) int32 residues (a_dtype FFP_U32), int8 centred residues
@@ -431,6 +433,8 @@ def syrk(A, p: int, alpha: int = 1, beta: int = 0, C=None, depth=None, fill_uppe
         flags |= FFP_DEPTH(depth)
     if force_f64:
         flags |= FFP_BASE_F64
+    if limb3:
+        flags |= FFP_BASE_LIMB3
     fsyrk_modp(n, k, p, A, lda, a_dtype, alpha, beta, C, C.stride(0), flags, stream)
     return C
 

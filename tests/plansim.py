@@ -14,7 +14,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-CLS_F64, CLS_I8, CLS_LIMB2 = 0, 1, 2
+CLS_F64, CLS_I8, CLS_LIMB2, CLS_LIMB3 = 0, 1, 2, 3
 OP_S1S2, OP_S34, OP_GEMM, OP_SYRK, OP_POSTADD, OP_ADDLOW, OP_SAVEC22, OP_MIRROR, OP_PACK, OP_COPY = range(10)
 
 
@@ -92,6 +92,11 @@ class Sim:
             return self._nd(v, np.uint32, rows, cols).astype(np.int64)
         if cls == CLS_I8:
             return self._nd(v, np.int8, rows, cols).astype(np.int64) % p
+        if cls == CLS_LIMB3:   # planes lo, mid, hi
+            lo = self._nd(v, np.int8, rows, cols).astype(np.int64)
+            mid = self._nd(v, np.int8, rows, cols, extra=v.plane).astype(np.int64)
+            hi = self._nd(v, np.int8, rows, cols, extra=2 * v.plane).astype(np.int64)
+            return (lo + 256 * mid + 65536 * hi) % p
         hi = self._nd(v, np.int8, rows, cols).astype(np.int64)
         lo = self._nd(v, np.int8, rows, cols, extra=v.plane).astype(np.int64)
         return (256 * hi + lo) % p
@@ -108,6 +113,16 @@ class Sim:
             x = np.where(vals > (p - 1) // 2, vals - p, vals)
             assert np.all(np.abs(x) <= 127)
             self._nd(v, np.int8, rows, cols)[...] = x.astype(np.int8)
+        elif cls == CLS_LIMB3:
+            x = np.where(vals > (p - 1) // 2, vals - p, vals)
+            lo = ((x + 128) & 255) - 128
+            y = (x - lo) >> 8
+            mid = ((y + 128) & 255) - 128
+            hi = (y - mid) >> 8
+            assert np.all((hi >= -128) & (hi <= 127))
+            self._nd(v, np.int8, rows, cols)[...] = lo.astype(np.int8)
+            self._nd(v, np.int8, rows, cols, extra=v.plane)[...] = mid.astype(np.int8)
+            self._nd(v, np.int8, rows, cols, extra=2 * v.plane)[...] = hi.astype(np.int8)
         else:
             x = np.where(vals <= 32639, vals, vals - p)
             lo = ((x + 128) & 255) - 128

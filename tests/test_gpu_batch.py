@@ -140,3 +140,13 @@ def test_batch_workload_1024_jobs_all_checked():
         rows = oracle.syrk_rows(A, p, 0, n)
         low = lower_mask(n)
         assert np.array_equal(out[low], rows[low]), j
+
+
+def test_batch_three_limb_base():
+    """FFP_BASE_LIMB3 for a whole batch (primes up to 1000003 and the int8
+    ones): grouped three-limb products, each job exact."""
+    specs = mixed_specs(14, 24, nmax=260)
+    outs = run_batch(specs, flags=ffp.FFP_BASE_LIMB3)
+    for (A, p, alpha, beta, C0), out in zip(specs, outs):
+        low = lower_mask(A.shape[0])
+        assert np.array_equal(out[low], oracle.syrk_ab(A, p, alpha, beta, C0)[low])

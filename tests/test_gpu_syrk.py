@@ -27,7 +27,7 @@ def _gpu():
 
 
 def gpu_syrk(A, p, depth=None, alpha=1, beta=0, C0=None, fill_upper=False, force_f64=False,
-             a_dtype=ffp.FFP_U32):
+             a_dtype=ffp.FFP_U32, limb3=False):
     import torch
     n = A.shape[-2]
     if a_dtype == ffp.FFP_U32:
@@ -38,7 +38,7 @@ def gpu_syrk(A, p, depth=None, alpha=1, beta=0, C0=None, fill_upper=False, force
         Ad = torch.from_numpy(limbs(A, p)).cuda()
     Cd = to_dev_u32(C0) if C0 is not None else torch.zeros((n, n), dtype=torch.int32, device="cuda")
     ffp.syrk(Ad, p, alpha, beta, Cd, depth=depth, fill_upper=fill_upper, a_dtype=a_dtype,
-             force_f64=force_f64)
+             force_f64=force_f64, limb3=limb3)
     torch.cuda.synchronize()
     return from_dev_u32(Cd)
 
@@ -201,6 +201,40 @@ def test_int8_max_entries():
     for p in (251, 65521):
         A = np.full((96, 4096), (p - 1) // 2 + 1, dtype=np.uint32)   # most negative centred value
         check_lower(gpu_syrk(A, p, depth=0), oracle.syrk(A, p))
+
+
+@pytest.mark.parametrize("p", [65537, 131071, 1000003, 8388593])
+@pytest.mark.parametrize("n,k", [(1, 1), (100, 37), (257, 300), (513, 64), (300, 1000)])
+def test_syrk_limb3_vs_oracle(p, n, k):
+    """Three int8 limbs: ragged shapes over several 128 x 128 tiles, p up to
+    the largest prime below 2^23."""
+    A = inputs.uniform((41, n, k, p), n, k, p)
+    check_lower(gpu_syrk(A, p, limb3=True), oracle.syrk(A, p))
+
+
+@pytest.mark.parametrize("p", [65537, 8388593])
+def test_limb3_alpha_beta_fill_and_forced_kblk(p):
+    n, k = 200, 1100
+    A = inputs.uniform(42, n, k, p)
+    C0 = inputs.uniform(43, n, n, p)
+    out = gpu_syrk(A, p, alpha=p - 1, beta=1, C0=C0, limb3=True, fill_upper=True)
+    expect = oracle.syrk_ab(A, p, p - 1, 1, C0)
+    check_lower(out, expect)
+    assert np.array_equal(out, np.tril(out) + np.tril(out, -1).T)
+    set_kblk(64)                          # every 64 columns a reduction and a new launch
+    out = gpu_syrk(A, p, alpha=3, beta=p - 2, C0=C0, limb3=True)
+    set_kblk(0)
+    check_lower(out, oracle.syrk_ab(A, p, 3, p - 2, C0))
+
+
+def test_limb3_max_entries_long_k():
+    """Largest centred magnitudes over more columns than one exact int32
+    block (43 648), so the product runs as two k-chunks."""
+    for p in (131071, 8388593):
+        n, k = 64, 50000
+        A = np.full((n, k), (p - 1) // 2 + 1, dtype=np.uint32)   # most negative centred value
+        A[::3] = (p - 1) // 2                                     # most positive
+        check_lower(gpu_syrk(A, p, limb3=True), oracle.syrk(A, p))
 
 
 def test_f64_forced_for_small_prime():

@@ -58,16 +58,19 @@ def test_autotune_then_exact_call(n, k, p, a_dtype, alpha, beta):
 
 
 def test_table_drives_batched_and_served_calls(tmp_path):
-    """Entries that force depths 1-2, the Table 3 placements and both tiles:
-    batched jobs and served requests stay exact; entries cleared while
-    requests wait do not change their workspace (fixed at submission)."""
+    """Entries that force depths 1-2, the Table 3 placements, both tiles and
+    the three-limb base: batched jobs and served requests stay exact;
+    entries cleared while requests wait do not change their workspace
+    (fixed at submission)."""
     import torch
-    rows = ["0 8 8 0 0 2 64 0 0", "0 8 9 0 0 1 128 1 0", "1 8 8 0 0 1 128 0 0", "0 9 9 0 0 2 128 1 0"]
+    rows = ["0 8 8 0 0 2 64 0 0 0", "0 8 9 0 0 1 128 1 0 0", "1 8 8 0 0 1 128 0 0 0", "0 9 9 0 0 2 128 1 0 0",
+            "0 9 10 0 0 0 0 1 3 0"]
     path = os.path.join(str(tmp_path), "t.txt")
     with open(path, "w") as f:
         f.write("\n".join(rows) + "\n")
-    assert ffp.ffp_tune_load(path) == 4
-    specs = [(200, 240, 131071), (256, 300, 65537), (180, 180, 251), (400, 400, 131071), (150, 90, 65537)]
+    assert ffp.ffp_tune_load(path) == 5
+    specs = [(200, 240, 131071), (256, 300, 65537), (180, 180, 251), (400, 400, 131071), (150, 90, 65537),
+             (300, 700, 131071)]
     mats = [inputs.uniform((13, j), n, k, p) for j, (n, k, p) in enumerate(specs)]
     devA = [to_dev_u32(A) for A in mats]
     devC = [torch.zeros((n, n), dtype=torch.int32, device="cuda") for n, _, _ in specs]

@@ -96,6 +96,26 @@ def test_int8_classes(p, a_dtype, depth):
     run_case(64, 64, p, depth, alpha=3, beta=p - 1, a_dtype=a_dtype, seed=6)
 
 
+@pytest.mark.parametrize("p", [65537, 131071, 1000003, 8388593])
+@pytest.mark.parametrize("n,k", [(40, 72), (33, 21), (64, 64)])
+def test_limb3_class(p, n, k):
+    """Three int8 limbs (FFP_BASE_LIMB3): base products only, any forced
+    depth falls back to 0; plain and accumulate forms."""
+    plan = run_case(n, k, p, 2, flags=ffp.FFP_BASE_LIMB3, seed=7)
+    assert plan.cls == plansim.CLS_LIMB3 and plan.depth == 0
+    run_case(n, k, p, 0, alpha=p - 1, beta=1, flags=ffp.FFP_BASE_LIMB3, seed=8)
+    run_case(n, k, p, 0, alpha=5, beta=p - 2, flags=ffp.FFP_BASE_LIMB3 | ffp.FFP_FILL_UPPER, seed=9)
+
+
+def test_limb3_argument_errors():
+    with pytest.raises(ffp.FfpError):       # p >= 2^23
+        ffp.plan_describe(16, 16, 8388617, flags=ffp.FFP_BASE_LIMB3)
+    with pytest.raises(ffp.FfpError):       # with FFP_BASE_F64
+        ffp.plan_describe(16, 16, 65537, flags=ffp.FFP_BASE_LIMB3 | ffp.FFP_BASE_F64)
+    with pytest.raises(ffp.FfpError):       # int8 storage
+        ffp.plan_describe(16, 16, 251, ffp.FFP_I8_CENTERED, 16, 16, flags=ffp.FFP_BASE_LIMB3)
+
+
 def test_force_f64_for_small_prime():
     plan = run_case(32, 40, 251, 2, flags=ffp.FFP_BASE_F64)
     assert plan.cls == plansim.CLS_F64
