@@ -42,6 +42,9 @@ WORKLOADS = {
                                  cls=1),
     "syrk_16384_p65521_limb2": dict(shapes=[(16384, 16384)], p=65521, depth=0, seed=2,
                                     dtype="limb2", cls=2),
+    # the depth-3 workload's shapes on three int8 limbs instead of FP64
+    "syrk_8192_p131071_limb3": dict(shapes=[(8192, 8192), (8192, 32768)], p=131071, depth=0, seed=1,
+                                    dtype="u32", cls=3, limb3=True),
 }
 
 
@@ -110,7 +113,7 @@ def run_workload(name, steps, warmup, check=True):
 
     def step():
         for Ad, Cd in zip(devs, outs):
-            ffp.syrk(Ad, p, C=Cd, depth=w["depth"], a_dtype=a_dtype)
+            ffp.syrk(Ad, p, C=Cd, depth=w["depth"], a_dtype=a_dtype, limb3=w.get("limb3", False))
 
     for _ in range(warmup):
         step()
@@ -247,6 +250,27 @@ def batched_vs_plain(steps=3, njobs=1024):
     del devA, devC, devC2, jobs
     torch.cuda.empty_cache()
     return out
+
+
+def tune_served_classes(nmin=256, nmax=4096):
+    """One autotuner run per shape class of the served A A^T requests on the
+    FP64 path (p = 65537 and 131071 share it): n in [nmin, nmax] and
+    k in [n/2, 2n] give ceil(log2 n) in 8..12 and ceil(log2 k) within one of
+    it; each class is tuned at n = 2^ceil(log2 n) (at most nmax), k =
+    2^ceil(log2 k).  Untimed; the served runs and their per-call comparison
+    then follow the table."""
+    from paper_2001_04109_amd import ffp
+    ffp.ffp_tune_clear()
+    t0 = time.perf_counter()
+    out = {}
+    ln0, ln1 = int(np.ceil(np.log2(nmin))), int(np.ceil(np.log2(nmax)))
+    for ln in range(ln0, ln1 + 1):
+        n = min(1 << ln, nmax)
+        for lk in (ln - 1, ln, ln + 1):
+            r = ffp.ffp_autotune(n, 1 << lk, 131071)
+            out[f"{ln},{lk}"] = "limb3" if r["base"] == 3 else f"f64 d{r['depth']} t{r['tile']}"
+    return {"shape_classes": len(out), "seconds": round(time.perf_counter() - t0, 2),
+            "limb3_classes": sum(v == "limb3" for v in out.values()), "choices": out}
 
 
 class OperandPool:
@@ -498,7 +522,7 @@ def main():
             "product_kernels_ms_per_step": res.get("all_kernels", {})}
     extra = {}
     if not args.no_extra:
-        for other in ("syrk_16384_p251_int8", "syrk_16384_p65521_limb2"):
+        for other in ("syrk_16384_p251_int8", "syrk_16384_p65521_limb2", "syrk_8192_p131071_limb3"):
             if other == name:
                 continue
             log(f"bench: extra {other}")
@@ -506,12 +530,15 @@ def main():
             a2 = r2["kernel_flops"] / (r2["kernel_ms"] * 1e-3) / 1e12 if r2.get("kernel_ms") else 0.0
             extra[other] = {"gops": round(r2["gops"], 1), "ms_per_step": round(r2["ms_per_step"], 4),
                             "frac_int8_peak_effective": round(r2["gops"] / 1e3 / PEAK_I8, 4),
-                            "kernel_achieved_TOPs": round(a2, 2)}
+                            "kernel_achieved_TOPs": round(a2, 2), "kernel": r2.get("kernel")}
     if not args.no_extra and not args.no_batched:
         log("bench: batched 1024 jobs vs per-call")
         extra["batched_1024_jobs"] = batched_vs_plain()
         log(f"bench: batched {extra['batched_1024_jobs']}")
     if not args.no_extra and args.serve_requests > 0:
+        log("bench: autotuning the served A A^T shape classes")
+        tuned = tune_served_classes()
+        log(f"bench: autotune {tuned}")
         log(f"bench: served stream, {args.serve_requests} requests at {args.serve_rate}/s")
         sv, reqs, pool = served(args.serve_requests, rate=args.serve_rate)
         log(f"bench: served {sv}")
@@ -528,7 +555,8 @@ def main():
         log(f"bench: underload {low}")
         extra["served_stream"] = {"arrivals": sv, "saturated": sat, "per_call_plain": pc,
                                   "saturated_vs_per_call": round(sat["gops_total"] / pc["gops_total"], 3),
-                                  "underload": low}
+                                  "underload": low, "autotune": tuned}
+        ffp.ffp_tune_clear()
         del pool
     cpu = None
     if not args.no_cpu_baseline:

@@ -58,6 +58,10 @@ PlanRequest schur_request(int64_t n2, const NodeLayout& L, uint32_t p, int64_t l
     rq.beta = 1;
     rq.depth = -1;
     rq.no_tune = true;      // the workspace figure must not depend on the tuning table
+    // above the one- and two-limb int8 range, three int8 limbs where they
+    // hold the residues (several times the FP64 matrix-core rate, no
+    // recursion needed)
+    rq.force_limb3 = p > 65521u && p < (1u << 23);
     rq.a_aligned16 = true;
     rq.c_aligned16 = c_aligned;
     return rq;

@@ -34,8 +34,12 @@ size_t result_bytes(const ffp_request& r)
     return (size_t)rup((int64_t)b, 256);
 }
 
-constexpr int kMaxBatch = 128;      // A*A^T requests per unit
-constexpr int kMaxLdltBatch = 32;   // LDL^T requests per unit
+}  // namespace
+
+int g_serve_batch = 128;      // A*A^T requests per unit
+int g_serve_ldlt_batch = 32;  // LDL^T requests per unit
+
+namespace {
 
 // Workspace the request needs while it runs (the same figure the batched
 // launch and the LDL^T driver use for it).
@@ -461,7 +465,7 @@ void Server::loop()
             while (!queue_.empty()) {
                 ServeReq& q = reqs_[queue_.front() - 1];
                 const int kind = q.rq.kind == FFP_REQ_LDLT ? 1 : 0;
-                if ((int)batch[kind].size() >= (kind ? kMaxLdltBatch : kMaxBatch)) break;
+                if ((int)batch[kind].size() >= (kind ? g_serve_ldlt_batch : g_serve_batch)) break;
                 const size_t need = q.bytes + q.ws_bytes;
                 size_t off = 0, ws_off = 0;
                 if (inflight_ >= max_inflight_ || used_ + need > budget_ || !arena_alloc(q.bytes, &off))

@@ -15,6 +15,10 @@
 
 namespace ffp {
 
+// Requests per unit part (tuning knobs; at least 1).
+extern int g_serve_batch;
+extern int g_serve_ldlt_batch;
+
 struct ServeReq {
     ffp_request rq;
     uint64_t ticket = 0;
