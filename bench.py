@@ -361,7 +361,7 @@ def eff_ops(r):
     return float(r["n"]) ** 2 * r["k"] if r["kind"] == "syrk" else float(r["n"]) ** 3 / 3.0
 
 
-def served(nreq, rate=2000.0, budget=48 << 30, nstreams=4, max_inflight=256, saturate=False,
+def served(nreq, rate=2000.0, budget=96 << 30, nstreams=4, max_inflight=1024, saturate=False,
            check=True, pool=None):
     """Serves the Poisson stream (seed 4) through the request loop; arrival
     times are followed unless saturate (all requests at t = 0).  Latency is

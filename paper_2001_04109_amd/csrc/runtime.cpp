@@ -6,6 +6,7 @@
 #include <vector>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 
 #include "ffp.h"
@@ -266,15 +267,24 @@ thread_local int g_last_variant = -1;
 
 int resident_blocks(const void* kernel, int threads)
 {
-    static int cus = 0;
+    // occupancy per (device, kernel, block size), queried once: launches
+    // are frequent and the query is a runtime call
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, int>, int> cache;
     int dev = 0;
-    if (cus == 0) {
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, kernel, threads);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
     }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per <= 0) per = 1;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = per * cus;
     return per * cus;
 }
 

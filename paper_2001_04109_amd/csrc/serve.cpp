@@ -218,6 +218,7 @@ Server::Server(DeviceIface* dev, size_t budget, int max_inflight, int nstreams)
     : dev_(dev), budget_(budget), max_inflight_(max_inflight), nstreams_(nstreams)
 {
     stream_busy_.assign(nstreams, 0);
+    pending_.assign(nstreams, nullptr);
     free_.push_back({0, budget});
 }
 
@@ -228,7 +229,14 @@ Server::~Server()
         stop_ = true;
     }
     cv_.notify_all();
-    if (th_.joinable()) th_.join();
+    if (th_.joinable()) th_.join();   // returns once every unit has finished
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        sched_done_ = true;
+    }
+    cv_launch_.notify_all();
+    for (std::thread& t : launchers_)
+        if (t.joinable()) t.join();
     delete dev_;
 }
 
@@ -236,8 +244,39 @@ int Server::start()
 {
     int st = dev_->init(budget_, nstreams_);
     if (st != FFP_OK) return st;
+    for (int s = 0; s < nstreams_; ++s) launchers_.emplace_back([this, s] { launcher(s); });
     th_ = std::thread([this] { loop(); });
     return FFP_OK;
+}
+
+// Enqueues the units the scheduler hands to stream s.  Units of different
+// streams are enqueued by their own threads, so the host work of one
+// (schedules, thousands of launches for a batch of factorisations) does not
+// hold up the others.
+void Server::launcher(int s)
+{
+    dev_->bind_thread();
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+        cv_launch_.wait(lk, [&] { return pending_[s] != nullptr || sched_done_; });
+        Unit* u = pending_[s];
+        if (!u) return;   // the scheduler has finished: nothing more to enqueue
+        pending_[s] = nullptr;
+        // the admitted entries are not touched by other threads while
+        // RUNNING (reqs_ is a deque: addresses are stable), nor is the unit
+        // until it is marked launched
+        lk.unlock();
+        int st[2] = {FFP_OK, FFP_OK};
+        if (!u->batch[0].empty()) st[0] = dev_->launch_syrk(u->batch[0], s, &u->part[0]);
+        if (!u->batch[1].empty()) st[1] = dev_->launch_ldlt(u->batch[1], s, &u->part[1]);
+        if (st[0] != FFP_OK || st[1] != FFP_OK) dev_->sync_stream(s);   // nothing may still run
+        lk.lock();
+        for (int k = 0; k < 2; ++k)
+            if (!u->batch[k].empty() && st[k] != FFP_OK) finish_part(u->part[k], st[k]);
+        u->launched = true;
+        cv_.notify_all();
+        cv_done_.notify_all();
+    }
 }
 
 
@@ -365,7 +404,7 @@ int Server::drain(double timeout_s)
     const auto deadline = std::chrono::steady_clock::now() +
                           std::chrono::duration_cast<std::chrono::steady_clock::duration>(
                               std::chrono::duration<double>(timeout_s));
-    auto idle = [this] { return queue_.empty() && running_.empty() && !launching_; };
+    auto idle = [this] { return queue_.empty() && running_.empty(); };
     while (!idle()) {
         if (cv_done_.wait_until(lk, deadline) == std::cv_status::timeout && !idle()) return FFP_EDEVICE;
     }
@@ -434,9 +473,13 @@ void Server::loop()
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
         bool progress = false;
-        // completions, part by part
-        for (size_t i = 0; i < running_.size();) {
-            Unit& u = running_[i];
+        // completions, part by part (of enqueued units)
+        for (auto it = running_.begin(); it != running_.end();) {
+            Unit& u = *it;
+            if (!u.launched) {
+                ++it;
+                continue;
+            }
             bool all = true;
             for (UnitPart& part : u.part) {
                 if (part.tickets.empty() || part.finished) continue;
@@ -449,10 +492,10 @@ void Server::loop()
             }
             if (all) {
                 stream_busy_[u.stream] = 0;
-                running_.erase(running_.begin() + (long)i);
+                it = running_.erase(it);
                 progress = true;
             } else {
-                ++i;
+                ++it;
             }
         }
         if (progress) cv_done_.notify_all();
@@ -494,24 +537,14 @@ void Server::loop()
                 for (ServeReq* q : batch[k]) u.part[k].tickets.push_back(q->ticket);
                 batched_jobs_ += (int64_t)batch[k].size();
                 max_batch_ = std::max<int64_t>(max_batch_, (int64_t)batch[k].size());
+                u.batch[k] = std::move(batch[k]);
             }
             if (running_.size() > 1) ++overlap_units_;
             ++units_;
             stream_busy_[s] = 1;
-            // Enqueue without the lock so that submitters are not held up by
-            // plan building; the admitted entries are not touched by other
-            // threads while RUNNING (reqs_ is a deque: addresses are stable),
-            // and running_ only changes on this thread.
-            launching_ = true;
-            lk.unlock();
-            int st[2] = {FFP_OK, FFP_OK};
-            if (!batch[0].empty()) st[0] = dev_->launch_syrk(batch[0], s, &u.part[0]);
-            if (!batch[1].empty()) st[1] = dev_->launch_ldlt(batch[1], s, &u.part[1]);
-            if (st[0] != FFP_OK || st[1] != FFP_OK) dev_->sync_stream(s);   // nothing may still run
-            lk.lock();
-            launching_ = false;
-            for (int k = 0; k < 2; ++k)
-                if (!batch[k].empty() && st[k] != FFP_OK) finish_part(u.part[k], st[k]);
+            // the stream's launch thread enqueues it
+            pending_[s] = &u;
+            cv_launch_.notify_all();
             progress = true;
         }
         if (stop_ && running_.empty()) break;

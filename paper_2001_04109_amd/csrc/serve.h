@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <deque>
+#include <list>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -41,20 +42,23 @@ struct UnitPart {
     bool finished = false;
 };
 
-// One launched unit of work on a stream: the admitted A*A^T requests as one
-// batched launch (part 0), then the admitted LDL^T requests as one
-// multi-factorisation (part 1).
+// One unit of work on a stream: the admitted A*A^T requests as one batched
+// launch (part 0), then the admitted LDL^T requests as one
+// multi-factorisation (part 1).  The stream's launch thread enqueues it;
+// completions are only checked once it has been enqueued.
 struct Unit {
     int stream = -1;
     double t_launch = 0;
     UnitPart part[2];
+    std::vector<ServeReq*> batch[2];
+    bool launched = false;
 };
 
 class DeviceIface {
 public:
     virtual ~DeviceIface() = default;
     virtual int init(size_t arena_bytes, int nstreams) = 0;
-    virtual void bind_thread() {}   // called first on the scheduler thread
+    virtual void bind_thread() {}   // called first on the scheduler and launch threads
     virtual char* arena() = 0;
     // Enqueue a batch of SYRK (or of LDLT) requests, results at arena + off,
     // on stream s.
@@ -84,6 +88,7 @@ public:
 
 private:
     void loop();
+    void launcher(int s);
     bool arena_alloc(size_t bytes, size_t* off);
     void arena_free(size_t off, size_t bytes);
 
@@ -91,14 +96,16 @@ private:
     size_t budget_;
     int max_inflight_, nstreams_;
     std::mutex mu_;
-    std::condition_variable cv_, cv_done_;
+    std::condition_variable cv_, cv_done_, cv_launch_;
     std::thread th_;
+    std::vector<std::thread> launchers_;   // one per stream
+    std::vector<Unit*> pending_;           // per stream: a unit to enqueue
     bool stop_ = false;
-    bool launching_ = false;               // a unit is being enqueued (lock dropped)
+    bool sched_done_ = false;              // the scheduler has returned: launch threads end
     std::deque<uint64_t> queue_;           // submitted, not admitted (FIFO)
     std::deque<ServeReq> reqs_;            // by ticket - 1 (stable addresses)
     std::deque<uint64_t> done_q_;          // finished, not yet returned by poll
-    std::vector<Unit> running_;
+    std::list<Unit> running_;              // admitted units (stable addresses)
     std::vector<char> stream_busy_;
     std::vector<std::pair<size_t, size_t>> free_;   // (offset, size), sorted
     size_t used_ = 0, peak_used_ = 0;
