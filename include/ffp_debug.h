@@ -62,7 +62,8 @@ void ffp_debug_set_kblk(int64_t kblk);
  * "f64_waves" (8, the default, or 4: waves per 128 x 128 FP64 workgroup;
  * other values FFP_EINVAL), "serve_batch" and "serve_ldlt_batch" (1 to
  * 4096: A*A^T and LDL^T requests per unit of the request loop; 128 and 32
- * by default),
+ * by default), "ldlt_fold" (1, the default: the LDL^T products run as steps
+ * of the per-level launch; 0: as separate product launches),
  * "i8_tile" (128 or 256: force the int8 product tile; 0 = automatic),
  * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile),
  * "i8_ring" (4 or 5: the 256 x 256 int8 tile loads its operands straight

@@ -39,15 +39,9 @@ __device__ inline void st_res(int cls, const Fp& f, const DView& v, int64_t i, i
         return;
     }
     if (cls == CLS_LIMB3) {
-        // centred value (|x| < 2^22) = l + 256 m + 65536 h
-        const int x = r > f.half ? (int)r - (int)f.p : (int)r;
-        const int l = ((x + 128) & 255) - 128;
-        const int y = (x - l) >> 8;
-        const int mid = ((y + 128) & 255) - 128;
         int8_t* b = (int8_t*)v.p;
-        b[i * v.ld + j] = (int8_t)l;
-        b[v.plane + i * v.ld + j] = (int8_t)mid;
-        b[2 * v.plane + i * v.ld + j] = (int8_t)((y - mid) >> 8);
+        limb3_split(r > f.half ? (int)r - (int)f.p : (int)r, &b[i * v.ld + j], &b[v.plane + i * v.ld + j],
+                    &b[2 * v.plane + i * v.ld + j]);
         return;
     }
     // limb pair with value in [-32896, 32639]

@@ -203,6 +203,7 @@ int ffp_debug_set(const char* key, int64_t value)
         return FFP_OK;
     }
     if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "ldlt_fold") == 0) { ffp::g_ldlt_fold = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "serve_batch") == 0 || strcmp(key, "serve_ldlt_batch") == 0) {
         if (value < 1 || value > 4096) return FFP_EINVAL;
         (key[6] == 'l' ? ffp::g_serve_ldlt_batch : ffp::g_serve_batch) = (int)value;

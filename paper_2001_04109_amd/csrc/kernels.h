@@ -71,6 +71,13 @@ constexpr int kL2TileM = 128, kL2TileN = 128;
 
 int64_t f64_kblk(uint32_t p);   // largest safe delayed-reduction block (multiple of 16)
 
+// Fill the tile grid and k-block of a task run tile by tile by another
+// kernel (the LDL^T step kernel): 64 x 64 FP64 tiles with operands from
+// global memory, or 64 x 64 three-limb int8 tiles.  false: the task needs
+// the regular launch (operand layout, or k beyond one exact block).
+bool prepare_f64_tile_task(ProdTask* t);
+bool prepare_limb3_tile_task(ProdTask* t);
+
 // Test cap on the delayed-reduction block (0: none).
 extern int64_t g_kblk_cap;
 // Tile-variant overrides for tests and tuning (0: automatic).

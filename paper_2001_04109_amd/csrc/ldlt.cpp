@@ -15,6 +15,8 @@
 
 namespace ffp {
 
+int g_ldlt_fold = 1;
+
 namespace {
 
 int64_t rup(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
@@ -121,6 +123,15 @@ struct Builder {
     }
     void prod(const ProdTask& t)
     {
+        if (g_ldlt_fold) {
+            // a step of the per-level launch, tile by tile
+            LdltDesc d = base();
+            d.t = t;
+            if (prepare_f64_tile_task(&d.t)) {
+                dev(LK_PRODF, d);
+                return;
+            }
+        }
         Step s{};
         s.level = level++;
         s.sk = SK_PROD;
@@ -130,6 +141,30 @@ struct Builder {
     }
     void plan_ops(const Plan& pl, const void* a, void* c, void* w)
     {
+        // a three-limb update (pack, product) as two steps of the per-level
+        // launches
+        if (g_ldlt_fold && pl.cls == CLS_LIMB3 && pl.ops.size() == 2 && pl.ops[0].kind == OP_PACK &&
+            pl.ops[1].kind == OP_SYRK) {
+            ProdTask t = make_task(pl, pl.ops[1], a, c, w);
+            if (prepare_limb3_tile_task(&t)) {
+                const PackDesc pk = make_pack(pl, pl.ops[0], a, c, w);
+                LdltDesc d = base();
+                d.X = (uint32_t*)pk.src.p;
+                d.ldx = pk.src.ld;
+                d.rows = pk.n;
+                d.ncols = (int32_t)pk.k;
+                d.rows_pad = pk.n_pad;
+                d.kpad = (int32_t)pk.k_pad;
+                d.Ab = (uint32_t*)pk.dst.p;
+                d.ldab = pk.dst.ld;
+                d.pplane = pk.dst.plane;
+                dev(LK_PACK3, d);
+                LdltDesc e = base();
+                e.t = t;
+                dev(LK_PRODL3, e);
+                return;
+            }
+        }
         std::vector<SchedItem> items;
         items.reserve(pl.ops.size());
         for (const Op& o : pl.ops) items.push_back(SchedItem{&pl, &o, a, c, w, 0});
@@ -268,7 +303,8 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
     // longest-running first); product tables for groups beyond the inline
     // capacity
     struct Slice { int first, count, blocks; };
-    static const int kOrder[LK_KINDS] = {LK_LEAF, LK_PAIR, LK_CLASSIFY, LK_TRSM, LK_ABAR, LK_SCALE, LK_ZERO};
+    static const int kOrder[LK_KINDS] = {LK_LEAF,  LK_PRODL3, LK_PRODF, LK_PAIR, LK_CLASSIFY,
+                                         LK_TRSM, LK_PACK3,  LK_ABAR,  LK_SCALE, LK_ZERO};
     std::vector<Slice> slices(maxlev + 1, Slice{0, 0, 0});
     std::vector<LdltDesc> table;
     size_t prod_bytes = 0;

@@ -44,6 +44,9 @@ enum LdltKind : int32_t {
     LK_PAIR,         // Algorithm 5: rank the non-residues, Algorithm 4 per pair, column ops
     LK_SCALE,        // L21 = W D1^-1 (X = W, rows x nb)
     LK_ABAR,         // Abar (rows x kpad) from the column ops on L21 = X
+    LK_PRODF,        // product task t, 64 x 64 FP64 tiles
+    LK_PACK3,        // uint32 residues -> three int8 limb planes (zero padded)
+    LK_PRODL3,       // product task t, 64 x 64 three-limb int8 tiles
     LK_KINDS
 };
 
@@ -66,6 +69,10 @@ struct LdltDesc {
     uint32_t s_lqnr, c_lqnr;
     uint32_t* Ab;
     int64_t ldab;
+    ProdTask t;        // LK_PRODF, LK_PRODL3
+    // LK_PACK3: X (rows x ncols, ldx) -> Ab as int8 planes (ldab, plane
+    // offset pplane) of rows_pad x kpad
+    int64_t rows_pad, pplane;
 };
 
 // Workgroups a descriptor of the kind needs (sets d->gx where used).
@@ -75,6 +82,9 @@ int ldlt_blocks(int kind, LdltDesc* d);
 hipError_t launch_ldlt_steps(const LdltDesc* dev, int n, int total_blocks, hipStream_t s);
 // Residue products whose sum stays below 2^53, at most 64.
 int ldlt_dot_block(uint32_t p);
+// 1 (default): products of the factorisation (solve updates, three-limb
+// Schur updates) run as steps of the per-level launch; 0: separate launches.
+extern int g_ldlt_fold;
 
 struct LdltJobSpec {
     int64_t n;

@@ -4,6 +4,8 @@
 // applied as column operations on L21.
 #include "ldlt.h"
 #include "modp.h"
+#include "prod_f64_tile.h"
+#include "prod_i8_tile.h"
 
 namespace ffp {
 
@@ -337,6 +339,20 @@ __device__ __forceinline__ void pair_body(Fp f, int n1, const uint32_t* S, int64
     if (tid == 0 && (total & 1) == 0) desc[n1] = ColOp{-1, 0u, -1, 0u};
 }
 
+// Abar (uint32 residues, rows x ncols at X) into three int8 limb planes of
+// rows_pad x kpad at Ab (zero padded), for the three-limb Schur product.
+__device__ __forceinline__ void pack3_body(const LdltDesc& d, int bx, int by, int gy)
+{
+    const int64_t c = (int64_t)bx * 64 + (threadIdx.x & 63);
+    if (c >= d.kpad) return;
+    int8_t* __restrict__ dst = (int8_t*)d.Ab;
+    for (int64_t r = (int64_t)by * 4 + (threadIdx.x >> 6); r < d.rows_pad; r += (int64_t)gy * 4) {
+        const uint32_t v = (r < d.rows && c < d.ncols) ? d.X[r * d.ldx + c] : 0u;
+        const int64_t o = r * d.ldab + c;
+        limb3_split(v > d.f.half ? (int)v - (int)d.f.p : (int)v, &dst[o], &dst[d.pplane + o], &dst[2 * d.pplane + o]);
+    }
+}
+
 // L21 = W D^-1 in place (column j scaled by dinv[j]).
 __device__ __forceinline__ void scale_cols_body(Fp f, int64_t rows, int n1, uint32_t* W, int64_t ldw,
                                                 const uint32_t* dinv, int bx, int by, int gy)
@@ -393,6 +409,7 @@ union StepLds {
     LeafLds leaf;
     TrsmLds trsm;
     PairLds pair;
+    int8_t i8[I8Tile<64, 64, 64, 3>::LDS];
 };
 
 __global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n)
@@ -424,6 +441,15 @@ __global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n
         build_abar_body(d.f, d.rows, d.ncols, d.kpad, d.X, d.ldx, d.sc.desc, d.Ab, d.ldab, lb % d.gx, lb / d.gx,
                         row_bands(d.rows));
         break;
+    case LK_PRODF:
+        f64_tile_task(d.t, lb);
+        break;
+    case LK_PACK3:
+        pack3_body(d, lb % d.gx, lb / d.gx, row_bands(d.rows_pad));
+        break;
+    case LK_PRODL3:
+        i8_tile_task<64, 64, 64, 3>(d.t, lb, lds.i8);
+        break;
     default:
         break;
     }
@@ -452,6 +478,12 @@ int ldlt_blocks(int kind, LdltDesc* d)
     case LK_ABAR:
         d->gx = (d->kpad + 63) / 64;
         return d->rows > 0 ? d->gx * row_bands(d->rows) : 0;
+    case LK_PACK3:
+        d->gx = (d->kpad + 63) / 64;
+        return d->rows_pad > 0 ? d->gx * row_bands(d->rows_pad) : 0;
+    case LK_PRODF:
+    case LK_PRODL3:
+        return d->t.syrk ? d->t.tm * (d->t.tm + 1) / 2 : d->t.tm * d->t.tn;
     default: return 0;
     }
 }

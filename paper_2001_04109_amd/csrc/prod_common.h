@@ -47,6 +47,18 @@ __device__ inline int xcd_remap(int b, int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
+// Three-limb storage of a centred residue x (|x| < 2^22): x = l + 256 m +
+// 65536 h with l, m in [-128, 127] (and then |h| <= 65).
+__device__ inline void limb3_split(int x, int8_t* l, int8_t* m, int8_t* h)
+{
+    const int lo = ((x + 128) & 255) - 128;
+    const int y = (x - lo) >> 8;
+    const int mid = ((y + 128) & 255) - 128;
+    *l = (int8_t)lo;
+    *m = (int8_t)mid;
+    *h = (int8_t)((y - mid) >> 8);
+}
+
 __device__ inline double mod_f64(double x, double p, double pinv)
 {
     // x is an integer with |x| < 2^53; the quotient estimate is off by at most one

@@ -138,3 +138,27 @@ def test_ldlt_batched_equals_alone_and_oracle():
             assert np.array_equal(out[low], alone[low])
             assert np.array_equal(out[low], ref[low])
     assert infos[-1] == 101
+
+
+@pytest.mark.parametrize("p", [65537, 131071, 251])
+def test_ldlt_products_folded_or_launched_agree(p):
+    """The factorisation's products as steps of the per-level launch (the
+    default) or as separate product launches: bit-identical results."""
+    from tests.gpu_util import set_knob
+    n = 700
+    S = inputs.symmetric(960 + p % 7, n, p)
+    outs = []
+    for fold in (1, 0):
+        set_knob("ldlt_fold", fold)
+        try:
+            outs.append(gpu_ldlt(S, p))
+        finally:
+            set_knob("ldlt_fold", 1)
+    (a, ia), (b, ib) = outs
+    assert ia == ib
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(a[low], b[low])
+    ref, rinfo = oracle.ldlt_packed(S, p)
+    assert ia == rinfo
+    if ia == 0:
+        assert np.array_equal(a[low], ref[low])
