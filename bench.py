@@ -86,7 +86,7 @@ def profile_hooks():
     def read_variants():
         """{variant: (ms, flops, launches, name)} of the recorded launches."""
         out = {}
-        for v in range(10):
+        for v in range(11):
             ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
             L.ffp_debug_profile_read_variant(v, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n))
             if n.value:
@@ -448,6 +448,31 @@ def per_call_plain(reqs, pool):
     return {"s": round(dt, 3), "gops_total": round(tot / dt / 1e9, 1)}
 
 
+def vendor_int8_gemm(n=16384, reps=5):
+    """The vendor library's int8 GEMM (torch._int_mm, hipBLASLt on ROCm) on an
+    n x n operand of centred residues mod 251 times its transpose, as context
+    for the int8 product kernel: it computes the full n x n int32 product
+    (2 n^3 operations), so as an A A^T path its effective rate is n^3 / time."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2)
+    A = torch.randint(-125, 126, (n, n), dtype=torch.int8, device="cuda", generator=g)
+    B = A.t().contiguous()
+    torch._int_mm(A, B)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch._int_mm(A, B)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    real = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    return {"op": "torch._int_mm int8 x int8 -> int32, full %dx%dx%d" % (n, n, n), "ms": round(ms, 4),
+            "TOPs": round(real, 1), "frac_int8_peak": round(real / PEAK_I8, 4),
+            "as_AAT_effective_gops": round(n ** 3 / (ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(name):
     """Oracle on a bounded sample: rows [n-r, n) of the lower triangle of the
     first shape, i.e. r*(2n-r+1)/2 dot products of length k (r = n for the
@@ -531,6 +556,14 @@ def main():
             extra[other] = {"gops": round(r2["gops"], 1), "ms_per_step": round(r2["ms_per_step"], 4),
                             "frac_int8_peak_effective": round(r2["gops"] / 1e3 / PEAK_I8, 4),
                             "kernel_achieved_TOPs": round(a2, 2), "kernel": r2.get("kernel")}
+            if other == "syrk_16384_p251_int8":
+                try:
+                    v = vendor_int8_gemm()
+                    v["ours_vs_vendor_effective"] = round(r2["gops"] / v["as_AAT_effective_gops"], 3)
+                except Exception as e:   # the library GEMM is context only
+                    v = {"error": repr(e)[:200]}
+                log(f"bench: vendor int8 GEMM {v}")
+                extra[other]["vendor_int8_gemm"] = v
     if not args.no_extra and not args.no_batched:
         log("bench: batched 1024 jobs vs per-call")
         extra["batched_1024_jobs"] = batched_vs_plain()

@@ -68,7 +68,10 @@ void ffp_debug_set_kblk(int64_t kblk);
  * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile),
  * "i8_ring" (4 or 5: the 256 x 256 int8 tile loads its operands straight
  * into a ring of that many LDS stages; 0 = register-staged loads; other
- * values FFP_EINVAL),
+ * values FFP_EINVAL), "i8_pipe" (1, the default: the 256 x 256 int8 tile
+ * with 128-byte k stages writes each stage's operands to LDS between the
+ * MFMAs of the previous stage and loads them up to two stages ahead; 0: the
+ * stage's LDS writes after its MFMAs),
  * "persistent" (1: grouped product launches run persistent workgroups that
  * stride over the tiles; 0: one workgroup per tile), "leveled" (1, the
  * default: a call's block operations run level by level, independent
@@ -90,7 +93,9 @@ int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches
 /* Same, restricted to one product-kernel variant (0 FP64 64x64 tiles, 1 FP64
  * 128x128 LDS-staged tiles, 2 int8 128x128, 3 int8 256x256 with 64-byte k
  * stages, 4 int8 256x256 with 128-byte k stages, 5 int8 limbs 128x128,
- * 6 and 7 int8 256x256 with a ring of 4 or 5 direct-to-LDS stages);
+ * 6 and 7 int8 256x256 with a ring of 4 or 5 direct-to-LDS stages, 8 FP64
+ * 128x128 with 8 waves, 9 int8 three limbs 64x64, 10 int8 256x256 with the
+ * LDS writes between the MFMAs);
  * ffp_debug_variant_name gives the kernel's demangled name. */
 int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches);
 const char* ffp_debug_variant_name(int variant);

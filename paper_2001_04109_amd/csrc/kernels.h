@@ -90,6 +90,7 @@ extern int g_f64_waves;        // waves per 128 x 128 FP64 workgroup: 8 (default
 // choice of the call's plan.
 extern thread_local int g_tile_hint;
 extern int g_i8_ring;          // CLS_I8 256x256: ring of 4 or 5 direct-to-LDS stages (0: off)
+extern int g_i8_pipe;          // CLS_I8 256x256x128: LDS writes spread over the MFMAs, loads two stages ahead
 // Multi-task product launches run persistent workgroups (1, default) or one
 // workgroup per tile (0).
 extern int g_persistent;

@@ -233,6 +233,214 @@ __global__ __launch_bounds__(256) void prod_i8_ring_kernel(ProdArgs args, int mo
     if (b < args.total_tiles) i8_ring_tile<BM, BN, NS>(args, b);
 }
 
+// ---- CLS_I8 with the LDS writes spread over the MFMAs -------------------
+//
+// Same tile, wave decomposition, LDS layout and epilogue as
+// i8_tile_task<BM, BN, BK, 1>, in a different order per stage of BK = 128
+// bytes (four k-steps of 32): two register sets hold the operand panels of
+// the next two stages, so the global loads issued at the start of stage t
+// (for stage t + 2) have more than a stage to land; the set loaded one stage
+// earlier is written to the free LDS buffer during k-steps 1 (A panel) and 2
+// (B panel) of stage t, between the MFMAs; the workgroup barrier sits before
+// k-step 3, whose MFMAs cover the reads of the first fragments of stage t + 1.
+// Stages are processed in pairs; the loads of stages past the end of k return
+// zeros (see bload), so an odd count gets one stage of zero products.
+// Panel loads through a buffer resource whose base is the panel's first row
+// (raw buffer, size = the valid rows' bytes, below 2^31).  For a full panel
+// the row offset of each pass is uniform and goes in the scalar offset, so a
+// lane keeps one vector offset for all its loads; for a partial panel (EDGE)
+// every load carries its own row offset and rows past the end fall outside
+// the resource.  Buffer loads outside the resource return zero, and the
+// outputs of rows past the end are never stored.  A stage past the end of k
+// (`live` false) adds 2^31 to the vector offsets, so all its loads return
+// zero and it adds nothing.
+template <int ROWS, int BK, bool EDGE>
+__device__ __forceinline__ void bload(Prefetch<ROWS, BK>& pf, __amdgpu_buffer_rsrc_t rs, int ld, int k0,
+                                      bool live)
+{
+    constexpr int CHUNKS = Prefetch<ROWS, BK>::CHUNKS;
+    constexpr int RPP = 256 / CHUNKS;                      // rows per pass
+    const uint32_t off = live ? 0u : 0x80000000u;
+    const int r0 = threadIdx.x / CHUNKS, c = threadIdx.x % CHUNKS;
+    const uint32_t vbase = (uint32_t)(r0 * ld + c * 16) + off;
+#pragma unroll
+    for (int ps = 0; ps < Prefetch<ROWS, BK>::PASSES; ++ps) {
+        if constexpr (EDGE) {
+            pf.v[ps] = __builtin_amdgcn_raw_buffer_load_b128(rs, vbase + (uint32_t)(ps * RPP * ld),
+                                                             __builtin_amdgcn_readfirstlane(k0), 0);
+        } else {
+            pf.v[ps] = __builtin_amdgcn_raw_buffer_load_b128(rs, vbase,
+                                                             __builtin_amdgcn_readfirstlane(k0 + ps * RPP * ld), 0);
+        }
+    }
+}
+
+// The panel's values are the same in every lane; readfirstlane lets the
+// compiler keep the resource in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const int8_t* p, int64_t bytes)
+{
+    const uint64_t a = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const int nb = __builtin_amdgcn_readfirstlane((int)(bytes < 0x7FFFFFFF ? bytes : 0x7FFFFFFF));
+    void* base = (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    // raw buffer (stride 0), 32-bit dword format word for CDNA
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nb, 0x00020000);
+}
+
+template <int BM, int BN, int BK, bool EDGE>
+__device__ __forceinline__ void i8_pipe_body(const ProdTask& t, int ti, int tj, int8_t* smem)
+{
+    constexpr int PITCH = BK + 16;
+    constexpr int WTM = BM / 2, WTN = BN / 2;
+    constexpr int FM = WTM / 32, FN = WTN / 32;
+    constexpr int KS = BK / 32;
+    static_assert(KS == 4, "four k-steps per stage");
+    auto sa = reinterpret_cast<int8_t(*)[BM * PITCH]>(smem);
+    auto sb = reinterpret_cast<int8_t(*)[BN * PITCH]>(smem + 2 * BM * PITCH);
+    const int tile_r = ti * BM, tile_c = tj * BN;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lrow = lane & 31, lk = lane >> 5;
+
+    v16i acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0;
+    const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
+
+    const int nk = t.k / BK;
+    if (nk > 0) {
+        auto read_frags = [&](v4i (&xa)[FM], v4i (&xb)[FN], int buf, int ks) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                xa[i] = *reinterpret_cast<const v4i*>(&sa[buf][(wr * WTM + i * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                xb[j] = *reinterpret_cast<const v4i*>(&sb[buf][(wc * WTN + j * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
+        };
+        auto mfmas = [&](const v4i (&xa)[FM], const v4i (&xb)[FN]) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[i], xb[j], acc[i][j], 0, 0, 0);
+        };
+        constexpr int NREAD = FM + FN, NMFMA = FM * FN;
+        constexpr int WA = Prefetch<BM, BK>::PASSES, WB = Prefetch<BN, BK>::PASSES;
+        const int va = t.m - tile_r < BM ? t.m - tile_r : BM;    // valid rows of the panels
+        const int vb = t.n - tile_c < BN ? t.n - tile_c : BN;
+        const int lda = __builtin_amdgcn_readfirstlane((int)t.A.ld);
+        const int ldb = __builtin_amdgcn_readfirstlane((int)t.B.ld);
+        const __amdgpu_buffer_rsrc_t ra =
+            panel_rsrc((const int8_t*)t.A.p + (int64_t)tile_r * t.A.ld, (int64_t)va * t.A.ld);
+        const __amdgpu_buffer_rsrc_t rb =
+            panel_rsrc((const int8_t*)t.B.p + (int64_t)tile_c * t.B.ld, (int64_t)vb * t.B.ld);
+        Prefetch<BM, BK> pa0, pa1;
+        Prefetch<BN, BK> pb;
+        bload<BM, BK, EDGE>(pa0, ra, lda, 0, true);
+        bload<BN, BK, EDGE>(pb, rb, ldb, 0, true);
+        bload<BM, BK, EDGE>(pa1, ra, lda, BK, nk > 1);
+        lstore<BM, BK>(sa[0], pa0);
+        lstore<BN, BK>(sb[0], pb);
+        bload<BN, BK, EDGE>(pb, rb, ldb, BK, nk > 1);
+        __syncthreads();
+        v4i fa[FM], fb[FN];
+        read_frags(fa, fb, 0, 0);
+
+        auto stage = [&](auto par, int kt) {
+            constexpr int cur = decltype(par)::value;
+            Prefetch<BM, BK>& la = cur ? pa1 : pa0;   // reloaded now (its stage is in LDS)
+            Prefetch<BM, BK>& wa = cur ? pa0 : pa1;   // stage kt + 1, written now
+            __builtin_amdgcn_sched_barrier(0);
+            bload<BM, BK, EDGE>(la, ra, lda, (kt + 2) * BK, kt + 2 < nk);
+            __builtin_amdgcn_sched_barrier(0);
+            v4i na[FM], nb[FN];
+            // k-step 0
+            read_frags(na, nb, cur, 1);
+            mfmas(fa, fb);
+#pragma unroll
+            for (int q = 0; q < NREAD; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / NREAD, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // k-step 1, A panel of stage kt + 1 to LDS
+            read_frags(fa, fb, cur, 2);
+            mfmas(na, nb);
+            lstore<BM, BK>(sa[cur ^ 1], wa);
+#pragma unroll
+            for (int q = 0; q < NREAD; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WA), 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, WA / NREAD, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WA), 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // k-step 2, B panel of stage kt + 1 to LDS, then the loads of
+            // stage kt + 2's B panel into the same registers
+            read_frags(na, nb, cur, 3);
+            mfmas(fa, fb);
+            lstore<BN, BK>(sb[cur ^ 1], pb);
+#pragma unroll
+            for (int q = 0; q < NREAD; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WB), 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, WB / NREAD, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WB), 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            bload<BN, BK, EDGE>(pb, rb, ldb, (kt + 2) * BK, kt + 2 < nk);
+            __syncthreads();
+            // k-step 3 with the first fragments of stage kt + 1
+            read_frags(fa, fb, cur ^ 1, 0);
+            mfmas(na, nb);
+#pragma unroll
+            for (int q = 0; q < NREAD; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / NREAD, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        // stages in pairs (static register sets and buffers, no branch
+        // between them); for odd nk the last stage of the last pair has
+        // all-zero operands
+        for (int kt = 0; kt < nk; kt += 2) {
+            stage(std::integral_constant<int, 0>{}, kt);
+            stage(std::integral_constant<int, 1>{}, kt + 1);
+        }
+    }
+    store_tile_i8_reg<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+}
+
+template <int BM, int BN, int BK>
+__device__ __forceinline__ void i8_pipe_tile(const ProdArgs& args, int b)
+{
+    __shared__ __attribute__((aligned(16))) int8_t smem[I8Tile<BM, BN, BK, 1>::LDS];
+    ProdTask t;
+    select_task(args, b, &t);
+    const int r = b - t.tile0;
+    int ti, tj;
+    if (t.syrk) band_tri(r, t.tm, &ti, &tj);
+    else band_rect(r, t.tm, t.tn, &ti, &tj);
+    if ((ti + 1) * BM <= t.m && (tj + 1) * BN <= t.n) i8_pipe_body<BM, BN, BK, false>(t, ti, tj, smem);
+    else i8_pipe_body<BM, BN, BK, true>(t, ti, tj, smem);
+}
+
+template <int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void prod_i8_pipe_kernel(ProdArgs args, int mode)
+{
+    if (mode == 2) {
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) i8_pipe_tile<BM, BN, BK>(args, b);
+        return;
+    }
+    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b < args.total_tiles) i8_pipe_tile<BM, BN, BK>(args, b);
+}
+
 // mode 0: one workgroup per tile; 1: same, XCD-aware order; 2: persistent.
 template <int BM, int BN, int BK, int PLANES>
 __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int mode)
@@ -281,6 +489,14 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         }
         g_last_variant = 6 + (RING - 4);
         hipLaunchKernelGGL((prod_i8_ring_kernel<BM, BN, RING>), dim3(grid), dim3(256), 0, s, args, mode);
+    } else if constexpr (RING < 0) {
+        static_assert(PLANES == 1 && BK == 128, "pipelined variant: CLS_I8, 128-byte stages");
+        if (mode == 2) {
+            const int resident = resident_blocks((const void*)prod_i8_pipe_kernel<BM, BN, BK>);
+            grid = total < resident ? total : resident;
+        }
+        g_last_variant = 10;
+        hipLaunchKernelGGL((prod_i8_pipe_kernel<BM, BN, BK>), dim3(grid), dim3(256), 0, s, args, mode);
     } else {
         if (mode == 2) {
             const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES>);
@@ -369,6 +585,7 @@ bool prepare_limb3_tile_task(ProdTask* t)
 int g_i8_tile_override = 0;
 int g_i8_bk_override = 0;
 int g_i8_ring = 0;
+int g_i8_pipe = 1;
 
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
@@ -383,6 +600,11 @@ hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_bu
         if (g_i8_ring == 4) return launch_i8_impl<256, 256, 64, 1, 4>(tasks, ntasks, dev_task_buf, s);
         if (g_i8_ring == 5) return launch_i8_impl<256, 256, 64, 1, 5>(tasks, ntasks, dev_task_buf, s);
         if (g_i8_bk_override == 64 || !k128) return launch_i8_impl<256, 256, 64, 1>(tasks, ntasks, dev_task_buf, s);
+        // the pipelined kernel addresses a 256-row panel with 32-bit offsets
+        bool pipe_ok = g_i8_pipe != 0;
+        for (int i = 0; i < ntasks; ++i)
+            pipe_ok = pipe_ok && tasks[i].A.ld < (1 << 23) && tasks[i].B.ld < (1 << 23);
+        if (pipe_ok) return launch_i8_impl<256, 256, 128, 1, -1>(tasks, ntasks, dev_task_buf, s);
         return launch_i8_impl<256, 256, 128, 1>(tasks, ntasks, dev_task_buf, s);
     }
     return launch_i8_impl<128, 128, 64, 1>(tasks, ntasks, dev_task_buf, s);

@@ -176,6 +176,33 @@ def test_i8_ring_variants(ring, n, k):
         set_knob("i8_tile", 0)
 
 
+@pytest.mark.parametrize("pipe", [1, 0])
+@pytest.mark.parametrize("n,k", [(300, 256), (513, 128), (512, 384), (1000, 640), (1100, 4096), (256, 128)])
+def test_i8_pipe_variant(pipe, n, k):
+    """256 x 256 int8 tiles with 128-byte k stages, with the LDS writes
+    between the MFMAs and the loads two stages ahead (the default) or after
+    them: one, two and an odd number of k-stages, partial and full panels,
+    general products (depth 1) and k in chunks."""
+    p = 251
+    A = inputs.uniform(n + k + 11, n, k, p)
+    set_knob("i8_tile", 256)
+    set_knob("i8_pipe", pipe)
+    try:
+        check_lower(gpu_syrk(A, p, depth=0, a_dtype=ffp.FFP_I8_CENTERED), oracle.syrk(A, p))
+        C0 = inputs.uniform(9, n, n, p)
+        check_lower(gpu_syrk(A, p, depth=0, alpha=3, beta=5, C0=C0), oracle.syrk_ab(A, p, 3, 5, C0))
+        if k % 256 == 0:
+            check_lower(gpu_syrk(A, p, depth=1, alpha=p - 1, beta=1, C0=C0),
+                        oracle.syrk_ab(A, p, p - 1, 1, C0))
+            set_kblk(256)      # k in chunks of two stages, accumulated through C
+            check_lower(gpu_syrk(A, p, depth=0, alpha=p - 1, beta=1, C0=C0),
+                        oracle.syrk_ab(A, p, p - 1, 1, C0))
+    finally:
+        set_kblk(0)
+        set_knob("i8_pipe", 1)
+        set_knob("i8_tile", 0)
+
+
 @pytest.mark.parametrize("p,a_dtype", [(251, ffp.FFP_U32), (251, ffp.FFP_I8_CENTERED),
                                        (65521, ffp.FFP_U32), (65521, ffp.FFP_I8_LIMB2),
                                        (257, ffp.FFP_U32)])
