@@ -71,7 +71,10 @@ void ffp_debug_set_kblk(int64_t kblk);
  * values FFP_EINVAL), "i8_pipe" (1, the default: the 256 x 256 int8 tile
  * with 128-byte k stages writes each stage's operands to LDS between the
  * MFMAs of the previous stage and loads them up to two stages ahead; 0: the
- * stage's LDS writes after its MFMAs),
+ * stage's LDS writes after its MFMAs), "f64_pipe" (1, the default: the
+ * 128 x 128 FP64 tile of 8 waves keeps its operands as doubles in LDS,
+ * converted once per workgroup, when k fits one exact block; 0: centred
+ * int32 in LDS, converted by every wave that reads them),
  * "persistent" (1: grouped product launches run persistent workgroups that
  * stride over the tiles; 0: one workgroup per tile), "leveled" (1, the
  * default: a call's block operations run level by level, independent
@@ -95,7 +98,7 @@ int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches
  * stages, 4 int8 256x256 with 128-byte k stages, 5 int8 limbs 128x128,
  * 6 and 7 int8 256x256 with a ring of 4 or 5 direct-to-LDS stages, 8 FP64
  * 128x128 with 8 waves, 9 int8 three limbs 64x64, 10 int8 256x256 with the
- * LDS writes between the MFMAs);
+ * LDS writes between the MFMAs, 11 FP64 128x128 with doubles in LDS);
  * ffp_debug_variant_name gives the kernel's demangled name. */
 int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches);
 const char* ffp_debug_variant_name(int variant);

@@ -203,6 +203,7 @@ int ffp_debug_set(const char* key, int64_t value)
         return FFP_OK;
     }
     if (strcmp(key, "i8_pipe") == 0) { ffp::g_i8_pipe = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "f64_pipe") == 0) { ffp::g_f64_pipe = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "ldlt_fold") == 0) { ffp::g_ldlt_fold = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "serve_batch") == 0 || strcmp(key, "serve_ldlt_batch") == 0) {
@@ -244,6 +245,7 @@ const char* ffp_debug_variant_name(int variant)
     case 8: return "void ffp::prod_f64_lds_kernel<8>(ffp::ProdArgs, int)";
     case 9: return "void ffp::prod_i8_kernel<64, 64, 64, 3>(ffp::ProdArgs, int)";
     case 10: return "void ffp::prod_i8_pipe_kernel<256, 256, 128>(ffp::ProdArgs, int)";
+    case 11: return "ffp::prod_f64_pipe_kernel(ffp::ProdArgs, int)";
     default: return "";
     }
 }

@@ -85,6 +85,7 @@ extern int g_f64_tile_override;
 extern int g_i8_tile_override;
 extern int g_i8_bk_override;
 extern int g_f64_waves;        // waves per 128 x 128 FP64 workgroup: 8 (default) or 4
+extern int g_f64_pipe;         // FP64 128x128, 8 waves: operands as doubles in LDS (when k fits one exact block)
 // Tile edge chosen for the product launches of the current call on this
 // thread (0: the launch rule or the override above); set from the tuned
 // choice of the call's plan.

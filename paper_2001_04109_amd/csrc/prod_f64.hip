@@ -231,6 +231,213 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
     }
 }
 
+// ---- 128 x 128 tiles, operands as doubles in LDS ---------------------------
+// Same tile and 8-wave decomposition as f64_lds_tile<8>, for tasks with
+// k <= kblk (no reduction inside the k-loop), k a multiple of 4 and aligned
+// rows.  Matrix-core instructions do not run while the SIMD executes other
+// vector instructions, so this variant minimises them: every operand value
+// is centred and converted to double once per workgroup, when it is written
+// to LDS, instead of once per wave that reads it (four waves read each A
+// value, two each B value).  Two LDS buffers of 128 x 32 doubles per
+// operand; two register sets hold the raw panels of the next two stages
+// (loaded through buffer resources with one 32-bit offset per load; chunks
+// past the end of k or of the rows return zero); stage t writes the panels
+// of stage t + 1 into the free buffer during its first k-group, the barrier
+// sits between its two k-groups, and the second k-group's MFMAs cover the
+// reads of stage t + 1's first fragments.  Stages run in pairs (static
+// register sets); for an odd count the last stage is all zeros.
+namespace {
+constexpr int PD = BK2 + 2;   // LDS pitch in doubles: 16 rows of a 16-byte column hit distinct banks
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t f64_panel_rsrc(const uint32_t* p, int64_t bytes)
+{
+    const uint64_t a = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const int nb = __builtin_amdgcn_readfirstlane((int)(bytes < 0x7FFFFFFF ? bytes : 0x7FFFFFFF));
+    void* base = (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nb, 0x00020000);
+}
+
+struct F64Raw { v4u v[2]; };   // 2 passes of 512 threads x 4 values = 128 rows x 32 k
+
+// Raw residues of stage k0 (columns k0 .. k0 + 31) of a 128-row panel.
+__device__ __forceinline__ void f64_bload(F64Raw& pf, __amdgpu_buffer_rsrc_t rs, int ld, int k0, int K)
+{
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+        const int idx = ps * 512 + threadIdx.x;
+        const int r = idx >> 3, c = (idx & 7) * 4;
+        // bit 31 set (out of range) for chunks past the end of k, without a branch
+        const uint32_t out = (uint32_t)(K - 4 - c - k0) >> 31;
+        const uint32_t off = ((uint32_t)(r * ld + k0 + c) * 4u) | (out << 31);
+        pf.v[ps] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    }
+}
+
+// Centre, convert and write one stage's panel to LDS (row r, 4 doubles).
+__device__ __forceinline__ void f64_dstore(double* __restrict__ lds, const F64Raw& pf, uint32_t half, uint32_t p)
+{
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+        const int idx = ps * 512 + threadIdx.x;
+        const int r = idx >> 3, c = (idx & 7) * 4;
+        const v4u v = pf.v[ps];
+        v4d d;
+        d.x = (double)(int32_t)(v.x > half ? v.x - p : v.x);
+        d.y = (double)(int32_t)(v.y > half ? v.y - p : v.y);
+        d.z = (double)(int32_t)(v.z > half ? v.z - p : v.z);
+        d.w = (double)(int32_t)(v.w > half ? v.w - p : v.w);
+        *reinterpret_cast<v4d*>(lds + r * PD + c) = d;
+    }
+}
+}  // namespace
+
+__device__ __forceinline__ void f64_pipe_tile(const ProdArgs& args, int b)
+{
+    constexpr int NW = 8;
+    using G = F64Lds<NW>;
+    constexpr int WM2 = G::WM, WN2 = G::WN;     // 4 x 2 blocks of 16 x 16
+    __shared__ __attribute__((aligned(16))) double sa[2][BM2 * PD];
+    __shared__ __attribute__((aligned(16))) double sb[2][BM2 * PD];
+    ProdTask t;
+    select_task(args, b, &t);
+    const int r = b - t.tile0;
+    int ti, tj;
+    if (t.syrk) tri_index(r, &ti, &tj);
+    else { ti = r / t.tn; tj = r - ti * t.tn; }
+    const int tile_r = ti * BM2, tile_c = tj * BM2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wr = wave / G::WCOLS, wc = wave % G::WCOLS;
+    const int lr = lane & 15, lk = lane >> 4;
+    const double pd = (double)t.p;
+    const int K = t.k;
+    const int nk = (K + BK2 - 1) / BK2;
+
+    v4d acc[WM2][WN2];
+#pragma unroll
+    for (int i = 0; i < WM2; ++i)
+#pragma unroll
+        for (int j = 0; j < WN2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    if (nk > 0) {
+        const int va = t.m - tile_r < BM2 ? t.m - tile_r : BM2;
+        const int vb = t.n - tile_c < BM2 ? t.n - tile_c : BM2;
+        const int lda = __builtin_amdgcn_readfirstlane((int)t.A.ld);
+        const int ldb = __builtin_amdgcn_readfirstlane((int)t.B.ld);
+        const __amdgpu_buffer_rsrc_t ra =
+            f64_panel_rsrc((const uint32_t*)t.A.p + (int64_t)tile_r * t.A.ld, (int64_t)va * t.A.ld * 4);
+        const __amdgpu_buffer_rsrc_t rb =
+            f64_panel_rsrc((const uint32_t*)t.B.p + (int64_t)tile_c * t.B.ld, (int64_t)vb * t.B.ld * 4);
+        const uint32_t half = t.half, p = t.p;
+
+        // fragments: lane (lr, lk) holds k = 4 lk .. 4 lk + 3 of its row in a k-group
+        auto read_frags = [&](v4d (&xa)[WM2], v4d (&xb)[WN2], int buf, int kg) {
+#pragma unroll
+            for (int i = 0; i < WM2; ++i)
+                xa[i] = *reinterpret_cast<const v4d*>(&sa[buf][(wr * 64 + i * 16 + lr) * PD + kg * 16 + 4 * lk]);
+#pragma unroll
+            for (int j = 0; j < WN2; ++j)
+                xb[j] = *reinterpret_cast<const v4d*>(&sb[buf][(wc * G::WTN + j * 16 + lr) * PD + kg * 16 + 4 * lk]);
+        };
+        auto mfmas = [&](const v4d (&xa)[WM2], const v4d (&xb)[WN2]) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int i = 0; i < WM2; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i][s4], xb[j][s4], acc[i][j], 0, 0, 0);
+        };
+        constexpr int NMF = 4 * WM2 * WN2;          // MFMAs per k-group
+        constexpr int NRD = 2 * (WM2 + WN2);        // 16-byte LDS reads per k-group
+
+        F64Raw a0, b0, a1, b1;
+        f64_bload(a0, ra, lda, 0, K);
+        f64_bload(b0, rb, ldb, 0, K);
+        f64_bload(a1, ra, lda, BK2, K);
+        f64_bload(b1, rb, ldb, BK2, K);
+        f64_dstore(sa[0], a0, half, p);
+        f64_dstore(sb[0], b0, half, p);
+        __syncthreads();
+        v4d fa[WM2], fb[WN2];
+        read_frags(fa, fb, 0, 0);
+
+        auto stage = [&](auto par, int kt) {
+            constexpr int cur = decltype(par)::value;
+            F64Raw& la = cur ? a1 : a0;   // reloaded now (its stage is in LDS)
+            F64Raw& lb = cur ? b1 : b0;
+            F64Raw& wa = cur ? a0 : a1;   // stage kt + 1, written now
+            F64Raw& wb = cur ? b0 : b1;
+            __builtin_amdgcn_sched_barrier(0);
+            f64_bload(la, ra, lda, (kt + 2) * BK2, K);
+            f64_bload(lb, rb, ldb, (kt + 2) * BK2, K);
+            __builtin_amdgcn_sched_barrier(0);
+            v4d na[WM2], nb[WN2];
+            // k-group 0: stage kt + 1 to LDS, k-group 1's fragments read
+            read_frags(na, nb, cur, 1);
+            f64_dstore(sa[cur ^ 1], wa, half, p);
+            f64_dstore(sb[cur ^ 1], wb, half, p);
+            mfmas(fa, fb);
+            // per quarter: 3 reads, 2 MFMAs, 16 conversion instructions,
+            // 2 LDS writes, 6 MFMAs
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x100, NRD / 4, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF / 4 - 2, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();
+            // k-group 1 with the first fragments of stage kt + 1
+            read_frags(fa, fb, cur ^ 1, 0);
+            mfmas(na, nb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x100, NRD / 4, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF / 4, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        for (int kt = 0; kt < nk; kt += 2) {
+            stage(std::integral_constant<int, 0>{}, kt);
+            stage(std::integral_constant<int, 1>{}, kt + 1);
+        }
+    }
+
+    const double alpha = (double)t.alpha, beta = (double)t.beta;
+#pragma unroll
+    for (int i = 0; i < WM2; ++i) {
+#pragma unroll
+        for (int j = 0; j < WN2; ++j) {
+            const int col = tile_c + wc * G::WTN + j * 16 + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = tile_r + wr * 64 + i * 16 + 4 * e + lk;
+                if (row >= t.m || col >= t.n) continue;
+                if (t.syrk && col > row) continue;
+                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                double v = mod_f64(acc[i][j][e], pd, t.pinv);
+                double x = alpha * v;
+                if (t.beta != 0u) x += beta * (double)(*dst);
+                *dst = (uint32_t)mod_f64(x, pd, t.pinv);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(512) void prod_f64_pipe_kernel(ProdArgs args, int mode)
+{
+    if (mode == 2) {
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) f64_pipe_tile(args, b);
+        return;
+    }
+    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b < args.total_tiles) f64_pipe_tile(args, b);
+}
+
 // mode 0: one workgroup per tile; 1: same, XCD-aware order; 2: persistent
 // (workgroups stride over the tiles, which are ordered longest first).
 __global__ __launch_bounds__(256) void prod_f64_kernel(ProdArgs args, int mode)
@@ -266,6 +473,7 @@ int64_t f64_kblk(uint32_t p)
 }
 
 int g_f64_waves = 8;
+int g_f64_pipe = 1;
 
 template <int TILE>
 static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
@@ -294,16 +502,28 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
     const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
     int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
     const bool w8 = TILE == 128 && g_f64_waves == 8;
+    // the doubles-in-LDS variant: whole k in one exact block, 16-byte rows,
+    // 128-row panels addressable with 32-bit byte offsets
+    bool pipe = w8 && g_f64_pipe != 0;
+    for (int i = 0; i < ntasks && pipe; ++i) {
+        const ProdTask& t = tasks[i];
+        pipe = t.k <= t.kblk && (t.k & 3) == 0 && (t.A.ld & 3) == 0 && (t.B.ld & 3) == 0 &&
+               (((uintptr_t)t.A.p) & 15) == 0 && (((uintptr_t)t.B.p) & 15) == 0 && t.A.ld < (1 << 22) &&
+               t.B.ld < (1 << 22);
+    }
     const void* kern = TILE != 128 ? (const void*)prod_f64_kernel
-                                   : (w8 ? (const void*)prod_f64_lds_kernel<8> : (const void*)prod_f64_lds_kernel<4>);
+                       : pipe      ? (const void*)prod_f64_pipe_kernel
+                       : (w8 ? (const void*)prod_f64_lds_kernel<8> : (const void*)prod_f64_lds_kernel<4>);
     const int threads = w8 ? 512 : 256;
     if (mode == 2) {
         const int resident = resident_blocks(kern, threads);
         grid = total < resident ? total : resident;
     }
-    g_last_variant = TILE == 128 ? (w8 ? 8 : 1) : 0;
+    g_last_variant = TILE == 128 ? (pipe ? 11 : (w8 ? 8 : 1)) : 0;
     if (TILE != 128)
         hipLaunchKernelGGL(prod_f64_kernel, dim3(grid), dim3(256), 0, s, args, mode);
+    else if (pipe)
+        hipLaunchKernelGGL(prod_f64_pipe_kernel, dim3(grid), dim3(512), 0, s, args, mode);
     else if (w8)
         hipLaunchKernelGGL((prod_f64_lds_kernel<8>), dim3(grid), dim3(512), 0, s, args, mode);
     else

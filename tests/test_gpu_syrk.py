@@ -138,6 +138,33 @@ def test_f64_tile_variants(tile, n, k, depth):
         set_knob("f64_tile", 0)
 
 
+@pytest.mark.parametrize("pipe", [1, 0])
+@pytest.mark.parametrize("n,k,depth", [(300, 100, 0), (513, 64, 0), (256, 96, 0), (640, 640, 1),
+                                       (130, 1000, 0), (1100, 2052, 0), (300, 257, 0), (384, 32, 1)])
+def test_f64_pipe_variant(pipe, n, k, depth):
+    """128 x 128 FP64 tiles of 8 waves with the operands as doubles in LDS
+    (the default) or as centred int32: partial last k-stage, odd and even
+    stage counts, partial panels, general products at depth 1, a k that is
+    not a multiple of 4 (the int32 kernel runs) and k past the exact block
+    (likewise)."""
+    p = 131071
+    A = inputs.uniform(n + 3 * k + pipe, n, k, p)
+    set_knob("f64_tile", 128)
+    set_knob("f64_pipe", pipe)
+    try:
+        check_lower(gpu_syrk(A, p, depth=depth), oracle.syrk(A, p))
+        C0 = inputs.uniform(10, n, n, p)
+        check_lower(gpu_syrk(A, p, depth=depth, alpha=7, beta=p - 2, C0=C0),
+                    oracle.syrk_ab(A, p, 7, p - 2, C0))
+        set_kblk(64)       # exact blocks shorter than k: reductions inside the k-loop
+        check_lower(gpu_syrk(A, p, depth=depth, alpha=p - 1, beta=1, C0=C0),
+                    oracle.syrk_ab(A, p, p - 1, 1, C0))
+    finally:
+        set_kblk(0)
+        set_knob("f64_pipe", 1)
+        set_knob("f64_tile", 0)
+
+
 # ------------------------------------------------------------- int8 paths
 
 @pytest.mark.parametrize("tile", [128, 256])
