@@ -236,9 +236,10 @@ __device__ __forceinline__ void f64_lds_tile(const ProdArgs& args, int b)
 // k <= kblk (no reduction inside the k-loop), k a multiple of 4 and aligned
 // rows.  Matrix-core instructions do not run while the SIMD executes other
 // vector instructions, so this variant minimises them: every operand value
-// is centred and converted to double once per workgroup, when it is written
-// to LDS, instead of once per wave that reads it (four waves read each A
-// value, two each B value).  Two LDS buffers of 128 x 32 doubles per
+// is converted to double once per workgroup, when it is written to LDS,
+// instead of once per wave that reads it (four waves read each A value, two
+// each B value), and is not centred (residues in [0, p), so it needs
+// k (p - 1)^2 < 2^53 instead of k ((p - 1) / 2)^2 < 2^53).  Two LDS buffers of 128 x 32 doubles per
 // operand; two register sets hold the raw panels of the next two stages
 // (loaded through buffer resources with one 32-bit offset per load; chunks
 // past the end of k or of the rows return zero); stage t writes the panels
@@ -275,8 +276,10 @@ __device__ __forceinline__ void f64_bload(F64Raw& pf, __amdgpu_buffer_rsrc_t rs,
     }
 }
 
-// Centre, convert and write one stage's panel to LDS (row r, 4 doubles).
-__device__ __forceinline__ void f64_dstore(double* __restrict__ lds, const F64Raw& pf, uint32_t half, uint32_t p)
+// Convert and write one stage's panel to LDS (row r, 4 doubles).  The
+// residues stay in [0, p): one conversion per value, no centring; the
+// launcher only picks this kernel when k (p - 1)^2 stays below 2^53.
+__device__ __forceinline__ void f64_dstore(double* __restrict__ lds, const F64Raw& pf)
 {
 #pragma unroll
     for (int ps = 0; ps < 2; ++ps) {
@@ -284,10 +287,10 @@ __device__ __forceinline__ void f64_dstore(double* __restrict__ lds, const F64Ra
         const int r = idx >> 3, c = (idx & 7) * 4;
         const v4u v = pf.v[ps];
         v4d d;
-        d.x = (double)(int32_t)(v.x > half ? v.x - p : v.x);
-        d.y = (double)(int32_t)(v.y > half ? v.y - p : v.y);
-        d.z = (double)(int32_t)(v.z > half ? v.z - p : v.z);
-        d.w = (double)(int32_t)(v.w > half ? v.w - p : v.w);
+        d.x = (double)v.x;
+        d.y = (double)v.y;
+        d.z = (double)v.z;
+        d.w = (double)v.w;
         *reinterpret_cast<v4d*>(lds + r * PD + c) = d;
     }
 }
@@ -329,7 +332,6 @@ __device__ __forceinline__ void f64_pipe_tile(const ProdArgs& args, int b)
             f64_panel_rsrc((const uint32_t*)t.A.p + (int64_t)tile_r * t.A.ld, (int64_t)va * t.A.ld * 4);
         const __amdgpu_buffer_rsrc_t rb =
             f64_panel_rsrc((const uint32_t*)t.B.p + (int64_t)tile_c * t.B.ld, (int64_t)vb * t.B.ld * 4);
-        const uint32_t half = t.half, p = t.p;
 
         // fragments: lane (lr, lk) holds k = 4 lk .. 4 lk + 3 of its row in a k-group
         auto read_frags = [&](v4d (&xa)[WM2], v4d (&xb)[WN2], int buf, int kg) {
@@ -357,8 +359,8 @@ __device__ __forceinline__ void f64_pipe_tile(const ProdArgs& args, int b)
         f64_bload(b0, rb, ldb, 0, K);
         f64_bload(a1, ra, lda, BK2, K);
         f64_bload(b1, rb, ldb, BK2, K);
-        f64_dstore(sa[0], a0, half, p);
-        f64_dstore(sb[0], b0, half, p);
+        f64_dstore(sa[0], a0);
+        f64_dstore(sb[0], b0);
         __syncthreads();
         v4d fa[WM2], fb[WN2];
         read_frags(fa, fb, 0, 0);
@@ -376,16 +378,16 @@ __device__ __forceinline__ void f64_pipe_tile(const ProdArgs& args, int b)
             v4d na[WM2], nb[WN2];
             // k-group 0: stage kt + 1 to LDS, k-group 1's fragments read
             read_frags(na, nb, cur, 1);
-            f64_dstore(sa[cur ^ 1], wa, half, p);
-            f64_dstore(sb[cur ^ 1], wb, half, p);
+            f64_dstore(sa[cur ^ 1], wa);
+            f64_dstore(sb[cur ^ 1], wb);
             mfmas(fa, fb);
-            // per quarter: 3 reads, 2 MFMAs, 16 conversion instructions,
-            // 2 LDS writes, 6 MFMAs
+            // per quarter: 3 reads, 2 MFMAs, 4 conversions, 2 LDS writes,
+            // 6 MFMAs
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 __builtin_amdgcn_sched_group_barrier(0x100, NRD / 4, 0);
                 __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-                __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
                 __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
                 __builtin_amdgcn_sched_group_barrier(0x008, NMF / 4 - 2, 0);
             }
@@ -507,7 +509,9 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
     bool pipe = w8 && g_f64_pipe != 0;
     for (int i = 0; i < ntasks && pipe; ++i) {
         const ProdTask& t = tasks[i];
-        pipe = t.k <= t.kblk && (t.k & 3) == 0 && (t.A.ld & 3) == 0 && (t.B.ld & 3) == 0 &&
+        const double pm1 = (double)(t.p - 1);
+        pipe = t.k <= t.kblk && (double)t.k * pm1 * pm1 < 9007199254740992.0 - 2.0 * (double)t.p &&
+               (t.k & 3) == 0 && (t.A.ld & 3) == 0 && (t.B.ld & 3) == 0 &&
                (((uintptr_t)t.A.p) & 15) == 0 && (((uintptr_t)t.B.p) & 15) == 0 && t.A.ld < (1 << 22) &&
                t.B.ld < (1 << 22);
     }
