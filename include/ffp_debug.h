@@ -76,7 +76,10 @@ void ffp_debug_set_kblk(int64_t kblk);
  * converted once per workgroup, when k fits one exact block; 0: centred
  * int32 in LDS, converted by every wave that reads them),
  * "persistent" (1: grouped product launches run persistent workgroups that
- * stride over the tiles; 0: one workgroup per tile), "leveled" (1, the
+ * stride over the tiles; 0: one workgroup per tile), "merge_products" (1,
+ * the default: after the as-soon-as-possible levels are set, a product whose
+ * grouped launch would be small moves to a later level with a larger
+ * launch of its class when its dependents allow; 0: off), "leveled" (1, the
  * default: a call's block operations run level by level, independent
  * products of a level as one grouped launch; 0: one by one in schedule
  * order), "wide" (1, the default: Algorithm 2 keeps S1, S2 and P2 in

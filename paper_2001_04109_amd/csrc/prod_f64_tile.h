@@ -2,6 +2,8 @@
 // global memory (see prod_f64.hip); shared with the LDL^T step kernel, which
 // runs such tiles for its small products inside its per-level launch.
 #pragma once
+#include <type_traits>
+
 #include "prod_common.h"
 
 namespace ffp {
@@ -72,38 +74,51 @@ __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    Loaded la[WM], lb[WN];
-    int since_red = 0;
-    for (int kk = 0; kk < K; kk += 16) {
-        const int kc = kk + 4 * lk;
+    // When k (p - 1)^2 < 2^53 the residues enter the products as they are
+    // (one conversion per value; FP64 matrix instructions do not overlap
+    // other vector instructions, so the centring would cost matrix time);
+    // otherwise they are centred and the accumulators reduced every kblk.
+    const double pm1 = (double)(t.p - 1);
+    const bool raw = (double)K * pm1 * pm1 < 9007199254740992.0 - 2.0 * pd;
+    auto kloop = [&](auto rawc) {
+        constexpr bool RAW = decltype(rawc)::value;
+        Loaded la[WM], lb[WN];
+        int since_red = 0;
+        for (int kk = 0; kk < K; kk += 16) {
+            const int kc = kk + 4 * lk;
 #pragma unroll
-        for (int i = 0; i < WM; ++i) load4(Ab, t.A.ld, row0 + i * 16 + lr, t.m, kc, K, vec_ok, la[i]);
+            for (int i = 0; i < WM; ++i) load4(Ab, t.A.ld, row0 + i * 16 + lr, t.m, kc, K, vec_ok, la[i]);
 #pragma unroll
-        for (int j = 0; j < WN; ++j) load4(Bb, t.B.ld, col0 + j * 16 + lr, t.n, kc, K, vec_ok, lb[j]);
+            for (int j = 0; j < WN; ++j) load4(Bb, t.B.ld, col0 + j * 16 + lr, t.n, kc, K, vec_ok, lb[j]);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            double av[WM], bv[WN];
+            for (int s = 0; s < 4; ++s) {
+                double av[WM], bv[WN];
 #pragma unroll
-            for (int i = 0; i < WM; ++i) av[i] = centred(la[i].v[s], t.half, t.p);
+                for (int i = 0; i < WM; ++i) av[i] = RAW ? (double)la[i].v[s] : centred(la[i].v[s], t.half, t.p);
 #pragma unroll
-            for (int j = 0; j < WN; ++j) bv[j] = centred(lb[j].v[s], t.half, t.p);
+                for (int j = 0; j < WN; ++j) bv[j] = RAW ? (double)lb[j].v[s] : centred(lb[j].v[s], t.half, t.p);
 #pragma unroll
-            for (int i = 0; i < WM; ++i)
+                for (int i = 0; i < WM; ++i)
 #pragma unroll
-                for (int j = 0; j < WN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < WN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+            }
+            if constexpr (!RAW) {
+                since_red += 16;
+                if (since_red >= t.kblk && kk + 16 < K) {
+                    since_red = 0;
+#pragma unroll
+                    for (int i = 0; i < WM; ++i)
+#pragma unroll
+                        for (int j = 0; j < WN; ++j)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) acc[i][j][e] = mod_f64(acc[i][j][e], pd, t.pinv);
+                }
+            }
         }
-        since_red += 16;
-        if (since_red >= t.kblk && kk + 16 < K) {
-            since_red = 0;
-#pragma unroll
-            for (int i = 0; i < WM; ++i)
-#pragma unroll
-                for (int j = 0; j < WN; ++j)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[i][j][e] = mod_f64(acc[i][j][e], pd, t.pinv);
-        }
-    }
+    };
+    if (raw) kloop(std::integral_constant<bool, true>{});
+    else kloop(std::integral_constant<bool, false>{});
 
     // Epilogue.  16x16 f64 MFMA result layout: element e of lane l is row
     // 4*e + l/16, column l%16.

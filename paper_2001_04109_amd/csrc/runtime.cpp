@@ -519,6 +519,59 @@ int64_t rup256(int64_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
+// Products (GEMM, SYRK) of one representation class on one level form one
+// grouped launch.  After the as-soon-as-possible levels are set, a product
+// whose launch would be small (under kSmallLaunch output elements, about two
+// rounds of 128 x 128 tiles over the 256 CUs) moves to the later level, within
+// the range its dependents allow, that already holds the most product work of
+// its class: the leaves on blocks of A that are ready at once (the chains of
+// P1 and P2) join a large launch instead of running on a fraction of the
+// CUs.  Moving an operation later keeps every dependency satisfied as long as
+// no operation that depends on it runs at or before its new level.
+namespace {
+constexpr double kSmallLaunch = 512.0 * 128 * 128;
+
+bool is_product(const SchedItem& it) { return it.op->kind == OP_GEMM || it.op->kind == OP_SYRK; }
+
+double product_area(const SchedItem& it)
+{
+    const Op& o = *it.op;
+    return o.kind == OP_SYRK ? 0.5 * (double)o.m * (double)(o.m + 1) : (double)o.m * (double)o.n;
+}
+
+void merge_small_products(const std::vector<SchedItem>& items, const std::vector<OpRegions>& regs,
+                          std::vector<int>& level)
+{
+    const size_t n = items.size();
+    int maxlev = 0;
+    for (int lv : level) maxlev = lv > maxlev ? lv : maxlev;
+    std::vector<double> area((size_t)(maxlev + 1) * kNumCls, 0.0);
+    auto slot = [&](int lv, int cls) -> double& { return area[(size_t)lv * kNumCls + cls]; };
+    for (size_t i = 0; i < n; ++i)
+        if (is_product(items[i])) slot(level[i], items[i].op->cls) += product_area(items[i]);
+    std::vector<size_t> job_end(n);
+    for (size_t i = n; i-- > 0;) job_end[i] = (i + 1 < n && items[i + 1].job == items[i].job) ? job_end[i + 1] : i + 1;
+    for (size_t i = n; i-- > 0;) {
+        if (!is_product(items[i])) continue;
+        const int cls = items[i].op->cls, cur = level[i];
+        if (slot(cur, cls) >= kSmallLaunch) continue;
+        int alap = maxlev;
+        for (size_t j = i + 1; j < job_end[i]; ++j)
+            if (level[j] - 1 < alap && depends(regs[i], regs[j])) alap = level[j] - 1;
+        int best = cur;
+        for (int lv = cur + 1; lv <= alap; ++lv)
+            if (slot(lv, cls) > slot(best, cls)) best = lv;
+        if (best == cur || slot(best, cls) <= slot(cur, cls)) continue;
+        const double a = product_area(items[i]);
+        slot(cur, cls) -= a;
+        slot(best, cls) += a;
+        level[i] = best;
+    }
+}
+}  // namespace
+
+int g_merge_products = 1;
+
 std::vector<int> schedule_levels(const std::vector<SchedItem>& items)
 {
     const size_t n = items.size();
@@ -533,6 +586,7 @@ std::vector<int> schedule_levels(const std::vector<SchedItem>& items)
             if (level[i] + 1 > lv && depends(regs[i], regs[j])) lv = level[i] + 1;
         level[j] = lv;
     }
+    if (g_merge_products) merge_small_products(items, regs, level);
     return level;
 }
 

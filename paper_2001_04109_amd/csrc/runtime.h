@@ -98,6 +98,9 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s);
 std::vector<int> schedule_levels(const std::vector<SchedItem>& items);
 // 1: execute_plan runs the level scheduler (default); 0: ops in program order.
 extern int g_leveled;
+// 1 (default): products of small grouped launches move to a later level
+// with a larger launch of their class when their dependents allow.
+extern int g_merge_products;
 ProdTask make_task(const Plan& pl, const Op& o, const void* a, void* c, void* ws);
 PackDesc make_pack(const Plan& pl, const Op& o, const void* a, void* c, void* ws);
 
