@@ -76,7 +76,10 @@ void ffp_debug_set_kblk(int64_t kblk);
  * converted once per workgroup, when k fits one exact block; 0: centred
  * int32 in LDS, converted by every wave that reads them),
  * "persistent" (1: grouped product launches run persistent workgroups that
- * stride over the tiles; 0: one workgroup per tile), "merge_products" (1,
+ * stride over the tiles; 0: one workgroup per tile), "pack_vec" (1, the
+ * default: representation changes from uint32 residues convert 4 columns
+ * per thread, 16 x 256 per workgroup, when the destination keeps those
+ * stores aligned; 0: one element per thread), "merge_products" (1,
  * the default: after the as-soon-as-possible levels are set, a product whose
  * grouped launch would be small moves to a later level with a larger
  * launch of its class when its dependents allow; 0: off), "leveled" (1, the

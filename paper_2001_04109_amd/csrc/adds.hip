@@ -243,6 +243,98 @@ __global__ __launch_bounds__(256) void pack_grouped_kernel(Fp f, const PackDesc*
     st_res(DST, g, q.dst, i, j, r);
 }
 
+// Representation change from uint32 residues with 4 columns per thread: a
+// block converts 16 rows x 256 columns, each thread reading 4 consecutive
+// residues (one 16-byte load when the row allows it) and writing them with
+// one store per destination plane (4 bytes for int8 planes, 16 for uint32);
+// padding rows and columns get zero.  For the grouped form the block looks
+// up its descriptor once for 4096 elements.  The launcher checks that the
+// destination rows, planes and k_pad keep those stores aligned.
+constexpr int PV_ROWS = 16, PV_COLS = 256;
+
+template <int DST>
+__device__ __forceinline__ void pack_vec_store(const PackDesc& q, int64_t i, int64_t j, const uint32_t (&v)[4])
+{
+    const uint32_t p = q.p, half = (p - 1) / 2;
+    if constexpr (DST == CLS_F64) {
+        *reinterpret_cast<uint4*>((uint32_t*)q.dst.p + i * q.dst.ld + j) = make_uint4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (DST == CLS_I8) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int x = v[e] > half ? (int)v[e] - (int)p : (int)v[e];
+            w |= ((uint32_t)x & 255u) << (8 * e);
+        }
+        *reinterpret_cast<uint32_t*>((int8_t*)q.dst.p + i * q.dst.ld + j) = w;
+    } else if constexpr (DST == CLS_LIMB2) {
+        uint32_t wh = 0, wl = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int x = v[e] <= 32639u ? (int)v[e] : (int)v[e] - (int)p;
+            const int lo = ((x + 128) & 255) - 128;
+            const int hi = (x - lo) >> 8;
+            wh |= ((uint32_t)hi & 255u) << (8 * e);
+            wl |= ((uint32_t)lo & 255u) << (8 * e);
+        }
+        int8_t* b = (int8_t*)q.dst.p + i * q.dst.ld + j;
+        *reinterpret_cast<uint32_t*>(b) = wh;
+        *reinterpret_cast<uint32_t*>(b + q.dst.plane) = wl;
+    } else {
+        uint32_t w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int8_t l, m, h;
+            limb3_split(v[e] > half ? (int)v[e] - (int)p : (int)v[e], &l, &m, &h);
+            w0 |= ((uint32_t)(uint8_t)l) << (8 * e);
+            w1 |= ((uint32_t)(uint8_t)m) << (8 * e);
+            w2 |= ((uint32_t)(uint8_t)h) << (8 * e);
+        }
+        int8_t* b = (int8_t*)q.dst.p + i * q.dst.ld + j;
+        *reinterpret_cast<uint32_t*>(b) = w0;
+        *reinterpret_cast<uint32_t*>(b + q.dst.plane) = w1;
+        *reinterpret_cast<uint32_t*>(b + 2 * q.dst.plane) = w2;
+    }
+}
+
+template <int DST>
+__global__ __launch_bounds__(256) void pack_vec_kernel(const PackDesc* __restrict__ d, int nd, PackDesc one)
+{
+    const int b = blockIdx.x;
+    PackDesc q = one;
+    if (d != nullptr) {
+        int lo = 0, hi = nd - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
+        }
+        q = d[lo];
+    }
+    const int local = b - q.block0;
+    const int64_t bx = (q.k_pad + PV_COLS - 1) / PV_COLS;
+    const int64_t j = (local % bx) * PV_COLS + (threadIdx.x & 63) * 4;
+    const int64_t i0 = (local / bx) * PV_ROWS + (threadIdx.x >> 6);
+    if (j >= q.k_pad) return;
+    const uint32_t* __restrict__ src = (const uint32_t*)q.src.p;
+    const bool vec = (q.src.ld & 3) == 0 && (((uintptr_t)src) & 15) == 0 && j + 4 <= q.k;
+#pragma unroll
+    for (int rr = 0; rr < PV_ROWS / 4; ++rr) {
+        const int64_t i = i0 + 4 * rr;
+        if (i >= q.n_pad) break;
+        uint32_t v[4] = {0u, 0u, 0u, 0u};
+        if (i < q.n) {
+            const uint32_t* row = src + i * q.src.ld;
+            if (vec) {
+                const uint4 x = *reinterpret_cast<const uint4*>(row + j);
+                v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = j + e < q.k ? row[j + e] : 0u;
+            }
+        }
+        pack_vec_store<DST>(q, i, j, v);
+    }
+}
+
 __global__ __launch_bounds__(256) void copy_u32_kernel(int64_t rows, int64_t cols, const uint32_t* src,
                                                       int64_t lds, uint32_t* dst, int64_t ldd,
                                                       int lower_only)
@@ -366,10 +458,55 @@ hipError_t launch_mirror_lower(int64_t n, uint32_t* C, int64_t ldc, hipStream_t 
     return hipGetLastError();
 }
 
+namespace {
+// The 4-column stores of pack_vec_kernel stay aligned for this destination.
+bool pack_vec_ok(int src_cls, int dst_cls, const DView& dst, int64_t k_pad)
+{
+    if (src_cls != CLS_F64 || (k_pad & 3) != 0) return false;
+    if (dst_cls == CLS_F64) return (dst.ld & 3) == 0 && (((uintptr_t)dst.p) & 15) == 0;
+    return (dst.ld & 3) == 0 && (((uintptr_t)dst.p) & 3) == 0 && (dst_cls == CLS_I8 || (dst.plane & 3) == 0);
+}
+
+int64_t pack_vec_blocks(int64_t n_pad, int64_t k_pad)
+{
+    return ((n_pad + PV_ROWS - 1) / PV_ROWS) * ((k_pad + PV_COLS - 1) / PV_COLS);
+}
+
+hipError_t launch_pack_vec(int dst_cls, const PackDesc* dev, int nd, const PackDesc& one, int64_t blocks,
+                           hipStream_t s)
+{
+    switch (dst_cls) {
+    case CLS_F64: hipLaunchKernelGGL(pack_vec_kernel<CLS_F64>, dim3((unsigned)blocks), dim3(256), 0, s, dev, nd, one); break;
+    case CLS_I8: hipLaunchKernelGGL(pack_vec_kernel<CLS_I8>, dim3((unsigned)blocks), dim3(256), 0, s, dev, nd, one); break;
+    case CLS_LIMB2: hipLaunchKernelGGL(pack_vec_kernel<CLS_LIMB2>, dim3((unsigned)blocks), dim3(256), 0, s, dev, nd, one); break;
+    default: hipLaunchKernelGGL(pack_vec_kernel<CLS_LIMB3>, dim3((unsigned)blocks), dim3(256), 0, s, dev, nd, one); break;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+int g_pack_vec = 1;
+
 hipError_t launch_pack(const Fp& f, int src_cls, DView src, int64_t n, int64_t k, int dst_cls,
                        DView dst, int64_t n_pad, int64_t k_pad, hipStream_t s)
 {
     if (n_pad <= 0 || k_pad <= 0) return hipSuccess;
+    // a single small pack keeps one element per thread (more workgroups for
+    // the same latency)
+    const int64_t vb = pack_vec_blocks(n_pad, k_pad);
+    if (g_pack_vec && pack_vec_ok(src_cls, dst_cls, dst, k_pad) && vb >= 256 && vb < (1LL << 31)) {
+        PackDesc one{};
+        one.src = src;
+        one.dst = dst;
+        one.n = n;
+        one.k = k;
+        one.n_pad = n_pad;
+        one.k_pad = k_pad;
+        one.p = f.p;
+        one.pinv = f.pinv;
+        one.block0 = 0;
+        return launch_pack_vec(dst_cls, nullptr, 0, one, vb, s);
+    }
     dim3 g = grid2d(n_pad, k_pad);
 #define FFP_PACK(SC, DC)                                                                       \
     if (src_cls == SC && dst_cls == DC) {                                                      \
@@ -387,6 +524,22 @@ hipError_t launch_pack(const Fp& f, int src_cls, DView src, int64_t n, int64_t k
 hipError_t launch_pack_grouped(int src_cls, int dst_cls, PackDesc* descs, int nd,
                                PackDesc* dev_descs, hipStream_t s)
 {
+    bool vec = g_pack_vec != 0;
+    int64_t vtotal = 0;
+    for (int i = 0; i < nd && vec; ++i) {
+        vec = pack_vec_ok(src_cls, dst_cls, descs[i].dst, descs[i].k_pad);
+        vtotal += pack_vec_blocks(descs[i].n_pad, descs[i].k_pad);
+    }
+    if (vec && vtotal > 0 && vtotal < (1LL << 31)) {
+        int64_t b0 = 0;
+        for (int i = 0; i < nd; ++i) {
+            descs[i].block0 = (int32_t)b0;
+            b0 += pack_vec_blocks(descs[i].n_pad, descs[i].k_pad);
+        }
+        hipError_t e = hipMemcpyAsync(dev_descs, descs, sizeof(PackDesc) * nd, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return launch_pack_vec(dst_cls, dev_descs, nd, PackDesc{}, vtotal, s);
+    }
     int total = 0;
     for (int i = 0; i < nd; ++i) {
         descs[i].block0 = total;

@@ -204,6 +204,7 @@ int ffp_debug_set(const char* key, int64_t value)
         return FFP_OK;
     }
     if (strcmp(key, "i8_pipe") == 0) { ffp::g_i8_pipe = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "pack_vec") == 0) { ffp::g_pack_vec = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "f64_pipe") == 0) { ffp::g_f64_pipe = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "ldlt_fold") == 0) { ffp::g_ldlt_fold = value ? 1 : 0; return FFP_OK; }

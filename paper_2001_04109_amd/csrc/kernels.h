@@ -156,6 +156,9 @@ struct PackDesc {
     double pinv;
     int32_t block0;
 };
+// 1 (default): representation changes from uint32 run 4 columns per thread
+// when the destination allows aligned 4-column stores; 0: one per thread.
+extern int g_pack_vec;
 hipError_t launch_pack_grouped(int src_cls, int dst_cls, PackDesc* descs, int nd,
                                PackDesc* dev_descs, hipStream_t s);
 // Copy the lower triangle (or all, if full) of an n x n uint32 block.

@@ -165,6 +165,31 @@ def test_f64_pipe_variant(pipe, n, k, depth):
         set_knob("f64_tile", 0)
 
 
+@pytest.mark.parametrize("vec", [1, 0])
+@pytest.mark.parametrize("p,limb3,depth", [(251, False, 0), (65521, False, 0), (131071, True, 0),
+                                           (251, False, 1), (65537, False, 2)])
+@pytest.mark.parametrize("n,k,pad", [(37, 70, 0), (300, 257, 3), (130, 1000, 1), (256, 512, 0),
+                                     (1040, 1030, 1), (1030, 1024, 0)])
+def test_pack_paths(vec, p, limb3, depth, n, k, pad):
+    """Representation changes from uint32 (int8, two and three limbs, FP64
+    padding): 4 columns per thread or one (single packs of at least 256
+    workgroups of 16 x 256 take the former), with aligned and unaligned
+    source rows (lda = k + pad) and ragged n and k."""
+    import torch
+    A = inputs.uniform(n * 7 + k + pad, n, k, p)
+    full = np.zeros((n, k + pad), dtype=np.uint32)
+    full[:, :k] = A
+    Ad = to_dev_u32(full)[:, :k]
+    C = torch.zeros((n, n), dtype=torch.int32, device="cuda")
+    set_knob("pack_vec", vec)
+    try:
+        ffp.syrk(Ad, p, C=C, depth=depth, limb3=limb3)
+        torch.cuda.synchronize()
+        check_lower(from_dev_u32(C), oracle.syrk(A, p))
+    finally:
+        set_knob("pack_vec", 1)
+
+
 # ------------------------------------------------------------- int8 paths
 
 @pytest.mark.parametrize("tile", [128, 256])
