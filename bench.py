@@ -562,7 +562,9 @@ def main():
             if other == name:
                 continue
             log(f"bench: extra {other}")
-            r2 = run_workload(other, max(3, args.steps // 3), 1)
+            # short kernels: enough steps that the clock has settled (the first
+            # launches after the host-side setup run slower)
+            r2 = run_workload(other, max(10, args.steps), 3)
             a2 = r2["kernel_flops"] / (r2["kernel_ms"] * 1e-3) / 1e12 if r2.get("kernel_ms") else 0.0
             extra[other] = {"gops": round(r2["gops"], 1), "ms_per_step": round(r2["ms_per_step"], 4),
                             "frac_int8_peak_effective": round(r2["gops"] / 1e3 / PEAK_I8, 4),
