@@ -420,6 +420,10 @@ def served(nreq, rate=2000.0, budget=96 << 30, nstreams=4, max_inflight=1024, sa
             "gops_total": round((syrk_ops + ldlt_ops) / span / 1e9, 1),
             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "p50_p99_ms_by_kind": {
+                kind: [round(float(np.percentile(lat[sel], q)) * 1e3, 3) for q in (50, 99)]
+                for kind in ("syrk", "ldlt")
+                for sel in [np.array([r["kind"] == kind for r in reqs])] if sel.any()},
             "units": stats.units, "max_batch": stats.max_batch,
             "overlapped_units": stats.overlapped_units, "peak_inflight": stats.peak_inflight,
             "peak_bytes": stats.peak_bytes,
