@@ -246,8 +246,9 @@ const char* ffp_debug_variant_name(int variant)
     case 7: return "void ffp::prod_i8_ring_kernel<256, 256, 5>(ffp::ProdArgs, int)";
     case 8: return "void ffp::prod_f64_lds_kernel<8>(ffp::ProdArgs, int)";
     case 9: return "void ffp::prod_i8_kernel<64, 64, 64, 3>(ffp::ProdArgs, int)";
-    case 10: return "void ffp::prod_i8_pipe_kernel<256, 256, 128>(ffp::ProdArgs, int)";
+    case 10: return "void ffp::prod_i8_pipe_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";
     case 11: return "ffp::prod_f64_pipe_kernel(ffp::ProdArgs, int)";
+    case 12: return "void ffp::prod_i8_pipe_kernel<128, 128, 128, 2>(ffp::ProdArgs, int)";
     default: return "";
     }
 }

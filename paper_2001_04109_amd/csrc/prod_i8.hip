@@ -288,77 +288,109 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const int8_t* p, in
     return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nb, 0x00020000);
 }
 
-template <int BM, int BN, int BK, bool EDGE>
+// PLANES = 1: centred int8 (one accumulator); 2: two int8 limbs (hh, ll and
+// hl + lh accumulators, as in i8_tile_task).
+template <int BM, int BN, int BK, int PLANES, bool EDGE>
 __device__ __forceinline__ void i8_pipe_body(const ProdTask& t, int ti, int tj, int8_t* smem)
 {
     constexpr int PITCH = BK + 16;
     constexpr int WTM = BM / 2, WTN = BN / 2;
     constexpr int FM = WTM / 32, FN = WTN / 32;
     constexpr int KS = BK / 32;
+    constexpr int NACC = PLANES == 1 ? 1 : 3;
     static_assert(KS == 4, "four k-steps per stage");
-    auto sa = reinterpret_cast<int8_t(*)[BM * PITCH]>(smem);
-    auto sb = reinterpret_cast<int8_t(*)[BN * PITCH]>(smem + 2 * BM * PITCH);
+    static_assert(PLANES == 1 || PLANES == 2, "one plane or two limbs");
+    auto sa = reinterpret_cast<int8_t(*)[PLANES][BM * PITCH]>(smem);
+    auto sb = reinterpret_cast<int8_t(*)[PLANES][BN * PITCH]>(smem + 2 * PLANES * BM * PITCH);
     const int tile_r = ti * BM, tile_c = tj * BN;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wr = wave >> 1, wc = wave & 1;
     const int lrow = lane & 31, lk = lane >> 5;
 
-    v16i acc[FM][FN];
+    v16i acc[NACC][FM][FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int q = 0; q < NACC; ++q)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0;
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[q][i][j][e] = 0;
     const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
 
     const int nk = t.k / BK;
     if (nk > 0) {
-        auto read_frags = [&](v4i (&xa)[FM], v4i (&xb)[FN], int buf, int ks) {
+        auto read_frags = [&](v4i (&xa)[PLANES][FM], v4i (&xb)[PLANES][FN], int buf, int ks) {
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
-                xa[i] = *reinterpret_cast<const v4i*>(&sa[buf][(wr * WTM + i * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
+            for (int pl = 0; pl < PLANES; ++pl) {
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-                xb[j] = *reinterpret_cast<const v4i*>(&sb[buf][(wc * WTN + j * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
-        };
-        auto mfmas = [&](const v4i (&xa)[FM], const v4i (&xb)[FN]) {
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i)
+                    xa[pl][i] = *reinterpret_cast<const v4i*>(
+                        &sa[buf][pl][(wr * WTM + i * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[i], xb[j], acc[i][j], 0, 0, 0);
+                    xb[pl][j] = *reinterpret_cast<const v4i*>(
+                        &sb[buf][pl][(wc * WTN + j * 32 + lrow) * PITCH + ks * 32 + lk * 16]);
+            }
         };
-        constexpr int NREAD = FM + FN, NMFMA = FM * FN;
-        constexpr int WA = Prefetch<BM, BK>::PASSES, WB = Prefetch<BN, BK>::PASSES;
+        auto mfmas = [&](const v4i (&xa)[PLANES][FM], const v4i (&xb)[PLANES][FN]) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    if constexpr (PLANES == 1) {
+                        acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][i], xb[0][j], acc[0][i][j], 0, 0, 0);
+                    } else {
+                        acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][i], xb[0][j], acc[0][i][j], 0, 0, 0);
+                        acc[1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[1][i], xb[1][j], acc[1][i][j], 0, 0, 0);
+                        acc[2][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][i], xb[1][j], acc[2][i][j], 0, 0, 0);
+                        acc[2][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[1][i], xb[0][j], acc[2][i][j], 0, 0, 0);
+                    }
+                }
+        };
+        constexpr int NREAD = PLANES * (FM + FN), NMFMA = FM * FN * PLANES * PLANES;
+        constexpr int WA = PLANES * Prefetch<BM, BK>::PASSES, WB = PLANES * Prefetch<BN, BK>::PASSES;
         const int va = t.m - tile_r < BM ? t.m - tile_r : BM;    // valid rows of the panels
         const int vb = t.n - tile_c < BN ? t.n - tile_c : BN;
         const int lda = __builtin_amdgcn_readfirstlane((int)t.A.ld);
         const int ldb = __builtin_amdgcn_readfirstlane((int)t.B.ld);
-        const __amdgpu_buffer_rsrc_t ra =
-            panel_rsrc((const int8_t*)t.A.p + (int64_t)tile_r * t.A.ld, (int64_t)va * t.A.ld);
-        const __amdgpu_buffer_rsrc_t rb =
-            panel_rsrc((const int8_t*)t.B.p + (int64_t)tile_c * t.B.ld, (int64_t)vb * t.B.ld);
-        Prefetch<BM, BK> pa0, pa1;
-        Prefetch<BN, BK> pb;
-        bload<BM, BK, EDGE>(pa0, ra, lda, 0, true);
-        bload<BN, BK, EDGE>(pb, rb, ldb, 0, true);
-        bload<BM, BK, EDGE>(pa1, ra, lda, BK, nk > 1);
-        lstore<BM, BK>(sa[0], pa0);
-        lstore<BN, BK>(sb[0], pb);
-        bload<BN, BK, EDGE>(pb, rb, ldb, BK, nk > 1);
+        __amdgpu_buffer_rsrc_t ra[PLANES], rb[PLANES];
+#pragma unroll
+        for (int pl = 0; pl < PLANES; ++pl) {
+            ra[pl] = panel_rsrc((const int8_t*)t.A.p + pl * t.A.plane + (int64_t)tile_r * t.A.ld, (int64_t)va * t.A.ld);
+            rb[pl] = panel_rsrc((const int8_t*)t.B.p + pl * t.B.plane + (int64_t)tile_c * t.B.ld, (int64_t)vb * t.B.ld);
+        }
+        auto load_a = [&](Prefetch<BM, BK> (&x)[PLANES], int k0, bool live) {
+#pragma unroll
+            for (int pl = 0; pl < PLANES; ++pl) bload<BM, BK, EDGE>(x[pl], ra[pl], lda, k0, live);
+        };
+        auto load_b = [&](Prefetch<BN, BK> (&x)[PLANES], int k0, bool live) {
+#pragma unroll
+            for (int pl = 0; pl < PLANES; ++pl) bload<BN, BK, EDGE>(x[pl], rb[pl], ldb, k0, live);
+        };
+        Prefetch<BM, BK> pa0[PLANES], pa1[PLANES];
+        Prefetch<BN, BK> pb[PLANES];
+        load_a(pa0, 0, true);
+        load_b(pb, 0, true);
+        load_a(pa1, BK, nk > 1);
+#pragma unroll
+        for (int pl = 0; pl < PLANES; ++pl) {
+            lstore<BM, BK>(sa[0][pl], pa0[pl]);
+            lstore<BN, BK>(sb[0][pl], pb[pl]);
+        }
+        load_b(pb, BK, nk > 1);
         __syncthreads();
-        v4i fa[FM], fb[FN];
+        v4i fa[PLANES][FM], fb[PLANES][FN];
         read_frags(fa, fb, 0, 0);
 
         auto stage = [&](auto par, int kt) {
             constexpr int cur = decltype(par)::value;
-            Prefetch<BM, BK>& la = cur ? pa1 : pa0;   // reloaded now (its stage is in LDS)
-            Prefetch<BM, BK>& wa = cur ? pa0 : pa1;   // stage kt + 1, written now
+            Prefetch<BM, BK> (&la)[PLANES] = cur ? pa1 : pa0;   // reloaded now (its stage is in LDS)
+            Prefetch<BM, BK> (&wa)[PLANES] = cur ? pa0 : pa1;   // stage kt + 1, written now
             __builtin_amdgcn_sched_barrier(0);
-            bload<BM, BK, EDGE>(la, ra, lda, (kt + 2) * BK, kt + 2 < nk);
+            load_a(la, (kt + 2) * BK, kt + 2 < nk);
             __builtin_amdgcn_sched_barrier(0);
-            v4i na[FM], nb[FN];
+            v4i na[PLANES][FM], nb[PLANES][FN];
             // k-step 0
             read_frags(na, nb, cur, 1);
             mfmas(fa, fb);
@@ -371,7 +403,8 @@ __device__ __forceinline__ void i8_pipe_body(const ProdTask& t, int ti, int tj, 
             // k-step 1, A panel of stage kt + 1 to LDS
             read_frags(fa, fb, cur, 2);
             mfmas(na, nb);
-            lstore<BM, BK>(sa[cur ^ 1], wa);
+#pragma unroll
+            for (int pl = 0; pl < PLANES; ++pl) lstore<BM, BK>(sa[cur ^ 1][pl], wa[pl]);
 #pragma unroll
             for (int q = 0; q < NREAD; ++q) {
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
@@ -384,7 +417,8 @@ __device__ __forceinline__ void i8_pipe_body(const ProdTask& t, int ti, int tj, 
             // stage kt + 2's B panel into the same registers
             read_frags(na, nb, cur, 3);
             mfmas(fa, fb);
-            lstore<BN, BK>(sb[cur ^ 1], pb);
+#pragma unroll
+            for (int pl = 0; pl < PLANES; ++pl) lstore<BN, BK>(sb[cur ^ 1][pl], pb[pl]);
 #pragma unroll
             for (int q = 0; q < NREAD; ++q) {
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
@@ -393,7 +427,7 @@ __device__ __forceinline__ void i8_pipe_body(const ProdTask& t, int ti, int tj, 
                 __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WB), 0);
             }
             __builtin_amdgcn_sched_barrier(0);
-            bload<BN, BK, EDGE>(pb, rb, ldb, (kt + 2) * BK, kt + 2 < nk);
+            load_b(pb, (kt + 2) * BK, kt + 2 < nk);
             __syncthreads();
             // k-step 3 with the first fragments of stage kt + 1
             read_frags(fa, fb, cur ^ 1, 0);
@@ -413,32 +447,59 @@ __device__ __forceinline__ void i8_pipe_body(const ProdTask& t, int ti, int tj, 
             stage(std::integral_constant<int, 1>{}, kt + 1);
         }
     }
-    store_tile_i8_reg<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+    if constexpr (PLANES == 1) {
+        store_tile_i8_reg<WTM, WTN, FM, FN>(acc[0], t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+    } else {
+        if (!wave_live) return;
+        const double pd = (double)t.p;
+        const double alpha = (double)t.alpha, beta = (double)t.beta;
+        const double r16 = (double)((65536u) % t.p), r8 = (double)(256u % t.p);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = tile_c + wc * WTN + j * 32 + lrow;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int row = tile_r + wr * WTM + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
+                    if (row >= t.m || col >= t.n) continue;
+                    if (t.syrk && col > row) continue;
+                    const double hh = mod_f64((double)acc[0][i][j][e], pd, t.pinv);
+                    const double ll = mod_f64((double)acc[1][i][j][e], pd, t.pinv);
+                    const double xx = mod_f64((double)acc[2][i][j][e], pd, t.pinv);
+                    const double v = mod_f64(hh * r16 + xx * r8 + ll, pd, t.pinv);
+                    uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                    double x = alpha * v;
+                    if (t.beta != 0u) x += beta * (double)(*dst);
+                    *dst = (uint32_t)mod_f64(x, pd, t.pinv);
+                }
+            }
+    }
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int PLANES>
 __device__ __forceinline__ void i8_pipe_tile(const ProdArgs& args, int b)
 {
-    __shared__ __attribute__((aligned(16))) int8_t smem[I8Tile<BM, BN, BK, 1>::LDS];
+    __shared__ __attribute__((aligned(16))) int8_t smem[I8Tile<BM, BN, BK, PLANES>::LDS];
     ProdTask t;
     select_task(args, b, &t);
     const int r = b - t.tile0;
     int ti, tj;
     if (t.syrk) band_tri(r, t.tm, &ti, &tj);
     else band_rect(r, t.tm, t.tn, &ti, &tj);
-    if ((ti + 1) * BM <= t.m && (tj + 1) * BN <= t.n) i8_pipe_body<BM, BN, BK, false>(t, ti, tj, smem);
-    else i8_pipe_body<BM, BN, BK, true>(t, ti, tj, smem);
+    if ((ti + 1) * BM <= t.m && (tj + 1) * BN <= t.n) i8_pipe_body<BM, BN, BK, PLANES, false>(t, ti, tj, smem);
+    else i8_pipe_body<BM, BN, BK, PLANES, true>(t, ti, tj, smem);
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int PLANES>
 __global__ __launch_bounds__(256) void prod_i8_pipe_kernel(ProdArgs args, int mode)
 {
     if (mode == 2) {
-        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) i8_pipe_tile<BM, BN, BK>(args, b);
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) i8_pipe_tile<BM, BN, BK, PLANES>(args, b);
         return;
     }
     const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (b < args.total_tiles) i8_pipe_tile<BM, BN, BK>(args, b);
+    if (b < args.total_tiles) i8_pipe_tile<BM, BN, BK, PLANES>(args, b);
 }
 
 // mode 0: one workgroup per tile; 1: same, XCD-aware order; 2: persistent.
@@ -490,13 +551,13 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         g_last_variant = 6 + (RING - 4);
         hipLaunchKernelGGL((prod_i8_ring_kernel<BM, BN, RING>), dim3(grid), dim3(256), 0, s, args, mode);
     } else if constexpr (RING < 0) {
-        static_assert(PLANES == 1 && BK == 128, "pipelined variant: CLS_I8, 128-byte stages");
+        static_assert(PLANES <= 2 && BK == 128, "pipelined variant: int8 or two limbs, 128-byte stages");
         if (mode == 2) {
-            const int resident = resident_blocks((const void*)prod_i8_pipe_kernel<BM, BN, BK>);
+            const int resident = resident_blocks((const void*)prod_i8_pipe_kernel<BM, BN, BK, PLANES>);
             grid = total < resident ? total : resident;
         }
-        g_last_variant = 10;
-        hipLaunchKernelGGL((prod_i8_pipe_kernel<BM, BN, BK>), dim3(grid), dim3(256), 0, s, args, mode);
+        g_last_variant = PLANES == 1 ? 10 : 12;
+        hipLaunchKernelGGL((prod_i8_pipe_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
     } else {
         if (mode == 2) {
             const int resident = resident_blocks((const void*)prod_i8_kernel<BM, BN, BK, PLANES>);
@@ -524,9 +585,12 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
             return hipErrorInvalidValue;
         const int64_t half = (t.p - 1) / 2;
         const int64_t per_k = PLANES == 1 ? half * half : (PLANES == 2 ? 2 * 128 * 128 : 3 * 128 * 128);
+        // the kernels run whole stages of BK bytes: the k-blocks (and so the k
+        // of every chunk launch) are multiples of BK
+        constexpr int KU = BK > KSTEP ? BK : KSTEP;
         int64_t kb = (2147483647LL - (int64_t)t.p) / (per_k > 0 ? per_k : 1);
-        kb -= kb % KSTEP;
-        t.kblk = cap_kblk(kb > (1 << 30) ? (1 << 30) : kb, KSTEP);
+        kb -= kb % KU;
+        t.kblk = cap_kblk(kb > (1 << 30) ? (1 << 30) : kb, KU);
         kblk = t.kblk < kblk ? t.kblk : kblk;
         maxk = t.k > maxk ? t.k : maxk;
     }
@@ -613,6 +677,10 @@ hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_bu
 hipError_t launch_products_limb2(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
                                  hipStream_t s)
 {
+    bool pipe = g_i8_pipe != 0;
+    for (int i = 0; i < ntasks && pipe; ++i)
+        pipe = (tasks[i].k % 128) == 0 && tasks[i].A.ld < (1 << 23) && tasks[i].B.ld < (1 << 23);
+    if (pipe) return launch_i8_impl<128, 128, 128, 2, -1>(tasks, ntasks, dev_task_buf, s);
     return launch_i8_impl<128, 128, 64, 2>(tasks, ntasks, dev_task_buf, s);
 }
 

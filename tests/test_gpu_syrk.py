@@ -165,6 +165,33 @@ def test_f64_pipe_variant(pipe, n, k, depth):
         set_knob("f64_tile", 0)
 
 
+@pytest.mark.parametrize("pipe", [1, 0])
+@pytest.mark.parametrize("n,k,dtype", [(300, 256, "limb2"), (513, 128, "u32"), (256, 384, "limb2"),
+                                       (1000, 640, "u32"), (130, 1000, "u32"), (700, 2048, "limb2")])
+def test_limb2_pipe_variant(pipe, n, k, dtype):
+    """Two int8 limbs on 128 x 128 tiles with 128-byte k stages, LDS writes
+    between the MFMAs (the default) or 64-byte stages: limb operands given
+    or packed from uint32, one, two and odd stage counts, partial panels,
+    alpha/beta, entries at the ends of the range, k in chunks."""
+    p = 65521
+    A = inputs.uniform(n + 5 * k, n, k, p)
+    A[:3] = p - 1
+    A[3:5] = (p - 1) // 2
+    a_dtype = ffp.FFP_I8_LIMB2 if dtype == "limb2" else ffp.FFP_U32
+    set_knob("i8_pipe", pipe)
+    try:
+        check_lower(gpu_syrk(A, p, depth=0, a_dtype=a_dtype), oracle.syrk(A, p))
+        C0 = inputs.uniform(11, n, n, p)
+        check_lower(gpu_syrk(A, p, depth=0, alpha=p - 1, beta=1, C0=C0, a_dtype=a_dtype),
+                    oracle.syrk_ab(A, p, p - 1, 1, C0))
+        set_kblk(192)      # chunks of whole 128-byte stages
+        check_lower(gpu_syrk(A, p, depth=0, alpha=3, beta=5, C0=C0, a_dtype=a_dtype),
+                    oracle.syrk_ab(A, p, 3, 5, C0))
+    finally:
+        set_kblk(0)
+        set_knob("i8_pipe", 1)
+
+
 @pytest.mark.parametrize("vec", [1, 0])
 @pytest.mark.parametrize("p,limb3,depth", [(251, False, 0), (65521, False, 0), (131071, True, 0),
                                            (251, False, 1), (65537, False, 2)])
@@ -249,6 +276,10 @@ def test_i8_pipe_variant(pipe, n, k):
             set_kblk(256)      # k in chunks of two stages, accumulated through C
             check_lower(gpu_syrk(A, p, depth=0, alpha=p - 1, beta=1, C0=C0),
                         oracle.syrk_ab(A, p, p - 1, 1, C0))
+        # a block length that is a multiple of 64 but not of 128: the chunks
+        # of the 128-byte-stage kernel stay whole stages
+        set_kblk(192)
+        check_lower(gpu_syrk(A, p, depth=0, alpha=2, beta=3, C0=C0), oracle.syrk_ab(A, p, 2, 3, C0))
     finally:
         set_kblk(0)
         set_knob("i8_pipe", 1)
