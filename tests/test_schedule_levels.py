@@ -6,7 +6,8 @@ level in reverse program order: a dependency the scheduler missed (a read of
 memory an earlier operation of the same level writes, or a write over
 memory it still reads) shows as a result different from the oracle's,
 since the workspace starts as garbage.  Covers the placements of Tables 3
-and 4 and the wide variant, whose independent products share levels.
+and 4 and the wide variant, whose independent products share levels, with
+and without the pass that moves the products of small launches later.
 """
 import numpy as np
 import pytest
@@ -22,6 +23,15 @@ def wide(request):
     ffp.set_knob("wide", request.param)
     yield request.param
     ffp.set_knob("wide", 1)
+
+
+@pytest.fixture(autouse=True, params=[1, 0], ids=["merged", "asap"])
+def merge_products(request):
+    """With and without moving the products of small launches to later
+    levels (both schedules must keep every dependency)."""
+    ffp.set_knob("merge_products", request.param)
+    yield request.param
+    ffp.set_knob("merge_products", 1)
 
 
 def check_reordered(n, k, p, depth, alpha=1, beta=0, a_dtype=ffp.FFP_U32, seed=0):
@@ -77,3 +87,22 @@ def test_wide_products_share_levels():
     assert sum(per_level.values()) == 53
     assert max(per_level.values()) >= 6
     assert len(per_level) <= 20
+
+
+def test_small_launch_products_move_later():
+    """8192 x 32768 at depth 3: the eight leaves on blocks of A (the chains
+    of P1 and P2) are ready at level 0, where they alone would form a launch
+    of 288 tiles of 128 x 128; they join the large launch of a later level."""
+    n, k, p = 8192, 32768, 131071
+    text = ffp.plan_describe(n, k, p, flags=ffp.FFP_DEPTH(3))
+    kinds = [int(line.split()[1]) for line in text.splitlines()[1:]]
+    prods = [i for i, kd in enumerate(kinds) if kd in (2, 3)]
+    ffp.set_knob("merge_products", 0)
+    asap = ffp.plan_levels(n, k, p, flags=ffp.FFP_DEPTH(3))
+    ffp.set_knob("merge_products", 1)
+    merged = ffp.plan_levels(n, k, p, flags=ffp.FFP_DEPTH(3))
+    assert sum(asap[i] == 0 for i in prods) == 8
+    assert sum(merged[i] == 0 for i in prods) == 0
+    assert all(merged[i] >= asap[i] for i in prods)
+    assert all(merged[i] == asap[i] for i in range(len(kinds)) if i not in prods)
+    assert len(set(merged[i] for i in prods)) < len(set(asap[i] for i in prods))
