@@ -76,7 +76,12 @@ void ffp_debug_set_kblk(int64_t kblk);
  * converted once per workgroup, when k fits one exact block; 0: centred
  * int32 in LDS, converted by every wave that reads them),
  * "persistent" (1: grouped product launches run persistent workgroups that
- * stride over the tiles; 0: one workgroup per tile), "pack_vec" (1, the
+ * stride over the tiles; 0: one workgroup per tile), "winograd_min" (n:
+ * general products P3, P4 of the FP64 class with wide placements, beta = 0
+ * and m, n, k >= n run one level of Strassen-Winograd, Algorithm 1, with its
+ * additions as separate operations; 0, the default: never), "merge_tiles"
+ * (size in 128 x 128 tiles under which a level's product launch counts as
+ * small for "merge_products"; 512 by default), "pack_vec" (1, the
  * default: representation changes from uint32 residues convert 4 columns
  * per thread, 16 x 256 per workgroup, when the destination keeps those
  * stores aligned; 0: one element per thread), "merge_products" (1,

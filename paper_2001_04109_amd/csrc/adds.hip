@@ -335,6 +335,41 @@ __global__ __launch_bounds__(256) void pack_vec_kernel(const PackDesc* __restric
     }
 }
 
+// Linear combination out = sum of +-in[i] mod p of uint32 residue blocks
+// (the additions of Strassen-Winograd): 4 columns per thread when every row
+// start is 16-byte aligned, else one.  Each term is added or subtracted
+// with one conditional correction, so the result stays in [0, p).
+struct LinIn { const uint32_t* p[5]; int64_t ld[5]; };
+
+template <int VEC>
+__global__ __launch_bounds__(256) void lincomb_kernel(uint32_t p, int64_t m, int64_t k, int nin, LinIn in,
+                                                     unsigned neg, uint32_t* __restrict__ out, int64_t ldo)
+{
+    const int64_t j = ((int64_t)blockIdx.x * 64 + (threadIdx.x & 63)) * VEC;
+    if (j >= k) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < m; i += (int64_t)gridDim.y * 4) {
+        uint32_t acc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] = 0u;
+        for (int t = 0; t < nin; ++t) {
+            uint32_t v[VEC];
+            const uint32_t* row = in.p[t] + i * in.ld[t] + j;
+            if constexpr (VEC == 4) {
+                const uint4 x = *reinterpret_cast<const uint4*>(row);
+                v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+            } else {
+                v[0] = row[0];
+            }
+            const bool sub = (neg >> t) & 1u;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] = sub ? sub_m(acc[e], v[e], p) : add_m(acc[e], v[e], p);
+        }
+        uint32_t* o = out + i * ldo + j;
+        if constexpr (VEC == 4) *reinterpret_cast<uint4*>(o) = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+        else o[0] = acc[0];
+    }
+}
+
 __global__ __launch_bounds__(256) void copy_u32_kernel(int64_t rows, int64_t cols, const uint32_t* src,
                                                       int64_t lds, uint32_t* dst, int64_t ldd,
                                                       int lower_only)
@@ -559,6 +594,28 @@ hipError_t launch_pack_grouped(int src_cls, int dst_cls, PackDesc* descs, int nd
     FFP_PACKG(CLS_I8, CLS_I8) FFP_PACKG(CLS_LIMB2, CLS_LIMB2) FFP_PACKG(CLS_F64, CLS_LIMB3)
 #undef FFP_PACKG
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_lincomb(const Fp& f, int64_t m, int64_t k, int nin, const DView* in, unsigned neg, DView out,
+                          hipStream_t s)
+{
+    if (m <= 0 || k <= 0) return hipSuccess;
+    if (nin < 1 || nin > 5) return hipErrorInvalidValue;
+    LinIn li{};
+    bool vec = (k & 3) == 0 && (out.ld & 3) == 0 && (((uintptr_t)out.p) & 15) == 0;
+    for (int t = 0; t < nin; ++t) {
+        li.p[t] = (const uint32_t*)in[t].p;
+        li.ld[t] = in[t].ld;
+        vec = vec && (in[t].ld & 3) == 0 && (((uintptr_t)in[t].p) & 15) == 0;
+    }
+    if (vec) {
+        hipLaunchKernelGGL(lincomb_kernel<4>, grid2d(m, k / 4), dim3(256), 0, s, f.p, m, k, nin, li, neg,
+                           (uint32_t*)out.p, out.ld);
+    } else {
+        hipLaunchKernelGGL(lincomb_kernel<1>, grid2d(m, k), dim3(256), 0, s, f.p, m, k, nin, li, neg,
+                           (uint32_t*)out.p, out.ld);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_copy_u32(int64_t rows, int64_t cols, const uint32_t* src, int64_t lds,

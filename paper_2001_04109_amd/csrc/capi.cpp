@@ -196,8 +196,18 @@ int ffp_debug_set(const char* key, int64_t value)
     if (strcmp(key, "i8_tile") == 0) { ffp::g_i8_tile_override = (int)value; return FFP_OK; }
     if (strcmp(key, "i8_bk") == 0) { ffp::g_i8_bk_override = (int)value; return FFP_OK; }
     if (strcmp(key, "wide") == 0) { ffp::g_wide_schedule = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "winograd_min") == 0) {
+        if (value < 0) return FFP_EINVAL;
+        ffp::g_winograd_min = value;
+        return FFP_OK;
+    }
     if (strcmp(key, "leveled") == 0) { ffp::g_leveled = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "merge_products") == 0) { ffp::g_merge_products = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "merge_tiles") == 0) {
+        if (value < 0 || value > (1 << 24)) return FFP_EINVAL;
+        ffp::g_merge_tiles = (int)value;
+        return FFP_OK;
+    }
     if (strcmp(key, "i8_ring") == 0) {
         if (value != 0 && value != 4 && value != 5) return FFP_EINVAL;
         ffp::g_i8_ring = (int)value;

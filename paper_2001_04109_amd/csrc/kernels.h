@@ -161,6 +161,10 @@ struct PackDesc {
 extern int g_pack_vec;
 hipError_t launch_pack_grouped(int src_cls, int dst_cls, PackDesc* descs, int nd,
                                PackDesc* dev_descs, hipStream_t s);
+// out <- sum of +-in[i] (i < nin <= 5; bit i of neg: subtract) mod p over
+// m x k uint32 blocks of residues in [0, p).
+hipError_t launch_lincomb(const Fp& f, int64_t m, int64_t k, int nin, const DView* in, unsigned neg, DView out,
+                          hipStream_t s);
 // Copy the lower triangle (or all, if full) of an n x n uint32 block.
 hipError_t launch_copy_u32(int64_t rows, int64_t cols, const uint32_t* src, int64_t lds,
                            uint32_t* dst, int64_t ldd, int lower_only, hipStream_t s);

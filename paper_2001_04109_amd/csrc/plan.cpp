@@ -4,12 +4,14 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <initializer_list>
 
 #include "ffp.h"
 
 namespace ffp {
 
 int g_wide_schedule = 1;
+int64_t g_winograd_min = 0;
 
 namespace {
 
@@ -112,6 +114,68 @@ struct Builder {
         emit(o);
     }
 
+    // v <- sum of +-in[i] mod p over m x k uint32 blocks (neg: bit i set = subtract)
+    void lincomb(int level, int64_t m, int64_t k, std::initializer_list<PView> in, unsigned neg,
+                 const PView& out)
+    {
+        Op o = op(OP_LINCOMB, level);
+        o.m = m;
+        o.k = k;
+        o.mode = (int32_t)in.size() | (int32_t)(neg << 3);
+        int i = 0;
+        for (const PView& v : in) o.v[i++] = v;
+        o.v[5] = out;
+        emit(o);
+    }
+
+    // C <- alpha A B^T (m x n, inner k), with one level of Strassen-Winograd
+    // (Algorithm 1) when the FP64 class runs with wide placements, beta = 0
+    // and the product is large; X = A, Y = B^T split in 2 x 2 blocks:
+    //   S1 = X21 + X22, S2 = S1 - X11, S3 = X11 - X21, S4 = X12 - S2,
+    //   T1 = Y12 - Y11, T2 = Y22 - T1, T3 = Y22 - Y12, T4 = T2 - Y21,
+    //   P1 = X11 Y11, P2 = X12 Y21, P3 = S4 Y22, P4 = X22 T4, P5 = S1 T1,
+    //   P6 = S2 T2, P7 = S3 T3,
+    //   C11 = P1 + P2, C12 = P1 + P6 + P5 + P3, C21 = P1 + P6 + P7 - P4,
+    //   C22 = P1 + P6 + P7 + P5.
+    // With Y = B^T the T blocks are transposes of combinations of B blocks
+    // (T1^T = B21 - B11, ...), so all seven products stay of the A B^T form.
+    void gemm(int level, int64_t m, int64_t n, int64_t k, const PView& A, const PView& B, uint32_t alpha,
+              uint32_t beta, const PView& C)
+    {
+        const bool wino = g_winograd_min > 0 && cls == CLS_F64 && wide && beta == 0 && m >= g_winograd_min &&
+                          n >= g_winograd_min && k >= g_winograd_min && m % 2 == 0 && n % 2 == 0 && k % 2 == 0;
+        if (!wino) { prod_gemm(level, m, n, k, A, B, alpha, beta, C); return; }
+        const int64_t mm = m / 2, nn = n / 2, h = k / 2, e = es();
+        const PView X11 = sub(A, 0, 0, e), X12 = sub(A, 0, h, e), X21 = sub(A, mm, 0, e), X22 = sub(A, mm, h, e);
+        const PView B11 = sub(B, 0, 0, e), B12 = sub(B, 0, h, e), B21 = sub(B, nn, 0, e), B22 = sub(B, nn, h, e);
+        const PView S1 = ws_opnd(mm, h), S2 = ws_opnd(mm, h), S3 = ws_opnd(mm, h), S4 = ws_opnd(mm, h);
+        const PView T1 = ws_opnd(nn, h), T2 = ws_opnd(nn, h), T3 = ws_opnd(nn, h), T4 = ws_opnd(nn, h);
+        // each block from the quadrants directly (no chains between the
+        // additions, so all eight share a level and the seven products the next)
+        lincomb(level, mm, h, {X21, X22}, 0u, S1);
+        lincomb(level, mm, h, {X21, X22, X11}, 4u, S2);
+        lincomb(level, mm, h, {X11, X21}, 2u, S3);
+        lincomb(level, mm, h, {X12, X21, X22, X11}, 6u, S4);                 // X12 - S2
+        lincomb(level, nn, h, {B21, B11}, 2u, T1);                           // T1^T
+        lincomb(level, nn, h, {B22, B21, B11}, 2u, T2);                      // T2^T = B22 - T1^T
+        lincomb(level, nn, h, {B22, B21}, 2u, T3);                           // T3^T
+        lincomb(level, nn, h, {B22, B21, B11, B12}, 10u, T4);                // T4^T = T2^T - B12
+        PView P[7];
+        for (PView& v : P) v = ws_u32(mm, round_up(nn, 4));
+        prod_gemm(level, mm, nn, h, X11, B11, alpha, 0, P[0]);
+        prod_gemm(level, mm, nn, h, X12, B12, alpha, 0, P[1]);
+        prod_gemm(level, mm, nn, h, S4, B22, alpha, 0, P[2]);
+        prod_gemm(level, mm, nn, h, X22, T4, alpha, 0, P[3]);
+        prod_gemm(level, mm, nn, h, S1, T1, alpha, 0, P[4]);
+        prod_gemm(level, mm, nn, h, S2, T2, alpha, 0, P[5]);
+        prod_gemm(level, mm, nn, h, S3, T3, alpha, 0, P[6]);
+        const PView C11 = sub(C, 0, 0, 4), C12 = sub(C, 0, nn, 4), C21 = sub(C, mm, 0, 4), C22 = sub(C, mm, nn, 4);
+        lincomb(level, mm, nn, {P[0], P[1]}, 0u, C11);
+        lincomb(level, mm, nn, {P[0], P[5], P[4], P[2]}, 0u, C12);
+        lincomb(level, mm, nn, {P[0], P[5], P[6], P[3]}, 8u, C21);
+        lincomb(level, mm, nn, {P[0], P[5], P[6], P[4]}, 0u, C22);
+    }
+
     // Table 3: lower(C) <- alpha A A^T, with C's strict upper triangle as the
     // only temporary when k <= n; two m x h workspace blocks otherwise.
     void syrk3(int d, int level, int64_t n, int64_t k, const PView& A, uint32_t alpha, const PView& C)
@@ -137,13 +201,13 @@ struct Builder {
         a.m = m; a.k = h;
         a.v[0] = A11; a.v[1] = A21; a.v[2] = A22; a.v[3] = S1; a.v[4] = S2;
         emit(a);
-        prod_gemm(level, m, m, h, S2, S1, alpha, 0, C22);                  // P4^T = S2 S1^T
+        gemm(level, m, m, h, S2, S1, alpha, 0, C22);                       // P4^T = S2 S1^T
         Op b = op(OP_S34, level);
         b.mode = 3; b.m = m; b.k = h;
         b.v[0] = S1; b.v[1] = A22; b.v[2] = A12; b.v[3] = S1; b.v[4] = S4;
         emit(b);                                                            // S3 = S1 - A22, S4 = S3 + A12
         syrk3(d - 1, level + 1, m, h, S1, alpha, C12);                     // P5 = S3 S3^T
-        prod_gemm(level, m, m, h, A22, S4, alpha, 0, C21);                 // P3 = A22 S4^T
+        gemm(level, m, m, h, A22, S4, alpha, 0, C21);                      // P3 = A22 S4^T
         syrk3(d - 1, level + 1, m, h, A11, alpha, C11);                    // P1 = A11 A11^T
         Op c = op(OP_POSTADD, level);
         c.m = m;

@@ -35,6 +35,8 @@ enum OpKind : int32_t {
     OP_MIRROR = 7,   // Up(v0) <- Low(v0)^T
     OP_PACK = 8,     // v1 (class cls, m x k padded from n x k... see pack_*) <- v0 (class src_cls)
     OP_COPY = 9,     // v1 <- v0 (m x n uint32), mode 1: lower triangle only
+    OP_LINCOMB = 10, // v5 <- sum of +-v_i, i < (mode & 7), mod p; bit 3 + i of mode: subtract v_i
+                     // (m x k uint32 blocks; the Strassen-Winograd additions)
 };
 
 struct Op {
@@ -93,6 +95,12 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out);
 // Process-wide default of PlanRequest::wide for fsyrk_modp (tuning knob;
 // 1 by default).
 extern int g_wide_schedule;
+// General products (P3, P4) of the FP64 class with wide placements and
+// beta = 0 whose m, n and k are all at least this run one level of
+// Strassen-Winograd (Algorithm 1): 7 half-size products instead of 8
+// (0, the default: never; on the depth-3 8192 workload the additions and
+// the smaller launches cost more than the eighth of the products saved).
+extern int64_t g_winograd_min;
 int choose_class(uint32_t p, int a_cls, bool force_f64, bool force_limb3 = false);
 int default_depth(int cls, int64_t n, int64_t k);
 std::string describe_plan(const Plan& pl);

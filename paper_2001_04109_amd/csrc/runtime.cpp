@@ -491,6 +491,10 @@ OpRegions regions_of(const SchedItem& it)
         add_view(r.rd, o.v[0], o.m, o.n, 4, 1, it);
         add_view(r.wr, o.v[1], o.m, o.n, 4, 1, it);
         break;
+    case OP_LINCOMB:
+        for (int i = 0; i < (o.mode & 7); ++i) add_view(r.rd, o.v[i], o.m, o.k, 4, 1, it);
+        add_view(r.wr, o.v[5], o.m, o.k, 4, 1, it);
+        break;
     }
     return r;
 }
@@ -521,15 +525,16 @@ int64_t rup256(int64_t x) { return (x + 255) / 256 * 256; }
 
 // Products (GEMM, SYRK) of one representation class on one level form one
 // grouped launch.  After the as-soon-as-possible levels are set, a product
-// whose launch would be small (under kSmallLaunch output elements, about two
-// rounds of 128 x 128 tiles over the 256 CUs) moves to the later level, within
+// whose launch would be small (under g_merge_tiles tiles of 128 x 128, two
+// rounds over the 256 CUs by default) moves to the later level, within
 // the range its dependents allow, that already holds the most product work of
 // its class: the leaves on blocks of A that are ready at once (the chains of
 // P1 and P2) join a large launch instead of running on a fraction of the
 // CUs.  Moving an operation later keeps every dependency satisfied as long as
 // no operation that depends on it runs at or before its new level.
+int g_merge_tiles = 512;
+
 namespace {
-constexpr double kSmallLaunch = 512.0 * 128 * 128;
 
 bool is_product(const SchedItem& it) { return it.op->kind == OP_GEMM || it.op->kind == OP_SYRK; }
 
@@ -554,7 +559,7 @@ void merge_small_products(const std::vector<SchedItem>& items, const std::vector
     for (size_t i = n; i-- > 0;) {
         if (!is_product(items[i])) continue;
         const int cls = items[i].op->cls, cur = level[i];
-        if (slot(cur, cls) >= kSmallLaunch) continue;
+        if (slot(cur, cls) >= (double)g_merge_tiles * 128.0 * 128.0) continue;
         int alap = maxlev;
         for (size_t j = i + 1; j < job_end[i]; ++j)
             if (level[j] - 1 < alap && depends(regs[i], regs[j])) alap = level[j] - 1;
@@ -803,6 +808,12 @@ int execute_op(const Plan& pl, const Op& o, const void* a, void* c, void* ws, hi
             e = launch_copy_u32(o.m, o.n, (const uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld,
                                 (uint32_t*)at(o.v[1], a, c, ws), o.v[1].ld, o.mode & 1, s);
             break;
+        case OP_LINCOMB: {
+            DView in[5] = {};
+            for (int i = 0; i < (o.mode & 7); ++i) in[i] = dview(o.v[i], a, c, ws);
+            e = launch_lincomb(f, o.m, o.k, o.mode & 7, in, (unsigned)(o.mode >> 3), dview(o.v[5], a, c, ws), s);
+            break;
+        }
         }
         if (e != hipSuccess) return FFP_EDEVICE;
     }

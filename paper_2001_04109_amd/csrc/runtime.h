@@ -101,6 +101,8 @@ extern int g_leveled;
 // 1 (default): products of small grouped launches move to a later level
 // with a larger launch of their class when their dependents allow.
 extern int g_merge_products;
+// Size (in 128 x 128 tiles) under which a level's product launch counts as small.
+extern int g_merge_tiles;
 ProdTask make_task(const Plan& pl, const Op& o, const void* a, void* c, void* ws);
 PackDesc make_pack(const Plan& pl, const Op& o, const void* a, void* c, void* ws);
 

@@ -15,7 +15,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 CLS_F64, CLS_I8, CLS_LIMB2, CLS_LIMB3 = 0, 1, 2, 3
-OP_S1S2, OP_S34, OP_GEMM, OP_SYRK, OP_POSTADD, OP_ADDLOW, OP_SAVEC22, OP_MIRROR, OP_PACK, OP_COPY = range(10)
+(OP_S1S2, OP_S34, OP_GEMM, OP_SYRK, OP_POSTADD, OP_ADDLOW, OP_SAVEC22, OP_MIRROR, OP_PACK, OP_COPY,
+ OP_LINCOMB) = range(11)
 
 
 @dataclass
@@ -231,6 +232,13 @@ class Sim:
         dst = np.zeros((o.m, o.k), dtype=np.int64)
         dst[: o.m_src, : o.k_src] = src
         self.put(o.v[1], o.cls, dst)
+
+    def op10(self, o):  # v5 = sum of +-v_i mod p (bit 3 + i of mode: subtract)
+        acc = np.zeros((o.m, o.k), dtype=np.int64)
+        for i in range(o.mode & 7):
+            X = self.get(o.v[i], CLS_F64, o.m, o.k)
+            acc = acc - X if (o.mode >> (3 + i)) & 1 else acc + X
+        self.put(o.v[5], CLS_F64, acc % self.p)
 
     def op9(self, o):   # copy
         X = self.get(o.v[0], CLS_F64, o.m, o.n)

@@ -192,6 +192,21 @@ def test_limb2_pipe_variant(pipe, n, k, dtype):
         set_knob("i8_pipe", 1)
 
 
+@pytest.mark.parametrize("p", [65537, 131071])
+@pytest.mark.parametrize("n,k,depth", [(1024, 1024, 1), (1000, 1500, 2), (768, 2048, 3)])
+def test_winograd_general_products(p, n, k, depth):
+    """P3 and P4 through one level of Strassen-Winograd (threshold lowered to
+    256 so that these sizes take it), with alpha; bit-exact."""
+    A = inputs.uniform(n + k + depth, n, k, p)
+    set_knob("winograd_min", 256)
+    try:
+        check_lower(gpu_syrk(A, p, depth=depth), oracle.syrk(A, p))
+        check_lower(gpu_syrk(A, p, depth=depth, alpha=p - 1, beta=0),
+                    oracle.syrk_ab(A, p, p - 1, 0, np.zeros((n, n), np.uint32)))
+    finally:
+        set_knob("winograd_min", 0)
+
+
 @pytest.mark.parametrize("vec", [1, 0])
 @pytest.mark.parametrize("p,limb3,depth", [(251, False, 0), (65521, False, 0), (131071, True, 0),
                                            (251, False, 1), (65537, False, 2)])

@@ -106,3 +106,42 @@ def test_small_launch_products_move_later():
     assert all(merged[i] >= asap[i] for i in prods)
     assert all(merged[i] == asap[i] for i in range(len(kinds)) if i not in prods)
     assert len(set(merged[i] for i in prods)) < len(set(asap[i] for i in prods))
+
+
+@pytest.mark.parametrize("p", [65537, 131071])
+@pytest.mark.parametrize("n,k,depth", [(64, 64, 1), (96, 160, 2), (128, 48, 1), (64, 256, 3)])
+def test_winograd_general_products(p, n, k, depth):
+    """General products P3, P4 through one level of Strassen-Winograd (the
+    size threshold lowered to 16): the plan holds the additions, and run in
+    program order and level by level (reverse order inside a level) it still
+    computes A A^T."""
+    ffp.set_knob("winograd_min", 16)
+    try:
+        plan, levels = check_reordered(n, k, p, depth)
+        kinds = [o.kind for o in plan.ops]
+        assert plansim.OP_LINCOMB in kinds
+        A = inputs.uniform(3, n, k, p)
+        text = ffp.plan_describe(n, k, p, flags=ffp.FFP_DEPTH(depth))
+        out = plansim.simulate(text, p, A.astype(np.uint32).tobytes(), np.zeros((n, n), np.uint32))
+        low = np.tril(np.ones((n, n), dtype=bool))
+        assert np.array_equal(out[low], oracle.syrk(A, p)[low])
+    finally:
+        ffp.set_knob("winograd_min", 0)
+
+
+def test_winograd_only_for_plain_wide_fp64():
+    """No Strassen-Winograd additions under Table 4 (beta != 0), with the
+    Table 3 placements, on int8 paths or below the size threshold."""
+    ffp.set_knob("winograd_min", 16)
+    try:
+        def has_lincomb(*args, **kw):
+            text = ffp.plan_describe(*args, **kw)
+            return any(int(l.split()[1]) == plansim.OP_LINCOMB for l in text.splitlines()[1:])
+        assert has_lincomb(64, 64, 65537, flags=ffp.FFP_DEPTH(1))
+        assert not has_lincomb(64, 64, 65537, alpha=3, beta=2, flags=ffp.FFP_DEPTH(1))
+        assert not has_lincomb(64, 64, 65537, flags=ffp.FFP_DEPTH(1) | ffp.FFP_LOW_MEMORY)
+        assert not has_lincomb(64, 64, 251, flags=ffp.FFP_DEPTH(1))
+        ffp.set_knob("winograd_min", 64)
+        assert not has_lincomb(64, 64, 65537, flags=ffp.FFP_DEPTH(1))
+    finally:
+        ffp.set_knob("winograd_min", 0)
