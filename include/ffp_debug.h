@@ -84,7 +84,9 @@ void ffp_debug_set_kblk(int64_t kblk);
  * small for "merge_products"; 512 by default), "pack_vec" (1, the
  * default: representation changes from uint32 residues convert 4 columns
  * per thread, 16 x 256 per workgroup, when the destination keeps those
- * stores aligned; 0: one element per thread), "merge_products" (1,
+ * stores aligned, and the FP64-class pre-additions run 4 columns per thread
+ * when their rows are 16-byte aligned; 0: one element per thread),
+ * "merge_products" (1,
  * the default: after the as-soon-as-possible levels are set, a product whose
  * grouped launch would be small moves to a later level with a larger
  * launch of its class when its dependents allow; 0: off), "leveled" (1, the

@@ -8,6 +8,8 @@
 #include "modp.h"
 #include "prod_common.h"
 
+#include <initializer_list>
+
 namespace ffp {
 
 namespace {
@@ -107,6 +109,86 @@ __global__ __launch_bounds__(256) void preadd_s34_kernel(Fp f, int mode, int64_t
         if (mode & 2) {
             uint32_t s4 = add_m(s3, ld_res(CLS, f, A12, i, c), f.p);               // S4 = S3 + A12
             st_res(CLS, f, S4, i, c, s4);
+        }
+    }
+}
+
+// FP64 class (uint32 residues) with 4 consecutive columns per thread; the
+// launchers take these when every row start is 16-byte aligned and the
+// column count (of pairs, for Y = [[aI, bI], [-bI, aI]]) is a multiple of 4.
+__device__ __forceinline__ uint4 ld4(const DView& v, int64_t i, int64_t j)
+{
+    return *reinterpret_cast<const uint4*>((const uint32_t*)v.p + i * v.ld + j);
+}
+
+__device__ __forceinline__ void st4(const DView& v, int64_t i, int64_t j, uint4 x)
+{
+    *reinterpret_cast<uint4*>((uint32_t*)v.p + i * v.ld + j) = x;
+}
+
+__device__ __forceinline__ uint32_t comp(const uint4& x, int e) { return e == 0 ? x.x : e == 1 ? x.y : e == 2 ? x.z : x.w; }
+
+__global__ __launch_bounds__(256) void preadd_s1s2_u32x4_kernel(Fp f, int64_t m, int64_t h, DView A11, DView A21,
+                                                               DView A22, DView S1, DView S2)
+{
+    const int64_t ncol = f.yb ? h / 2 : h;
+    const int64_t h2 = h / 2;
+    const int64_t c = ((int64_t)blockIdx.x * 64 + (threadIdx.x & 63)) * 4;
+    if (c >= ncol) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < m; i += (int64_t)gridDim.y * 4) {
+        if (f.yb == 0) {
+            const uint4 a11 = ld4(A11, i, c), a21 = ld4(A21, i, c), a22 = ld4(A22, i, c);
+            uint32_t s1[4], s2[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t x11 = comp(a11, e), x21 = comp(a21, e), x22 = comp(a22, e);
+                s1[e] = mul_m(sub_m(x21, x11, f.p), f.ya, f.p, f.pinv);
+                s2[e] = sub_m(x22, mul_m(x21, f.ya, f.p, f.pinv), f.p);
+            }
+            st4(S1, i, c, make_uint4(s1[0], s1[1], s1[2], s1[3]));
+            st4(S2, i, c, make_uint4(s2[0], s2[1], s2[2], s2[3]));
+        } else {
+            const int64_t cl = c, cr = c + h2;
+            const uint4 a11l = ld4(A11, i, cl), a11r = ld4(A11, i, cr), a21l = ld4(A21, i, cl),
+                        a21r = ld4(A21, i, cr), a22l = ld4(A22, i, cl), a22r = ld4(A22, i, cr);
+            uint32_t s1l[4], s1r[4], s2l[4], s2r[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t xl = comp(a21l, e), xr = comp(a21r, e);
+                const uint32_t dl = sub_m(xl, comp(a11l, e), f.p), dr = sub_m(xr, comp(a11r, e), f.p);
+                s1l[e] = sub_m(mul_m(dl, f.ya, f.p, f.pinv), mul_m(dr, f.yb, f.p, f.pinv), f.p);
+                s1r[e] = add_m(mul_m(dl, f.yb, f.p, f.pinv), mul_m(dr, f.ya, f.p, f.pinv), f.p);
+                const uint32_t tl = sub_m(mul_m(xl, f.ya, f.p, f.pinv), mul_m(xr, f.yb, f.p, f.pinv), f.p);
+                const uint32_t tr = add_m(mul_m(xl, f.yb, f.p, f.pinv), mul_m(xr, f.ya, f.p, f.pinv), f.p);
+                s2l[e] = sub_m(comp(a22l, e), tl, f.p);
+                s2r[e] = sub_m(comp(a22r, e), tr, f.p);
+            }
+            st4(S1, i, cl, make_uint4(s1l[0], s1l[1], s1l[2], s1l[3]));
+            st4(S1, i, cr, make_uint4(s1r[0], s1r[1], s1r[2], s1r[3]));
+            st4(S2, i, cl, make_uint4(s2l[0], s2l[1], s2l[2], s2l[3]));
+            st4(S2, i, cr, make_uint4(s2r[0], s2r[1], s2r[2], s2r[3]));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void preadd_s34_u32x4_kernel(Fp f, int mode, int64_t m, int64_t h, DView S1,
+                                                              DView A22, DView A12, DView S3, DView S4)
+{
+    const int64_t c = ((int64_t)blockIdx.x * 64 + (threadIdx.x & 63)) * 4;
+    if (c >= h) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < m; i += (int64_t)gridDim.y * 4) {
+        uint4 s3;
+        if (mode & 1) {
+            const uint4 x = ld4(S1, i, c), y = ld4(A22, i, c);
+            s3 = make_uint4(sub_m(x.x, y.x, f.p), sub_m(x.y, y.y, f.p), sub_m(x.z, y.z, f.p), sub_m(x.w, y.w, f.p));
+            st4(S3, i, c, s3);
+        } else {
+            s3 = ld4(S3, i, c);
+        }
+        if (mode & 2) {
+            const uint4 y = ld4(A12, i, c);
+            st4(S4, i, c, make_uint4(add_m(s3.x, y.x, f.p), add_m(s3.y, y.y, f.p), add_m(s3.z, y.z, f.p),
+                                     add_m(s3.w, y.w, f.p)));
         }
     }
 }
@@ -421,6 +503,15 @@ inline dim3 grid2d(int64_t rows, int64_t cols)
     return dim3((unsigned)gx, (unsigned)gy);
 }
 
+// every view's rows start 16-byte aligned and the column count is a multiple of 4
+inline bool u32x4_ok(int64_t ncol, std::initializer_list<DView> views)
+{
+    if (!g_pack_vec || (ncol & 3) != 0) return false;
+    for (const DView& v : views)
+        if ((v.ld & 3) != 0 || (((uintptr_t)v.p) & 15) != 0) return false;
+    return true;
+}
+
 inline unsigned tri_blocks(int64_t m)
 {
     const int64_t t = (m + T - 1) / T;
@@ -434,6 +525,11 @@ hipError_t launch_preadd_s1s2(int cls, const Fp& f, int64_t m, int64_t h, DView 
 {
     if (m <= 0 || h <= 0) return hipSuccess;
     const int64_t ncol = f.yb ? h / 2 : h;
+    if (cls == CLS_F64 && u32x4_ok(ncol, {A11, A21, A22, S1, S2})) {
+        hipLaunchKernelGGL(preadd_s1s2_u32x4_kernel, grid2d(m, ncol / 4), dim3(256), 0, s, f, m, h, A11, A21, A22,
+                           S1, S2);
+        return hipGetLastError();
+    }
     dim3 g = grid2d(m, ncol);
     switch (cls) {
     case CLS_F64: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_F64>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
@@ -447,6 +543,11 @@ hipError_t launch_preadd_s34(int cls, const Fp& f, int mode, int64_t m, int64_t 
                              DView A22, DView A12, DView S3, DView S4, hipStream_t s)
 {
     if (m <= 0 || h <= 0) return hipSuccess;
+    if (cls == CLS_F64 && u32x4_ok(h, {S1, A22, A12, S3, S4})) {
+        hipLaunchKernelGGL(preadd_s34_u32x4_kernel, grid2d(m, h / 4), dim3(256), 0, s, f, mode, m, h, S1, A22, A12,
+                           S3, S4);
+        return hipGetLastError();
+    }
     dim3 g = grid2d(m, h);
     switch (cls) {
     case CLS_F64: hipLaunchKernelGGL(preadd_s34_kernel<CLS_F64>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
