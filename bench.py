@@ -534,7 +534,7 @@ def main():
         torch.cuda.synchronize()
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus {args.gpus} "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (--gpus {args.gpus} "
               "requested)", file=sys.stderr)
         sys.exit(2)
     import torch
