@@ -309,7 +309,8 @@ class OperandPool:
 
 
 class ServedCheck:
-    """Checks every stride-th served result before it is released: LDL^T
+    """Checks every stride-th served result (after the stream, before it is
+    released): LDL^T
     results against the leading block of the pool's factorisation, A A^T
     results on 32 sampled entries against the oracle.  Copies run on a side
     stream of their own."""
@@ -378,19 +379,24 @@ def served(nreq, rate=2000.0, budget=96 << 30, nstreams=4, max_inflight=1024, sa
     done_at = np.zeros(nreq)
     bad = []
     chk = ServedCheck(pool) if check else None
+    # checked results stay in the arena until the stream is over, so that
+    # fetching and comparing them does not hold up the reaper (or, through the
+    # interpreter lock, the submitting thread) while requests are arriving
+    deferred = []
     with ffp.Server(budget, max_inflight=max_inflight, nstreams=nstreams) as srv:
         def reaper():
             got = 0
             while got < nreq:
                 for t in srv.poll(512, 0.05):
                     st = srv.status(t)
+                    done_at[t - 1] = st.t_done
+                    got += 1
                     if st.state != ffp.FFP_STATE_DONE:
                         bad.append((t - 1, st.state))
                     elif chk and (t - 1) % chk.stride == 0:
-                        chk.take(srv, t, reqs[t - 1])
-                    done_at[t - 1] = st.t_done
+                        deferred.append(t)
+                        continue
                     srv.release(t)
-                    got += 1
 
         th = threading.Thread(target=reaper, daemon=True)
         th.start()
@@ -406,6 +412,9 @@ def served(nreq, rate=2000.0, budget=96 << 30, nstreams=4, max_inflight=1024, sa
         if th.is_alive():
             raise SystemExit("bench: served stream did not finish")
         stats = srv.stats()
+        for t in deferred:
+            chk.take(srv, t, reqs[t - 1])
+            srv.release(t)
     if bad:
         raise SystemExit(f"bench: {len(bad)} served requests failed, first {bad[0]}")
     arrive = t0 + (np.zeros(nreq) if saturate else np.array([r["t"] for r in reqs]))
@@ -581,10 +590,6 @@ def main():
                     v = {"error": repr(e)[:200]}
                 log(f"bench: vendor int8 GEMM {v}")
                 extra[other]["vendor_int8_gemm"] = v
-    if not args.no_extra and not args.no_batched:
-        log("bench: batched 1024 jobs vs per-call")
-        extra["batched_1024_jobs"] = batched_vs_plain()
-        log(f"bench: batched {extra['batched_1024_jobs']}")
     if not args.no_extra and args.serve_requests > 0:
         log("bench: autotuning the served A A^T shape classes")
         tuned = tune_served_classes()
@@ -608,6 +613,11 @@ def main():
                                   "underload": low, "autotune": tuned}
         ffp.ffp_tune_clear()
         del pool
+    if not args.no_extra and not args.no_batched:
+        log("bench: batched 1024 jobs vs per-call")
+        extra["batched_1024_jobs"] = batched_vs_plain()
+        log(f"bench: batched {extra['batched_1024_jobs']}")
+        ffp.ffp_tune_clear()      # each leg runs with the table tuned for its own workload
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
