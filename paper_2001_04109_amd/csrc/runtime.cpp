@@ -143,8 +143,15 @@ int acquire_workspace(hipStream_t s, size_t bytes, size_t ntasks, Workspace** ou
     }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return FFP_EDEVICE;
-    std::lock_guard<std::mutex> lk(g_ws_mutex);
-    Workspace& w = g_ws[std::make_pair(dev, s)];
+    // the lock covers the lookup only: a stream's workspace is used by one
+    // thread at a time (the library is thread-safe across streams), and its
+    // growth waits for the stream, which must not hold up other streams
+    Workspace* wp;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mutex);
+        wp = &g_ws[std::make_pair(dev, s)];
+    }
+    Workspace& w = *wp;
     if (bytes > w.bytes || ntasks > w.task_cap) {
         if (w.ptr || w.tasks) {
             if (note_hip("hipStreamSynchronize (workspace)", hipStreamSynchronize(s)) != hipSuccess)
@@ -209,8 +216,14 @@ int acquire_staging(hipStream_t s, size_t bytes, char** host, char** dev)
     }
     int d = 0;
     if (hipGetDevice(&d) != hipSuccess) return FFP_EDEVICE;
-    std::lock_guard<std::mutex> lk(g_ws_mutex);
-    Staging& st = g_stage[std::make_pair(d, s)];
+    // lookup under the lock; the wait for the previous use of this stream's
+    // staging area outside it (other streams' launches go on meanwhile)
+    Staging* sp;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mutex);
+        sp = &g_stage[std::make_pair(d, s)];
+    }
+    Staging& st = *sp;
     if (st.pending) {
         if (hipEventSynchronize(st.done) != hipSuccess) return FFP_EDEVICE;
         st.pending = false;
@@ -242,8 +255,12 @@ int release_staging(hipStream_t s)
     if (g_cap) return FFP_OK;   // the graph owns its staging area
     int d = 0;
     if (hipGetDevice(&d) != hipSuccess) return FFP_EDEVICE;
-    std::lock_guard<std::mutex> lk(g_ws_mutex);
-    Staging& st = g_stage[std::make_pair(d, s)];
+    Staging* sp;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mutex);
+        sp = &g_stage[std::make_pair(d, s)];
+    }
+    Staging& st = *sp;
     if (!st.done) return FFP_OK;
     if (hipEventRecord(st.done, s) != hipSuccess) return FFP_EDEVICE;
     st.pending = true;
