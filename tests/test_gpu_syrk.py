@@ -449,6 +449,19 @@ def test_full_size_8192_p131071_depth3(k, wide):
     _sampled(A, p, from_dev_u32(Cd))
 
 
+@pytest.mark.parametrize("k", [8192, 32768])
+def test_full_size_8192_p131071_three_limbs(k):
+    """The depth-3 workload's shapes on three int8 limbs (as bench.py's
+    syrk_8192_p131071_limb3): sampled entries against the oracle."""
+    import torch
+    p, n = 131071, 8192
+    A = inputs.uniform(1, n, k, p)
+    Cd = torch.zeros((n, n), dtype=torch.int32, device="cuda")
+    ffp.syrk(to_dev_u32(A), p, C=Cd, limb3=True)
+    torch.cuda.synchronize()
+    _sampled(A, p, from_dev_u32(Cd))
+
+
 @pytest.mark.parametrize("p,a_dtype,ring", [(251, ffp.FFP_I8_CENTERED, 0), (251, ffp.FFP_I8_CENTERED, 4),
                                             (251, ffp.FFP_I8_CENTERED, 5), (65521, ffp.FFP_I8_LIMB2, 0)])
 def test_full_size_16384_int8(p, a_dtype, ring):
