@@ -240,8 +240,9 @@ __global__ __launch_bounds__(256) void prod_i8_ring_kernel(ProdArgs args, int mo
 // bytes (four k-steps of 32): two register sets hold the operand panels of
 // the next two stages, so the global loads issued at the start of stage t
 // (for stage t + 2) have more than a stage to land; the set loaded one stage
-// earlier is written to the free LDS buffer during k-steps 1 (A panel) and 2
-// (B panel) of stage t, between the MFMAs; the workgroup barrier sits before
+// earlier is written to the free LDS buffer during k-steps 0 and 1 (A panel,
+// half in each) and 2 (B panel) of stage t, between the MFMAs; the workgroup
+// barrier sits before
 // k-step 3, whose MFMAs cover the reads of the first fragments of stage t + 1.
 // Stages are processed in pairs; the loads of stages past the end of k return
 // zeros (see bload), so an odd count gets one stage of zero products.
@@ -286,6 +287,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const int8_t* p, in
     void* base = (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
     // raw buffer (stride 0), 32-bit dword format word for CDNA
     return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nb, 0x00020000);
+}
+
+// Passes [P0, P1) of a staged panel to LDS (lstore's layout).
+template <int ROWS, int BK, int P0, int P1>
+__device__ __forceinline__ void lstore_part(int8_t* __restrict__ lds, const Prefetch<ROWS, BK>& pf)
+{
+    constexpr int CHUNKS = Prefetch<ROWS, BK>::CHUNKS;
+#pragma unroll
+    for (int ps = P0; ps < P1; ++ps) {
+        const int idx = ps * 256 + threadIdx.x;
+        const int r = idx / CHUNKS, c = idx % CHUNKS;
+        *reinterpret_cast<v4i*>(lds + r * Prefetch<ROWS, BK>::PITCH + c * 16) = pf.v[ps];
+    }
 }
 
 // PLANES = 1: centred int8 (one accumulator); 2: two int8 limbs (hh, ll and
@@ -391,26 +405,31 @@ __device__ __forceinline__ void i8_pipe_body(const ProdTask& t, int ti, int tj, 
             load_a(la, (kt + 2) * BK, kt + 2 < nk);
             __builtin_amdgcn_sched_barrier(0);
             v4i na[PLANES][FM], nb[PLANES][FN];
-            // k-step 0
+            constexpr int PA = Prefetch<BM, BK>::PASSES, HA = PA / 2;
+            // k-step 0, first half of the A panel of stage kt + 1 to LDS
             read_frags(na, nb, cur, 1);
             mfmas(fa, fb);
 #pragma unroll
+            for (int pl = 0; pl < PLANES; ++pl) lstore_part<BM, BK, 0, HA>(sa[cur ^ 1][pl], wa[pl]);
+#pragma unroll
             for (int q = 0; q < NREAD; ++q) {
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / NREAD, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WA / 2), 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, (WA / 2) / NREAD > 0 ? (WA / 2) / NREAD : 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WA / 2), 0);
             }
             __builtin_amdgcn_sched_barrier(0);
-            // k-step 1, A panel of stage kt + 1 to LDS
+            // k-step 1, second half of the A panel
             read_frags(fa, fb, cur, 2);
             mfmas(na, nb);
 #pragma unroll
-            for (int pl = 0; pl < PLANES; ++pl) lstore<BM, BK>(sa[cur ^ 1][pl], wa[pl]);
+            for (int pl = 0; pl < PLANES; ++pl) lstore_part<BM, BK, HA, PA>(sa[cur ^ 1][pl], wa[pl]);
 #pragma unroll
             for (int q = 0; q < NREAD; ++q) {
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WA), 0);
-                __builtin_amdgcn_sched_group_barrier(0x200, WA / NREAD, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WA), 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WA / 2), 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, (WA / 2) / NREAD > 0 ? (WA / 2) / NREAD : 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / (NREAD + WA / 2), 0);
             }
             __builtin_amdgcn_sched_barrier(0);
             // k-step 2, B panel of stage kt + 1 to LDS, then the loads of
