@@ -11,11 +11,13 @@ Inputs are drawn on the host with numpy's PCG64 (seed 1) and are resident in
 HBM before the timed region.  Besides the JSON line the run prints nothing
 on stdout.  Roofline figures come from HIP events around every product
 launch in the timed region; the CPU baseline is the oracle on a bounded row
-panel of the same product.  The "extra" object reports the int8 and int8
-limb products of 16384 x 16384, the 1024-job batched form against the same
-jobs as per-call fsyrk_modp, and the served Poisson stream of A A^T and
-LDL^T requests (p50/p99 latency from arrival to completion, throughput),
-with the same requests at once and per call for comparison.
+panel of the same product.  The "extra" object reports, in this order, the
+int8 and int8-limb products of 16384 x 16384 (with the vendor library's int8
+GEMM on the same shape as context) and the three-limb form of the default
+workload, the served Poisson stream of A A^T and LDL^T requests (p50/p99
+latency from arrival to completion, overall and per kind, throughput) with
+the same requests at once and per call for comparison, and the 1024-job
+batched form against the same jobs as per-call fsyrk_modp.
 """
 from __future__ import annotations
 
