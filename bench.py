@@ -56,7 +56,7 @@ def log(*a):
 
 def upload(A, p, dtype):
     import torch
-    from tests.gpu_util import centred_i8, limbs
+    from paper_2001_04109_amd.storage import centred_i8, limbs
     if dtype == "u32":
         return torch.from_numpy(A.view(np.int32)).cuda()
     if dtype == "i8":

@@ -48,6 +48,8 @@ extern "C" {
 #define FFP_ENOMEM       (-4) /* device workspace could not be allocated */
 #define FFP_EDEVICE      (-5) /* a HIP runtime call failed */
 #define FFP_EUNSUPPORTED (-6) /* a valid request this library does not implement */
+#define FFP_ECANCELED    (-7) /* a served request was cancelled before it ran */
+#define FFP_ETIMEDOUT    (-8) /* a served request was still queued at its deadline */
 
 /* ---- operand storage of A ------------------------------------------- */
 /* uint32 residues in [0,p).  Any prime 2 < p < 2^25 is accepted.  The base
@@ -281,6 +283,8 @@ typedef struct ffp_request {
     uint32_t alpha;        /* SYRK scale, residue in [0,p) */
     const void* A;         /* device pointer, uint32 residues (FFP_U32 storage) */
     int64_t lda;
+    double timeout_s;      /* > 0: the request fails with FFP_ETIMEDOUT if it has not
+                              been admitted this many seconds after submission; 0: none */
 } ffp_request;
 
 typedef struct ffp_result {
@@ -308,8 +312,16 @@ int ffp_server_create(size_t hbm_budget, int max_inflight, int nstreams, ffp_ser
  * exceeds the budget. */
 int ffp_server_submit(ffp_server* s, const ffp_request* r, uint64_t* ticket);
 int ffp_server_status(ffp_server* s, uint64_t ticket, ffp_result* out);
-/* Returns a done request's result memory to the budget. */
+/* Returns a done request's result memory to the budget.  Copies that
+ * ffp_server_fetch enqueued from it may still be pending on the caller's
+ * stream: the memory then returns to the arena only once they have executed
+ * (the fetch records an event after them), so a release never lets a later
+ * request overwrite a result that is still being copied. */
 int ffp_server_release(ffp_server* s, uint64_t ticket);
+/* Cancels a request that is still queued: it becomes done with state
+ * FFP_ECANCELED and holds no memory.  FFP_EINVAL if it has already been
+ * admitted (running work is not interrupted) or is done. */
+int ffp_server_cancel(ffp_server* s, uint64_t ticket);
 /* Waits until every submitted request is done (FFP_EDEVICE on timeout). */
 int ffp_server_drain(ffp_server* s, double timeout_s);
 /* Completion queue: waits up to timeout_s seconds (0: no wait) until some

@@ -93,6 +93,8 @@ const char* ffp_strerror(int status)
     case FFP_ENOMEM: return "device workspace allocation failed";
     case FFP_EDEVICE: return "HIP runtime error";
     case FFP_EUNSUPPORTED: return "not supported";
+    case FFP_ECANCELED: return "request cancelled";
+    case FFP_ETIMEDOUT: return "request deadline passed before admission";
     default: return "unknown status";
     }
 }

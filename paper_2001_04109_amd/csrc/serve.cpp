@@ -237,6 +237,18 @@ Server::~Server()
     cv_launch_.notify_all();
     for (std::thread& t : launchers_)
         if (t.joinable()) t.join();
+    // fetch events (only a HIP device has them): pending copies finish first
+    for (Deferred& d : deferred_) {
+        (void)hipEventSynchronize((hipEvent_t)d.ev);
+        (void)hipEventDestroy((hipEvent_t)d.ev);
+    }
+    deferred_.clear();
+    for (ServeReq& q : reqs_)
+        if (q.fetch_ev) {
+            (void)hipEventSynchronize((hipEvent_t)q.fetch_ev);
+            (void)hipEventDestroy((hipEvent_t)q.fetch_ev);
+            q.fetch_ev = nullptr;
+        }
     delete dev_;
 }
 
@@ -351,16 +363,87 @@ int Server::submit(const ffp_request* r, uint64_t* ticket)
     q.flags = pinned_flags(q.rq);
     q.ws_bytes = workspace_bytes(q.rq, q.flags);
     if (q.bytes + q.ws_bytes > budget_) return FFP_ENOMEM;
+    if (!(r->timeout_s >= 0.0)) return FFP_EINVAL;
     {
         std::lock_guard<std::mutex> lk(mu_);
         q.ticket = reqs_.size() + 1;
         q.t_submit = now_s();
+        if (r->timeout_s > 0.0) {
+            q.deadline = q.t_submit + r->timeout_s;
+            ++n_deadlines_;
+        }
         reqs_.push_back(q);
         queue_.push_back(q.ticket);
         *ticket = q.ticket;
     }
     cv_.notify_all();
     return FFP_OK;
+}
+
+// A queued request leaves the queue as done with a failure status (cancel,
+// deadline).  Called with the lock held; the caller removes it from queue_.
+void Server::fail_queued(ServeReq& q, int status, double now)
+{
+    q.status = status;
+    q.state = FFP_STATE_DONE;
+    q.t_done = now;
+    q.released = true;   // holds no memory
+    if (q.deadline > 0.0) --n_deadlines_;
+    done_q_.push_back(q.ticket);
+}
+
+int Server::cancel(uint64_t ticket)
+{
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (ticket == 0 || ticket > reqs_.size()) return FFP_EINVAL;
+        ServeReq& q = reqs_[ticket - 1];
+        if (q.state != FFP_STATE_QUEUED) return FFP_EINVAL;   // admitted work is not interrupted
+        auto it = std::find(queue_.begin(), queue_.end(), ticket);
+        if (it == queue_.end()) return FFP_EINVAL;
+        queue_.erase(it);
+        fail_queued(q, FFP_ECANCELED, now_s());
+    }
+    cv_done_.notify_all();
+    cv_.notify_all();
+    return FFP_OK;
+}
+
+// Queued requests whose deadline has passed fail with FFP_ETIMEDOUT.  Called
+// with the lock held.
+void Server::expire_queued(double now)
+{
+    if (n_deadlines_ == 0 || now < next_expiry_check_) return;
+    next_expiry_check_ = now + 1e-4;
+    for (auto it = queue_.begin(); it != queue_.end();) {
+        ServeReq& q = reqs_[*it - 1];
+        if (q.deadline > 0.0 && now >= q.deadline) {
+            fail_queued(q, FFP_ETIMEDOUT, now);
+            it = queue_.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// Released results whose last fetch copy has executed return to the arena.
+// Called with the lock held.
+void Server::reap_deferred()
+{
+    for (size_t i = 0; i < deferred_.size();) {
+        Deferred& d = deferred_[i];
+        const hipError_t e = hipEventQuery((hipEvent_t)d.ev);
+        if (e == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        (void)hipGetLastError();
+        (void)hipEventDestroy((hipEvent_t)d.ev);
+        arena_free(d.off, d.bytes);
+        used_ -= d.bytes;
+        deferred_[i] = deferred_.back();
+        deferred_.pop_back();
+    }
 }
 
 int Server::status(uint64_t ticket, ffp_result* out)
@@ -391,8 +474,15 @@ int Server::release(uint64_t ticket)
     if (q.state != FFP_STATE_DONE) return FFP_EINVAL;
     if (!q.released) {
         q.released = true;
-        arena_free(q.off, q.bytes);
-        used_ -= q.bytes;
+        if (q.fetch_ev) {
+            // a fetch copy enqueued on the caller's stream may still read the
+            // result: its memory returns to the arena once the copy has run
+            deferred_.push_back(Deferred{q.off, q.bytes, q.fetch_ev});
+            q.fetch_ev = nullptr;
+        } else {
+            arena_free(q.off, q.bytes);
+            used_ -= q.bytes;
+        }
     }
     cv_.notify_all();
     return FFP_OK;
@@ -434,7 +524,7 @@ int Server::fetch(uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst
 {
     std::lock_guard<std::mutex> lk(mu_);
     if (ticket == 0 || ticket > reqs_.size()) return FFP_EINVAL;
-    const ServeReq& q = reqs_[ticket - 1];
+    ServeReq& q = reqs_[ticket - 1];
     char* base = dev_->arena();
     if (!base || q.state != FFP_STATE_DONE || q.status != FFP_OK || q.released) return FFP_EINVAL;
     const int64_t n = q.rq.n, ld = result_ld(q.rq);
@@ -448,6 +538,13 @@ int Server::fetch(uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst
         hipMemcpyAsync(info_dst, base + q.off + rup(n * ld * 4, 256), sizeof(int64_t),
                        hipMemcpyDeviceToDevice, s) != hipSuccess)
         return FFP_EDEVICE;
+    // release() keeps the result's memory until these copies have executed
+    if (!q.fetch_ev &&
+        hipEventCreateWithFlags((hipEvent_t*)&q.fetch_ev, hipEventDisableTiming) != hipSuccess) {
+        q.fetch_ev = nullptr;
+        return FFP_EDEVICE;
+    }
+    if (hipEventRecord((hipEvent_t)q.fetch_ev, s) != hipSuccess) return FFP_EDEVICE;
     return FFP_OK;
 }
 
@@ -473,6 +570,12 @@ void Server::loop()
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
         bool progress = false;
+        if (!deferred_.empty()) reap_deferred();
+        {
+            const size_t before = done_q_.size();
+            expire_queued(now_s());
+            if (done_q_.size() != before) progress = true;
+        }
         // completions, part by part (of enqueued units)
         for (auto it = running_.begin(); it != running_.end();) {
             Unit& u = *it;
@@ -618,6 +721,11 @@ int ffp_server_fetch(ffp_server* s, uint64_t ticket, uint32_t* dst, int64_t ldd,
                      void* stream)
 {
     return s ? s->impl->fetch(ticket, dst, ldd, info_dst, stream) : FFP_EINVAL;
+}
+
+int ffp_server_cancel(ffp_server* s, uint64_t ticket)
+{
+    return s ? s->impl->cancel(ticket) : FFP_EINVAL;
 }
 
 int ffp_server_stats(ffp_server* s, ffp_serve_stats* out)

@@ -32,6 +32,8 @@ struct ServeReq {
     double t_submit = 0, t_admit = 0, t_done = 0;
     int status = FFP_OK;
     bool released = false;
+    double deadline = 0;     // steady-clock time after which a queued request times out (0: none)
+    void* fetch_ev = nullptr; // real device: hipEvent_t recorded after the last fetch's copies
 };
 
 // One batch of a unit: its requests complete together.
@@ -84,6 +86,7 @@ public:
     void finish_part(UnitPart& part, int status);
     int poll(uint64_t* tickets, int max, double timeout_s, int* count);
     int fetch(uint64_t ticket, uint32_t* dst, int64_t ldd, int64_t* info_dst, void* stream);
+    int cancel(uint64_t ticket);
     int stats(ffp_serve_stats* out);
 
 private:
@@ -91,6 +94,9 @@ private:
     void launcher(int s);
     bool arena_alloc(size_t bytes, size_t* off);
     void arena_free(size_t off, size_t bytes);
+    void expire_queued(double now);
+    void reap_deferred();
+    void fail_queued(ServeReq& q, int status, double now);
 
     DeviceIface* dev_;
     size_t budget_;
@@ -108,6 +114,15 @@ private:
     std::list<Unit> running_;              // admitted units (stable addresses)
     std::vector<char> stream_busy_;
     std::vector<std::pair<size_t, size_t>> free_;   // (offset, size), sorted
+    // released results whose memory a pending fetch copy still reads:
+    // (offset, bytes, event recorded after the copy)
+    struct Deferred {
+        size_t off, bytes;
+        void* ev;
+    };
+    std::vector<Deferred> deferred_;
+    int64_t n_deadlines_ = 0;              // queued requests with a deadline
+    double next_expiry_check_ = 0;
     size_t used_ = 0, peak_used_ = 0;
     int inflight_ = 0, peak_inflight_ = 0;
     int64_t units_ = 0, batched_jobs_ = 0, max_batch_ = 0, overlap_units_ = 0;

@@ -21,6 +21,8 @@ FFP_EDTYPE = -3
 FFP_ENOMEM = -4
 FFP_EDEVICE = -5
 FFP_EUNSUPPORTED = -6
+FFP_ECANCELED = -7
+FFP_ETIMEDOUT = -8
 
 FFP_U32 = 0
 FFP_I8_CENTERED = 1
@@ -65,7 +67,7 @@ class ffp_ldlt_job(ctypes.Structure):
 class ffp_request(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
                 ("p", ctypes.c_uint32), ("alpha", ctypes.c_uint32), ("A", ctypes.c_void_p),
-                ("lda", ctypes.c_int64)]
+                ("lda", ctypes.c_int64), ("timeout_s", ctypes.c_double)]
 
 
 class ffp_result(ctypes.Structure):
@@ -146,6 +148,7 @@ def lib():
             "ffp_server_stats": (c_int, [P, P]),
             "ffp_server_poll": (c_int, [P, P, c_int, ctypes.c_double, P]),
             "ffp_server_fetch": (c_int, [P, ctypes.c_uint64, P, i64, P, P]),
+            "ffp_server_cancel": (c_int, [P, ctypes.c_uint64]),
             "ffp_server_destroy": (c_int, [P]),
             "ffp_graph_syrk_batched": (c_int, [c_int, P, c_uint, P, P]),
             "ffp_graph_ldlt_batched": (c_int, [c_int, P, P, P]),
@@ -489,18 +492,24 @@ class Server:
             st = lib().ffp_server_create(hbm_budget, max_inflight, nstreams, ctypes.byref(self._h))
         _check(st, "ffp_server_create")
 
-    def submit_syrk(self, A, p, alpha=1, n=None, k=None, lda=None) -> int:
+    def submit_syrk(self, A, p, alpha=1, n=None, k=None, lda=None, timeout_s=0.0) -> int:
         n = A.shape[0] if n is None else n
         k = A.shape[1] if k is None else k
         lda = A.stride(0) if lda is None else lda
-        r = ffp_request(kind=FFP_REQ_SYRK, n=n, k=k, p=p, alpha=alpha, A=_ptr(A), lda=lda)
+        r = ffp_request(kind=FFP_REQ_SYRK, n=n, k=k, p=p, alpha=alpha, A=_ptr(A), lda=lda,
+                        timeout_s=timeout_s)
         return self._submit(r)
 
-    def submit_ldlt(self, S, p, n=None, lds=None) -> int:
+    def submit_ldlt(self, S, p, n=None, lds=None, timeout_s=0.0) -> int:
         n = S.shape[0] if n is None else n
         lds = S.stride(0) if lds is None else lds
-        r = ffp_request(kind=FFP_REQ_LDLT, n=n, k=n, p=p, alpha=0, A=_ptr(S), lda=lds)
+        r = ffp_request(kind=FFP_REQ_LDLT, n=n, k=n, p=p, alpha=0, A=_ptr(S), lda=lds,
+                        timeout_s=timeout_s)
         return self._submit(r)
+
+    def cancel(self, ticket: int):
+        """Cancels a still-queued request (FfpError if it was already admitted)."""
+        _check(lib().ffp_server_cancel(self._h, ticket), "cancel")
 
     def _submit(self, r) -> int:
         t = ctypes.c_uint64()

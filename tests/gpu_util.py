@@ -5,6 +5,7 @@ import ctypes
 import numpy as np
 
 from paper_2001_04109_amd import ffp
+from paper_2001_04109_amd.storage import centred_i8, limbs  # noqa: F401 (re-exported for the tests)
 
 
 def dev():
@@ -19,17 +20,6 @@ def to_dev_u32(A: np.ndarray):
 
 def from_dev_u32(T) -> np.ndarray:
     return T.cpu().numpy().view(np.uint32)
-
-
-def centred_i8(A: np.ndarray, p: int) -> np.ndarray:
-    return np.where(A > (p - 1) // 2, A.astype(np.int64) - p, A).astype(np.int8)
-
-
-def limbs(A: np.ndarray, p: int) -> np.ndarray:
-    x = np.where(A <= 32639, A.astype(np.int64), A.astype(np.int64) - p)
-    lo = ((x + 128) & 255) - 128
-    hi = (x - lo) >> 8
-    return np.stack([hi.astype(np.int8), lo.astype(np.int8)])
 
 
 def set_kblk(k: int):

@@ -166,3 +166,67 @@ def test_completion_queue_returns_each_ticket_once():
         assert st.completed == len(reqs)
     finally:
         srv.close()
+
+
+def _one_result_server():
+    """A server whose budget holds one 256 x 256 result and its workspace."""
+    n = 256
+    budget = n * n * 4 + ffp.ffp_workspace_bytes(n, n, 65537) + 4096
+    srv = ffp.Server(budget, max_inflight=8, nstreams=2, simulated=True, ns_per_op=0.0,
+                     launch_us=1.0)
+    req = ffp.ffp_request(kind=ffp.FFP_REQ_SYRK, n=n, k=n, p=65537, alpha=1, A=_fake_ptr(), lda=n)
+    return srv, req
+
+
+def _wait_state(srv, t, state, timeout=5.0):
+    deadline = time.time() + timeout
+    while srv.status(t).state != state and time.time() < deadline:
+        time.sleep(0.001)
+    return srv.status(t).state
+
+
+def test_cancel_queued_request():
+    srv, req = _one_result_server()
+    try:
+        t1 = srv._submit(req)
+        t2 = srv._submit(req)
+        assert _wait_state(srv, t1, ffp.FFP_STATE_DONE) == ffp.FFP_STATE_DONE
+        assert srv.status(t2).state == ffp.FFP_STATE_QUEUED     # no room while t1 is held
+        srv.cancel(t2)
+        assert srv.status(t2).state == ffp.FFP_ECANCELED
+        assert sorted(srv.poll(8, 0.05)) == [t1, t2]
+        with pytest.raises(ffp.FfpError) as e:                   # done work is not cancelled
+            srv.cancel(t1)
+        assert e.value.status == ffp.FFP_EINVAL
+        srv.release(t2)                                          # holds no memory: a no-op
+        srv.release(t1)
+        t3 = srv._submit(req)                                    # the budget is whole again
+        assert _wait_state(srv, t3, ffp.FFP_STATE_DONE) == ffp.FFP_STATE_DONE
+    finally:
+        srv.close()
+
+
+def test_deadline_fails_request_still_queued():
+    srv, req = _one_result_server()
+    try:
+        t1 = srv._submit(req)
+        assert _wait_state(srv, t1, ffp.FFP_STATE_DONE) == ffp.FFP_STATE_DONE
+        timed = ffp.ffp_request(kind=req.kind, n=req.n, k=req.k, p=req.p, alpha=1, A=req.A,
+                                lda=req.lda, timeout_s=0.02)
+        t2 = srv._submit(timed)
+        t3 = srv._submit(req)                                    # no deadline: waits
+        assert _wait_state(srv, t2, ffp.FFP_ETIMEDOUT) == ffp.FFP_ETIMEDOUT
+        assert srv.status(t3).state == ffp.FFP_STATE_QUEUED
+        srv.release(t1)
+        assert _wait_state(srv, t3, ffp.FFP_STATE_DONE) == ffp.FFP_STATE_DONE
+        # a deadline that is met changes nothing
+        srv.release(t3)
+        t4 = srv._submit(timed)
+        assert _wait_state(srv, t4, ffp.FFP_STATE_DONE) == ffp.FFP_STATE_DONE
+        bad = ffp.ffp_request(kind=req.kind, n=req.n, k=req.k, p=req.p, alpha=1, A=req.A,
+                              lda=req.lda, timeout_s=-1.0)
+        with pytest.raises(ffp.FfpError) as e:
+            srv._submit(bad)
+        assert e.value.status == ffp.FFP_EINVAL
+    finally:
+        srv.close()
