@@ -109,6 +109,23 @@ int fsyrk_modp(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int
                uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, unsigned flags,
                void* stream);
 
+/* fsyrk_modp for callers that cannot allocate device memory: code under HIP
+ * stream capture, serving loops and harnesses that forbid hipMalloc.  Same
+ * arguments, result and errors as fsyrk_modp; it allocates no device or
+ * pinned host memory.  Its workspace is a static device buffer of
+ * ffp_noalloc_scratch_bytes() (64 MiB) that every device the library runs
+ * on holds until the process ends; a shape whose workspace
+ * (ffp_workspace_bytes) exceeds it is rejected with FFP_ENOMEM before
+ * anything is enqueued.  Grouped product launches carry their task tables
+ * in the kernel arguments (several launches where fsyrk_modp would make
+ * one).  All calls on one device share that device's buffer, which keeps
+ * the last call's contents: calls that may overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller. */
+int fsyrk_modp_noalloc(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int a_dtype,
+                       uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, unsigned flags,
+                       void* stream);
+size_t ffp_noalloc_scratch_bytes(void);
+
 /* C <- (alpha * A * B^T + beta * C) mod p, the general products P3 and P4
  * of Algorithm 2 as a stand-alone call.  A is m x k, B is n x k, C is
  * m x n, all uint32 residues; 2 < p < 2^25.  FP64 matrix cores with

@@ -396,13 +396,13 @@ hipError_t launch_products(int cls, ProdTask* tasks, int ntasks, ProdTask* dev_t
 
 int g_leveled = 1;
 
-int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s)
+int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s, bool no_alloc)
 {
     if (g_leveled) {
         std::vector<SchedItem> items;
         items.reserve(pl.ops.size());
         for (const Op& o : pl.ops) items.push_back(SchedItem{&pl, &o, a, c, ws, 0});
-        return run_leveled(items, s);
+        return run_leveled(items, s, no_alloc);
     }
     for (const Op& o : pl.ops) {
         int st = execute_op(pl, o, a, c, ws, s);
@@ -612,7 +612,7 @@ std::vector<int> schedule_levels(const std::vector<SchedItem>& items)
     return level;
 }
 
-int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
+int run_leveled(const std::vector<SchedItem>& items, hipStream_t s, bool no_alloc)
 {
     const size_t n = items.size();
     if (n == 0) return FFP_OK;
@@ -631,6 +631,7 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
             if (o.kind == OP_SYRK || o.kind == OP_GEMM) ++np[o.cls];
             else if (o.kind == OP_PACK) ++nk[o.src_cls * kNumCls + o.cls];
         }
+        if (no_alloc) continue;
         for (size_t q : np)
             if (q > (size_t)kInlineTasks) meta += (size_t)rup256((int64_t)(q * sizeof(ProdTask)));
         for (size_t q : nk) if (q > 1) meta += (size_t)rup256((int64_t)(q * sizeof(PackDesc)));
@@ -668,10 +669,14 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
                 continue;
             }
             // up to kInlineTasks tasks travel in the kernel arguments
+            std::vector<ProdTask> own;
             ProdTask inl[kInlineTasks];
             ProdTask* tasks = inl;
             ProdTask* dtasks = nullptr;
-            if (g.size() > (size_t)kInlineTasks) {
+            if (no_alloc && g.size() > (size_t)kInlineTasks) {
+                own.resize(g.size());
+                tasks = own.data();
+            } else if (g.size() > (size_t)kInlineTasks) {
                 tasks = (ProdTask*)(host_meta + moff);
                 dtasks = (ProdTask*)(dev_meta + moff);
                 moff += (size_t)rup256((int64_t)(g.size() * sizeof(ProdTask)));
@@ -697,13 +702,29 @@ int run_leveled(const std::vector<SchedItem>& items, hipStream_t s)
             if (prof) prof_begin(s, &e0);
             {
                 TileHint hint(tile);
-                if (launch_products(cls, tasks, nt, dtasks, s) != hipSuccess) status = FFP_EDEVICE;
+                if (no_alloc) {
+                    // longest first, kInlineTasks per launch
+                    for (int t0 = 0; t0 < nt && status == FFP_OK; t0 += kInlineTasks)
+                        if (launch_products(cls, tasks + t0, std::min(kInlineTasks, nt - t0), nullptr, s) !=
+                            hipSuccess)
+                            status = FFP_EDEVICE;
+                } else if (launch_products(cls, tasks, nt, dtasks, s) != hipSuccess) {
+                    status = FFP_EDEVICE;
+                }
             }
             if (prof) prof_end(s, e0, flops, cls);
         }
         for (int q = 0; q < kNumCls * kNumCls && status == FFP_OK; ++q) {
             const auto& g = packs[q];
             if (g.empty()) continue;
+            if (no_alloc) {
+                for (size_t j : g) {
+                    const SchedItem& it = items[j];
+                    status = execute_op(*it.pl, *it.op, it.a, it.c, it.ws, s);
+                    if (status != FFP_OK) break;
+                }
+                continue;
+            }
             if (g.size() == 1) {
                 const SchedItem& it = items[g[0]];
                 status = execute_op(*it.pl, *it.op, it.a, it.c, it.ws, s);

@@ -72,7 +72,7 @@ int capture_point(hipStream_t s);
 
 // Enqueues every op of the plan on stream s.  a, c: caller buffers; ws:
 // workspace of at least pl.ws_bytes.
-int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s);
+int execute_plan(const Plan& pl, const void* a, void* c, void* ws, hipStream_t s, bool no_alloc = false);
 
 int execute_op(const Plan& pl, const Op& o, const void* a, void* c, void* ws, hipStream_t s);
 
@@ -93,7 +93,11 @@ struct SchedItem {
     void* ws;
     int job;
 };
-int run_leveled(const std::vector<SchedItem>& items, hipStream_t s);
+// no_alloc: acquire no staging area (no pinned or device allocation): a
+// level's product group of more than kInlineTasks tasks runs as several
+// launches of at most kInlineTasks tasks (tables in the kernel arguments),
+// and packs run one by one.
+int run_leveled(const std::vector<SchedItem>& items, hipStream_t s, bool no_alloc = false);
 // The level of every item (host only; also used by tests through the C ABI).
 std::vector<int> schedule_levels(const std::vector<SchedItem>& items);
 // 1: execute_plan runs the level scheduler (default); 0: ops in program order.

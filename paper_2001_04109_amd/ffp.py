@@ -121,6 +121,8 @@ def lib():
                                       ctypes.c_int, ctypes.c_uint)
         sigs = {
             "fsyrk_modp": (c_int, [i64, i64, u32, P, i64, c_int, u32, u32, P, i64, c_uint, P]),
+            "fsyrk_modp_noalloc": (c_int, [i64, i64, u32, P, i64, c_int, u32, u32, P, i64, c_uint, P]),
+            "ffp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
             "fgemm_modp": (c_int, [i64, i64, i64, u32, P, i64, P, i64, u32, u32, P, i64, P]),
             "fldlt_modp": (c_int, [i64, u32, P, i64, P, P]),
             "ffp_workspace_bytes": (ctypes.c_size_t, [i64, i64, u32, c_int, c_uint]),
@@ -208,6 +210,15 @@ def _stream(stream):
 def fsyrk_modp(n, k, p, A, lda, a_dtype, alpha, beta, C, ldc, flags=0, stream=None):
     return _check(lib().fsyrk_modp(n, k, p, _ptr(A), lda, a_dtype, alpha, beta, _ptr(C), ldc,
                                    flags, _stream(stream)), "fsyrk_modp")
+
+
+def fsyrk_modp_noalloc(n, k, p, A, lda, a_dtype, alpha, beta, C, ldc, flags=0, stream=None):
+    return _check(lib().fsyrk_modp_noalloc(n, k, p, _ptr(A), lda, a_dtype, alpha, beta, _ptr(C), ldc,
+                                           flags, _stream(stream)), "fsyrk_modp_noalloc")
+
+
+def ffp_noalloc_scratch_bytes() -> int:
+    return lib().ffp_noalloc_scratch_bytes()
 
 
 def fgemm_modp(m, n, k, p, A, lda, B, ldb, alpha, beta, C, ldc, stream=None):
