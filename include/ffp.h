@@ -52,18 +52,20 @@ extern "C" {
 #define FFP_ETIMEDOUT    (-8) /* a served request was still queued at its deadline */
 
 /* ---- operand storage of A ------------------------------------------- */
-/* uint32 residues in [0,p).  Any prime 2 < p < 2^25 is accepted.  The base
- * path is chosen from p: p <= 251 packs to centered int8 (int8 matrix
- * cores, int32 accumulation); p <= 65521 packs to two int8 limbs; larger p
- * runs on FP64 matrix cores with delayed reduction, exact while every
- * partial sum stays below 2^53. */
+/* uint32 residues in [0,p).  Any prime 2 <= p <= 94906249 is accepted (the
+ * largest prime with p (p-1) < 2^53).  The base path is chosen from p:
+ * 3 <= p <= 251 packs to centered int8 (int8 matrix cores, int32
+ * accumulation); p <= 65521 packs to two int8 limbs; p = 2 and larger p run
+ * on FP64 matrix cores with delayed reduction, exact while every partial sum
+ * stays below 2^53 (for p >= 2^25 the accumulators are reduced after every
+ * 4-column matrix-core step). */
 #define FFP_U32          0
-/* int8 residues in [-(p-1)/2, (p-1)/2]; requires p <= 251. */
+/* int8 residues in [-(p-1)/2, (p-1)/2]; requires 3 <= p <= 251. */
 #define FFP_I8_CENTERED  1
 /* Two int8 planes of the same shape and leading dimension: the value of an
  * entry is 256*hi + lo, and must lie in [-32896, 32639] and be congruent to
  * the residue.  `A` points to the hi plane; the lo plane starts at
- * (const int8_t*)A + n*lda.  Requires p <= 65521. */
+ * (const int8_t*)A + n*lda.  Requires 3 <= p <= 65521. */
 #define FFP_I8_LIMB2     2
 
 /* ---- flags ----------------------------------------------------------- */
@@ -128,8 +130,9 @@ size_t ffp_noalloc_scratch_bytes(void);
 
 /* C <- (alpha * A * B^T + beta * C) mod p, the general products P3 and P4
  * of Algorithm 2 as a stand-alone call.  A is m x k, B is n x k, C is
- * m x n, all uint32 residues; 2 < p < 2^25.  FP64 matrix cores with
- * delayed reduction.  Errors: FFP_EINVAL, FFP_EPRIME, FFP_EDEVICE. */
+ * m x n, all uint32 residues; p a prime with 2 <= p <= 94906249.  FP64
+ * matrix cores with delayed reduction.  Errors: FFP_EINVAL, FFP_EPRIME,
+ * FFP_EDEVICE. */
 int fgemm_modp(int64_t m, int64_t n, int64_t k, uint32_t p, const uint32_t* A, int64_t lda,
                const uint32_t* B, int64_t ldb, uint32_t alpha, uint32_t beta, uint32_t* C,
                int64_t ldc, void* stream);
@@ -138,7 +141,7 @@ int fgemm_modp(int64_t m, int64_t n, int64_t k, uint32_t p, const uint32_t* A, i
  * (the symmetric factorisation of Section 5, whose Schur-complement
  * updates C <- C - A*D*A^T run as Algorithm 5 followed by fsyrk_modp with
  * alpha = p-1, beta = 1).
- *   n        order of S, n >= 0;  p an odd prime < 2^25.
+ *   n        order of S, n >= 0;  p an odd prime <= 94906249.
  *   S, lds   device pointer; on entry the lower triangle holds the
  *            symmetric matrix (residues in [0,p)); on exit the strict lower
  *            triangle holds the unit lower triangular L and the diagonal
@@ -150,7 +153,7 @@ int fgemm_modp(int64_t m, int64_t n, int64_t k, uint32_t p, const uint32_t* A, i
 int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, void* stream);
 
 /* Device workspace fldlt_modp needs for order n (bytes), for admission
- * control; 0 if p is not an odd prime below 2^25. */
+ * control; 0 if p is not an odd prime <= 94906249. */
 size_t ffp_ldlt_workspace_bytes(int64_t n, uint32_t p);
 
 /* One factorisation of fldlt_modp_batched (host struct; device pointers). */
@@ -181,7 +184,7 @@ size_t ffp_workspace_bytes(int64_t n, int64_t k, uint32_t p, int a_dtype, unsign
 /* One independent fsyrk_modp job of a batch. */
 typedef struct ffp_job {
     int64_t n, k;       /* A is n x k, C is n x n */
-    uint32_t p;         /* prime, 2 < p < 2^25 */
+    uint32_t p;         /* prime, 2 <= p <= 94906249 */
     uint32_t alpha, beta;
     int32_t a_dtype;    /* FFP_U32 only, in this version */
     const void* A;      /* device pointer */
@@ -296,7 +299,7 @@ void ffp_graph_destroy(ffp_graph g);
 typedef struct ffp_request {
     int32_t kind;          /* FFP_REQ_SYRK or FFP_REQ_LDLT */
     int64_t n, k;          /* SYRK: A is n x k; LDLT: A is n x n and k is ignored */
-    uint32_t p;            /* prime, 2 < p < 2^25 (LDLT: odd) */
+    uint32_t p;            /* prime, 2 <= p <= 94906249 (LDLT: odd) */
     uint32_t alpha;        /* SYRK scale, residue in [0,p) */
     const void* A;         /* device pointer, uint32 residues (FFP_U32 storage) */
     int64_t lda;

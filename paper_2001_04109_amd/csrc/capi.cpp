@@ -44,7 +44,7 @@ int fgemm_modp(int64_t m, int64_t n, int64_t k, uint32_t p, const uint32_t* A, i
                int64_t ldc, void* stream)
 {
     if (m < 0 || n < 0 || k < 0) return FFP_EINVAL;
-    if (p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return FFP_EPRIME;
+    if (!supported_prime(p)) return FFP_EPRIME;
     if (alpha >= p || beta >= p) return FFP_EINVAL;
     if (m > 0 && n > 0 && (C == nullptr || ldc < n)) return FFP_EINVAL;
     if (m > 0 && n > 0 && k > 0 && (A == nullptr || B == nullptr || lda < k || ldb < k))
@@ -268,7 +268,7 @@ const char* ffp_debug_variant_name(int variant)
 int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, void* stream)
 {
     if (n < 0 || info == nullptr) return FFP_EINVAL;
-    if (p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return FFP_EPRIME;
+    if (p < 3 || !supported_prime(p)) return FFP_EPRIME;
     if (n > 0 && (S == nullptr || lds < n)) return FFP_EINVAL;
     if (n > (int64_t)1 << 30) return FFP_EINVAL;
     return ldlt_run(n, p, S, lds, info, (hipStream_t)stream);
@@ -282,7 +282,7 @@ int fldlt_modp_batched(int njobs, const ffp_ldlt_job* jobs, void* stream)
     for (int j = 0; j < njobs; ++j) {
         const ffp_ldlt_job& b = jobs[j];
         if (b.n < 0 || b.info == nullptr || b.n > ((int64_t)1 << 30)) return FFP_EINVAL;
-        if (b.p < 3 || b.p >= (1u << 25) || !is_prime_u32(b.p)) return FFP_EPRIME;
+        if (b.p < 3 || !supported_prime(b.p)) return FFP_EPRIME;
         if (b.n > 0 && (b.S == nullptr || b.lds < b.n)) return FFP_EINVAL;
         off[j] = total;
         total += (ldlt_workspace_bytes(b.n, b.p, b.lds) + 255) / 256 * 256;
@@ -302,7 +302,7 @@ int fldlt_modp_batched(int njobs, const ffp_ldlt_job* jobs, void* stream)
 
 size_t ffp_ldlt_workspace_bytes(int64_t n, uint32_t p)
 {
-    if (n < 0 || p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return 0;
+    if (n < 0 || p < 3 || !supported_prime(p)) return 0;
     return ldlt_workspace_bytes(n, p, n);
 }
 

@@ -137,13 +137,19 @@ bool nrsyf(uint64_t p, uint64_t alpha, uint64_t beta, uint64_t Y[4])
     return true;
 }
 
+bool supported_prime(uint64_t p) { return p >= 2 && p <= kMaxPrime && is_prime_u32(p); }
+
 bool make_field_plan(uint32_t p, FieldPlan* out)
 {
-    if (p < 3 || !is_prime_u32(p)) return false;
+    if (p < 2 || !is_prime_u32(p)) return false;
     FieldPlan f;
     f.p = p;
     f.pinv = 1.0 / (double)p;
-    if (p % 4 == 1) {
+    if (p == 2) {              // 1^2 + 0^2 = 1 = -1: Y = I
+        f.ya = 1;
+        f.yb = 0;
+        f.ycost = 1;
+    } else if (p % 4 == 1) {
         f.ya = (uint32_t)sqrt_mod(p - 1, p);
         f.yb = 0;
         f.ycost = 1;

@@ -32,6 +32,15 @@ struct FieldPlan {
     int ycost = 0;            // y of Theorem 4.1
     double pinv = 0.0;        // 1/p rounded to nearest
 };
+// p = 2: a = 1, b = 0 (1 = -1 in characteristic 2, Proposition 3.3).
 bool make_field_plan(uint32_t p, FieldPlan* out);
+
+// Largest prime p with p (p - 1) < 2^53: the FP64 base products stay exact
+// with a reduction after every 4-column matrix-core step (a reduced
+// accumulator, below p, plus four products of centred residues, each at
+// most ((p-1)/2)^2), and every product of two residues is exact in a double.
+constexpr uint32_t kMaxPrime = 94906249u;
+// Moduli the product paths accept: primes 2 <= p <= kMaxPrime.
+bool supported_prime(uint64_t p);
 
 }  // namespace ffp

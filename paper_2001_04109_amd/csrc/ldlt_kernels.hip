@@ -61,8 +61,10 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
     // their residue in [-p, 2p) (one quotient estimate, no correction):
     // a M[i][j] - M[i][k] M[j][k] then stays below 8 p^2 < 2^53, so every
     // product is exact; entries are brought into [0, p) at the end, the
-    // pivot at every step for the zero test.
+    // pivot at every step for the zero test.  For p >= 2^25 every entry is
+    // brought into [0, p) after each update instead.
     const int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
+    const bool big = p >= (1u << 25);
     double m[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -103,6 +105,9 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
                     if (r0 + x > k && c0 + y > k) {
                         const double v = fma(a, m[x][y], -(ci[x] * cj[y]));   // |v| < 8 p^2
                         m[x][y] = fma(-floor(v * pinv), pd, v);               // in [-p, 2p)
+                        // p >= 2^25: 8 p^2 passes 2^53, so entries stay in
+                        // [0, p) (then |v| < p^2 < 2^53)
+                        if (big) m[x][y] = canon(m[x][y], pd);
                     }
             // owners of column k + 1 publish it for the next step
             if (kk < 3) {
@@ -158,8 +163,12 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
         li[b0 + c][b0 + c] = 1u;
         for (int i = c + 1; i < 8; ++i) {
             double acc = 0.0;
-            for (int t = c; t < i; ++t) acc = fma((double)lo(b0 + i, b0 + t), (double)li[b0 + t][b0 + c], acc);
-            const uint32_t v = mod53(acc, p, pinv);   // at most 7 terms
+            int cnt = 1;
+            for (int t = c; t < i; ++t) {   // at most 7 terms
+                acc = fma((double)lo(b0 + i, b0 + t), (double)li[b0 + t][b0 + c], acc);
+                if (++cnt == kb) { acc = (double)mod53(acc, p, pinv); cnt = 1; }
+            }
+            const uint32_t v = mod53(acc, p, pinv);
             li[b0 + i][b0 + c] = v == 0u ? 0u : p - v;
         }
     }
@@ -171,7 +180,7 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
             const int q = e / (b * b), rem = e - q * b * b, i = rem / b, j = rem - i * b;
             const int a0 = q * 2 * b, c0 = a0 + b;
             double acc = 0.0;
-            int cnt = 0;
+            int cnt = 1;   // slots of a block: the (reduced) accumulator and kb - 1 products
             for (int t = j; t < b; ++t) {
                 acc = fma((double)lo(c0 + i, a0 + t), (double)li[a0 + t][a0 + j], acc);
                 if (++cnt == kb) { acc = (double)mod53(acc, p, pinv); cnt = 1; }
@@ -184,7 +193,7 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
             const int q = e / (b * b), rem = e - q * b * b, i = rem / b, j = rem - i * b;
             const int a0 = q * 2 * b, c0 = a0 + b;
             double acc = 0.0;
-            int cnt = 0;
+            int cnt = 1;
             for (int t = 0; t <= i; ++t) {
                 acc = fma((double)li[c0 + i][c0 + t], (double)tq[c0 + t][a0 + j], acc);
                 if (++cnt == kb) { acc = (double)mod53(acc, p, pinv); cnt = 1; }
@@ -234,7 +243,7 @@ __device__ __forceinline__ void trsm_inv_body(Fp f, int kb, int64_t nrows, int n
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    int cnt = 0;
+    int cnt = 1;   // slots of a block: the (reduced) accumulator and kb - 1 products
     for (int t = 0; t < NB; ++t) {
         double xv[4], lv[4];
 #pragma unroll
@@ -459,9 +468,12 @@ __global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n
 
 int ldlt_dot_block(uint32_t p)
 {
+    // kb slots per block: the accumulator (a residue below p after each
+    // reduction, 0 at the start) and kb - 1 products of two residues, each at
+    // most (p-1)^2; the sum stays below 2^53 when (kb - 1)(p-1)^2 + p - 1 does.
     const double pm = (double)(p - 1);
-    const double kb = floor(9007199254740992.0 / (pm * pm + 1.0)) - 1.0;
-    return kb > 64.0 ? 64 : (int)kb;
+    const double kb = 1.0 + floor((9007199254740991.0 - pm) / (pm * pm + 1.0));
+    return kb > 64.0 ? 64 : (kb < 2.0 ? 2 : (int)kb);
 }
 
 int ldlt_blocks(int kind, LdltDesc* d)

@@ -1,4 +1,5 @@
-// Device arithmetic on residues in [0,p) for primes p < 2^25.
+// Device arithmetic on residues in [0,p) for primes p with p^2 < 2^53
+// (p <= 94906249): a product of two residues is exact in a double.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -28,7 +29,7 @@ __device__ inline uint32_t mod53(double x, uint32_t p, double pinv)
     return (uint32_t)r;
 }
 
-// a*b mod p: the product of two residues is below 2^50, exact in a double.
+// a*b mod p: the product of two residues is below p^2 < 2^53, exact in a double.
 __device__ inline uint32_t mul_m(uint32_t a, uint32_t b, uint32_t p, double pinv)
 {
     return mod53((double)a * (double)b, p, pinv);

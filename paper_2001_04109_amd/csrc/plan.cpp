@@ -304,9 +304,10 @@ int make_syrk_request(int64_t n, int64_t k, uint32_t p, const void* A, int64_t l
 {
     if (n < 0 || k < 0) return FFP_EINVAL;
     if (!valid_dtype_(a_dtype)) return FFP_EDTYPE;
-    if (p < 3 || p >= (1u << 25) || !is_prime_u32(p)) return FFP_EPRIME;
-    if (a_dtype == FFP_I8_CENTERED && p > 251) return FFP_EDTYPE;
-    if (a_dtype == FFP_I8_LIMB2 && p > 65521) return FFP_EDTYPE;
+    if (!supported_prime(p)) return FFP_EPRIME;
+    // the int8 storages hold odd-p residues (centred, or two limbs)
+    if (a_dtype == FFP_I8_CENTERED && (p > 251 || p == 2)) return FFP_EDTYPE;
+    if (a_dtype == FFP_I8_LIMB2 && (p > 65521 || p == 2)) return FFP_EDTYPE;
     if (alpha >= p || beta >= p) return FFP_EINVAL;
     if (n > 0 && (C == nullptr || ldc < n)) return FFP_EINVAL;
     if (n > 0 && k > 0 && (A == nullptr || lda < k)) return FFP_EINVAL;
@@ -339,6 +340,7 @@ int choose_class(uint32_t p, int a_cls, bool force_f64, bool force_limb3)
     if (a_cls == CLS_LIMB2) return CLS_LIMB2;
     if (force_f64) return CLS_F64;
     if (force_limb3) return CLS_LIMB3;
+    if (p == 2) return CLS_F64;     // residues 0, 1 (centred: 0, -1) on FP64 matrix cores
     if (p <= 251) return CLS_I8;
     if (p <= 65521) return CLS_LIMB2;
     return CLS_F64;
@@ -362,8 +364,7 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
 {
     if (rq.n < 0 || rq.k < 0) return FFP_EINVAL;
     Plan pl;
-    if (!make_field_plan(rq.p, &pl.field)) return FFP_EPRIME;
-    if (rq.p >= (1u << 25)) return FFP_EPRIME;
+    if (!supported_prime(rq.p) || !make_field_plan(rq.p, &pl.field)) return FFP_EPRIME;
     pl.cls = choose_class(rq.p, rq.a_cls, rq.force_f64, rq.force_limb3);
     if (pl.cls == CLS_I8 && rq.p > 251) return FFP_EDTYPE;
     if (pl.cls == CLS_LIMB2 && rq.p > 65521) return FFP_EDTYPE;

@@ -471,7 +471,20 @@ int64_t f64_kblk(uint32_t p)
     if (kb > (double)(1 << 30)) kb = (double)(1 << 30);
     int64_t k = (int64_t)kb;
     k -= k % 16;
+    // p above 2^25: fewer than 16 columns fit; the 64 x 64 tile then reduces
+    // after every 4-column matrix-core step (a reduced accumulator plus four
+    // centred products stays below p + (p-1)^2 < 2^53 for p <= kMaxPrime)
+    if (k < 16) k = 4;
     return k;
+}
+
+// Delayed-reduction block of a task for a kernel that reduces every `unit`
+// columns (16 or 32); blocks under 16 columns stay as they are (only the
+// 64 x 64 tile runs them).
+static int32_t task_kblk(uint32_t p, int unit)
+{
+    const int64_t kb = f64_kblk(p);
+    return kb < 16 ? (int32_t)kb : cap_kblk(kb, unit);
 }
 
 int g_f64_waves = 8;
@@ -484,7 +497,7 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
     int total = 0;
     for (int i = 0; i < ntasks; ++i) {
         ProdTask& t = tasks[i];
-        t.kblk = cap_kblk(f64_kblk(t.p), TILE == 128 ? BK2 : 16);
+        t.kblk = task_kblk(t.p, TILE == 128 ? BK2 : 16);
         t.tm = (t.m + TILE - 1) / TILE;
         t.tn = (t.n + TILE - 1) / TILE;
         t.tile0 = total;
@@ -537,7 +550,7 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
 
 bool prepare_f64_tile_task(ProdTask* t)
 {
-    t->kblk = cap_kblk(f64_kblk(t->p), 16);
+    t->kblk = task_kblk(t->p, 16);
     t->tm = (t->m + kF64TileM - 1) / kF64TileM;
     t->tn = (t->n + kF64TileN - 1) / kF64TileN;
     t->tile0 = 0;
@@ -559,6 +572,9 @@ hipError_t launch_products_f64(ProdTask* tasks, int ntasks, ProdTask* dev_task_b
     const int ov = g_tile_hint ? g_tile_hint : g_f64_tile_override;
     if (ov == 64) big = false;
     if (ov == 128) big = true;
+    // the 128 x 128 kernels reduce once per 32-column stage at most often
+    for (int i = 0; i < ntasks; ++i)
+        if (f64_kblk(tasks[i].p) < BK2) big = false;
     return big ? launch_f64_impl<128>(tasks, ntasks, dev_task_buf, s)
                : launch_f64_impl<64>(tasks, ntasks, dev_task_buf, s);
 }

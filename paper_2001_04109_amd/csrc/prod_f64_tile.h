@@ -78,10 +78,21 @@ __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
     // (one conversion per value; FP64 matrix instructions do not overlap
     // other vector instructions, so the centring would cost matrix time);
     // otherwise they are centred and the accumulators reduced every kblk.
+    // For p above 2^25 fewer than 16 columns fit one exact block (kblk < 16):
+    // the accumulators are then reduced after every 4-column step.
     const double pm1 = (double)(t.p - 1);
     const bool raw = (double)K * pm1 * pm1 < 9007199254740992.0 - 2.0 * pd;
-    auto kloop = [&](auto rawc) {
+    auto reduce_all = [&]() {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[i][j][e] = mod_f64(acc[i][j][e], pd, t.pinv);
+    };
+    auto kloop = [&](auto rawc, auto stepc) {
         constexpr bool RAW = decltype(rawc)::value;
+        constexpr bool STEP = decltype(stepc)::value;
         Loaded la[WM], lb[WN];
         int since_red = 0;
         for (int kk = 0; kk < K; kk += 16) {
@@ -102,27 +113,28 @@ __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
 #pragma unroll
                     for (int j = 0; j < WN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+                if constexpr (STEP) reduce_all();
             }
-            if constexpr (!RAW) {
+            if constexpr (!RAW && !STEP) {
                 since_red += 16;
                 if (since_red >= t.kblk && kk + 16 < K) {
                     since_red = 0;
-#pragma unroll
-                    for (int i = 0; i < WM; ++i)
-#pragma unroll
-                        for (int j = 0; j < WN; ++j)
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) acc[i][j][e] = mod_f64(acc[i][j][e], pd, t.pinv);
+                    reduce_all();
                 }
             }
         }
     };
-    if (raw) kloop(std::integral_constant<bool, true>{});
-    else kloop(std::integral_constant<bool, false>{});
+    using T_ = std::integral_constant<bool, true>;
+    using F_ = std::integral_constant<bool, false>;
+    if (raw) kloop(T_{}, F_{});
+    else if (t.kblk < 16) kloop(F_{}, T_{});
+    else kloop(F_{}, F_{});
 
     // Epilogue.  16x16 f64 MFMA result layout: element e of lane l is row
     // 4*e + l/16, column l%16.
     const double alpha = (double)t.alpha, beta = (double)t.beta;
+    // 2 (p-1)^2 >= 2^53 from p = 67108865 on; p >= 2^25 takes the split form
+    const bool big = t.p >= (1u << 25);
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
 #pragma unroll
@@ -135,8 +147,15 @@ __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
                 if (t.syrk && col > row) continue;
                 uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
                 double v = mod_f64(acc[i][j][e], pd, t.pinv);
-                double x = alpha * v;
-                if (t.beta != 0u) x += beta * (double)(*dst);
+                double x;
+                if (big) {
+                    // alpha v + beta c may pass 2^53: reduce each term
+                    x = mod_f64(alpha * v, pd, t.pinv);
+                    if (t.beta != 0u) x += mod_f64(beta * (double)(*dst), pd, t.pinv);
+                } else {
+                    x = alpha * v;
+                    if (t.beta != 0u) x += beta * (double)(*dst);
+                }
                 *dst = (uint32_t)mod_f64(x, pd, t.pinv);
             }
         }

@@ -349,7 +349,7 @@ int Server::submit(const ffp_request* r, uint64_t* ticket)
     if (!r || !ticket) return FFP_EINVAL;
     if (r->kind != FFP_REQ_SYRK && r->kind != FFP_REQ_LDLT) return FFP_EINVAL;
     if (r->n < 0 || r->n > ((int64_t)1 << 20)) return FFP_EINVAL;
-    if (r->p < 3 || r->p >= (1u << 25) || !is_prime_u32(r->p)) return FFP_EPRIME;
+    if (!supported_prime(r->p) || (r->kind == FFP_REQ_LDLT && r->p < 3)) return FFP_EPRIME;
     if (r->kind == FFP_REQ_SYRK) {
         if (r->k < 0 || r->alpha >= r->p) return FFP_EINVAL;
         if (r->n > 0 && r->k > 0 && (r->A == nullptr || r->lda < r->k)) return FFP_EINVAL;

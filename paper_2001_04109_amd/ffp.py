@@ -2,7 +2,7 @@
 
 Argument marshalling only: every step of the computation runs in the HIP
 library.  Device memory and streams come from PyTorch; matrices of residues
-are int32 tensors (values in [0, p) with p < 2^25), int8 tensors for the
+are int32 tensors (values in [0, p), p <= 94906249), int8 tensors for the
 int8 storages.  The functions raise FfpError on a negative status and
 ImportError/OSError when the library has not been built.
 """

@@ -69,8 +69,14 @@ def parse(text: str) -> Plan:
 
 
 def matmul_nt(X, Y):
-    """Exact X Y^T of non-negative int64 residues (test sizes keep sums < 2^63)."""
-    return X.astype(np.int64) @ Y.astype(np.int64).T
+    """Exact X Y^T of non-negative residues: int64 while every sum stays
+    below 2^63, Python integers otherwise (large p)."""
+    big = int(max(X.max(initial=0), Y.max(initial=0)))
+    if big * big * max(X.shape[1], 1) < 2**62:
+        return X.astype(np.int64) @ Y.astype(np.int64).T
+    if X.size == 0 or Y.size == 0:
+        return np.zeros((X.shape[0], Y.shape[0]), dtype=np.int64)
+    return X.astype(object) @ Y.astype(object).T
 
 
 class Sim:

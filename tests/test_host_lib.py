@@ -40,15 +40,16 @@ def test_strerror_and_version():
     assert "gfx950" in ffp.ffp_version()
 
 
-PRIMES = [3, 5, 7, 11, 13, 17, 251, 257, 65521, 65537, 131041, 131071, 1000003, 2147483647,
-          33554393]
+PRIMES = [2, 3, 5, 7, 11, 13, 17, 251, 257, 65521, 65537, 131041, 131071, 1000003, 33554393,
+          33554467, 94906249, 2147483647]
 
 
 @pytest.mark.parametrize("p", PRIMES)
 def test_field_plan_is_skew_orthogonal(p):
-    if p >= 2 ** 25:
-        pytest.skip("field plan limited to p < 2^25 by the GPU paths")
     a, b, y = ffp.field_info(p)
+    if p == 2:
+        assert (a, b, y) == (1, 0, 1)     # 1 = -1: Y = I
+        return
     assert (a * a + b * b) % p == p - 1
     if p % 4 == 1:
         assert b == 0 and y == 1
@@ -70,7 +71,7 @@ def test_field_plan_every_prime_below_2_13():
 
 def test_host_sqrt_matches_oracle():
     rng = np.random.default_rng(0)
-    for p in PRIMES:
+    for p in PRIMES[1:]:                  # odd primes
         for a in rng.integers(0, p, size=40):
             assert ffp.host_sqrt(int(a), p) == oracle.sqrt_mod(int(a), p), (a, p)
 

@@ -161,3 +161,28 @@ def test_k_zero_and_tiny():
     out = plansim.simulate(text, 65537, A.tobytes(), C0)
     low = np.tril(np.ones((4, 4), bool))
     assert np.array_equal(out[low], ((2 * C0.astype(np.int64)) % 65537)[low].astype(np.uint32))
+
+
+@pytest.mark.parametrize("p", [2, 33554467, 94906249])
+@pytest.mark.parametrize("depth", [0, 1, 2])
+@pytest.mark.parametrize("n,k", [(40, 72), (33, 21)])
+def test_extreme_primes(p, depth, n, k):
+    """The smallest prime (Y = I) and primes past 2^25 up to the largest with
+    p (p - 1) < 2^53: FP64 class, both placements, the accumulate form."""
+    plan = run_case(n, k, p, depth, seed=11)
+    assert plan.cls == plansim.CLS_F64
+    run_case(n, k, p, depth, seed=12, flags=ffp.FFP_LOW_MEMORY)
+    run_case(n, k, p, depth, alpha=p - 1, beta=1, seed=13)
+    if p > 2:
+        run_case(n, k, p, depth, alpha=(p - 1) // 3, beta=(p + 1) // 2, seed=14)
+
+
+def test_primes_outside_the_range_are_refused():
+    for p in (94906297, 2147483647, 4, 1, 0):   # 94906297: the next prime, p (p - 1) > 2^53
+        with pytest.raises(ffp.FfpError) as e:
+            ffp.plan_describe(8, 8, p, ffp.FFP_U32, 8, 8, 1, 0, 0)
+        assert e.value.status == ffp.FFP_EPRIME
+    for dtype in (ffp.FFP_I8_CENTERED, ffp.FFP_I8_LIMB2):    # int8 storages hold odd-p residues
+        with pytest.raises(ffp.FfpError) as e:
+            ffp.plan_describe(8, 8, 2, dtype, 16, 8, 1, 0, 0)
+        assert e.value.status == ffp.FFP_EDTYPE
