@@ -279,6 +279,103 @@ int oracle_syrkd(int64_t m, int64_t n, uint64_t p, const uint32_t* A, int64_t ld
     return ORACLE_OK;
 }
 
+/* C <- (alpha * A * B * A^T + beta * C) mod p, the Ensure of Algorithm 6
+ * (syrkd with block diagonal scaling, Section 5.2), full symmetric m x m
+ * result; A is m x n.  B is the symmetric tridiagonal n x n matrix with
+ * diagonal bdiag[0..n) and off-diagonal B[l][l+1] = B[l+1][l] = boff[l]
+ * (l < n-1); the block diagonal matrices of Algorithm 6 (scalar blocks and
+ * 2 x 2 blocks [[0, beta], [beta, gamma]]) are of this form.  The plain
+ * definition: C_ij = sum_l A_il (B A^T)_lj. */
+int oracle_syrkbd(int64_t m, int64_t n, uint64_t p, const uint32_t* A, int64_t lda,
+                  const uint32_t* bdiag, const uint32_t* boff, uint64_t alpha, uint64_t beta,
+                  uint32_t* C, int64_t ldc)
+{
+    if (m < 0 || n < 0 || p < 2 || (m > 0 && (lda < n || ldc < m))) return ORACLE_EINVAL;
+    alpha %= p; beta %= p;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t j = 0; j <= i; ++j) {
+            u128 s = 0;
+            for (int64_t l = 0; l < n; ++l) {
+                /* (B A^T)_lj = B_ll A_jl + B_l,l+1 A_j,l+1 + B_l,l-1 A_j,l-1 */
+                u128 t = (u128)bdiag[l] * A[j * lda + l];
+                if (l + 1 < n) t += (u128)boff[l] * A[j * lda + l + 1];
+                if (l > 0) t += (u128)boff[l - 1] * A[j * lda + l - 1];
+                s += (u128)A[i * lda + l] * (uint64_t)(t % p);
+            }
+            uint64_t prod = (uint64_t)(s % p);
+            u128 vij = (u128)alpha * prod + (u128)beta * C[i * ldc + j];
+            u128 vji = (u128)alpha * prod + (u128)beta * C[j * ldc + i];
+            C[i * ldc + j] = (uint32_t)(vij % p);
+            if (j != i) C[j * ldc + i] = (uint32_t)(vji % p);
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Products over F_p[i] = F_p[x]/(x^2 + 1), the field F_{p^2} for p = 3 mod 4 */
+/* (Section 3.1 "Over the complex field", Section 3.3, Section 4.1)        */
+/* ---------------------------------------------------------------------- */
+
+/* An element a + i b is held as two residues (a, b); a matrix as two
+ * planes, re at X and im at X + plane (same leading dimension). */
+
+/* C = A * A^H mod p with A^H the conjugate transpose, conj(a + i b) =
+ * a - i b (Section 3.3), full n x n result:
+ *   C_jl = sum_t (x_jt + i y_jt)(x_lt - i y_lt)
+ *        = sum_t (x_jt x_lt + y_jt y_lt) + i sum_t (y_jt x_lt - x_jt y_lt). */
+int oracle_herk(int64_t n, int64_t k, uint64_t p, const uint32_t* A, int64_t lda, int64_t aplane,
+                uint32_t* C, int64_t ldc, int64_t cplane)
+{
+    if (n < 0 || k < 0 || p < 2 || (n > 0 && (lda < k || ldc < n))) return ORACLE_EINVAL;
+    const uint32_t* X = A;
+    const uint32_t* Y = A + aplane;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t l = 0; l < n; ++l) {
+            u128 re = 0, im_pos = 0, im_neg = 0;
+            for (int64_t t = 0; t < k; ++t) {
+                const uint64_t xj = X[j * lda + t], yj = Y[j * lda + t];
+                const uint64_t xl = X[l * lda + t], yl = Y[l * lda + t];
+                re += (u128)(xj * xl) + (u128)(yj * yl);
+                im_pos += (u128)(yj * xl);
+                im_neg += (u128)(xj * yl);
+            }
+            C[j * ldc + l] = (uint32_t)(re % p);
+            C[cplane + j * ldc + l] = (uint32_t)(((uint64_t)(im_pos % p) + p - (uint64_t)(im_neg % p)) % p);
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* C = A * A^T mod p over F_p[i] (transposition without conjugation: the
+ * complex symmetric product of Section 3.1), full n x n result:
+ *   C_jl = sum_t (x_jt x_lt - y_jt y_lt) + i sum_t (x_jt y_lt + y_jt x_lt). */
+int oracle_zsyrk(int64_t n, int64_t k, uint64_t p, const uint32_t* A, int64_t lda, int64_t aplane,
+                 uint32_t* C, int64_t ldc, int64_t cplane)
+{
+    if (n < 0 || k < 0 || p < 2 || (n > 0 && (lda < k || ldc < n))) return ORACLE_EINVAL;
+    const uint32_t* X = A;
+    const uint32_t* Y = A + aplane;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t l = 0; l < n; ++l) {
+            u128 re_pos = 0, re_neg = 0, im = 0;
+            for (int64_t t = 0; t < k; ++t) {
+                const uint64_t xj = X[j * lda + t], yj = Y[j * lda + t];
+                const uint64_t xl = X[l * lda + t], yl = Y[l * lda + t];
+                re_pos += (u128)(xj * xl);
+                re_neg += (u128)(yj * yl);
+                im += (u128)(xj * yl) + (u128)(yj * xl);
+            }
+            C[j * ldc + l] = (uint32_t)(((uint64_t)(re_pos % p) + p - (uint64_t)(re_neg % p)) % p);
+            C[cplane + j * ldc + l] = (uint32_t)(im % p);
+        }
+    }
+    return ORACLE_OK;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Symmetric factorisation S = L * D * L^T (Section 5's use of the product) */
 /* ---------------------------------------------------------------------- */

@@ -56,6 +56,9 @@ def load():
             "oracle_syrk_ab": (c_int, [i64, i64, u64, P, i64, u64, u64, P, i64]),
             "oracle_syrkd": (c_int, [i64, i64, u64, P, i64, P, P, i64]),
             "oracle_ldlt": (c_int, [i64, u64, P, i64, P]),
+            "oracle_syrkbd": (c_int, [i64, i64, u64, P, i64, P, P, u64, u64, P, i64]),
+            "oracle_herk": (c_int, [i64, i64, u64, P, i64, i64, P, i64, i64]),
+            "oracle_zsyrk": (c_int, [i64, i64, u64, P, i64, i64, P, i64, i64]),
             "oracle_num_threads": (c_int, []),
         }
         for name, (res, args) in sigs.items():
@@ -208,6 +211,44 @@ def ldlt_packed(S, p: int):
     info = ctypes.c_int64(0)
     _check(load().oracle_ldlt(n, p, _ptr(S), max(n, 1), ctypes.byref(info)), "ldlt")
     return S, int(info.value)
+
+
+def syrkbd(A, bdiag, boff, p: int, alpha: int = 1, beta: int = 0, C=None) -> np.ndarray:
+    """alpha A B A^T + beta C mod p (full m x m) with B the symmetric
+    tridiagonal matrix of diagonal bdiag (n) and off-diagonal boff (n - 1)."""
+    A = _u32(A)
+    m, n = A.shape
+    bdiag = _u32(np.asarray(bdiag, dtype=np.uint32).reshape(n))
+    boff = _u32(np.zeros(1, dtype=np.uint32) if n <= 1 else np.asarray(boff, dtype=np.uint32).reshape(n - 1))
+    C = np.zeros((m, m), dtype=np.uint32) if C is None else _u32(C).copy()
+    _check(load().oracle_syrkbd(m, n, p, _ptr(A), max(n, 1), _ptr(bdiag), _ptr(boff), alpha, beta,
+                                _ptr(C), max(m, 1)), "syrkbd")
+    return C
+
+
+def _cplx(re, im):
+    re, im = _u32(re), _u32(im)
+    if re.shape != im.shape:
+        raise ValueError("real and imaginary planes differ in shape")
+    return np.ascontiguousarray(np.stack([re, im]))
+
+
+def herk(re, im, p: int):
+    """(Re, Im) of A A^H over F_p[i] (conj(a + ib) = a - ib), full n x n."""
+    A = _cplx(re, im)
+    _, n, k = A.shape
+    C = np.zeros((2, n, n), dtype=np.uint32)
+    _check(load().oracle_herk(n, k, p, _ptr(A), max(k, 1), n * k, _ptr(C), max(n, 1), n * n), "herk")
+    return C[0], C[1]
+
+
+def zsyrk(re, im, p: int):
+    """(Re, Im) of A A^T over F_p[i] (no conjugation), full n x n."""
+    A = _cplx(re, im)
+    _, n, k = A.shape
+    C = np.zeros((2, n, n), dtype=np.uint32)
+    _check(load().oracle_zsyrk(n, k, p, _ptr(A), max(k, 1), n * k, _ptr(C), max(n, 1), n * n), "zsyrk")
+    return C[0], C[1]
 
 
 def num_threads() -> int:

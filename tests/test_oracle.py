@@ -349,3 +349,162 @@ def test_costmodel_y_constants():
     assert costmodel.y_cost(65537) == 1
     assert costmodel.y_cost(251) == 2       # 251 = 3 mod 8
     assert costmodel.y_cost(131071) == 3    # 131071 = 7 mod 8
+
+
+# ------------------------------------------- Algorithm 6 (block diagonal B)
+
+def dense_tridiagonal(bdiag, boff):
+    n = len(bdiag)
+    B = np.zeros((n, n), dtype=object)
+    for l in range(n):
+        B[l, l] = int(bdiag[l])
+    for l in range(n - 1):
+        B[l, l + 1] = B[l + 1, l] = int(boff[l])
+    return B
+
+
+def random_block_diagonal(rng, n, p, two_by_two=0.5, char2_gamma=False):
+    """Scalar blocks and 2x2 blocks [[0, b], [b, g]] (g = 0 unless char2_gamma)."""
+    bdiag = rng.integers(0, p, size=n, dtype=np.uint64).astype(np.uint32)
+    boff = np.zeros(max(n - 1, 0), dtype=np.uint32)
+    j = 0
+    while j < n:
+        if j + 1 < n and rng.random() < two_by_two:
+            boff[j] = rng.integers(1, p)
+            bdiag[j] = 0
+            bdiag[j + 1] = rng.integers(0, p) if char2_gamma else 0
+            j += 2
+        else:
+            j += 1
+    return bdiag, boff
+
+
+@pytest.mark.parametrize("p", [2, 3, 7, 251, 65537, 94906249])
+def test_syrkbd_vs_dense_exact_matmul(p):
+    rng = np.random.default_rng(p)
+    for m, n in [(1, 1), (4, 3), (9, 8), (17, 30)]:
+        A = rng.integers(0, p, size=(m, n), dtype=np.uint64).astype(np.uint32)
+        bdiag = rng.integers(0, p, size=n, dtype=np.uint64).astype(np.uint32)
+        boff = rng.integers(0, p, size=max(n - 1, 0), dtype=np.uint64).astype(np.uint32)
+        B = dense_tridiagonal(bdiag, boff)
+        expect = modp(matmul_exact(matmul_exact(A, B), A.T), p)
+        assert np.array_equal(oracle.syrkbd(A, bdiag, boff, p), expect)
+        C0 = rng.integers(0, p, size=(m, m), dtype=np.uint64).astype(np.uint32)
+        al, be = int(rng.integers(0, p)), int(rng.integers(0, p))
+        got = oracle.syrkbd(A, bdiag, boff, p, al, be, C0)
+        assert np.array_equal(got, modp(al * matmul_exact(matmul_exact(A, B), A.T) + be * C0.astype(object), p))
+
+
+def test_syrkbd_exhaustive_p3_tiny():
+    p = 3
+    for vals in itertools.product(range(p), repeat=4):       # A is 2 x 2
+        A = np.array(vals, dtype=np.uint32).reshape(2, 2)
+        for b0, b1, e in itertools.product(range(p), repeat=3):
+            B = np.array([[b0, e], [e, b1]], dtype=object)
+            expect = modp(matmul_exact(matmul_exact(A, B), A.T), p)
+            got = oracle.syrkbd(A, [b0, b1], [e], p)
+            assert np.array_equal(got, expect)
+
+
+@pytest.mark.parametrize("p", [65537, 131071, 251])
+def test_syrkbd_reduces_to_syrkd_by_the_antidiagonal_factorisation(p):
+    """Section 5.2: [[0, b], [b, 0]] = T diag(b/2, -b/2) T^T with
+    T = [[1, 1], [1, -1]]: A B A^T equals syrkd of A T with those scalars."""
+    rng = np.random.default_rng(5 + p)
+    m, n = 13, 10
+    bdiag, boff = random_block_diagonal(rng, n, p)
+    A = rng.integers(0, p, size=(m, n), dtype=np.uint64).astype(np.uint32)
+    AT = A.astype(np.int64).copy()
+    d = bdiag.astype(np.int64).copy()
+    half = (p + 1) // 2
+    for j in range(n - 1):
+        if boff[j]:
+            b = int(boff[j])
+            AT[:, j] = (A[:, j].astype(np.int64) + A[:, j + 1]) % p
+            AT[:, j + 1] = (A[:, j].astype(np.int64) - A[:, j + 1]) % p
+            d[j] = b * half % p
+            d[j + 1] = (p - b * half % p) % p
+    got = oracle.syrkbd(A, bdiag, boff, p)
+    assert np.array_equal(got, oracle.syrkd(AT.astype(np.uint32), d.astype(np.uint32), p))
+    # a diagonal B is Algorithm 5's D
+    assert np.array_equal(oracle.syrkbd(A, bdiag, np.zeros(n - 1, np.uint32), p), oracle.syrkd(A, bdiag, p))
+
+
+def test_characteristic_two_factorisations():
+    """Section 5.2's identities in characteristic 2 (F_2): the antitriangular
+    block, the antidiagonal block with one extra column, and the
+    combination of a scalar block x with an antidiagonal block."""
+    p = 2
+    tri = np.array([[1, 1], [1, 0]], dtype=object)
+    for g in (1,):                      # [[0, 1], [1, g]], gamma != 0; delta = sqrt(g) = 1
+        F = matmul_exact(np.array([[1, 0], [0, 1]], dtype=object), tri)
+        assert np.array_equal(modp(matmul_exact(F, F.T), p), np.array([[0, 1], [1, g]]))
+    F = np.array([[1, 0, 1], [0, 1, 1]], dtype=object)
+    assert np.array_equal(modp(matmul_exact(F, F.T), p), np.array([[0, 1], [1, 0]]))
+    for x in (0, 1):
+        F = np.array([[x, x, x], [1, 0, 1], [0, 1, 1]], dtype=object)
+        assert np.array_equal(modp(matmul_exact(F, F.T), p), np.array([[x, 0, 0], [0, 0, 1], [0, 1, 0]]))
+
+
+# ------------------------------------- products over F_p[i] (Sections 3, 4.1)
+
+def cmul(a, b, p):
+    return ((a[0] * b[0] - a[1] * b[1]) % p, (a[0] * b[1] + a[1] * b[0]) % p)
+
+
+def brute_complex(re, im, p, conj):
+    n, k = re.shape
+    Cr = np.zeros((n, n), dtype=np.uint64)
+    Ci = np.zeros((n, n), dtype=np.uint64)
+    for j in range(n):
+        for l in range(n):
+            acc = (0, 0)
+            for t in range(k):
+                a = (int(re[j, t]), int(im[j, t]))
+                b = (int(re[l, t]), (p - int(im[l, t])) % p if conj else int(im[l, t]))
+                c = cmul(a, b, p)
+                acc = ((acc[0] + c[0]) % p, (acc[1] + c[1]) % p)
+            Cr[j, l], Ci[j, l] = acc
+    return Cr, Ci
+
+
+@pytest.mark.parametrize("p", [3, 7, 131071, 94906247])
+def test_herk_and_zsyrk_brute_force(p):
+    rng = np.random.default_rng(p)
+    for n, k in [(1, 1), (3, 2), (6, 7)]:
+        re = rng.integers(0, p, size=(n, k), dtype=np.uint64).astype(np.uint32)
+        im = rng.integers(0, p, size=(n, k), dtype=np.uint64).astype(np.uint32)
+        for fn, conj in ((oracle.herk, True), (oracle.zsyrk, False)):
+            Cr, Ci = fn(re, im, p)
+            er, ei = brute_complex(re, im, p, conj)
+            assert np.array_equal(Cr, er) and np.array_equal(Ci, ei), (fn.__name__, n, k)
+
+
+@pytest.mark.parametrize("p", [7, 131071])
+def test_herk_and_zsyrk_structure(p):
+    rng = np.random.default_rng(3 * p)
+    n, k = 9, 11
+    re = rng.integers(0, p, size=(n, k), dtype=np.uint64).astype(np.uint32)
+    im = rng.integers(0, p, size=(n, k), dtype=np.uint64).astype(np.uint32)
+    Hr, Hi = oracle.herk(re, im, p)
+    assert np.array_equal(Hr, Hr.T)                          # Hermitian: Re symmetric,
+    assert np.array_equal(Hi, (p - Hi.T.astype(np.int64)) % p)   # Im skew-symmetric
+    assert not Hi.diagonal().any()                           # real diagonal
+    Zr, Zi = oracle.zsyrk(re, im, p)
+    assert np.array_equal(Zr, Zr.T) and np.array_equal(Zi, Zi.T)
+    zero = np.zeros_like(re)
+    # a real A: both are A A^T; A = i B: A A^H = B B^T, A A^T = -B B^T
+    for fn in (oracle.herk, oracle.zsyrk):
+        r, i = fn(re, zero, p)
+        assert np.array_equal(r, oracle.syrk(re, p)) and not i.any()
+    r, i = oracle.herk(zero, im, p)
+    assert np.array_equal(r, oracle.syrk(im, p)) and not i.any()
+    r, i = oracle.zsyrk(zero, im, p)
+    assert np.array_equal(r, (p - oracle.syrk(im, p).astype(np.int64)) % p) and not i.any()
+    # rank one: C_jl = u_j conj(u_l)
+    u = (re[:, :1], im[:, :1])
+    r, i = oracle.herk(u[0], u[1], p)
+    for j in range(n):
+        for l in range(n):
+            c = cmul((int(u[0][j, 0]), int(u[1][j, 0])), (int(u[0][l, 0]), (p - int(u[1][l, 0])) % p), p)
+            assert (int(r[j, l]), int(i[j, l])) == c
