@@ -156,6 +156,33 @@ int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, v
  * control; 0 if p is not an odd prime <= 94906249. */
 size_t ffp_ldlt_workspace_bytes(int64_t n, uint32_t p);
 
+/* lower(C) <- (alpha * A * B * A^T + beta * lower(C)) mod p for B block
+ * diagonal with scalar blocks and 2 x 2 blocks [[0, b], [b, 0]], b != 0:
+ * the symmetric product with block diagonal scaling of Algorithm 6
+ * (Section 5.2, odd characteristic).  Each 2 x 2 block is factored by
+ * eq. (antidiagonal) into two scalar pivots b/2 and -b/2 on the columns
+ * A_j + A_(j+1) and A_j - A_(j+1); the resulting diagonal scaling runs as
+ * Algorithm 5 (square roots of residues, Algorithm 4 on pairs of
+ * non-residues, one appended zero column when their count is odd) and the
+ * product of the scaled matrix as fsyrk_modp (Algorithm 2).
+ *   m, n     A is m x n, B is n x n, C is m x m; m, n >= 0.
+ *   p        odd prime <= 94906249 (characteristic 2 is not built).
+ *   A, lda   device uint32 residues, lda >= n.
+ *   bdiag    device array of n residues: B_jj.
+ *   boff     device array of n - 1 residues: B_(j,j+1) = B_(j+1,j); a
+ *            nonzero entry makes (j, j+1) a 2 x 2 block, whose diagonal
+ *            entries must then be zero.  May be NULL when n <= 1.
+ *   alpha, beta  residues in [0,p); C, ldc as in fsyrk_modp.
+ *   info     device pointer to one int64, or NULL: 0, or j >= 1 when
+ *            column j - 1 starts a malformed block (blocks overlap, a 2 x 2
+ *            block has a nonzero diagonal entry, an entry of B is not below
+ *            p); C is then unspecified.
+ *   flags    FFP_FILL_UPPER, FFP_DEPTH(d), FFP_BASE_F64, FFP_LOW_MEMORY.
+ * Errors: FFP_EINVAL, FFP_EPRIME (also p = 2), FFP_ENOMEM, FFP_EDEVICE. */
+int fsyrkbd_modp(int64_t m, int64_t n, uint32_t p, const uint32_t* A, int64_t lda, const uint32_t* bdiag,
+                 const uint32_t* boff, uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, int64_t* info,
+                 unsigned flags, void* stream);
+
 /* One factorisation of fldlt_modp_batched (host struct; device pointers). */
 typedef struct ffp_ldlt_job {
     int64_t n;

@@ -210,11 +210,7 @@ int ffp_debug_set(const char* key, int64_t value)
         ffp::g_merge_tiles = (int)value;
         return FFP_OK;
     }
-    if (strcmp(key, "i8_ring") == 0) {
-        if (value != 0 && value != 4 && value != 5) return FFP_EINVAL;
-        ffp::g_i8_ring = (int)value;
-        return FFP_OK;
-    }
+    if (strcmp(key, "i8_dma") == 0) { ffp::g_i8_dma = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "i8_pipe") == 0) { ffp::g_i8_pipe = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "pack_vec") == 0) { ffp::g_pack_vec = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "f64_pipe") == 0) { ffp::g_f64_pipe = value ? 1 : 0; return FFP_OK; }
@@ -254,8 +250,7 @@ const char* ffp_debug_variant_name(int variant)
     case 3: return "void ffp::prod_i8_kernel<256, 256, 64, 1>(ffp::ProdArgs, int)";
     case 4: return "void ffp::prod_i8_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";
     case 5: return "void ffp::prod_i8_kernel<128, 128, 64, 2>(ffp::ProdArgs, int)";
-    case 6: return "void ffp::prod_i8_ring_kernel<256, 256, 4>(ffp::ProdArgs, int)";
-    case 7: return "void ffp::prod_i8_ring_kernel<256, 256, 5>(ffp::ProdArgs, int)";
+    case 6: return "ffp::prod_i8_dma_kernel(ffp::ProdArgs, int)";
     case 8: return "void ffp::prod_f64_lds_kernel<8>(ffp::ProdArgs, int)";
     case 9: return "void ffp::prod_i8_kernel<64, 64, 64, 3>(ffp::ProdArgs, int)";
     case 10: return "void ffp::prod_i8_pipe_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";
@@ -272,6 +267,31 @@ int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, v
     if (n > 0 && (S == nullptr || lds < n)) return FFP_EINVAL;
     if (n > (int64_t)1 << 30) return FFP_EINVAL;
     return ldlt_run(n, p, S, lds, info, (hipStream_t)stream);
+}
+
+int fsyrkbd_modp(int64_t m, int64_t n, uint32_t p, const uint32_t* A, int64_t lda, const uint32_t* bdiag,
+                 const uint32_t* boff, uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, int64_t* info,
+                 unsigned flags, void* stream)
+{
+    if (m < 0 || n < 0) return FFP_EINVAL;
+    if (p < 3 || !supported_prime(p)) return FFP_EPRIME;
+    if (n > 0 && (A == nullptr || lda < n || bdiag == nullptr || (n > 1 && boff == nullptr))) return FFP_EINVAL;
+    if (n > (int64_t)1 << 30) return FFP_EINVAL;
+    if (flags & (FFP_BASE_LIMB3 | FFP_WS_BETA)) return FFP_EINVAL;
+    // the product on Abar (m x kpad, uint32, in the workspace: 256-byte aligned)
+    const int64_t kpad = n > 0 ? syrkbd_kpad(n) : 0;
+    PlanRequest rq;
+    int st = make_syrk_request(m, kpad, p, (const void*)256, kpad > 0 ? kpad : 1, FFP_U32, alpha, beta, C, ldc,
+                               flags, &rq);
+    if (st != FFP_OK) return st;
+    if (m == 0) return FFP_OK;
+    const size_t need = syrkbd_workspace_bytes(m, n, rq);
+    if (need == 0) return FFP_EPRIME;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace* ws = nullptr;
+    st = acquire_workspace(s, need, 0, &ws);
+    if (st != FFP_OK) return st;
+    return syrkbd_run(m, n, p, A, lda, bdiag, boff, rq, C, info, ws->ptr, s);
 }
 
 int fldlt_modp_batched(int njobs, const ffp_ldlt_job* jobs, void* stream)

@@ -303,8 +303,8 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
     // longest-running first); product tables for groups beyond the inline
     // capacity
     struct Slice { int first, count, blocks; };
-    static const int kOrder[LK_KINDS] = {LK_LEAF,  LK_PRODL3, LK_PRODF, LK_PAIR, LK_CLASSIFY,
-                                         LK_TRSM, LK_PACK3,  LK_ABAR,  LK_SCALE, LK_ZERO};
+    static const int kOrder[LK_KINDS] = {LK_LEAF, LK_PRODL3, LK_PRODF, LK_PAIR,  LK_BDIAG, LK_CLASSIFY,
+                                         LK_TRSM, LK_PACK3,  LK_ABAR2, LK_ABAR, LK_SCALE, LK_ZERO};
     std::vector<Slice> slices(maxlev + 1, Slice{0, 0, 0});
     std::vector<LdltDesc> table;
     size_t prod_bytes = 0;
@@ -450,6 +450,114 @@ int ldlt_run_multi(const std::vector<LdltJobSpec>& jobs, hipStream_t s)
         b.rec(j.n, j.S, 0);
         if (b.status != FFP_OK) return b.status;
     }
+    return execute_steps(steps, s);
+}
+
+namespace {
+
+// Workspace of fsyrkbd_modp: Dbar and the Algorithm 5 scratch (n pivots),
+// the Algorithm 6 column ops (n) and Algorithm 5's (n + 1), Abar, then the
+// product's own workspace.
+struct BdLayout {
+    int64_t kpad;
+    int64_t off_dbar, off_flag, off_root, off_dinv, off_rank, off_desc1, off_desc, off_abar, off_syrk;
+};
+
+BdLayout bd_layout(int64_t m, int64_t n)
+{
+    BdLayout L;
+    L.kpad = syrkbd_kpad(n);
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { int64_t o = rup(off, 256); off = o + bytes; return o; };
+    L.off_dbar = take(n * 4);
+    L.off_flag = take(n * 4);
+    L.off_root = take(n * 4);
+    L.off_dinv = take(n * 4);
+    L.off_rank = take(n * 4);
+    L.off_desc1 = take(n * (int64_t)sizeof(ColOp));
+    L.off_desc = take((n + 1) * (int64_t)sizeof(ColOp));
+    L.off_abar = take(m * L.kpad * 4);
+    L.off_syrk = rup(off, 256);
+    return L;
+}
+
+}  // namespace
+
+int64_t syrkbd_kpad(int64_t n) { return rup(n + 1, 128); }
+
+size_t syrkbd_workspace_bytes(int64_t m, int64_t n, const PlanRequest& rq)
+{
+    const BdLayout L = bd_layout(m, n);
+    Plan pl;
+    if (build_syrk_plan(rq, &pl) != FFP_OK) return 0;
+    return (size_t)(L.off_syrk + pl.ws_bytes);
+}
+
+int syrkbd_run(int64_t m, int64_t n, uint32_t p, const uint32_t* A, int64_t lda, const uint32_t* bd,
+               const uint32_t* bo, const PlanRequest& rq, uint32_t* C, int64_t* info, void* ws, hipStream_t s)
+{
+    const BdLayout L = bd_layout(m, n);
+    std::deque<Plan> plans;
+    std::vector<Step> steps;
+    Builder b;
+    if (!make_field_plan(p, &b.fpl)) return FFP_EPRIME;
+    b.f = Fp{p, (p - 1) / 2, b.fpl.pinv, b.fpl.ya, b.fpl.yb};
+    b.kb = ldlt_dot_block(p);
+    uint32_t sq = 2;
+    while (legendre(sq, p) == 1) ++sq;
+    b.s_lqnr = sq;
+    b.c_lqnr = (uint32_t)sqrt_mod(sq - 1, p);
+    b.info = info;
+    b.lds = rq.ldc;
+    b.linv = nullptr;
+    b.ws = (char*)ws;
+    b.plans = &plans;
+    b.out = &steps;
+    char* w = (char*)ws;
+    ColOp* desc1 = (ColOp*)(w + L.off_desc1);
+    uint32_t* dbar = (uint32_t*)(w + L.off_dbar);
+    uint32_t* Ab = (uint32_t*)(w + L.off_abar);
+    if (n > 0) {
+        // Algorithm 6: Abar = A M, Dbar (column ops only; Abar is formed once below)
+        LdltDesc d = b.base();
+        d.nb = (int32_t)n;
+        d.bd = bd;
+        d.bo = bo;
+        d.desc1 = desc1;
+        d.dbar = dbar;
+        b.dev(LK_BDIAG, d);
+        // Algorithm 5 on Dbar: square roots of the residues, non-residues in
+        // pairs through Algorithm 4 (the pivots are read with stride 1)
+        LdltDesc c = b.base();
+        c.sc = Alg5Scratch{(int32_t*)(w + L.off_flag), (uint32_t*)(w + L.off_root), (uint32_t*)(w + L.off_dinv),
+                           (int32_t*)(w + L.off_rank), (ColOp*)(w + L.off_desc)};
+        c.nb = (int32_t)n;
+        c.X = dbar;
+        c.ldx = 0;
+        b.dev(LK_CLASSIFY, c);
+        b.dev(LK_PAIR, c);
+        LdltDesc a = c;
+        a.rows = m;
+        a.ncols = (int32_t)(n + 1);
+        a.kpad = (int32_t)L.kpad;
+        a.X = (uint32_t*)A;
+        a.ldx = lda;
+        a.desc1 = desc1;
+        a.Ab = Ab;
+        a.ldab = L.kpad;
+        b.dev(LK_ABAR2, a);
+    } else if (info != nullptr) {
+        b.dev(LK_ZERO, b.base());
+    }
+    // lower(C) <- alpha Abar Abar^T + beta lower(C) through Algorithm 2
+    plans.emplace_back();
+    Plan& pl = plans.back();
+    PlanRequest r = rq;
+    r.k = n > 0 ? L.kpad : 0;
+    r.lda = L.kpad;
+    const int st = build_syrk_plan(r, &pl);
+    if (st != FFP_OK) return st;
+    b.plan_ops(pl, Ab, C, w + L.off_syrk);
     return execute_steps(steps, s);
 }
 

@@ -47,6 +47,8 @@ enum LdltKind : int32_t {
     LK_PRODF,        // product task t, 64 x 64 FP64 tiles
     LK_PACK3,        // uint32 residues -> three int8 limb planes (zero padded)
     LK_PRODL3,       // product task t, 64 x 64 three-limb int8 tiles
+    LK_BDIAG,        // Algorithm 6 (odd p): column ops desc1 and diagonal dbar of a block diagonal B
+    LK_ABAR2,        // Abar (rows x kpad) from the column ops desc (on A desc1) on A = X
     LK_KINDS
 };
 
@@ -73,6 +75,12 @@ struct LdltDesc {
     // LK_PACK3: X (rows x ncols, ldx) -> Ab as int8 planes (ldab, plane
     // offset pplane) of rows_pad x kpad
     int64_t rows_pad, pplane;
+    // LK_BDIAG: B's diagonal bd (nb entries) and off-diagonal bo (nb - 1);
+    // out: desc1 (nb column ops on A), dbar (nb pivots).  LK_ABAR2 reads desc1.
+    const uint32_t* bd;
+    const uint32_t* bo;
+    ColOp* desc1;
+    uint32_t* dbar;
 };
 
 // Workgroups a descriptor of the kind needs (sets d->gx where used).
@@ -104,5 +112,17 @@ int ldlt_run(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, hip
 // enqueued together on s.
 int ldlt_run_multi(const std::vector<LdltJobSpec>& jobs, hipStream_t s);
 size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds);
+
+// fsyrkbd_modp (Algorithm 6, odd p): lower(C) <- alpha A B A^T + beta lower(C)
+// for A m x n and B block diagonal (diagonal bd, off-diagonal bo, both device
+// arrays).  rq: the product request for Abar (m x kpad) with Abar in the
+// workspace; validated by the caller.  ws: syrkbd_workspace_bytes bytes.
+struct PlanRequest;
+int syrkbd_run(int64_t m, int64_t n, uint32_t p, const uint32_t* A, int64_t lda, const uint32_t* bd,
+               const uint32_t* bo, const PlanRequest& rq, uint32_t* C, int64_t* info, void* ws,
+               hipStream_t s);
+// Columns of Abar (n + 1 rounded up to 128) and workspace of syrkbd_run.
+int64_t syrkbd_kpad(int64_t n);
+size_t syrkbd_workspace_bytes(int64_t m, int64_t n, const PlanRequest& rq);
 
 }  // namespace ffp

@@ -389,6 +389,88 @@ __device__ __forceinline__ void build_abar_body(Fp f, int64_t rows, int ncols, i
     }
 }
 
+// Algorithm 6, odd characteristic (Section 5.2): B = M Dbar M^T with M
+// the identity except for the 2 x 2 blocks of B, where eq. (antidiagonal)
+// gives [[0, b], [b, 0]] = [[1, 1], [1, -1]] diag(b/2, -b/2) [[1, 1], [1, -1]]^T,
+// so A B A^T = Abar Dbar Abar^T with Abar = A M:
+//   first column j of a block:  Abar_j = A_j + A_(j+1),  Dbar_j = b/2
+//   second column:              Abar_(j+1) = A_j - A_(j+1),  Dbar_(j+1) = -b/2
+//   scalar block:               Abar_j = A_j,  Dbar_j = B_jj.
+// B is given by its diagonal bd (n) and off-diagonal bo (n - 1); bo[j] != 0
+// marks the block (j, j + 1).  One workgroup.  *info (if not null) is the
+// 1-based index of the first column of a malformed block (two blocks
+// overlapping, a nonzero diagonal entry inside a 2 x 2 block, an entry not
+// below p), else 0.
+struct BdiagLds {
+    int32_t wave_min[4];
+};
+
+__device__ __forceinline__ void bdiag_body(Fp f, int n, const uint32_t* bd, const uint32_t* bo, ColOp* desc1,
+                                           uint32_t* dbar, int64_t* info, BdiagLds& L)
+{
+    const uint32_t p = f.p, half = (p + 1u) / 2u;   // the inverse of 2
+    int bad = 0x7FFFFFFF;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const uint32_t prev = j > 0 ? bo[j - 1] : 0u;
+        const uint32_t next = j + 1 < n ? bo[j] : 0u;
+        const uint32_t dj = bd[j];
+        if (dj >= p || prev >= p || next >= p) bad = min(bad, j);
+        if (next != 0u) {
+            if (prev != 0u || dj != 0u || bd[j + 1] != 0u) bad = min(bad, j);
+            desc1[j] = ColOp{j, 1u, j + 1, 1u};
+            dbar[j] = mul_m(next, half, p, f.pinv);
+        } else if (prev != 0u) {
+            desc1[j] = ColOp{j - 1, 1u, j, p - 1u};
+            dbar[j] = sub_m(0u, mul_m(prev, half, p, f.pinv), p);
+        } else {
+            desc1[j] = ColOp{j, 1u, -1, 0u};
+            dbar[j] = dj;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) bad = min(bad, __shfl_xor(bad, o));
+    if ((threadIdx.x & 63) == 0) L.wave_min[threadIdx.x >> 6] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0 && info != nullptr) {
+        const int b = min(min(L.wave_min[0], L.wave_min[1]), min(L.wave_min[2], L.wave_min[3]));
+        *info = b == 0x7FFFFFFF ? 0 : (int64_t)b + 1;
+    }
+}
+
+// Abar[:, c] = s1 Abar1_(j1) + s2 Abar1_(j2) for the column ops desc (Algorithm 5
+// on Dbar) over the columns Abar1 = A desc1 (Algorithm 6), formed straight
+// from A; zero beyond ncols, up to kpad.
+__device__ __forceinline__ void build_abar2_body(Fp f, int64_t rows, int ncols, int kpad, const uint32_t* A,
+                                                 int64_t lda, const ColOp* desc1, const ColOp* desc,
+                                                 uint32_t* Ab, int64_t ldab, int bx, int by, int gy)
+{
+    const int64_t c = (int64_t)bx * 64 + (threadIdx.x & 63);
+    if (c >= kpad) return;
+    // up to four columns of A with their factors
+    int32_t col[4] = {-1, -1, -1, -1};
+    uint32_t fac[4] = {0u, 0u, 0u, 0u};
+    if (c < ncols) {
+        const ColOp o = desc[c];
+        const int32_t js[2] = {o.j1, o.j2};
+        const uint32_t ss[2] = {o.s1, o.s2};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (js[u] < 0) continue;
+            const ColOp q = desc1[js[u]];
+            col[2 * u] = q.j1;
+            fac[2 * u] = mul_m(ss[u], q.s1, f.p, f.pinv);
+            col[2 * u + 1] = q.j2;
+            fac[2 * u + 1] = q.j2 >= 0 ? mul_m(ss[u], q.s2, f.p, f.pinv) : 0u;
+        }
+    }
+    for (int64_t r = (int64_t)by * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gy * 4) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (col[u] >= 0) v = add_m(v, mul_m(A[r * lda + col[u]], fac[u], f.p, f.pinv), f.p);
+        Ab[r * ldab + c] = v;
+    }
+}
+
 // ---- launches over descriptor arrays ---------------------------------------
 
 // Descriptor owning workgroup b (descriptors sorted by block0; uniform).
@@ -418,6 +500,7 @@ union StepLds {
     LeafLds leaf;
     TrsmLds trsm;
     PairLds pair;
+    BdiagLds bdiag;
     int8_t i8[I8Tile<64, 64, 64, 3>::LDS];
 };
 
@@ -459,6 +542,13 @@ __global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n
     case LK_PRODL3:
         i8_tile_task<64, 64, 64, 3>(d.t, lb, lds.i8);
         break;
+    case LK_BDIAG:
+        bdiag_body(d.f, d.nb, d.bd, d.bo, d.desc1, d.dbar, d.info, lds.bdiag);
+        break;
+    case LK_ABAR2:
+        build_abar2_body(d.f, d.rows, d.ncols, d.kpad, d.X, d.ldx, d.desc1, d.sc.desc, d.Ab, d.ldab, lb % d.gx,
+                         lb / d.gx, row_bands(d.rows));
+        break;
     default:
         break;
     }
@@ -481,6 +571,7 @@ int ldlt_blocks(int kind, LdltDesc* d)
     switch (kind) {
     case LK_ZERO:
     case LK_LEAF:
+    case LK_BDIAG:
     case LK_PAIR: return 1;
     case LK_TRSM: return (int)((d->rows + TR - 1) / TR);
     case LK_CLASSIFY: return (d->nb + 255) / 256;
@@ -488,6 +579,7 @@ int ldlt_blocks(int kind, LdltDesc* d)
         d->gx = (d->nb + 63) / 64;
         return d->rows > 0 ? d->gx * row_bands(d->rows) : 0;
     case LK_ABAR:
+    case LK_ABAR2:
         d->gx = (d->kpad + 63) / 64;
         return d->rows > 0 ? d->gx * row_bands(d->rows) : 0;
     case LK_PACK3:

@@ -125,6 +125,7 @@ def lib():
             "ffp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
             "fgemm_modp": (c_int, [i64, i64, i64, u32, P, i64, P, i64, u32, u32, P, i64, P]),
             "fldlt_modp": (c_int, [i64, u32, P, i64, P, P]),
+            "fsyrkbd_modp": (c_int, [i64, i64, u32, P, i64, P, P, u32, u32, P, i64, P, c_uint, P]),
             "ffp_workspace_bytes": (ctypes.c_size_t, [i64, i64, u32, c_int, c_uint]),
             "fsyrk_modp_batched": (c_int, [c_int, P, c_uint, P]),
             "ffp_strerror": (ctypes.c_char_p, [c_int]),
@@ -228,6 +229,11 @@ def fgemm_modp(m, n, k, p, A, lda, B, ldb, alpha, beta, C, ldc, stream=None):
 
 def fldlt_modp(n, p, S, lds, info, stream=None):
     return _check(lib().fldlt_modp(n, p, _ptr(S), lds, _ptr(info), _stream(stream)), "fldlt_modp")
+
+
+def fsyrkbd_modp(m, n, p, A, lda, bdiag, boff, alpha, beta, C, ldc, info=None, flags=0, stream=None):
+    return _check(lib().fsyrkbd_modp(m, n, p, _ptr(A), lda, _ptr(bdiag), _ptr(boff), alpha, beta, _ptr(C),
+                                     ldc, _ptr(info), flags, _stream(stream)), "fsyrkbd_modp")
 
 
 def ffp_workspace_bytes(n, k, p, a_dtype=FFP_U32, flags=0) -> int:
@@ -450,6 +456,25 @@ def syrk(A, p: int, alpha: int = 1, beta: int = 0, C=None, depth=None, fill_uppe
     if limb3:
         flags |= FFP_BASE_LIMB3
     fsyrk_modp(n, k, p, A, lda, a_dtype, alpha, beta, C, C.stride(0), flags, stream)
+    return C
+
+
+def syrkbd(A, bdiag, boff, p: int, alpha: int = 1, beta: int = 0, C=None, info=None, depth=None,
+           fill_upper=False, stream=None):
+    """lower(C) <- alpha A B A^T + beta lower(C) mod p (Algorithm 6) on device
+    int32 tensors: A (m, n), B block diagonal given by bdiag (n) and boff
+    (n - 1).  Returns C ((m, m) int32)."""
+    import torch
+    m, n = A.shape
+    if A.stride(-1) != 1:
+        raise ValueError("A must be row-major")
+    if C is None:
+        C = torch.zeros((m, m), dtype=torch.int32, device=A.device)
+    flags = FFP_FILL_UPPER if fill_upper else 0
+    if depth is not None:
+        flags |= FFP_DEPTH(depth)
+    fsyrkbd_modp(m, n, p, A, A.stride(0), bdiag, boff if n > 1 else None, alpha, beta, C, C.stride(0), info,
+                 flags, stream)
     return C
 
 

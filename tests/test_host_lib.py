@@ -108,3 +108,14 @@ def test_workspace_bytes_monotone():
     L.ffp_ldlt_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_uint32]
     assert L.ffp_ldlt_workspace_bytes(4096, 65537) > 0
     assert L.ffp_ldlt_workspace_bytes(4096, 65535) == 0
+
+
+def test_syrkbd_argument_checks():
+    # validated synchronously, before anything touches a device
+    assert ffp.lib().fsyrkbd_modp(4, 4, 2, 16, 4, 16, 16, 1, 0, 16, 4, None, 0, None) == ffp.FFP_EPRIME
+    assert ffp.lib().fsyrkbd_modp(4, 4, 15, 16, 4, 16, 16, 1, 0, 16, 4, None, 0, None) == ffp.FFP_EPRIME
+    assert ffp.lib().fsyrkbd_modp(4, 4, 7, 16, 4, 16, None, 1, 0, 16, 4, None, 0, None) == ffp.FFP_EINVAL
+    assert ffp.lib().fsyrkbd_modp(4, 4, 7, 16, 3, 16, 16, 1, 0, 16, 4, None, 0, None) == ffp.FFP_EINVAL
+    assert ffp.lib().fsyrkbd_modp(4, 4, 7, 16, 4, 16, 16, 7, 0, 16, 4, None, 0, None) == ffp.FFP_EINVAL
+    assert ffp.lib().fsyrkbd_modp(-1, 4, 7, 16, 4, 16, 16, 1, 0, 16, 4, None, 0, None) == ffp.FFP_EINVAL
+    assert ffp.lib().fsyrkbd_modp(0, 4, 7, 16, 4, 16, 16, 1, 0, 16, 4, None, 0, None) == ffp.FFP_OK
