@@ -36,6 +36,7 @@
 // of that order (blocks are dispatched round-robin over the 8 XCDs).
 #include "prod_i8_tile.h"
 
+#include <type_traits>
 #include <vector>
 
 namespace ffp {
@@ -48,189 +49,6 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
     ProdTask t;
     select_task(args, b, &t);
     i8_tile_task<BM, BN, BK, PLANES>(t, b - t.tile0, smem);
-}
-
-// ---- CLS_I8 with direct-to-LDS operand loads ---------------------------
-//
-// Same tile and wave decomposition as i8_tile with BK = 64, but the operand
-// panels go from global memory straight into LDS (global_load_lds_dwordx4:
-// each wave instruction fills 1 KB of LDS, lane L at byte 16 L) through a
-// ring of NS stages, so loads run NS - 2 stages ahead without staging
-// registers or LDS write instructions.  A stage holds the BM + BN rows of
-// 64 bytes of the A and B panels; the four 16-byte chunks of row r are
-// stored in the order c ^ s(r) with s(r) = (r >> 2) & 3, which keeps the
-// fragment reads (consecutive rows, one chunk) free of LDS bank conflicts
-// (measured: the plain row-major order costs four times as much).  The compiler does not order these loads against LDS
-// reads, so completion is waited for explicitly (vmcnt) before the
-// workgroup barrier that publishes a stage.
-
-__device__ __forceinline__ int swz64(int r) { return (r >> 2) & 3; }
-
-// Workgroup barrier without the compiler's fence (which would wait for every
-// direct-to-LDS load in flight); LDS reads of this wave are complete first.
-__device__ __forceinline__ void ring_barrier()
-{
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-// Waits until at most n of this wave's vector-memory loads are in flight.
-template <int L>
-__device__ __forceinline__ void wait_loads(int stages_after)
-{
-    static_assert(3 * L < 64, "vmcnt range");
-    if (stages_after >= 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * L) : "memory");
-    else if (stages_after == 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * L) : "memory");
-    else if (stages_after == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(L) : "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-}
-
-typedef __attribute__((address_space(1))) const void GVoid;
-typedef __attribute__((address_space(3))) void LVoid;
-
-template <int BM, int BN>
-__device__ __forceinline__ void ring_load(int8_t* stage, const int8_t* __restrict__ A, int64_t lda,
-                                          int a_row0, int a_rows, const int8_t* __restrict__ B,
-                                          int64_t ldb, int b_row0, int b_rows, int k0)
-{
-    constexpr int BLOCKS = (BM + BN) / 16;
-    constexpr int PER_WAVE = BLOCKS / 4;
-    static_assert(BLOCKS % 4 == 0 && (BM / 16) % PER_WAVE == 0, "a wave loads from one panel");
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const bool isA = wave * PER_WAVE < BM / 16;             // uniform per wave
-    const int8_t* __restrict__ g = isA ? A : B;
-    const int64_t ld = isA ? lda : ldb;
-    const int prow0 = isA ? a_row0 : b_row0, prows = isA ? a_rows : b_rows;
-    const int blk0 = isA ? wave * PER_WAVE : wave * PER_WAVE - BM / 16;
-#pragma unroll
-    for (int q = 0; q < PER_WAVE; ++q) {
-        const int r = (blk0 + q) * 16 + (lane >> 2);           // row within the panel
-        const int c = (lane & 3) ^ swz64(r);
-        // rows past the end re-read the last row (their outputs are not stored)
-        const int row = prow0 + r < prows ? prow0 + r : prows - 1;
-        const int8_t* src = g + (int64_t)row * ld + k0 + c * 16;
-        __builtin_amdgcn_global_load_lds((GVoid*)src, (LVoid*)(stage + (wave * PER_WAVE + q) * 1024),
-                                         16, 0, 0);
-    }
-}
-
-template <int BM, int BN, int NS>
-__device__ __forceinline__ void i8_ring_tile(const ProdArgs& args, int b)
-{
-    constexpr int BK = 64;
-    constexpr int STAGE = (BM + BN) * BK;
-    constexpr int WTM = BM / 2, WTN = BN / 2;
-    constexpr int FM = WTM / 32, FN = WTN / 32;
-    constexpr int LOADS = (BM + BN) / 16 / 4;              // per wave and stage
-    __shared__ __attribute__((aligned(1024))) int8_t smem[NS * STAGE];
-
-    ProdTask t;
-    select_task(args, b, &t);
-    const int r = b - t.tile0;
-    int ti, tj;
-    if (t.syrk) band_tri(r, t.tm, &ti, &tj);
-    else band_rect(r, t.tm, t.tn, &ti, &tj);
-    const int tile_r = ti * BM, tile_c = tj * BN;
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int lrow = lane & 31, lk = lane >> 5;
-    const int8_t* __restrict__ Ab = (const int8_t*)t.A.p;
-    const int8_t* __restrict__ Bb = (const int8_t*)t.B.p;
-
-    v16i acc[FM][FN];
-    // the task is the same for the whole workgroup: keep its loop bounds scalar
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0;
-    const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
-
-    // byte offsets of this lane's fragment rows inside a stage; the chunk of
-    // k-step ks is (2 ks + lk) ^ s(row), and s(row) only depends on lrow
-    const int sw = swz64(lrow);
-    const int ch0 = ((0 + lk) ^ sw) * 16, ch1 = ((2 + lk) ^ sw) * 16;
-    const int offA = (wr * WTM + lrow) * BK, offB = BM * BK + (wc * WTN + lrow) * BK;
-
-    const int nk = __builtin_amdgcn_readfirstlane(t.k / BK);
-    auto load_stage = [&](int s) {
-        ring_load<BM, BN>(smem + (s % NS) * STAGE, Ab, t.A.ld, tile_r, t.m, Bb, t.B.ld, tile_c, t.n,
-                          s * BK);
-    };
-    auto read_frags = [&](v4i (&xa)[FM], v4i (&xb)[FN], int s, int ch) {
-        const int8_t* st = smem + (s % NS) * STAGE;
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-            xa[i] = *reinterpret_cast<const v4i*>(st + offA + i * 32 * BK + ch);
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-            xb[j] = *reinterpret_cast<const v4i*>(st + offB + j * 32 * BK + ch);
-    };
-    auto mfmas = [&](const v4i (&xa)[FM], const v4i (&xb)[FN]) {
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[i], xb[j], acc[i][j], 0, 0, 0);
-    };
-    // one LDS read per MFMA over the first FM + FN MFMAs of a k-step, so the
-    // reads have the rest of the k-step to land; with mfma_first the k-step
-    // opens with an MFMA (its operands' wait then precedes the new reads)
-    auto interleave = [&](auto mfma_first) {
-        constexpr int lead = decltype(mfma_first)::value ? 1 : 0;
-        if constexpr (lead) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-#pragma unroll
-        for (int q = 0; q < FM + FN; ++q) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, FM * FN - (FM + FN) - lead, 0);
-    };
-
-    if (nk > 0) {
-        for (int s = 0; s < NS - 1 && s < nk; ++s) load_stage(s);
-        // stage 0 complete: the later prologue stages may stay in flight
-        wait_loads<LOADS>((nk < NS - 1 ? nk : NS - 1) - 1);
-        ring_barrier();
-        v4i fa[FM], fb[FN], na[FM], nb[FN];
-        read_frags(fa, fb, 0, ch0);
-        for (int kt = 0; kt < nk; ++kt) {
-            if (kt + 1 < nk) {
-                // publish stage kt + 1; this also ends every read of the
-                // buffer the next load overwrites (stage kt - 1)
-                const int issued = kt + NS - 1 < nk ? kt + NS - 1 : nk;
-                wait_loads<LOADS>(issued - (kt + 2));
-                ring_barrier();
-                if (kt + NS - 1 < nk) load_stage(kt + NS - 1);
-            }
-            // fa/fb (read during the previous k-step) have landed; stated to
-            // the compiler so that it adds no wait inside the MFMA stream
-            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
-            read_frags(na, nb, kt, ch1);
-            mfmas(fa, fb);
-            interleave(std::false_type{});
-            // first k-step of the next stage; after the last stage this reads
-            // an idle ring buffer whose values are never used
-            read_frags(fa, fb, kt + 1, ch0);
-            mfmas(na, nb);
-            interleave(std::true_type{});
-        }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    }
-    ring_barrier();
-    store_tile_i8_reg<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
-}
-
-template <int BM, int BN, int NS>
-__global__ __launch_bounds__(256) void prod_i8_ring_kernel(ProdArgs args, int mode)
-{
-    if (mode == 2) {
-        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) i8_ring_tile<BM, BN, NS>(args, b);
-        return;
-    }
-    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (b < args.total_tiles) i8_ring_tile<BM, BN, NS>(args, b);
 }
 
 // ---- CLS_I8 with the LDS writes spread over the MFMAs -------------------
@@ -496,6 +314,191 @@ __device__ __forceinline__ void i8_pipe_body(const ProdTask& t, int ti, int tj, 
     }
 }
 
+// ---- CLS_I8 with operands straight to LDS -------------------------------
+//
+// 256 x 256 tiles, 4 waves of 128 x 128, 128-byte k stages in two LDS
+// buffers of 64 KB (the A panel's 256 rows of 128 bytes, then the B
+// panel's).  The operands go from global memory to LDS with buffer loads
+// that write LDS themselves: no staging registers and no LDS write
+// instructions between the MFMAs.  One load instruction fills 1 KB, 8 rows
+// of a panel: lane L writes slot L % 8 of row L / 8 with that row's 16-byte
+// chunk (L % 8) ^ s(row), s(r) = (r & 7) ^ ((r >> 3) & 1), so that the
+// fragment reads (one chunk of 8 or 16 consecutive rows) meet distinct
+// banks.  The loads of stage t + 2 go into the buffer of stage t once the
+// barrier of k-step 3 of stage t has ended every read of it: half during
+// k-step 3 of stage t, half during k-step 0 of stage t + 1; each wave waits
+// for its own loads (vmcnt) before the barrier of k-step 3 of stage t + 1,
+// which publishes stage t + 2.  Each k-step issues its 16 MFMAs with the
+// other instructions between them in a fixed order (a scheduling barrier
+// after each): the LDS reads of the next k-step's fragments in the order the
+// MFMAs consume them, and the loads.  Without the fixed order the compiler
+// grouped the LDS traffic between MFMAs that then waited for it.
+//
+// Panels are read through buffer resources: stages past the end of k add
+// 2^31 to the vector offsets, so their loads return zeros; a partial panel
+// (EDGE) keeps the row of every load in its vector offset, and rows past the
+// valid ones fall outside the resource (zeros).  Outputs of rows or columns
+// past the end are never stored.
+
+template <int N> using IC = std::integral_constant<int, N>;
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(IC<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+typedef __attribute__((address_space(3))) void LdsVoid;
+
+__device__ __forceinline__ int dma_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
+template <bool EDGE>
+__device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, int8_t* smem)
+{
+    constexpr int BM = 256, BN = 256, BK = 128;
+    constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 32, FN = WTN / 32;
+    static_assert(FM == 4 && FN == 4, "the k-step order below assumes 4 x 4 blocks per wave");
+    constexpr int BUF = (BM + BN) * BK;
+    const int tile_r = ti * BM, tile_c = tj * BN;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lrow = lane & 31, lk = lane >> 5;
+
+    v16i acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0;
+    const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
+
+    const int nk = t.k / BK;
+    if (nk > 0) {
+        const int va = t.m - tile_r < BM ? t.m - tile_r : BM;    // valid rows of the panels
+        const int vb = t.n - tile_c < BN ? t.n - tile_c : BN;
+        const int lda = __builtin_amdgcn_readfirstlane((int)t.A.ld);
+        const int ldb = __builtin_amdgcn_readfirstlane((int)t.B.ld);
+        const __amdgpu_buffer_rsrc_t ra =
+            panel_rsrc((const int8_t*)t.A.p + (int64_t)tile_r * t.A.ld, (int64_t)va * t.A.ld);
+        const __amdgpu_buffer_rsrc_t rb =
+            panel_rsrc((const int8_t*)t.B.p + (int64_t)tile_c * t.B.ld, (int64_t)vb * t.B.ld);
+        // load q (0..15) of a stage: blocks 8 wave + (q & 7) of the A (q < 8) or B panel
+        const int lr8 = lane >> 3, slot = lane & 7;
+        const int va0 = lr8 * lda + 16 * (slot ^ lr8), va1 = lr8 * lda + 16 * (slot ^ lr8 ^ 1);
+        const int vb0 = lr8 * ldb + 16 * (slot ^ lr8), vb1 = lr8 * ldb + 16 * (slot ^ lr8 ^ 1);
+        auto dload = [&](int q, int stg, bool live) {
+            const uint32_t dead = live ? 0u : 0x80000000u;
+            const bool isB = q >= 8;
+            const int blk = wave * 8 + (q & 7);
+            int8_t* dst = smem + (stg & 1) * BUF + (isB ? BM * BK : 0) + blk * 1024;
+            const int ld = isB ? ldb : lda;
+            const int v = isB ? ((blk & 1) ? vb1 : vb0) : ((blk & 1) ? va1 : va0);
+            if constexpr (EDGE) {
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(isB ? rb : ra, (LdsVoid*)dst, 16,
+                                                         (uint32_t)(v + 8 * blk * ld) + dead,
+                                                         __builtin_amdgcn_readfirstlane(stg * BK), 0, 0);
+            } else {
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(isB ? rb : ra, (LdsVoid*)dst, 16, (uint32_t)v + dead,
+                                                         __builtin_amdgcn_readfirstlane(stg * BK + 8 * blk * ld),
+                                                         0, 0);
+            }
+        };
+        const int sw = dma_swz(lrow);
+        int coff[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) coff[ks] = 16 * ((2 * ks + lk) ^ sw);
+        const int rowA = (wr * WTM + lrow) * BK, rowB = BM * BK + (wc * WTN + lrow) * BK;
+        v4i fa[FM], fb[FN], na[FM], nb[FN];
+        // fragment o of a k-step, in the order the MFMAs use them: a0 b0 b1 b2 b3 a1 a2 a3
+        auto rd = [&](v4i (&xa)[FM], v4i (&xb)[FN], int buf, int ks, int o) {
+            const int8_t* base = smem + buf * BUF + coff[ks];
+            if (o == 0 || o >= 5) {
+                const int i = o == 0 ? 0 : o - 4;
+                xa[i] = *reinterpret_cast<const v4i*>(base + rowA + i * 32 * BK);
+            } else {
+                xb[o - 1] = *reinterpret_cast<const v4i*>(base + rowB + (o - 1) * 32 * BK);
+            }
+        };
+        // the previous tile of a persistent workgroup may still read LDS
+        __syncthreads();
+        for (int q = 0; q < 16; ++q) dload(q, 0, true);
+        for (int q = 0; q < 16; ++q) dload(q, 1, nk > 1);
+        asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+        __syncthreads();
+        for (int o = 0; o < 8; ++o) rd(fa, fb, 0, 0, o);
+        // one k-step: 16 MFMAs on (xa, xb), the NOPS other operations spread
+        // between them in order
+        auto kstep = [&](const v4i (&xa)[FM], const v4i (&xb)[FN], auto nops, auto&& op) {
+            constexpr int NOPS = decltype(nops)::value;
+            static_for<0, 16>([&](auto q) {
+                constexpr int Q = decltype(q)::value;
+                acc[Q / 4][Q % 4] =
+                    __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[Q / 4], xb[Q % 4], acc[Q / 4][Q % 4], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                static_for<Q * NOPS / 16, (Q + 1) * NOPS / 16>([&](auto o) {
+                    op(o);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            });
+        };
+        auto stage = [&](auto par, int kt) {
+            constexpr int cur = decltype(par)::value;
+            // k0: fragments of k-step 1; second half of stage kt + 1's loads
+            kstep(fa, fb, IC<16>{}, [&](auto o) {
+                constexpr int O = decltype(o)::value;
+                if constexpr (O % 2 == 0) rd(na, nb, cur, 1, O / 2);
+                else dload(8 + O / 2, kt + 1, kt + 1 < nk);
+            });
+            kstep(na, nb, IC<8>{}, [&](auto o) { rd(fa, fb, cur, 2, decltype(o)::value); });
+            kstep(fa, fb, IC<8>{}, [&](auto o) { rd(na, nb, cur, 3, decltype(o)::value); });
+            // stage kt + 1 in LDS: this wave's loads, then every wave's
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            // k3: first fragments of stage kt + 1; first half of stage kt + 2's loads
+            kstep(na, nb, IC<16>{}, [&](auto o) {
+                constexpr int O = decltype(o)::value;
+                if constexpr (O % 2 == 0) rd(fa, fb, cur ^ 1, 0, O / 2);
+                else dload(O / 2, kt + 2, kt + 2 < nk);
+            });
+        };
+        // stages in pairs (static buffer indices); for odd nk the last stage of
+        // the last pair reads loads past the end of k, i.e. zeros.  The first
+        // k-step 0 re-issues the second half of stage 1 (same data).
+        for (int kt = 0; kt < nk; kt += 2) {
+            stage(IC<0>{}, kt);
+            stage(IC<1>{}, kt + 1);
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    store_tile_i8_reg<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+}
+
+__device__ __forceinline__ void i8_dma_tile(const ProdArgs& args, int b)
+{
+    __shared__ __attribute__((aligned(1024))) int8_t smem[2 * 512 * 128];
+    ProdTask t;
+    select_task(args, b, &t);
+    const int r = b - t.tile0;
+    int ti, tj;
+    if (t.syrk) band_tri(r, t.tm, &ti, &tj);
+    else band_rect(r, t.tm, t.tn, &ti, &tj);
+    if ((ti + 1) * 256 <= t.m && (tj + 1) * 256 <= t.n) i8_dma_body<false>(t, ti, tj, smem);
+    else i8_dma_body<true>(t, ti, tj, smem);
+}
+
+__global__ __launch_bounds__(256) void prod_i8_dma_kernel(ProdArgs args, int mode)
+{
+    if (mode == 2) {
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) i8_dma_tile(args, b);
+        return;
+    }
+    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b < args.total_tiles) i8_dma_tile(args, b);
+}
+
 template <int BM, int BN, int BK, int PLANES>
 __device__ __forceinline__ void i8_pipe_tile(const ProdArgs& args, int b)
 {
@@ -562,13 +565,13 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
     const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
     int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
     if constexpr (RING > 0) {
-        static_assert(PLANES == 1 && BK == 64, "ring variant: CLS_I8, 64-byte stages");
+        static_assert(BM == 256 && BN == 256 && PLANES == 1 && BK == 128, "direct-to-LDS variant: CLS_I8 256-tiles");
         if (mode == 2) {
-            const int resident = resident_blocks((const void*)prod_i8_ring_kernel<BM, BN, RING>);
+            const int resident = resident_blocks((const void*)prod_i8_dma_kernel);
             grid = total < resident ? total : resident;
         }
-        g_last_variant = 6 + (RING - 4);
-        hipLaunchKernelGGL((prod_i8_ring_kernel<BM, BN, RING>), dim3(grid), dim3(256), 0, s, args, mode);
+        g_last_variant = 6;
+        hipLaunchKernelGGL(prod_i8_dma_kernel, dim3(grid), dim3(256), 0, s, args, mode);
     } else if constexpr (RING < 0) {
         static_assert(PLANES <= 2 && BK == 128, "pipelined variant: int8 or two limbs, 128-byte stages");
         if (mode == 2) {
@@ -667,7 +670,7 @@ bool prepare_limb3_tile_task(ProdTask* t)
 
 int g_i8_tile_override = 0;
 int g_i8_bk_override = 0;
-int g_i8_ring = 0;
+int g_i8_dma = 1;
 int g_i8_pipe = 1;
 
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
@@ -680,13 +683,12 @@ hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_bu
     bool k128 = true;
     for (int i = 0; i < ntasks; ++i) k128 = k128 && (tasks[i].k % 128) == 0;
     if (big) {
-        if (g_i8_ring == 4) return launch_i8_impl<256, 256, 64, 1, 4>(tasks, ntasks, dev_task_buf, s);
-        if (g_i8_ring == 5) return launch_i8_impl<256, 256, 64, 1, 5>(tasks, ntasks, dev_task_buf, s);
         if (g_i8_bk_override == 64 || !k128) return launch_i8_impl<256, 256, 64, 1>(tasks, ntasks, dev_task_buf, s);
         // the pipelined kernel addresses a 256-row panel with 32-bit offsets
         bool pipe_ok = g_i8_pipe != 0;
         for (int i = 0; i < ntasks; ++i)
             pipe_ok = pipe_ok && tasks[i].A.ld < (1 << 23) && tasks[i].B.ld < (1 << 23);
+        if (pipe_ok && g_i8_dma) return launch_i8_impl<256, 256, 128, 1, 1>(tasks, ntasks, dev_task_buf, s);
         if (pipe_ok) return launch_i8_impl<256, 256, 128, 1, -1>(tasks, ntasks, dev_task_buf, s);
         return launch_i8_impl<256, 256, 128, 1>(tasks, ntasks, dev_task_buf, s);
     }

@@ -248,25 +248,28 @@ def test_i8_tile_variants(tile, n, k):
         set_knob("i8_tile", 0)
 
 
-@pytest.mark.parametrize("ring", [4, 5])
-@pytest.mark.parametrize("n,k", [(300, 256), (513, 64), (1000, 320), (1100, 4096), (256, 128)])
-def test_i8_ring_variants(ring, n, k):
-    """256 x 256 int8 tiles fed by direct-to-LDS loads through a ring of 4
-    or 5 stages: fewer, as many and more k-stages than ring slots."""
+@pytest.mark.parametrize("dma", [1, 0])
+@pytest.mark.parametrize("n,k", [(300, 256), (513, 128), (1000, 384), (1100, 4096), (256, 128), (600, 1280)])
+def test_i8_dma_variants(dma, n, k):
+    """256 x 256 int8 tiles with operands loaded straight into LDS (the
+    default) or through registers: one, odd and even stage counts, partial
+    panels, alpha/beta, k in chunks accumulated through C."""
     p = 251
-    A = inputs.uniform(n + 7 * ring, n, k, p)
+    A = inputs.uniform(n + 7 * dma + k, n, k, p)
+    A[:2] = p - 1
+    A[2:4] = (p + 1) // 2
     set_knob("i8_tile", 256)
-    set_knob("i8_ring", ring)
+    set_knob("i8_dma", dma)
     try:
         check_lower(gpu_syrk(A, p, depth=0, a_dtype=ffp.FFP_I8_CENTERED), oracle.syrk(A, p))
         C0 = inputs.uniform(8, n, n, p)
         check_lower(gpu_syrk(A, p, depth=0, alpha=3, beta=5, C0=C0), oracle.syrk_ab(A, p, 3, 5, C0))
-        set_kblk(128)      # k in chunks of two stages, accumulated through C
+        set_kblk(256)      # k in chunks of two stages, accumulated through C
         check_lower(gpu_syrk(A, p, depth=1, alpha=p - 1, beta=1, C0=C0),
                     oracle.syrk_ab(A, p, p - 1, 1, C0))
     finally:
         set_kblk(0)
-        set_knob("i8_ring", 0)
+        set_knob("i8_dma", 1)
         set_knob("i8_tile", 0)
 
 
@@ -280,6 +283,7 @@ def test_i8_pipe_variant(pipe, n, k):
     p = 251
     A = inputs.uniform(n + k + 11, n, k, p)
     set_knob("i8_tile", 256)
+    set_knob("i8_dma", 0)
     set_knob("i8_pipe", pipe)
     try:
         check_lower(gpu_syrk(A, p, depth=0, a_dtype=ffp.FFP_I8_CENTERED), oracle.syrk(A, p))
@@ -298,6 +302,7 @@ def test_i8_pipe_variant(pipe, n, k):
     finally:
         set_kblk(0)
         set_knob("i8_pipe", 1)
+        set_knob("i8_dma", 1)
         set_knob("i8_tile", 0)
 
 
@@ -391,14 +396,32 @@ def test_argument_errors():
 
 # ------------------------------------------------------ full-size workloads
 
-def _sampled(A, p, out, nsamp=4000, seed=0):
+def _sampled(A, p, out, tile=128, per_tile=2, seed=0):
+    """Entries of every lower tile of edge `tile` of the output against the
+    oracle: its four corners (those on or below the diagonal), two random
+    entries below the diagonal and, on diagonal tiles, two diagonal entries."""
     n = A.shape[0]
     rng = np.random.default_rng(seed)
-    rows = rng.integers(0, n, size=nsamp)
-    cols = rng.integers(0, n, size=nsamp)
-    lo, hi = np.maximum(rows, cols), np.minimum(rows, cols)
-    lo = np.concatenate([lo, [n - 1, n - 1, 0, n // 2]])
-    hi = np.concatenate([hi, [0, n - 1, 0, n // 2 - 1]])
+    nt = (n + tile - 1) // tile
+    rows, cols = [], []
+    for ti in range(nt):
+        r0, r1 = ti * tile, min(n, ti * tile + tile) - 1
+        for tj in range(ti + 1):
+            c0, c1 = tj * tile, min(n, tj * tile + tile) - 1
+            for r, c in ((r0, c0), (r1, c0), (r0, c1), (r1, c1)):
+                if c <= r:
+                    rows.append(r)
+                    cols.append(c)
+            rr = rng.integers(r0, r1 + 1, size=per_tile)
+            cc = rng.integers(c0, c1 + 1, size=per_tile)
+            rows.extend(np.maximum(rr, cc))
+            cols.extend(np.minimum(rr, cc))
+            if ti == tj:
+                d = rng.integers(r0, r1 + 1, size=2)
+                rows.extend(d)
+                cols.extend(d)
+    lo = np.asarray(rows, dtype=np.int64)
+    hi = np.asarray(cols, dtype=np.int64)
     expect = oracle.syrk_entries(A, p, lo, hi)
     got = out[lo, hi]
     assert np.array_equal(got, expect)
@@ -462,9 +485,11 @@ def test_full_size_8192_p131071_three_limbs(k):
     _sampled(A, p, from_dev_u32(Cd))
 
 
-@pytest.mark.parametrize("p,a_dtype,ring", [(251, ffp.FFP_I8_CENTERED, 0), (251, ffp.FFP_I8_CENTERED, 4),
-                                            (251, ffp.FFP_I8_CENTERED, 5), (65521, ffp.FFP_I8_LIMB2, 0)])
-def test_full_size_16384_int8(p, a_dtype, ring):
+@pytest.mark.parametrize("p,a_dtype,dma", [(251, ffp.FFP_I8_CENTERED, 1), (251, ffp.FFP_I8_CENTERED, 0),
+                                           (65521, ffp.FFP_I8_LIMB2, 1)])
+def test_full_size_16384_int8(p, a_dtype, dma):
+    """The 16384^2 workloads in the launch configuration the benchmark
+    times: every 256 x 256 output tile sampled against the oracle."""
     import torch
     n = 16384
     A = inputs.uniform(2, n, n, p)
@@ -473,10 +498,10 @@ def test_full_size_16384_int8(p, a_dtype, ring):
     else:
         Ad = torch.from_numpy(limbs(A, p)).cuda()
     Cd = torch.zeros((n, n), dtype=torch.int32, device="cuda")
-    set_knob("i8_ring", ring)
+    set_knob("i8_dma", dma)
     try:
         ffp.syrk(Ad, p, C=Cd, depth=0, a_dtype=a_dtype)
         torch.cuda.synchronize()
     finally:
-        set_knob("i8_ring", 0)
-    _sampled(A, p, from_dev_u32(Cd), nsamp=2000)
+        set_knob("i8_dma", 1)
+    _sampled(A, p, from_dev_u32(Cd), tile=256)
