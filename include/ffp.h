@@ -183,6 +183,32 @@ int fsyrkbd_modp(int64_t m, int64_t n, uint32_t p, const uint32_t* A, int64_t ld
                  const uint32_t* boff, uint32_t alpha, uint32_t beta, uint32_t* C, int64_t ldc, int64_t* info,
                  unsigned flags, void* stream);
 
+/* lower(C) <- A * A^T over F_p[i] = F_p[x]/(x^2 + 1) (the field F_(p^2)
+ * when p = 3 mod 4): the symmetric product of Section 3.1 ("over the
+ * complex field"), Algorithm 2 with Y = i I, whose multiplication only
+ * exchanges the two planes with one sign change.  Its general products run
+ * as three real products each (the 3M method) and its leaves as two (the
+ * 2M method of Section 4.1), on FP64 matrix cores.
+ *   n, k     A is n x k, C is n x n; n, k >= 0.
+ *   p        odd prime <= 94906249.
+ *   A, lda   device uint32 residues: real parts at A, imaginary parts at
+ *            A + a_plane (elements, same lda); the planes must not overlap.
+ *   C, ldc   likewise with c_plane.  The strict upper triangle of both
+ *            planes is scratch unless FFP_FILL_UPPER mirrors it.
+ *   flags    FFP_FILL_UPPER, FFP_DEPTH(d).
+ * Errors: FFP_EINVAL, FFP_EPRIME (also p = 2), FFP_ENOMEM, FFP_EDEVICE. */
+int fzsyrk_modp(int64_t n, int64_t k, uint32_t p, const uint32_t* A, int64_t lda, int64_t a_plane, uint32_t* C,
+                int64_t ldc, int64_t c_plane, unsigned flags, void* stream);
+
+/* lower(C) <- A * A^H over F_p[i], conj(a + ib) = a - ib (Section 3.3):
+ * Algorithm 2 with conjugate transposition and Y = (a + ib) I, where
+ * a^2 + b^2 = -1 in F_p (Algorithm 3 for p = 3 mod 4; a = sqrt(-1), b = 0
+ * for p = 1 mod 4), so that Y Y^H = -I.  The diagonal of C is real.  Same
+ * arguments, flags and errors as fzsyrk_modp; FFP_FILL_UPPER writes the
+ * conjugate of the lower triangle into the upper one. */
+int fherk_modp(int64_t n, int64_t k, uint32_t p, const uint32_t* A, int64_t lda, int64_t a_plane, uint32_t* C,
+               int64_t ldc, int64_t c_plane, unsigned flags, void* stream);
+
 /* One factorisation of fldlt_modp_batched (host struct; device pointers). */
 typedef struct ffp_ldlt_job {
     int64_t n;

@@ -39,9 +39,18 @@ int ffp_host_nrsyf(uint32_t p, uint32_t alpha, uint32_t beta, uint32_t Y[4]);
  * then one line per operation:
  *   "op kind cls src_cls mode m n k m_src k_src alpha beta level" followed
  *   by six views "buf off ld plane" (buf 0 = A, 1 = C, 2 = workspace; off in
- *   bytes, ld and plane in elements of the view's storage). */
+ *   bytes, ld and plane in elements of the view's storage) and the five
+ *   coefficients of a linear combination (1 for other operations). */
 int ffp_plan_describe(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda, int64_t ldc,
                       uint32_t alpha, uint32_t beta, unsigned flags, char* buf, size_t len);
+/* Same for the schedule of fzsyrk_modp (herk = 0) or fherk_modp (herk = 1);
+ * the op lines end with the five coefficients of the linear combinations. */
+int ffp_complex_plan_describe(int64_t n, int64_t k, uint32_t p, int herk, int64_t lda, int64_t a_plane,
+                              int64_t ldc, int64_t c_plane, unsigned flags, char* buf, size_t len);
+/* Scheduler levels of that complex schedule's operations (as
+ * ffp_plan_levels). */
+int ffp_complex_plan_levels(int64_t n, int64_t k, uint32_t p, int herk, int64_t lda, int64_t a_plane,
+                            int64_t ldc, int64_t c_plane, unsigned flags, int32_t* levels, size_t cap);
 
 /* Level of every operation of the same plan (as ffp_plan_describe lists
  * them) under the library's level scheduler: an operation's level is one

@@ -452,6 +452,74 @@ __global__ __launch_bounds__(256) void lincomb_kernel(uint32_t p, int64_t m, int
     }
 }
 
+// out = sum_i coef[i] * op_i(in[i]) mod p over an m x k block, op_i the
+// identity or the transpose (the additions of the complex products: 3M
+// combinations, the multiplication by Y of the pre-additions, the post-
+// additions with P4 read transposed).  A workgroup forms a 64 x 64 tile of
+// out; a transposed input goes through a 64 x 65 LDS tile so that its
+// global reads stay coalesced.
+struct LctIn { const uint32_t* p[5]; int64_t ld[5]; uint32_t c[5]; };
+
+__global__ __launch_bounds__(256) void lct_kernel(uint32_t p, double pinv, int64_t m, int64_t k, int nin, LctIn in,
+                                                  unsigned trans, int lower, uint32_t* __restrict__ out, int64_t ldo)
+{
+    __shared__ uint32_t tl[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    if (lower && c0 > r0 + 63) return;     // the whole tile above the diagonal (uniform)
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 4 rows of 64 per pass
+    uint32_t acc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0u;
+    for (int t = 0; t < nin; ++t) {
+        const uint32_t cf = in.c[t];
+        if ((trans >> t) & 1u) {
+            // out[r][c] += cf * in[c][r]: stage in rows c0.., columns r0..
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t sr = c0 + ty + 4 * e, sc = r0 + tx;
+                tl[ty + 4 * e][tx] = (sr < k && sc < m) ? in.p[t][sr * in.ld[t] + sc] : 0u;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                acc[e] = add_m(acc[e], mul_m(cf, tl[tx][ty + 4 * e], p, pinv), p);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t r = r0 + ty + 4 * e, c = c0 + tx;
+                if (r < m && c < k) acc[e] = add_m(acc[e], mul_m(cf, in.p[t][r * in.ld[t] + c], p, pinv), p);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int64_t r = r0 + ty + 4 * e, c = c0 + tx;
+        if (r < m && c < k && (!lower || c <= r)) out[r * ldo + c] = acc[e];
+    }
+}
+
+// Up(C) <- -Low(C)^T mod p, through 32 x 32 LDS tiles (as lower_to_upper_kernel).
+__global__ __launch_bounds__(256) void lower_to_upper_neg_kernel(uint32_t p, int m, uint32_t* C, int64_t ldc)
+{
+    __shared__ uint32_t s[T][T + 1];
+    int bi, bj;
+    tri_index(blockIdx.x, &bi, &bj);
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int rr = ty; rr < T; rr += 8) {
+        const int I = bi * T + rr, J = bj * T + tx;
+        if (I < m && J < m && I >= J) s[rr][tx] = C[(int64_t)I * ldc + J];
+    }
+    __syncthreads();
+    for (int rr = ty; rr < T; rr += 8) {
+        const int Jr = bj * T + rr, Ic = bi * T + tx;
+        if (Jr < m && Ic < m && Ic > Jr) {
+            const uint32_t v = s[tx][rr];
+            C[(int64_t)Jr * ldc + Ic] = v == 0u ? 0u : p - v;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void copy_u32_kernel(int64_t rows, int64_t cols, const uint32_t* src,
                                                       int64_t lds, uint32_t* dst, int64_t ldd,
                                                       int lower_only)
@@ -716,6 +784,30 @@ hipError_t launch_lincomb(const Fp& f, int64_t m, int64_t k, int nin, const DVie
         hipLaunchKernelGGL(lincomb_kernel<1>, grid2d(m, k), dim3(256), 0, s, f.p, m, k, nin, li, neg,
                            (uint32_t*)out.p, out.ld);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_lct(const Fp& f, int64_t m, int64_t k, int nin, const DView* in, const uint32_t* coef,
+                      unsigned trans, int lower, DView out, hipStream_t s)
+{
+    if (m <= 0 || k <= 0) return hipSuccess;
+    if (nin < 1 || nin > 5 || (lower && m != k)) return hipErrorInvalidValue;
+    LctIn li{};
+    for (int t = 0; t < nin; ++t) {
+        li.p[t] = (const uint32_t*)in[t].p;
+        li.ld[t] = in[t].ld;
+        li.c[t] = coef[t] % f.p;
+    }
+    const dim3 g((unsigned)((k + 63) / 64), (unsigned)((m + 63) / 64));
+    hipLaunchKernelGGL(lct_kernel, g, dim3(256), 0, s, f.p, f.pinv, m, k, nin, li, trans, lower,
+                       (uint32_t*)out.p, out.ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror_lower_neg(uint32_t p, int64_t n, uint32_t* C, int64_t ldc, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lower_to_upper_neg_kernel, dim3(tri_blocks(n)), dim3(256), 0, s, p, (int)n, C, ldc);
     return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include "ldlt.h"
 #include "plan.h"
 #include "batch.h"
+#include "cplan.h"
 #include "runtime.h"
 #include "serve.h"
 
@@ -162,6 +163,70 @@ int ffp_plan_describe(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda
     return (int)s.size();
 }
 
+namespace {
+ComplexRequest complex_request(int64_t n, int64_t k, uint32_t p, int herk, int64_t lda, int64_t a_plane,
+                               int64_t ldc, int64_t c_plane, unsigned flags)
+{
+    ComplexRequest rq;
+    rq.n = n;
+    rq.k = k;
+    rq.p = p;
+    rq.herk = herk != 0;
+    rq.lda = lda;
+    rq.a_plane = a_plane;
+    rq.ldc = ldc;
+    rq.c_plane = c_plane;
+    const unsigned dfield = (flags >> 4) & 0xFu;
+    rq.depth = dfield ? (int)dfield - 1 : -1;
+    rq.fill_upper = (flags & FFP_FILL_UPPER) != 0;
+    return rq;
+}
+}  // namespace
+
+int ffp_complex_plan_levels(int64_t n, int64_t k, uint32_t p, int herk, int64_t lda, int64_t a_plane,
+                            int64_t ldc, int64_t c_plane, unsigned flags, int32_t* levels, size_t cap)
+{
+    Plan pl;
+    const int st = build_complex_plan(complex_request(n, k, p, herk, lda, a_plane, ldc, c_plane, flags), &pl);
+    if (st != FFP_OK) return st;
+    const void* a = (const void*)((uintptr_t)1 << 44);
+    void* c = (void*)((uintptr_t)2 << 44);
+    void* ws = (void*)((uintptr_t)3 << 44);
+    std::vector<SchedItem> items;
+    for (const Op& o : pl.ops) items.push_back(SchedItem{&pl, &o, a, c, ws, 0});
+    const std::vector<int> lv = schedule_levels(items);
+    if (levels)
+        for (size_t i = 0; i < lv.size() && i < cap; ++i) levels[i] = lv[i];
+    return (int)lv.size();
+}
+
+int ffp_complex_plan_describe(int64_t n, int64_t k, uint32_t p, int herk, int64_t lda, int64_t a_plane,
+                              int64_t ldc, int64_t c_plane, unsigned flags, char* buf, size_t len)
+{
+    ComplexRequest rq;
+    rq.n = n;
+    rq.k = k;
+    rq.p = p;
+    rq.herk = herk != 0;
+    rq.lda = lda;
+    rq.a_plane = a_plane;
+    rq.ldc = ldc;
+    rq.c_plane = c_plane;
+    const unsigned dfield = (flags >> 4) & 0xFu;
+    rq.depth = dfield ? (int)dfield - 1 : -1;
+    rq.fill_upper = (flags & FFP_FILL_UPPER) != 0;
+    Plan pl;
+    const int st = build_complex_plan(rq, &pl);
+    if (st != FFP_OK) return st;
+    std::string s = describe_plan(pl);
+    if (buf && len > 0) {
+        size_t c = s.size() < len - 1 ? s.size() : len - 1;
+        memcpy(buf, s.data(), c);
+        buf[c] = '\0';
+    }
+    return (int)s.size();
+}
+
 int ffp_plan_levels(int64_t n, int64_t k, uint32_t p, int a_dtype, int64_t lda, int64_t ldc,
                     uint32_t alpha, uint32_t beta, unsigned flags, int32_t* levels, size_t cap)
 {
@@ -267,6 +332,57 @@ int fldlt_modp(int64_t n, uint32_t p, uint32_t* S, int64_t lds, int64_t* info, v
     if (n > 0 && (S == nullptr || lds < n)) return FFP_EINVAL;
     if (n > (int64_t)1 << 30) return FFP_EINVAL;
     return ldlt_run(n, p, S, lds, info, (hipStream_t)stream);
+}
+
+namespace {
+
+int complex_syrk(bool herk, int64_t n, int64_t k, uint32_t p, const uint32_t* A, int64_t lda, int64_t a_plane,
+                 uint32_t* C, int64_t ldc, int64_t c_plane, unsigned flags, void* stream)
+{
+    if (n < 0 || k < 0) return FFP_EINVAL;
+    if (p < 3 || !supported_prime(p)) return FFP_EPRIME;
+    if (flags & ~(FFP_FILL_UPPER | 0xF0u)) return FFP_EINVAL;   // fill and depth bits only
+    if (n > 0 && (C == nullptr || ldc < n)) return FFP_EINVAL;
+    if (n > 0 && k > 0 && (A == nullptr || lda < k)) return FFP_EINVAL;
+    if (n > (int64_t)1 << 30 || k > (int64_t)1 << 30) return FFP_EINVAL;
+    // the planes of A and of C must not overlap
+    if (n > 0 && k > 0 && (a_plane < 0 ? -a_plane : a_plane) < (n - 1) * lda + k) return FFP_EINVAL;
+    if (n > 0 && (c_plane < 0 ? -c_plane : c_plane) < (n - 1) * ldc + n) return FFP_EINVAL;
+    if (n == 0) return FFP_OK;
+    ComplexRequest rq;
+    rq.n = n;
+    rq.k = k;
+    rq.p = p;
+    rq.herk = herk;
+    rq.lda = lda;
+    rq.a_plane = a_plane;
+    rq.ldc = ldc;
+    rq.c_plane = c_plane;
+    const unsigned dfield = (flags >> 4) & 0xFu;
+    rq.depth = dfield ? (int)dfield - 1 : -1;
+    rq.fill_upper = (flags & FFP_FILL_UPPER) != 0;
+    Plan pl;
+    int st = build_complex_plan(rq, &pl);
+    if (st != FFP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace* ws = nullptr;
+    st = acquire_workspace(s, (size_t)pl.ws_bytes, 0, &ws);
+    if (st != FFP_OK) return st;
+    return execute_plan(pl, A, C, ws->ptr, s);
+}
+
+}  // namespace
+
+int fzsyrk_modp(int64_t n, int64_t k, uint32_t p, const uint32_t* A, int64_t lda, int64_t a_plane, uint32_t* C,
+                int64_t ldc, int64_t c_plane, unsigned flags, void* stream)
+{
+    return complex_syrk(false, n, k, p, A, lda, a_plane, C, ldc, c_plane, flags, stream);
+}
+
+int fherk_modp(int64_t n, int64_t k, uint32_t p, const uint32_t* A, int64_t lda, int64_t a_plane, uint32_t* C,
+               int64_t ldc, int64_t c_plane, unsigned flags, void* stream)
+{
+    return complex_syrk(true, n, k, p, A, lda, a_plane, C, ldc, c_plane, flags, stream);
 }
 
 int fsyrkbd_modp(int64_t m, int64_t n, uint32_t p, const uint32_t* A, int64_t lda, const uint32_t* bdiag,

@@ -141,6 +141,12 @@ hipError_t launch_save_c22(int64_t m, const uint32_t* C22, int64_t ld22, uint32_
                            int64_t ld11, uint32_t* dvec, hipStream_t s);
 // Up(C) = Low(C)^T.
 hipError_t launch_mirror_lower(int64_t n, uint32_t* C, int64_t ldc, hipStream_t s);
+// Up(C) <- -Low(C)^T mod p (the imaginary part of a Hermitian matrix).
+hipError_t launch_mirror_lower_neg(uint32_t p, int64_t n, uint32_t* C, int64_t ldc, hipStream_t s);
+// out (m x k) <- sum_i coef[i] * op_i(in[i]) mod p, op_i the transpose when
+// bit i of trans is set (in[i] then k x m); lower: only entries j <= i (m = k).
+hipError_t launch_lct(const Fp& f, int64_t m, int64_t k, int nin, const DView* in, const uint32_t* coef,
+                      unsigned trans, int lower, DView out, hipStream_t s);
 
 // ---- representation changes ----------------------------------------
 // Copy an n x k block of uint32 residues (or int8 / limb storage of class

@@ -499,6 +499,10 @@ std::string describe_plan(const Plan& pl)
                      (long long)o.v[i].ld, (long long)o.v[i].plane);
             s += buf;
         }
+        for (int i = 0; i < 5; ++i) {
+            snprintf(buf, sizeof buf, " %u", o.coef[i]);
+            s += buf;
+        }
         s += "\n";
     }
     return s;

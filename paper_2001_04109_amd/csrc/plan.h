@@ -37,7 +37,12 @@ enum OpKind : int32_t {
     OP_COPY = 9,     // v1 <- v0 (m x n uint32), mode 1: lower triangle only
     OP_LINCOMB = 10, // v5 <- sum of +-v_i, i < (mode & 7), mod p; bit 3 + i of mode: subtract v_i
                      // (m x k uint32 blocks; the Strassen-Winograd additions)
+    OP_LCT = 11,     // v5 <- sum of coef[i] * op_i(v_i), i < (mode & 7), mod p, over m x k uint32;
+                     // bit 3 + i of mode: op_i is the transpose (v_i is k x m); bit 8: lower
+                     // triangle only (m = k)
 };
+// OP_GEMM mode bit 0: lower-triangle tiles of C only (m = n; the product
+// A B^T need not be symmetric).  OP_MIRROR mode bit 0: Up(v0) <- -Low(v0)^T.
 
 struct Op {
     OpKind kind;
@@ -49,6 +54,7 @@ struct Op {
     uint32_t alpha = 1, beta = 0;
     int32_t level = 0;          // recursion level that emitted the op
     PView v[6];
+    uint32_t coef[5] = {1, 1, 1, 1, 1};   // OP_LCT
 };
 
 struct PlanRequest {

@@ -512,6 +512,13 @@ OpRegions regions_of(const SchedItem& it)
         for (int i = 0; i < (o.mode & 7); ++i) add_view(r.rd, o.v[i], o.m, o.k, 4, 1, it);
         add_view(r.wr, o.v[5], o.m, o.k, 4, 1, it);
         break;
+    case OP_LCT:
+        for (int i = 0; i < (o.mode & 7); ++i) {
+            const bool tr = (o.mode >> (3 + i)) & 1;
+            add_view(r.rd, o.v[i], tr ? o.k : o.m, tr ? o.m : o.k, 4, 1, it);
+        }
+        add_view(r.wr, o.v[5], o.m, o.k, 4, 1, it);
+        break;
     }
     return r;
 }
@@ -762,7 +769,8 @@ ProdTask make_task(const Plan& pl, const Op& o, const void* a, void* c, void* ws
     t.m = (int32_t)o.m;
     t.n = (int32_t)(syrk ? o.m : o.n);
     t.k = (int32_t)o.k;
-    t.syrk = syrk ? 1 : 0;
+    // a SYRK, or a general product restricted to the lower-triangle tiles
+    t.syrk = (syrk || (o.kind == OP_GEMM && (o.mode & 1))) ? 1 : 0;
     t.alpha = o.alpha;
     t.beta = o.beta;
     return t;
@@ -836,7 +844,8 @@ int execute_op(const Plan& pl, const Op& o, const void* a, void* c, void* ws, hi
                                 (uint32_t*)at(o.v[2], a, c, ws), s);
             break;
         case OP_MIRROR:
-            e = launch_mirror_lower(o.m, (uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld, s);
+            e = (o.mode & 1) ? launch_mirror_lower_neg(fpl.p, o.m, (uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld, s)
+                             : launch_mirror_lower(o.m, (uint32_t*)at(o.v[0], a, c, ws), o.v[0].ld, s);
             break;
         case OP_PACK:
             e = launch_pack(f, o.src_cls, dview(o.v[0], a, c, ws), o.m_src, o.k_src, o.cls,
@@ -850,6 +859,13 @@ int execute_op(const Plan& pl, const Op& o, const void* a, void* c, void* ws, hi
             DView in[5] = {};
             for (int i = 0; i < (o.mode & 7); ++i) in[i] = dview(o.v[i], a, c, ws);
             e = launch_lincomb(f, o.m, o.k, o.mode & 7, in, (unsigned)(o.mode >> 3), dview(o.v[5], a, c, ws), s);
+            break;
+        }
+        case OP_LCT: {
+            DView in[5] = {};
+            for (int i = 0; i < (o.mode & 7); ++i) in[i] = dview(o.v[i], a, c, ws);
+            e = launch_lct(f, o.m, o.k, o.mode & 7, in, o.coef, (unsigned)((o.mode >> 3) & 31), (o.mode >> 8) & 1,
+                           dview(o.v[5], a, c, ws), s);
             break;
         }
         }

@@ -126,6 +126,8 @@ def lib():
             "fgemm_modp": (c_int, [i64, i64, i64, u32, P, i64, P, i64, u32, u32, P, i64, P]),
             "fldlt_modp": (c_int, [i64, u32, P, i64, P, P]),
             "fsyrkbd_modp": (c_int, [i64, i64, u32, P, i64, P, P, u32, u32, P, i64, P, c_uint, P]),
+            "fzsyrk_modp": (c_int, [i64, i64, u32, P, i64, i64, P, i64, i64, c_uint, P]),
+            "fherk_modp": (c_int, [i64, i64, u32, P, i64, i64, P, i64, i64, c_uint, P]),
             "ffp_workspace_bytes": (ctypes.c_size_t, [i64, i64, u32, c_int, c_uint]),
             "fsyrk_modp_batched": (c_int, [c_int, P, c_uint, P]),
             "ffp_strerror": (ctypes.c_char_p, [c_int]),
@@ -138,6 +140,10 @@ def lib():
             "ffp_plan_describe": (c_int, [i64, i64, u32, c_int, i64, i64, u32, u32, c_uint,
                                           ctypes.c_char_p, ctypes.c_size_t]),
             "ffp_ldlt_workspace_bytes": (ctypes.c_size_t, [i64, u32]),
+            "ffp_complex_plan_describe": (c_int, [i64, i64, u32, c_int, i64, i64, i64, i64, c_uint,
+                                                  ctypes.c_char_p, ctypes.c_size_t]),
+            "ffp_complex_plan_levels": (c_int, [i64, i64, u32, c_int, i64, i64, i64, i64, c_uint, P,
+                                                ctypes.c_size_t]),
             "ffp_plan_levels": (c_int, [i64, i64, u32, c_int, i64, i64, u32, u32, c_uint, P,
                                         ctypes.c_size_t]),
             "fldlt_modp_batched": (c_int, [c_int, P, P]),
@@ -234,6 +240,16 @@ def fldlt_modp(n, p, S, lds, info, stream=None):
 def fsyrkbd_modp(m, n, p, A, lda, bdiag, boff, alpha, beta, C, ldc, info=None, flags=0, stream=None):
     return _check(lib().fsyrkbd_modp(m, n, p, _ptr(A), lda, _ptr(bdiag), _ptr(boff), alpha, beta, _ptr(C),
                                      ldc, _ptr(info), flags, _stream(stream)), "fsyrkbd_modp")
+
+
+def fzsyrk_modp(n, k, p, A, lda, a_plane, C, ldc, c_plane, flags=0, stream=None):
+    return _check(lib().fzsyrk_modp(n, k, p, _ptr(A), lda, a_plane, _ptr(C), ldc, c_plane, flags,
+                                    _stream(stream)), "fzsyrk_modp")
+
+
+def fherk_modp(n, k, p, A, lda, a_plane, C, ldc, c_plane, flags=0, stream=None):
+    return _check(lib().fherk_modp(n, k, p, _ptr(A), lda, a_plane, _ptr(C), ldc, c_plane, flags,
+                                   _stream(stream)), "fherk_modp")
 
 
 def ffp_workspace_bytes(n, k, p, a_dtype=FFP_U32, flags=0) -> int:
@@ -406,6 +422,29 @@ def plan_describe(n, k, p, a_dtype=FFP_U32, lda=None, ldc=None, alpha=1, beta=0,
     return buf.value.decode()
 
 
+def complex_plan_describe(n, k, p, herk=False, lda=None, ldc=None, flags=0) -> str:
+    """The host schedule of fzsyrk_modp / fherk_modp (planes stacked: the
+    imaginary plane n*lda elements after the real one)."""
+    lda = k if lda is None else lda
+    ldc = n if ldc is None else ldc
+    size = _check(lib().ffp_complex_plan_describe(n, k, p, int(herk), lda, n * lda, ldc, n * ldc, flags,
+                                                  None, 0), "complex_plan_describe")
+    buf = ctypes.create_string_buffer(size + 1)
+    lib().ffp_complex_plan_describe(n, k, p, int(herk), lda, n * lda, ldc, n * ldc, flags, buf, size + 1)
+    return buf.value.decode()
+
+
+def complex_plan_levels(n, k, p, herk=False, lda=None, ldc=None, flags=0) -> list:
+    """Scheduler level of every operation of complex_plan_describe's plan."""
+    lda = k if lda is None else lda
+    ldc = n if ldc is None else ldc
+    args = (n, k, p, int(herk), lda, n * lda, ldc, n * ldc, flags)
+    cnt = _check(lib().ffp_complex_plan_levels(*args, None, 0), "complex_plan_levels")
+    buf = (ctypes.c_int32 * max(cnt, 1))()
+    _check(lib().ffp_complex_plan_levels(*args, buf, cnt), "complex_plan_levels")
+    return list(buf[:cnt])
+
+
 def plan_levels(n, k, p, a_dtype=FFP_U32, lda=None, ldc=None, alpha=1, beta=0, flags=0) -> list:
     """Scheduler level of every operation of the plan plan_describe prints."""
     lda = k if lda is None else lda
@@ -475,6 +514,23 @@ def syrkbd(A, bdiag, boff, p: int, alpha: int = 1, beta: int = 0, C=None, info=N
         flags |= FFP_DEPTH(depth)
     fsyrkbd_modp(m, n, p, A, A.stride(0), bdiag, boff if n > 1 else None, alpha, beta, C, C.stride(0), info,
                  flags, stream)
+    return C
+
+
+def complex_syrk(A, p: int, herk: bool = False, C=None, depth=None, fill_upper=False, stream=None):
+    """lower(C) <- A A^T (herk: A A^H) over F_p[i] on device int32 tensors:
+    A of shape (2, n, k) with the real plane first.  Returns C (2, n, n)."""
+    import torch
+    _, n, k = A.shape
+    if A.stride(-1) != 1:
+        raise ValueError("A must be row-major")
+    if C is None:
+        C = torch.zeros((2, n, n), dtype=torch.int32, device=A.device)
+    flags = FFP_FILL_UPPER if fill_upper else 0
+    if depth is not None:
+        flags |= FFP_DEPTH(depth)
+    f = fherk_modp if herk else fzsyrk_modp
+    f(n, k, p, A, A.stride(1), A.stride(0), C, C.stride(1), C.stride(0), flags, stream)
     return C
 
 

@@ -16,7 +16,7 @@ import numpy as np
 
 CLS_F64, CLS_I8, CLS_LIMB2, CLS_LIMB3 = 0, 1, 2, 3
 (OP_S1S2, OP_S34, OP_GEMM, OP_SYRK, OP_POSTADD, OP_ADDLOW, OP_SAVEC22, OP_MIRROR, OP_PACK, OP_COPY,
- OP_LINCOMB) = range(11)
+ OP_LINCOMB, OP_LCT) = range(12)
 
 
 @dataclass
@@ -42,6 +42,7 @@ class Op:
     beta: int
     level: int
     v: list = field(default_factory=list)
+    coef: list = field(default_factory=lambda: [1] * 5)
 
 
 @dataclass
@@ -63,7 +64,8 @@ def parse(text: str) -> Plan:
     for ln in lines[1:]:
         f = [int(x) for x in ln.split()[1:]]
         views = [View(*f[12 + 4 * i: 16 + 4 * i]) for i in range(6)]
-        ops.append(Op(*f[:12], v=views))
+        coef = f[36:41] if len(f) >= 41 else [1] * 5
+        ops.append(Op(*f[:12], v=views, coef=coef))
     return Plan(int(head["cls"]), int(head["depth"]), int(head["n_pad"]), int(head["k_pad"]),
                 int(head["ws"]), int(head["ya"]), int(head["yb"]), ops)
 
@@ -171,11 +173,16 @@ class Sim:
         if o.mode & 2:
             self.put(o.v[4], c, (S3 + self.get(o.v[2], c, m, h)) % p)
 
-    def op2(self, o):   # C = alpha A B^T + beta C
+    def op2(self, o):   # C = alpha A B^T + beta C (mode bit 0: lower triangle only)
         A = self.get(o.v[0], o.cls, o.m, o.k)
         B = self.get(o.v[1], o.cls, o.n, o.k)
         C = self.get(o.v[2], CLS_F64, o.m, o.n)
-        self.put(o.v[2], CLS_F64, (o.alpha * (matmul_nt(A, B) % self.p) + o.beta * C) % self.p)
+        R = (o.alpha * (matmul_nt(A, B) % self.p) + o.beta * C) % self.p
+        if o.mode & 1:
+            low = np.tril(np.ones((o.m, o.n), dtype=bool))
+            C[low] = R[low]
+            R = C
+        self.put(o.v[2], CLS_F64, R)
 
     def op3(self, o):   # lower(C) = alpha A A^T + beta lower(C)
         n = o.m
@@ -226,12 +233,28 @@ class Sim:
         self.put(o.v[1], CLS_F64, D)
         self.put(o.v[2], CLS_F64, np.diag(S)[None, :])
 
-    def op7(self, o):   # Up(C) = Low(C)^T
+    def op7(self, o):   # Up(C) = Low(C)^T (mode bit 0: -Low(C)^T)
         m = o.m
         C = self.get(o.v[0], CLS_F64, m, m)
         up = np.triu(np.ones((m, m), dtype=bool), 1)
-        C[up] = C.T[up]
+        C[up] = (-C.T[up] % self.p) if o.mode & 1 else C.T[up]
         self.put(o.v[0], CLS_F64, C)
+
+    def op11(self, o):  # v5 = sum coef_i op_i(v_i) mod p (bit 3 + i: transpose; bit 8: lower only)
+        acc = np.zeros((o.m, o.k), dtype=object)
+        for i in range(o.mode & 7):
+            if (o.mode >> (3 + i)) & 1:
+                X = self.get(o.v[i], CLS_F64, o.k, o.m).T
+            else:
+                X = self.get(o.v[i], CLS_F64, o.m, o.k)
+            acc = acc + int(o.coef[i]) * X.astype(object)
+        R = np.array(acc % self.p, dtype=np.int64)
+        if (o.mode >> 8) & 1:
+            C = self.get(o.v[5], CLS_F64, o.m, o.k)
+            low = np.tril(np.ones((o.m, o.k), dtype=bool))
+            C[low] = R[low]
+            R = C
+        self.put(o.v[5], CLS_F64, R)
 
     def op8(self, o):   # pack with zero padding
         src = self.get(o.v[0], o.src_cls, o.m_src, o.k_src)
@@ -255,6 +278,22 @@ class Sim:
         else:
             Y = X
         self.put(o.v[1], CLS_F64, Y)
+
+
+def simulate_complex(plan_text: str, p: int, A: np.ndarray, order=None):
+    """Run a complex schedule (A of shape (2, n, k), planes stacked) on host
+    copies; returns the (2, n, n) result planes."""
+    plan = parse(plan_text)
+    _, n, k = A.shape
+    bufA = bytearray(np.ascontiguousarray(A, dtype=np.uint32).tobytes())
+    C = np.zeros((2, n, n), dtype=np.uint32)
+    bufC = bytearray(C.tobytes())
+    bufW = bytearray(max(plan.ws, 16))
+    rng = np.random.default_rng(4321)
+    bufW[:] = rng.integers(0, 256, size=len(bufW), dtype=np.uint8).tobytes()
+    sim = Sim([bufA, bufC, bufW], p, plan)
+    sim.run(order)
+    return np.frombuffer(bytes(bufC), dtype=np.uint32).reshape(2, n, n).copy()
 
 
 def simulate(plan_text: str, p: int, A_bytes: bytes, C: np.ndarray, order=None) -> np.ndarray:

@@ -119,3 +119,15 @@ def test_syrkbd_argument_checks():
     assert ffp.lib().fsyrkbd_modp(4, 4, 7, 16, 4, 16, 16, 7, 0, 16, 4, None, 0, None) == ffp.FFP_EINVAL
     assert ffp.lib().fsyrkbd_modp(-1, 4, 7, 16, 4, 16, 16, 1, 0, 16, 4, None, 0, None) == ffp.FFP_EINVAL
     assert ffp.lib().fsyrkbd_modp(0, 4, 7, 16, 4, 16, 16, 1, 0, 16, 4, None, 0, None) == ffp.FFP_OK
+
+
+def test_complex_argument_checks():
+    L = ffp.lib()
+    for f in (L.fzsyrk_modp, L.fherk_modp):
+        assert f(4, 4, 2, 16, 4, 16, 16, 4, 16, 0, None) == ffp.FFP_EPRIME
+        assert f(4, 4, 9, 16, 4, 16, 16, 4, 16, 0, None) == ffp.FFP_EPRIME
+        assert f(4, 4, 7, 16, 3, 16, 16, 4, 16, 0, None) == ffp.FFP_EINVAL   # lda < k
+        assert f(4, 4, 7, 16, 4, 8, 16, 4, 16, 0, None) == ffp.FFP_EINVAL    # planes of A overlap
+        assert f(4, 4, 7, 16, 4, 16, 16, 4, 8, 0, None) == ffp.FFP_EINVAL    # planes of C overlap
+        assert f(4, 4, 7, 16, 4, 16, 16, 4, 16, 0x100, None) == ffp.FFP_EINVAL
+        assert f(0, 4, 7, 16, 4, 16, 16, 4, 16, 0, None) == ffp.FFP_OK
