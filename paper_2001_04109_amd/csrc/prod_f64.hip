@@ -276,6 +276,16 @@ __device__ __forceinline__ void f64_bload(F64Raw& pf, __amdgpu_buffer_rsrc_t rs,
     }
 }
 
+// Pass ps of f64_bload.
+__device__ __forceinline__ void f64_bload1(F64Raw& pf, __amdgpu_buffer_rsrc_t rs, int ld, int k0, int K, int ps)
+{
+    const int idx = ps * 512 + threadIdx.x;
+    const int r = idx >> 3, c = (idx & 7) * 4;
+    const uint32_t out = (uint32_t)(K - 4 - c - k0) >> 31;
+    const uint32_t off = ((uint32_t)(r * ld + k0 + c) * 4u) | (out << 31);
+    pf.v[ps] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+}
+
 // Convert and write one stage's panel to LDS (row r, 4 doubles).  The
 // residues stay in [0, p): one conversion per value, no centring; the
 // launcher only picks this kernel when k (p - 1)^2 stays below 2^53.
@@ -292,6 +302,30 @@ __device__ __forceinline__ void f64_dstore(double* __restrict__ lds, const F64Ra
         d.z = (double)v.z;
         d.w = (double)v.w;
         *reinterpret_cast<v4d*>(lds + r * PD + c) = d;
+    }
+}
+
+// Pass ps of f64_dstore.
+__device__ __forceinline__ void f64_dstore1(double* __restrict__ lds, const F64Raw& pf, int ps)
+{
+    const int idx = ps * 512 + threadIdx.x;
+    const int r = idx >> 3, c = (idx & 7) * 4;
+    const v4u v = pf.v[ps];
+    v4d d;
+    d.x = (double)v.x;
+    d.y = (double)v.y;
+    d.z = (double)v.z;
+    d.w = (double)v.w;
+    *reinterpret_cast<v4d*>(lds + r * PD + c) = d;
+}
+
+template <int N> using IntC = std::integral_constant<int, N>;
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(IntC<B>{});
+        static_for<B + 1, E>(f);
     }
 }
 }  // namespace
@@ -365,43 +399,57 @@ __device__ __forceinline__ void f64_pipe_tile(const ProdArgs& args, int b)
         v4d fa[WM2], fb[WN2];
         read_frags(fa, fb, 0, 0);
 
+        // One k-group: its 32 MFMAs with the NOPS other operations between
+        // them in a fixed order (a scheduling barrier after each).  Left to
+        // the compiler's grouping the LDS writes and reads clustered between
+        // MFMAs, which then waited for them (7 % slower).
+        auto kgroup = [&](const v4d (&xa)[WM2], const v4d (&xb)[WN2], auto nops, auto&& op) {
+            constexpr int NOPS = decltype(nops)::value;
+            static_for<0, 4 * WM2 * WN2>([&](auto q) {
+                constexpr int Q = decltype(q)::value;
+                constexpr int S4 = Q / (WM2 * WN2), I = (Q / WN2) % WM2, J = Q % WN2;
+                acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][S4], xb[J][S4], acc[I][J], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                static_for<Q * NOPS / (4 * WM2 * WN2), (Q + 1) * NOPS / (4 * WM2 * WN2)>([&](auto o) {
+                    op(o);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            });
+        };
+        // fragment o of k-group kg: A blocks 0..WM2-1, then B blocks
+        auto rd1 = [&](v4d (&xa)[WM2], v4d (&xb)[WN2], int buf, int kg, int o) {
+            if (o < WM2)
+                xa[o] = *reinterpret_cast<const v4d*>(&sa[buf][(wr * 64 + o * 16 + lr) * PD + kg * 16 + 4 * lk]);
+            else
+                xb[o - WM2] = *reinterpret_cast<const v4d*>(
+                    &sb[buf][(wc * G::WTN + (o - WM2) * 16 + lr) * PD + kg * 16 + 4 * lk]);
+        };
         auto stage = [&](auto par, int kt) {
             constexpr int cur = decltype(par)::value;
             F64Raw& la = cur ? a1 : a0;   // reloaded now (its stage is in LDS)
             F64Raw& lb = cur ? b1 : b0;
             F64Raw& wa = cur ? a0 : a1;   // stage kt + 1, written now
             F64Raw& wb = cur ? b0 : b1;
-            __builtin_amdgcn_sched_barrier(0);
-            f64_bload(la, ra, lda, (kt + 2) * BK2, K);
-            f64_bload(lb, rb, ldb, (kt + 2) * BK2, K);
-            __builtin_amdgcn_sched_barrier(0);
             v4d na[WM2], nb[WN2];
-            // k-group 0: stage kt + 1 to LDS, k-group 1's fragments read
-            read_frags(na, nb, cur, 1);
-            f64_dstore(sa[cur ^ 1], wa);
-            f64_dstore(sb[cur ^ 1], wb);
-            mfmas(fa, fb);
-            // per quarter: 3 reads, 2 MFMAs, 4 conversions, 2 LDS writes,
-            // 6 MFMAs
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                __builtin_amdgcn_sched_group_barrier(0x100, NRD / 4, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-                __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
-                __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, NMF / 4 - 2, 0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            // k-group 0: the fragments of k-group 1, stage kt + 1 converted
+            // into the free LDS buffer, the loads of stage kt + 2
+            static_assert(WM2 + WN2 == 6, "the operation order below assumes 6 fragments");
+            kgroup(fa, fb, std::integral_constant<int, 14>{}, [&](auto o) {
+                constexpr int O = decltype(o)::value;
+                if constexpr (O % 2 == 0 && O < 12) rd1(na, nb, cur, 1, O / 2);
+                else if constexpr (O == 1) f64_dstore1(sa[cur ^ 1], wa, 0);
+                else if constexpr (O == 3) f64_dstore1(sa[cur ^ 1], wa, 1);
+                else if constexpr (O == 5) f64_dstore1(sb[cur ^ 1], wb, 0);
+                else if constexpr (O == 7) f64_dstore1(sb[cur ^ 1], wb, 1);
+                else if constexpr (O == 9) f64_bload1(la, ra, lda, (kt + 2) * BK2, K, 0);
+                else if constexpr (O == 11) f64_bload1(la, ra, lda, (kt + 2) * BK2, K, 1);
+                else if constexpr (O == 12) f64_bload1(lb, rb, ldb, (kt + 2) * BK2, K, 0);
+                else f64_bload1(lb, rb, ldb, (kt + 2) * BK2, K, 1);
+            });
             __syncthreads();
             // k-group 1 with the first fragments of stage kt + 1
-            read_frags(fa, fb, cur ^ 1, 0);
-            mfmas(na, nb);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                __builtin_amdgcn_sched_group_barrier(0x100, NRD / 4, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, NMF / 4, 0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            kgroup(na, nb, std::integral_constant<int, 6>{},
+                   [&](auto o) { rd1(fa, fb, cur ^ 1, 0, decltype(o)::value); });
         };
         for (int kt = 0; kt < nk; kt += 2) {
             stage(std::integral_constant<int, 0>{}, kt);
