@@ -75,9 +75,9 @@ void ffp_debug_set_kblk(int64_t kblk);
  * of the per-level launch; 0: as separate product launches),
  * "i8_tile" (128 or 256: force the int8 product tile; 0 = automatic),
  * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile),
- * "i8_dma" (1, the default: the 256 x 256 int8 tile with 128-byte k stages
- * loads its operands straight into LDS, no staging registers; 0: through
- * registers as "i8_pipe" says), "i8_pipe" (1, the default: with "i8_dma" 0,
+ * "i8_dma" (1, the default: the 256 x 256 int8 tile and the 128 x 128
+ * two-limb tile with 128-byte k stages load their operands straight into
+ * LDS, no staging registers; 0: through registers as "i8_pipe" says), "i8_pipe" (1, the default: with "i8_dma" 0,
  * the 256 x 256 int8 tile with 128-byte k stages writes each stage's
  * operands to LDS between the MFMAs of the previous stage and loads them up
  * to two stages ahead; 0: the stage's LDS writes after its MFMAs), "f64_pipe" (1, the default: the
@@ -118,7 +118,8 @@ int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches
 /* Same, restricted to one product-kernel variant (0 FP64 64x64 tiles, 1 FP64
  * 128x128 LDS-staged tiles, 2 int8 128x128, 3 int8 256x256 with 64-byte k
  * stages, 4 int8 256x256 with 128-byte k stages, 5 int8 limbs 128x128,
- * 6 int8 256x256 with operands straight to LDS, 8 FP64
+ * 6 int8 256x256 with operands straight to LDS, 7 int8 limbs 128x128
+ * straight to LDS, 8 FP64
  * 128x128 with 8 waves, 9 int8 three limbs 64x64, 10 int8 256x256 with the
  * LDS writes between the MFMAs, 11 FP64 128x128 with doubles in LDS);
  * ffp_debug_variant_name gives the kernel's demangled name. */

@@ -315,7 +315,8 @@ const char* ffp_debug_variant_name(int variant)
     case 3: return "void ffp::prod_i8_kernel<256, 256, 64, 1>(ffp::ProdArgs, int)";
     case 4: return "void ffp::prod_i8_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";
     case 5: return "void ffp::prod_i8_kernel<128, 128, 64, 2>(ffp::ProdArgs, int)";
-    case 6: return "ffp::prod_i8_dma_kernel(ffp::ProdArgs, int)";
+    case 6: return "void ffp::prod_i8_dma_kernel<1>(ffp::ProdArgs, int)";
+    case 7: return "void ffp::prod_i8_dma_kernel<2>(ffp::ProdArgs, int)";
     case 8: return "void ffp::prod_f64_lds_kernel<8>(ffp::ProdArgs, int)";
     case 9: return "void ffp::prod_i8_kernel<64, 64, 64, 3>(ffp::ProdArgs, int)";
     case 10: return "void ffp::prod_i8_pipe_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";

@@ -90,7 +90,8 @@ extern int g_f64_pipe;         // FP64 128x128, 8 waves: operands as doubles in 
 // thread (0: the launch rule or the override above); set from the tuned
 // choice of the call's plan.
 extern thread_local int g_tile_hint;
-extern int g_i8_dma;           // CLS_I8 256x256, k a multiple of 128: operands straight to LDS (1, default)
+extern int g_i8_dma;           // CLS_I8 256x256 / CLS_LIMB2 128x128, k a multiple of 128: operands
+                               // straight to LDS (1, default)
 extern int g_i8_pipe;          // CLS_I8 256x256x128: LDS writes spread over the MFMAs, loads two stages ahead
 // Multi-task product launches run persistent workgroups (1, default) or one
 // workgroup per tile (0).
@@ -98,7 +99,8 @@ extern int g_persistent;
 // Product-kernel variant chosen by the most recent launch on this thread
 // (for the timing hooks): 0 FP64 64x64, 1 FP64 128x128 LDS (4 waves), 2 int8
 // 128x128, 3 int8 256x256 (k stage 64), 4 int8 256x256 (k stage 128), 5 int8
-// limbs, 6 int8 256x256 straight to LDS, 8 FP64 128x128 LDS (8 waves), 9 int8
+// limbs, 6 int8 256x256 straight to LDS, 7 limbs 128x128 straight to LDS, 8 FP64
+// 128x128 LDS (8 waves), 9 int8
 // three limbs, 10 int8 256x256 register-staged, 11 FP64 doubles in LDS, 12 limbs
 // register-staged.
 extern thread_local int g_last_variant;

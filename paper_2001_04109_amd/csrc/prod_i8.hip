@@ -354,25 +354,70 @@ typedef __attribute__((address_space(3))) void LdsVoid;
 
 __device__ __forceinline__ int dma_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
-template <bool EDGE>
+// Epilogue of a two-limb wave tile (hh, ll and hl + lh accumulators):
+// 2^16 hh + 2^8 x + ll mod p, then alpha and beta.
+template <int WTM, int WTN, int FM, int FN>
+__device__ __forceinline__ void store_tile_limb2(const v16i (&acc)[3][FM][FN], const ProdTask& t, int row0,
+                                                 int col0, bool live)
+{
+    if (!live) return;
+    const int lane = threadIdx.x & 63, lrow = lane & 31, lk = lane >> 5;
+    const double pd = (double)t.p;
+    const double alpha = (double)t.alpha, beta = (double)t.beta;
+    const double r16 = (double)((65536u) % t.p), r8 = (double)(256u % t.p);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = col0 + j * 32 + lrow;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = row0 + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
+                if (row >= t.m || col >= t.n) continue;
+                if (t.syrk && col > row) continue;
+                const double hh = mod_f64((double)acc[0][i][j][e], pd, t.pinv);
+                const double ll = mod_f64((double)acc[1][i][j][e], pd, t.pinv);
+                const double xx = mod_f64((double)acc[2][i][j][e], pd, t.pinv);
+                const double v = mod_f64(hh * r16 + xx * r8 + ll, pd, t.pinv);
+                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                double x = alpha * v;
+                if (t.beta != 0u) x += beta * (double)(*dst);
+                *dst = (uint32_t)mod_f64(x, pd, t.pinv);
+            }
+        }
+}
+
+// PLANES = 1: centred int8 on 256 x 256 tiles (one accumulator);
+// PLANES = 2: two int8 limbs on 128 x 128 tiles (hh, ll and hl + lh
+// accumulators).  Either way a wave issues 16 MFMAs and reads 8 fragments
+// per k-step, and a stage is 64 blocks of 1 KB: the A and B panels (and
+// their planes) one after the other.
+template <int PLANES, bool EDGE>
 __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, int8_t* smem)
 {
-    constexpr int BM = 256, BN = 256, BK = 128;
+    constexpr int BM = PLANES == 1 ? 256 : 128, BN = BM, BK = 128;
     constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 32, FN = WTN / 32;
-    static_assert(FM == 4 && FN == 4, "the k-step order below assumes 4 x 4 blocks per wave");
-    constexpr int BUF = (BM + BN) * BK;
+    constexpr int NACC = PLANES == 1 ? 1 : 3;
+    constexpr int NFRAG = PLANES * (FM + FN);
+    static_assert(NFRAG == 8 && FM * FN * PLANES * PLANES == 16, "16 MFMAs and 8 fragment reads per k-step");
+    constexpr int REGION = BM * BK;                 // bytes of one plane of one panel per stage
+    constexpr int BUF = 2 * PLANES * REGION;        // A planes then B planes
+    static_assert(BUF == 64 * 1024, "64 blocks of 1 KB per stage");
+    constexpr int RBLK = BM / 8;                    // 1 KB blocks per region
     const int tile_r = ti * BM, tile_c = tj * BN;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wr = wave >> 1, wc = wave & 1;
     const int lrow = lane & 31, lk = lane >> 5;
 
-    v16i acc[FM][FN];
+    v16i acc[NACC][FM][FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int q = 0; q < NACC; ++q)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0;
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[q][i][j][e] = 0;
     const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
 
     const int nk = t.k / BK;
@@ -381,27 +426,27 @@ __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, i
         const int vb = t.n - tile_c < BN ? t.n - tile_c : BN;
         const int lda = __builtin_amdgcn_readfirstlane((int)t.A.ld);
         const int ldb = __builtin_amdgcn_readfirstlane((int)t.B.ld);
-        const __amdgpu_buffer_rsrc_t ra =
-            panel_rsrc((const int8_t*)t.A.p + (int64_t)tile_r * t.A.ld, (int64_t)va * t.A.ld);
-        const __amdgpu_buffer_rsrc_t rb =
-            panel_rsrc((const int8_t*)t.B.p + (int64_t)tile_c * t.B.ld, (int64_t)vb * t.B.ld);
-        // load q (0..15) of a stage: blocks 8 wave + (q & 7) of the A (q < 8) or B panel
+        // this wave loads blocks 16 wave .. 16 wave + 15 of a stage, all in
+        // one region (panel and plane): region = 16 wave / RBLK
+        const int region = (16 * wave) / RBLK, blk0 = (16 * wave) % RBLK;
+        const bool isB = region >= PLANES;
+        const int pl = region % PLANES;
+        const int ld = isB ? ldb : lda;
+        const __amdgpu_buffer_rsrc_t rs = isB
+            ? panel_rsrc((const int8_t*)t.B.p + pl * t.B.plane + (int64_t)tile_c * t.B.ld, (int64_t)vb * t.B.ld)
+            : panel_rsrc((const int8_t*)t.A.p + pl * t.A.plane + (int64_t)tile_r * t.A.ld, (int64_t)va * t.A.ld);
         const int lr8 = lane >> 3, slot = lane & 7;
-        const int va0 = lr8 * lda + 16 * (slot ^ lr8), va1 = lr8 * lda + 16 * (slot ^ lr8 ^ 1);
-        const int vb0 = lr8 * ldb + 16 * (slot ^ lr8), vb1 = lr8 * ldb + 16 * (slot ^ lr8 ^ 1);
+        const int v0 = lr8 * ld + 16 * (slot ^ lr8), v1 = lr8 * ld + 16 * (slot ^ lr8 ^ 1);
         auto dload = [&](int q, int stg, bool live) {
             const uint32_t dead = live ? 0u : 0x80000000u;
-            const bool isB = q >= 8;
-            const int blk = wave * 8 + (q & 7);
-            int8_t* dst = smem + (stg & 1) * BUF + (isB ? BM * BK : 0) + blk * 1024;
-            const int ld = isB ? ldb : lda;
-            const int v = isB ? ((blk & 1) ? vb1 : vb0) : ((blk & 1) ? va1 : va0);
+            const int blk = blk0 + q;
+            int8_t* dst = smem + (stg & 1) * BUF + region * REGION + blk * 1024;
+            const int v = (blk & 1) ? v1 : v0;
             if constexpr (EDGE) {
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(isB ? rb : ra, (LdsVoid*)dst, 16,
-                                                         (uint32_t)(v + 8 * blk * ld) + dead,
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsVoid*)dst, 16, (uint32_t)(v + 8 * blk * ld) + dead,
                                                          __builtin_amdgcn_readfirstlane(stg * BK), 0, 0);
             } else {
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(isB ? rb : ra, (LdsVoid*)dst, 16, (uint32_t)v + dead,
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsVoid*)dst, 16, (uint32_t)v + dead,
                                                          __builtin_amdgcn_readfirstlane(stg * BK + 8 * blk * ld),
                                                          0, 0);
             }
@@ -410,16 +455,29 @@ __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, i
         int coff[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) coff[ks] = 16 * ((2 * ks + lk) ^ sw);
-        const int rowA = (wr * WTM + lrow) * BK, rowB = BM * BK + (wc * WTN + lrow) * BK;
-        v4i fa[FM], fb[FN], na[FM], nb[FN];
-        // fragment o of a k-step, in the order the MFMAs use them: a0 b0 b1 b2 b3 a1 a2 a3
-        auto rd = [&](v4i (&xa)[FM], v4i (&xb)[FN], int buf, int ks, int o) {
+        const int rowA = (wr * WTM + lrow) * BK, rowB = PLANES * REGION + (wc * WTN + lrow) * BK;
+        v4i fa[PLANES][FM], fb[PLANES][FN], na[PLANES][FM], nb[PLANES][FN];
+        // fragment o of a k-step, in the order the MFMAs first use them
+        auto rd = [&](v4i (&xa)[PLANES][FM], v4i (&xb)[PLANES][FN], int buf, int ks, int o) {
             const int8_t* base = smem + buf * BUF + coff[ks];
-            if (o == 0 || o >= 5) {
-                const int i = o == 0 ? 0 : o - 4;
-                xa[i] = *reinterpret_cast<const v4i*>(base + rowA + i * 32 * BK);
+            if constexpr (PLANES == 1) {
+                // a0 b0 b1 b2 b3 a1 a2 a3
+                if (o == 0 || o >= 5) {
+                    const int i = o == 0 ? 0 : o - 4;
+                    xa[0][i] = *reinterpret_cast<const v4i*>(base + rowA + i * 32 * BK);
+                } else {
+                    xb[0][o - 1] = *reinterpret_cast<const v4i*>(base + rowB + (o - 1) * 32 * BK);
+                }
             } else {
-                xb[o - 1] = *reinterpret_cast<const v4i*>(base + rowB + (o - 1) * 32 * BK);
+                // ah0 bh0 al0 bl0 bh1 bl1 ah1 al1 (planes: 0 = hi, 1 = lo)
+                constexpr int kA = 0, kB = 1;
+                const int who[8] = {kA, kB, kA, kB, kB, kB, kA, kA};
+                const int pli[8] = {0, 0, 1, 1, 0, 1, 0, 1};
+                const int idx[8] = {0, 0, 0, 0, 1, 1, 1, 1};
+                if (who[o] == kA)
+                    xa[pli[o]][idx[o]] = *reinterpret_cast<const v4i*>(base + pli[o] * REGION + rowA + idx[o] * 32 * BK);
+                else
+                    xb[pli[o]][idx[o]] = *reinterpret_cast<const v4i*>(base + pli[o] * REGION + rowB + idx[o] * 32 * BK);
             }
         };
         // the previous tile of a persistent workgroup may still read LDS
@@ -431,12 +489,21 @@ __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, i
         for (int o = 0; o < 8; ++o) rd(fa, fb, 0, 0, o);
         // one k-step: 16 MFMAs on (xa, xb), the NOPS other operations spread
         // between them in order
-        auto kstep = [&](const v4i (&xa)[FM], const v4i (&xb)[FN], auto nops, auto&& op) {
+        auto kstep = [&](const v4i (&xa)[PLANES][FM], const v4i (&xb)[PLANES][FN], auto nops, auto&& op) {
             constexpr int NOPS = decltype(nops)::value;
             static_for<0, 16>([&](auto q) {
                 constexpr int Q = decltype(q)::value;
-                acc[Q / 4][Q % 4] =
-                    __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[Q / 4], xb[Q % 4], acc[Q / 4][Q % 4], 0, 0, 0);
+                if constexpr (PLANES == 1) {
+                    acc[0][Q / 4][Q % 4] =
+                        __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[0][Q / 4], xb[0][Q % 4], acc[0][Q / 4][Q % 4], 0, 0, 0);
+                } else {
+                    // block (i, j) = (Q / 8, (Q / 4) % 2); products hh, ll, hl, lh
+                    constexpr int I = Q / 8, J = (Q / 4) % 2, W = Q % 4;
+                    constexpr int PA = (W == 0 || W == 2) ? 0 : 1, PB = (W == 0 || W == 3) ? 0 : 1;
+                    constexpr int ACC = W == 0 ? 0 : (W == 1 ? 1 : 2);
+                    acc[ACC][I][J] =
+                        __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[PA][I], xb[PB][J], acc[ACC][I][J], 0, 0, 0);
+                }
                 __builtin_amdgcn_sched_barrier(0);
                 static_for<Q * NOPS / 16, (Q + 1) * NOPS / 16>([&](auto o) {
                     op(o);
@@ -473,30 +540,36 @@ __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, i
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
-    store_tile_i8_reg<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+    if constexpr (PLANES == 1)
+        store_tile_i8_reg<WTM, WTN, FM, FN>(acc[0], t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+    else
+        store_tile_limb2<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
 }
 
+template <int PLANES>
 __device__ __forceinline__ void i8_dma_tile(const ProdArgs& args, int b)
 {
-    __shared__ __attribute__((aligned(1024))) int8_t smem[2 * 512 * 128];
+    constexpr int BM = PLANES == 1 ? 256 : 128;
+    __shared__ __attribute__((aligned(1024))) int8_t smem[2 * 64 * 1024];
     ProdTask t;
     select_task(args, b, &t);
     const int r = b - t.tile0;
     int ti, tj;
     if (t.syrk) band_tri(r, t.tm, &ti, &tj);
     else band_rect(r, t.tm, t.tn, &ti, &tj);
-    if ((ti + 1) * 256 <= t.m && (tj + 1) * 256 <= t.n) i8_dma_body<false>(t, ti, tj, smem);
-    else i8_dma_body<true>(t, ti, tj, smem);
+    if ((ti + 1) * BM <= t.m && (tj + 1) * BM <= t.n) i8_dma_body<PLANES, false>(t, ti, tj, smem);
+    else i8_dma_body<PLANES, true>(t, ti, tj, smem);
 }
 
+template <int PLANES>
 __global__ __launch_bounds__(256) void prod_i8_dma_kernel(ProdArgs args, int mode)
 {
     if (mode == 2) {
-        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) i8_dma_tile(args, b);
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) i8_dma_tile<PLANES>(args, b);
         return;
     }
     const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    if (b < args.total_tiles) i8_dma_tile(args, b);
+    if (b < args.total_tiles) i8_dma_tile<PLANES>(args, b);
 }
 
 template <int BM, int BN, int BK, int PLANES>
@@ -565,13 +638,14 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
     const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
     int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
     if constexpr (RING > 0) {
-        static_assert(BM == 256 && BN == 256 && PLANES == 1 && BK == 128, "direct-to-LDS variant: CLS_I8 256-tiles");
+        static_assert(BK == 128 && ((PLANES == 1 && BM == 256) || (PLANES == 2 && BM == 128)) && BN == BM,
+                      "direct-to-LDS variant: int8 256-tiles or two limbs on 128-tiles");
         if (mode == 2) {
-            const int resident = resident_blocks((const void*)prod_i8_dma_kernel);
+            const int resident = resident_blocks((const void*)prod_i8_dma_kernel<PLANES>);
             grid = total < resident ? total : resident;
         }
-        g_last_variant = 6;
-        hipLaunchKernelGGL(prod_i8_dma_kernel, dim3(grid), dim3(256), 0, s, args, mode);
+        g_last_variant = PLANES == 1 ? 6 : 7;
+        hipLaunchKernelGGL((prod_i8_dma_kernel<PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
     } else if constexpr (RING < 0) {
         static_assert(PLANES <= 2 && BK == 128, "pipelined variant: int8 or two limbs, 128-byte stages");
         if (mode == 2) {
@@ -701,6 +775,7 @@ hipError_t launch_products_limb2(ProdTask* tasks, int ntasks, ProdTask* dev_task
     bool pipe = g_i8_pipe != 0;
     for (int i = 0; i < ntasks && pipe; ++i)
         pipe = (tasks[i].k % 128) == 0 && tasks[i].A.ld < (1 << 23) && tasks[i].B.ld < (1 << 23);
+    if (pipe && g_i8_dma) return launch_i8_impl<128, 128, 128, 2, 1>(tasks, ntasks, dev_task_buf, s);
     if (pipe) return launch_i8_impl<128, 128, 128, 2, -1>(tasks, ntasks, dev_task_buf, s);
     return launch_i8_impl<128, 128, 64, 2>(tasks, ntasks, dev_task_buf, s);
 }

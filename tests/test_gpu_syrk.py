@@ -178,6 +178,7 @@ def test_limb2_pipe_variant(pipe, n, k, dtype):
     A[:3] = p - 1
     A[3:5] = (p - 1) // 2
     a_dtype = ffp.FFP_I8_LIMB2 if dtype == "limb2" else ffp.FFP_U32
+    set_knob("i8_dma", 0)
     set_knob("i8_pipe", pipe)
     try:
         check_lower(gpu_syrk(A, p, depth=0, a_dtype=a_dtype), oracle.syrk(A, p))
@@ -190,6 +191,7 @@ def test_limb2_pipe_variant(pipe, n, k, dtype):
     finally:
         set_kblk(0)
         set_knob("i8_pipe", 1)
+        set_knob("i8_dma", 1)
 
 
 @pytest.mark.parametrize("p", [65537, 131071])
@@ -246,6 +248,31 @@ def test_i8_tile_variants(tile, n, k):
         check_lower(gpu_syrk(A, p, depth=0, alpha=3, beta=5, C0=C0), oracle.syrk_ab(A, p, 3, 5, C0))
     finally:
         set_knob("i8_tile", 0)
+
+
+@pytest.mark.parametrize("n,k,dtype", [(300, 256, "limb2"), (513, 128, "u32"), (256, 384, "limb2"),
+                                       (1000, 640, "u32"), (130, 1000, "u32"), (700, 2048, "limb2")])
+def test_limb2_dma_variant(n, k, dtype):
+    """Two int8 limbs on 128 x 128 tiles with operands straight to LDS (the
+    default): limb operands given or packed from uint32, one, two and odd
+    stage counts, partial panels, alpha/beta, entries at the ends of the
+    range, k in chunks."""
+    p = 65521
+    A = inputs.uniform(n + 3 * k, n, k, p)
+    A[:3] = p - 1
+    A[3:5] = (p - 1) // 2
+    a_dtype = ffp.FFP_I8_LIMB2 if dtype == "limb2" else ffp.FFP_U32
+    check_lower(gpu_syrk(A, p, depth=0, a_dtype=a_dtype), oracle.syrk(A, p))
+    C0 = inputs.uniform(12, n, n, p)
+    check_lower(gpu_syrk(A, p, depth=0, alpha=p - 1, beta=1, C0=C0, a_dtype=a_dtype),
+                oracle.syrk_ab(A, p, p - 1, 1, C0))
+    set_kblk(384)      # chunks of whole 128-byte stages
+    try:
+        check_lower(gpu_syrk(A, p, depth=0, alpha=3, beta=5, C0=C0, a_dtype=a_dtype),
+                    oracle.syrk_ab(A, p, 3, 5, C0))
+        check_lower(gpu_syrk(A, p, depth=1), oracle.syrk(A, p))
+    finally:
+        set_kblk(0)
 
 
 @pytest.mark.parametrize("dma", [1, 0])
@@ -486,7 +513,7 @@ def test_full_size_8192_p131071_three_limbs(k):
 
 
 @pytest.mark.parametrize("p,a_dtype,dma", [(251, ffp.FFP_I8_CENTERED, 1), (251, ffp.FFP_I8_CENTERED, 0),
-                                           (65521, ffp.FFP_I8_LIMB2, 1)])
+                                           (65521, ffp.FFP_I8_LIMB2, 1), (65521, ffp.FFP_I8_LIMB2, 0)])
 def test_full_size_16384_int8(p, a_dtype, dma):
     """The 16384^2 workloads in the launch configuration the benchmark
     times: every 256 x 256 output tile sampled against the oracle."""
@@ -504,4 +531,4 @@ def test_full_size_16384_int8(p, a_dtype, dma):
         torch.cuda.synchronize()
     finally:
         set_knob("i8_dma", 1)
-    _sampled(A, p, from_dev_u32(Cd), tile=256)
+    _sampled(A, p, from_dev_u32(Cd), tile=256 if p <= 251 else 128)
