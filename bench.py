@@ -14,7 +14,8 @@ launch in the timed region; the CPU baseline is the oracle on a bounded row
 panel of the same product.  The "extra" object reports, in this order, the
 int8 and int8-limb products of 16384 x 16384 (with the vendor library's int8
 GEMM on the same shape as context) and the three-limb form of the default
-workload, the served Poisson stream of A A^T and LDL^T requests (p50/p99
+workload, the products over F_p[i] and with block-diagonal scaling, the
+served Poisson stream of A A^T and LDL^T requests (p50/p99
 latency from arrival to completion, overall and per kind, throughput) with
 the same requests at once and per call for comparison, and the 1024-job
 batched form against the same jobs as per-call fsyrk_modp.
@@ -97,7 +98,7 @@ def profile_hooks():
     return L.ffp_debug_profile, read, read_variants
 
 
-def run_workload(name, steps, warmup, check=True):
+def run_workload(name, steps, warmup, check=True, keep_first=False):
     import torch
     from paper_2001_04109_amd import ffp, inputs
     import oracle
@@ -154,6 +155,8 @@ def run_workload(name, steps, warmup, check=True):
             got = Cd.cpu().numpy().view(np.uint32)[lo, hi]
             if not np.array_equal(got, oracle.syrk_entries(A, p, lo, hi)):
                 raise SystemExit(f"bench: {name} result differs from the oracle")
+    if keep_first:
+        res["first_c"] = outs[0].cpu().numpy().view(np.uint32)
     del devs, outs
     torch.cuda.empty_cache()
     return res
@@ -303,6 +306,17 @@ class OperandPool:
             raise SystemExit("bench: no generic-rank symmetric pool matrix in 8 draws")
         self.S = Sd
         self.LD = W      # packed L (strict lower) and D (diagonal) of the whole S
+        # the served LDL^T results are compared with leading blocks of LD;
+        # its leading 1024 x 1024 block is checked against the oracle's
+        # Crout factorisation here (the LDL^T of a leading block is the
+        # leading block of the whole factorisation)
+        import oracle
+        m = min(1024, nmax)
+        ref, rinfo = oracle.ldlt_packed(S[:m, :m].copy(), ldlt_prime)
+        got = W[:m, :m].cpu().numpy().view(np.uint32)
+        low = np.tril(np.ones((m, m), dtype=bool))
+        if rinfo != 0 or not np.array_equal(got[low], ref[low]):
+            raise SystemExit("bench: the pool's LDL^T differs from the oracle")
 
     def operand(self, r):
         if r["kind"] == "syrk":
@@ -312,10 +326,10 @@ class OperandPool:
 
 class ServedCheck:
     """Checks every stride-th served result (after the stream, before it is
-    released): LDL^T
-    results against the leading block of the pool's factorisation, A A^T
-    results on 32 sampled entries against the oracle.  Copies run on a side
-    stream of their own."""
+    released): LDL^T results against the leading block of the pool's GPU
+    factorisation (whose leading 1024 x 1024 block the pool checks against
+    the oracle), A A^T results on 32 sampled entries against the oracle.
+    Copies run on a side stream of their own."""
 
     def __init__(self, pool, stride=200):
         import torch
@@ -463,6 +477,61 @@ def per_call_plain(reqs, pool):
     return {"s": round(dt, 3), "gops_total": round(tot / dt / 1e9, 1)}
 
 
+def complex_and_block_diagonal(n=4096, k=4096, p=131071, reps=5):
+    """A A^T and A A^H over F_p[i] (p = 131071 = 3 mod 4: the field F_(p^2))
+    for a uniform n x k operand: Algorithm 2 at the default depth against
+    depth 0 (the 2M leaf alone), effective real Gop/s counted as 4 n^2 k
+    (the classical lower-triangle cost: n^2 k / 2 complex multiply-adds of 4
+    real ones, 2 operations each).  Then A B A^T with B block diagonal
+    (n / 8 antidiagonal 2 x 2 blocks, the rest scalar) against fsyrk_modp on
+    the same A: the cost of Algorithms 6 and 5 before the product."""
+    import torch
+    from paper_2001_04109_amd import ffp, inputs
+    rng = np.random.default_rng(11)
+    A = rng.integers(0, p, size=(2, n, k), dtype=np.uint64).astype(np.uint32)
+    Ad = torch.from_numpy(A.view(np.int32)).cuda()
+    C = torch.zeros((2, n, n), dtype=torch.int32, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"n": n, "k": k, "p": p}
+    for herk in (False, True):
+        tag = "herk" if herk else "zsyrk"
+        ms_d = timed(lambda: ffp.complex_syrk(Ad, p, herk=herk, C=C))
+        ms_0 = timed(lambda: ffp.complex_syrk(Ad, p, herk=herk, C=C, depth=0))
+        out[tag] = {"ms": round(ms_d, 3), "ms_depth0_2M": round(ms_0, 3),
+                    "gops_real_effective": round(4.0 * n * n * k / (ms_d * 1e-3) / 1e9, 1),
+                    "alg2_vs_2M": round(ms_0 / ms_d, 3)}
+    del Ad, C
+    B = inputs.uniform(12, n, k, p)
+    Bd = torch.from_numpy(B.view(np.int32)).cuda()
+    bdiag = rng.integers(0, p, size=k, dtype=np.uint64).astype(np.uint32)
+    boff = np.zeros(k - 1, dtype=np.uint32)
+    for j in range(0, k - 1, 16):       # every 16th column starts an antidiagonal block
+        boff[j] = rng.integers(1, p)
+        bdiag[j] = bdiag[j + 1] = 0
+    bd = torch.from_numpy(bdiag.view(np.int32)).cuda()
+    bo = torch.from_numpy(boff.view(np.int32)).cuda()
+    Cb = torch.zeros((n, n), dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ms_bd = timed(lambda: ffp.syrkbd(Bd, bd, bo, p, C=Cb, info=info))
+    ms_pl = timed(lambda: ffp.syrk(Bd, p, C=Cb))
+    if int(info.item()) != 0:
+        raise SystemExit("bench: fsyrkbd_modp reported a malformed block")
+    out["syrkbd"] = {"blocks_2x2": int(np.count_nonzero(boff)), "ms": round(ms_bd, 3),
+                     "ms_fsyrk_same_A": round(ms_pl, 3), "overhead": round(ms_bd / ms_pl, 3)}
+    return out
+
+
 def vendor_int8_gemm(n=16384, reps=5):
     """The vendor library's int8 GEMM (torch._int_mm, hipBLASLt on ROCm) on an
     n x n operand of centred residues mod 251 times its transpose, as context
@@ -488,10 +557,26 @@ def vendor_int8_gemm(n=16384, reps=5):
             "as_AAT_effective_gops": round(n ** 3 / (ms * 1e-3) / 1e9, 1)}
 
 
-def cpu_baseline(name):
-    """Oracle on a bounded sample: rows [n-r, n) of the lower triangle of the
-    first shape, i.e. r*(2n-r+1)/2 dot products of length k (r = n for the
-    8192 x 8192 product: its whole lower triangle)."""
+def _oracle_rate(A, p, r):
+    """Seconds and Gop/s (2 per multiply-add) of the oracle on rows
+    [n - r, n) of lower(A A^T), and those rows."""
+    import oracle
+    n, k = A.shape
+    t0 = time.perf_counter()
+    rows = oracle.syrk_rows(A, p, n - r, n)
+    dt = time.perf_counter() - t0
+    macs = r * (2 * n - r + 1) // 2 * k
+    return dt, 2.0 * macs / dt / 1e9, macs, rows
+
+
+def cpu_baseline(name, gpu_c=None):
+    """Oracle on bounded samples, on all host cores and on one.
+
+    Headline: rows [n-r, n) of the lower triangle of the first shape (r = n
+    for the 8192 x 8192 product: its whole lower triangle), compared entry
+    by entry with the GPU's result of the same product (the run fails on any
+    difference).  Then one thread on 64 of those rows, and all cores on a
+    row panel of the other workloads (the small 512 x 512 one in full)."""
     import oracle
     from paper_2001_04109_amd import inputs
     w = WORKLOADS[name]
@@ -499,14 +584,42 @@ def cpu_baseline(name):
     p = w["p"]
     A = inputs.uniform(w["seed"], n, k, p)
     r = n if n * n * k <= 8192 ** 3 else max(64, int(8192 ** 3 / (n * k)))
-    t0 = time.perf_counter()
-    oracle.syrk_rows(A, p, n - r, n)
-    dt = time.perf_counter() - t0
-    macs = r * (2 * n - r + 1) // 2 * k
-    return {"value": round(2.0 * macs / dt / 1e9, 3), "unit": "Gop/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"rows [{n - r},{n}) of lower(A A^T) for A {n}x{k} mod {p} "
-                      f"({macs:.3e} multiply-adds, {dt:.1f} s)"}
+    cores = oracle.num_threads()
+    dt, rate, macs, rows = _oracle_rate(A, p, r)
+    compared = None
+    if gpu_c is not None:
+        lo = np.tril(np.ones((r, n), dtype=bool), n - r)
+        got = gpu_c[n - r:, :n]
+        bad = int(np.count_nonzero((got != rows[:, :n]) & lo))
+        if bad:
+            raise SystemExit(f"bench: {bad} entries of the GPU result differ from the oracle")
+        compared = int(np.count_nonzero(lo))
+    out = {"value": round(rate, 3), "unit": "Gop/s", "cores": cores, "kind": "oracle",
+           "sample": f"rows [{n - r},{n}) of lower(A A^T) for A {n}x{k} mod {p} "
+                     f"({macs:.3e} multiply-adds, {dt:.1f} s)"}
+    if compared is not None:
+        out["gpu_entries_compared"] = compared
+    oracle.set_num_threads(1)
+    try:
+        dt1, rate1, macs1, _ = _oracle_rate(A, p, 64)
+    finally:
+        oracle.set_num_threads(cores)
+    out["single_thread"] = {"value": round(rate1, 3), "unit": "Gop/s",
+                            "sample": f"rows [{n - 64},{n}) ({macs1:.3e} multiply-adds, {dt1:.1f} s)"}
+    per = {}
+    cfgs = [("syrk_512_p65537", 512, 512, 65537, 0, 512),
+            ("syrk_8192x32768_p131071", 8192, 32768, 131071, 1, 64),
+            ("syrk_16384_p251", 16384, 16384, 251, 2, 64),
+            ("syrk_16384_p65521", 16384, 16384, 65521, 2, 64)]
+    for key, cn, ck, cp, seed, cr in cfgs:
+        if (cn, ck) == (n, k) and cp == p:
+            continue
+        B = inputs.uniform(seed, cn, ck, cp)
+        dtc, ratec, macsc, _ = _oracle_rate(B, cp, cr)
+        per[key] = {"value": round(ratec, 3), "unit": "Gop/s",
+                    "sample": f"rows [{cn - cr},{cn}) of {cn}x{ck} ({macsc:.3e} multiply-adds, {dtc:.2f} s)"}
+    out["per_config"] = per
+    return out
 
 
 def traffic_for(kernel, workload):
@@ -557,7 +670,8 @@ def main():
     name = args.workload
     w = WORKLOADS[name]
     log(f"bench: {name} steps={args.steps} warmup={args.warmup}")
-    res = run_workload(name, args.steps, args.warmup)
+    res = run_workload(name, args.steps, args.warmup, keep_first=not args.no_cpu_baseline)
+    first_c = res.pop("first_c", None)
     log(f"bench: {name} {res['ms_per_step']:.3f} ms/step {res['gops']:.1f} Gop/s")
     if w["cls"] == 0:
         peak, unit = PEAK_F64, "TFLOP/s"
@@ -592,6 +706,10 @@ def main():
                     v = {"error": repr(e)[:200]}
                 log(f"bench: vendor int8 GEMM {v}")
                 extra[other]["vendor_int8_gemm"] = v
+    if not args.no_extra:
+        log("bench: complex and block-diagonal products")
+        extra["complex_and_block_diagonal"] = complex_and_block_diagonal()
+        log(f"bench: {extra['complex_and_block_diagonal']}")
     if not args.no_extra and args.serve_requests > 0:
         log("bench: autotuning the served A A^T shape classes")
         tuned = tune_served_classes()
@@ -623,7 +741,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        cpu = cpu_baseline(name)
+        cpu = cpu_baseline(name, first_c)
+    del first_c
     n0, _ = w["shapes"][0]
     out = {
         "metric": METRIC,

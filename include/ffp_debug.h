@@ -68,8 +68,7 @@ void ffp_debug_set_kblk(int64_t kblk);
 
 /* Tuning and test knobs (process-wide): "kblk" (as ffp_debug_set_kblk),
  * "f64_tile" (64 or 128: force the FP64 product tile; 0 = automatic),
- * "f64_waves" (8, the default, or 4: waves per 128 x 128 FP64 workgroup;
- * other values FFP_EINVAL), "serve_batch" and "serve_ldlt_batch" (1 to
+ * "serve_batch" and "serve_ldlt_batch" (1 to
  * 4096: A*A^T and LDL^T requests per unit of the request loop; 128 and 32
  * by default), "ldlt_fold" (1, the default: the LDL^T products run as steps
  * of the per-level launch; 0: as separate product launches),
@@ -115,13 +114,13 @@ int ffp_debug_set(const char* key, int64_t value);
  * lower-triangle product) and their count, and forgets them. */
 void ffp_debug_profile(int enable);
 int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches);
-/* Same, restricted to one product-kernel variant (0 FP64 64x64 tiles, 1 FP64
- * 128x128 LDS-staged tiles, 2 int8 128x128, 3 int8 256x256 with 64-byte k
- * stages, 4 int8 256x256 with 128-byte k stages, 5 int8 limbs 128x128,
- * 6 int8 256x256 with operands straight to LDS, 7 int8 limbs 128x128
- * straight to LDS, 8 FP64
- * 128x128 with 8 waves, 9 int8 three limbs 64x64, 10 int8 256x256 with the
- * LDS writes between the MFMAs, 11 FP64 128x128 with doubles in LDS);
+/* Same, restricted to one product-kernel variant (0 FP64 64x64 tiles,
+ * 1 unused, 2 int8 128x128, 3 int8 256x256 with 64-byte k stages, 4 int8
+ * 256x256 with 128-byte k stages, 5 int8 limbs 128x128, 6 int8 256x256
+ * with operands straight to LDS, 7 int8 limbs 128x128 straight to LDS,
+ * 8 FP64 128x128 with centred int32 in LDS, 9 int8 three limbs 64x64,
+ * 10 int8 256x256 with the LDS writes between the MFMAs, 11 FP64 128x128
+ * with doubles in LDS, 12 int8 limbs 128x128 register-staged);
  * ffp_debug_variant_name gives the kernel's demangled name. */
 int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches);
 const char* ffp_debug_variant_name(int variant);

@@ -7,6 +7,6 @@ from .oracle import (  # noqa: F401
     build, load, is_prime, legendre, sqrt_mod, inv_mod, sos, nrsyf,
     syrk, syrk_rows, syrk_entries, gemm, syrk_ab, syrkd, ldlt, ldlt_packed,
     syrkbd, herk, zsyrk,
-    num_threads,
+    num_threads, set_num_threads,
 )
 from . import costmodel  # noqa: F401

@@ -425,3 +425,14 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the following parallel loops (timing of the oracle itself). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -60,6 +60,7 @@ def load():
             "oracle_herk": (c_int, [i64, i64, u64, P, i64, i64, P, i64, i64]),
             "oracle_zsyrk": (c_int, [i64, i64, u64, P, i64, i64, P, i64, i64]),
             "oracle_num_threads": (c_int, []),
+            "oracle_set_num_threads": (None, [c_int]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(lib, name)
@@ -253,3 +254,8 @@ def zsyrk(re, im, p: int):
 
 def num_threads() -> int:
     return int(load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    load().oracle_set_num_threads(int(n))

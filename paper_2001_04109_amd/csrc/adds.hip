@@ -456,46 +456,79 @@ __global__ __launch_bounds__(256) void lincomb_kernel(uint32_t p, int64_t m, int
 // identity or the transpose (the additions of the complex products: 3M
 // combinations, the multiplication by Y of the pre-additions, the post-
 // additions with P4 read transposed).  A workgroup forms a 64 x 64 tile of
-// out; a transposed input goes through a 64 x 65 LDS tile so that its
-// global reads stay coalesced.
+// out, each thread 4 consecutive columns of 4 rows; a transposed input goes
+// through a 64 x 65 LDS tile so that its global reads stay coalesced.
+// Coefficients 1 and p - 1 are a modular addition or subtraction, others a
+// modular multiply-add.  VEC: every non-transposed row start and out are
+// 16-byte aligned (4 columns per 16-byte access).
 struct LctIn { const uint32_t* p[5]; int64_t ld[5]; uint32_t c[5]; };
 
+template <bool VEC>
 __global__ __launch_bounds__(256) void lct_kernel(uint32_t p, double pinv, int64_t m, int64_t k, int nin, LctIn in,
                                                   unsigned trans, int lower, uint32_t* __restrict__ out, int64_t ldo)
 {
     __shared__ uint32_t tl[64][65];
     const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
     if (lower && c0 > r0 + 63) return;     // the whole tile above the diagonal (uniform)
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 4 rows of 64 per pass
-    uint32_t acc[16];
+    const int tid = threadIdx.x;
+    const int cx = (tid & 15) * 4, ry = tid >> 4;           // columns cx..cx+3 of rows ry + 16 e
+    uint32_t acc[4][4];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = 0u;
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[e][u] = 0u;
+    auto fold = [&](uint32_t& a, uint32_t v, uint32_t cf) {
+        if (cf == 1u) a = add_m(a, v, p);
+        else if (cf == p - 1u) a = sub_m(a, v, p);
+        else a = add_m(a, mul_m(cf, v, p, pinv), p);
+    };
     for (int t = 0; t < nin; ++t) {
         const uint32_t cf = in.c[t];
+        if (cf == 0u) continue;
         if ((trans >> t) & 1u) {
-            // out[r][c] += cf * in[c][r]: stage in rows c0.., columns r0..
+            // out[r][c] += cf * in[c][r]: stage rows c0.., columns r0.. of in
             __syncthreads();
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int64_t sr = c0 + ty + 4 * e, sc = r0 + tx;
-                tl[ty + 4 * e][tx] = (sr < k && sc < m) ? in.p[t][sr * in.ld[t] + sc] : 0u;
+            for (int e = tid; e < 64 * 64; e += 256) {
+                const int a = e >> 6, b = e & 63;
+                const int64_t sr = c0 + a, sc = r0 + b;
+                tl[a][b] = (sr < k && sc < m) ? in.p[t][sr * in.ld[t] + sc] : 0u;
             }
             __syncthreads();
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                acc[e] = add_m(acc[e], mul_m(cf, tl[tx][ty + 4 * e], p, pinv), p);
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) fold(acc[e][u], tl[cx + u][ry + 16 * e], cf);
         } else {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int64_t r = r0 + ty + 4 * e, c = c0 + tx;
-                if (r < m && c < k) acc[e] = add_m(acc[e], mul_m(cf, in.p[t][r * in.ld[t] + c], p, pinv), p);
+            for (int e = 0; e < 4; ++e) {
+                const int64_t r = r0 + ry + 16 * e, c = c0 + cx;
+                if (r >= m) continue;
+                const uint32_t* src = in.p[t] + r * in.ld[t] + c;
+                uint32_t v[4];
+                if (VEC && c + 4 <= k) {
+                    const uint4 x = *reinterpret_cast<const uint4*>(src);
+                    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = c + u < k ? src[u] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) fold(acc[e][u], v[u], cf);
             }
         }
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int64_t r = r0 + ty + 4 * e, c = c0 + tx;
-        if (r < m && c < k && (!lower || c <= r)) out[r * ldo + c] = acc[e];
+    for (int e = 0; e < 4; ++e) {
+        const int64_t r = r0 + ry + 16 * e, c = c0 + cx;
+        if (r >= m) continue;
+        uint32_t* dst = out + r * ldo + c;
+        if (VEC && c + 4 <= k && (!lower || c + 3 <= r)) {
+            *reinterpret_cast<uint4*>(dst) = make_uint4(acc[e][0], acc[e][1], acc[e][2], acc[e][3]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c + u < k && (!lower || c + u <= r)) dst[u] = acc[e][u];
+        }
     }
 }
 
@@ -793,14 +826,20 @@ hipError_t launch_lct(const Fp& f, int64_t m, int64_t k, int nin, const DView* i
     if (m <= 0 || k <= 0) return hipSuccess;
     if (nin < 1 || nin > 5 || (lower && m != k)) return hipErrorInvalidValue;
     LctIn li{};
+    bool vec = (out.ld & 3) == 0 && (((uintptr_t)out.p) & 15) == 0;
     for (int t = 0; t < nin; ++t) {
         li.p[t] = (const uint32_t*)in[t].p;
         li.ld[t] = in[t].ld;
         li.c[t] = coef[t] % f.p;
+        if (!((trans >> t) & 1u)) vec = vec && (in[t].ld & 3) == 0 && (((uintptr_t)in[t].p) & 15) == 0;
     }
     const dim3 g((unsigned)((k + 63) / 64), (unsigned)((m + 63) / 64));
-    hipLaunchKernelGGL(lct_kernel, g, dim3(256), 0, s, f.p, f.pinv, m, k, nin, li, trans, lower,
-                       (uint32_t*)out.p, out.ld);
+    if (vec)
+        hipLaunchKernelGGL(lct_kernel<true>, g, dim3(256), 0, s, f.p, f.pinv, m, k, nin, li, trans, lower,
+                           (uint32_t*)out.p, out.ld);
+    else
+        hipLaunchKernelGGL(lct_kernel<false>, g, dim3(256), 0, s, f.p, f.pinv, m, k, nin, li, trans, lower,
+                           (uint32_t*)out.p, out.ld);
     return hipGetLastError();
 }
 

@@ -286,11 +286,6 @@ int ffp_debug_set(const char* key, int64_t value)
         (key[6] == 'l' ? ffp::g_serve_ldlt_batch : ffp::g_serve_batch) = (int)value;
         return FFP_OK;
     }
-    if (strcmp(key, "f64_waves") == 0) {
-        if (value != 4 && value != 8) return FFP_EINVAL;
-        ffp::g_f64_waves = (int)value;
-        return FFP_OK;
-    }
     return FFP_EINVAL;
 }
 
@@ -310,7 +305,6 @@ const char* ffp_debug_variant_name(int variant)
 {
     switch (variant) {
     case 0: return "ffp::prod_f64_kernel(ffp::ProdArgs, int)";
-    case 1: return "void ffp::prod_f64_lds_kernel<4>(ffp::ProdArgs, int)";
     case 2: return "void ffp::prod_i8_kernel<128, 128, 64, 1>(ffp::ProdArgs, int)";
     case 3: return "void ffp::prod_i8_kernel<256, 256, 64, 1>(ffp::ProdArgs, int)";
     case 4: return "void ffp::prod_i8_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";

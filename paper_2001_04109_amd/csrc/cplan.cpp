@@ -219,9 +219,13 @@ struct CBuilder {
 
 int default_complex_depth(int64_t n, int64_t k)
 {
+    // Each level saves an eighth of the real products for a dozen
+    // plane-wise block additions; measured on the FP64 matrix cores the
+    // trade pays from n = 8192 (n = k = 8192, p = 131071: 24.6 ms at depth
+    // 0, 23.0 ms at depth 1; n = 4096: 3.63 ms at depth 0, 3.70 at depth 1).
     int d = 0;
     const int64_t nn = std::min(n, 2 * k);
-    while (d < 4 && (nn >> (d + 1)) >= 1024) ++d;
+    while (d < 4 && (nn >> (d + 1)) >= 4096) ++d;
     return d;
 }
 

@@ -84,7 +84,6 @@ extern int64_t g_kblk_cap;
 extern int g_f64_tile_override;
 extern int g_i8_tile_override;
 extern int g_i8_bk_override;
-extern int g_f64_waves;        // waves per 128 x 128 FP64 workgroup: 8 (default) or 4
 extern int g_f64_pipe;         // FP64 128x128, 8 waves: operands as doubles in LDS (when k fits one exact block)
 // Tile edge chosen for the product launches of the current call on this
 // thread (0: the launch rule or the override above); set from the tuned
@@ -97,7 +96,7 @@ extern int g_i8_pipe;          // CLS_I8 256x256x128: LDS writes spread over the
 // workgroup per tile (0).
 extern int g_persistent;
 // Product-kernel variant chosen by the most recent launch on this thread
-// (for the timing hooks): 0 FP64 64x64, 1 FP64 128x128 LDS (4 waves), 2 int8
+// (for the timing hooks): 0 FP64 64x64, 1 unused, 2 int8
 // 128x128, 3 int8 256x256 (k stage 64), 4 int8 256x256 (k stage 128), 5 int8
 // limbs, 6 int8 256x256 straight to LDS, 7 limbs 128x128 straight to LDS, 8 FP64
 // 128x128 LDS (8 waves), 9 int8

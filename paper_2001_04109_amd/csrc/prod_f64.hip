@@ -535,7 +535,6 @@ static int32_t task_kblk(uint32_t p, int unit)
     return kb < 16 ? (int32_t)kb : cap_kblk(kb, unit);
 }
 
-int g_f64_waves = 8;
 int g_f64_pipe = 1;
 
 template <int TILE>
@@ -564,7 +563,7 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
     }
     const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
     int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
-    const bool w8 = TILE == 128 && g_f64_waves == 8;
+    const bool w8 = TILE == 128;
     // the doubles-in-LDS variant: whole k in one exact block, 16-byte rows,
     // 128-row panels addressable with 32-bit byte offsets
     bool pipe = w8 && g_f64_pipe != 0;
@@ -578,21 +577,19 @@ static hipError_t launch_f64_impl(ProdTask* tasks, int ntasks, ProdTask* dev_tas
     }
     const void* kern = TILE != 128 ? (const void*)prod_f64_kernel
                        : pipe      ? (const void*)prod_f64_pipe_kernel
-                       : (w8 ? (const void*)prod_f64_lds_kernel<8> : (const void*)prod_f64_lds_kernel<4>);
+                                   : (const void*)prod_f64_lds_kernel<8>;
     const int threads = w8 ? 512 : 256;
     if (mode == 2) {
         const int resident = resident_blocks(kern, threads);
         grid = total < resident ? total : resident;
     }
-    g_last_variant = TILE == 128 ? (pipe ? 11 : (w8 ? 8 : 1)) : 0;
+    g_last_variant = TILE == 128 ? (pipe ? 11 : 8) : 0;
     if (TILE != 128)
         hipLaunchKernelGGL(prod_f64_kernel, dim3(grid), dim3(256), 0, s, args, mode);
     else if (pipe)
         hipLaunchKernelGGL(prod_f64_pipe_kernel, dim3(grid), dim3(512), 0, s, args, mode);
-    else if (w8)
-        hipLaunchKernelGGL((prod_f64_lds_kernel<8>), dim3(grid), dim3(512), 0, s, args, mode);
     else
-        hipLaunchKernelGGL((prod_f64_lds_kernel<4>), dim3(grid), dim3(256), 0, s, args, mode);
+        hipLaunchKernelGGL((prod_f64_lds_kernel<8>), dim3(grid), dim3(512), 0, s, args, mode);
     return hipGetLastError();
 }
 
