@@ -88,8 +88,9 @@ extern "C" {
 #define FFP_LOW_MEMORY    0x200u
 /* Run the base products on three int8 limbs (value = l + 256 m + 65536 h of
  * the centred residue, nine int8 matrix-core products per block, exact
- * int32 sums) instead of FP64 matrix cores; FFP_U32 operands, p < 2^23,
- * no recursion (depth 0).  The autotuner chooses it where it is faster.
+ * int32 sums) instead of FP64 matrix cores; FFP_U32 operands, p < 2^23.
+ * Algorithm 2's blocks S1..S4 are then formed in the three limb planes.
+ * The autotuner chooses it (at depth 0) where it is faster.
  * Not with FFP_BASE_F64 (FFP_EINVAL); other storage or p: FFP_EDTYPE. */
 #define FFP_BASE_LIMB3    0x400u
 

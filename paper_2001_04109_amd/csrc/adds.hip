@@ -193,6 +193,159 @@ __global__ __launch_bounds__(256) void preadd_s34_u32x4_kernel(Fp f, int mode, i
     }
 }
 
+// int8 storage classes (centred int8, two or three int8 limbs) with 16
+// consecutive columns per thread: one 16-byte access per plane.  Values are
+// decoded to a signed representative x of the residue (|x| < 2^22), the
+// block arithmetic runs on exact doubles (every term below 2^53), and the
+// result is encoded back to the class's representative (centred; for two
+// limbs the one in [-32896, 32639]).  The launchers take these when every
+// row start and plane offset is 16-byte aligned and the column count (of
+// pairs, for Y = [[aI, bI], [-bI, aI]]) is a multiple of 16.
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+template <int CLS>
+struct Vec16 {
+    static constexpr int PL = CLS == CLS_I8 ? 1 : (CLS == CLS_LIMB2 ? 2 : 3);
+    v4i w[PL];
+};
+
+template <int CLS>
+__device__ __forceinline__ void ld16(const DView& v, int64_t i, int64_t j, Vec16<CLS>& o)
+{
+#pragma unroll
+    for (int q = 0; q < Vec16<CLS>::PL; ++q)
+        o.w[q] = *reinterpret_cast<const v4i*>((const int8_t*)v.p + q * v.plane + i * v.ld + j);
+}
+
+template <int CLS>
+__device__ __forceinline__ void st16(const DView& v, int64_t i, int64_t j, const Vec16<CLS>& o)
+{
+#pragma unroll
+    for (int q = 0; q < Vec16<CLS>::PL; ++q)
+        *reinterpret_cast<v4i*>((int8_t*)v.p + q * v.plane + i * v.ld + j) = o.w[q];
+}
+
+__device__ __forceinline__ int sbyte(const v4i& w, int e) { return (int)(int8_t)((uint32_t)w[e >> 2] >> (8 * (e & 3))); }
+
+// signed value of element e (a representative of its residue)
+template <int CLS>
+__device__ __forceinline__ double dec(const Vec16<CLS>& x, int e)
+{
+    if constexpr (CLS == CLS_I8) return (double)sbyte(x.w[0], e);
+    else if constexpr (CLS == CLS_LIMB2) return (double)(256 * sbyte(x.w[0], e) + sbyte(x.w[1], e));
+    else return (double)(sbyte(x.w[0], e) + 256 * sbyte(x.w[1], e) + 65536 * sbyte(x.w[2], e));
+}
+
+// store the residue of the exact integer v (|v| < 2^53) as element e
+template <int CLS>
+__device__ __forceinline__ void enc(Vec16<CLS>& x, int e, double v, const Fp& f)
+{
+    const uint32_t r = (uint32_t)mod_f64(v, (double)f.p, f.pinv);
+    int y;
+    if constexpr (CLS == CLS_LIMB2) y = r <= 32639u ? (int)r : (int)r - (int)f.p;
+    else y = r > f.half ? (int)r - (int)f.p : (int)r;
+    const int sh = 8 * (e & 3), wi = e >> 2;
+    auto put = [&](int q, int b) {
+        uint32_t w = (uint32_t)x.w[q][wi];
+        w = (w & ~(0xFFu << sh)) | ((uint32_t)(b & 0xFF) << sh);
+        x.w[q][wi] = (int)w;
+    };
+    if constexpr (CLS == CLS_I8) {
+        put(0, y);
+    } else if constexpr (CLS == CLS_LIMB2) {
+        const int lo = ((y + 128) & 255) - 128;
+        put(0, (y - lo) >> 8);
+        put(1, lo);
+    } else {
+        int8_t l, mid, h;
+        limb3_split(y, &l, &mid, &h);
+        put(0, l);
+        put(1, mid);
+        put(2, h);
+    }
+}
+
+template <int CLS>
+__global__ __launch_bounds__(256) void preadd_s1s2_vec_kernel(Fp f, int64_t m, int64_t h, DView A11, DView A21,
+                                                             DView A22, DView S1, DView S2)
+{
+    const int64_t ncol = f.yb ? h / 2 : h;
+    const int64_t h2 = h / 2;
+    const int64_t c = ((int64_t)blockIdx.x * 64 + (threadIdx.x & 63)) * 16;
+    if (c >= ncol) return;
+    // centred Y entries: a, b small signed integers, products exact in doubles
+    const double a = (double)(f.ya > f.half ? (int)f.ya - (int)f.p : (int)f.ya);
+    const double b = (double)(f.yb > f.half ? (int)f.yb - (int)f.p : (int)f.yb);
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < m; i += (int64_t)gridDim.y * 4) {
+        if (f.yb == 0) {
+            // Y = a I:  S1 = a (A21 - A11),  S2 = A22 - a A21
+            Vec16<CLS> x11, x21, x22, s1, s2;
+            ld16(A11, i, c, x11);
+            ld16(A21, i, c, x21);
+            ld16(A22, i, c, x22);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const double v11 = dec(x11, e), v21 = dec(x21, e), v22 = dec(x22, e);
+                enc(s1, e, a * (v21 - v11), f);
+                enc(s2, e, v22 - a * v21, f);
+            }
+            st16(S1, i, c, s1);
+            st16(S2, i, c, s2);
+        } else {
+            // X Y = [a X_L - b X_R, b X_L + a X_R]
+            const int64_t cl = c, cr = c + h2;
+            Vec16<CLS> x11l, x11r, x21l, x21r, x22l, x22r, s1l, s1r, s2l, s2r;
+            ld16(A11, i, cl, x11l);
+            ld16(A11, i, cr, x11r);
+            ld16(A21, i, cl, x21l);
+            ld16(A21, i, cr, x21r);
+            ld16(A22, i, cl, x22l);
+            ld16(A22, i, cr, x22r);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const double xl = dec(x21l, e), xr = dec(x21r, e);
+                const double dl = xl - dec(x11l, e), dr = xr - dec(x11r, e);
+                enc(s1l, e, a * dl - b * dr, f);
+                enc(s1r, e, b * dl + a * dr, f);
+                enc(s2l, e, dec(x22l, e) - (a * xl - b * xr), f);
+                enc(s2r, e, dec(x22r, e) - (b * xl + a * xr), f);
+            }
+            st16(S1, i, cl, s1l);
+            st16(S1, i, cr, s1r);
+            st16(S2, i, cl, s2l);
+            st16(S2, i, cr, s2r);
+        }
+    }
+}
+
+template <int CLS>
+__global__ __launch_bounds__(256) void preadd_s34_vec_kernel(Fp f, int mode, int64_t m, int64_t h, DView S1,
+                                                            DView A22, DView A12, DView S3, DView S4)
+{
+    const int64_t c = ((int64_t)blockIdx.x * 64 + (threadIdx.x & 63)) * 16;
+    if (c >= h) return;
+    for (int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); i < m; i += (int64_t)gridDim.y * 4) {
+        Vec16<CLS> s3, t;
+        if (mode & 1) {
+            Vec16<CLS> x1, x22;
+            ld16(S1, i, c, x1);
+            ld16(A22, i, c, x22);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) enc(s3, e, dec(x1, e) - dec(x22, e), f);          // S3 = S1 - A22
+            st16(S3, i, c, s3);
+        } else {
+            ld16(S3, i, c, s3);
+        }
+        if (mode & 2) {
+            Vec16<CLS> x12;
+            ld16(A12, i, c, x12);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) enc(t, e, dec(s3, e) + dec(x12, e), f);           // S4 = S3 + A12
+            st16(S4, i, c, t);
+        }
+    }
+}
+
 constexpr int T = 32;
 
 __global__ __launch_bounds__(256) void postadd_kernel(Fp f, int m, const uint32_t* __restrict__ P1,
@@ -613,6 +766,15 @@ inline bool u32x4_ok(int64_t ncol, std::initializer_list<DView> views)
     return true;
 }
 
+// int8 storage: every row start and plane offset 16-byte aligned, column count a multiple of 16
+inline bool i8x16_ok(int64_t ncol, std::initializer_list<DView> views)
+{
+    if (!g_pack_vec || (ncol & 15) != 0) return false;
+    for (const DView& v : views)
+        if ((v.ld & 15) != 0 || (((uintptr_t)v.p) & 15) != 0 || (v.plane & 15) != 0) return false;
+    return true;
+}
+
 inline unsigned tri_blocks(int64_t m)
 {
     const int64_t t = (m + T - 1) / T;
@@ -631,11 +793,21 @@ hipError_t launch_preadd_s1s2(int cls, const Fp& f, int64_t m, int64_t h, DView 
                            S1, S2);
         return hipGetLastError();
     }
+    if (cls != CLS_F64 && i8x16_ok(ncol, {A11, A21, A22, S1, S2})) {
+        const dim3 g = grid2d(m, ncol / 16);
+        switch (cls) {
+        case CLS_I8: hipLaunchKernelGGL(preadd_s1s2_vec_kernel<CLS_I8>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
+        case CLS_LIMB2: hipLaunchKernelGGL(preadd_s1s2_vec_kernel<CLS_LIMB2>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
+        default: hipLaunchKernelGGL(preadd_s1s2_vec_kernel<CLS_LIMB3>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
+        }
+        return hipGetLastError();
+    }
     dim3 g = grid2d(m, ncol);
     switch (cls) {
     case CLS_F64: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_F64>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
     case CLS_I8: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_I8>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
-    default: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_LIMB2>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
+    case CLS_LIMB2: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_LIMB2>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
+    default: hipLaunchKernelGGL(preadd_s1s2_kernel<CLS_LIMB3>, g, dim3(256), 0, s, f, m, h, A11, A21, A22, S1, S2); break;
     }
     return hipGetLastError();
 }
@@ -649,11 +821,21 @@ hipError_t launch_preadd_s34(int cls, const Fp& f, int mode, int64_t m, int64_t 
                            S3, S4);
         return hipGetLastError();
     }
+    if (cls != CLS_F64 && i8x16_ok(h, {S1, A22, A12, S3, S4})) {
+        const dim3 g = grid2d(m, h / 16);
+        switch (cls) {
+        case CLS_I8: hipLaunchKernelGGL(preadd_s34_vec_kernel<CLS_I8>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
+        case CLS_LIMB2: hipLaunchKernelGGL(preadd_s34_vec_kernel<CLS_LIMB2>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
+        default: hipLaunchKernelGGL(preadd_s34_vec_kernel<CLS_LIMB3>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
+        }
+        return hipGetLastError();
+    }
     dim3 g = grid2d(m, h);
     switch (cls) {
     case CLS_F64: hipLaunchKernelGGL(preadd_s34_kernel<CLS_F64>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
     case CLS_I8: hipLaunchKernelGGL(preadd_s34_kernel<CLS_I8>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
-    default: hipLaunchKernelGGL(preadd_s34_kernel<CLS_LIMB2>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
+    case CLS_LIMB2: hipLaunchKernelGGL(preadd_s34_kernel<CLS_LIMB2>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
+    default: hipLaunchKernelGGL(preadd_s34_kernel<CLS_LIMB3>, g, dim3(256), 0, s, f, mode, m, h, S1, A22, A12, S3, S4); break;
     }
     return hipGetLastError();
 }

@@ -71,7 +71,7 @@ struct Builder {
     {
         PView v = blk;
         v.ld = blk.ld * 4 / es();
-        v.plane = cls == CLS_LIMB2 ? h : 0;
+        v.plane = (cls == CLS_LIMB2 || cls == CLS_LIMB3) ? h : 0;   // planes side by side in a row
         return v;
     }
 
@@ -351,11 +351,16 @@ int default_depth(int cls, int64_t n, int64_t k)
     // Each level trades one eighth of the multiply-adds (5 products instead
     // of 6 on half-size blocks, Table 1) for HBM-bound block additions.  On
     // FP64 matrix cores that trade pays while the leaves stay large enough
-    // to fill the chip; on int8 matrix cores the additions cost more than
-    // the saved products at every size measured, so no recursion.
+    // to fill the chip.  Three int8 limbs (nine products per block): one
+    // level pays from about n = 4096 (8192 x 8192 and 8192 x 32768,
+    // p = 131071: 3-5 % faster at depth 1, slower at depth 2).  One int8
+    // plane and two limbs: the additions cost as much as or more than the
+    // saved products at every size measured (16384^2: int8 2.17 ms at depth
+    // 0, 2.50 at depth 1; two limbs 7.50 and 7.52 ms), so no recursion.
+    const int64_t nn = std::min(n, 2 * k);
+    if (cls == CLS_LIMB3) return nn >= 4096 ? 1 : 0;
     if (cls != CLS_F64) return 0;
     int d = 0;
-    int64_t nn = std::min(n, 2 * k);
     while (d < 4 && (nn >> (d + 1)) >= 1024) ++d;
     return d;
 }
@@ -392,7 +397,7 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
     }
     if (d < 0) d = default_depth(pl.cls, n, k);
     while (d > 0 && (n >> d) < 8) --d;
-    if (k == 0 || pl.cls == CLS_LIMB3) d = 0;   // three-limb storage: base products only
+    if (k == 0) d = 0;
     pl.depth = d;
     pl.wide = wide;
     pl.tile = tile;

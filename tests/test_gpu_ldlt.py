@@ -162,3 +162,69 @@ def test_ldlt_products_folded_or_launched_agree(p):
     assert ia == rinfo
     if ia == 0:
         assert np.array_equal(a[low], ref[low])
+
+
+def _freivalds_ldlt(S, out, p, rounds=3, seed=0):
+    """L D L^T x = S x mod p for random x (a wrong factorisation passes with
+    probability at most p^-rounds); exact in int64 for p < 2^24, n <= 8192."""
+    n = S.shape[0]
+    L = np.tril(out.astype(np.int64), -1)
+    L[np.arange(n), np.arange(n)] = 1
+    D = out[np.arange(n), np.arange(n)].astype(np.int64)
+    Sl = S.astype(np.int64)
+    rng = np.random.default_rng(seed)
+    for _ in range(rounds):
+        x = rng.integers(0, p, size=n, dtype=np.int64)
+        y = (L.T @ x) % p
+        y = (D * y) % p
+        z = (L @ y) % p
+        assert np.array_equal(z, (Sl @ x) % p)
+
+
+def _big_ldlt_case(n, p, seed0):
+    for attempt in range(4):
+        S = inputs.symmetric((seed0, attempt), n, p)
+        out, info = gpu_ldlt(S, p)
+        if info == 0:
+            return S, out
+    pytest.fail("no draw with a generic rank profile in 4 attempts")
+
+
+def test_ldlt_schur_update_through_algorithm2():
+    """n = 8192, p = 131071: the top Schur update (n2 = 4096, k = 4097
+    padded) runs on three int8 limbs through one level of Algorithm 2.  The
+    leading 1024 x 1024 block of L and D (the factorisation of the leading
+    block) against the oracle's Crout LDL^T; the whole factorisation by
+    Freivalds' check of L D L^T = S."""
+    p, n = 131071, 8192
+    ffp.ffp_tune_clear()
+    plan = ffp.plan_describe(4096, 4224, p, lda=4224, ldc=n, alpha=p - 1, beta=1, flags=ffp.FFP_BASE_LIMB3)
+    assert " depth=1 " in plan.splitlines()[0] and " cls=3 " in plan.splitlines()[0]
+    S, out = _big_ldlt_case(n, p, 51)
+    m = 1024
+    ref, rinfo = oracle.ldlt_packed(S[:m, :m].copy(), p)
+    assert rinfo == 0
+    low = np.tril(np.ones((m, m), dtype=bool))
+    assert np.array_equal(out[:m, :m][low], ref[low])
+    _freivalds_ldlt(S, out, p)
+
+
+def test_ldlt_fp64_table4_schur_path():
+    """p above 2^23: the Schur updates run on FP64 matrix cores through the
+    Table 4 schedule (alpha = p - 1, beta = 1) at depth 1 for the top node
+    of n = 4096 (n2 = 2048)."""
+    p = (1 << 23) + 1
+    while not oracle.is_prime(p):
+        p += 2
+    n = 4096
+    ffp.ffp_tune_clear()
+    plan = ffp.plan_describe(2048, 2176, p, lda=2176, ldc=n, alpha=p - 1, beta=1)
+    head = plan.splitlines()[0]
+    assert " depth=1 " in head and " cls=0 " in head
+    S, out = _big_ldlt_case(n, p, 52)
+    m = 768
+    ref, rinfo = oracle.ldlt_packed(S[:m, :m].copy(), p)
+    assert rinfo == 0
+    low = np.tril(np.ones((m, m), dtype=bool))
+    assert np.array_equal(out[:m, :m][low], ref[low])
+    _freivalds_ldlt(S, out, p)

@@ -369,6 +369,41 @@ def test_syrk_limb3_vs_oracle(p, n, k):
     check_lower(gpu_syrk(A, p, limb3=True), oracle.syrk(A, p))
 
 
+@pytest.mark.parametrize("p", [65537, 131071, 8388593])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("n,k", [(256, 256), (300, 1000), (1000, 640), (1030, 2100)])
+def test_limb3_recursive(p, depth, n, k):
+    """Algorithm 2 over three int8 limbs: the pre-additions in the limb
+    planes (16 columns per thread where aligned), plain and accumulate
+    forms, wide and Table 3 placements."""
+    A = inputs.uniform((43, n, k, p, depth), n, k, p)
+    check_lower(gpu_syrk(A, p, depth=depth, limb3=True), oracle.syrk(A, p))
+    C0 = inputs.uniform(44, n, n, p)
+    check_lower(gpu_syrk(A, p, depth=depth, alpha=p - 1, beta=1, C0=C0, limb3=True),
+                oracle.syrk_ab(A, p, p - 1, 1, C0))
+    set_knob("wide", 0)
+    try:
+        check_lower(gpu_syrk(A, p, depth=depth, limb3=True), oracle.syrk(A, p))
+    finally:
+        set_knob("wide", 1)
+
+
+@pytest.mark.parametrize("vec", [1, 0])
+@pytest.mark.parametrize("p,a_dtype", [(251, ffp.FFP_U32), (251, ffp.FFP_I8_CENTERED), (65521, ffp.FFP_U32),
+                                       (65521, ffp.FFP_I8_LIMB2), (3, ffp.FFP_U32), (257, ffp.FFP_U32)])
+@pytest.mark.parametrize("depth", [1, 2])
+def test_int8_preadditions_vector_or_scalar(vec, p, a_dtype, depth):
+    """The int8-class pre-additions 16 columns per thread (where aligned) or
+    one: both against the oracle, p = 3 (y = 2) and 257 (y = 1) included."""
+    n, k = 600, 1024
+    A = inputs.uniform((45, p, depth), n, k, p)
+    set_knob("pack_vec", vec)
+    try:
+        check_lower(gpu_syrk(A, p, depth=depth, a_dtype=a_dtype), oracle.syrk(A, p))
+    finally:
+        set_knob("pack_vec", 1)
+
+
 @pytest.mark.parametrize("p", [65537, 8388593])
 def test_limb3_alpha_beta_fill_and_forced_kblk(p):
     n, k = 200, 1100

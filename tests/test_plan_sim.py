@@ -98,13 +98,16 @@ def test_int8_classes(p, a_dtype, depth):
 
 @pytest.mark.parametrize("p", [65537, 131071, 1000003, 8388593])
 @pytest.mark.parametrize("n,k", [(40, 72), (33, 21), (64, 64)])
-def test_limb3_class(p, n, k):
-    """Three int8 limbs (FFP_BASE_LIMB3): base products only, any forced
-    depth falls back to 0; plain and accumulate forms."""
-    plan = run_case(n, k, p, 2, flags=ffp.FFP_BASE_LIMB3, seed=7)
-    assert plan.cls == plansim.CLS_LIMB3 and plan.depth == 0
-    run_case(n, k, p, 0, alpha=p - 1, beta=1, flags=ffp.FFP_BASE_LIMB3, seed=8)
-    run_case(n, k, p, 0, alpha=5, beta=p - 2, flags=ffp.FFP_BASE_LIMB3 | ffp.FFP_FILL_UPPER, seed=9)
+@pytest.mark.parametrize("depth", [0, 1, 2])
+def test_limb3_class(p, n, k, depth):
+    """Three int8 limbs (FFP_BASE_LIMB3) with Algorithm 2 to the forced
+    depth (pre-additions in the three limb planes); plain and accumulate
+    forms, Table 3 placements too."""
+    plan = run_case(n, k, p, depth, flags=ffp.FFP_BASE_LIMB3, seed=7)
+    assert plan.cls == plansim.CLS_LIMB3 and plan.depth == depth
+    run_case(n, k, p, depth, flags=ffp.FFP_BASE_LIMB3 | ffp.FFP_LOW_MEMORY, seed=10)
+    run_case(n, k, p, depth, alpha=p - 1, beta=1, flags=ffp.FFP_BASE_LIMB3, seed=8)
+    run_case(n, k, p, depth, alpha=5, beta=p - 2, flags=ffp.FFP_BASE_LIMB3 | ffp.FFP_FILL_UPPER, seed=9)
 
 
 def test_limb3_argument_errors():
