@@ -76,7 +76,11 @@ void ffp_debug_set_kblk(int64_t kblk);
  * "i8_bk" (64 or 128: k bytes per LDS stage of the 256 x 256 int8 tile),
  * "i8_dma" (1, the default: the 256 x 256 int8 tile and the 128 x 128
  * two-limb tile with 128-byte k stages load their operands straight into
- * LDS, no staging registers; 0: through registers as "i8_pipe" says), "i8_pipe" (1, the default: with "i8_dma" 0,
+ * LDS, no staging registers; 0: through registers as "i8_pipe" says),
+ * "i8_split_tail" (1, the default: an fsyrk_modp int8 product launch whose
+ * last round of 256 x 256 tiles would leave most workgroups idle runs that
+ * round's tiles as k-chunks and adds them in a second small kernel; 0: no
+ * split), "i8_pipe" (1, the default: with "i8_dma" 0,
  * the 256 x 256 int8 tile with 128-byte k stages writes each stage's
  * operands to LDS between the MFMAs of the previous stage and loads them up
  * to two stages ahead; 0: the stage's LDS writes after its MFMAs), "f64_pipe" (1, the default: the

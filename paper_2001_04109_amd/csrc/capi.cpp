@@ -35,8 +35,13 @@ int fsyrk_modp(int64_t n, int64_t k, uint32_t p, const void* A, int64_t lda, int
     if (st != FFP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Workspace* ws = nullptr;
-    st = acquire_workspace(s, (size_t)pl.ws_bytes, 0, &ws);
+    // large int8 products may split their last round of tiles along k: 64 MiB
+    // for the int32 chunks after the plan's own workspace
+    const size_t base = ((size_t)pl.ws_bytes + 255) / 256 * 256;
+    const size_t tail = (pl.cls == CLS_I8 && pl.n_pad >= 4096 && g_split_tail) ? ((size_t)64 << 20) : 0;
+    st = acquire_workspace(s, base + tail, 0, &ws);
     if (st != FFP_OK) return st;
+    TailScratchScope scope(tail ? (char*)ws->ptr + base : nullptr, tail);
     return execute_plan(pl, A, C, ws->ptr, s);
 }
 
@@ -276,6 +281,7 @@ int ffp_debug_set(const char* key, int64_t value)
         return FFP_OK;
     }
     if (strcmp(key, "i8_dma") == 0) { ffp::g_i8_dma = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "i8_split_tail") == 0) { ffp::g_split_tail = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "i8_pipe") == 0) { ffp::g_i8_pipe = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "pack_vec") == 0) { ffp::g_pack_vec = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "f64_pipe") == 0) { ffp::g_f64_pipe = value ? 1 : 0; return FFP_OK; }

@@ -91,6 +91,21 @@ extern int g_f64_pipe;         // FP64 128x128, 8 waves: operands as doubles in 
 extern thread_local int g_tile_hint;
 extern int g_i8_dma;           // CLS_I8 256x256 / CLS_LIMB2 128x128, k a multiple of 128: operands
                                // straight to LDS (1, default)
+// Scratch the int8 launcher may use for the k-chunks of a split tile round
+// (set for one call by the executor; null: no split).
+struct TailScratch {
+    void* ptr;
+    size_t bytes;
+};
+extern thread_local TailScratch g_tail_scratch;
+struct TailScratchScope {
+    TailScratch saved;
+    TailScratchScope(void* p, size_t b) : saved(g_tail_scratch) { g_tail_scratch = TailScratch{p, b}; }
+    ~TailScratchScope() { g_tail_scratch = saved; }
+};
+// 1 (default): a single-task int8 launch whose last round of tiles would
+// leave most workgroups idle splits that round's tiles along k.
+extern int g_split_tail;
 extern int g_i8_pipe;          // CLS_I8 256x256x128: LDS writes spread over the MFMAs, loads two stages ahead
 // Multi-task product launches run persistent workgroups (1, default) or one
 // workgroup per tile (0).

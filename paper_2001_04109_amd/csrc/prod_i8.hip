@@ -393,7 +393,8 @@ __device__ __forceinline__ void store_tile_limb2(const v16i (&acc)[3][FM][FN], c
 // per k-step, and a stage is 64 blocks of 1 KB: the A and B panels (and
 // their planes) one after the other.
 template <int PLANES, bool EDGE>
-__device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, int8_t* smem)
+__device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, int8_t* smem, int kst0 = 0,
+                                            int kst1 = -1, int32_t* part = nullptr)
 {
     constexpr int BM = PLANES == 1 ? 256 : 128, BN = BM, BK = 128;
     constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 32, FN = WTN / 32;
@@ -420,12 +421,15 @@ __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, i
                 for (int e = 0; e < 16; ++e) acc[q][i][j][e] = 0;
     const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
 
-    const int nk = t.k / BK;
+    // stages [kst0, kst1) of the task's k (a k-chunk of a split tile), or all
+    const int kend = kst1 < 0 ? t.k / BK : kst1;
+    const int nk = kend - kst0;
     if (nk > 0) {
         const int va = t.m - tile_r < BM ? t.m - tile_r : BM;    // valid rows of the panels
         const int vb = t.n - tile_c < BN ? t.n - tile_c : BN;
         const int lda = __builtin_amdgcn_readfirstlane((int)t.A.ld);
         const int ldb = __builtin_amdgcn_readfirstlane((int)t.B.ld);
+        const int kbyte0 = kst0 * BK;
         // this wave loads blocks 16 wave .. 16 wave + 15 of a stage, all in
         // one region (panel and plane): region = 16 wave / RBLK
         const int region = (16 * wave) / RBLK, blk0 = (16 * wave) % RBLK;
@@ -444,11 +448,11 @@ __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, i
             const int v = (blk & 1) ? v1 : v0;
             if constexpr (EDGE) {
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsVoid*)dst, 16, (uint32_t)(v + 8 * blk * ld) + dead,
-                                                         __builtin_amdgcn_readfirstlane(stg * BK), 0, 0);
+                                                         __builtin_amdgcn_readfirstlane(kbyte0 + stg * BK), 0, 0);
             } else {
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsVoid*)dst, 16, (uint32_t)v + dead,
-                                                         __builtin_amdgcn_readfirstlane(stg * BK + 8 * blk * ld),
-                                                         0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (LdsVoid*)dst, 16, (uint32_t)v + dead,
+                    __builtin_amdgcn_readfirstlane(kbyte0 + stg * BK + 8 * blk * ld), 0, 0);
             }
         };
         const int sw = dma_swz(lrow);
@@ -540,10 +544,44 @@ __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, i
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
+    if (part != nullptr) {
+        // a k-chunk of a split tile: the raw int32 sums, row-major BM x BN
+        if constexpr (PLANES == 1) {
+            const int lane2 = threadIdx.x & 63;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int r = wr * WTM + i * 32 + 8 * (e >> 2) + 4 * (lane2 >> 5) + (e & 3);
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) part[r * BN + wc * WTN + j * 32 + (lane2 & 31)] = acc[0][i][j][e];
+                }
+        }
+        return;
+    }
     if constexpr (PLANES == 1)
         store_tile_i8_reg<WTM, WTN, FM, FN>(acc[0], t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
     else
         store_tile_limb2<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+}
+
+// Tile-rounds tail of a single-task int8 launch: workgroups b < args.total_tiles
+// run whole tiles; the next ntail * nsplit run the k-chunk (b - total) % nsplit
+// of tile total + (b - total) / nsplit, writing its int32 sums to
+// part + (b - total) * 65536.  tail_reduce_kernel then adds the chunks.
+__device__ __forceinline__ void i8_dma_split_item(const ProdArgs& args, int item, int nsplit, int32_t* part,
+                                                  int8_t* smem)
+{
+    const ProdTask& t = args.inl[0];
+    const int tile = args.total_tiles + item / nsplit, chunk = item % nsplit;
+    int ti, tj;
+    if (t.syrk) band_tri(tile, t.tm, &ti, &tj);
+    else band_rect(tile, t.tm, t.tn, &ti, &tj);
+    const int nst = t.k / 128;
+    const int k0 = (int)((int64_t)nst * chunk / nsplit), k1 = (int)((int64_t)nst * (chunk + 1) / nsplit);
+    int32_t* dst = part + (int64_t)item * 65536;
+    if ((ti + 1) * 256 <= t.m && (tj + 1) * 256 <= t.n) i8_dma_body<1, false>(t, ti, tj, smem, k0, k1, dst);
+    else i8_dma_body<1, true>(t, ti, tj, smem, k0, k1, dst);
 }
 
 template <int PLANES>
@@ -570,6 +608,72 @@ __global__ __launch_bounds__(256) void prod_i8_dma_kernel(ProdArgs args, int mod
     }
     const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     if (b < args.total_tiles) i8_dma_tile<PLANES>(args, b);
+}
+
+// Single task, int8: the whole tiles [0, args.total_tiles) first (one per
+// workgroup, XCD-aware over the first nfull_grid blocks), then the k-chunks
+// of the remaining ntail tiles.
+__global__ __launch_bounds__(256) void prod_i8_dma_split_kernel(ProdArgs args, int nfull_grid, int nsplit,
+                                                                int32_t* part)
+{
+    __shared__ __attribute__((aligned(1024))) int8_t smem[2 * 64 * 1024];
+    const int bid = blockIdx.x;
+    if (bid < nfull_grid) {
+        const int b = xcd_remap(bid, nfull_grid);
+        if (b < args.total_tiles) {
+            const ProdTask& t = args.inl[0];
+            int ti, tj;
+            if (t.syrk) band_tri(b, t.tm, &ti, &tj);
+            else band_rect(b, t.tm, t.tn, &ti, &tj);
+            if ((ti + 1) * 256 <= t.m && (tj + 1) * 256 <= t.n) i8_dma_body<1, false>(t, ti, tj, smem);
+            else i8_dma_body<1, true>(t, ti, tj, smem);
+        }
+        return;
+    }
+    i8_dma_split_item(args, bid - nfull_grid, nsplit, part, smem);
+}
+
+// C of the ntail split tiles: the sum of their nsplit int32 chunks, reduced
+// mod p with alpha and beta; 16 elements per thread, 16 workgroups per tile.
+__global__ __launch_bounds__(256) void tail_reduce_kernel(ProdTask t, int tile0, int nsplit, const int32_t* part)
+{
+    const int ltile = blockIdx.x / 16, piece = blockIdx.x % 16;
+    int ti, tj;
+    if (t.syrk) band_tri(tile0 + ltile, t.tm, &ti, &tj);
+    else band_rect(tile0 + ltile, t.tm, t.tn, &ti, &tj);
+    const int e0 = (piece * 256 + (int)threadIdx.x) * 16;           // element of the 256 x 256 tile
+    const int r = e0 / 256, c0 = e0 % 256;
+    const int row = ti * 256 + r;
+    if (row >= t.m) return;
+    int32_t sum[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sum[u] = 0;
+    for (int q = 0; q < nsplit; ++q) {
+        const int32_t* src = part + ((int64_t)ltile * nsplit + q) * 65536 + e0;
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) {
+            const v4i x = *reinterpret_cast<const v4i*>(src + u);
+            sum[u] += x[0];
+            sum[u + 1] += x[1];
+            sum[u + 2] += x[2];
+            sum[u + 3] += x[3];
+        }
+    }
+    const SmallMod md(t.p);
+    const bool plain = t.alpha == 1u && t.beta == 0u;
+    uint32_t* rp = t.C + (int64_t)row * t.ldc;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int col = tj * 256 + c0 + u;
+        if (col >= t.n || (t.syrk && col > row)) continue;
+        uint32_t v = md.red_i(sum[u]);
+        if (!plain) {
+            uint32_t w = t.alpha * v;
+            if (t.beta != 0u) w += t.beta * rp[col];
+            v = md.red_u(w);
+        }
+        rp[col] = v;
+    }
 }
 
 template <int BM, int BN, int BK, int PLANES>
@@ -640,6 +744,33 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
     if constexpr (RING > 0) {
         static_assert(BK == 128 && ((PLANES == 1 && BM == 256) || (PLANES == 2 && BM == 128)) && BN == BM,
                       "direct-to-LDS variant: int8 256-tiles or two limbs on 128-tiles");
+        if constexpr (PLANES == 1) {
+            // a single task whose tiles leave the last round mostly idle: that
+            // round's tiles split along k into chunks that fill it
+            const TailScratch sc = g_tail_scratch;
+            if (mode == 1 && g_split_tail && sc.ptr != nullptr && ntasks == 1) {
+                const int R = resident_blocks((const void*)prod_i8_dma_split_kernel);
+                const int tail = R > 0 ? total % R : 0;
+                const int nst = tasks[0].k / 128;
+                if (total > R && tail > 0 && 4 * tail <= R) {
+                    int ns = R / tail;
+                    if (ns > 8) ns = 8;
+                    if (ns > nst) ns = nst;
+                    while (ns > 1 && (size_t)tail * (size_t)ns * 65536u * 4u > sc.bytes) --ns;
+                    if (ns >= 2) {
+                        ProdArgs a2 = args;
+                        a2.total_tiles = total - tail;
+                        const int nfull_grid = (total - tail + 7) / 8 * 8;
+                        g_last_variant = 6;
+                        hipLaunchKernelGGL(prod_i8_dma_split_kernel, dim3(nfull_grid + tail * ns), dim3(256), 0, s,
+                                           a2, nfull_grid, ns, (int32_t*)sc.ptr);
+                        hipLaunchKernelGGL(tail_reduce_kernel, dim3(tail * 16), dim3(256), 0, s, tasks[0],
+                                           total - tail, ns, (const int32_t*)sc.ptr);
+                        return hipGetLastError();
+                    }
+                }
+            }
+        }
         if (mode == 2) {
             const int resident = resident_blocks((const void*)prod_i8_dma_kernel<PLANES>);
             grid = total < resident ? total : resident;
@@ -745,6 +876,8 @@ bool prepare_limb3_tile_task(ProdTask* t)
 int g_i8_tile_override = 0;
 int g_i8_bk_override = 0;
 int g_i8_dma = 1;
+int g_split_tail = 1;
+thread_local TailScratch g_tail_scratch = {nullptr, 0};
 int g_i8_pipe = 1;
 
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)

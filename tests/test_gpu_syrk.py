@@ -275,6 +275,25 @@ def test_limb2_dma_variant(n, k, dtype):
         set_kblk(0)
 
 
+@pytest.mark.parametrize("n,k,depth", [(6000, 1024, 0), (5000, 640, 0), (6000, 2048, 1)])
+def test_i8_split_tail_round(n, k, depth):
+    """int8 products whose last round of 256 x 256 tiles is short: that
+    round's tiles run as k-chunks (int32 sums in scratch) added by a second
+    kernel; partial panels, alpha/beta, against the split switched off and
+    the oracle."""
+    p = 251
+    A = inputs.uniform((46, n, k), n, k, p)
+    C0 = inputs.uniform(47, n, n, p)
+    want = oracle.syrk_ab(A, p, 3, 5, C0)
+    check_lower(gpu_syrk(A, p, depth=depth, alpha=3, beta=5, C0=C0, a_dtype=ffp.FFP_I8_CENTERED), want)
+    set_knob("i8_split_tail", 0)
+    try:
+        check_lower(gpu_syrk(A, p, depth=depth, alpha=3, beta=5, C0=C0, a_dtype=ffp.FFP_I8_CENTERED), want)
+    finally:
+        set_knob("i8_split_tail", 1)
+    check_lower(gpu_syrk(A, p, depth=depth), oracle.syrk(A, p))
+
+
 @pytest.mark.parametrize("dma", [1, 0])
 @pytest.mark.parametrize("n,k", [(300, 256), (513, 128), (1000, 384), (1100, 4096), (256, 128), (600, 1280)])
 def test_i8_dma_variants(dma, n, k):
