@@ -89,7 +89,7 @@ def profile_hooks():
     def read_variants():
         """{variant: (ms, flops, launches, name)} of the recorded launches."""
         out = {}
-        for v in range(13):
+        for v in range(16):
             ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
             L.ffp_debug_profile_read_variant(v, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n))
             if n.value:

@@ -124,7 +124,9 @@ int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches
  * with operands straight to LDS, 7 int8 limbs 128x128 straight to LDS,
  * 8 FP64 128x128 with centred int32 in LDS, 9 int8 three limbs 64x64,
  * 10 int8 256x256 with the LDS writes between the MFMAs, 11 FP64 128x128
- * with doubles in LDS, 12 int8 limbs 128x128 register-staged);
+ * with doubles in LDS, 12 int8 limbs 128x128 register-staged, 13 int8
+ * 256x256 straight to LDS with the last round of tiles split along k; its
+ * time excludes the small kernel that adds the split tiles' chunks);
  * ffp_debug_variant_name gives the kernel's demangled name. */
 int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches);
 const char* ffp_debug_variant_name(int variant);

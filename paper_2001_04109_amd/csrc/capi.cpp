@@ -322,6 +322,7 @@ const char* ffp_debug_variant_name(int variant)
     case 10: return "void ffp::prod_i8_pipe_kernel<256, 256, 128, 1>(ffp::ProdArgs, int)";
     case 11: return "ffp::prod_f64_pipe_kernel(ffp::ProdArgs, int)";
     case 12: return "void ffp::prod_i8_pipe_kernel<128, 128, 128, 2>(ffp::ProdArgs, int)";
+    case 13: return "ffp::prod_i8_dma_split_kernel(ffp::ProdArgs, int, int, int*)";
     default: return "";
     }
 }

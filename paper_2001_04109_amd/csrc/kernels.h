@@ -56,6 +56,17 @@ struct ProdTask {
     int32_t tile0;    // first global tile index
 };
 
+// Operand forms of the 64 x 64 FP64 tile body (prod_f64_tile.h).
+// C = alpha A B^T + beta C (A m x k, B n x k, row-major) in the plain form; the triangular forms skip the k-range where
+// a triangular operand is zero (its zero entries inside the diagonal 64 x 64
+// blocks must be stored; blocks above them are never read):
+//   TILE_NT_BLOW  B lower triangular (B[c][t] = 0 for t > c)
+//   TILE_NN_BLOW  C = alpha A B + beta C with B k x n row-major, lower
+//                 triangular (B[t][c] = 0 for t < c)
+//   TILE_NN_ALOW  C = alpha A B + beta C with A lower triangular
+//                 (A[r][t] = 0 for t > r), B k x n row-major
+enum TileForm : int { TILE_NT = 0, TILE_NT_BLOW = 1, TILE_NN_BLOW = 2, TILE_NN_ALOW = 3 };
+
 constexpr int kInlineTasks = 6;
 struct ProdArgs {
     int32_t ntasks;
@@ -116,8 +127,13 @@ extern int g_persistent;
 // limbs, 6 int8 256x256 straight to LDS, 7 limbs 128x128 straight to LDS, 8 FP64
 // 128x128 LDS (8 waves), 9 int8
 // three limbs, 10 int8 256x256 register-staged, 11 FP64 doubles in LDS, 12 limbs
-// register-staged.
+// register-staged, 13 int8 256x256 straight to LDS with the last round's tiles
+// split along k.
 extern thread_local int g_last_variant;
+// Called by a launcher after the kernel whose time the current timing bracket
+// measures when a small follow-up kernel of the same launch comes next: the
+// bracket then ends there (no effect when timing is off).
+void prof_mark_end(hipStream_t s);
 // Workgroups of `kernel` (256 threads) resident at once on the device.
 int resident_blocks(const void* kernel, int threads = 256);
 inline int32_t cap_kblk(int64_t kb, int64_t unit)

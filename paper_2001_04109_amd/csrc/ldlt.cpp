@@ -2,6 +2,14 @@
 // Schur-complement updates S22 <- S22 - L21 D1 L21^T run as Algorithm 5
 // (D1 = Delta Delta^T, Abar = L21 Delta) followed by the accumulate form of
 // Algorithm 2 (Table 4 schedule) with alpha = p - 1, beta = 1.
+//
+// The triangular solve W = S21 L11^-T is one product with the inverse of
+// L11, which the recursion assembles from the inverses of its parts:
+// [[La, 0], [Lb, Lc]]^-1 = [[La^-1, 0], [-Lc^-1 Lb La^-1, Lc^-1]], the leaves
+// inverting their 64 x 64 unit factors; the product Lb La^-1 runs beside
+// the Schur update, the one with Lc^-1 once Lc is factored.  A node needs
+// its inverse unless it lies on the path from the root through right
+// children, so a solve never waits for a chain of smaller solves.
 #include "ldlt.h"
 
 #include <algorithm>
@@ -25,8 +33,7 @@ int64_t split_point(int64_t n) { return rup((n + 1) / 2, kLdltLeaf); }
 
 struct NodeLayout {
     int64_t abar_ld, kpad;
-    int64_t off_abar, off_flag, off_root, off_dinv, off_rank, off_desc, off_syrk;
-    int64_t bytes_before_syrk;
+    int64_t off_abar, off_syrk;
 };
 
 NodeLayout layout(int64_t n1, int64_t n2)
@@ -34,16 +41,8 @@ NodeLayout layout(int64_t n1, int64_t n2)
     NodeLayout L;
     L.kpad = rup(n1 + 1, 128);
     L.abar_ld = L.kpad;
-    int64_t off = 0;
-    auto take = [&](int64_t bytes) { int64_t o = rup(off, 256); off = o + bytes; return o; };
-    L.off_abar = take(n2 * L.abar_ld * 4);
-    L.off_flag = take(n1 * 4);
-    L.off_root = take(n1 * 4);
-    L.off_dinv = take(n1 * 4);
-    L.off_rank = take(n1 * 4);
-    L.off_desc = take((n1 + 1) * (int64_t)sizeof(ColOp));
-    L.off_syrk = rup(off, 256);
-    L.bytes_before_syrk = L.off_syrk;
+    L.off_abar = 0;
+    L.off_syrk = rup(n2 * L.abar_ld * 4, 256);
     return L;
 }
 
@@ -85,20 +84,27 @@ struct Step {
     void* ws;
 };
 
-// Flattens the recursion of one factorisation into steps.  Consecutive
-// steps depend on each other, except the block operations of one Schur
-// update, which take the levels of the level scheduler.
+// Flattens the recursion of one factorisation into steps.  Steps go one
+// level after the step they wait for; the product Lb La^-1 of a node shares
+// the level of its Schur update, and the block operations of a Schur update
+// take the levels of the level scheduler.
 struct Builder {
-    FieldPlan fpl;
-    Fp f;
-    int kb;
-    uint32_t s_lqnr, c_lqnr;
-    uint32_t* linv;     // inverses of the leaf blocks of L: column block c at linv + 64 c
-    char* ws;
-    int64_t* info;
-    int64_t lds;
-    std::deque<Plan>* plans;
-    std::vector<Step>* out;
+    FieldPlan fpl{};
+    Fp f{};
+    int kb = 0;
+    uint32_t s_lqnr = 0, c_lqnr = 0, s_inv = 0;
+    Alg5Scratch piv{};  // per pivot of the whole factorisation (LDL^T)
+    uint32_t* invbuf = nullptr;   // inverse of the left child of a node on the right spine
+    int64_t ldi = 0;
+    std::vector<uint32_t*> t1;   // per depth: Lb La^-1 of the node being built
+    std::vector<int64_t> t1ld;
+    uint32_t* wbuf = nullptr;   // W = S21 L11^-T of the current node (dense, ld n1)
+    char* ws = nullptr;         // node region: Abar, then the Schur update's workspace
+    int64_t* info = nullptr;
+    int64_t lds = 0;
+    int64_t ntotal = 0;         // order of the whole factorisation
+    std::deque<Plan>* plans = nullptr;
+    std::vector<Step>* out = nullptr;
     int level = 0;
     int status = FFP_OK;
 
@@ -109,62 +115,42 @@ struct Builder {
         d.kb = kb;
         d.s_lqnr = s_lqnr;
         d.c_lqnr = c_lqnr;
+        d.s_inv = s_inv;
         d.info = info;
         return d;
     }
-    void dev(int kind, const LdltDesc& d)
+    void dev_at(int kind, const LdltDesc& d, int lv)
     {
         Step s{};
-        s.level = level++;
+        s.level = lv;
         s.sk = SK_DEV;
         s.kind = kind;
         s.d = d;
         out->push_back(s);
     }
-    void prod(const ProdTask& t)
+    void dev(int kind, const LdltDesc& d) { dev_at(kind, d, level++); }
+    // C (m x n, ldc) <- alpha A op(B) as 64 x 64 FP64 tiles of the level's launch
+    void tile_prod(int form, int lv, const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t* C,
+                   int64_t ldc, int64_t m, int64_t n, int64_t k, uint32_t alpha)
     {
-        if (g_ldlt_fold) {
-            // a step of the per-level launch, tile by tile
-            LdltDesc d = base();
-            d.t = t;
-            if (prepare_f64_tile_task(&d.t)) {
-                dev(LK_PRODF, d);
-                return;
-            }
-        }
-        Step s{};
-        s.level = level++;
-        s.sk = SK_PROD;
-        s.cls = CLS_F64;
-        s.t = t;
-        out->push_back(s);
+        LdltDesc d = base();
+        init_task(&d.t, fpl);
+        d.t.A = DView{(void*)A, lda, 0};
+        d.t.B = DView{(void*)B, ldb, 0};
+        d.t.C = C;
+        d.t.ldc = ldc;
+        d.t.m = (int32_t)m;
+        d.t.n = (int32_t)n;
+        d.t.k = (int32_t)k;
+        d.t.syrk = 0;
+        d.t.alpha = alpha;
+        d.t.beta = 0;
+        prepare_f64_tile_task(&d.t);
+        d.pform = form;
+        dev_at(LK_PRODF, d, lv);
     }
     void plan_ops(const Plan& pl, const void* a, void* c, void* w)
     {
-        // a three-limb update (pack, product) as two steps of the per-level
-        // launches
-        if (g_ldlt_fold && pl.cls == CLS_LIMB3 && pl.ops.size() == 2 && pl.ops[0].kind == OP_PACK &&
-            pl.ops[1].kind == OP_SYRK) {
-            ProdTask t = make_task(pl, pl.ops[1], a, c, w);
-            if (prepare_limb3_tile_task(&t)) {
-                const PackDesc pk = make_pack(pl, pl.ops[0], a, c, w);
-                LdltDesc d = base();
-                d.X = (uint32_t*)pk.src.p;
-                d.ldx = pk.src.ld;
-                d.rows = pk.n;
-                d.ncols = (int32_t)pk.k;
-                d.rows_pad = pk.n_pad;
-                d.kpad = (int32_t)pk.k_pad;
-                d.Ab = (uint32_t*)pk.dst.p;
-                d.ldab = pk.dst.ld;
-                d.pplane = pk.dst.plane;
-                dev(LK_PACK3, d);
-                LdltDesc e = base();
-                e.t = t;
-                dev(LK_PRODL3, e);
-                return;
-            }
-        }
         std::vector<SchedItem> items;
         items.reserve(pl.ops.size());
         for (const Op& o : pl.ops) items.push_back(SchedItem{&pl, &o, a, c, w, 0});
@@ -192,43 +178,10 @@ struct Builder {
         level += mx + 1;
     }
 
-    // X <- X L^-T for the unit lower triangular m x m factor L whose first
-    // column is column col0 of the whole factorisation.  The blocks split as
-    // the factorisation does, so every leaf is a leaf block of rec() whose
-    // inverse is in linv.
-    void trsm(int64_t nrows, int64_t m, uint32_t* X, int64_t ldx, const uint32_t* L, int64_t ldl, int64_t col0)
-    {
-        if (nrows <= 0 || m <= 0) return;
-        if (m <= kLdltLeaf) {
-            LdltDesc d = base();
-            d.rows = nrows;
-            d.nb = (int32_t)m;
-            d.X = X;
-            d.ldx = ldx;
-            d.linv = linv + col0 * kLdltLeaf;
-            dev(LK_TRSM, d);
-            return;
-        }
-        const int64_t m1 = rup((m + 1) / 2, kLdltLeaf);
-        trsm(nrows, m1, X, ldx, L, ldl, col0);
-        // X[:, m1:] <- X[:, m1:] - X[:, :m1] L[m1:, :m1]^T
-        ProdTask t{};
-        init_task(&t, fpl);
-        t.A = DView{X, ldx, 0};
-        t.B = DView{(void*)(L + m1 * ldl), ldl, 0};
-        t.C = X + m1;
-        t.ldc = ldx;
-        t.m = (int32_t)nrows;
-        t.n = (int32_t)(m - m1);
-        t.k = (int32_t)m1;
-        t.syrk = 0;
-        t.alpha = f.p - 1;
-        t.beta = 1;
-        prod(t);
-        trsm(nrows, m - m1, X + m1, ldx, L + m1 * ldl + m1, ldl, col0 + m1);
-    }
-
-    void rec(int64_t n, uint32_t* S, int64_t offset)
+    // Factors the n x n block at S whose first pivot is pivot `offset` of the
+    // whole factorisation; when inv is not null, also writes the inverse of
+    // its unit lower factor there (ld ldi).
+    void rec(int64_t n, uint32_t* S, int64_t offset, uint32_t* inv, int depth)
     {
         if (n <= 0 || status != FFP_OK) return;
         if (n <= kLdltLeaf) {
@@ -237,41 +190,25 @@ struct Builder {
             d.X = S;
             d.ldx = lds;
             d.offset = offset;
-            d.linv = linv + offset * kLdltLeaf;
+            d.sc = piv;
+            d.linv = inv;
+            d.ldi = ldi;
             dev(LK_LEAF, d);
+            // its pivots' classes beside the next step (none after the last leaf)
+            if (offset + n < ntotal) dev_at(LK_ROOTS, d, level);
             return;
         }
         const int64_t n1 = split_point(n), n2 = n - n1;
         uint32_t* S11 = S;
         uint32_t* S21 = S + n1 * lds;
         uint32_t* S22 = S + n1 * lds + n1;
-        rec(n1, S11, offset);
-        // W = S21 L11^-T, then L21 = W D1^-1
-        trsm(n2, n1, S21, lds, S11, lds, offset);
+        uint32_t* inv1 = inv ? inv : invbuf;
+        uint32_t* inv2 = inv ? inv + n1 * (ldi + 1) : nullptr;
+        rec(n1, S11, offset, inv1, depth + 1);
+        // W = S21 L11^-T (L11^-1 lower triangular)
+        tile_prod(TILE_NT_BLOW, level++, S21, lds, inv1, ldi, wbuf, n1, n2, n1, n1, 1u);
+        // S22 <- S22 - Abar Abar^T (alpha = p - 1, beta = 1: Table 4 schedule)
         const NodeLayout L = layout(n1, n2);
-        LdltDesc d = base();
-        d.sc = Alg5Scratch{(int32_t*)(ws + L.off_flag), (uint32_t*)(ws + L.off_root),
-                           (uint32_t*)(ws + L.off_dinv), (int32_t*)(ws + L.off_rank),
-                           (ColOp*)(ws + L.off_desc)};
-        d.nb = (int32_t)n1;
-        d.X = S11;
-        d.ldx = lds;
-        dev(LK_CLASSIFY, d);
-        dev(LK_PAIR, d);
-        LdltDesc sd = d;
-        sd.rows = n2;
-        sd.X = S21;
-        dev(LK_SCALE, sd);
-        uint32_t* Ab = (uint32_t*)(ws + L.off_abar);
-        LdltDesc ad = d;
-        ad.rows = n2;
-        ad.ncols = (int32_t)(n1 + 1);
-        ad.kpad = (int32_t)L.kpad;
-        ad.X = S21;
-        ad.Ab = Ab;
-        ad.ldab = L.abar_ld;
-        dev(LK_ABAR, ad);
-        // S22 <- S22 - Abar Abar^T  (alpha = p - 1, beta = 1: Table 4 schedule)
         plans->emplace_back();
         Plan& pl = plans->back();
         const int st = build_syrk_plan(schur_request(n2, L, f.p, lds, (((uintptr_t)S22) & 15) == 0), &pl);
@@ -279,8 +216,53 @@ struct Builder {
             status = st;
             return;
         }
-        plan_ops(pl, Ab, S22, ws + L.off_syrk);
-        rec(n2, S22, offset + n1);
+        uint32_t* Ab = (uint32_t*)(ws + L.off_abar);
+        void* w = ws + L.off_syrk;
+        // Algorithm 5: L21 = W D1^-1 and Abar = L21 Delta; a three-limb
+        // update takes Abar straight in limb planes
+        LdltDesc ad = base();
+        ad.nb = (int32_t)n1;
+        ad.offset = offset;
+        ad.sc = piv;
+        ad.rows = n2;
+        ad.ncols = (int32_t)(n1 + 1);
+        ad.kpad = (int32_t)L.kpad;
+        ad.X = wbuf;
+        ad.ldx = n1;
+        ad.Y = S21;
+        ad.ldy = lds;
+        ad.Ab = Ab;
+        ad.ldab = L.abar_ld;
+        bool folded = false;
+        ProdTask lt{};
+        if (g_ldlt_fold && pl.cls == CLS_LIMB3 && pl.ops.size() == 2 && pl.ops[0].kind == OP_PACK &&
+            pl.ops[1].kind == OP_SYRK) {
+            lt = make_task(pl, pl.ops[1], Ab, S22, w);
+            const PackDesc pk = make_pack(pl, pl.ops[0], Ab, S22, w);
+            if (prepare_limb3_tile_task(&lt) && pk.k_pad == L.kpad && pk.n == n2) {
+                folded = true;
+                ad.amode = 1;
+                ad.Ab = (uint32_t*)pk.dst.p;
+                ad.ldab = pk.dst.ld;
+                ad.pplane = pk.dst.plane;
+                ad.rows_pad = pk.n_pad;
+            }
+        }
+        dev(LK_ABARX, ad);
+        // Lb La^-1 (La^-1 lower triangular), beside the Schur update
+        if (inv) tile_prod(TILE_NN_BLOW, level, S21, lds, inv1, ldi, t1[depth], t1ld[depth], n2, n1, n1, 1u);
+        if (folded) {
+            LdltDesc e = base();
+            e.t = lt;
+            dev(LK_PRODL3, e);
+        } else {
+            plan_ops(pl, Ab, S22, w);
+        }
+        rec(n2, S22, offset + n1, inv2, depth + 1);
+        // -Lc^-1 (Lb La^-1) below the diagonal blocks of the inverse
+        if (inv)
+            tile_prod(TILE_NN_ALOW, level++, inv2, ldi, t1[depth], t1ld[depth], inv + n1 * ldi, ldi, n2, n1, n2,
+                      f.p - 1);
     }
 };
 
@@ -303,8 +285,8 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
     // longest-running first); product tables for groups beyond the inline
     // capacity
     struct Slice { int first, count, blocks; };
-    static const int kOrder[LK_KINDS] = {LK_LEAF, LK_PRODL3, LK_PRODF, LK_PAIR,  LK_BDIAG, LK_CLASSIFY,
-                                         LK_TRSM, LK_PACK3,  LK_ABAR2, LK_ABAR, LK_SCALE, LK_ZERO};
+    static const int kOrder[LK_KINDS] = {LK_LEAF,     LK_PRODL3, LK_PRODF, LK_PAIR,  LK_ROOTS,
+                                         LK_BDIAG, LK_CLASSIFY, LK_ABARX, LK_ABAR2, LK_ZERO};
     std::vector<Slice> slices(maxlev + 1, Slice{0, 0, 0});
     std::vector<LdltDesc> table;
     size_t prod_bytes = 0;
@@ -409,23 +391,69 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
     return status;
 }
 
-size_t ws_need(int64_t n, uint32_t p, int64_t lds)
+// Workspace of one factorisation: the pivot data of Algorithm 5, the
+// inverse of the leading unit factor of a node on the right spine, one
+// Lb La^-1 block per recursion depth, W, then the node region (Abar and the
+// Schur update's workspace, reused node after node).
+struct JobLayout {
+    int64_t off_flag = 0, off_root = 0, off_dinv = 0, off_inv = 0, ldi = 0, off_w = 0, off_node = 0;
+    std::vector<int64_t> off_t1, ld_t1;
+    size_t bytes = 0;
+};
+
+void walk(int64_t n, int depth, bool spine, uint32_t p, int64_t lds, std::vector<int64_t>* m1,
+          std::vector<int64_t>* m2, int64_t* wmax, size_t* node_max)
 {
-    if (n <= kLdltLeaf) return 0;
+    if (n <= kLdltLeaf) return;
     const int64_t n1 = split_point(n), n2 = n - n1;
+    if ((int)m1->size() <= depth) {
+        m1->resize(depth + 1, 0);
+        m2->resize(depth + 1, 0);
+    }
+    if (!spine) {
+        (*m1)[depth] = std::max((*m1)[depth], n1);
+        (*m2)[depth] = std::max((*m2)[depth], n2);
+    }
+    *wmax = std::max(*wmax, n1 * n2);
     const NodeLayout L = layout(n1, n2);
     Plan pl;
     size_t syrk_ws = 0;
     if (build_syrk_plan(schur_request(n2, L, p, lds, false), &pl) == FFP_OK) syrk_ws = (size_t)pl.ws_bytes;
-    size_t here = (size_t)L.off_syrk + syrk_ws;
-    return std::max(here, std::max(ws_need(n1, p, lds), ws_need(n2, p, lds)));
+    *node_max = std::max(*node_max, (size_t)L.off_syrk + syrk_ws);
+    walk(n1, depth + 1, false, p, lds, m1, m2, wmax, node_max);
+    walk(n2, depth + 1, spine, p, lds, m1, m2, wmax, node_max);
 }
 
-size_t linv_bytes(int64_t n) { return (size_t)rup(n * kLdltLeaf * 4, 256); }
+JobLayout job_layout(int64_t n, uint32_t p, int64_t lds)
+{
+    JobLayout J;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { int64_t o = rup(off, 256); off = o + bytes; return o; };
+    J.off_flag = take(n * 4);
+    J.off_root = take(n * 4);
+    J.off_dinv = take(n * 4);
+    if (n > kLdltLeaf) {
+        const int64_t n1 = split_point(n);
+        J.ldi = n1;
+        J.off_inv = take(n1 * n1 * 4);
+        std::vector<int64_t> m1, m2;
+        int64_t wmax = 0;
+        size_t node_max = 0;
+        walk(n, 0, true, p, lds, &m1, &m2, &wmax, &node_max);
+        for (size_t d = 0; d < m1.size(); ++d) {
+            J.off_t1.push_back(take(m1[d] * m2[d] * 4));
+            J.ld_t1.push_back(m1[d]);
+        }
+        J.off_w = take(wmax * 4);
+        J.off_node = take((int64_t)node_max);
+    }
+    J.bytes = (size_t)rup(off, 256);
+    return J;
+}
 
 }  // namespace
 
-size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds) { return linv_bytes(n) + ws_need(n, p, lds); }
+size_t ldlt_workspace_bytes(int64_t n, uint32_t p, int64_t lds) { return job_layout(n, p, lds).bytes; }
 
 int ldlt_run_multi(const std::vector<LdltJobSpec>& jobs, hipStream_t s)
 {
@@ -440,14 +468,26 @@ int ldlt_run_multi(const std::vector<LdltJobSpec>& jobs, hipStream_t s)
         while (legendre(sq, j.p) == 1) ++sq;
         b.s_lqnr = sq;
         b.c_lqnr = (uint32_t)sqrt_mod(sq - 1, j.p);
+        b.s_inv = (uint32_t)inv_mod(sq, j.p);
+        const JobLayout J = job_layout(j.n, j.p, j.lds);
+        char* w = (char*)j.ws;
+        b.piv = Alg5Scratch{(int32_t*)(w + J.off_flag), (uint32_t*)(w + J.off_root), (uint32_t*)(w + J.off_dinv),
+                            nullptr, nullptr};
+        b.invbuf = (uint32_t*)(w + J.off_inv);
+        b.ldi = J.ldi;
+        for (size_t d = 0; d < J.off_t1.size(); ++d) {
+            b.t1.push_back((uint32_t*)(w + J.off_t1[d]));
+            b.t1ld.push_back(J.ld_t1[d]);
+        }
+        b.wbuf = (uint32_t*)(w + J.off_w);
+        b.ws = w + J.off_node;
         b.info = j.info;
         b.lds = j.lds;
-        b.linv = (uint32_t*)j.ws;
-        b.ws = (char*)j.ws + linv_bytes(j.n);
+        b.ntotal = j.n;
         b.plans = &plans;
         b.out = &steps;
         b.dev(LK_ZERO, b.base());
-        b.rec(j.n, j.S, 0);
+        b.rec(j.n, j.S, 0, nullptr, 0);
         if (b.status != FFP_OK) return b.status;
     }
     return execute_steps(steps, s);
@@ -509,7 +549,6 @@ int syrkbd_run(int64_t m, int64_t n, uint32_t p, const uint32_t* A, int64_t lda,
     b.c_lqnr = (uint32_t)sqrt_mod(sq - 1, p);
     b.info = info;
     b.lds = rq.ldc;
-    b.linv = nullptr;
     b.ws = (char*)ws;
     b.plans = &plans;
     b.out = &steps;

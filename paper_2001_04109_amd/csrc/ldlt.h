@@ -1,11 +1,11 @@
 // LDL^T factorisation without pivoting (Section 5 of the paper): recursive
-// split, unit-lower triangular solve, Algorithm 5 applied to the pivots and
-// the Schur-complement update S22 <- S22 - Abar Abar^T through the Table 4
-// schedule of fsyrk.
+// split, unit-lower triangular solve through inverses of the leading unit
+// factors, Algorithm 5 applied to the pivots and the Schur-complement update
+// S22 <- S22 - Abar Abar^T through the Table 4 schedule of fsyrk.
 //
 // The host flattens the recursion of every factorisation into a sequence of
 // steps; the steps of several factorisations run together, level by level,
-// each device step kind as one launch over an array of descriptors.
+// each level as one launch over an array of descriptors.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -28,24 +28,22 @@ struct ColOp {
 };
 
 struct Alg5Scratch {
-    int32_t* flag;      // n1: pivot is a quadratic non-residue
-    uint32_t* root;     // n1: square root of residue pivots
-    uint32_t* dinv;     // n1: inverse pivots
-    int32_t* rank_idx;  // n1: indices of the non-residues in order
-    ColOp* desc;        // n1 + 1 column operations
+    int32_t* flag;      // per pivot: quadratic non-residue
+    uint32_t* root;     // per pivot: square root (LDL^T: of D / s for a non-residue)
+    uint32_t* dinv;     // per pivot: inverse
+    int32_t* rank_idx;  // indices of the non-residues in order (fsyrkbd_modp)
+    ColOp* desc;        // n1 + 1 column operations (fsyrkbd_modp)
 };
 
 // Device step kinds.
 enum LdltKind : int32_t {
     LK_ZERO = 0,     // *info = 0
-    LK_LEAF,         // leaf factorisation of the nb x nb block at X, inverse of its unit factor to linv
-    LK_TRSM,         // X (rows x nb) <- X L^-T with L^-1 at linv
-    LK_CLASSIFY,     // Algorithm 5, per pivot of S11 = X (nb pivots): flag, root, inverse
+    LK_LEAF,         // leaf factorisation of the nb x nb block at X; inverse of its unit factor
+    LK_ROOTS,        // Algorithm 5 per pivot of a factored leaf: flag, root, inverse
+    LK_CLASSIFY,     // Algorithm 5, per pivot of X (nb pivots, stride ldx + 1): flag, root, inverse
     LK_PAIR,         // Algorithm 5: rank the non-residues, Algorithm 4 per pair, column ops
-    LK_SCALE,        // L21 = W D1^-1 (X = W, rows x nb)
-    LK_ABAR,         // Abar (rows x kpad) from the column ops on L21 = X
-    LK_PRODF,        // product task t, 64 x 64 FP64 tiles
-    LK_PACK3,        // uint32 residues -> three int8 limb planes (zero padded)
+    LK_ABARX,        // Algorithm 5 on a node's pivots: L21 = W D1^-1 and Abar from W in one pass
+    LK_PRODF,        // product task t, 64 x 64 FP64 tiles (operand form pform)
     LK_PRODL3,       // product task t, 64 x 64 three-limb int8 tiles
     LK_BDIAG,        // Algorithm 6 (odd p): column ops desc1 and diagonal dbar of a block diagonal B
     LK_ABAR2,        // Abar (rows x kpad) from the column ops desc (on A desc1) on A = X
@@ -57,23 +55,27 @@ struct LdltDesc {
     int32_t kind;      // LK_*
     Fp f;
     int32_t kb;        // residue products per FP64 partial sum
-    int32_t nb;        // leaf / solve width; Algorithm 5: n1
-    int64_t rows;      // solve, scale, abar: rows
+    int32_t nb;        // leaf order; Algorithm 5: number of pivots n1
+    int64_t rows;      // LK_ABARX, LK_ABAR2: rows of W / A
     int32_t ncols, kpad;
     int32_t block0;    // first workgroup of this descriptor in its launch
-    int32_t gx;        // scale, abar: workgroups across the columns
+    int32_t gx;        // column blocks (LK_ABARX, LK_ABAR2)
     uint32_t* X;
     int64_t ldx;
     int64_t* info;
-    int64_t offset;    // leaf: its first column in the whole factorisation
-    uint32_t* linv;
+    int64_t offset;    // leaf, LK_ABARX: index of its first pivot in the whole factorisation
+    uint32_t* linv;    // leaf: inverse of its unit factor (ld ldi), or null
+    int64_t ldi;
     Alg5Scratch sc;
-    uint32_t s_lqnr, c_lqnr;
+    uint32_t s_lqnr, c_lqnr, s_inv;   // smallest non-residue s, sqrt(s - 1), 1/s
     uint32_t* Ab;
     int64_t ldab;
+    uint32_t* Y;       // LK_ABARX: L21 (ldy)
+    int64_t ldy;
+    int32_t amode;     // LK_ABARX: 0 Abar as uint32, 1 as three int8 limb planes
+    int32_t pform;     // LK_PRODF: operand form (TILE_* of prod_f64_tile.h)
     ProdTask t;        // LK_PRODF, LK_PRODL3
-    // LK_PACK3: X (rows x ncols, ldx) -> Ab as int8 planes (ldab, plane
-    // offset pplane) of rows_pad x kpad
+    // LK_ABARX with amode 1: limb planes of rows_pad x kpad at Ab, plane offset pplane
     int64_t rows_pad, pplane;
     // LK_BDIAG: B's diagonal bd (nb entries) and off-diagonal bo (nb - 1);
     // out: desc1 (nb column ops on A), dbar (nb pivots).  LK_ABAR2 reads desc1.
@@ -90,8 +92,9 @@ int ldlt_blocks(int kind, LdltDesc* d);
 hipError_t launch_ldlt_steps(const LdltDesc* dev, int n, int total_blocks, hipStream_t s);
 // Residue products whose sum stays below 2^53, at most 64.
 int ldlt_dot_block(uint32_t p);
-// 1 (default): products of the factorisation (solve updates, three-limb
-// Schur updates) run as steps of the per-level launch; 0: separate launches.
+// 1 (default): three-limb Schur updates run as steps of the per-level
+// launch (Abar written straight into limb planes); 0: through the product
+// schedule's own launches.
 extern int g_ldlt_fold;
 
 struct LdltJobSpec {

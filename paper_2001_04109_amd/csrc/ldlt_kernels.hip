@@ -1,7 +1,7 @@
-// Kernels of the LDL^T factorisation (Section 5): leaf factorisation,
-// unit-lower triangular solve, and Algorithm 5's factorisation D = Delta
-// Delta^T (square roots of residues, Algorithm 4 on pairs of non-residues)
-// applied as column operations on L21.
+// Kernels of the LDL^T factorisation (Section 5): leaf factorisation with
+// the classification of its pivots and the inverse of its unit factor, and
+// Algorithm 5's factorisation D = Delta Delta^T (square roots of residues,
+// Algorithm 4 on pairs of non-residues) applied as column operations.
 #include "ldlt.h"
 #include "modp.h"
 #include "prod_f64_tile.h"
@@ -13,21 +13,6 @@ namespace {
 
 constexpr int NB = kLdltLeaf;   // leaf order and triangular-solve block
 
-// In-place LDL^T of an nb x nb block (nb <= NB) in LDS, followed (when
-// every pivot is nonzero) by the inverse of its unit lower triangular
-// factor, written to linv (row i at linv + 64 i, columns <= i), which the
-// triangular solves against this block use.  kb: number of products of two
-// residues whose sum stays below 2^53.
-//
-// The elimination is division-free, so no modular inverse sits on the
-// sequential path: step k replaces M[i][j] by a_k M[i][j] - M[i][k] M[j][k]
-// (i >= j > k) with a_k = M[k][k].  By induction M = g_k S_k on the
-// trailing block, where S_k is the true Schur complement and
-// g_k = a_0 ... a_{k-1}; hence D[k] = a_k / g_k and L[i][k] = M[i][k] / a_k
-// (M taken at step k), and a_k = 0 exactly when the true pivot is 0.  The
-// inverses are then formed in parallel.  The inverse of L is built from its
-// 8 x 8 diagonal blocks up: [[A, 0], [B, C]]^-1 = [[A^-1, 0], [-C^-1 B A^-1,
-// C^-1]] on blocks of 8, 16 and 32.
 struct LeafLds {
     uint32_t sm[NB][NB + 1];
     uint32_t li[NB][NB + 1];
@@ -42,14 +27,140 @@ __device__ __forceinline__ double canon(double x, double pd)
     return x < 0.0 ? x + pd : (x >= pd ? x - pd : x);
 }
 
-__device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S, int64_t lds, int64_t* info,
-                                               int64_t offset, uint32_t* linv, LeafLds& L)
+// Exclusive prefix product over the 64 lanes of a wave (lane 0: 1).
+__device__ __forceinline__ uint32_t wave_prefix_mul(uint32_t v, uint32_t p, double pinv)
 {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)v, d, 64);
+        if (lane >= d) v = mul_m(v, u, p, pinv);
+    }
+    const uint32_t e = (uint32_t)__shfl_up((int)v, 1, 64);
+    return lane == 0 ? 1u : e;
+}
+
+// Division-free elimination of the block held in registers (see
+// ldlt_leaf_body).  BIG: p >= 2^25, entries kept in [0, p).  Returns false
+// at a zero pivot (uniform: every thread reads the same pivot).
+template <bool BIG>
+__device__ __forceinline__ bool leaf_eliminate(double (&m)[4][4], int nb, int r0, int c0, double pd, double pinv,
+                                               double (&colk)[2][NB], int64_t* info, int64_t offset)
+{
+    for (int k0 = 0; k0 < nb; k0 += 4) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = k0 + kk;
+            if (k >= nb) break;
+            const double* col = colk[k & 1];
+            const double a = col[k];
+            if (canon(a, pd) == 0.0) {
+                if (threadIdx.x == 0 && *info == 0) *info = offset + k + 1;
+                return false;
+            }
+            double ci[4], cj[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                ci[x] = col[r0 + x];
+                cj[x] = col[c0 + x];
+            }
+            // every entry is updated and the rows or columns <= k keep their
+            // value by selection, so the 16 updates are independent
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    const double v = fma(a, m[x][y], -(ci[x] * cj[y]));   // |v| < 8 p^2
+                    double u = fma(-floor(v * pinv), pd, v);                // in [-p, 2p)
+                    if constexpr (BIG) u = canon(u, pd);
+                    m[x][y] = (r0 + x > k && c0 + y > k) ? u : m[x][y];
+                }
+            // owners of column k + 1 publish it for the next step
+            if (kk < 3) {
+                if (c0 == k0)
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) colk[(k + 1) & 1][r0 + x] = m[x][kk + 1];
+            } else {
+                if (c0 == k0 + 4)
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) colk[(k + 1) & 1][r0 + x] = m[x][0];
+            }
+            __syncthreads();
+        }
+    }
+    return true;
+}
+
+// One doubling step of the inverse of the unit lower factor: for each pair
+// of consecutive diagonal blocks of size B, [[A, 0], [X, C]]^-1 =
+// [[A^-1, 0], [-C^-1 X A^-1, C^-1]] from the inverses of A and C (in li,
+// zero above the diagonal).  RED: reduce after every product (p too large
+// for B products in one exact sum).
+template <int B, bool RED>
+__device__ __forceinline__ void leaf_inverse_step(LeafLds& L, uint32_t p, double pinv)
+{
+    constexpr int PAIRS = NB / (2 * B), NE = PAIRS * B * B;
+    constexpr int PER = (NE + 255) / 256;
+    const int tid = threadIdx.x;
+    // T = X A^-1
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        if (NE % 256 == 0 || e < NE) {
+            const int pr = e / (B * B), rem = e - pr * B * B, i = rem / B, j = rem - i * B;
+            const int a0 = pr * 2 * B, c0 = a0 + B;
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                const double x = (c0 + i > a0 + t) ? (double)L.sm[c0 + i][a0 + t] : 0.0;
+                acc = fma(x, (double)L.li[a0 + t][a0 + j], acc);
+                if constexpr (RED) acc = (double)mod53(acc, p, pinv);
+            }
+            L.tq[c0 + i][a0 + j] = mod53(acc, p, pinv);
+        }
+    }
+    __syncthreads();
+    // X' = -C^-1 T
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        if (NE % 256 == 0 || e < NE) {
+            const int pr = e / (B * B), rem = e - pr * B * B, i = rem / B, j = rem - i * B;
+            const int a0 = pr * 2 * B, c0 = a0 + B;
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                acc = fma((double)L.li[c0 + i][c0 + t], (double)L.tq[c0 + t][a0 + j], acc);
+                if constexpr (RED) acc = (double)mod53(acc, p, pinv);
+            }
+            const uint32_t v = mod53(acc, p, pinv);
+            L.li[c0 + i][a0 + j] = v == 0u ? 0u : p - v;
+        }
+    }
+    __syncthreads();
+}
+
+// In-place LDL^T of an nb x nb block (nb <= NB).  The elimination is
+// division-free, so no modular inverse sits on the sequential path: step k
+// replaces M[i][j] by a_k M[i][j] - M[i][k] M[j][k] (i >= j > k) with
+// a_k = M[k][k].  By induction M = g_k S_k on the trailing block, where S_k
+// is the true Schur complement and g_k = a_0 ... a_{k-1}; hence
+// D[k] = a_k / g_k and L[i][k] = M[i][k] / a_k (M taken at step k), and
+// a_k = 0 exactly when the true pivot is 0.
+//
+// With every pivot nonzero the leaf then writes, when linv is not null,
+// the inverse of its unit lower factor to linv (ld ldi; nb x nb, zero above
+// the diagonal), built from the diagonal up: [[A, 0], [X, C]]^-1 =
+// [[A^-1, 0], [-C^-1 X A^-1, C^-1]] on blocks of 1, 2, 4, ..., 32.
+__device__ __forceinline__ void ldlt_leaf_body(const LdltDesc& d, LeafLds& L)
+{
+    const Fp f = d.f;
+    const int nb = d.nb;
+    uint32_t* S = d.X;
+    const int64_t lds = d.ldx;
     auto& sm = L.sm;
     auto& li = L.li;
-    auto& tq = L.tq;
     auto& ainv = L.ainv;
-    auto& colk = L.colk;
     const uint32_t p = f.p;
     const double pd = (double)p, pinv = f.pinv;
     const int tid = threadIdx.x;
@@ -64,7 +175,6 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
     // pivot at every step for the zero test.  For p >= 2^25 every entry is
     // brought into [0, p) after each update instead.
     const int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
-    const bool big = p >= (1u << 25);
     double m[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -77,74 +187,29 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
         }
     if (c0 == 0)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) colk[0][r0 + a] = m[a][0];
+        for (int a = 0; a < 4; ++a) L.colk[0][r0 + a] = m[a][0];
     __syncthreads();
-    bool stop = false;
-    for (int k0 = 0; k0 < nb && !stop; k0 += 4) {
+    const bool ok = p >= (1u << 25) ? leaf_eliminate<true>(m, nb, r0, c0, pd, pinv, L.colk, d.info, d.offset)
+                                    : leaf_eliminate<false>(m, nb, r0, c0, pd, pinv, L.colk, d.info, d.offset);
+    if (!ok) return;   // contents unspecified after a zero pivot
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const int k = k0 + kk;
-            if (k >= nb) break;
-            const double* col = colk[k & 1];
-            const double a = col[k];
-            if (canon(a, pd) == 0.0) {
-                if (tid == 0 && *info == 0) *info = offset + k + 1;
-                stop = true;                          // every thread read the same a
-                break;
-            }
-            double ci[4], cj[4];
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                ci[x] = col[r0 + x];
-                cj[x] = col[c0 + x];
-            }
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y)
-                    if (r0 + x > k && c0 + y > k) {
-                        const double v = fma(a, m[x][y], -(ci[x] * cj[y]));   // |v| < 8 p^2
-                        m[x][y] = fma(-floor(v * pinv), pd, v);               // in [-p, 2p)
-                        // p >= 2^25: 8 p^2 passes 2^53, so entries stay in
-                        // [0, p) (then |v| < p^2 < 2^53)
-                        if (big) m[x][y] = canon(m[x][y], pd);
-                    }
-            // owners of column k + 1 publish it for the next step
-            if (kk < 3) {
-                if (c0 == k0)
-#pragma unroll
-                    for (int x = 0; x < 4; ++x) colk[(k + 1) & 1][r0 + x] = m[x][kk + 1];
-            } else {
-                if (c0 == k0 + 4)
-#pragma unroll
-                    for (int x = 0; x < 4; ++x) colk[(k + 1) & 1][r0 + x] = m[x][0];
-            }
-            __syncthreads();
+        for (int b = 0; b < 4; ++b) {
+            const int i = r0 + a, j = c0 + b;
+            if (i < nb && j <= i) sm[i][j] = (uint32_t)canon(m[a][b], pd);
         }
-    }
-    if (!stop) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = r0 + a, j = c0 + b;
-                if (i < nb && j <= i) sm[i][j] = (uint32_t)canon(m[a][b], pd);
-            }
+    __syncthreads();
+    // one wave: D[k] = a_k / g_k with 1/g_k the prefix product of the 1/a
+    if (tid < 64) {
+        const int k = tid;
+        const uint32_t a = k < nb ? sm[k][k] : 1u;
+        const uint32_t ai = pow_m(a, p - 2, p, pinv);
+        const uint32_t gi = wave_prefix_mul(ai, p, pinv);
+        ainv[k] = ai;
+        if (k < nb) sm[k][k] = mul_m(a, gi, p, pinv);
     }
     __syncthreads();
-    if (stop) return;   // contents unspecified after a zero pivot
-    // D[k] = a_k / g_k, L[i][k] = M[i][k] / a_k
-    uint32_t dk = 0u;
-    if (tid < nb) {
-        const int k = tid;
-        uint32_t g = 1u;
-        for (int t = 0; t < k; ++t) g = mul_m(g, sm[t][t], p, pinv);
-        const uint32_t a = sm[k][k];
-        ainv[k] = pow_m(a, p - 2, p, pinv);
-        dk = mul_m(a, pow_m(g, p - 2, p, pinv), p, pinv);
-    }
-    __syncthreads();                 // every a_k read before D overwrites the diagonal
-    if (tid < nb) sm[tid][tid] = dk;
     for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
         if (j < i) sm[i][j] = mul_m(sm[i][j], ainv[j], p, pinv);
@@ -154,121 +219,33 @@ __device__ __forceinline__ void ldlt_leaf_body(Fp f, int kb, int nb, uint32_t* S
         const int i = e / nb, j = e % nb;
         if (j <= i) S[(int64_t)i * lds + j] = sm[i][j];
     }
+    if (d.linv == nullptr) return;
     // inverse of the unit lower factor; rows and columns past nb act as an
-    // identity block.  Strict lower entries of L: lo(i, j).
-    auto lo = [&](int i, int j) -> uint32_t { return (i < nb && j < nb) ? sm[i][j] : 0u; };
-    // 8 x 8 diagonal blocks by forward substitution, one column per thread
-    if (tid < NB) {
-        const int q = tid >> 3, c = tid & 7, b0 = q * 8;
-        li[b0 + c][b0 + c] = 1u;
-        for (int i = c + 1; i < 8; ++i) {
-            double acc = 0.0;
-            int cnt = 1;
-            for (int t = c; t < i; ++t) {   // at most 7 terms
-                acc = fma((double)lo(b0 + i, b0 + t), (double)li[b0 + t][b0 + c], acc);
-                if (++cnt == kb) { acc = (double)mod53(acc, p, pinv); cnt = 1; }
-            }
-            const uint32_t v = mod53(acc, p, pinv);
-            li[b0 + i][b0 + c] = v == 0u ? 0u : p - v;
-        }
+    // identity block
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        li[i][j] = i == j ? 1u : 0u;
+        if (i >= nb || j >= nb) sm[i][j] = 0u;
     }
     __syncthreads();
-    for (int b = 8; b < NB; b *= 2) {
-        const int pairs = NB / (2 * b);
-        // T = B A^-1 for each pair: B = L[C rows][A cols], A^-1 lower triangular
-        for (int e = tid; e < pairs * b * b; e += blockDim.x) {
-            const int q = e / (b * b), rem = e - q * b * b, i = rem / b, j = rem - i * b;
-            const int a0 = q * 2 * b, c0 = a0 + b;
-            double acc = 0.0;
-            int cnt = 1;   // slots of a block: the (reduced) accumulator and kb - 1 products
-            for (int t = j; t < b; ++t) {
-                acc = fma((double)lo(c0 + i, a0 + t), (double)li[a0 + t][a0 + j], acc);
-                if (++cnt == kb) { acc = (double)mod53(acc, p, pinv); cnt = 1; }
-            }
-            tq[c0 + i][a0 + j] = mod53(acc, p, pinv);
-        }
-        __syncthreads();
-        // X21 = -C^-1 T
-        for (int e = tid; e < pairs * b * b; e += blockDim.x) {
-            const int q = e / (b * b), rem = e - q * b * b, i = rem / b, j = rem - i * b;
-            const int a0 = q * 2 * b, c0 = a0 + b;
-            double acc = 0.0;
-            int cnt = 1;
-            for (int t = 0; t <= i; ++t) {
-                acc = fma((double)li[c0 + i][c0 + t], (double)tq[c0 + t][a0 + j], acc);
-                if (++cnt == kb) { acc = (double)mod53(acc, p, pinv); cnt = 1; }
-            }
-            const uint32_t v = mod53(acc, p, pinv);
-            li[c0 + i][a0 + j] = v == 0u ? 0u : p - v;
-        }
-        __syncthreads();
+    if (d.kb > NB / 2) {
+        leaf_inverse_step<1, false>(L, p, pinv);
+        leaf_inverse_step<2, false>(L, p, pinv);
+        leaf_inverse_step<4, false>(L, p, pinv);
+        leaf_inverse_step<8, false>(L, p, pinv);
+        leaf_inverse_step<16, false>(L, p, pinv);
+        leaf_inverse_step<32, false>(L, p, pinv);
+    } else {
+        leaf_inverse_step<1, true>(L, p, pinv);
+        leaf_inverse_step<2, true>(L, p, pinv);
+        leaf_inverse_step<4, true>(L, p, pinv);
+        leaf_inverse_step<8, true>(L, p, pinv);
+        leaf_inverse_step<16, true>(L, p, pinv);
+        leaf_inverse_step<32, true>(L, p, pinv);
     }
     for (int e = tid; e < nb * nb; e += blockDim.x) {
         const int i = e / nb, j = e % nb;
-        if (j <= i) linv[i * NB + j] = li[i][j];
-    }
-}
-
-// X <- X L^-T for an nrows x nb block X, given Linv = L^-1 of the unit lower
-// triangular nb x nb factor (row i at linv + 64 i, columns <= i):
-// X'[r][c] = sum_{t <= c} X[r][t] Linv[c][t].  64 rows per workgroup; each
-// thread forms a 4 x 4 block of entries in FP64 with delayed reduction
-// (Linv is zero above the diagonal in LDS, so every sum runs over all t).
-constexpr int TR = 64;
-struct TrsmLds {
-    double sl[NB][NB + 1];
-    double sx[TR][NB + 1];
-};
-
-__device__ __forceinline__ void trsm_inv_body(Fp f, int kb, int64_t nrows, int nb, uint32_t* X, int64_t ldx,
-                                              const uint32_t* linv, int lb, TrsmLds& L)
-{
-    auto& sl = L.sl;
-    auto& sx = L.sx;
-    const uint32_t p = f.p;
-    const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)lb * TR;
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int i = e / NB, j = e % NB;
-        sl[i][j] = (i < nb && j <= i) ? (double)linv[i * NB + j] : 0.0;
-    }
-    for (int e = tid; e < TR * NB; e += 256) {
-        const int i = e / NB, j = e % NB;
-        sx[i][j] = (r0 + i < nrows && j < nb) ? (double)X[(r0 + i) * ldx + j] : 0.0;
-    }
-    __syncthreads();
-    const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    int cnt = 1;   // slots of a block: the (reduced) accumulator and kb - 1 products
-    for (int t = 0; t < NB; ++t) {
-        double xv[4], lv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) xv[a] = sx[tr + a][t];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) lv[b] = sl[tc + b][t];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], lv[b], acc[a][b]);
-        if (++cnt == kb) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = (double)mod53(acc[a][b], p, f.pinv);
-            cnt = 1;
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t r = r0 + tr + a;
-        if (r >= nrows) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-            if (tc + b < nb) X[r * ldx + tc + b] = mod53(acc[a][b], p, f.pinv);
+        d.linv[(int64_t)i * d.ldi + j] = li[i][j];
     }
 }
 
@@ -348,44 +325,155 @@ __device__ __forceinline__ void pair_body(Fp f, int n1, const uint32_t* S, int64
     if (tid == 0 && (total & 1) == 0) desc[n1] = ColOp{-1, 0u, -1, 0u};
 }
 
-// Abar (uint32 residues, rows x ncols at X) into three int8 limb planes of
-// rows_pad x kpad at Ab (zero padded), for the three-limb Schur product.
-__device__ __forceinline__ void pack3_body(const LdltDesc& d, int bx, int by, int gy)
+// Algorithm 5 per pivot of a factored leaf (D[k] on the diagonal of X,
+// k < nb; pivot j = offset + k of the whole factorisation):
+//   flag[j]  1 if D[k] is a quadratic non-residue (Euler's criterion),
+//   root[j]  a square root of D[k] for a residue, of D[k] / s for a
+//            non-residue (s the smallest non-residue),
+//   dinv[j]  the inverse of D[k].
+// It runs beside the step after the leaf: the first use of these values is
+// the column step of an ancestor, after that ancestor's solve.
+__device__ __forceinline__ void leaf_roots_body(const LdltDesc& d)
 {
-    const int64_t c = (int64_t)bx * 64 + (threadIdx.x & 63);
-    if (c >= d.kpad) return;
-    int8_t* __restrict__ dst = (int8_t*)d.Ab;
-    for (int64_t r = (int64_t)by * 4 + (threadIdx.x >> 6); r < d.rows_pad; r += (int64_t)gy * 4) {
-        const uint32_t v = (r < d.rows && c < d.ncols) ? d.X[r * d.ldx + c] : 0u;
-        const int64_t o = r * d.ldab + c;
-        limb3_split(v > d.f.half ? (int)v - (int)d.f.p : (int)v, &dst[o], &dst[d.pplane + o], &dst[2 * d.pplane + o]);
+    const int k = threadIdx.x;
+    if (k >= d.nb) return;
+    const uint32_t p = d.f.p;
+    const double pinv = d.f.pinv;
+    const uint32_t dk = d.X[(int64_t)k * (d.ldx + 1)];
+    const uint32_t x = pow_m(dk, (p - 3) / 2, p, pinv);            // D^((p-3)/2)
+    const bool nr = mul_m(x, dk, p, pinv) == p - 1;
+    const int64_t j = d.offset + k;
+    d.sc.flag[j] = nr ? 1 : 0;
+    d.sc.dinv[j] = mul_m(mul_m(x, x, p, pinv), dk, p, pinv);       // D^(p-2)
+    d.sc.root[j] = sqrt_m(nr ? mul_m(dk, d.s_inv, p, pinv) : dk, d.s_lqnr, p, pinv);
+}
+
+// Algorithm 5 on the n1 pivots of a node (classified by the leaves), with
+// L21 = W D1^-1: writes L21 (Y) and Abar = L21 Delta (n1 + 1 columns, zero
+// up to kpad) in one pass over W (rows x n1).  Residue pivot j:
+// Abar_j = sqrt(D_j) L_j.  The non-residues are paired in index order
+// (rank 2t with rank 2t + 1); for a pair (i, j), with r_x = sqrt(D_x / s) and
+// c = sqrt(s - 1) (s the smallest non-residue), Algorithm 3 gives
+// D_i = a^2 + b^2 with a = r_i, b = c r_i, and Algorithm 4 takes the root
+// r_j / r_i of D_j / D_i, so that
+//   [Abar_i Abar_j] = [L_i L_j] [[r_i, c r_i], [-c r_j, r_j]],
+// whose rows are orthogonal with squared norms D_i, D_j.  An odd one out i
+// pairs with the extra column: Abar_i = r_i L_i, Abar_(n1) = c r_i L_i.
+// Every workgroup finds the ranks and partners of its 64 columns itself
+// (a count and the nearest non-residues outside its block from the
+// pivot flags), so no separate pairing step runs.
+//   amode 0: Abar as uint32 residues (ldab); 1: as three int8 limb planes
+//   (ldab, plane pplane, rows zero-padded to rows_pad).
+struct AbarLds {
+    int32_t red[3][4];
+};
+
+__device__ __forceinline__ void build_abarx_body(const LdltDesc& d, int bx, int by, int gy, AbarLds& L)
+{
+    const Fp f = d.f;
+    const uint32_t p = f.p;
+    const int n1 = d.nb;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int cb = bx * 64, c = cb + lane;
+    const int32_t* flag = d.sc.flag + d.offset;
+    const uint32_t* root = d.sc.root + d.offset;
+    const uint32_t* dinv = d.sc.dinv + d.offset;
+    // non-residues before the block (count, last index) and after it (first index)
+    int cnt = 0, prev = -1, next = 0x7FFFFFFF;
+    for (int t = tid; t < n1; t += 256) {
+        if (t >= cb && t < cb + 64) continue;
+        if (flag[t] != 0) {
+            if (t < cb) {
+                ++cnt;
+                prev = t;   // increasing in t
+            } else if (next == 0x7FFFFFFF) {
+                next = t;
+            }
+        }
     }
-}
-
-// L21 = W D^-1 in place (column j scaled by dinv[j]).
-__device__ __forceinline__ void scale_cols_body(Fp f, int64_t rows, int n1, uint32_t* W, int64_t ldw,
-                                                const uint32_t* dinv, int bx, int by, int gy)
-{
-    const int64_t c = (int64_t)bx * 64 + (threadIdx.x & 63);
-    if (c >= n1) return;
-    const uint32_t s = dinv[c];
-    for (int64_t r = (int64_t)by * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gy * 4)
-        W[r * ldw + c] = mul_m(W[r * ldw + c], s, f.p, f.pinv);
-}
-
-// Abar[:, c] from the column operations (zero beyond ncols, up to kpad).
-__device__ __forceinline__ void build_abar_body(Fp f, int64_t rows, int ncols, int kpad, const uint32_t* L,
-                                                int64_t ldl, const ColOp* desc, uint32_t* Ab, int64_t ldab,
-                                                int bx, int by, int gy)
-{
-    const int64_t c = (int64_t)bx * 64 + (threadIdx.x & 63);
-    if (c >= kpad) return;
-    ColOp o = c < ncols ? desc[c] : ColOp{-1, 0u, -1, 0u};
-    for (int64_t r = (int64_t)by * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gy * 4) {
-        uint32_t v = 0;
-        if (o.j1 >= 0) v = mul_m(L[r * ldl + o.j1], o.s1, f.p, f.pinv);
-        if (o.j2 >= 0) v = add_m(v, mul_m(L[r * ldl + o.j2], o.s2, f.p, f.pinv), f.p);
-        Ab[r * ldab + c] = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt += __shfl_xor(cnt, o, 64);
+        prev = max(prev, __shfl_xor(prev, o, 64));
+        next = min(next, __shfl_xor(next, o, 64));
+    }
+    if (lane == 0) {
+        L.red[0][wv] = cnt;
+        L.red[1][wv] = prev;
+        L.red[2][wv] = next;
+    }
+    __syncthreads();
+    cnt = L.red[0][0] + L.red[0][1] + L.red[0][2] + L.red[0][3];
+    prev = max(max(L.red[1][0], L.red[1][1]), max(L.red[1][2], L.red[1][3]));
+    next = min(min(L.red[2][0], L.red[2][1]), min(L.red[2][2], L.red[2][3]));
+    // this lane's column: Abar_c = s1 W_j1 + s2 W_j2 (the D^-1 of L folded in)
+    const bool nr = c < n1 && flag[c] != 0;
+    const uint64_t bal = __ballot(nr);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int rank = cnt + __popcll(bal & lt);
+    const uint64_t above = lane == 63 ? 0ull : (bal >> (lane + 1)) << (lane + 1);
+    const uint64_t below = bal & lt;
+    auto next_nr = [&]() { return above ? cb + __ffsll((long long)above) - 1 : (next < n1 ? next : -1); };
+    auto prev_nr = [&]() { return below ? cb + 63 - __clzll(below) : prev; };
+    int j1 = -1, j2 = -1;
+    uint32_t s1 = 0u, s2 = 0u;
+    if (c < n1) {
+        const uint32_t rc = root[c], dc = dinv[c];
+        if (!nr) {
+            j1 = c;
+            s1 = mul_m(rc, dc, p, f.pinv);
+        } else if ((rank & 1) == 0) {
+            j1 = c;
+            s1 = mul_m(rc, dc, p, f.pinv);
+            const int j = next_nr();
+            if (j >= 0) {
+                j2 = j;
+                s2 = sub_m(0u, mul_m(mul_m(d.c_lqnr, root[j], p, f.pinv), dinv[j], p, f.pinv), p);
+            }
+        } else {
+            const int i = prev_nr();
+            j1 = i;
+            s1 = mul_m(mul_m(d.c_lqnr, root[i], p, f.pinv), dinv[i], p, f.pinv);
+            j2 = c;
+            s2 = mul_m(rc, dc, p, f.pinv);
+        }
+    } else if (c == n1 && (rank & 1) != 0) {
+        const int i = prev_nr();   // the odd one out
+        j1 = i;
+        s1 = mul_m(mul_m(d.c_lqnr, root[i], p, f.pinv), dinv[i], p, f.pinv);
+    }
+    if (c >= d.kpad) return;
+    const uint32_t dself = c < n1 ? dinv[c] : 0u;
+    const uint32_t* W = d.X;
+    const int64_t rows_out = d.amode == 1 ? d.rows_pad : d.rows;
+    // rows in batches of four per thread, their loads issued together
+    constexpr int RB = 4;
+    for (int64_t rb = (int64_t)by * 4 * RB; rb < rows_out; rb += (int64_t)gy * 4 * RB) {
+        uint32_t w1[RB], w2[RB], wc[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int64_t r = rb + 4 * q + wv;
+            const bool in = r < d.rows;
+            const uint32_t* w = W + (in ? r : 0) * d.ldx;
+            w1[q] = (in && j1 >= 0) ? w[j1] : 0u;
+            w2[q] = (in && j2 >= 0) ? w[j2] : 0u;
+            wc[q] = (in && c < n1) ? w[c] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int64_t r = rb + 4 * q + wv;
+            if (r >= rows_out) break;
+            const uint32_t v = add_m(mul_m(w1[q], s1, p, f.pinv), mul_m(w2[q], s2, p, f.pinv), p);
+            if (r < d.rows && c < n1) d.Y[r * d.ldy + c] = mul_m(wc[q], dself, p, f.pinv);
+            if (d.amode == 1) {
+                int8_t* dst = (int8_t*)d.Ab;
+                const int64_t o = r * d.ldab + c;
+                limb3_split(v > f.half ? (int)v - (int)p : (int)v, &dst[o], &dst[d.pplane + o],
+                            &dst[2 * d.pplane + o]);
+            } else {
+                d.Ab[r * d.ldab + c] = v;
+            }
+        }
     }
 }
 
@@ -485,7 +573,7 @@ __device__ inline int desc_of(const LdltDesc* D, int n, int b)
     return lo;
 }
 
-constexpr int kRowBands = 256;   // scale, abar: at most this many bands of 4 rows per descriptor
+constexpr int kRowBands = 256;   // LK_ABAR2: at most this many bands of 4 rows per descriptor
 
 __host__ __device__ inline int row_bands(int64_t rows)
 {
@@ -493,14 +581,23 @@ __host__ __device__ inline int row_bands(int64_t rows)
     return (int)(g < 1 ? 1 : (g > kRowBands ? kRowBands : g));
 }
 
+// LK_ABARX: bands of 16 rows (one batch of four rows per thread), at most
+// 64 bands, since each workgroup first works out the pairing of its 64
+// columns from all n1 pivot flags
+__host__ __device__ inline int abar_bands(int64_t rows)
+{
+    const int64_t g = (rows + 15) / 16;
+    return (int)(g < 1 ? 1 : (g > 64 ? 64 : g));
+}
+
 // One launch runs the device steps of one level, whatever their kinds:
 // workgroup b takes the descriptor whose block range holds b and runs the
 // step of its kind (uniform per workgroup).  The steps share one LDS area.
 union StepLds {
     LeafLds leaf;
-    TrsmLds trsm;
     PairLds pair;
     BdiagLds bdiag;
+    AbarLds abar;
     int8_t i8[I8Tile<64, 64, 64, 3>::LDS];
 };
 
@@ -514,10 +611,10 @@ __global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n
         if (threadIdx.x == 0) *d.info = 0;
         break;
     case LK_LEAF:
-        ldlt_leaf_body(d.f, d.kb, d.nb, d.X, d.ldx, d.info, d.offset, d.linv, lds.leaf);
+        ldlt_leaf_body(d, lds.leaf);
         break;
-    case LK_TRSM:
-        trsm_inv_body(d.f, d.kb, d.rows, d.nb, d.X, d.ldx, d.linv, lb, lds.trsm);
+    case LK_ROOTS:
+        leaf_roots_body(d);
         break;
     case LK_CLASSIFY:
         classify_body(d.f, d.nb, d.X, d.ldx, d.s_lqnr, d.sc.flag, d.sc.root, d.sc.dinv, lb);
@@ -526,18 +623,16 @@ __global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n
         pair_body(d.f, d.nb, d.X, d.ldx, d.sc.flag, d.sc.root, d.sc.rank_idx, d.s_lqnr, d.c_lqnr, d.s_lqnr,
                   d.sc.desc, lds.pair);
         break;
-    case LK_SCALE:
-        scale_cols_body(d.f, d.rows, d.nb, d.X, d.ldx, d.sc.dinv, lb % d.gx, lb / d.gx, row_bands(d.rows));
-        break;
-    case LK_ABAR:
-        build_abar_body(d.f, d.rows, d.ncols, d.kpad, d.X, d.ldx, d.sc.desc, d.Ab, d.ldab, lb % d.gx, lb / d.gx,
-                        row_bands(d.rows));
+    case LK_ABARX:
+        build_abarx_body(d, lb % d.gx, lb / d.gx, abar_bands(d.amode == 1 ? d.rows_pad : d.rows), lds.abar);
         break;
     case LK_PRODF:
-        f64_tile_task(d.t, lb);
-        break;
-    case LK_PACK3:
-        pack3_body(d, lb % d.gx, lb / d.gx, row_bands(d.rows_pad));
+        switch (d.pform) {
+        case TILE_NT_BLOW: f64_tile_task<TILE_NT_BLOW>(d.t, lb); break;
+        case TILE_NN_BLOW: f64_tile_task<TILE_NN_BLOW>(d.t, lb); break;
+        case TILE_NN_ALOW: f64_tile_task<TILE_NN_ALOW>(d.t, lb); break;
+        default: f64_tile_task<TILE_NT>(d.t, lb); break;
+        }
         break;
     case LK_PRODL3:
         i8_tile_task<64, 64, 64, 3>(d.t, lb, lds.i8);
@@ -571,20 +666,18 @@ int ldlt_blocks(int kind, LdltDesc* d)
     switch (kind) {
     case LK_ZERO:
     case LK_LEAF:
+    case LK_ROOTS:
     case LK_BDIAG:
     case LK_PAIR: return 1;
-    case LK_TRSM: return (int)((d->rows + TR - 1) / TR);
     case LK_CLASSIFY: return (d->nb + 255) / 256;
-    case LK_SCALE:
-        d->gx = (d->nb + 63) / 64;
-        return d->rows > 0 ? d->gx * row_bands(d->rows) : 0;
-    case LK_ABAR:
+    case LK_ABARX: {
+        d->gx = (d->kpad + 63) / 64;
+        const int64_t rows = d->amode == 1 ? d->rows_pad : d->rows;
+        return rows > 0 ? d->gx * abar_bands(rows) : 0;
+    }
     case LK_ABAR2:
         d->gx = (d->kpad + 63) / 64;
         return d->rows > 0 ? d->gx * row_bands(d->rows) : 0;
-    case LK_PACK3:
-        d->gx = (d->kpad + 63) / 64;
-        return d->rows_pad > 0 ? d->gx * row_bands(d->rows_pad) : 0;
     case LK_PRODF:
     case LK_PRODL3:
         return d->t.syrk ? d->t.tm * (d->t.tm + 1) / 2 : d->t.tm * d->t.tn;

@@ -48,8 +48,10 @@ __device__ inline double centred(uint32_t v, uint32_t half, uint32_t p)
 
 // Tile r (row-major over the task's tile grid, or over its lower triangle
 // for a SYRK task) of one product task.
+template <int FORM = TILE_NT>
 __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
 {
+    constexpr bool NN = FORM == TILE_NN_BLOW || FORM == TILE_NN_ALOW;
     int ti, tj;
     if (t.syrk) tri_index(r, &ti, &tj);
     else { ti = r / t.tn; tj = r - ti * t.tn; }
@@ -63,10 +65,15 @@ __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
     const int lr = lane & 15, lk = lane >> 4;
     const uint32_t* __restrict__ Ab = (const uint32_t*)t.A.p;
     const uint32_t* __restrict__ Bb = (const uint32_t*)t.B.p;
-    const bool vec_ok = ((t.A.ld & 3) == 0) && ((t.B.ld & 3) == 0) &&
-                        ((((uintptr_t)Ab) & 15) == 0) && ((((uintptr_t)Bb) & 15) == 0);
+    const bool vec_ok = ((t.A.ld & 3) == 0) && (NN || (t.B.ld & 3) == 0) &&
+                        ((((uintptr_t)Ab) & 15) == 0) && (NN || (((uintptr_t)Bb) & 15) == 0);
     const double pd = (double)t.p;
     const int K = t.k;
+    // k-range of the tile (multiples of 16 except the end of k)
+    int kbeg = 0, kend = K;
+    if constexpr (FORM == TILE_NT_BLOW) kend = min(K, (tj + 1) * BN);
+    if constexpr (FORM == TILE_NN_BLOW) kbeg = min(K, tj * BN);
+    if constexpr (FORM == TILE_NN_ALOW) kend = min(K, (ti + 1) * BM);
 
     v4d acc[WM][WN];
 #pragma unroll
@@ -81,7 +88,7 @@ __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
     // For p above 2^25 fewer than 16 columns fit one exact block (kblk < 16):
     // the accumulators are then reduced after every 4-column step.
     const double pm1 = (double)(t.p - 1);
-    const bool raw = (double)K * pm1 * pm1 < 9007199254740992.0 - 2.0 * pd;
+    const bool raw = (double)(kend - kbeg) * pm1 * pm1 < 9007199254740992.0 - 2.0 * pd;
     auto reduce_all = [&]() {
 #pragma unroll
         for (int i = 0; i < WM; ++i)
@@ -90,37 +97,75 @@ __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[i][j][e] = mod_f64(acc[i][j][e], pd, t.pinv);
     };
+    // B of the NN forms: element (t, c) at Bb + t ldb + c; lane (lr, lk)
+    // takes rows kc .. kc + 3 of its column (16 lanes read 64 contiguous bytes)
+    auto loadb = [&](int kc, Loaded (&lb)[WN]) {
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            if constexpr (NN) {
+                const int col = col0 + j * 16 + lr;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    lb[j].v[q] = (col < t.n && kc + q < K) ? Bb[(int64_t)(kc + q) * t.B.ld + col] : 0u;
+            } else {
+                load4(Bb, t.B.ld, col0 + j * 16 + lr, t.n, kc, K, vec_ok, lb[j]);
+            }
+        }
+    };
+    // operands in chunks of CH 16-column steps; the next chunk is loaded
+    // while the current one is multiplied
+    constexpr int CH = 2;
+    auto load_chunk = [&](int k0, Loaded (&a)[CH][WM], Loaded (&b)[CH][WN]) {
+#pragma unroll
+        for (int h = 0; h < CH; ++h) {
+            const int kc = k0 + 16 * h + 4 * lk;
+#pragma unroll
+            for (int i = 0; i < WM; ++i) load4(Ab, t.A.ld, row0 + i * 16 + lr, t.m, kc, K, vec_ok, a[h][i]);
+            loadb(kc, b[h]);
+        }
+    };
     auto kloop = [&](auto rawc, auto stepc) {
         constexpr bool RAW = decltype(rawc)::value;
         constexpr bool STEP = decltype(stepc)::value;
-        Loaded la[WM], lb[WN];
+        Loaded la[CH][WM], lb[CH][WN];
         int since_red = 0;
-        for (int kk = 0; kk < K; kk += 16) {
-            const int kc = kk + 4 * lk;
+        if (kbeg < kend) load_chunk(kbeg, la, lb);
+        for (int kk = kbeg; kk < kend; kk += 16 * CH) {
+            Loaded na[CH][WM], nb[CH][WN];
+            if (kk + 16 * CH < kend) load_chunk(kk + 16 * CH, na, nb);
 #pragma unroll
-            for (int i = 0; i < WM; ++i) load4(Ab, t.A.ld, row0 + i * 16 + lr, t.m, kc, K, vec_ok, la[i]);
+            for (int h = 0; h < CH; ++h) {
+                if (kk + 16 * h >= kend) break;
 #pragma unroll
-            for (int j = 0; j < WN; ++j) load4(Bb, t.B.ld, col0 + j * 16 + lr, t.n, kc, K, vec_ok, lb[j]);
+                for (int s = 0; s < 4; ++s) {
+                    double av[WM], bv[WN];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                double av[WM], bv[WN];
-#pragma unroll
-                for (int i = 0; i < WM; ++i) av[i] = RAW ? (double)la[i].v[s] : centred(la[i].v[s], t.half, t.p);
-#pragma unroll
-                for (int j = 0; j < WN; ++j) bv[j] = RAW ? (double)lb[j].v[s] : centred(lb[j].v[s], t.half, t.p);
-#pragma unroll
-                for (int i = 0; i < WM; ++i)
+                    for (int i = 0; i < WM; ++i)
+                        av[i] = RAW ? (double)la[h][i].v[s] : centred(la[h][i].v[s], t.half, t.p);
 #pragma unroll
                     for (int j = 0; j < WN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
-                if constexpr (STEP) reduce_all();
-            }
-            if constexpr (!RAW && !STEP) {
-                since_red += 16;
-                if (since_red >= t.kblk && kk + 16 < K) {
-                    since_red = 0;
-                    reduce_all();
+                        bv[j] = RAW ? (double)lb[h][j].v[s] : centred(lb[h][j].v[s], t.half, t.p);
+#pragma unroll
+                    for (int i = 0; i < WM; ++i)
+#pragma unroll
+                        for (int j = 0; j < WN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    if constexpr (STEP) reduce_all();
                 }
+                if constexpr (!RAW && !STEP) {
+                    since_red += 16;
+                    if (since_red >= t.kblk && kk + 16 * (h + 1) < kend) {
+                        since_red = 0;
+                        reduce_all();
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < CH; ++h) {
+#pragma unroll
+                for (int i = 0; i < WM; ++i) la[h][i] = na[h][i];
+#pragma unroll
+                for (int j = 0; j < WN; ++j) lb[h][j] = nb[h][j];
             }
         }
     };
@@ -166,5 +211,6 @@ __device__ __forceinline__ void f64_tile_task(const ProdTask& t, int r)
 
 using f64tile::centred;
 using f64tile::f64_tile_task;
+
 
 }  // namespace ffp

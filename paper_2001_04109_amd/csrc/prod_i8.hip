@@ -761,9 +761,10 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
                         ProdArgs a2 = args;
                         a2.total_tiles = total - tail;
                         const int nfull_grid = (total - tail + 7) / 8 * 8;
-                        g_last_variant = 6;
+                        g_last_variant = 13;
                         hipLaunchKernelGGL(prod_i8_dma_split_kernel, dim3(nfull_grid + tail * ns), dim3(256), 0, s,
                                            a2, nfull_grid, ns, (int32_t*)sc.ptr);
+                        prof_mark_end(s);
                         hipLaunchKernelGGL(tail_reduce_kernel, dim3(tail * 16), dim3(256), 0, s, tasks[0],
                                            total - tail, ns, (const int32_t*)sc.ptr);
                         return hipGetLastError();

@@ -326,12 +326,31 @@ void prof_begin(hipStream_t s, hipEvent_t* e0)
     (void)hipEventRecord(*e0, s);
 }
 
+namespace {
+// end event recorded by a launcher between its main kernel and a follow-up
+// kernel of the same launch (prof_mark_end), taken by the next prof_end
+thread_local hipEvent_t g_prof_mid = nullptr;
+}  // namespace
+
+void prof_mark_end(hipStream_t s)
+{
+    if (!prof_enabled() || g_prof_mid != nullptr) return;
+    if (hipEventCreate(&g_prof_mid) != hipSuccess) { g_prof_mid = nullptr; return; }
+    (void)hipEventRecord(g_prof_mid, s);
+}
+
 void prof_end(hipStream_t s, hipEvent_t e0, double work, int cls)
 {
-    if (!e0) return;
-    hipEvent_t e1;
-    if (hipEventCreate(&e1) != hipSuccess) return;
-    (void)hipEventRecord(e1, s);
+    hipEvent_t e1 = g_prof_mid;
+    g_prof_mid = nullptr;
+    if (!e0) {
+        if (e1) (void)hipEventDestroy(e1);
+        return;
+    }
+    if (e1 == nullptr) {
+        if (hipEventCreate(&e1) != hipSuccess) return;
+        (void)hipEventRecord(e1, s);
+    }
     std::lock_guard<std::mutex> lk(g_prof_mutex);
     g_prof.push_back(ProfRec{e0, e1, work, cls, g_last_variant});
 }
