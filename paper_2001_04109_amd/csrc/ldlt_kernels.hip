@@ -601,7 +601,9 @@ union StepLds {
     int8_t i8[I8Tile<64, 64, 64, 3>::LDS];
 };
 
-__global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n)
+// D is read-only and never aliased by the steps' stores, so its fields
+// need not be read again after a store.
+__global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* __restrict__ D, int n)
 {
     __shared__ __attribute__((aligned(16))) StepLds lds;
     const LdltDesc& d = D[desc_of(D, n, blockIdx.x)];
@@ -626,17 +628,21 @@ __global__ __launch_bounds__(256) void ldlt_step_kernel(const LdltDesc* D, int n
     case LK_ABARX:
         build_abarx_body(d, lb % d.gx, lb / d.gx, abar_bands(d.amode == 1 ? d.rows_pad : d.rows), lds.abar);
         break;
-    case LK_PRODF:
+    case LK_PRODF: {
+        const ProdTask t = d.t;
         switch (d.pform) {
-        case TILE_NT_BLOW: f64_tile_task<TILE_NT_BLOW>(d.t, lb); break;
-        case TILE_NN_BLOW: f64_tile_task<TILE_NN_BLOW>(d.t, lb); break;
-        case TILE_NN_ALOW: f64_tile_task<TILE_NN_ALOW>(d.t, lb); break;
-        default: f64_tile_task<TILE_NT>(d.t, lb); break;
+        case TILE_NT_BLOW: f64_tile_task<TILE_NT_BLOW>(t, lb); break;
+        case TILE_NN_BLOW: f64_tile_task<TILE_NN_BLOW>(t, lb); break;
+        case TILE_NN_ALOW: f64_tile_task<TILE_NN_ALOW>(t, lb); break;
+        default: f64_tile_task<TILE_NT>(t, lb); break;
         }
         break;
-    case LK_PRODL3:
-        i8_tile_task<64, 64, 64, 3>(d.t, lb, lds.i8);
+    }
+    case LK_PRODL3: {
+        const ProdTask t = d.t;
+        i8_tile_task<64, 64, 64, 3>(t, lb, lds.i8);
         break;
+    }
     case LK_BDIAG:
         bdiag_body(d.f, d.nb, d.bd, d.bo, d.desc1, d.dbar, d.info, lds.bdiag);
         break;
