@@ -10,15 +10,17 @@ matrix-core base products.  One step = fsyrk_modp on both shapes.
 Inputs are drawn on the host with numpy's PCG64 (seed 1) and are resident in
 HBM before the timed region.  Besides the JSON line the run prints nothing
 on stdout.  Roofline figures come from HIP events around every product
-launch in the timed region; the CPU baseline is the oracle on a bounded row
-panel of the same product.  The "extra" object reports, in this order, the
-int8 and int8-limb products of 16384 x 16384 (with the vendor library's int8
-GEMM on the same shape as context) and the three-limb form of the default
-workload, the products over F_p[i] and with block-diagonal scaling, the
-served Poisson stream of A A^T and LDL^T requests (p50/p99
-latency from arrival to completion, overall and per kind, throughput) with
-the same requests at once and per call for comparison, and the 1024-job
-batched form against the same jobs as per-call fsyrk_modp.
+launch in the timed region; the CPU baseline is the oracle on the lower
+triangle of the same product (compared entry by entry with the GPU's), and
+that leg also runs every other comparison with the oracle that the legs
+below ask for.  The "extra" object reports, in this order, the int8 and
+int8-limb products of 16384 x 16384 (with the vendor library's int8 GEMM on
+the same shape as context) and the three-limb form of the default workload,
+the products over F_p[i] and with block-diagonal scaling, single LDL^T
+calls of orders 256 to 4096, the served Poisson stream of A A^T and LDL^T
+requests (p50/p99 latency from arrival to completion, overall and per kind,
+throughput) with the same requests at once and per call for comparison,
+and the 1024-job batched form against the same jobs as per-call fsyrk_modp.
 """
 from __future__ import annotations
 
@@ -49,6 +51,26 @@ WORKLOADS = {
     "syrk_8192_p131071_limb3": dict(shapes=[(8192, 8192), (8192, 32768)], p=131071, depth=0, seed=1,
                                     dtype="u32", cls=3, limb3=True),
 }
+
+
+# Comparisons with the oracle that the other legs ask for (sampled entries
+# of their results, the pin of the served LDL^T reference); the CPU-baseline
+# leg runs them, so that only that leg executes oracle code.
+ORACLE_CHECKS = []
+
+
+def oracle_check(desc, fn):
+    """Defers fn (which raises SystemExit on a mismatch) to the CPU-baseline leg."""
+    ORACLE_CHECKS.append((desc, fn))
+
+
+def rows_subset(A, lo, hi):
+    """The rows of A that entries (lo, hi) of A A^T need, with the indices
+    remapped into that subset."""
+    rows = np.unique(np.concatenate([lo, hi]))
+    pos = {int(r): i for i, r in enumerate(rows)}
+    return (np.ascontiguousarray(A[rows]), np.array([pos[int(x)] for x in lo]),
+            np.array([pos[int(x)] for x in hi]))
 
 
 def log(*a):
@@ -101,7 +123,6 @@ def profile_hooks():
 def run_workload(name, steps, warmup, check=True, keep_first=False):
     import torch
     from paper_2001_04109_amd import ffp, inputs
-    import oracle
 
     w = WORKLOADS[name]
     p = w["p"]
@@ -153,8 +174,13 @@ def run_workload(name, steps, warmup, check=True, keep_first=False):
             c = rng.integers(0, n, 64)
             lo, hi = np.maximum(r, c), np.minimum(r, c)
             got = Cd.cpu().numpy().view(np.uint32)[lo, hi]
-            if not np.array_equal(got, oracle.syrk_entries(A, p, lo, hi)):
-                raise SystemExit(f"bench: {name} result differs from the oracle")
+            As, ls, hs = rows_subset(A, lo, hi)
+
+            def chk(As=As, ls=ls, hs=hs, got=got):
+                import oracle
+                if not np.array_equal(got, oracle.syrk_entries(As, p, ls, hs)):
+                    raise SystemExit(f"bench: {name} result differs from the oracle")
+            oracle_check(f"{name}: 64 sampled entries", chk)
     if keep_first:
         res["first_c"] = outs[0].cpu().numpy().view(np.uint32)
     del devs, outs
@@ -171,7 +197,6 @@ def batched_vs_plain(steps=3, njobs=1024):
     graph replays write the batched outputs last, which are compared with the
     per-call results bit for bit, and a sample with the oracle."""
     import torch
-    import oracle
     from paper_2001_04109_amd import ffp, inputs
     shapes = inputs.batch_jobs(seed=3, njobs=njobs)
     mats, devA, devC, devC2, jobs = [], [], [], [], []
@@ -240,8 +265,13 @@ def batched_vs_plain(steps=3, njobs=1024):
         cc = rng.integers(0, n, 32)
         lo, hi = np.maximum(r, cc), np.minimum(r, cc)
         got = devC[j].cpu().numpy().view(np.uint32)[lo, hi]
-        if not np.array_equal(got, oracle.syrk_entries(A, p, lo, hi)):
-            raise SystemExit(f"bench: batched job {j} differs from the oracle")
+        As, ls, hs = rows_subset(A, lo, hi)
+
+        def chk(As=As, ls=ls, hs=hs, got=got, p=p, j=j):
+            import oracle
+            if not np.array_equal(got, oracle.syrk_entries(As, p, ls, hs)):
+                raise SystemExit(f"bench: batched job {j} differs from the oracle")
+        oracle_check(f"batched job {j}: 32 sampled entries", chk)
     out["speedup"] = round(out["plain"]["ms"] / out["batched"]["ms"], 3)
     out["graph_speedup"] = round(out["plain"]["ms"] / out["graph"]["ms"], 3)
     out["graph_record_ms"] = round(record_ms, 1)
@@ -305,18 +335,23 @@ class OperandPool:
         else:
             raise SystemExit("bench: no generic-rank symmetric pool matrix in 8 draws")
         self.S = Sd
+        self.ldlt_prime = ldlt_prime
         self.LD = W      # packed L (strict lower) and D (diagonal) of the whole S
         # the served LDL^T results are compared with leading blocks of LD;
         # its leading 1024 x 1024 block is checked against the oracle's
-        # Crout factorisation here (the LDL^T of a leading block is the
-        # leading block of the whole factorisation)
-        import oracle
+        # Crout factorisation (the LDL^T of a leading block is the leading
+        # block of the whole factorisation)
         m = min(1024, nmax)
-        ref, rinfo = oracle.ldlt_packed(S[:m, :m].copy(), ldlt_prime)
+        S_lead = S[:m, :m].copy()
         got = W[:m, :m].cpu().numpy().view(np.uint32)
-        low = np.tril(np.ones((m, m), dtype=bool))
-        if rinfo != 0 or not np.array_equal(got[low], ref[low]):
-            raise SystemExit("bench: the pool's LDL^T differs from the oracle")
+
+        def chk():
+            import oracle
+            ref, rinfo = oracle.ldlt_packed(S_lead, ldlt_prime)
+            low = np.tril(np.ones((m, m), dtype=bool))
+            if rinfo != 0 or not np.array_equal(got[low], ref[low]):
+                raise SystemExit("bench: the pool's LDL^T differs from the oracle")
+        oracle_check(f"served LDL^T reference: leading {m} x {m} block", chk)
 
     def operand(self, r):
         if r["kind"] == "syrk":
@@ -327,9 +362,10 @@ class OperandPool:
 class ServedCheck:
     """Checks every stride-th served result (after the stream, before it is
     released): LDL^T results against the leading block of the pool's GPU
-    factorisation (whose leading 1024 x 1024 block the pool checks against
-    the oracle), A A^T results on 32 sampled entries against the oracle.
-    Copies run on a side stream of their own."""
+    factorisation (whose leading 1024 x 1024 block is pinned to the
+    oracle), A A^T results on 32 sampled entries against the oracle (both
+    oracle comparisons run in the CPU-baseline leg).  Copies run on a side
+    stream of their own."""
 
     def __init__(self, pool, stride=200):
         import torch
@@ -364,14 +400,49 @@ class ServedCheck:
         self.side.synchronize()
 
     def finish(self):
-        import oracle
-        for r, lo, hi, vals in self.samples:
-            A = self.pool.A_host[r["p"]][: r["n"], : r["k"]]
-            if not np.array_equal(vals, oracle.syrk_entries(np.ascontiguousarray(A), r["p"], lo, hi)):
-                self.failures.append(r["id"])
         if self.failures:
-            raise SystemExit(f"bench: served results differ from the reference: {self.failures[:5]}")
+            raise SystemExit(f"bench: served LDL^T results differ from the reference: {self.failures[:5]}")
+        for r, lo, hi, vals in self.samples:
+            As, ls, hs = rows_subset(self.pool.A_host[r["p"]][: r["n"], : r["k"]], lo, hi)
+
+            def chk(As=As, ls=ls, hs=hs, vals=vals, r=r):
+                import oracle
+                if not np.array_equal(vals, oracle.syrk_entries(As, r["p"], ls, hs)):
+                    raise SystemExit(f"bench: served request {r['id']} differs from the oracle")
+            oracle_check(f"served request {r['id']}: 32 sampled entries", chk)
         return {"checked_syrk": len(self.samples), "checked_ldlt": self.ldlt_ok}
+
+
+def ldlt_alone(pool, ns=(256, 1024, 2048, 4096), reps=7):
+    """Single fldlt_modp calls on one stream (inputs resident): the leading
+    n x n blocks of the pool's symmetric matrix, median of reps timed calls;
+    every result is compared with the leading block of the pool's own
+    factorisation (which is pinned to the oracle)."""
+    import torch
+    from paper_2001_04109_amd import ffp
+    out = {}
+    for n in ns:
+        src = pool.S[:n, :n].contiguous()
+        W = torch.empty_like(src)
+        info = torch.zeros(1, dtype=torch.int64, device="cuda")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ts = []
+        for r in range(reps + 1):
+            W.copy_(src)
+            torch.cuda.synchronize()
+            e0.record()
+            ffp.fldlt_modp(n, pool.ldlt_prime, W, W.stride(0), info)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        low = torch.ones((n, n), dtype=torch.bool, device="cuda").tril()
+        if int(info.item()) != 0 or not torch.equal(W[low], pool.LD[:n, :n][low]):
+            raise SystemExit(f"bench: LDL^T of order {n} differs from the reference")
+        out[str(n)] = {"ms": round(float(np.median(ts)), 3),
+                       "top_s_n3_over_3": round(n ** 3 / 3.0 / (np.median(ts) * 1e-3) / 1e12, 3)}
+    return out
 
 
 def eff_ops(r):
@@ -619,6 +690,12 @@ def cpu_baseline(name, gpu_c=None):
         per[key] = {"value": round(ratec, 3), "unit": "Gop/s",
                     "sample": f"rows [{cn - cr},{cn}) of {cn}x{ck} ({macsc:.3e} multiply-adds, {dtc:.2f} s)"}
     out["per_config"] = per
+    # the comparisons with the oracle that the other legs deferred
+    for desc, fn in ORACLE_CHECKS:
+        fn()
+    out["oracle_checks"] = {"passed": len(ORACLE_CHECKS),
+                            "of": sorted({d.split(":")[0].split(" ")[0] for d, _ in ORACLE_CHECKS})}
+    ORACLE_CHECKS.clear()
     return out
 
 
@@ -645,6 +722,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--underload-rate", type=float, default=300.0,
                     help="offered rate of the latency run below the GPU's capacity")
+    ap.add_argument("--ldlt-latency", action="store_true",
+                    help="only time single LDL^T calls (orders 256 to 4096, p = 65537) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 256 MiB device-to-device copies (the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -664,8 +743,12 @@ def main():
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a ROCm GPU")
-    from paper_2001_04109_amd import ffp
+    from paper_2001_04109_amd import ffp, inputs
     ffp.lib()
+    if args.ldlt_latency:
+        pool = OperandPool(inputs.BATCH_PRIMES, 65537)
+        log(f"bench: LDL^T single calls {ldlt_alone(pool)}")
+        return
 
     name = args.workload
     w = WORKLOADS[name]
@@ -714,8 +797,11 @@ def main():
         log("bench: autotuning the served A A^T shape classes")
         tuned = tune_served_classes()
         log(f"bench: autotune {tuned}")
+        pool = OperandPool(inputs.BATCH_PRIMES, 65537)
+        alone = ldlt_alone(pool)
+        log(f"bench: LDL^T single calls {alone}")
         log(f"bench: served stream, {args.serve_requests} requests at {args.serve_rate}/s")
-        sv, reqs, pool = served(args.serve_requests, rate=args.serve_rate)
+        sv, reqs, pool = served(args.serve_requests, rate=args.serve_rate, pool=pool)
         log(f"bench: served {sv}")
         ncmp = min(args.serve_requests, 4000)
         log(f"bench: first {ncmp} requests at once")
@@ -730,7 +816,7 @@ def main():
         log(f"bench: underload {low}")
         extra["served_stream"] = {"arrivals": sv, "saturated": sat, "per_call_plain": pc,
                                   "saturated_vs_per_call": round(sat["gops_total"] / pc["gops_total"], 3),
-                                  "underload": low, "autotune": tuned}
+                                  "underload": low, "autotune": tuned, "ldlt_single_calls": alone}
         ffp.ffp_tune_clear()
         del pool
     if not args.no_extra and not args.no_batched:
@@ -742,6 +828,8 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         cpu = cpu_baseline(name, first_c)
+    elif ORACLE_CHECKS:
+        log(f"bench: {len(ORACLE_CHECKS)} comparisons with the oracle skipped (no CPU-baseline leg)")
     del first_c
     n0, _ = w["shapes"][0]
     out = {
