@@ -91,6 +91,69 @@ __device__ __forceinline__ bool leaf_eliminate(double (&m)[4][4], int nb, int r0
     return true;
 }
 
+// The centred residue of an integer-valued double |v| < 2^53: in
+// [-(p + 1)/2, (p + 1)/2] (the rounded quotient is off by at most one only
+// next to a half-integer, where either choice stays in that range).
+__device__ __forceinline__ double cred(double v, double pd, double pinv)
+{
+    return fma(-rint(v * pinv), pd, v);
+}
+
+// The same elimination for p < 2^18 with entries centred and every second
+// step unreduced: after an unreduced step |M| <= (p + 1)^2 / 2, and the next
+// step's a M - c c' (pivot and published column always reduced) stays below
+// (p + 1)^3 / 4 + (p + 1)^2 / 4 < 2^53.  Entries start centred; the owners of
+// the next column reduce it before publishing; every entry is reduced at
+// the end.
+__device__ __forceinline__ bool leaf_eliminate_lazy(double (&m)[4][4], int nb, int r0, int c0, double pd,
+                                                    double pinv, double (&colk)[2][NB], int64_t* info,
+                                                    int64_t offset)
+{
+    for (int k0 = 0; k0 < nb; k0 += 4) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = k0 + kk;
+            if (k >= nb) break;
+            const double* col = colk[k & 1];
+            const double a = col[k];
+            if (a == 0.0) {
+                if (threadIdx.x == 0 && *info == 0) *info = offset + k + 1;
+                return false;
+            }
+            double ci[4], cj[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                ci[x] = col[r0 + x];
+                cj[x] = col[c0 + x];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    double v = fma(a, m[x][y], -(ci[x] * cj[y]));
+                    if (kk & 1) v = cred(v, pd, pinv);
+                    m[x][y] = (r0 + x > k && c0 + y > k) ? v : m[x][y];
+                }
+            if (kk < 3) {
+                if (c0 == k0)
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
+                        colk[(k + 1) & 1][r0 + x] = (kk & 1) ? m[x][kk + 1] : cred(m[x][kk + 1], pd, pinv);
+            } else {
+                if (c0 == k0 + 4)
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) colk[(k + 1) & 1][r0 + x] = m[x][0];
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) m[x][y] = cred(m[x][y], pd, pinv);
+    return true;
+}
+
 // One doubling step of the inverse of the unit lower factor: for each pair
 // of consecutive diagonal blocks of size B, [[A, 0], [X, C]]^-1 =
 // [[A^-1, 0], [-C^-1 X A^-1, C^-1]] from the inverses of A and C (in li,
@@ -184,13 +247,15 @@ __device__ __forceinline__ void ldlt_leaf_body(const LdltDesc& d, LeafLds& L)
             uint32_t v = 0u;
             if (i < nb && j < nb) v = j <= i ? S[(int64_t)i * lds + j] : S[(int64_t)j * lds + i];
             m[a][b] = (double)v;
+            if (p < (1u << 18) && v > f.half) m[a][b] -= pd;   // centred for the lazy elimination
         }
     if (c0 == 0)
 #pragma unroll
         for (int a = 0; a < 4; ++a) L.colk[0][r0 + a] = m[a][0];
     __syncthreads();
-    const bool ok = p >= (1u << 25) ? leaf_eliminate<true>(m, nb, r0, c0, pd, pinv, L.colk, d.info, d.offset)
-                                    : leaf_eliminate<false>(m, nb, r0, c0, pd, pinv, L.colk, d.info, d.offset);
+    const bool ok = p < (1u << 18)  ? leaf_eliminate_lazy(m, nb, r0, c0, pd, pinv, L.colk, d.info, d.offset)
+                    : p >= (1u << 25) ? leaf_eliminate<true>(m, nb, r0, c0, pd, pinv, L.colk, d.info, d.offset)
+                                      : leaf_eliminate<false>(m, nb, r0, c0, pd, pinv, L.colk, d.info, d.offset);
     if (!ok) return;   // contents unspecified after a zero pivot
 #pragma unroll
     for (int a = 0; a < 4; ++a)

@@ -246,3 +246,51 @@ def test_recursion_with_assembled_inverses_matches_crout(p, n, leaf):
     assert np.array_equal(np.array(got, dtype=np.uint64)[low], ref.astype(np.uint64)[low])
     Lunit = np.tril(np.array(got, dtype=object), -1) + np.eye(n, dtype=object)
     assert np.array_equal(Lunit.dot(Linv) % p, np.eye(n, dtype=object))
+
+
+@pytest.mark.parametrize("p", [3, 251, 65537, 131071, 262139])
+def test_lazy_leaf_elimination_stays_exact(p):
+    """The leaf's elimination for p < 2^18 in doubles: entries centred, every
+    second step left unreduced, pivot and published column always reduced,
+    quotients rounded to nearest.  Every intermediate value stays an integer
+    below 2^53 (so each product and sum is exact), and the result matches the
+    integer recurrence."""
+    n = 64
+    rng = np.random.default_rng(p)
+    S = rng.integers(0, p, size=(n, n))
+    S = np.tril(S) + np.tril(S, -1).T
+    half = (p - 1) // 2
+    M = np.where(S > half, S - p, S).astype(np.float64)
+    pd = float(p)
+    pinv = 1.0 / pd
+
+    def cred(v):
+        return v - np.rint(v * pinv) * pd
+
+    biggest = 0.0
+    ref = [[int(S[i][j]) for j in range(n)] for i in range(n)]
+    for k in range(n):
+        col = M[:, k].copy()
+        # the published column is reduced whenever the previous step was lazy
+        if k > 0 and (k - 1) % 4 in (0, 2):
+            col = cred(col)
+        a = col[k]
+        assert a == np.rint(a) and abs(a) <= (p + 1) / 2
+        if a == 0.0:
+            break
+        upd = a * M - np.outer(col, col)
+        biggest = max(biggest, float(np.max(np.abs(upd[k + 1:, k + 1:]))) if k + 1 < n else 0.0)
+        if k % 4 in (1, 3):
+            upd = cred(upd)
+        mask = np.zeros((n, n), dtype=bool)
+        mask[k + 1:, k + 1:] = True
+        M = np.where(mask, upd, M)
+        ak = ref[k][k]
+        for i in range(k + 1, n):
+            for j in range(k + 1, n):
+                ref[i][j] = (ak * ref[i][j] - ref[i][k] * ref[j][k]) % p
+    assert biggest < 2.0 ** 53
+    got = np.mod(cred(M), pd).astype(np.int64)
+    want = np.array(ref, dtype=np.int64)
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(got[low], want[low])
