@@ -12,7 +12,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libffp.so")
+# FFP_LIBRARY: another build of the library to load instead (the host
+# AddressSanitizer build of paper_2001_04109_amd.build, for host tests)
+LIB_PATH = os.environ.get("FFP_LIBRARY") or os.path.join(HERE, "libffp.so")
 
 FFP_OK = 0
 FFP_EINVAL = -1
