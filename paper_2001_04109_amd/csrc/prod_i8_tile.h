@@ -325,6 +325,7 @@ __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* s
         cw[0] = 1.0;
 #pragma unroll
         for (int q = 1; q < 5; ++q) cw[q] = mod_f64(cw[q - 1] * 256.0, pd, t.pinv);
+        const bool small = t.p < (1u << 19);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -335,9 +336,16 @@ __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* s
                     const int row = tile_r + wr * WTM + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
                     if (row >= t.m || col >= t.n) continue;
                     if (t.syrk && col > row) continue;
-                    double v = 0.0;                      // five terms below p^2 < 2^46: exact
+                    double v = 0.0;
+                    if (small) {
+                        // |acc| < 2^31 and weights below p < 2^19: five terms below 2^52, exact
 #pragma unroll
-                    for (int q = 0; q < 5; ++q) v += mod_f64((double)acc[q][i][j][e], pd, t.pinv) * cw[q];
+                        for (int q = 0; q < 5; ++q) v = fma((double)acc[q][i][j][e], cw[q], v);
+                    } else {
+                        // five reduced terms below p^2 < 2^46: exact
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) v += mod_f64((double)acc[q][i][j][e], pd, t.pinv) * cw[q];
+                    }
                     v = mod_f64(v, pd, t.pinv);
                     uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
                     double x = alpha * v;
