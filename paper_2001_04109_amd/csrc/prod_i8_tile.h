@@ -366,10 +366,11 @@ __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* s
                     const int row = tile_r + wr * WTM + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
                     if (row >= t.m || col >= t.n) continue;
                     if (t.syrk && col > row) continue;
-                    const double hh = mod_f64((double)acc[0][i][j][e], pd, t.pinv);
-                    const double ll = mod_f64((double)acc[NACC - 2][i][j][e], pd, t.pinv);
-                    const double xx = mod_f64((double)acc[NACC - 1][i][j][e], pd, t.pinv);
-                    const double v = mod_f64(hh * r16 + xx * r8 + ll, pd, t.pinv);
+                    // |acc| < 2^31, r16 < p <= 65521, r8 <= 256: the sum is below 2^49, exact
+                    const double v = mod_f64(fma((double)acc[0][i][j][e], r16,
+                                                 fma((double)acc[NACC - 1][i][j][e], r8,
+                                                     (double)acc[NACC - 2][i][j][e])),
+                                             pd, t.pinv);
                     uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
                     double x = alpha * v;
                     if (t.beta != 0u) x += beta * (double)(*dst);
