@@ -80,7 +80,10 @@ void ffp_debug_set_kblk(int64_t kblk);
  * "i8_split_tail" (1, the default: an fsyrk_modp int8 product launch whose
  * last round of 256 x 256 tiles would leave most workgroups idle runs that
  * round's tiles as k-chunks and adds them in a second small kernel; 0: no
- * split), "i8_pipe" (1, the default: with "i8_dma" 0,
+ * split), "l3_dma" (1, the default: three-limb products of at least four
+ * rounds of 128 x 64 tiles with k >= 1024 a multiple of 128 run those tiles
+ * with operands straight to LDS; 2: whenever k is a multiple of 128; 0:
+ * always the 64 x 64 tile), "i8_pipe" (1, the default: with "i8_dma" 0,
  * the 256 x 256 int8 tile with 128-byte k stages writes each stage's
  * operands to LDS between the MFMAs of the previous stage and loads them up
  * to two stages ahead; 0: the stage's LDS writes after its MFMAs), "f64_pipe" (1, the default: the
@@ -126,7 +129,8 @@ int ffp_debug_profile_read(int cls, double* ms, double* flops, int64_t* launches
  * 10 int8 256x256 with the LDS writes between the MFMAs, 11 FP64 128x128
  * with doubles in LDS, 12 int8 limbs 128x128 register-staged, 13 int8
  * 256x256 straight to LDS with the last round of tiles split along k; its
- * time excludes the small kernel that adds the split tiles' chunks);
+ * time excludes the small kernel that adds the split tiles' chunks, 14 int8
+ * three limbs 128x64 straight to LDS);
  * ffp_debug_variant_name gives the kernel's demangled name. */
 int ffp_debug_profile_read_variant(int variant, double* ms, double* flops, int64_t* launches);
 const char* ffp_debug_variant_name(int variant);

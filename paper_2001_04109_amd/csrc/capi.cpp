@@ -282,6 +282,7 @@ int ffp_debug_set(const char* key, int64_t value)
     }
     if (strcmp(key, "i8_dma") == 0) { ffp::g_i8_dma = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "i8_split_tail") == 0) { ffp::g_split_tail = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "l3_dma") == 0) { ffp::g_l3_dma = value < 0 ? 0 : (value > 2 ? 2 : (int)value); return FFP_OK; }
     if (strcmp(key, "i8_pipe") == 0) { ffp::g_i8_pipe = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "pack_vec") == 0) { ffp::g_pack_vec = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "f64_pipe") == 0) { ffp::g_f64_pipe = value ? 1 : 0; return FFP_OK; }
@@ -323,6 +324,7 @@ const char* ffp_debug_variant_name(int variant)
     case 11: return "ffp::prod_f64_pipe_kernel(ffp::ProdArgs, int)";
     case 12: return "void ffp::prod_i8_pipe_kernel<128, 128, 128, 2>(ffp::ProdArgs, int)";
     case 13: return "ffp::prod_i8_dma_split_kernel(ffp::ProdArgs, int, int, int*)";
+    case 14: return "ffp::(anonymous namespace)::prod_l3_dma_kernel(ffp::ProdArgs, int)";
     default: return "";
     }
 }

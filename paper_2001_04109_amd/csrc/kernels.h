@@ -109,6 +109,8 @@ struct TailScratch {
     size_t bytes;
 };
 extern thread_local TailScratch g_tail_scratch;
+extern int g_l3_dma;           // CLS_LIMB3 128 x 64 tiles straight to LDS: 1 (default) for large
+                               // products, 2 whenever k is a multiple of 128, 0 never
 struct TailScratchScope {
     TailScratch saved;
     TailScratchScope(void* p, size_t b) : saved(g_tail_scratch) { g_tail_scratch = TailScratch{p, b}; }
@@ -128,7 +130,7 @@ extern int g_persistent;
 // 128x128 LDS (8 waves), 9 int8
 // three limbs, 10 int8 256x256 register-staged, 11 FP64 doubles in LDS, 12 limbs
 // register-staged, 13 int8 256x256 straight to LDS with the last round's tiles
-// split along k.
+// split along k, 14 three limbs 128x64 straight to LDS.
 extern thread_local int g_last_variant;
 // Called by a launcher after the kernel whose time the current timing bracket
 // measures when a small follow-up kernel of the same launch comes next: the

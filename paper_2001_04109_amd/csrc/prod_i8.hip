@@ -716,6 +716,228 @@ __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int mode)
 
 namespace {
 
+// ---- CLS_LIMB3 with operands straight to LDS -------------------------------
+// Three int8 limbs on 128 x 64 tiles: 4 waves of 64 x 32 with five weight
+// accumulators (160 registers); per k-step a wave issues 18 MFMAs (nine limb
+// products on two row blocks) and reads 9 fragments.  A stage (128 bytes of
+// k) is 72 blocks of 1 KB, the A panel's three planes (16 blocks each) then
+// the B panel's (8 blocks each); each wave loads 18 of them, in two halves
+// placed like the int8 tile's.
+
+// Epilogue of a three-limb wave tile: sum over q of 2^(8q) acc_q mod p,
+// then alpha and beta.
+template <int FM, int FN>
+__device__ __forceinline__ void store_tile_limb3(const v16i (&acc)[5][FM][FN], const ProdTask& t, int row0,
+                                                 int col0, bool live)
+{
+    if (!live) return;
+    const int lane = threadIdx.x & 63, lrow = lane & 31, lk = lane >> 5;
+    const double pd = (double)t.p;
+    const double alpha = (double)t.alpha, beta = (double)t.beta;
+    double cw[5];
+    cw[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q < 5; ++q) cw[q] = mod_f64(cw[q - 1] * 256.0, pd, t.pinv);
+    const bool small = t.p < (1u << 19);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = col0 + j * 32 + lrow;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = row0 + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
+                if (row >= t.m || col >= t.n) continue;
+                if (t.syrk && col > row) continue;
+                double v = 0.0;
+                if (small) {
+                    // |acc| < 2^31 and weights below p < 2^19: five terms below 2^52, exact
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) v = fma((double)acc[q][i][j][e], cw[q], v);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) v += mod_f64((double)acc[q][i][j][e], pd, t.pinv) * cw[q];
+                }
+                v = mod_f64(v, pd, t.pinv);
+                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                double x = alpha * v;
+                if (t.beta != 0u) x += beta * (double)(*dst);
+                *dst = (uint32_t)mod_f64(x, pd, t.pinv);
+            }
+        }
+}
+
+template <bool EDGE>
+__device__ __forceinline__ void l3_dma_body(const ProdTask& t, int ti, int tj, int8_t* smem)
+{
+    constexpr int BM = 128, BN = 64, BK = 128, WTM = 64, WTN = 32, FM = 2, FN = 1;
+    constexpr int RA = BM * BK, RB = BN * BK;        // bytes of one plane of a panel per stage
+    constexpr int BUF = 3 * (RA + RB);               // 72 blocks of 1 KB
+    constexpr int PER = BUF / 1024 / 4;              // blocks per wave and stage
+    static_assert(PER == 18, "18 blocks per wave");
+    const int tile_r = ti * BM, tile_c = tj * BN;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lrow = lane & 31, lk = lane >> 5;
+
+    v16i acc[5][FM][FN];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[q][i][j][e] = 0;
+    const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
+
+    const int nk = t.k / BK;
+    if (nk > 0) {
+        const int va = t.m - tile_r < BM ? t.m - tile_r : BM;    // valid rows of the panels
+        const int vb = t.n - tile_c < BN ? t.n - tile_c : BN;
+        const int lda = __builtin_amdgcn_readfirstlane((int)t.A.ld);
+        const int ldb = __builtin_amdgcn_readfirstlane((int)t.B.ld);
+        const int lr8 = lane >> 3, slot = lane & 7;
+        // load q of this wave: block gb = 18 wave + q of the stage; gb < 48:
+        // A plane gb / 16, block gb % 16; else B plane (gb - 48) / 8, block
+        // (gb - 48) % 8.  Row 8 blk + lr8 of the panel, 16-byte chunk
+        // slot ^ lr8 ^ (blk & 1) of its 128 bytes (the swizzle the fragment
+        // reads undo).
+        auto dload = [&](int q, int stg, bool live) {
+            const int gb = PER * wave + q;
+            const bool isB = gb >= 48;
+            const int pl = isB ? (gb - 48) >> 3 : gb >> 4;
+            const int blk = isB ? (gb - 48) & 7 : gb & 15;
+            const int ld = isB ? ldb : lda;
+            const __amdgpu_buffer_rsrc_t rs =
+                isB ? panel_rsrc((const int8_t*)t.B.p + pl * t.B.plane + (int64_t)tile_c * t.B.ld,
+                                 (int64_t)vb * t.B.ld)
+                    : panel_rsrc((const int8_t*)t.A.p + pl * t.A.plane + (int64_t)tile_r * t.A.ld,
+                                 (int64_t)va * t.A.ld);
+            const uint32_t dead = live ? 0u : 0x80000000u;
+            int8_t* dst = smem + (stg & 1) * BUF + gb * 1024;
+            const int v = lr8 * ld + 16 * (slot ^ lr8 ^ (blk & 1));
+            if constexpr (EDGE) {
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsVoid*)dst, 16, (uint32_t)(v + 8 * blk * ld) + dead,
+                                                         __builtin_amdgcn_readfirstlane(stg * BK), 0, 0);
+            } else {
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (LdsVoid*)dst, 16, (uint32_t)v + dead,
+                    __builtin_amdgcn_readfirstlane(stg * BK + 8 * blk * ld), 0, 0);
+            }
+        };
+        const int sw = dma_swz(lrow);
+        int coff[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) coff[ks] = 16 * ((2 * ks + lk) ^ sw);
+        const int rowA = (wr * WTM + lrow) * BK, rowB = 3 * RA + (wc * WTN + lrow) * BK;
+        v4i fa[3][FM], fb[3][FN], na[3][FM], nb[3][FN];
+        // fragment o of a k-step, in the order the MFMAs first use them:
+        // a0[0] b0 a0[1] b1 b2 a1[0] a1[1] a2[0] a2[1]
+        auto rd = [&](v4i (&xa)[3][FM], v4i (&xb)[3][FN], int buf, int ks, int o) {
+            const int8_t* base = smem + buf * BUF + coff[ks];
+            const int isA[9] = {1, 0, 1, 0, 0, 1, 1, 1, 1};
+            const int pli[9] = {0, 0, 0, 1, 2, 1, 1, 2, 2};
+            const int idx[9] = {0, 0, 1, 0, 0, 0, 1, 0, 1};
+            if (isA[o])
+                xa[pli[o]][idx[o]] = *reinterpret_cast<const v4i*>(base + pli[o] * RA + rowA + idx[o] * 32 * BK);
+            else
+                xb[pli[o]][idx[o]] = *reinterpret_cast<const v4i*>(base + pli[o] * RB + rowB);
+        };
+        // the previous tile of a persistent workgroup may still read LDS
+        __syncthreads();
+        for (int q = 0; q < PER; ++q) dload(q, 0, true);
+        for (int q = 0; q < PER; ++q) dload(q, 1, nk > 1);
+        asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
+        __syncthreads();
+        for (int o = 0; o < 9; ++o) rd(fa, fb, 0, 0, o);
+        // one k-step: 18 MFMAs on (xa, xb) (limb products u x v into the
+        // accumulator of weight u + v), the NOPS other operations spread
+        // between them in order
+        auto kstep = [&](const v4i (&xa)[3][FM], const v4i (&xb)[3][FN], auto nops, auto&& op) {
+            constexpr int NOPS = decltype(nops)::value;
+            static_for<0, 18>([&](auto q) {
+                constexpr int Q = decltype(q)::value;
+                constexpr int U = Q / 6, V = (Q % 6) / 2, I = Q % 2;
+                acc[U + V][I][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[U][I], xb[V][0], acc[U + V][I][0], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                static_for<Q * NOPS / 18, (Q + 1) * NOPS / 18>([&](auto o) {
+                    op(o);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            });
+        };
+        auto stage = [&](auto par, int kt) {
+            constexpr int cur = decltype(par)::value;
+            // k0: fragments of k-step 1; second half of stage kt + 1's loads
+            kstep(fa, fb, IC<18>{}, [&](auto o) {
+                constexpr int O = decltype(o)::value;
+                if constexpr (O % 2 == 0) rd(na, nb, cur, 1, O / 2);
+                else dload(9 + O / 2, kt + 1, kt + 1 < nk);
+            });
+            kstep(na, nb, IC<9>{}, [&](auto o) { rd(fa, fb, cur, 2, decltype(o)::value); });
+            kstep(fa, fb, IC<9>{}, [&](auto o) { rd(na, nb, cur, 3, decltype(o)::value); });
+            // stage kt + 1 in LDS: this wave's loads, then every wave's
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            // k3: first fragments of stage kt + 1; first half of stage kt + 2's loads
+            kstep(na, nb, IC<18>{}, [&](auto o) {
+                constexpr int O = decltype(o)::value;
+                if constexpr (O % 2 == 0) rd(fa, fb, cur ^ 1, 0, O / 2);
+                else dload(O / 2, kt + 2, kt + 2 < nk);
+            });
+        };
+        // stages in pairs (static buffer indices); for odd nk the last stage of
+        // the last pair reads loads past the end of k, i.e. zeros
+        for (int kt = 0; kt < nk; kt += 2) {
+            stage(IC<0>{}, kt);
+            stage(IC<1>{}, kt + 1);
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    store_tile_limb3<FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+}
+
+// Lower-triangle tiles of a SYRK task on 128 x 64 tiles: row block ti holds
+// column blocks 0 .. 2 ti + 1 (those of the last may stop at tn - 1), so
+// tile r is in row ti with ti (ti + 1) <= r < (ti + 1) (ti + 2).
+__host__ __device__ inline int l3_syrk_tiles(int tm, int tn)
+{
+    int total = 0;
+    for (int i = 0; i < tm; ++i) total += 2 * i + 2 < tn ? 2 * i + 2 : tn;
+    return total;
+}
+
+__device__ __forceinline__ void l3_dma_tile(const ProdArgs& args, int b, int8_t* smem)
+{
+    ProdTask t;
+    select_task(args, b, &t);
+    const int r = b - t.tile0;
+    int ti, tj;
+    if (t.syrk) {
+        ti = (int)((sqrtf(4.0f * (float)r + 1.0f) - 1.0f) * 0.5f);
+        while ((ti + 1) * (ti + 2) <= r) ++ti;
+        while (ti * (ti + 1) > r) --ti;
+        tj = r - ti * (ti + 1);
+    } else {
+        ti = r / t.tn;
+        tj = r - ti * t.tn;
+    }
+    if ((ti + 1) * 128 <= t.m && (tj + 1) * 64 <= t.n) l3_dma_body<false>(t, ti, tj, smem);
+    else l3_dma_body<true>(t, ti, tj, smem);
+}
+
+__global__ __launch_bounds__(256) void prod_l3_dma_kernel(ProdArgs args, int mode)
+{
+    __shared__ __attribute__((aligned(1024))) int8_t smem[2 * 72 * 1024];
+    if (mode == 2) {
+        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x) l3_dma_tile(args, b, smem);
+        return;
+    }
+    const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if (b < args.total_tiles) l3_dma_tile(args, b, smem);
+}
+
 template <int BM, int BN, int BK, int PLANES, int RING>
 hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
@@ -726,7 +948,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         t.tm = (t.m + BM - 1) / BM;
         t.tn = (t.n + BN - 1) / BN;
         t.tile0 = total;
-        total += t.syrk ? t.tm * (t.tm + 1) / 2 : t.tm * t.tn;
+        total += t.syrk ? (BM == BN ? t.tm * (t.tm + 1) / 2 : l3_syrk_tiles(t.tm, t.tn)) : t.tm * t.tn;
     }
     if (total == 0) return hipSuccess;
     args.ntasks = ntasks;
@@ -741,7 +963,15 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
     }
     const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
     int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
-    if constexpr (RING > 0) {
+    if constexpr (RING > 0 && PLANES == 3) {
+        static_assert(BK == 128 && BM == 128 && BN == 64, "direct-to-LDS three limbs: 128 x 64 tiles");
+        if (mode == 2) {
+            const int resident = resident_blocks((const void*)prod_l3_dma_kernel);
+            grid = total < resident ? total : resident;
+        }
+        g_last_variant = 14;
+        hipLaunchKernelGGL(prod_l3_dma_kernel, dim3(grid), dim3(256), 0, s, args, mode);
+    } else if constexpr (RING > 0) {
         static_assert(BK == 128 && ((PLANES == 1 && BM == 256) || (PLANES == 2 && BM == 128)) && BN == BM,
                       "direct-to-LDS variant: int8 256-tiles or two limbs on 128-tiles");
         if constexpr (PLANES == 1) {
@@ -878,6 +1108,7 @@ int g_i8_tile_override = 0;
 int g_i8_bk_override = 0;
 int g_i8_dma = 1;
 int g_split_tail = 1;
+int g_l3_dma = 1;
 thread_local TailScratch g_tail_scratch = {nullptr, 0};
 int g_i8_pipe = 1;
 
@@ -917,6 +1148,21 @@ hipError_t launch_products_limb2(ProdTask* tasks, int ntasks, ProdTask* dev_task
 hipError_t launch_products_limb3(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf,
                                  hipStream_t s)
 {
+    // 128 x 64 tiles with operands straight to LDS for large products (at
+    // least four rounds of 128 x 64 tiles, k of at least 1024, a multiple of
+    // 128; panels addressable with 32-bit offsets).  Their workgroup holds
+    // 144 KB of LDS, one per CU, so on small products (batches of small
+    // jobs) the 64 x 64 tiles, two workgroups per CU, hide the start of
+    // each tile better.
+    bool dma = g_i8_dma != 0 && g_l3_dma != 0;
+    int64_t tiles = 0;
+    for (int i = 0; i < ntasks && dma; ++i) {
+        const ProdTask& t = tasks[i];
+        dma = (t.k % 128) == 0 && t.k >= 1024 && t.A.ld < (1 << 23) && t.B.ld < (1 << 23);
+        const int tm = (t.m + 127) / 128, tn = (t.n + 63) / 64;
+        tiles += t.syrk ? l3_syrk_tiles(tm, tn) : (int64_t)tm * tn;
+    }
+    if (dma && (tiles >= 1024 || g_l3_dma > 1)) return launch_i8_impl<128, 64, 128, 3, 1>(tasks, ntasks, dev_task_buf, s);
     return launch_i8_impl<64, 64, 64, 3>(tasks, ntasks, dev_task_buf, s);
 }
 

@@ -407,6 +407,49 @@ def test_limb3_recursive(p, depth, n, k):
         set_knob("wide", 1)
 
 
+@pytest.mark.parametrize("p", [131071, 8388593])
+@pytest.mark.parametrize("n,k,depth", [(300, 256, 0), (513, 128, 0), (130, 384, 0), (1000, 1024, 0),
+                                       (700, 2048, 1), (1030, 1280, 2)])
+def test_limb3_dma_variant(p, n, k, depth):
+    """Three int8 limbs on 128 x 64 tiles with operands straight to LDS
+    (forced for every k that is a multiple of 128): partial tiles, one and
+    odd stage counts, general products of the recursion, alpha/beta, the
+    upper fill, k in chunks of whole stages; against the oracle."""
+    A = inputs.uniform((48, n, k, p), n, k, p)
+    A[:2] = (p - 1) // 2 + 1              # most negative centred value
+    A[2:4] = (p - 1) // 2                 # most positive
+    C0 = inputs.uniform(49, n, n, p)
+    set_knob("l3_dma", 2)
+    try:
+        check_lower(gpu_syrk(A, p, depth=depth, limb3=True), oracle.syrk(A, p))
+        out = gpu_syrk(A, p, depth=depth, alpha=p - 1, beta=1, C0=C0, limb3=True, fill_upper=True)
+        check_lower(out, oracle.syrk_ab(A, p, p - 1, 1, C0))
+        assert np.array_equal(out, np.tril(out) + np.tril(out, -1).T)
+        set_kblk(128)
+        try:
+            check_lower(gpu_syrk(A, p, depth=depth, alpha=3, beta=5, C0=C0, limb3=True),
+                        oracle.syrk_ab(A, p, 3, 5, C0))
+        finally:
+            set_kblk(0)
+    finally:
+        set_knob("l3_dma", 1)
+
+
+def test_limb3_dma_long_k():
+    """Largest centred magnitudes over more columns than one exact int32
+    block, so the product runs as three k-chunks, each a whole number of
+    128-byte stages, on the direct-to-LDS three-limb tile."""
+    p = 8388593
+    n, k = 130, 2 * 43648
+    A = np.full((n, k), (p - 1) // 2 + 1, dtype=np.uint32)
+    A[::3] = (p - 1) // 2
+    set_knob("l3_dma", 2)
+    try:
+        check_lower(gpu_syrk(A, p, limb3=True), oracle.syrk(A, p))
+    finally:
+        set_knob("l3_dma", 1)
+
+
 @pytest.mark.parametrize("vec", [1, 0])
 @pytest.mark.parametrize("p,a_dtype", [(251, ffp.FFP_U32), (251, ffp.FFP_I8_CENTERED), (65521, ffp.FFP_U32),
                                        (65521, ffp.FFP_I8_LIMB2), (3, ffp.FFP_U32), (257, ffp.FFP_U32)])
