@@ -532,7 +532,7 @@ __device__ __forceinline__ void i8_dma_body(const ProdTask& t, int ti, int tj, i
             kstep(na, nb, IC<16>{}, [&](auto o) {
                 constexpr int O = decltype(o)::value;
                 if constexpr (O % 2 == 0) rd(fa, fb, cur ^ 1, 0, O / 2);
-                else dload(O / 2, kt + 2, kt + 2 < nk);
+                else dload(IC<O / 2>{}, kt + 2, kt + 2 < nk);
             });
         };
         // stages in pairs (static buffer indices); for odd nk the last stage of
@@ -798,32 +798,40 @@ __device__ __forceinline__ void l3_dma_body(const ProdTask& t, int ti, int tj, i
         const int lda = __builtin_amdgcn_readfirstlane((int)t.A.ld);
         const int ldb = __builtin_amdgcn_readfirstlane((int)t.B.ld);
         const int lr8 = lane >> 3, slot = lane & 7;
-        // load q of this wave: block gb = 18 wave + q of the stage; gb < 48:
-        // A plane gb / 16, block gb % 16; else B plane (gb - 48) / 8, block
-        // (gb - 48) % 8.  Row 8 blk + lr8 of the panel, 16-byte chunk
-        // slot ^ lr8 ^ (blk & 1) of its 128 bytes (the swizzle the fragment
-        // reads undo).
-        auto dload = [&](int q, int stg, bool live) {
-            const int gb = PER * wave + q;
-            const bool isB = gb >= 48;
-            const int pl = isB ? (gb - 48) >> 3 : gb >> 4;
-            const int blk = isB ? (gb - 48) & 7 : gb & 15;
-            const int ld = isB ? ldb : lda;
-            const __amdgpu_buffer_rsrc_t rs =
-                isB ? panel_rsrc((const int8_t*)t.B.p + pl * t.B.plane + (int64_t)tile_c * t.B.ld,
-                                 (int64_t)vb * t.B.ld)
-                    : panel_rsrc((const int8_t*)t.A.p + pl * t.A.plane + (int64_t)tile_r * t.A.ld,
-                                 (int64_t)va * t.A.ld);
+        // Load q of a stage is block gb = 4 q + wave, so that at a given q
+        // every wave loads from the same plane of the same panel, known at
+        // compile time: q < 12: A plane q / 4, block 4 (q % 4) + wave; else B
+        // plane (q - 12) / 2, block 4 ((q - 12) % 2) + wave.  Row 8 blk + lr8
+        // of the panel, 16-byte chunk slot ^ lr8 ^ (blk & 1) of its 128 bytes
+        // (the swizzle the fragment reads undo; blk & 1 = wave & 1).  One
+        // resource per panel covers its three planes (offset pl * plane);
+        // rows past the panel's valid ones fall in the next plane or, in the
+        // last plane, past the range, i.e. zeros; either only feeds output
+        // rows or columns that are not stored.
+        const __amdgpu_buffer_rsrc_t rsa = panel_rsrc((const int8_t*)t.A.p + (int64_t)tile_r * t.A.ld,
+                                                      2 * t.A.plane + (int64_t)va * t.A.ld);
+        const __amdgpu_buffer_rsrc_t rsb = panel_rsrc((const int8_t*)t.B.p + (int64_t)tile_c * t.B.ld,
+                                                      2 * t.B.plane + (int64_t)vb * t.B.ld);
+        const int pla = __builtin_amdgcn_readfirstlane((int)t.A.plane);
+        const int plb = __builtin_amdgcn_readfirstlane((int)t.B.plane);
+        const int chunk = 16 * (slot ^ lr8 ^ (wave & 1));
+        const int va0 = (8 * wave + lr8) * lda + chunk, vb0 = (8 * wave + lr8) * ldb + chunk;
+        auto dload = [&](auto qc, int stg, bool live) {
+            constexpr int Q = decltype(qc)::value;
+            constexpr bool ISB = Q >= 12;
+            constexpr int PL = ISB ? (Q - 12) / 2 : Q / 4;
+            constexpr int BQ = ISB ? 4 * ((Q - 12) % 2) : 4 * (Q % 4);   // block - wave
             const uint32_t dead = live ? 0u : 0x80000000u;
-            int8_t* dst = smem + (stg & 1) * BUF + gb * 1024;
-            const int v = lr8 * ld + 16 * (slot ^ lr8 ^ (blk & 1));
+            int8_t* dst = smem + (stg & 1) * BUF + (4 * Q + wave) * 1024;
+            const int pofs = ISB ? PL * plb + 8 * BQ * ldb : PL * pla + 8 * BQ * lda;
+            const int v0 = ISB ? vb0 : va0;
             if constexpr (EDGE) {
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsVoid*)dst, 16, (uint32_t)(v + 8 * blk * ld) + dead,
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ISB ? rsb : rsa, (LdsVoid*)dst, 16,
+                                                         (uint32_t)(v0 + pofs) + dead,
                                                          __builtin_amdgcn_readfirstlane(stg * BK), 0, 0);
             } else {
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    rs, (LdsVoid*)dst, 16, (uint32_t)v + dead,
-                    __builtin_amdgcn_readfirstlane(stg * BK + 8 * blk * ld), 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ISB ? rsb : rsa, (LdsVoid*)dst, 16, (uint32_t)v0 + dead,
+                                                         __builtin_amdgcn_readfirstlane(stg * BK + pofs), 0, 0);
             }
         };
         const int sw = dma_swz(lrow);
@@ -846,8 +854,8 @@ __device__ __forceinline__ void l3_dma_body(const ProdTask& t, int ti, int tj, i
         };
         // the previous tile of a persistent workgroup may still read LDS
         __syncthreads();
-        for (int q = 0; q < PER; ++q) dload(q, 0, true);
-        for (int q = 0; q < PER; ++q) dload(q, 1, nk > 1);
+        static_for<0, PER>([&](auto q) { dload(q, 0, true); });
+        static_for<0, PER>([&](auto q) { dload(q, 1, nk > 1); });
         asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
         __syncthreads();
         for (int o = 0; o < 9; ++o) rd(fa, fb, 0, 0, o);
@@ -873,7 +881,7 @@ __device__ __forceinline__ void l3_dma_body(const ProdTask& t, int ti, int tj, i
             kstep(fa, fb, IC<18>{}, [&](auto o) {
                 constexpr int O = decltype(o)::value;
                 if constexpr (O % 2 == 0) rd(na, nb, cur, 1, O / 2);
-                else dload(9 + O / 2, kt + 1, kt + 1 < nk);
+                else dload(IC<9 + O / 2>{}, kt + 1, kt + 1 < nk);
             });
             kstep(na, nb, IC<9>{}, [&](auto o) { rd(fa, fb, cur, 2, decltype(o)::value); });
             kstep(fa, fb, IC<9>{}, [&](auto o) { rd(na, nb, cur, 3, decltype(o)::value); });
@@ -884,7 +892,7 @@ __device__ __forceinline__ void l3_dma_body(const ProdTask& t, int ti, int tj, i
             kstep(na, nb, IC<18>{}, [&](auto o) {
                 constexpr int O = decltype(o)::value;
                 if constexpr (O % 2 == 0) rd(fa, fb, cur ^ 1, 0, O / 2);
-                else dload(O / 2, kt + 2, kt + 2 < nk);
+                else dload(IC<O / 2>{}, kt + 2, kt + 2 < nk);
             });
         };
         // stages in pairs (static buffer indices); for odd nk the last stage of
@@ -1158,7 +1166,9 @@ hipError_t launch_products_limb3(ProdTask* tasks, int ntasks, ProdTask* dev_task
     int64_t tiles = 0;
     for (int i = 0; i < ntasks && dma; ++i) {
         const ProdTask& t = tasks[i];
-        dma = (t.k % 128) == 0 && t.k >= 1024 && t.A.ld < (1 << 23) && t.B.ld < (1 << 23);
+        // 32-bit buffer offsets: rows of up to 2^23 bytes, planes below 2^29
+        dma = (t.k % 128) == 0 && (t.k >= 1024 || g_l3_dma > 1) && t.A.ld < (1 << 23) && t.B.ld < (1 << 23) &&
+              t.A.plane < (1 << 29) && t.B.plane < (1 << 29);
         const int tm = (t.m + 127) / 128, tn = (t.n + 63) / 64;
         tiles += t.syrk ? l3_syrk_tiles(tm, tn) : (int64_t)tm * tn;
     }
