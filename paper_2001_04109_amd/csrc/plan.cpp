@@ -403,7 +403,10 @@ int build_syrk_plan(const PlanRequest& rq, Plan* out)
     pl.tile = tile;
 
     const int64_t es_op = elem_size(pl.cls);
-    const int64_t kunit = ((pl.cls == CLS_F64) ? 4 : 64) << (d + (pl.field.yb ? 1 : 0));
+    int64_t kunit = ((pl.cls == CLS_F64) ? 4 : 64) << (d + (pl.field.yb ? 1 : 0));
+    // three-limb leaf products with k a multiple of 128 can take the
+    // direct-to-LDS tile (whole 128-byte stages)
+    if (pl.cls == CLS_LIMB3 && kunit < ((int64_t)128 << d)) kunit = (int64_t)128 << d;
     const int64_t nunit = d > 0 ? (int64_t)4 << d : 1;
     const int64_t n_pad = n == 0 ? 0 : round_up(n, nunit);
     const int64_t k_pad = k == 0 ? 0 : round_up(k, (pl.cls == CLS_F64 && d == 0) ? 1 : kunit);
