@@ -47,8 +47,9 @@ WORKLOADS = {
                                  cls=1),
     "syrk_16384_p65521_limb2": dict(shapes=[(16384, 16384)], p=65521, depth=0, seed=2,
                                     dtype="limb2", cls=2),
-    # the depth-3 workload's shapes on three int8 limbs instead of FP64
-    "syrk_8192_p131071_limb3": dict(shapes=[(8192, 8192), (8192, 32768)], p=131071, depth=0, seed=1,
+    # the depth-3 workload's shapes on three int8 limbs instead of FP64, one
+    # level of Algorithm 2 above them (the library's default depth there)
+    "syrk_8192_p131071_limb3": dict(shapes=[(8192, 8192), (8192, 32768)], p=131071, depth=1, seed=1,
                                     dtype="u32", cls=3, limb3=True),
 }
 

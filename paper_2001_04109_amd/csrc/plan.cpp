@@ -352,13 +352,15 @@ int default_depth(int cls, int64_t n, int64_t k)
     // of 6 on half-size blocks, Table 1) for HBM-bound block additions.  On
     // FP64 matrix cores that trade pays while the leaves stay large enough
     // to fill the chip.  Three int8 limbs (nine products per block): one
-    // level pays from about n = 4096 (8192 x 8192 and 8192 x 32768,
-    // p = 131071: 3-5 % faster at depth 1, slower at depth 2).  One int8
+    // level pays once n and k / 2 reach 4096 (p = 131071: 8192 x 8192 2.16
+    // against 2.26 ms at depth 0, 8192 x 32768 7.32 against 8.56 ms,
+    // 16384^2 14.1 against 16.0 ms; 4096^2 0.39 against 0.32 ms; depth 2
+    // slower than depth 1 everywhere).  One int8
     // plane and two limbs: the additions cost as much as or more than the
     // saved products at every size measured (16384^2: int8 2.17 ms at depth
     // 0, 2.50 at depth 1; two limbs 7.50 and 7.52 ms), so no recursion.
+    if (cls == CLS_LIMB3) return std::min(n, k / 2) >= 4096 ? 1 : 0;
     const int64_t nn = std::min(n, 2 * k);
-    if (cls == CLS_LIMB3) return nn >= 4096 ? 1 : 0;
     if (cls != CLS_F64) return 0;
     int d = 0;
     while (d < 4 && (nn >> (d + 1)) >= 1024) ++d;
