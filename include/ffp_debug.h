@@ -116,7 +116,7 @@ int ffp_debug_set(const char* key, int64_t value);
 /* Timing hook for benchmarks: while enabled, every product-kernel launch is
  * bracketed by two HIP events on its stream.  ffp_debug_profile_read waits
  * for the recorded launches of base-path class cls (0 = FP64, 1 = int8,
- * 2 = int8 limbs, -1 = all), returns the sum of their durations (ms), of
+ * 2 = two int8 limbs, 3 = three int8 limbs, -1 = all), returns the sum of their durations (ms), of
  * their algorithmic flops (2 m n k for a general product, n (n+1) k for a
  * lower-triangle product) and their count, and forgets them. */
 void ffp_debug_profile(int enable);

@@ -57,12 +57,15 @@ PlanRequest schur_request(int64_t n2, const NodeLayout& L, uint32_t p, int64_t l
     rq.ldc = lds;
     rq.alpha = p - 1;
     rq.beta = 1;
-    rq.depth = -1;
     rq.no_tune = true;      // the workspace figure must not depend on the tuning table
     // above the one- and two-limb int8 range, three int8 limbs where they
-    // hold the residues (several times the FP64 matrix-core rate, no
-    // recursion needed)
+    // hold the residues (several times the FP64 matrix-core rate)
     rq.force_limb3 = p > 65521u && p < (1u << 23);
+    // Algorithm 5 ends with the product of A-bar by its transpose through
+    // Algorithm 2: updates of order 4096 and more keep one level of it on
+    // three limbs (k about n, where the base product alone is some 0.07 ms
+    // faster at order 4096); otherwise the class's default depth.
+    rq.depth = (rq.force_limb3 && n2 >= 4096) ? 1 : -1;
     rq.a_aligned16 = true;
     rq.c_aligned16 = c_aligned;
     return rq;
@@ -371,7 +374,17 @@ int execute_steps(const std::vector<Step>& steps, hipStream_t s)
                 poff += (size_t)rup256((int64_t)(g.size() * sizeof(ProdTask)));
                 memcpy(tasks, g.data(), g.size() * sizeof(ProdTask));
             }
+            hipEvent_t e0 = nullptr;
+            const bool prof = prof_enabled();
+            double flops = 0.0;
+            if (prof) {
+                for (const ProdTask& t : g)
+                    flops += t.syrk ? (double)t.m * (double)(t.m + 1) * (double)t.k
+                                    : 2.0 * (double)t.m * (double)t.n * (double)t.k;
+                prof_begin(ps, &e0);
+            }
             if (launch_products(cls, tasks, (int)g.size(), dtasks, ps) != hipSuccess) status = FFP_EDEVICE;
+            if (prof) prof_end(ps, e0, flops, cls);
         }
         if (ps != s) {
             // join even after a failure, so that no work is left unordered

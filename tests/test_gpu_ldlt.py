@@ -193,15 +193,31 @@ def _big_ldlt_case(n, p, seed0):
 
 def test_ldlt_schur_update_through_algorithm2():
     """n = 8192, p = 131071: the top Schur update (n2 = 4096, k = 4097
-    padded) runs on three int8 limbs through one level of Algorithm 2.  The
-    leading 1024 x 1024 block of L and D (the factorisation of the leading
-    block) against the oracle's Crout LDL^T; the whole factorisation by
-    Freivalds' check of L D L^T = S."""
+    padded) runs on three int8 limbs through one level of Algorithm 2, so
+    its products are launched by that plan (updates at depth 0 are steps of
+    the LDL^T kernel and launch none).  The leading 1024 x 1024 block of L
+    and D (the factorisation of the leading block) against the oracle's
+    Crout LDL^T; the whole factorisation by Freivalds' check of
+    L D L^T = S."""
+    import ctypes
     p, n = 131071, 8192
     ffp.ffp_tune_clear()
     plan = ffp.plan_describe(4096, 4224, p, lda=4224, ldc=n, alpha=p - 1, beta=1, flags=ffp.FFP_BASE_LIMB3)
-    assert " depth=1 " in plan.splitlines()[0] and " cls=3 " in plan.splitlines()[0]
-    S, out = _big_ldlt_case(n, p, 51)
+    assert " cls=3 " in plan.splitlines()[0]
+    L = ffp.lib()
+    L.ffp_debug_profile.argtypes = [ctypes.c_int]
+    L.ffp_debug_profile.restype = None
+    L.ffp_debug_profile_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.ffp_debug_profile_read.restype = ctypes.c_int
+    ms, fl, cnt = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    L.ffp_debug_profile(1)
+    try:
+        S, out = _big_ldlt_case(n, p, 51)
+        L.ffp_debug_profile_read(3, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(cnt))
+    finally:
+        L.ffp_debug_profile(0)
+    assert cnt.value > 0, "no three-limb product launched by a Schur update's plan"
     m = 1024
     ref, rinfo = oracle.ldlt_packed(S[:m, :m].copy(), p)
     assert rinfo == 0
