@@ -1166,9 +1166,10 @@ hipError_t launch_products_limb3(ProdTask* tasks, int ntasks, ProdTask* dev_task
     int64_t tiles = 0;
     for (int i = 0; i < ntasks && dma; ++i) {
         const ProdTask& t = tasks[i];
-        // 32-bit buffer offsets: rows of up to 2^23 bytes, planes below 2^29
-        dma = (t.k % 128) == 0 && (t.k >= 1024 || g_l3_dma > 1) && t.A.ld < (1 << 23) && t.B.ld < (1 << 23) &&
-              t.A.plane < (1 << 29) && t.B.plane < (1 << 29);
+        // 32-bit buffer offsets: a panel's three planes, 128 rows deep, in
+        // one resource (2 plane + 128 ld bytes) stay below 2^31
+        dma = (t.k % 128) == 0 && (t.k >= 1024 || g_l3_dma > 1) &&
+              2 * t.A.plane + 128 * t.A.ld < (1LL << 31) && 2 * t.B.plane + 128 * t.B.ld < (1LL << 31);
         const int tm = (t.m + 127) / 128, tn = (t.n + 63) / 64;
         tiles += t.syrk ? l3_syrk_tiles(tm, tn) : (int64_t)tm * tn;
     }

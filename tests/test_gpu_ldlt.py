@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_2001_04109_amd import ffp, inputs
-from tests.gpu_util import from_dev_u32, to_dev_u32
+from tests.gpu_util import from_dev_u32, product_launches, to_dev_u32
 
 pytestmark = pytest.mark.gpu
 
@@ -199,25 +199,14 @@ def test_ldlt_schur_update_through_algorithm2():
     and D (the factorisation of the leading block) against the oracle's
     Crout LDL^T; the whole factorisation by Freivalds' check of
     L D L^T = S."""
-    import ctypes
     p, n = 131071, 8192
     ffp.ffp_tune_clear()
     plan = ffp.plan_describe(4096, 4224, p, lda=4224, ldc=n, alpha=p - 1, beta=1, flags=ffp.FFP_BASE_LIMB3)
     assert " cls=3 " in plan.splitlines()[0]
-    L = ffp.lib()
-    L.ffp_debug_profile.argtypes = [ctypes.c_int]
-    L.ffp_debug_profile.restype = None
-    L.ffp_debug_profile_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
-                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
-    L.ffp_debug_profile_read.restype = ctypes.c_int
-    ms, fl, cnt = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-    L.ffp_debug_profile(1)
-    try:
-        S, out = _big_ldlt_case(n, p, 51)
-        L.ffp_debug_profile_read(3, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(cnt))
-    finally:
-        L.ffp_debug_profile(0)
-    assert cnt.value > 0, "no three-limb product launched by a Schur update's plan"
+    res = {}
+    nl = product_launches(lambda: res.update(case=_big_ldlt_case(n, p, 51)), cls=3)
+    assert nl > 0, "no three-limb product launched by a Schur update's plan"
+    S, out = res["case"]
     m = 1024
     ref, rinfo = oracle.ldlt_packed(S[:m, :m].copy(), p)
     assert rinfo == 0

@@ -9,8 +9,8 @@ import pytest
 
 import oracle
 from paper_2001_04109_amd import ffp, inputs
-from tests.gpu_util import (centred_i8, from_dev_u32, limbs, lower_mask, set_kblk, set_knob,
-                            to_dev_u32)
+from tests.gpu_util import (centred_i8, from_dev_u32, limbs, lower_mask, product_launches, set_kblk,
+                            set_knob, to_dev_u32)
 
 pytestmark = pytest.mark.gpu
 
@@ -607,6 +607,28 @@ def test_full_size_8192_p131071_three_limbs(k):
     ffp.syrk(to_dev_u32(A), p, C=Cd, limb3=True)
     torch.cuda.synchronize()
     _sampled(A, p, from_dev_u32(Cd))
+
+
+@pytest.mark.parametrize("depth", [0, 1])
+def test_three_limbs_planes_near_offset_limit(depth):
+    """16384 x 32768, p = 8388593 on three limbs: limb planes of 2^29 bytes,
+    so that a panel's three planes in one buffer resource reach 2^30 + 2^22
+    bytes of offset; the direct-to-LDS tile must run (kernel variant 14)
+    and every 128 x 128 output tile is sampled against the oracle."""
+    import torch
+    p, n, k = 8388593, 16384, 32768
+    A = inputs.uniform((60, depth), n, k, p)
+    A[:64] = (p - 1) // 2 + 1             # most negative centred value
+    A[-64:] = (p - 1) // 2                # most positive
+    Ad = to_dev_u32(A)
+    Cd = torch.zeros((n, n), dtype=torch.int32, device="cuda")
+
+    def run():
+        ffp.syrk(Ad, p, C=Cd, depth=depth, limb3=True)
+        torch.cuda.synchronize()
+    assert product_launches(run, variant=14) > 0
+    del Ad
+    _sampled(A, p, from_dev_u32(Cd), per_tile=1, seed=depth)
 
 
 @pytest.mark.parametrize("p,a_dtype,dma", [(251, ffp.FFP_I8_CENTERED, 1), (251, ffp.FFP_I8_CENTERED, 0),
