@@ -1122,8 +1122,11 @@ int g_i8_pipe = 1;
 
 hipError_t launch_products_i8(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
-    // 256 x 256 tiles once they alone fill the 256 CUs twice over
-    bool big = tiles_of(tasks, ntasks, 256) >= 512;
+    // 256 x 256 tiles once they alone fill the 256 CUs twice over and
+    // cover about the area 128 x 128 tiles would (many small products, as
+    // in a batch, leave much of a 256-tile idle: 128-tiles then win)
+    const int64_t t256 = tiles_of(tasks, ntasks, 256);
+    bool big = t256 >= 512 && t256 * 4 * 10 <= tiles_of(tasks, ntasks, 128) * 11;
     const int ov = g_tile_hint ? g_tile_hint : g_i8_tile_override;
     if (ov == 128) big = false;
     if (ov == 256) big = true;
