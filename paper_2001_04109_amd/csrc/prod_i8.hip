@@ -724,49 +724,6 @@ namespace {
 // the B panel's (8 blocks each); each wave loads 18 of them, in two halves
 // placed like the int8 tile's.
 
-// Epilogue of a three-limb wave tile: sum over q of 2^(8q) acc_q mod p,
-// then alpha and beta.
-template <int FM, int FN>
-__device__ __forceinline__ void store_tile_limb3(const v16i (&acc)[5][FM][FN], const ProdTask& t, int row0,
-                                                 int col0, bool live)
-{
-    if (!live) return;
-    const int lane = threadIdx.x & 63, lrow = lane & 31, lk = lane >> 5;
-    const double pd = (double)t.p;
-    const double alpha = (double)t.alpha, beta = (double)t.beta;
-    double cw[5];
-    cw[0] = 1.0;
-#pragma unroll
-    for (int q = 1; q < 5; ++q) cw[q] = mod_f64(cw[q - 1] * 256.0, pd, t.pinv);
-    const bool small = t.p < (1u << 19);
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int col = col0 + j * 32 + lrow;
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int row = row0 + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
-                if (row >= t.m || col >= t.n) continue;
-                if (t.syrk && col > row) continue;
-                double v = 0.0;
-                if (small) {
-                    // |acc| < 2^31 and weights below p < 2^19: five terms below 2^52, exact
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) v = fma((double)acc[q][i][j][e], cw[q], v);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) v += mod_f64((double)acc[q][i][j][e], pd, t.pinv) * cw[q];
-                }
-                v = mod_f64(v, pd, t.pinv);
-                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
-                double x = alpha * v;
-                if (t.beta != 0u) x += beta * (double)(*dst);
-                *dst = (uint32_t)mod_f64(x, pd, t.pinv);
-            }
-        }
-}
-
 template <bool EDGE>
 __device__ __forceinline__ void l3_dma_body(const ProdTask& t, int ti, int tj, int8_t* smem)
 {
@@ -903,7 +860,7 @@ __device__ __forceinline__ void l3_dma_body(const ProdTask& t, int ti, int tj, i
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
-    store_tile_limb3<FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
+    store_tile_limb3<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
 }
 
 // Lower-triangle tiles of a SYRK task on 128 x 64 tiles: row block ti holds

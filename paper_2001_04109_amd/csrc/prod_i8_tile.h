@@ -12,6 +12,8 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 // 16-byte vector in the global address space (global_load rather than flat)
 typedef __attribute__((address_space(1))) const v4i GV4;
+// a result word in the global address space (global_store rather than flat)
+typedef __attribute__((address_space(1))) uint32_t GU32;
 
 namespace {
 
@@ -162,6 +164,81 @@ __device__ __forceinline__ void store_tile_i8_reg(const v16i (&acc)[FM][FN], con
                 rp[j * 32] = r;
             }
             __builtin_amdgcn_sched_barrier(0);
+        }
+}
+
+// Epilogue of a CLS_LIMB3 wave tile: the five accumulators of weights
+// 2^(8 q) are combined mod p (for p < 2^19 in one exact double: five terms
+// below 2^52, one reduction; otherwise each term reduced first), then
+// alpha / beta applied.  A sub-tile wholly inside C and not above the
+// diagonal takes one row address per output row and no per-element tests.
+template <int WTM, int WTN, int FM, int FN>
+__device__ __forceinline__ void store_tile_limb3(const v16i (&acc)[5][FM][FN], const ProdTask& t, int row0,
+                                                 int col0, bool live)
+{
+    if (!live) return;
+    const int lane = threadIdx.x & 63, lrow = lane & 31, lk = lane >> 5;
+    const double pd = (double)t.p, pinv = t.pinv;
+    const double alpha = (double)t.alpha, beta = (double)t.beta;
+    double cw[5];
+    cw[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q < 5; ++q) cw[q] = mod_f64(cw[q - 1] * 256.0, pd, pinv);
+    const bool small = t.p < (1u << 19);
+    const bool plain = t.alpha == 1u && t.beta == 0u;
+    const bool inside = row0 + WTM <= t.m && col0 + WTN <= t.n && (!t.syrk || col0 + WTN - 1 <= row0);
+    if (inside && small) {
+        GU32* base = (GU32*)(t.C + (int64_t)(row0 + 4 * lk) * t.ldc + col0 + lrow);
+        // output rows one at a time (the barrier keeps the compiler from
+        // hoisting every row's address at once)
+        auto rows = [&](auto with_ab) {
+            constexpr bool AB = decltype(with_ab)::value;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    GU32* rp = base + (int64_t)(i * 32 + 8 * (e >> 2) + (e & 3)) * t.ldc;
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        double v = (double)acc[0][i][j][e];
+#pragma unroll
+                        for (int q = 1; q < 5; ++q) v = fma((double)acc[q][i][j][e], cw[q], v);
+                        double r = mod_f64(v, pd, pinv);
+                        if constexpr (AB)
+                            r = mod_f64(fma(alpha, r, t.beta != 0u ? beta * (double)rp[j * 32] : 0.0), pd, pinv);
+                        rp[j * 32] = (uint32_t)r;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+        };
+        if (plain) rows(std::false_type{});
+        else rows(std::true_type{});
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = col0 + j * 32 + lrow;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = row0 + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
+                if (row >= t.m || col >= t.n) continue;
+                if (t.syrk && col > row) continue;
+                double v = 0.0;
+                if (small) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) v = fma((double)acc[q][i][j][e], cw[q], v);
+                } else {
+                    // five reduced terms below p^2 < 2^46: exact
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) v += mod_f64((double)acc[q][i][j][e], pd, pinv) * cw[q];
+                }
+                v = mod_f64(v, pd, pinv);
+                uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
+                if (!plain) v = mod_f64(fma(alpha, v, t.beta != 0u ? beta * (double)(*dst) : 0.0), pd, pinv);
+                *dst = (uint32_t)v;
+            }
         }
 }
 
@@ -319,40 +396,7 @@ __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* s
     if constexpr (PLANES == 1) {
         store_tile_i8_reg<WTM, WTN, FM, FN>(acc[0], t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
     } else if constexpr (PLANES == 3) {
-        if (!wave_live) return;
-        // 2^(8 q) mod p for the five weights
-        double cw[5];
-        cw[0] = 1.0;
-#pragma unroll
-        for (int q = 1; q < 5; ++q) cw[q] = mod_f64(cw[q - 1] * 256.0, pd, t.pinv);
-        const bool small = t.p < (1u << 19);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const int col = tile_c + wc * WTN + j * 32 + lrow;
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int row = tile_r + wr * WTM + i * 32 + 8 * (e >> 2) + 4 * lk + (e & 3);
-                    if (row >= t.m || col >= t.n) continue;
-                    if (t.syrk && col > row) continue;
-                    double v = 0.0;
-                    if (small) {
-                        // |acc| < 2^31 and weights below p < 2^19: five terms below 2^52, exact
-#pragma unroll
-                        for (int q = 0; q < 5; ++q) v = fma((double)acc[q][i][j][e], cw[q], v);
-                    } else {
-                        // five reduced terms below p^2 < 2^46: exact
-#pragma unroll
-                        for (int q = 0; q < 5; ++q) v += mod_f64((double)acc[q][i][j][e], pd, t.pinv) * cw[q];
-                    }
-                    v = mod_f64(v, pd, t.pinv);
-                    uint32_t* dst = t.C + (int64_t)row * t.ldc + col;
-                    double x = alpha * v;
-                    if (t.beta != 0u) x += beta * (double)(*dst);
-                    *dst = (uint32_t)mod_f64(x, pd, t.pinv);
-                }
-            }
+        store_tile_limb3<WTM, WTN, FM, FN>(acc, t, tile_r + wr * WTM, tile_c + wc * WTN, wave_live);
     } else {
         if (!wave_live) return;
         const double r16 = (double)((65536u) % t.p), r8 = (double)(256u % t.p);
