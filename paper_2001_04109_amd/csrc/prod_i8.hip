@@ -903,7 +903,10 @@ __global__ __launch_bounds__(256) void prod_l3_dma_kernel(ProdArgs args, int mod
     if (b < args.total_tiles) l3_dma_tile(args, b, smem);
 }
 
-template <int BM, int BN, int BK, int PLANES, int RING>
+// STAGING: 1 operands straight to LDS (DMA kernels), -1 register-staged with
+// the LDS writes between the previous stage's MFMAs, 0 register-staged with
+// the LDS writes after the stage's MFMAs.
+template <int BM, int BN, int BK, int PLANES, int STAGING>
 hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     ProdArgs args{};
@@ -928,7 +931,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
     }
     const int mode = ntasks == 1 ? 1 : (g_persistent ? 2 : 0);
     int grid = mode == 1 ? (total + 7) / 8 * 8 : total;
-    if constexpr (RING > 0 && PLANES == 3) {
+    if constexpr (STAGING > 0 && PLANES == 3) {
         static_assert(BK == 128 && BM == 128 && BN == 64, "direct-to-LDS three limbs: 128 x 64 tiles");
         if (mode == 2) {
             const int resident = resident_blocks((const void*)prod_l3_dma_kernel);
@@ -936,7 +939,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         }
         g_last_variant = 14;
         hipLaunchKernelGGL(prod_l3_dma_kernel, dim3(grid), dim3(256), 0, s, args, mode);
-    } else if constexpr (RING > 0) {
+    } else if constexpr (STAGING > 0) {
         static_assert(BK == 128 && ((PLANES == 1 && BM == 256) || (PLANES == 2 && BM == 128)) && BN == BM,
                       "direct-to-LDS variant: int8 256-tiles or two limbs on 128-tiles");
         if constexpr (PLANES == 1) {
@@ -973,7 +976,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         }
         g_last_variant = PLANES == 1 ? 6 : 7;
         hipLaunchKernelGGL((prod_i8_dma_kernel<PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
-    } else if constexpr (RING < 0) {
+    } else if constexpr (STAGING < 0) {
         static_assert(PLANES <= 2 && BK == 128, "pipelined variant: int8 or two limbs, 128-byte stages");
         if (mode == 2) {
             const int resident = resident_blocks((const void*)prod_i8_pipe_kernel<BM, BN, BK, PLANES>);
@@ -996,7 +999,7 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
 // block length the task runs as consecutive launches over k-chunks, each
 // accumulating into C (beta = 1 after the first), which reduces mod p
 // between chunks.
-template <int BM, int BN, int BK, int PLANES, int RING = 0>
+template <int BM, int BN, int BK, int PLANES, int STAGING = 0>
 hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, hipStream_t s)
 {
     int32_t maxk = 0, kblk = 1 << 30;
@@ -1017,7 +1020,7 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         kblk = t.kblk < kblk ? t.kblk : kblk;
         maxk = t.k > maxk ? t.k : maxk;
     }
-    if (maxk <= kblk) return launch_i8_once<BM, BN, BK, PLANES, RING>(tasks, ntasks, dev_task_buf, s);
+    if (maxk <= kblk) return launch_i8_once<BM, BN, BK, PLANES, STAGING>(tasks, ntasks, dev_task_buf, s);
     std::vector<ProdTask> part(tasks, tasks + ntasks);
     for (int32_t k0 = 0; k0 < maxk; k0 += kblk) {
         int np = 0;
@@ -1034,7 +1037,7 @@ hipError_t launch_i8_impl(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
         // chunk launches carry their tasks inline (no staging copy outlives `part`)
         for (int q0 = 0; q0 < np; q0 += kInlineTasks) {
             const int nq = np - q0 < kInlineTasks ? np - q0 : kInlineTasks;
-            hipError_t e = launch_i8_once<BM, BN, BK, PLANES, RING>(part.data() + q0, nq, nullptr, s);
+            hipError_t e = launch_i8_once<BM, BN, BK, PLANES, STAGING>(part.data() + q0, nq, nullptr, s);
             if (e != hipSuccess) return e;
         }
     }
