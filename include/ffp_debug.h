@@ -90,8 +90,10 @@ void ffp_debug_set_kblk(int64_t kblk);
  * 128 x 128 FP64 tile of 8 waves keeps its operands as doubles in LDS,
  * converted once per workgroup, when k fits one exact block; 0: centred
  * int32 in LDS, converted by every wave that reads them),
- * "persistent" (1: grouped product launches run persistent workgroups that
- * stride over the tiles; 0: one workgroup per tile), "winograd_min" (n:
+ * "persistent" (2, the default: grouped product launches run persistent
+ * workgroups; the register-staged int8 and limb tiles are dealt to the 8
+ * XCDs in chunks of 8 neighbouring tiles; 1: persistent workgroups striding
+ * over the tiles; 0: one workgroup per tile), "winograd_min" (n:
  * general products P3, P4 of the FP64 class with wide placements, beta = 0
  * and m, n, k >= n run one level of Strassen-Winograd, Algorithm 1, with its
  * additions as separate operations; 0, the default: never), "merge_tiles"

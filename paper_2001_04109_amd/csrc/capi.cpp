@@ -286,7 +286,7 @@ int ffp_debug_set(const char* key, int64_t value)
     if (strcmp(key, "i8_pipe") == 0) { ffp::g_i8_pipe = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "pack_vec") == 0) { ffp::g_pack_vec = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "f64_pipe") == 0) { ffp::g_f64_pipe = value ? 1 : 0; return FFP_OK; }
-    if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value ? 1 : 0; return FFP_OK; }
+    if (strcmp(key, "persistent") == 0) { ffp::g_persistent = value < 0 ? 0 : (value > 2 ? 2 : (int)value); return FFP_OK; }
     if (strcmp(key, "ldlt_fold") == 0) { ffp::g_ldlt_fold = value ? 1 : 0; return FFP_OK; }
     if (strcmp(key, "serve_batch") == 0 || strcmp(key, "serve_ldlt_batch") == 0) {
         if (value < 1 || value > 4096) return FFP_EINVAL;

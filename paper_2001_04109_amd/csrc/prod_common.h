@@ -41,6 +41,20 @@ __device__ inline void tri_index(int r, int* ti, int* tj)
 // For a launch of one uniform task, give each XCD a contiguous range of
 // tiles so that neighbouring tiles, which share operand panels, meet in the
 // same L2.  `nblocks` is a multiple of 8.
+// Tile visited i-th by workgroup w of a persistent launch of G workgroups:
+// tiles are dealt to the 8 XCDs in chunks of 8 consecutive ones (round
+// robin), so that neighbouring tiles, which share operand panels, meet in
+// one XCD's L2, and every XCD gets a share of the long tasks at the front
+// of the list; an XCD's workgroups stride over its chunks.  A tile index at
+// or past the launch's tile count ends the workgroup's sequence (it grows
+// with i).  For G not a multiple of 8: plain striding.
+__device__ inline int persistent_tile(int w, int G, int i)
+{
+    if (G & 7) return w + i * G;
+    const int x = w & 7, j = (w >> 3) + i * (G >> 3);
+    return (((j >> 3) << 3) + x) * 8 + (j & 7);
+}
+
 __device__ inline int xcd_remap(int b, int nblocks)
 {
     const int per = nblocks >> 3;

@@ -702,12 +702,18 @@ __global__ __launch_bounds__(256) void prod_i8_pipe_kernel(ProdArgs args, int mo
 }
 
 // mode 0: one workgroup per tile; 1: same, XCD-aware order; 2: persistent.
+// mode 0: one workgroup per tile; 1: one task, tiles dealt to the XCDs in
+// contiguous ranges; 2: persistent workgroups striding over the tiles; 3:
+// persistent, tiles dealt to the XCDs in chunks of neighbours.
 template <int BM, int BN, int BK, int PLANES>
 __global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int mode)
 {
-    if (mode == 2) {
-        for (int b = blockIdx.x; b < args.total_tiles; b += gridDim.x)
+    if (mode >= 2) {
+        for (int i = 0;; ++i) {
+            const int b = mode == 3 ? persistent_tile(blockIdx.x, gridDim.x, i) : blockIdx.x + i * gridDim.x;
+            if (b >= args.total_tiles) break;
             i8_tile<BM, BN, BK, PLANES>(args, b);
+        }
         return;
     }
     const int b = mode == 1 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -990,7 +996,8 @@ hipError_t launch_i8_once(ProdTask* tasks, int ntasks, ProdTask* dev_task_buf, h
             grid = total < resident ? total : resident;
         }
         g_last_variant = PLANES == 3 ? 9 : (PLANES == 2 ? 5 : (BM == 128 ? 2 : (BK == 64 ? 3 : 4)));
-        hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, mode);
+        const int m3 = mode == 2 && g_persistent == 2 ? 3 : mode;
+        hipLaunchKernelGGL((prod_i8_kernel<BM, BN, BK, PLANES>), dim3(grid), dim3(256), 0, s, args, m3);
     }
     return hipGetLastError();
 }

@@ -279,7 +279,7 @@ struct TileHint {
 }  // namespace
 
 int64_t g_kblk_cap = 0;
-int g_persistent = 1;
+int g_persistent = 2;
 thread_local int g_last_variant = -1;
 
 int resident_blocks(const void* kernel, int threads)

@@ -59,8 +59,10 @@ def mixed_specs(seed, count, nmax=300, primes=(251, 65521, 65537, 131071, 100000
     return specs
 
 
-@pytest.mark.parametrize("persistent", [1, 0])
+@pytest.mark.parametrize("persistent", [2, 1, 0])
 def test_batch_mixed_matches_oracle_and_alone(persistent):
+    """Grouped launches with persistent workgroups (tiles dealt to the XCDs
+    in chunks, or plain striding) or one workgroup per tile."""
     set_knob("persistent", persistent)
     try:
         specs = mixed_specs(10, 40)
@@ -73,7 +75,7 @@ def test_batch_mixed_matches_oracle_and_alone(persistent):
             alone = run_alone(A, p, alpha, beta, C0)
             assert np.array_equal(out[low], alone[low])
     finally:
-        set_knob("persistent", 1)
+        set_knob("persistent", 2)
 
 
 @pytest.mark.parametrize("depth", [1, 2])
