@@ -48,7 +48,9 @@ __device__ __forceinline__ void i8_tile(const ProdArgs& args, int b)
     __shared__ __attribute__((aligned(16))) int8_t smem[I8Tile<BM, BN, BK, PLANES>::LDS];
     ProdTask t;
     select_task(args, b, &t);
-    i8_tile_task<BM, BN, BK, PLANES>(t, b - t.tile0, smem);
+    // three limbs: short products (batches, served requests) wait on their
+    // loads; a second register set issues them two stages ahead
+    i8_tile_task<BM, BN, BK, PLANES, PLANES == 3>(t, b - t.tile0, smem);
 }
 
 // ---- CLS_I8 with the LDS writes spread over the MFMAs -------------------
@@ -705,8 +707,10 @@ __global__ __launch_bounds__(256) void prod_i8_pipe_kernel(ProdArgs args, int mo
 // mode 0: one workgroup per tile; 1: one task, tiles dealt to the XCDs in
 // contiguous ranges; 2: persistent workgroups striding over the tiles; 3:
 // persistent, tiles dealt to the XCDs in chunks of neighbours.
+// Three limbs: registers capped for two workgroups per CU (the second
+// prefetch set of the tile fits beside the accumulators).
 template <int BM, int BN, int BK, int PLANES>
-__global__ __launch_bounds__(256) void prod_i8_kernel(ProdArgs args, int mode)
+__global__ __launch_bounds__(256, PLANES == 3 ? 2 : 1) void prod_i8_kernel(ProdArgs args, int mode)
 {
     if (mode >= 2) {
         for (int i = 0;; ++i) {

@@ -251,7 +251,10 @@ struct I8Tile {
 
 // Tile r (banded order over the task's tile grid or its lower triangle) of
 // one product task; smem: I8Tile<...>::LDS bytes, 16-byte aligned.
-template <int BM, int BN, int BK, int PLANES>
+// AHEAD2: a second register set holds the next stage's operands, so each
+// stage's global loads are issued two stages before their LDS writes (more
+// time for the loads of short products to land; 24 more registers).
+template <int BM, int BN, int BK, int PLANES, bool AHEAD2 = false>
 __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* smem)
 {
     constexpr int PITCH = BK + 16;
@@ -288,13 +291,21 @@ __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* s
     const bool wave_live = !(t.syrk && (tile_c + wc * WTN) > (tile_r + wr * WTM + WTM - 1));
 
     const int nk = t.k / BK;
-    Prefetch<BM, BK> pa[PLANES];
-    Prefetch<BN, BK> pb[PLANES];
+    Prefetch<BM, BK> pa[PLANES], qa[AHEAD2 ? PLANES : 1];
+    Prefetch<BN, BK> pb[PLANES], qb[AHEAD2 ? PLANES : 1];
     if (nk > 0) {
 #pragma unroll
         for (int pl = 0; pl < PLANES; ++pl) {
             gload<BM, BK>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, 0);
             gload<BN, BK>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, 0);
+        }
+        if constexpr (AHEAD2) {
+            if (nk > 1)
+#pragma unroll
+                for (int pl = 0; pl < PLANES; ++pl) {
+                    gload<BM, BK>(qa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, BK);
+                    gload<BN, BK>(qb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, BK);
+                }
         }
 #pragma unroll
         for (int pl = 0; pl < PLANES; ++pl) {
@@ -346,14 +357,25 @@ __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* s
     constexpr int NREAD = PLANES * (FM + FN);
     constexpr int NMFMA = FM * FN * PLANES * PLANES;
     if (nk > 0) read_frags(fa, fb, 0, 0);
-    for (int kt = 0; kt < nk; ++kt) {
+    // one stage: x holds stage kt + 1's operands (loaded a stage earlier;
+    // with one set they are loaded here), y is free for stage kt + 2's
+    auto stage = [&](int kt, Prefetch<BM, BK> (&xa)[PLANES], Prefetch<BN, BK> (&xb)[PLANES], auto& ya,
+                     auto& yb) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
-        if (more) {
+        if constexpr (AHEAD2) {
+            if (kt + 2 < nk) {
+#pragma unroll
+                for (int pl = 0; pl < PLANES; ++pl) {
+                    gload<BM, BK>(ya[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 2) * BK);
+                    gload<BN, BK>(yb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 2) * BK);
+                }
+            }
+        } else if (more) {
 #pragma unroll
             for (int pl = 0; pl < PLANES; ++pl) {
-                gload<BM, BK>(pa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 1) * BK);
-                gload<BN, BK>(pb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
+                gload<BM, BK>(xa[pl], Ab + pl * t.A.plane, t.A.ld, tile_r, t.m, (kt + 1) * BK);
+                gload<BN, BK>(xb[pl], Bb + pl * t.B.plane, t.B.ld, tile_c, t.n, (kt + 1) * BK);
             }
         }
 #pragma unroll
@@ -382,12 +404,22 @@ __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* s
         if (more) {
 #pragma unroll
             for (int pl = 0; pl < PLANES; ++pl) {
-                lstore<BM, BK>(sa[cur ^ 1][pl], pa[pl]);
-                lstore<BN, BK>(sb[cur ^ 1][pl], pb[pl]);
+                lstore<BM, BK>(sa[cur ^ 1][pl], xa[pl]);
+                lstore<BN, BK>(sb[cur ^ 1][pl], xb[pl]);
             }
         }
         __syncthreads();
         if (more) read_frags(fa, fb, cur ^ 1, 0);
+    };
+    if constexpr (AHEAD2) {
+        // even stages find stage kt + 1 in q and load kt + 2 into p; odd
+        // stages the other way round
+        for (int kt = 0; kt < nk; kt += 2) {
+            stage(kt, qa, qb, pa, pb);
+            if (kt + 1 < nk) stage(kt + 1, pa, pb, qa, qb);
+        }
+    } else {
+        for (int kt = 0; kt < nk; ++kt) stage(kt, pa, pb, pa, pb);
     }
 
     // Epilogue.  32x32 i32 MFMA result layout: lane l, element e holds
