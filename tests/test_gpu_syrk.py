@@ -481,6 +481,23 @@ def test_limb3_alpha_beta_fill_and_forced_kblk(p):
     check_lower(out, oracle.syrk_ab(A, p, 3, p - 2, C0))
 
 
+@pytest.mark.parametrize("kblk", [64, 128, 192, 320])
+@pytest.mark.parametrize("n,k", [(130, 640), (257, 1100)])
+def test_limb3_small_tile_stage_counts(kblk, n, k):
+    """The 64 x 64 three-limb tile, whose second register set loads each
+    stage two stages ahead: one, two and odd numbers of 64-byte stages per
+    launch (k in chunks of kblk), partial tiles, alpha/beta; against the
+    oracle."""
+    p = 131071
+    A = inputs.uniform((63, n, k), n, k, p)
+    C0 = inputs.uniform(64, n, n, p)
+    set_kblk(kblk)
+    try:
+        check_lower(gpu_syrk(A, p, depth=0, alpha=5, beta=7, C0=C0, limb3=True), oracle.syrk_ab(A, p, 5, 7, C0))
+    finally:
+        set_kblk(0)
+
+
 def test_limb3_max_entries_long_k():
     """Largest centred magnitudes over more columns than one exact int32
     block (43 648), so the product runs as two k-chunks."""
