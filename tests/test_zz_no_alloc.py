@@ -58,6 +58,18 @@ def test_noalloc_many_grouped_products_and_fill_upper():
     assert np.array_equal(got, oracle.syrk(A, p))
 
 
+def test_noalloc_three_limbs():
+    # three int8 limbs packed into the scratch buffer, one level of
+    # Algorithm 2, alpha/beta form
+    p = 131071
+    A = inputs.uniform(74, 520, 700, p)
+    C0 = inputs.uniform(75, 520, 520, p)
+    ref, got = _both(A, p, 1, alpha=3, beta=p - 1, C0=C0, flags=ffp.FFP_BASE_LIMB3)
+    m = lower_mask(520)
+    assert np.array_equal(got[m], ref[m])
+    assert np.array_equal(got[m], oracle.syrk_ab(A, p, 3, p - 1, C0)[m])
+
+
 def test_noalloc_rejects_workspace_beyond_scratch():
     import torch
     cap = ffp.ffp_noalloc_scratch_bytes()
