@@ -253,7 +253,7 @@ struct I8Tile {
 // one product task; smem: I8Tile<...>::LDS bytes, 16-byte aligned.
 // AHEAD2: a second register set holds the next stage's operands, so each
 // stage's global loads are issued two stages before their LDS writes (more
-// time for the loads of short products to land; 24 more registers).
+// time for the loads of short products to land, at the cost of registers).
 template <int BM, int BN, int BK, int PLANES, bool AHEAD2 = false>
 __device__ __forceinline__ void i8_tile_task(const ProdTask& t, int r, int8_t* smem)
 {
